@@ -1,0 +1,202 @@
+"""ctypes binding of the C oracle (test infrastructure only).
+
+All arrays are numpy arrays; complex matrices are complex128, row-major.
+Builds ``liboracle.so`` on first use if it is missing.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB):
+            _build.build_oracle()
+        L = ctypes.CDLL(_build.LIB)
+        u32p = np.ctypeslib.ndpointer(np.uint32, flags="C_CONTIGUOUS")
+        u16p = np.ctypeslib.ndpointer(np.uint16, flags="C_CONTIGUOUS")
+        f32p = np.ctypeslib.ndpointer(np.float32, flags="C_CONTIGUOUS")
+        f64p = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
+        i8p = np.ctypeslib.ndpointer(np.int8, flags="C_CONTIGUOUS")
+        i32p = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
+        i64p = np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS")
+        c = ctypes
+        L.qeo_philox4x32_10.argtypes = [u32p, u32p, u32p]
+        L.qeo_check_desc.argtypes = [c.c_int, c.c_uint16]
+        L.qeo_unitary.argtypes = [c.c_int, c.c_int, u16p, f64p]
+        L.qeo_fitness.argtypes = [c.c_int, c.c_int, u16p, f64p, f64p]
+        L.qeo_eval_batch.argtypes = [c.c_int, i8p, i32p, u16p, i64p, f64p, f64p]
+        L.qeo_num_threads.restype = c.c_int
+        L.qeo_lib_size.argtypes = [c.c_int, c.c_int]
+        L.qeo_lib_desc.argtypes = [c.c_int, c.c_int, c.c_int]
+        L.qeo_lib_desc.restype = c.c_uint16
+        L.qeo_segment_index.argtypes = [c.c_int] * 5
+        L.qeo_segment_index.restype = c.c_uint32
+        L.qeo_measure.argtypes = [f32p, c.c_uint32]
+        L.qeo_qeqea_sample.argtypes = [c.c_int, c.c_int, c.c_int, c.c_int, c.c_uint64,
+                                       c.c_uint64, u32p, f32p, u32p, u16p]
+        L.qeo_qeqea_init.argtypes = [c.c_int, c.c_int, c.c_int, c.c_int, c.c_uint64,
+                                     u32p, f32p, f32p, u32p, f32p]
+        L.qeo_su3.argtypes = [f64p, f64p]
+        L.qeo_su3_step.argtypes = [f32p, c.c_int, c.c_int]
+        L.qeo_qeqea_update.argtypes = [c.c_int, c.c_int, c.c_int, c.c_int, c.c_uint64,
+                                       c.c_uint64, c.c_float, c.c_float, u32p, f32p,
+                                       u32p, f32p, f32p, u32p, f32p]
+        L.qeo_ga_init.argtypes = [c.c_int, c.c_int, c.c_int, c.c_int, c.c_int, c.c_uint64,
+                                  u16p]
+        L.qeo_ga_sus.argtypes = [c.c_int, f32p, c.c_uint32, i32p]
+        L.qeo_ga_update.argtypes = [c.c_int, c.c_int, c.c_int, c.c_int, c.c_int, c.c_uint64,
+                                    c.c_uint64, c.c_float, c.c_float, f32p, u16p]
+        _lib = L
+    return _lib
+
+
+# --------------------------------------------------------------------------- RNG
+def philox(ctr, key):
+    out = np.zeros(4, np.uint32)
+    lib().qeo_philox4x32_10(np.asarray(ctr, np.uint32), np.asarray(key, np.uint32), out)
+    return out
+
+
+# ------------------------------------------------------------------ gates, Eq. 11
+def desc(kind, tgt=0, ctl=0):
+    return np.uint16(kind | (tgt << 4) | (ctl << 8))
+
+
+def check_desc(n, d):
+    return lib().qeo_check_desc(n, int(d)) == 0
+
+
+def unitary(n, gates):
+    g = np.ascontiguousarray(gates, np.uint16)
+    U = np.zeros((1 << n) * (1 << n) * 2, np.float64)
+    rc = lib().qeo_unitary(n, len(g), g, U)
+    if rc:
+        raise ValueError("bad gate descriptor")
+    return U.view(np.complex128).reshape(1 << n, 1 << n)
+
+
+def fitness(n, gates, T):
+    """Returns (f, g, delta, f_trace) for one circuit against target T."""
+    g = np.ascontiguousarray(gates, np.uint16)
+    T = np.ascontiguousarray(T, np.complex128)
+    out = np.zeros(4, np.float64)
+    rc = lib().qeo_fitness(n, len(g), g, T.view(np.float64).ravel(), out)
+    if rc:
+        raise ValueError("bad gate descriptor")
+    return tuple(float(x) for x in out)
+
+
+def eval_batch(nq, goff, gates, toff, targets):
+    """Uneven batch: returns an array [B, 4] of (f, g, delta, f_trace)."""
+    nq = np.ascontiguousarray(nq, np.int8)
+    goff = np.ascontiguousarray(goff, np.int32)
+    gates = np.ascontiguousarray(gates, np.uint16)
+    toff = np.ascontiguousarray(toff, np.int64)
+    targets = np.ascontiguousarray(targets, np.complex128)
+    B = len(nq)
+    out = np.zeros((B, 4), np.float64)
+    if len(gates) == 0:
+        gates = np.zeros(1, np.uint16)
+    bad = lib().qeo_eval_batch(B, nq, goff, gates, toff, targets.view(np.float64).ravel(), out)
+    if bad:
+        raise ValueError(f"{bad} circuits with bad gate descriptors")
+    return out
+
+
+def num_threads():
+    return lib().qeo_num_threads()
+
+
+# --------------------------------------------------------------------- libraries
+def lib_size(library, n):
+    return lib().qeo_lib_size(library, n)
+
+
+def lib_table(library, n):
+    return np.array([lib().qeo_lib_desc(library, n, i) for i in range(lib_size(library, n))],
+                    np.uint16)
+
+
+# ------------------------------------------------------------------------ QEQEA
+def segment_index(L, P, region, ind, pos):
+    return int(lib().qeo_segment_index(L, P, region, ind, pos))
+
+
+def measure(q, w):
+    return lib().qeo_measure(np.ascontiguousarray(q, np.float32), int(w))
+
+
+class QeqeaState:
+    """Encoding of I independent QEQEA populations (n wires, L, P)."""
+
+    def __init__(self, n, L, P, I, seed):
+        self.n, self.L, self.P, self.I, self.seed = n, L, P, I, seed
+        S = n * n * L * P
+        Q = n * L * P
+        self.theta = np.zeros(I * S, np.uint32)
+        self.qutrit = np.zeros(I * Q * 6, np.float32)
+        self.best_f = np.zeros(I * S, np.float32)
+        self.best_theta = np.zeros(I * S, np.uint32)
+        self.best_qutrit = np.zeros(I * Q * 6, np.float32)
+        lib().qeo_qeqea_init(n, L, P, I, seed, self.theta, self.qutrit, self.best_f,
+                             self.best_theta, self.best_qutrit)
+
+    def copy(self):
+        o = object.__new__(QeqeaState)
+        o.__dict__.update({k: (v.copy() if isinstance(v, np.ndarray) else v)
+                           for k, v in self.__dict__.items()})
+        return o
+
+    def sample(self, gen):
+        n, L, P, I = self.n, self.L, self.P, self.I
+        slots = np.zeros(I * P * L, np.uint32)
+        gates = np.zeros(I * P * L, np.uint16)
+        lib().qeo_qeqea_sample(n, L, P, I, self.seed, gen, self.theta, self.qutrit, slots, gates)
+        return slots.reshape(I * P, L), gates.reshape(I * P, L)
+
+    def update(self, gen, pm, mrange, slots, f):
+        lib().qeo_qeqea_update(self.n, self.L, self.P, self.I, self.seed, gen, pm, mrange,
+                               np.ascontiguousarray(slots, np.uint32).ravel(),
+                               np.ascontiguousarray(f, np.float32).ravel(),
+                               self.theta, self.qutrit, self.best_f, self.best_theta,
+                               self.best_qutrit)
+
+
+def su3(params):
+    U = np.zeros(18, np.float64)
+    lib().qeo_su3(np.ascontiguousarray(params, np.float64), U)
+    return U.view(np.complex128).reshape(3, 3)
+
+
+def su3_step(q, j, a):
+    q = np.array(q, np.float32).copy()
+    lib().qeo_su3_step(q, j, a)
+    return q
+
+
+# --------------------------------------------------------------------------- GA
+def ga_init(n, library, L, P, I, seed):
+    g = np.zeros(I * P * L, np.uint16)
+    lib().qeo_ga_init(n, library, L, P, I, seed, g)
+    return g.reshape(I * P, L)
+
+
+def ga_sus(f, w0):
+    f = np.ascontiguousarray(f, np.float32)
+    sel = np.zeros(len(f), np.int32)
+    lib().qeo_ga_sus(len(f), f, int(w0), sel)
+    return sel
+
+
+def ga_update(n, library, L, P, I, seed, gen, pc, pg, f, genomes):
+    g = np.ascontiguousarray(genomes, np.uint16).ravel().copy()
+    lib().qeo_ga_update(n, library, L, P, I, seed, gen, pc, pg,
+                        np.ascontiguousarray(f, np.float32).ravel(), g)
+    return g.reshape(I * P, L)
