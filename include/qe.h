@@ -1,0 +1,252 @@
+/*
+ * qe.h -- C ABI of libqe, an MI355X (gfx950) implementation of the hot path of
+ * the Quantum Encoded Quantum Evolutionary Algorithm (QEQEA) and its classical
+ * GA baseline (Krylov & Lukac, arXiv:1809.11134): batched fitness evaluation
+ * of candidate circuits (Sec. IV-E, Eq. 11), circuit construction by sampling
+ * the qubit/qutrit encoding (Sec. IV-D, Eq. 10), segment fitness, elitism and
+ * adaptive mutation (Secs. IV-E.1, IV-F, Eq. 12), and the GA operators of
+ * Sec. V-B.
+ *
+ * Conventions shared by every entry point
+ *  - Gate descriptor (uint16): kind in bits 0-3, target wire in bits 4-7,
+ *    control wire in bits 8-11, bits 12-15 zero.  Kinds: 0 I, 1 NOT, 2 CNOT,
+ *    3 CV, 4 CV+ (V = sqrt(NOT)), 5 H, 6 T.  Single-qubit kinds ignore the
+ *    control field.
+ *  - Wire w of an n-wire register is bit (n-1-w) of a basis-state index: the
+ *    first Kronecker factor is the most significant (Eqs. 1-2).
+ *  - A circuit g_0 .. g_{L-1} denotes U = G_{L-1} ... G_0 (g_0 acts first).
+ *  - Matrices are row-major; complex64 = interleaved (re, im) float pairs,
+ *    complex128 = interleaved double pairs.
+ *  - Fitness (Eq. 11): f = 1 - sqrt((2^n - |tr(U^dagger T)|) / 2^n), computed
+ *    through the identity 2^n - |tr(T^dagger U)| = (1/2)||U T^dagger -
+ *    e^{i arg tr} I||_F^2 so that single precision keeps its accuracy near
+ *    f = 1; the radicand is clamped to [0, 1].  g = |tr(T^dagger U)| / 2^n
+ *    and delta = 2^n - |tr| are optional outputs.
+ *  - Pointers named *_dev are device memory owned by the caller (the library
+ *    never frees them); *_host are host memory.  All calls taking `stream`
+ *    (a hipStream_t passed as void*, NULL = the null stream) are asynchronous:
+ *    they validate host-side arguments, enqueue kernels and return without
+ *    synchronising.  Calls documented as "syncs" block on `stream`.
+ *  - Errors: every call returns a qe_status.  Invalid host arguments return
+ *    QE_ERR_INVALID (nothing is enqueued).  Malformed device-side data
+ *    (descriptors, widths, offsets out of range) cannot be checked before the
+ *    launch: the kernels never access memory out of bounds for it, write NaN
+ *    for the affected circuit and raise a device error flag that
+ *    qe_device_errors() reports.  qe_last_error() gives a message for the
+ *    last failing call of the calling thread.
+ *  - A context is not thread-safe; use it from one host thread and one
+ *    stream at a time.
+ */
+#ifndef QE_H
+#define QE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t qe_status;
+enum {
+    QE_OK = 0,
+    QE_ERR_INVALID = 1,     /* bad argument; nothing was launched */
+    QE_ERR_UNSUPPORTED = 2, /* valid but not implemented (e.g. QEQEA on library 1) */
+    QE_ERR_DEVICE = 3,      /* a HIP call failed */
+    QE_ERR_OOM = 4,         /* device allocation failed */
+    QE_ERR_NUMERIC = 5,     /* NaN/Inf met (qe_get_best) */
+    QE_ERR_STATE = 6        /* call out of order (e.g. no targets set) */
+};
+
+enum { QE_LIB_NCV = 0,      /* {I, NOT, CNOT, CV, CV+} */
+       QE_LIB_HT_NCV = 1 }; /* {H, T, CNOT, CV, CV+}   */
+enum { QE_ALG_QEQEA = 0, QE_ALG_GA = 1 };
+enum { QE_PATH_FP32 = 0,        /* per-gate row updates, FP32, tuned schedule per width */
+       QE_PATH_FP32_REG = 1,    /* forced: matrix held in registers, one wave per circuit */
+       QE_PATH_FP32_LDS = 2,    /* forced: matrix staged in LDS, columns split over waves */
+       QE_PATH_MFMA_BF16 = 3,   /* fused gate blocks on MFMA, bf16 hi+lo (n >= 5) */
+       QE_PATH_MFMA_FP16 = 4 }; /* fused gate blocks on MFMA, fp16 hi+lo (n >= 5) */
+
+/* Device error flags (bitmask) raised by kernels. */
+enum { QE_DEVERR_DESC = 1,      /* invalid gate descriptor */
+       QE_DEVERR_WIDTH = 2,     /* circuit width outside 1..6 */
+       QE_DEVERR_RANGE = 4,     /* gate or target offsets outside the buffers */
+       QE_DEVERR_NUMERIC = 8 }; /* NaN/Inf fitness */
+
+/* ------------------------------------------------------------------ batches */
+/* A batch of circuits to evaluate (Sec. IV-E).  Host struct; the arrays it
+ * points to live on the device.
+ *   num_circuits   B >= 0.
+ *   uniform_n      > 0: every circuit has this many wires (1..6) and n_qubits
+ *                  may be NULL; 0: widths from n_qubits[B] (int8).
+ *   uniform_L      > 0: circuit b is gates[b*uniform_L .. +uniform_L) and
+ *                  gate_offsets may be NULL; 0: gates[gate_offsets[b] ..
+ *                  gate_offsets[b+1]) with gate_offsets[B+1] (int32).
+ *   num_gates      number of descriptors in `gates` (bounds for offsets).
+ *   target_stride  >= 0: target b at targets + b*target_stride complex
+ *                  elements (0 = one shared target); < 0: at
+ *                  targets + target_offsets[b] (int64, complex elements).
+ *   targets        complex64 (FP32/MFMA paths) or complex128 (FP64 calls),
+ *                  2^n x 2^n row-major per target.
+ *   num_target_elems  complex elements in `targets` (bounds). */
+typedef struct {
+    int32_t num_circuits;
+    int32_t uniform_n;
+    const int8_t* n_qubits_dev;
+    int32_t uniform_L;
+    const int32_t* gate_offsets_dev;
+    const uint16_t* gates_dev;
+    int64_t num_gates;
+    int64_t target_stride;
+    const int64_t* target_offsets_dev;
+    const void* targets_dev;
+    int64_t num_target_elems;
+} qe_batch;
+
+/* Fitness of every circuit of the batch against its target, Eq. 11 of
+ * Sec. IV-E (the hot path).  path: QE_PATH_*.  f_dev [B] required; g_dev,
+ * delta_dev [B] optional (NULL).  One wavefront per circuit; the 2^n x 2^n
+ * product U T^dagger is built gate by gate from T^dagger.  Circuits whose
+ * width, gates or target are malformed get f = NaN (see qe_device_errors).
+ * ctx may be NULL. */
+typedef struct qe_ctx qe_ctx;
+qe_status qe_eval_fitness(qe_ctx* ctx, const qe_batch* batch, int32_t path, float* f_dev,
+                          float* g_dev, float* delta_dev, void* stream);
+
+/* The same fitness in FP64 (targets complex128), for re-checking elite
+ * circuits; f_dev required, g_dev/delta_dev optional. */
+qe_status qe_eval_fitness_fp64(const qe_batch* batch, double* f_dev, double* g_dev,
+                               double* delta_dev, void* stream);
+
+/* The unitary U = G_{L-1}...G_0 of every circuit (Eqs. 1-6 with the library
+ * gates), written to out_dev as [B][2^n][2^n] complex64 (precision 0) or
+ * complex128 (precision 1).  Requires batch->uniform_n > 0; out_elems is the
+ * capacity of out_dev in complex elements; targets are ignored. */
+qe_status qe_build_unitary(const qe_batch* batch, int32_t precision, void* out_dev,
+                           int64_t out_elems, void* stream);
+
+/* Reads and clears the device error flags raised since the last call
+ * (QE_DEVERR_* bitmask) on the current device.  Syncs the device. */
+qe_status qe_device_errors(int32_t* flags_host);
+
+/* ---------------------------------------------------------------- contexts */
+/* Parameters of the evolutionary search (Sec. IV-B, IV-F, V-B):
+ *   n_qubits (numberOfWires) 2..6 for QEQEA, 1..6 for GA; library QE_LIB_*;
+ *   algorithm QE_ALG_*; size_of_individual L (circuit length) 1..1024;
+ *   size_of_population P (circuits per instance per generation) 1..65536;
+ *   n_instances I independent populations, each with its own target;
+ *   prob_mutation (probabilityOfMutation, QEQEA) in [0, 1];
+ *   mutation_range (mutationRange, radians) in [0, 2 pi);
+ *   ga_crossover_prob, ga_gene_mutation_prob in [0, 1] (GA);
+ *   seed: the Philox4x32-10 key.
+ * QEQEA uses the library {I, NOT, CNOT, CV, CV+} only. */
+typedef struct {
+    int32_t n_qubits;
+    int32_t library;
+    int32_t algorithm;
+    int32_t size_of_individual;
+    int32_t size_of_population;
+    int32_t n_instances;
+    float prob_mutation;
+    float mutation_range;
+    float ga_crossover_prob;
+    float ga_gene_mutation_prob;
+    uint64_t seed;
+} qe_problem;
+
+/* Creates a context on the current device: allocates the ctx-owned encoding
+ * (QEQEA: (n + n(n-1)) * L * P u32 angles, n*L*P qutrits of 3 complex64, and
+ * their best copies and fitness; GA: two L*P genome buffers) per instance,
+ * and initialises it as the population initialisation of Sec. IV-B (angles
+ * from the Philox INIT stream, qutrits (1,1,1)/sqrt(3), no best yet).  Syncs. */
+qe_status qe_create(const qe_problem* problem, qe_ctx** ctx_out);
+qe_status qe_destroy(qe_ctx* ctx);
+
+/* Copies the I targets ([I][2^n][2^n] complex128, device) into the context
+ * (kept in complex128 for the FP64 re-check and in complex64 for the hot
+ * path).  Must precede sample/eval/update/generation.  Asynchronous. */
+qe_status qe_set_targets(qe_ctx* ctx, const void* targets_c128_dev, void* stream);
+
+/* Circuit construction (Sec. IV-D).  QEQEA: for each instance i, circuit
+ * k < P and position pos < L, draws whichIndividual and
+ * whichRotationOrInteraction from the Philox SAMPLE stream of generation
+ * `gen`, forms the segment index of Eq. 10 into slots_dev[(i*P+k)*L + pos]
+ * and decodes that segment (qutrit measured by the Born rule, angle rounded
+ * to quarter turns) into gates_dev[(i*P+k)*L + pos].  GA: copies the current
+ * population (slots_dev may be NULL). */
+qe_status qe_sample(qe_ctx* ctx, uint64_t gen, uint32_t* slots_dev, uint16_t* gates_dev,
+                    void* stream);
+
+/* Fitness of the I*P circuits in gates_dev against each instance's target
+ * (FP32 path); f_dev [I*P]. */
+qe_status qe_eval_population(qe_ctx* ctx, const uint16_t* gates_dev, float* f_dev,
+                             void* stream);
+
+/* One update step (Secs. IV-E.1, IV-F; GA: Sec. V-B).  QEQEA: every slot used
+ * in generation `gen` takes the largest fitness of the circuits it built;
+ * a used slot that beats its recorded best stores its state, otherwise
+ * reverts to it; each individual mutates with prob_mutation (all qubits by
+ * +-(1 - segFit) * mutation_range, or all qutrits by one SU(3) step of
+ * Eq. 12, equiprobably).  GA: SUS selection, two-point crossover, gene
+ * mutation, best individual kept.  slots_dev/gates_dev/f_dev as produced by
+ * qe_sample and qe_eval_population for the same `gen`. */
+qe_status qe_update(qe_ctx* ctx, uint64_t gen, const uint32_t* slots_dev,
+                    const uint16_t* gates_dev, const float* f_dev, void* stream);
+
+/* sample + eval + update of generation `gen` in two kernel launches (QEQEA)
+ * or two (GA); f_dev [I*P] receives the generation's fitness (may be NULL).
+ * Results equal qe_sample, qe_eval_population and qe_update in sequence. */
+qe_status qe_generation(qe_ctx* ctx, uint64_t gen, float* f_dev, void* stream);
+
+/* Runs generations first_gen .. first_gen + n_gen - 1 as one HIP graph
+ * (captured on first use for this n_gen and f_hist_dev, then replayed);
+ * f_hist_dev [n_gen][I*P] or NULL.  Same results as n_gen qe_generation
+ * calls. */
+qe_status qe_run_graph(qe_ctx* ctx, uint64_t first_gen, int32_t n_gen, float* f_hist_dev,
+                       void* stream);
+
+/* FP64 re-check of elite circuits: for each instance, the k circuits of
+ * gates_dev with the highest f_dev (ties: lowest index) are re-evaluated in
+ * FP64 against the complex128 target.  idx_dev [I][k] (int32, circuit index
+ * within the instance), f64_dev [I][k].  1 <= k <= P. */
+qe_status qe_elite_recheck(qe_ctx* ctx, const uint16_t* gates_dev, const float* f_dev,
+                           int32_t k, int32_t* idx_dev, double* f64_dev, void* stream);
+
+/* Best circuit seen so far by instance `instance` (over every generation run
+ * through qe_update / qe_generation / qe_run_graph): its L gates, its FP32
+ * fitness and its FP64 re-evaluated fitness.  Syncs the device. */
+qe_status qe_get_best(qe_ctx* ctx, int32_t instance, uint16_t* gates_host, float* f32_host,
+                      double* f64_host);
+
+/* Checkpoint / restore of the whole encoding state (bit-exact; the run is a
+ * pure function of the state, the seed and the generation index).  With
+ * buf_host NULL, qe_checkpoint stores the needed size in *size.  Both sync. */
+qe_status qe_checkpoint(qe_ctx* ctx, void* buf_host, size_t* size);
+qe_status qe_restore(qe_ctx* ctx, const void* buf_host, size_t size);
+
+/* Raw views of the context-owned state (device pointers; sizes in elements)
+ * for tests and inspection.  which: 0 theta (u32), 1 qutrit (f32, 6 per
+ * qutrit), 2 best_f (f32), 3 best_theta (u32), 4 best_qutrit (f32),
+ * 5 GA genomes of the current generation parity 0 (u16), 6 parity 1. */
+qe_status qe_state_view(qe_ctx* ctx, int32_t which, void** ptr_dev, int64_t* elems);
+
+/* Gate-library table used by the GA (instance index -> descriptor), host
+ * output of qe_lib_size() entries. */
+int32_t qe_lib_size(int32_t library, int32_t n_qubits);
+qe_status qe_lib_table(int32_t library, int32_t n_qubits, uint16_t* table_host);
+
+/* Schedule of the QE_PATH_FP32 path: for width n (1..6), lds != 0 selects
+ * the LDS-staged kernel, 0 the register-resident one (n <= 3 always use the
+ * one-element-per-lane kernel).  Process-wide; the defaults come from the
+ * tuning table measured on MI355X and can be overridden by the environment
+ * variable QE_SCHEDULE="n:lds,n:lds,...". */
+qe_status qe_set_schedule(int32_t n_qubits, int32_t lds);
+qe_status qe_get_schedule(int32_t n_qubits, int32_t* lds);
+
+const char* qe_last_error(void);
+const char* qe_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QE_H */

@@ -624,8 +624,9 @@ QEO_API void qeo_ga_update(int n, int lib, int L, int P, int I_, uint64_t seed, 
         const float* fi = f + (size_t)i * P;
         uint16_t* gi = genomes + (size_t)i * P * L;
         int best = 0;                           /* lowest index among the maxima */
-        for (int k = 1; k < P; ++k)
-            if (fi[k] > fi[best]) best = k;
+        float bv = -1.0f;                       /* NaN never counts */
+        for (int k = 0; k < P; ++k)
+            if (fi[k] > bv) { bv = fi[k]; best = k; }
         uint32_t w[4];
         draw(seed, TAG_GA_SUS, gen, (uint32_t)i, 0u, w);
         qeo_ga_sus(P, fi, w[0], sel);

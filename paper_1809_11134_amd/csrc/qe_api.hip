@@ -1,0 +1,617 @@
+// libqe C ABI: argument validation, context ownership, launches, graph
+// capture of the generation loop, checkpoint / restore.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/qe.h"
+#include "qe_common.hpp"
+#include "qe_internal.hpp"
+
+using namespace qe;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+qe_status fail(qe_status st, const std::string& msg) {
+    g_last_error = msg;
+    return st;
+}
+
+#define QE_HIP(call)                                                                       \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail(QE_ERR_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// One device error word per device, allocated on first use.
+std::mutex g_mu;
+std::map<int, uint32_t*> g_err_words;
+
+qe_status device_error_word(uint32_t** out) {
+    int dev = 0;
+    QE_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_err_words.find(dev);
+    if (it != g_err_words.end()) { *out = it->second; return QE_OK; }
+    uint32_t* p = nullptr;
+    QE_HIP(hipMalloc(&p, sizeof(uint32_t)));
+    QE_HIP(hipMemset(p, 0, sizeof(uint32_t)));
+    QE_HIP(hipDeviceSynchronize());
+    g_err_words[dev] = p;
+    *out = p;
+    return QE_OK;
+}
+
+// Per-width schedule of the FP32 path (1 = LDS-staged kernel).  Defaults from
+// the MI355X tuning sweep; QE_SCHEDULE="n:lds,..." overrides.
+int g_sched[MAX_QUBITS + 1] = {0, 0, 0, 0, 0, 1, 1};
+std::once_flag g_sched_once;
+
+void load_schedule_env() {
+    const char* s = std::getenv("QE_SCHEDULE");
+    if (!s) return;
+    std::string str(s);
+    size_t pos = 0;
+    while (pos < str.size()) {
+        size_t comma = str.find(',', pos);
+        std::string item = str.substr(pos, comma == std::string::npos ? std::string::npos : comma - pos);
+        int n = 0, l = 0;
+        if (std::sscanf(item.c_str(), "%d:%d", &n, &l) == 2 && n >= 1 && n <= MAX_QUBITS)
+            g_sched[n] = l ? 1 : 0;
+        if (comma == std::string::npos) break;
+        pos = comma + 1;
+    }
+}
+
+uint64_t prob_threshold(double p) {
+    if (!(p > 0)) return 0;
+    if (p >= 1) return (uint64_t)1 << 32;
+    return (uint64_t)std::floor(p * 4294967296.0);
+}
+
+qe_status to_args(const qe_batch* b, BatchArgs* a, bool need_targets) {
+    if (!b) return fail(QE_ERR_INVALID, "batch is NULL");
+    if (b->num_circuits < 0) return fail(QE_ERR_INVALID, "num_circuits < 0");
+    if (b->uniform_n < 0 || b->uniform_n > MAX_QUBITS)
+        return fail(QE_ERR_INVALID, "uniform_n must be 0 (mixed) or 1..6");
+    if (b->uniform_n == 0 && b->num_circuits > 0 && !b->n_qubits_dev)
+        return fail(QE_ERR_INVALID, "mixed widths need n_qubits_dev");
+    if (b->uniform_L < 0) return fail(QE_ERR_INVALID, "uniform_L < 0");
+    if (b->uniform_L == 0 && b->num_circuits > 0 && !b->gate_offsets_dev)
+        return fail(QE_ERR_INVALID, "uneven lengths need gate_offsets_dev");
+    if (b->num_gates < 0) return fail(QE_ERR_INVALID, "num_gates < 0");
+    if (b->uniform_L > 0 && (int64_t)b->num_circuits * b->uniform_L > b->num_gates)
+        return fail(QE_ERR_INVALID, "num_circuits * uniform_L exceeds num_gates");
+    if (b->num_gates > 0 && !b->gates_dev) return fail(QE_ERR_INVALID, "gates_dev is NULL");
+    if (need_targets) {
+        if (b->target_stride < 0 && b->num_circuits > 0 && !b->target_offsets_dev)
+            return fail(QE_ERR_INVALID, "target_stride < 0 needs target_offsets_dev");
+        if (b->num_circuits > 0 && !b->targets_dev) return fail(QE_ERR_INVALID, "targets_dev is NULL");
+        if (b->num_target_elems < 0) return fail(QE_ERR_INVALID, "num_target_elems < 0");
+        if (b->uniform_n > 0 && b->target_stride >= 0 && b->num_circuits > 0) {
+            const int64_t NN = (int64_t)1 << (2 * b->uniform_n);
+            if ((int64_t)(b->num_circuits - 1) * b->target_stride + NN > b->num_target_elems)
+                return fail(QE_ERR_INVALID, "targets buffer too small for the stride");
+        }
+    }
+    a->B = b->num_circuits;
+    a->uniform_n = b->uniform_n;
+    a->nq = b->n_qubits_dev;
+    a->uniform_L = b->uniform_L;
+    a->goff = b->gate_offsets_dev;
+    a->gates = b->gates_dev;
+    a->num_gates = b->num_gates;
+    a->tstride = b->target_stride;
+    a->toff = b->target_offsets_dev;
+    a->targets = b->targets_dev;
+    a->num_telems = b->num_target_elems;
+    return device_error_word(&a->err);
+}
+
+}  // namespace
+
+namespace qe {
+bool schedule_lds(int n) {
+    std::call_once(g_sched_once, load_schedule_env);
+    return n >= 1 && n <= MAX_QUBITS && g_sched[n] != 0;
+}
+}  // namespace qe
+
+// ====================================================================== ctx
+struct qe_ctx {
+    qe_problem prob;
+    int device = 0;
+    LoopArgs la{};
+    int N = 0;
+    size_t S = 0, Q = 0;          // per instance
+    bool targets_set = false;
+    // ctx-owned device buffers
+    std::vector<void*> owned;
+    uint32_t* slots = nullptr;    // [I*P*L] generation scratch
+    uint16_t* gates = nullptr;    // [I*P*L]
+    float* f = nullptr;           // [I*P]
+    uint64_t* d_gen = nullptr;
+    int32_t* elite_idx = nullptr;
+    hipStream_t capture_stream = nullptr;
+    std::map<std::pair<int, float*>, hipGraphExec_t> graphs;
+    hipGraph_t last_graph = nullptr;
+};
+
+namespace {
+
+template <typename T>
+qe_status ctx_alloc(qe_ctx* c, T** p, size_t elems) {
+    void* q = nullptr;
+    if (elems == 0) elems = 1;
+    hipError_t e = hipMalloc(&q, elems * sizeof(T));
+    if (e != hipSuccess) return fail(QE_ERR_OOM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    c->owned.push_back(q);
+    *p = static_cast<T*>(q);
+    return QE_OK;
+}
+
+void free_ctx(qe_ctx* c) {
+    for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second);
+    if (c->capture_stream) hipStreamDestroy(c->capture_stream);
+    for (void* p : c->owned) hipFree(p);
+    delete c;
+}
+
+#define QE_TRY(x)                        \
+    do {                                 \
+        qe_status s_ = (x);              \
+        if (s_ != QE_OK) return s_;      \
+    } while (0)
+
+qe_status check_ctx(qe_ctx* c, bool need_targets) {
+    if (!c) return fail(QE_ERR_INVALID, "ctx is NULL");
+    if (need_targets && !c->targets_set) return fail(QE_ERR_STATE, "qe_set_targets has not been called");
+    return QE_OK;
+}
+
+// sample + eval + update of one generation (gen is relative to la.gen_ptr
+// when graph-captured).
+qe_status enqueue_generation(qe_ctx* c, const LoopArgs& a, uint64_t gen, float* f, hipStream_t s) {
+    if (c->prob.algorithm == QE_ALG_QEQEA) {
+        QE_HIP(launch_qeqea_fused(a, gen, c->slots, c->gates, f, s));
+        QE_HIP(launch_qeqea_update(a, gen, c->slots, c->gates, f, s));
+    } else {
+        QE_HIP(launch_ga_copy(a, gen, c->gates, s));
+        QE_HIP(launch_eval_population(a, c->gates, f, s));
+        QE_HIP(launch_ga_update(a, gen, f, s));
+    }
+    return QE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* qe_last_error(void) { return g_last_error.c_str(); }
+const char* qe_version(void) { return "libqe 0.1 (gfx950)"; }
+
+int32_t qe_lib_size(int32_t library, int32_t n) {
+    if ((library != 0 && library != 1) || n < 1 || n > MAX_QUBITS) return -1;
+    return lib_size(library, n);
+}
+
+qe_status qe_lib_table(int32_t library, int32_t n, uint16_t* table_host) {
+    if ((library != 0 && library != 1) || n < 1 || n > MAX_QUBITS || !table_host)
+        return fail(QE_ERR_INVALID, "bad library, width or NULL table");
+    for (int i = 0; i < lib_size(library, n); ++i) table_host[i] = lib_desc(library, n, i);
+    return QE_OK;
+}
+
+qe_status qe_set_schedule(int32_t n, int32_t lds) {
+    std::call_once(g_sched_once, load_schedule_env);
+    if (n < 1 || n > MAX_QUBITS) return fail(QE_ERR_INVALID, "width must be 1..6");
+    g_sched[n] = lds ? 1 : 0;
+    return QE_OK;
+}
+
+qe_status qe_get_schedule(int32_t n, int32_t* lds) {
+    std::call_once(g_sched_once, load_schedule_env);
+    if (n < 1 || n > MAX_QUBITS || !lds) return fail(QE_ERR_INVALID, "width must be 1..6");
+    *lds = g_sched[n];
+    return QE_OK;
+}
+
+// ------------------------------------------------------------------- eval
+qe_status qe_eval_fitness(qe_ctx* ctx, const qe_batch* batch, int32_t path, float* f_dev,
+                          float* g_dev, float* delta_dev, void* stream) {
+    (void)ctx;
+    BatchArgs a;
+    QE_TRY(to_args(batch, &a, true));
+    if (path < QE_PATH_FP32 || path > QE_PATH_MFMA_FP16) return fail(QE_ERR_INVALID, "unknown path");
+    if (path >= QE_PATH_MFMA_BF16) return fail(QE_ERR_UNSUPPORTED, "MFMA paths are not built");
+    if (a.B > 0 && !f_dev) return fail(QE_ERR_INVALID, "f_dev is NULL");
+    QE_HIP(launch_eval_fp32(a, path, f_dev, g_dev, delta_dev, (hipStream_t)stream));
+    return QE_OK;
+}
+
+qe_status qe_eval_fitness_fp64(const qe_batch* batch, double* f_dev, double* g_dev,
+                               double* delta_dev, void* stream) {
+    BatchArgs a;
+    QE_TRY(to_args(batch, &a, true));
+    if (a.B > 0 && !f_dev) return fail(QE_ERR_INVALID, "f_dev is NULL");
+    QE_HIP(launch_eval_lds(a, true, f_dev, g_dev, delta_dev, (hipStream_t)stream));
+    return QE_OK;
+}
+
+qe_status qe_build_unitary(const qe_batch* batch, int32_t precision, void* out_dev,
+                           int64_t out_elems, void* stream) {
+    BatchArgs a;
+    QE_TRY(to_args(batch, &a, false));
+    if (a.uniform_n < 1) return fail(QE_ERR_INVALID, "qe_build_unitary needs uniform_n");
+    if (precision != 0 && precision != 1) return fail(QE_ERR_INVALID, "precision must be 0 or 1");
+    const int64_t need = (int64_t)a.B << (2 * a.uniform_n);
+    if (out_elems < need) return fail(QE_ERR_INVALID, "out_elems too small");
+    if (a.B > 0 && !out_dev) return fail(QE_ERR_INVALID, "out_dev is NULL");
+    QE_HIP(launch_unitary(a, precision == 1, out_dev, (hipStream_t)stream));
+    return QE_OK;
+}
+
+qe_status qe_device_errors(int32_t* flags_host) {
+    if (!flags_host) return fail(QE_ERR_INVALID, "flags_host is NULL");
+    uint32_t* w = nullptr;
+    QE_TRY(device_error_word(&w));
+    QE_HIP(hipDeviceSynchronize());
+    uint32_t v = 0;
+    QE_HIP(hipMemcpy(&v, w, sizeof(v), hipMemcpyDeviceToHost));
+    QE_HIP(hipMemset(w, 0, sizeof(uint32_t)));
+    QE_HIP(hipDeviceSynchronize());
+    *flags_host = (int32_t)v;
+    return QE_OK;
+}
+
+// ------------------------------------------------------------------ context
+qe_status qe_create(const qe_problem* p, qe_ctx** out) {
+    if (!p || !out) return fail(QE_ERR_INVALID, "NULL argument");
+    *out = nullptr;
+    const int n = p->n_qubits;
+    if (p->library != QE_LIB_NCV && p->library != QE_LIB_HT_NCV) return fail(QE_ERR_INVALID, "unknown library");
+    if (p->algorithm != QE_ALG_QEQEA && p->algorithm != QE_ALG_GA) return fail(QE_ERR_INVALID, "unknown algorithm");
+    if (n < 1 || n > MAX_QUBITS) return fail(QE_ERR_INVALID, "n_qubits must be 1..6");
+    if (p->algorithm == QE_ALG_QEQEA && n < 2) return fail(QE_ERR_INVALID, "QEQEA needs n_qubits >= 2");
+    if (p->algorithm == QE_ALG_QEQEA && p->library != QE_LIB_NCV)
+        return fail(QE_ERR_UNSUPPORTED, "QEQEA decodes to the library {I, NOT, CNOT, CV, CV+} only");
+    if (p->size_of_individual < 1 || p->size_of_individual > 1024) return fail(QE_ERR_INVALID, "L must be 1..1024");
+    if (p->size_of_population < 1 || p->size_of_population > 65536) return fail(QE_ERR_INVALID, "P must be 1..65536");
+    if (p->algorithm == QE_ALG_GA && p->size_of_population > 4096) return fail(QE_ERR_INVALID, "GA needs P <= 4096");
+    if (p->n_instances < 1) return fail(QE_ERR_INVALID, "n_instances must be >= 1");
+    const double pi2 = 2.0 * 3.14159265358979323846;
+    if (!(p->prob_mutation >= 0 && p->prob_mutation <= 1)) return fail(QE_ERR_INVALID, "prob_mutation must be in [0,1]");
+    if (!(p->mutation_range >= 0 && p->mutation_range < pi2)) return fail(QE_ERR_INVALID, "mutation_range must be in [0, 2 pi)");
+    if (!(p->ga_crossover_prob >= 0 && p->ga_crossover_prob <= 1)) return fail(QE_ERR_INVALID, "ga_crossover_prob must be in [0,1]");
+    if (!(p->ga_gene_mutation_prob >= 0 && p->ga_gene_mutation_prob <= 1)) return fail(QE_ERR_INVALID, "ga_gene_mutation_prob must be in [0,1]");
+    const size_t L = p->size_of_individual, P = p->size_of_population, I = p->n_instances;
+    const size_t S = (size_t)n * n * L * P, Q = (size_t)n * L * P;
+    if ((uint64_t)S >= (1ull << 32) || I * P * L >= (1ull << 32))
+        return fail(QE_ERR_INVALID, "encoding too large (slot indices are 32-bit)");
+    if (I > (1u << 31) / P) return fail(QE_ERR_INVALID, "too many instances");
+
+    qe_ctx* c = new qe_ctx();
+    c->prob = *p;
+    if (hipGetDevice(&c->device) != hipSuccess) { free_ctx(c); return fail(QE_ERR_DEVICE, "hipGetDevice"); }
+    c->N = 1 << n;
+    c->S = S;
+    c->Q = Q;
+    LoopArgs& a = c->la;
+    a.n = n; a.lib = p->library; a.L = (int)L; a.P = (int)P; a.I = (int)I;
+    a.seed = p->seed;
+    a.thr_pm = prob_threshold((double)p->prob_mutation);
+    a.thr_pc = prob_threshold((double)p->ga_crossover_prob);
+    a.thr_pg = prob_threshold((double)p->ga_gene_mutation_prob);
+    a.r32 = (float)((double)p->mutation_range / pi2 * 4294967296.0);
+    a.S = (uint32_t)S;
+    a.Q = (uint32_t)Q;
+    qe_status st = QE_OK;
+    const size_t NN = (size_t)c->N * c->N;
+#define ALLOC(ptr, n_) if (st == QE_OK) st = ctx_alloc(c, &(ptr), (n_))
+    if (p->algorithm == QE_ALG_QEQEA) {
+        ALLOC(a.theta, I * S);
+        ALLOC(a.best_theta, I * S);
+        ALLOC(a.best_f, I * S);
+        ALLOC(a.segfit, I * S);
+        ALLOC(a.qutrit, I * Q * 6);
+        ALLOC(a.best_qutrit, I * Q * 6);
+        ALLOC(a.su3_tab, (size_t)4 * SU3_TAB);
+    } else {
+        ALLOC(a.genomes[0], I * P * L);
+        ALLOC(a.genomes[1], I * P * L);
+    }
+    float* t32 = nullptr;
+    double* t64 = nullptr;
+    ALLOC(t32, I * NN * 2);
+    ALLOC(t64, I * NN * 2);
+    a.target32 = t32;
+    a.target64 = t64;
+    ALLOC(a.inst_best_f, I);
+    ALLOC(a.inst_best_gates, I * L);
+    ALLOC(c->slots, I * P * L);
+    ALLOC(c->gates, I * P * L);
+    ALLOC(c->f, I * P);
+    ALLOC(c->d_gen, 1);
+    ALLOC(c->elite_idx, I * P);
+#undef ALLOC
+    if (st == QE_OK) st = device_error_word(&a.err);
+    if (st != QE_OK) { std::string m = g_last_error; free_ctx(c); return fail(st, m); }
+    a.gen_ptr = nullptr;
+    hipError_t e = hipSuccess;
+    if (p->algorithm == QE_ALG_QEQEA) {
+        // SU(3) step tables: cos/sin of a*domain/4096, domain pi/2 (angles)
+        // and 2 pi (phases), computed in double, rounded to float.
+        std::vector<float> tab(4 * SU3_TAB);
+        for (int k = 0; k < SU3_TAB; ++k) {
+            const double th = (double)k * (3.14159265358979323846 / 2.0) / 4096.0;
+            const double ph = (double)k * (2.0 * 3.14159265358979323846) / 4096.0;
+            tab[k] = (float)std::cos(th);
+            tab[SU3_TAB + k] = (float)std::sin(th);
+            tab[2 * SU3_TAB + k] = (float)std::cos(ph);
+            tab[3 * SU3_TAB + k] = (float)std::sin(ph);
+        }
+        e = hipMemcpy((void*)a.su3_tab, tab.data(), tab.size() * sizeof(float), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = launch_qeqea_init(a, nullptr);
+    } else {
+        e = launch_ga_init(a, nullptr);
+    }
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        free_ctx(c);
+        return fail(QE_ERR_DEVICE, std::string("context initialisation: ") + hipGetErrorString(e));
+    }
+    *out = c;
+    return QE_OK;
+}
+
+qe_status qe_destroy(qe_ctx* c) {
+    if (!c) return fail(QE_ERR_INVALID, "ctx is NULL");
+    hipDeviceSynchronize();
+    free_ctx(c);
+    return QE_OK;
+}
+
+qe_status qe_set_targets(qe_ctx* c, const void* t, void* stream) {
+    QE_TRY(check_ctx(c, false));
+    if (!t) return fail(QE_ERR_INVALID, "targets is NULL");
+    const size_t reals = (size_t)c->prob.n_instances * c->N * c->N * 2;
+    hipStream_t s = (hipStream_t)stream;
+    QE_HIP(hipMemcpyAsync((void*)c->la.target64, t, reals * sizeof(double), hipMemcpyDeviceToDevice, s));
+    QE_HIP(launch_c128_to_c64(c->la.target64, (float*)c->la.target32, (int64_t)reals, s));
+    c->targets_set = true;
+    return QE_OK;
+}
+
+qe_status qe_sample(qe_ctx* c, uint64_t gen, uint32_t* slots, uint16_t* gates, void* stream) {
+    QE_TRY(check_ctx(c, false));
+    if (!gates) return fail(QE_ERR_INVALID, "gates is NULL");
+    LoopArgs a = c->la;
+    if (c->prob.algorithm == QE_ALG_QEQEA) {
+        if (!slots) return fail(QE_ERR_INVALID, "slots is NULL");
+        QE_HIP(launch_qeqea_sample(a, gen, slots, gates, (hipStream_t)stream));
+    } else {
+        QE_HIP(launch_ga_copy(a, gen, gates, (hipStream_t)stream));
+    }
+    return QE_OK;
+}
+
+qe_status qe_eval_population(qe_ctx* c, const uint16_t* gates, float* f, void* stream) {
+    QE_TRY(check_ctx(c, true));
+    if (!gates || !f) return fail(QE_ERR_INVALID, "NULL buffer");
+    QE_HIP(launch_eval_population(c->la, gates, f, (hipStream_t)stream));
+    return QE_OK;
+}
+
+qe_status qe_update(qe_ctx* c, uint64_t gen, const uint32_t* slots, const uint16_t* gates,
+                    const float* f, void* stream) {
+    QE_TRY(check_ctx(c, false));
+    if (!f || !gates) return fail(QE_ERR_INVALID, "NULL buffer");
+    hipStream_t s = (hipStream_t)stream;
+    if (c->prob.algorithm == QE_ALG_QEQEA) {
+        if (!slots) return fail(QE_ERR_INVALID, "slots is NULL");
+        QE_HIP(launch_scatter(c->la, gen, slots, f, s));
+        QE_HIP(launch_qeqea_update(c->la, gen, slots, gates, f, s));
+    } else {
+        QE_HIP(launch_ga_update(c->la, gen, f, s));
+    }
+    return QE_OK;
+}
+
+qe_status qe_generation(qe_ctx* c, uint64_t gen, float* f, void* stream) {
+    QE_TRY(check_ctx(c, true));
+    return enqueue_generation(c, c->la, gen, f ? f : c->f, (hipStream_t)stream);
+}
+
+qe_status qe_run_graph(qe_ctx* c, uint64_t first_gen, int32_t n_gen, float* f_hist, void* stream) {
+    QE_TRY(check_ctx(c, true));
+    if (n_gen < 1) return fail(QE_ERR_INVALID, "n_gen must be >= 1");
+    hipStream_t s = (hipStream_t)stream;
+    auto key = std::make_pair((int)n_gen, f_hist);
+    auto it = c->graphs.find(key);
+    if (it == c->graphs.end()) {
+        LoopArgs a = c->la;
+        a.gen_ptr = c->d_gen;
+        const size_t IP = (size_t)c->prob.n_instances * c->prob.size_of_population;
+        hipGraph_t g = nullptr;
+        QE_HIP(hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
+        qe_status st = QE_OK;
+        for (int j = 0; j < n_gen && st == QE_OK; ++j)
+            st = enqueue_generation(c, a, (uint64_t)j, f_hist ? f_hist + j * IP : c->f, c->capture_stream);
+        hipError_t e = hipStreamEndCapture(c->capture_stream, &g);
+        if (st != QE_OK) { if (g) hipGraphDestroy(g); return st; }
+        if (e != hipSuccess) return fail(QE_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+        hipGraphExec_t ex = nullptr;
+        e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        hipGraphDestroy(g);
+        if (e != hipSuccess) return fail(QE_ERR_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+        it = c->graphs.emplace(key, ex).first;
+    }
+    QE_HIP(launch_gen_set(c->d_gen, first_gen, s));
+    QE_HIP(hipGraphLaunch(it->second, s));
+    return QE_OK;
+}
+
+qe_status qe_elite_recheck(qe_ctx* c, const uint16_t* gates, const float* f, int32_t k,
+                           int32_t* idx, double* f64, void* stream) {
+    QE_TRY(check_ctx(c, true));
+    if (!gates || !f || !idx || !f64) return fail(QE_ERR_INVALID, "NULL buffer");
+    if (k < 1 || k > c->prob.size_of_population) return fail(QE_ERR_INVALID, "k must be 1..P");
+    if (c->prob.size_of_population > 4096) return fail(QE_ERR_UNSUPPORTED, "elite selection needs P <= 4096");
+    hipStream_t s = (hipStream_t)stream;
+    QE_HIP(launch_elite_select(c->la, f, k, idx, s));
+    QE_HIP(launch_elite_eval(c->la, gates, k, idx, f64, s));
+    return QE_OK;
+}
+
+qe_status qe_get_best(qe_ctx* c, int32_t inst, uint16_t* gates_host, float* f32_host,
+                      double* f64_host) {
+    QE_TRY(check_ctx(c, false));
+    if (inst < 0 || inst >= c->prob.n_instances) return fail(QE_ERR_INVALID, "instance out of range");
+    QE_HIP(hipDeviceSynchronize());
+    const int L = c->prob.size_of_individual;
+    float fv = 0;
+    QE_HIP(hipMemcpy(&fv, c->la.inst_best_f + inst, sizeof(float), hipMemcpyDeviceToHost));
+    if (gates_host)
+        QE_HIP(hipMemcpy(gates_host, c->la.inst_best_gates + (size_t)inst * L, L * sizeof(uint16_t),
+                         hipMemcpyDeviceToHost));
+    if (f32_host) *f32_host = fv;
+    if (f64_host) {
+        if (!c->targets_set) return fail(QE_ERR_STATE, "qe_set_targets has not been called");
+        qe_batch b{};
+        b.num_circuits = 1;
+        b.uniform_n = c->prob.n_qubits;
+        b.uniform_L = L;
+        b.gates_dev = c->la.inst_best_gates + (size_t)inst * L;
+        b.num_gates = L;
+        b.target_stride = 0;
+        b.targets_dev = c->la.target64 + (size_t)2 * inst * c->N * c->N;
+        b.num_target_elems = (int64_t)c->N * c->N;
+        double* d = nullptr;
+        QE_HIP(hipMalloc(&d, sizeof(double)));
+        qe_status st = qe_eval_fitness_fp64(&b, d, nullptr, nullptr, nullptr);
+        hipError_t e = st == QE_OK ? hipMemcpy(f64_host, d, sizeof(double), hipMemcpyDeviceToHost) : hipSuccess;
+        hipFree(d);
+        if (st != QE_OK) return st;
+        if (e != hipSuccess) return fail(QE_ERR_DEVICE, hipGetErrorString(e));
+    }
+    if (!(fv == fv)) return fail(QE_ERR_NUMERIC, "best fitness is NaN");
+    return QE_OK;
+}
+
+// ------------------------------------------------------ checkpoint / restore
+namespace {
+struct Section {
+    void* ptr;
+    size_t bytes;
+};
+
+std::vector<Section> state_sections(qe_ctx* c) {
+    const LoopArgs& a = c->la;
+    const size_t I = c->prob.n_instances, P = c->prob.size_of_population, L = c->prob.size_of_individual;
+    std::vector<Section> v;
+    if (c->prob.algorithm == QE_ALG_QEQEA) {
+        v.push_back({a.theta, I * c->S * 4});
+        v.push_back({a.best_theta, I * c->S * 4});
+        v.push_back({a.best_f, I * c->S * 4});
+        v.push_back({a.segfit, I * c->S * 4});
+        v.push_back({a.qutrit, I * c->Q * 24});
+        v.push_back({a.best_qutrit, I * c->Q * 24});
+    } else {
+        v.push_back({a.genomes[0], I * P * L * 2});
+        v.push_back({a.genomes[1], I * P * L * 2});
+    }
+    v.push_back({a.inst_best_f, I * 4});
+    v.push_back({a.inst_best_gates, I * L * 2});
+    return v;
+}
+
+struct CkptHeader {
+    char magic[8];
+    uint32_t version;
+    uint32_t reserved;
+    qe_problem prob;
+    uint64_t payload;
+};
+}  // namespace
+
+qe_status qe_checkpoint(qe_ctx* c, void* buf, size_t* size) {
+    QE_TRY(check_ctx(c, false));
+    if (!size) return fail(QE_ERR_INVALID, "size is NULL");
+    auto secs = state_sections(c);
+    size_t payload = 0;
+    for (auto& s : secs) payload += s.bytes;
+    const size_t need = sizeof(CkptHeader) + payload;
+    if (!buf) { *size = need; return QE_OK; }
+    if (*size < need) return fail(QE_ERR_INVALID, "checkpoint buffer too small");
+    QE_HIP(hipDeviceSynchronize());
+    CkptHeader h{};
+    std::memcpy(h.magic, "QECKPT01", 8);
+    h.version = 1;
+    h.prob = c->prob;
+    h.payload = payload;
+    std::memcpy(buf, &h, sizeof(h));
+    char* p = static_cast<char*>(buf) + sizeof(h);
+    for (auto& s : secs) {
+        QE_HIP(hipMemcpy(p, s.ptr, s.bytes, hipMemcpyDeviceToHost));
+        p += s.bytes;
+    }
+    *size = need;
+    return QE_OK;
+}
+
+qe_status qe_restore(qe_ctx* c, const void* buf, size_t size) {
+    QE_TRY(check_ctx(c, false));
+    if (!buf || size < sizeof(CkptHeader)) return fail(QE_ERR_INVALID, "checkpoint too small");
+    CkptHeader h;
+    std::memcpy(&h, buf, sizeof(h));
+    if (std::memcmp(h.magic, "QECKPT01", 8) != 0 || h.version != 1)
+        return fail(QE_ERR_INVALID, "not a libqe checkpoint");
+    if (std::memcmp(&h.prob, &c->prob, sizeof(qe_problem)) != 0)
+        return fail(QE_ERR_INVALID, "checkpoint was written for a different problem");
+    auto secs = state_sections(c);
+    size_t payload = 0;
+    for (auto& s : secs) payload += s.bytes;
+    if (h.payload != payload || size < sizeof(h) + payload) return fail(QE_ERR_INVALID, "checkpoint size mismatch");
+    QE_HIP(hipDeviceSynchronize());
+    const char* p = static_cast<const char*>(buf) + sizeof(h);
+    for (auto& s : secs) {
+        QE_HIP(hipMemcpy(s.ptr, p, s.bytes, hipMemcpyHostToDevice));
+        p += s.bytes;
+    }
+    QE_HIP(hipDeviceSynchronize());
+    return QE_OK;
+}
+
+qe_status qe_state_view(qe_ctx* c, int32_t which, void** ptr, int64_t* elems) {
+    QE_TRY(check_ctx(c, false));
+    if (!ptr || !elems) return fail(QE_ERR_INVALID, "NULL output");
+    const LoopArgs& a = c->la;
+    const size_t I = c->prob.n_instances, P = c->prob.size_of_population, L = c->prob.size_of_individual;
+    const bool q = c->prob.algorithm == QE_ALG_QEQEA;
+    switch (which) {
+        case 0: *ptr = a.theta; *elems = q ? (int64_t)(I * c->S) : 0; break;
+        case 1: *ptr = a.qutrit; *elems = q ? (int64_t)(I * c->Q * 6) : 0; break;
+        case 2: *ptr = a.best_f; *elems = q ? (int64_t)(I * c->S) : 0; break;
+        case 3: *ptr = a.best_theta; *elems = q ? (int64_t)(I * c->S) : 0; break;
+        case 4: *ptr = a.best_qutrit; *elems = q ? (int64_t)(I * c->Q * 6) : 0; break;
+        case 5: *ptr = a.genomes[0]; *elems = q ? 0 : (int64_t)(I * P * L); break;
+        case 6: *ptr = a.genomes[1]; *elems = q ? 0 : (int64_t)(I * P * L); break;
+        default: return fail(QE_ERR_INVALID, "unknown state view");
+    }
+    if (*elems == 0) *ptr = nullptr;
+    return QE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,66 @@
+// Device helpers shared by the libqe kernels (gfx950, wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "qe_common.hpp"
+
+namespace qe {
+
+// ---------------------------------------------------------------- Philox4x32-10
+// Counter-based generator of Salmon, Moraes, Dror and Shaw (SC'11): ten rounds
+// of two 32x32->64 multiplies with the Weyl key schedule.
+struct u32x4 {
+    uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ u32x4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                        uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+        const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return {c0, c1, c2, c3};
+}
+
+__device__ __forceinline__ u32x4 draw(uint64_t seed, uint32_t tag, uint32_t gen, uint32_t inst,
+                                      uint32_t item) {
+    return philox(tag, gen, inst, item, (uint32_t)seed, (uint32_t)(seed >> 32));
+}
+
+// floor(w * range / 2^32): a uniform integer in [0, range).
+__device__ __forceinline__ uint32_t scale_u32(uint32_t w, uint32_t range) {
+    return __umulhi(w, range);
+}
+
+// ------------------------------------------------------------------ descriptors
+__device__ __forceinline__ int desc_kind(uint32_t d) { return d & 15; }
+__device__ __forceinline__ int desc_tgt(uint32_t d) { return (d >> 4) & 15; }
+__device__ __forceinline__ int desc_ctl(uint32_t d) { return (d >> 8) & 15; }
+
+__device__ __forceinline__ bool desc_valid(uint32_t d, int n) {
+    const int k = d & 15, t = (d >> 4) & 15, c = (d >> 8) & 15;
+    if (d >> 12) return false;
+    if (k > KIND_T) return false;
+    if (k == KIND_I) return true;
+    if (t >= n) return false;
+    if (kind_controlled(k) && (c >= n || c == t)) return false;
+    return true;
+}
+
+// ------------------------------------------------------------- wave reductions
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+}  // namespace qe

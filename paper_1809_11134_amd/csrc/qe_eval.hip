@@ -1,0 +1,254 @@
+// Batched circuit-fitness kernels (Eq. 11 of Sec. IV-E) and unitary builders.
+#include "../../include/qe.h"
+#include "qe_eval_core.hpp"
+#include "qe_internal.hpp"
+
+namespace qe {
+
+constexpr int WPB = 4;   // wavefronts (circuits) per workgroup
+
+struct Item {
+    int n, L;
+    const uint16_t* g;
+    int64_t toff;
+    uint32_t err;
+};
+
+// Resolves circuit b of a batch (wave-uniform) and checks it against the
+// buffer bounds; err != 0 means the circuit must not be evaluated.
+__device__ __forceinline__ Item resolve(const BatchArgs& a, int b, bool need_target = true) {
+    Item it;
+    it.err = 0;
+    it.n = a.uniform_n > 0 ? a.uniform_n : (int)a.nq[b];
+    it.L = 0;
+    it.g = a.gates;
+    it.toff = 0;
+    if (it.n < 1 || it.n > MAX_QUBITS) { it.err = QE_DEVERR_WIDTH; return it; }
+    int64_t start, end;
+    if (a.uniform_L > 0) {
+        start = (int64_t)b * a.uniform_L;
+        end = start + a.uniform_L;
+    } else {
+        start = a.goff[b];
+        end = a.goff[b + 1];
+    }
+    if (start < 0 || end < start || end > a.num_gates) { it.err = QE_DEVERR_RANGE; return it; }
+    it.L = (int)(end - start);
+    it.g = a.gates + start;
+    if (!need_target) return it;
+    const int64_t NN = (int64_t)1 << (2 * it.n);
+    it.toff = a.tstride >= 0 ? (int64_t)b * a.tstride : a.toff[b];
+    if (it.toff < 0 || it.toff + NN > a.num_telems) { it.err = QE_DEVERR_RANGE; return it; }
+    return it;
+}
+
+// ------------------------------------------------------- FP32, one wave each
+// Register-resident path (n = 4..6) or one-element-per-lane path (n <= 3);
+// WPB circuits per workgroup.  FILTER: a mixed-width batch is served by one
+// launch per width, each skipping the circuits of other widths.
+template <int NQ, bool FILTER>
+__global__ __launch_bounds__(64 * WPB) void wave_kernel(BatchArgs a, float* __restrict__ f,
+                                                        float* __restrict__ g,
+                                                        float* __restrict__ delta) {
+    const int b = __builtin_amdgcn_readfirstlane(blockIdx.x * WPB + (threadIdx.x >> 6));
+    if (b >= a.B) return;
+    const int lane = (int)lane_id();
+    Item it = resolve(a, b);
+    if (FILTER && it.n != NQ) return;
+    if (it.err == 0 && it.n != NQ) it.err = QE_DEVERR_WIDTH;
+    FitOut o{__builtin_nanf(""), __builtin_nanf(""), __builtin_nanf("")};
+    if (it.err == 0) {
+        const uint16_t* gp = it.g;
+        const int L = it.L;
+        auto src = [&](int ch) -> uint32_t {
+            const int p = ch * 64 + lane;
+            return p < L ? (uint32_t)gp[p] : 0u;
+        };
+        const float* T = reinterpret_cast<const float*>(a.targets) + 2 * it.toff;
+        const bool ok = run_width<NQ, false>(NQ, T, L, src, nullptr, &o);
+        if (!ok) {
+            it.err = QE_DEVERR_DESC;
+            o = FitOut{__builtin_nanf(""), __builtin_nanf(""), __builtin_nanf("")};
+        } else if (!(o.f == o.f)) {
+            it.err = QE_DEVERR_NUMERIC;
+        }
+    }
+    if (lane == 0) {
+        f[b] = o.f;
+        if (g) g[b] = o.g;
+        if (delta) delta[b] = o.delta;
+        if (it.err) atomicOr(a.err, it.err);
+    }
+}
+
+// Marks circuits whose width is outside 1..6 (mixed-width batches only).
+__global__ void width_check_kernel(BatchArgs a, float* f, float* g, float* delta) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= a.B) return;
+    const int n = a.nq[b];
+    if (n >= 1 && n <= MAX_QUBITS) return;
+    f[b] = __builtin_nanf("");
+    if (g) g[b] = __builtin_nanf("");
+    if (delta) delta[b] = __builtin_nanf("");
+    atomicOr(a.err, (uint32_t)QE_DEVERR_WIDTH);
+}
+
+// LDS-staged path, W wavefronts per circuit (see run_lds_path).
+template <int NQ, int W, bool FILTER, bool IDENT>
+__global__ __launch_bounds__(64 * W) void lds32_kernel(BatchArgs a, float* __restrict__ f,
+                                                       float* __restrict__ g,
+                                                       float* __restrict__ delta,
+                                                       float* __restrict__ U_out) {
+    constexpr int N = 1 << NQ, CW = N / W;
+    __shared__ float2 M[N * N];
+    __shared__ float red[W][3];
+    const int b = blockIdx.x;
+    const int lane = (int)lane_id(), wave = (int)(threadIdx.x >> 6);
+    Item it = resolve(a, b, !IDENT);
+    if (FILTER && it.n != NQ) return;
+    if (it.err == 0 && it.n != NQ) it.err = QE_DEVERR_WIDTH;
+    bool ok = it.err == 0;
+    float off = 0.0f;
+    float2 dg = make_float2(0.0f, 0.0f);
+    if (ok) {
+        const uint16_t* gp = it.g;
+        const int L = it.L;
+        auto src = [&](int ch) -> uint32_t {
+            const int p = ch * 64 + lane;
+            return p < L ? (uint32_t)gp[p] : 0u;
+        };
+        const float* T = IDENT ? nullptr : reinterpret_cast<const float*>(a.targets) + 2 * it.toff;
+        ok = run_lds_path<NQ, W, IDENT>(M, T, L, src, IDENT ? nullptr : &off, &dg);
+        if (!ok) it.err = QE_DEVERR_DESC;
+    }
+    if (IDENT) {
+        __syncthreads();
+        float2* U = reinterpret_cast<float2*>(U_out) + (size_t)N * N * b;
+        const float nan = __builtin_nanf("");
+        for (int e = threadIdx.x; e < N * N; e += 64 * W) U[e] = ok ? M[e] : make_float2(nan, nan);
+        if (threadIdx.x == 0 && it.err) atomicOr(a.err, it.err);
+        return;
+    }
+    // fitness: reduce the per-wave partial sums over the workgroup
+    const float offw = wave_sum(off), trw = wave_sum(dg.x), tiw = wave_sum(dg.y);
+    if (lane == 0) { red[wave][0] = offw; red[wave][1] = trw; red[wave][2] = tiw; }
+    __syncthreads();
+    float offs = 0.0f, tr = 0.0f, ti = 0.0f;
+#pragma unroll
+    for (int w = 0; w < W; ++w) { offs += red[w][0]; tr += red[w][1]; ti += red[w][2]; }
+    const float am = sqrtf(tr * tr + ti * ti);
+    float er = 1.0f, ei = 0.0f;
+    if (am > 0.0f) { er = tr / am; ei = ti / am; }
+    float dl = 0.0f;
+    if (lane < CW) { const float xr = dg.x - er, xi = dg.y - ei; dl = xr * xr + xi * xi; }
+    const float dw = wave_sum(dl);
+    __syncthreads();
+    if (lane == 0) red[wave][0] = dw;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float D = 0.0f;
+#pragma unroll
+        for (int w = 0; w < W; ++w) D += red[w][0];
+        const float dlt = 0.5f * (offs + D);
+        float q = fminf(fmaxf(dlt / (float)N, 0.0f), 1.0f);
+        float fv = 1.0f - sqrtf(q);
+        const float nan = __builtin_nanf("");
+        if (ok && !(fv == fv)) it.err = QE_DEVERR_NUMERIC;
+        f[b] = ok ? fv : nan;
+        if (g) g[b] = ok ? am / (float)N : nan;
+        if (delta) delta[b] = ok ? dlt : nan;
+        if (it.err) atomicOr(a.err, it.err);
+    }
+}
+
+// --------------------------------------------------------- generic LDS path
+template <typename Real, bool IDENT>
+__global__ __launch_bounds__(256) void lds_kernel(BatchArgs a, Real* __restrict__ f,
+                                                  Real* __restrict__ g, Real* __restrict__ delta,
+                                                  Real* __restrict__ U_out) {
+    const int b = blockIdx.x;
+    Item it = resolve(a, b, !IDENT);
+    const Real* T = (IDENT || it.err) ? nullptr : reinterpret_cast<const Real*>(a.targets) + 2 * it.toff;
+    Real* U = nullptr;
+    if (IDENT) U = U_out + (size_t)2 * ((size_t)1 << (2 * a.uniform_n)) * b;
+    lds_generic_body<Real, IDENT>(it.n, it.L, it.g, T, it.err, f + (f ? b : 0),
+                                  g ? g + b : nullptr, delta ? delta + b : nullptr, U, a.err);
+}
+
+// ------------------------------------------------------------------ launchers
+// Per-width schedule: which kernel evaluates a circuit of width n on the
+// FP32 path.  path: QE_PATH_FP32 (default schedule), QE_PATH_FP32_REG,
+// QE_PATH_FP32_LDS.
+static bool use_lds(int n, int path) {
+    if (n <= 3) return false;
+    if (path == QE_PATH_FP32_REG) return false;
+    if (path == QE_PATH_FP32_LDS) return true;
+    return schedule_lds(n);
+}
+
+template <bool FILTER>
+static void launch_width(const BatchArgs& a, int n, bool lds, float* f, float* g, float* delta,
+                         hipStream_t s) {
+    const dim3 wgrid((a.B + WPB - 1) / WPB), wblock(64 * WPB);
+    if (lds) {
+        switch (n) {
+            case 4: lds32_kernel<4, 1, FILTER, false><<<a.B, 64, 0, s>>>(a, f, g, delta, nullptr); break;
+            case 5: lds32_kernel<5, 2, FILTER, false><<<a.B, 128, 0, s>>>(a, f, g, delta, nullptr); break;
+            default: lds32_kernel<6, 4, FILTER, false><<<a.B, 256, 0, s>>>(a, f, g, delta, nullptr); break;
+        }
+        return;
+    }
+    switch (n) {
+        case 1: wave_kernel<1, FILTER><<<wgrid, wblock, 0, s>>>(a, f, g, delta); break;
+        case 2: wave_kernel<2, FILTER><<<wgrid, wblock, 0, s>>>(a, f, g, delta); break;
+        case 3: wave_kernel<3, FILTER><<<wgrid, wblock, 0, s>>>(a, f, g, delta); break;
+        case 4: wave_kernel<4, FILTER><<<wgrid, wblock, 0, s>>>(a, f, g, delta); break;
+        case 5: wave_kernel<5, FILTER><<<wgrid, wblock, 0, s>>>(a, f, g, delta); break;
+        default: wave_kernel<6, FILTER><<<wgrid, wblock, 0, s>>>(a, f, g, delta); break;
+    }
+}
+
+hipError_t launch_eval_fp32(const BatchArgs& a, int path, float* f, float* g, float* delta,
+                            hipStream_t s) {
+    if (a.B == 0) return hipSuccess;
+    if (a.uniform_n > 0) {
+        launch_width<false>(a, a.uniform_n, use_lds(a.uniform_n, path), f, g, delta, s);
+    } else {
+        width_check_kernel<<<(a.B + 255) / 256, 256, 0, s>>>(a, f, g, delta);
+        for (int n = 1; n <= MAX_QUBITS; ++n)
+            launch_width<true>(a, n, use_lds(n, path), f, g, delta, s);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_eval_lds(const BatchArgs& a, bool fp64, void* f, void* g, void* delta,
+                           hipStream_t s) {
+    if (a.B == 0) return hipSuccess;
+    if (fp64)
+        lds_kernel<double, false><<<a.B, 256, 0, s>>>(a, (double*)f, (double*)g, (double*)delta,
+                                                      nullptr);
+    else
+        lds_kernel<float, false><<<a.B, 256, 0, s>>>(a, (float*)f, (float*)g, (float*)delta,
+                                                     nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_unitary(const BatchArgs& a, bool fp64, void* out, hipStream_t s) {
+    if (a.B == 0) return hipSuccess;
+    if (fp64) {
+        lds_kernel<double, true><<<a.B, 256, 0, s>>>(a, nullptr, nullptr, nullptr, (double*)out);
+    } else {
+        float* o = (float*)out;
+        switch (a.uniform_n) {
+            case 1: lds_kernel<float, true><<<a.B, 256, 0, s>>>(a, nullptr, nullptr, nullptr, o); break;
+            case 2: lds_kernel<float, true><<<a.B, 256, 0, s>>>(a, nullptr, nullptr, nullptr, o); break;
+            case 3: lds_kernel<float, true><<<a.B, 256, 0, s>>>(a, nullptr, nullptr, nullptr, o); break;
+            case 4: lds32_kernel<4, 1, false, true><<<a.B, 64, 0, s>>>(a, nullptr, nullptr, nullptr, o); break;
+            case 5: lds32_kernel<5, 2, false, true><<<a.B, 128, 0, s>>>(a, nullptr, nullptr, nullptr, o); break;
+            default: lds32_kernel<6, 4, false, true><<<a.B, 256, 0, s>>>(a, nullptr, nullptr, nullptr, o); break;
+        }
+    }
+    return hipGetLastError();
+}
+
+}  // namespace qe

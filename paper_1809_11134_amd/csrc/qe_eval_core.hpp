@@ -1,0 +1,705 @@
+// Per-circuit evaluation cores (one wavefront per circuit), gfx950.
+//
+// The hot path builds M = U T^dagger gate by gate starting from M_0 = T^dagger:
+// a gate G on wires (c, t) left-multiplies M, i.e. it mixes pairs of rows
+// (i, i ^ target bit) whose control bit is set.  tr(M_L) = tr(T^dagger U)
+// gives Eq. 11 of Sec. IV-E; the residual ||M_L - e^{i arg tr} I||_F^2 / 2
+// gives the same radicand without cancellation.
+//
+// Register layout (n = 4, 5, 6): the N x N complex matrix (N = 2^n) is spread
+// over the 64 lanes of a wavefront and E = N^2 / 64 registers per lane.  The
+// column index j occupies lane bits 0..n-1 and never moves (gates act on rows
+// only).  The n row bits ("slots") live either in register-index bits
+// 0..EB-1 (EB = 2n - 6) or in lane bits n..5.  A wave-uniform map records
+// which wire sits in which slot.  Before a gate the target wire is moved to
+// register bit 0 and a register-resident control to register bit EB-1, by
+// exchanging register bits (register renames) or a lane bit with a register
+// bit (v_permlane16/32_swap); a lane-resident control becomes an exec
+// predicate.  Every gate body is then one of a handful of fully unrolled
+// register loops, and no shuffle or LDS traffic is needed for the arithmetic.
+#pragma once
+#include "qe_device.hpp"
+
+namespace qe {
+
+__device__ __forceinline__ float bits_f(uint32_t u) { return __uint_as_float(u); }
+__device__ __forceinline__ uint32_t f_bits(float f) { return __float_as_uint(f); }
+
+// ----------------------------------------------------------- lane-bit swaps
+// Exchange lane bit 5 (LB = 5) or lane bit 4 (LB = 4) of the elements of
+// registers a (register bit 0) and b (register bit 1): after the call a holds
+// in its upper half-lanes what b held in its lower ones and vice versa.
+template <int LB>
+__device__ __forceinline__ void lane_swap(float& a, float& b) {
+    if constexpr (LB == 5) {
+        auto r = __builtin_amdgcn_permlane32_swap(f_bits(a), f_bits(b), false, false);
+        a = bits_f(r[0]);
+        b = bits_f(r[1]);
+    } else {
+        static_assert(LB == 4, "lane bit");
+        auto r = __builtin_amdgcn_permlane16_swap(f_bits(a), f_bits(b), false, false);
+        a = bits_f(r[0]);
+        b = bits_f(r[1]);
+    }
+}
+
+// ------------------------------------------------------------ register swaps
+// In-place exchange of two VGPRs.  Written as v_swap_b32 so that the values
+// stay in the registers the allocator gave the two variables: a plain C++
+// swap becomes a pair of renamed values that must be copied back at every
+// control-flow merge of the gate dispatch.
+__device__ __forceinline__ void vswap(float& a, float& b) {
+    asm volatile("v_swap_b32 %0, %1" : "+v"(a), "+v"(b));
+}
+
+// Exchange register bits A < B: element k with bit A set and bit B clear
+// trades places with k ^ (1<<A) ^ (1<<B).
+template <int E, int A, int B>
+__device__ __forceinline__ void swap_reg_bits(float* re, float* im) {
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+        if (((k >> A) & 1) == 1 && ((k >> B) & 1) == 0) {
+            const int k2 = k ^ (1 << A) ^ (1 << B);
+            vswap(re[k], re[k2]);
+            vswap(im[k], im[k2]);
+        }
+    }
+}
+
+// Exchange register bit R with lane bit LB.
+template <int E, int R, int LB>
+__device__ __forceinline__ void swap_lane_reg(float* re, float* im) {
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+        if (((k >> R) & 1) == 0) {
+            const int k2 = k | (1 << R);
+            lane_swap<LB>(re[k], re[k2]);
+            lane_swap<LB>(im[k], im[k2]);
+        }
+    }
+}
+
+template <int E, int EB>
+__device__ __forceinline__ void swap_reg_rt(int a, int b, float* re, float* im) {
+    // a < b < EB (wave-uniform)
+#define QE_SW(A, B)                                                  \
+    case (A)*8 + (B):                                                \
+        if constexpr ((B) < EB) swap_reg_bits<E, A, B>(re, im);      \
+        break;
+    switch (a * 8 + b) {
+        QE_SW(0, 1) QE_SW(0, 2) QE_SW(0, 3) QE_SW(0, 4) QE_SW(0, 5)
+        QE_SW(1, 2) QE_SW(1, 3) QE_SW(1, 4) QE_SW(1, 5)
+        QE_SW(2, 3) QE_SW(2, 4) QE_SW(2, 5)
+        QE_SW(3, 4) QE_SW(3, 5)
+        QE_SW(4, 5)
+        default: break;
+    }
+#undef QE_SW
+}
+
+template <int E, int EB>
+__device__ __forceinline__ void swap_lane_reg_rt(int r, int lb, float* re, float* im) {
+#define QE_LR(R)                                                                   \
+    case R:                                                                        \
+        if constexpr ((R) < EB) {                                                  \
+            if (lb == 5) swap_lane_reg<E, R, 5>(re, im);                           \
+            else swap_lane_reg<E, R, 4>(re, im);                                   \
+        }                                                                          \
+        break;
+    switch (r) {
+        QE_LR(0) QE_LR(1) QE_LR(2) QE_LR(3) QE_LR(4) QE_LR(5)
+        default: break;
+    }
+#undef QE_LR
+}
+
+// ------------------------------------------------------------------ slot map
+// Wave-uniform map between wires and slots, 4 bits per entry.
+struct SlotMap {
+    uint32_t w2s, s2w;
+    __device__ __forceinline__ int slot(int w) const { return (w2s >> (4 * w)) & 15; }
+    __device__ __forceinline__ int wire(int s) const { return (s2w >> (4 * s)) & 15; }
+    __device__ __forceinline__ void exchange(int a, int b) {
+        const int wa = wire(a), wb = wire(b);
+        s2w = (s2w & ~(15u << (4 * a)) & ~(15u << (4 * b))) | ((uint32_t)wb << (4 * a)) |
+              ((uint32_t)wa << (4 * b));
+        w2s = (w2s & ~(15u << (4 * wa)) & ~(15u << (4 * wb))) | ((uint32_t)b << (4 * wa)) |
+              ((uint32_t)a << (4 * wb));
+    }
+};
+
+// Exchange the contents of slots a != b (register bit < EB or lane bit).
+template <int NQ, int E, int EB>
+__device__ __forceinline__ void swap_slots(int a, int b, float* re, float* im, SlotMap& map) {
+    if (a > b) { const int t = a; a = b; b = t; }
+    if constexpr (EB == NQ) {   // every slot is a register bit
+        swap_reg_rt<E, EB>(a, b, re, im);
+    } else if (b < EB) {
+        swap_reg_rt<E, EB>(a, b, re, im);
+    } else if (a < EB) {
+        swap_lane_reg_rt<E, EB>(a, NQ + b - EB, re, im);
+    } else {
+        // both in lanes (n = 4): route through register bit 0
+        swap_lane_reg_rt<E, EB>(0, NQ + a - EB, re, im);
+        swap_lane_reg_rt<E, EB>(0, NQ + b - EB, re, im);
+        swap_lane_reg_rt<E, EB>(0, NQ + a - EB, re, im);
+    }
+    map.exchange(a, b);
+}
+
+// ---------------------------------------------------------------- gate bodies
+// Target at register bit 0.  CTL: 0 = uncontrolled, 1 = control at register
+// bit EB-1 (only the upper half of the registers is transformed).
+template <int E, int CTL>
+__device__ __forceinline__ void body_x(float* re, float* im) {
+#pragma unroll
+    for (int k = (CTL ? E / 2 : 0); k < E; k += 2) {
+        vswap(re[k], re[k + 1]);
+        vswap(im[k], im[k + 1]);
+    }
+}
+
+// V = (1/2)[[1+i, 1-i], [1-i, 1+i]]:  a' = (s + i d)/2, b' = (s - i d)/2 with
+// s = a + b, d = a - b.  V^dagger swaps the two outputs.
+template <int E, int CTL, bool DAG>
+__device__ __forceinline__ void body_v(float* re, float* im) {
+#pragma unroll
+    for (int k = (CTL ? E / 2 : 0); k < E; k += 2) {
+        const float p = re[k] + re[k + 1], q = im[k] + im[k + 1];
+        const float u = re[k] - re[k + 1], v = im[k] - im[k + 1];
+        const float xr = 0.5f * (p - v), xi = 0.5f * (q + u);
+        const float yr = 0.5f * (p + v), yi = 0.5f * (q - u);
+        if (DAG) { re[k] = yr; im[k] = yi; re[k + 1] = xr; im[k + 1] = xi; }
+        else     { re[k] = xr; im[k] = xi; re[k + 1] = yr; im[k + 1] = yi; }
+    }
+}
+
+template <int E>
+__device__ __forceinline__ void body_h(float* re, float* im) {
+    const float r = 0.70710678118654752f;
+#pragma unroll
+    for (int k = 0; k < E; k += 2) {
+        const float ar = re[k], ai = im[k], br = re[k + 1], bi = im[k + 1];
+        re[k] = (ar + br) * r; im[k] = (ai + bi) * r;
+        re[k + 1] = (ar - br) * r; im[k + 1] = (ai - bi) * r;
+    }
+}
+
+template <int E>
+__device__ __forceinline__ void body_t(float* re, float* im) {
+    const float r = 0.70710678118654752f;   // e^{i pi/4} = (1 + i)/sqrt(2)
+#pragma unroll
+    for (int k = 1; k < E; k += 2) {
+        const float br = re[k], bi = im[k];
+        re[k] = (br - bi) * r;
+        im[k] = (br + bi) * r;
+    }
+}
+
+// --------------------------------------------------------- fitness reduction
+struct FitOut {
+    float f, g, delta;
+};
+
+// Reduction of M (held as per-lane partial sums: off-diagonal |m|^2 and the
+// lane's diagonal element, if any) into Eq. 11.
+__device__ __forceinline__ FitOut finish_fitness(float off, float dre, float dim, bool hasd,
+                                                 int N) {
+    const float tre = wave_sum(dre), tim = wave_sum(dim);
+    const float offs = wave_sum(off);
+    const float a = sqrtf(tre * tre + tim * tim);
+    float er = 1.0f, ei = 0.0f;
+    if (a > 0.0f) { er = tre / a; ei = tim / a; }
+    float dl = 0.0f;
+    if (hasd) {
+        const float xr = dre - er, xi = dim - ei;
+        dl = xr * xr + xi * xi;
+    }
+    const float D = wave_sum(dl);
+    const float delta = 0.5f * (offs + D);
+    float q = delta / (float)N;
+    q = fminf(fmaxf(q, 0.0f), 1.0f);
+    FitOut o;
+    o.f = 1.0f - sqrtf(q);
+    o.g = a / (float)N;
+    o.delta = delta;
+    if (!(o.f == o.f) || !(delta == delta)) o.f = __builtin_nanf("");
+    return o;
+}
+
+// -------------------------------------------------------- register-path core
+// GateSrc: callable chunk(c) -> this lane's descriptor for position
+// c*64 + lane (0 beyond the circuit), evaluated by all lanes.
+// Returns false if a descriptor was invalid (the result is then garbage).
+template <int NQ, bool IDENT, typename GateSrc>
+__device__ __forceinline__ bool run_register_path(const float* __restrict__ T, int L,
+                                                  GateSrc&& src, float* U_out, FitOut* fit) {
+    constexpr int N = 1 << NQ;
+    constexpr int E = N * N / 64;
+    constexpr int EB = 2 * NQ - 6;
+    const int lane = (int)lane_id();
+    const int j = lane & (N - 1);
+    const int lr = lane >> NQ;
+    float re[E], im[E];
+    if (IDENT) {
+#pragma unroll
+        for (int k = 0; k < E; ++k) {
+            re[k] = ((k | (lr << EB)) == j) ? 1.0f : 0.0f;
+            im[k] = 0.0f;
+        }
+    } else {
+        // M_0 = T^dagger: element (i, j) = conj(T[j][i]); this lane's rows are
+        // i = lr*E + k, contiguous in row j of T.
+        const float2* src2 = reinterpret_cast<const float2*>(T) + (size_t)j * N + (size_t)lr * E;
+#pragma unroll
+        for (int k = 0; k < E; ++k) {
+            const float2 v = src2[k];
+            re[k] = v.x;
+            im[k] = -v.y;
+        }
+    }
+    // canonical map: wire w in slot n-1-w
+    SlotMap map;
+    map.w2s = 0; map.s2w = 0;
+#pragma unroll
+    for (int w = 0; w < NQ; ++w) {
+        map.w2s |= (uint32_t)(NQ - 1 - w) << (4 * w);
+        map.s2w |= (uint32_t)w << (4 * (NQ - 1 - w));
+    }
+    bool ok = true;
+    const int chunks = (L + 63) >> 6;
+    for (int ch = 0; ch < chunks; ++ch) {
+        const uint32_t dv = src(ch);
+        const int cnt = min(64, L - ch * 64);
+        const bool bad = (lane < cnt) && !desc_valid(dv, NQ);
+        if (__ballot(bad)) { ok = false; break; }
+        for (int g = 0; g < cnt; ++g) {
+            const uint32_t d = __builtin_amdgcn_readlane(dv, g);
+            const int kind = d & 15;
+            if (kind == KIND_I) continue;
+            const int t = (d >> 4) & 15;
+            const int st = map.slot(t);
+            if (st != 0) swap_slots<NQ, E, EB>(st, 0, re, im, map);
+            if (kind_controlled(kind)) {
+                const int c = (d >> 8) & 15;
+                const int sc = map.slot(c);
+                if (sc < EB) {
+                    if (sc != EB - 1) swap_slots<NQ, E, EB>(sc, EB - 1, re, im, map);
+                    if (kind == KIND_CNOT) body_x<E, 1>(re, im);
+                    else if (kind == KIND_CV) body_v<E, 1, false>(re, im);
+                    else body_v<E, 1, true>(re, im);
+                } else {
+                    const bool on = (lane >> (NQ + sc - EB)) & 1;
+                    if (on) {
+                        if (kind == KIND_CNOT) body_x<E, 0>(re, im);
+                        else if (kind == KIND_CV) body_v<E, 0, false>(re, im);
+                        else body_v<E, 0, true>(re, im);
+                    }
+                }
+            } else if (kind == KIND_NOT) {
+                body_x<E, 0>(re, im);
+            } else if (kind == KIND_H) {
+                body_h<E>(re, im);
+            } else {
+                body_t<E>(re, im);
+            }
+        }
+    }
+    // back to the canonical map (wire w in slot n-1-w)
+#pragma unroll
+    for (int w = 0; w < NQ; ++w) {
+        const int want = NQ - 1 - w;
+        const int s = map.slot(w);
+        if (s != want) swap_slots<NQ, E, EB>(s, want, re, im, map);
+    }
+    if (U_out) {
+        float2* dst = reinterpret_cast<float2*>(U_out);
+#pragma unroll
+        for (int k = 0; k < E; ++k) {
+            const int i = k | (lr << EB);
+            dst[(size_t)i * N + j] = make_float2(re[k], im[k]);
+        }
+    }
+    if (fit) {
+        const int key = ((j >> EB) == lr) ? (j & (E - 1)) : -1;
+        float off = 0.0f, dre = 0.0f, dim = 0.0f;
+#pragma unroll
+        for (int k = 0; k < E; ++k) {
+            const bool dg = (k == key);
+            const float m2 = re[k] * re[k] + im[k] * im[k];
+            off += dg ? 0.0f : m2;
+            dre = dg ? re[k] : dre;
+            dim = dg ? im[k] : dim;
+        }
+        *fit = finish_fitness(off, dre, dim, key >= 0, N);
+    }
+    return ok;
+}
+
+// ----------------------------------------------------- small widths (n <= 3)
+// One matrix element per lane (lane = i*N + j); a gate exchanges rows through
+// a lane xor.  Lanes >= N^2 hold nothing and only exchange among themselves.
+template <int NQ, bool IDENT, typename GateSrc>
+__device__ __forceinline__ bool run_small_path(const float* __restrict__ T, int L, GateSrc&& src,
+                                               float* U_out, FitOut* fit) {
+    constexpr int N = 1 << NQ;
+    const int lane = (int)lane_id();
+    const bool live = lane < N * N;
+    const int i = (lane >> NQ) & (N - 1), j = lane & (N - 1);
+    float mr = 0.0f, mi = 0.0f;
+    if (live) {
+        if (IDENT) {
+            mr = (i == j) ? 1.0f : 0.0f;
+        } else {
+            const float2 v = reinterpret_cast<const float2*>(T)[(size_t)j * N + i];
+            mr = v.x;
+            mi = -v.y;
+        }
+    }
+    bool ok = true;
+    const float r = 0.70710678118654752f;
+    const int chunks = (L + 63) >> 6;
+    for (int ch = 0; ch < chunks; ++ch) {
+        const uint32_t dv = src(ch);
+        const int cnt = min(64, L - ch * 64);
+        const bool bad = (lane < cnt) && !desc_valid(dv, NQ);
+        if (__ballot(bad)) { ok = false; break; }
+        for (int g = 0; g < cnt; ++g) {
+            const uint32_t d = __builtin_amdgcn_readlane(dv, g);
+            const int kind = d & 15;
+            if (kind == KIND_I) continue;
+            const int t = (d >> 4) & 15;
+            const int tb = 1 << (NQ - 1 - t);
+            const int mask = tb << NQ;
+            const float pr = __shfl_xor(mr, mask, 64), pi = __shfl_xor(mi, mask, 64);
+            const bool hi = (i & tb) != 0;
+            bool on = true;
+            if (kind_controlled(kind)) on = (i >> (NQ - 1 - ((d >> 8) & 15))) & 1;
+            if (!on) continue;
+            if (kind == KIND_NOT || kind == KIND_CNOT) {
+                mr = pr; mi = pi;
+            } else if (kind == KIND_CV || kind == KIND_CVDG) {
+                // both rows of the pair: (m + p)/2 +- i (m - p)/2
+                const float sr = mr + pr, si = mi + pi, dr = mr - pr, di = mi - pi;
+                if (kind == KIND_CV) { mr = 0.5f * (sr - di); mi = 0.5f * (si + dr); }
+                else { mr = 0.5f * (sr + di); mi = 0.5f * (si - dr); }
+            } else if (kind == KIND_H) {
+                const float xr = hi ? pr - mr : mr + pr, xi = hi ? pi - mi : mi + pi;
+                mr = xr * r; mi = xi * r;
+            } else if (hi) {   // T
+                const float br = mr, bi = mi;
+                mr = (br - bi) * r;
+                mi = (br + bi) * r;
+            }
+        }
+    }
+    if (U_out && live) reinterpret_cast<float2*>(U_out)[(size_t)i * N + j] = make_float2(mr, mi);
+    if (fit) {
+        const bool dg = live && (i == j);
+        const float off = (live && !dg) ? mr * mr + mi * mi : 0.0f;
+        *fit = finish_fitness(off, dg ? mr : 0.0f, dg ? mi : 0.0f, dg, N);
+    }
+    return ok;
+}
+
+// ------------------------------------------------------------ LDS-staged path
+// The circuit's N x N complex64 matrix lives in LDS, row-major.  W wavefronts
+// share one circuit and split its columns (CW = N / W each); since a gate only
+// mixes rows, every wavefront transforms its own columns with no barrier
+// between gates (LDS operations of one wavefront complete in order).  Lane l
+// owns column j = w*CW + l % CW and row group rg = l / CW; pass m of a gate
+// handles row pair pr = m*RG + rg (RG = 64 / CW), whose upper row index is
+// the pair index with a zero (and, for a controlled gate, a one) inserted at
+// the wire's bit position.  Insertion is additive over the disjoint bits of
+// m*RG and rg, so the per-lane part is computed once per gate and the pass
+// offset is wave-uniform.
+__device__ __forceinline__ int ins0(int x, int pos) {
+    return ((x >> pos) << (pos + 1)) | (x & ((1 << pos) - 1));
+}
+
+__device__ __forceinline__ void wave_lds_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int NIT>
+__device__ __forceinline__ void lds_pass_load(const float2* M, int base0, int base1,
+                                              const int* off, float2* A, float2* B, bool needA) {
+#pragma unroll
+    for (int m = 0; m < NIT; ++m) {
+        if (needA) A[m] = M[base0 + off[m]];
+        B[m] = M[base1 + off[m]];
+    }
+}
+
+// One gate on this wave's columns.  tpos/cpos: bit positions of the target /
+// control in the row index (cpos < 0: uncontrolled).
+template <int NQ, int CW, int KIND>
+__device__ __forceinline__ void lds_gate(float2* M, int j, int rg, int tpos, int cpos) {
+    constexpr int N = 1 << NQ, RG = 64 / CW;
+    const int tb = 1 << tpos;
+    const bool ctl = cpos >= 0;
+    if (!ctl) {
+        constexpr int NIT = (N / 2) / RG;
+        int off[NIT];
+#pragma unroll
+        for (int m = 0; m < NIT; ++m) off[m] = ins0(m * RG, tpos) * N;
+        const int base0 = ins0(rg, tpos) * N + j, base1 = base0 + tb * N;
+        float2 A[NIT], B[NIT];
+        lds_pass_load<NIT>(M, base0, base1, off, A, B, KIND != KIND_T);
+        const float r = 0.70710678118654752f;
+#pragma unroll
+        for (int m = 0; m < NIT; ++m) {
+            float2 a = A[m], b = B[m];
+            if constexpr (KIND == KIND_NOT) {
+                M[base0 + off[m]] = b; M[base1 + off[m]] = a;
+            } else if constexpr (KIND == KIND_H) {
+                M[base0 + off[m]] = make_float2((a.x + b.x) * r, (a.y + b.y) * r);
+                M[base1 + off[m]] = make_float2((a.x - b.x) * r, (a.y - b.y) * r);
+            } else {   // T
+                M[base1 + off[m]] = make_float2((b.x - b.y) * r, (b.x + b.y) * r);
+            }
+        }
+    } else {
+        constexpr int NIT = (N / 4) / RG;
+        const int lo = min(tpos, cpos), hi = max(tpos, cpos), cb = 1 << cpos;
+        int off[NIT];
+#pragma unroll
+        for (int m = 0; m < NIT; ++m) off[m] = ins0(ins0(m * RG, lo), hi) * N;
+        const int base0 = (ins0(ins0(rg, lo), hi) | cb) * N + j, base1 = base0 + tb * N;
+        float2 A[NIT], B[NIT];
+        lds_pass_load<NIT>(M, base0, base1, off, A, B, true);
+#pragma unroll
+        for (int m = 0; m < NIT; ++m) {
+            const float2 a = A[m], b = B[m];
+            if constexpr (KIND == KIND_CNOT) {
+                M[base0 + off[m]] = b; M[base1 + off[m]] = a;
+            } else {
+                const float p = a.x + b.x, q = a.y + b.y, u = a.x - b.x, v = a.y - b.y;
+                const float2 x = make_float2(0.5f * (p - v), 0.5f * (q + u));
+                const float2 y = make_float2(0.5f * (p + v), 0.5f * (q - u));
+                if constexpr (KIND == KIND_CV) { M[base0 + off[m]] = x; M[base1 + off[m]] = y; }
+                else { M[base0 + off[m]] = y; M[base1 + off[m]] = x; }
+            }
+        }
+    }
+}
+
+// Runs the circuit on this wave's columns and, with `fit`, leaves per-wave
+// partial sums for the fitness: off-diagonal |m|^2, and the diagonal
+// elements of the wave's columns (lane l < CW holds element (j, j)).
+template <int NQ, int W, bool IDENT, typename GateSrc>
+__device__ __forceinline__ bool run_lds_path(float2* M, const float* __restrict__ T, int L,
+                                             GateSrc&& src, float* off_out, float2* diag_out) {
+    constexpr int N = 1 << NQ, CW = N / W, RG = 64 / CW;
+    static_assert(CW <= 64 && 64 % CW == 0 && N % RG == 0, "layout");
+    const int lane = (int)lane_id();
+    const int wave = (int)(threadIdx.x >> 6);
+    const int jl = lane % CW, rg = lane / CW;
+    const int j = wave * CW + jl;
+    // M_0 = T^dagger (or I): M[r][j] = conj(T[j][r])
+    const float2* T2 = reinterpret_cast<const float2*>(T);
+#pragma unroll
+    for (int m = 0; m < N / RG; ++m) {
+        const int r = m * RG + rg;
+        float2 v;
+        if (IDENT) v = make_float2(r == j ? 1.0f : 0.0f, 0.0f);
+        else { v = T2[(size_t)j * N + r]; v.y = -v.y; }
+        M[r * N + j] = v;
+    }
+    wave_lds_fence();
+    bool ok = true;
+    const int chunks = (L + 63) >> 6;
+    for (int ch = 0; ch < chunks; ++ch) {
+        const uint32_t dv = src(ch);
+        const int cnt = min(64, L - ch * 64);
+        const bool bad = (lane < cnt) && !desc_valid(dv, NQ);
+        if (__ballot(bad)) { ok = false; break; }
+        for (int g = 0; g < cnt; ++g) {
+            const uint32_t d = __builtin_amdgcn_readlane(dv, g);
+            const int kind = d & 15;
+            if (kind == KIND_I) continue;
+            const int tpos = NQ - 1 - (int)((d >> 4) & 15);
+            const int cpos = NQ - 1 - (int)((d >> 8) & 15);
+            switch (kind) {
+                case KIND_NOT: lds_gate<NQ, CW, KIND_NOT>(M, j, rg, tpos, -1); break;
+                case KIND_CNOT: lds_gate<NQ, CW, KIND_CNOT>(M, j, rg, tpos, cpos); break;
+                case KIND_CV: lds_gate<NQ, CW, KIND_CV>(M, j, rg, tpos, cpos); break;
+                case KIND_CVDG: lds_gate<NQ, CW, KIND_CVDG>(M, j, rg, tpos, cpos); break;
+                case KIND_H: lds_gate<NQ, CW, KIND_H>(M, j, rg, tpos, -1); break;
+                default: lds_gate<NQ, CW, KIND_T>(M, j, rg, tpos, -1); break;
+            }
+            wave_lds_fence();
+        }
+    }
+    if (off_out) {
+        float off = 0.0f;
+#pragma unroll
+        for (int m = 0; m < N / RG; ++m) {
+            const int r = m * RG + rg;
+            const float2 v = M[r * N + j];
+            off += (r == j) ? 0.0f : v.x * v.x + v.y * v.y;
+        }
+        *off_out = off;
+        *diag_out = (lane < CW) ? M[j * N + j] : make_float2(0.0f, 0.0f);
+    }
+    return ok;
+}
+
+// ----------------------------------------------------- generic LDS body
+// One workgroup of 256 threads per circuit, any width 1..6, any precision:
+// M lives in LDS and every gate is one pass over the row pairs it touches,
+// followed by a workgroup barrier.  The FP64 instance re-checks elite
+// circuits and builds FP64 target unitaries; the FP32 one cross-checks the
+// tuned kernels.  err != 0 on entry: the circuit is malformed and only NaN is
+// written.  Outputs (f, g, delta: one element; U: N*N complex) may be null.
+template <typename Real>
+struct Cplx {
+    Real r, i;
+};
+
+template <typename Real>
+__device__ __forceinline__ void gate_coeffs(int kind, Cplx<Real> G[4]) {
+    const Real h = (Real)0.5, z = (Real)0, o = (Real)1;
+    const Real s = (Real)0.70710678118654752440084436210485;
+    switch (kind) {
+        case KIND_NOT: case KIND_CNOT:
+            G[0] = {z, z}; G[1] = {o, z}; G[2] = {o, z}; G[3] = {z, z}; break;
+        case KIND_CV:
+            G[0] = {h, h}; G[1] = {h, -h}; G[2] = {h, -h}; G[3] = {h, h}; break;
+        case KIND_CVDG:
+            G[0] = {h, -h}; G[1] = {h, h}; G[2] = {h, h}; G[3] = {h, -h}; break;
+        case KIND_H:
+            G[0] = {s, z}; G[1] = {s, z}; G[2] = {s, z}; G[3] = {-s, z}; break;
+        default:   // T
+            G[0] = {o, z}; G[1] = {z, z}; G[2] = {z, z}; G[3] = {s, s}; break;
+    }
+}
+
+template <typename Real>
+__device__ __forceinline__ Real block_sum(Real v, Real* scratch) {
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) scratch[w] = v;
+    __syncthreads();
+    Real t = 0;
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += scratch[k];
+    return t;
+}
+
+template <typename Real, bool IDENT>
+__device__ __forceinline__ void lds_generic_body(int n, int L, const uint16_t* gates,
+                                                 const Real* T, uint32_t err, Real* f, Real* g,
+                                                 Real* delta, Real* U, uint32_t* errw) {
+    __shared__ Real Mr[4096], Mi[4096];
+    __shared__ Real red[8];
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int N = 1 << (err == QE_DEVERR_WIDTH ? 1 : n);
+    const int NN = N * N;
+    bool ok = err == 0;
+    if (ok) {
+        for (int e = tid; e < NN; e += nt) {
+            const int i = e / N, j = e % N;
+            if (IDENT) {
+                Mr[e] = (i == j) ? (Real)1 : (Real)0;
+                Mi[e] = 0;
+            } else {
+                Mr[e] = T[2 * ((size_t)j * N + i)];
+                Mi[e] = -T[2 * ((size_t)j * N + i) + 1];
+            }
+        }
+        __syncthreads();
+        for (int l = 0; l < L; ++l) {
+            const uint32_t d = gates[l];
+            if (!desc_valid(d, n)) { ok = false; break; }
+            const int kind = d & 15;
+            if (kind == KIND_I) continue;
+            const int tpos = n - 1 - (int)((d >> 4) & 15);
+            const int tb = 1 << tpos;
+            const int cb = kind_controlled(kind) ? 1 << (n - 1 - (int)((d >> 8) & 15)) : 0;
+            Cplx<Real> G[4];
+            gate_coeffs<Real>(kind, G);
+            for (int e = tid; e < NN / 2; e += nt) {
+                const int p = e / N, j = e % N;
+                const int i0 = ((p >> tpos) << (tpos + 1)) | (p & (tb - 1));
+                if (cb && !(i0 & cb)) continue;
+                const int i1 = i0 | tb;
+                const Real ar = Mr[i0 * N + j], ai = Mi[i0 * N + j];
+                const Real br = Mr[i1 * N + j], bi = Mi[i1 * N + j];
+                Mr[i0 * N + j] = G[0].r * ar - G[0].i * ai + G[1].r * br - G[1].i * bi;
+                Mi[i0 * N + j] = G[0].r * ai + G[0].i * ar + G[1].r * bi + G[1].i * br;
+                Mr[i1 * N + j] = G[2].r * ar - G[2].i * ai + G[3].r * br - G[3].i * bi;
+                Mi[i1 * N + j] = G[2].r * ai + G[2].i * ar + G[3].r * bi + G[3].i * br;
+            }
+            __syncthreads();
+        }
+        if (!ok) err = QE_DEVERR_DESC;
+    }
+    const Real nan = (Real)__builtin_nan("");
+    if (IDENT) {
+        if (U)
+            for (int e = tid; e < NN; e += nt) {
+                U[2 * e] = ok ? Mr[e] : nan;
+                U[2 * e + 1] = ok ? Mi[e] : nan;
+            }
+        if (tid == 0 && err) atomicOr(errw, err);
+        return;
+    }
+    Real off = 0, tr = 0, ti = 0;
+    if (ok) {
+        for (int e = tid; e < NN; e += nt) {
+            const int i = e / N, j = e % N;
+            if (i == j) { tr += Mr[e]; ti += Mi[e]; }
+            else off += Mr[e] * Mr[e] + Mi[e] * Mi[e];
+        }
+    }
+    tr = block_sum(tr, red);
+    ti = block_sum(ti, red);
+    off = block_sum(off, red);
+    const Real am = sqrt(tr * tr + ti * ti);
+    Real er = 1, ei = 0;
+    if (am > 0) { er = tr / am; ei = ti / am; }
+    Real D = 0;
+    if (ok)
+        for (int i = tid; i < N; i += nt) {
+            const Real xr = Mr[i * N + i] - er, xi = Mi[i * N + i] - ei;
+            D += xr * xr + xi * xi;
+        }
+    D = block_sum(D, red);
+    if (tid == 0) {
+        const Real dl = (Real)0.5 * (off + D);
+        Real q = dl / (Real)N;
+        q = q < 0 ? (Real)0 : (q > 1 ? (Real)1 : q);
+        const Real fv = (Real)1 - sqrt(q);
+        if (ok && !(fv == fv)) err = QE_DEVERR_NUMERIC;
+        if (f) *f = ok ? fv : nan;
+        if (g) *g = ok ? am / (Real)N : nan;
+        if (delta) *delta = ok ? dl : nan;
+        if (err) atomicOr(errw, err);
+    }
+}
+
+template <bool IDENT, typename GateSrc>
+__device__ __forceinline__ bool run_any_width(int n, const float* __restrict__ T, int L,
+                                              GateSrc&& src, float* U_out, FitOut* fit) {
+    switch (n) {
+        case 1: return run_small_path<1, IDENT>(T, L, src, U_out, fit);
+        case 2: return run_small_path<2, IDENT>(T, L, src, U_out, fit);
+        case 3: return run_small_path<3, IDENT>(T, L, src, U_out, fit);
+        case 4: return run_register_path<4, IDENT>(T, L, src, U_out, fit);
+        case 5: return run_register_path<5, IDENT>(T, L, src, U_out, fit);
+        default: return run_register_path<6, IDENT>(T, L, src, U_out, fit);
+    }
+}
+
+template <int NQ, bool IDENT, typename GateSrc>
+__device__ __forceinline__ bool run_width(int n, const float* __restrict__ T, int L, GateSrc&& src,
+                                          float* U_out, FitOut* fit) {
+    if constexpr (NQ == 0) return run_any_width<IDENT>(n, T, L, src, U_out, fit);
+    else if constexpr (NQ <= 3) return run_small_path<NQ, IDENT>(T, L, src, U_out, fit);
+    else return run_register_path<NQ, IDENT>(T, L, src, U_out, fit);
+}
+
+}  // namespace qe

@@ -1,0 +1,84 @@
+// Internal interface between the libqe host code and its kernel translation
+// units (launchers run on the caller's stream and return hipError_t).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace qe {
+
+struct BatchArgs {
+    int32_t B;
+    int32_t uniform_n;
+    const int8_t* nq;
+    int32_t uniform_L;
+    const int32_t* goff;
+    const uint16_t* gates;
+    int64_t num_gates;
+    int64_t tstride;
+    const int64_t* toff;
+    const void* targets;
+    int64_t num_telems;
+    uint32_t* err;          // device error word (atomicOr of QE_DEVERR_*)
+};
+
+// api.hip: per-width schedule of the FP32 path (true = LDS-staged kernel)
+bool schedule_lds(int n);
+
+// eval.hip
+hipError_t launch_eval_fp32(const BatchArgs& a, int path, float* f, float* g, float* delta,
+                            hipStream_t s);
+hipError_t launch_eval_lds(const BatchArgs& a, bool fp64, void* f, void* g, void* delta,
+                           hipStream_t s);
+hipError_t launch_unitary(const BatchArgs& a, bool fp64, void* out, hipStream_t s);
+
+// Encoding-state arguments of the QEQEA / GA loop kernels.
+struct LoopArgs {
+    int32_t n, lib, L, P, I;
+    uint64_t seed;
+    uint64_t thr_pm, thr_pc, thr_pg;   // probability thresholds, floor(p * 2^32)
+    float r32;                         // mutation step per unit (1 - segFit), in 2^-32 turns
+    uint32_t S;                        // slots per instance: n*n*L*P
+    uint32_t Q;                        // qutrits per instance: n*L*P
+    uint32_t* theta;
+    float* qutrit;
+    float* best_f;
+    uint32_t* best_theta;
+    float* best_qutrit;
+    int32_t* segfit;                   // fitness bits, -1 = unused
+    uint16_t* genomes[2];              // GA double buffer
+    const float* target32;             // [I][N][N] complex64
+    const double* target64;            // [I][N][N] complex128
+    uint64_t* inst_best_key;           // per instance (f bits << 32 | ~index) of best ever
+    float* inst_best_f;                // per instance
+    uint16_t* inst_best_gates;         // [I][L]
+    const float* su3_tab;              // [4][4096]: cos/sin of angles, cos/sin of phases
+    const uint64_t* gen_ptr;           // device generation base (graphs) or null
+    uint32_t* err;
+};
+
+// loop.hip
+hipError_t launch_qeqea_init(const LoopArgs& a, hipStream_t s);
+hipError_t launch_ga_init(const LoopArgs& a, hipStream_t s);
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
+hipError_t launch_qeqea_sample(const LoopArgs& a, uint64_t gen, uint32_t* slots, uint16_t* gates,
+                               hipStream_t s);
+hipError_t launch_ga_copy(const LoopArgs& a, uint64_t gen, uint16_t* gates, hipStream_t s);
+hipError_t launch_eval_population(const LoopArgs& a, const uint16_t* gates, float* f,
+                                  hipStream_t s);
+hipError_t launch_qeqea_fused(const LoopArgs& a, uint64_t gen, uint32_t* slots, uint16_t* gates,
+                              float* f, hipStream_t s);
+hipError_t launch_scatter(const LoopArgs& a, uint64_t gen, const uint32_t* slots, const float* f,
+                          hipStream_t s);
+hipError_t launch_qeqea_update(const LoopArgs& a, uint64_t gen, const uint32_t* slots,
+                               const uint16_t* gates, const float* f, hipStream_t s);
+hipError_t launch_ga_eval(const LoopArgs& a, uint64_t gen, float* f, hipStream_t s);
+hipError_t launch_ga_update(const LoopArgs& a, uint64_t gen, const float* f, hipStream_t s);
+hipError_t launch_c128_to_c64(const double* src, float* dst, int64_t n_reals, hipStream_t s);
+hipError_t launch_gen_advance(uint64_t* gen_ptr, uint64_t by, hipStream_t s);
+hipError_t launch_gen_set(uint64_t* gen_ptr, uint64_t v, hipStream_t s);
+hipError_t launch_elite_select(const LoopArgs& a, const float* f, int k, int32_t* idx,
+                               hipStream_t s);
+hipError_t launch_elite_eval(const LoopArgs& a, const uint16_t* gates, int k, const int32_t* idx,
+                             double* f64, hipStream_t s);
+
+}  // namespace qe

@@ -1,0 +1,665 @@
+// The cheap loop around the fitness evaluation: circuit construction by
+// sampling the encoding (Sec. IV-D), segment fitness / elitism / adaptive
+// mutation (Secs. IV-E.1, IV-F), the GA operators of Sec. V-B, population
+// initialisation (Sec. IV-B) and the FP64 re-check of elite circuits.
+//
+// Everything that decides an integer or updates the encoding is written one
+// rounding per operation (floating-point contraction is switched off below)
+// so that it is reproducible bit for bit.
+#include "../../include/qe.h"
+#include "qe_eval_core.hpp"
+#include "qe_internal.hpp"
+
+#pragma clang fp contract(off)
+
+namespace qe {
+
+__device__ __forceinline__ uint32_t gen_of(const LoopArgs& a, uint64_t gen) {
+    return (uint32_t)(a.gen_ptr ? *a.gen_ptr + gen : gen);
+}
+
+// ------------------------------------------------------------- measurement
+// Born-rule measurement of a qutrit (3 complex amplitudes, unnormalised):
+// u in [0,1) from the top 24 bits of w scales the cumulative weights.
+__device__ __forceinline__ int measure_qutrit(const float* q, uint32_t w) {
+    const float2 a0 = *reinterpret_cast<const float2*>(q);
+    const float2 a1 = *reinterpret_cast<const float2*>(q + 2);
+    const float2 a2 = *reinterpret_cast<const float2*>(q + 4);
+    const float p0 = __fadd_rn(__fmul_rn(a0.x, a0.x), __fmul_rn(a0.y, a0.y));
+    const float p1 = __fadd_rn(__fmul_rn(a1.x, a1.x), __fmul_rn(a1.y, a1.y));
+    const float p2 = __fadd_rn(__fmul_rn(a2.x, a2.x), __fmul_rn(a2.y, a2.y));
+    const float c0 = p0, c1 = __fadd_rn(c0, p1), c2 = __fadd_rn(c1, p2);
+    const float u = __fmul_rn((float)(w >> 8), 0x1p-24f);
+    const float x = __fmul_rn(u, c2);
+    return x < c0 ? 0 : (x < c1 ? 1 : 2);
+}
+
+// Decodes slot s of instance i: rotation slot -> NOT on its wire when the
+// measured axis is x and the angle rounds to a half turn, else I; template
+// slot (c, t) -> controlled V^q with q the angle in quarter turns.
+__device__ __forceinline__ uint16_t decode_slot(const LoopArgs& a, uint32_t gen, uint32_t i,
+                                                uint32_t s) {
+    const uint32_t LP = (uint32_t)a.L * (uint32_t)a.P;
+    const uint32_t r = s / LP;
+    const uint32_t th = a.theta[(size_t)i * a.S + s];
+    const int q = (int)(((th + 0x20000000u) >> 30) & 3u);
+    if (r < (uint32_t)a.n) {
+        const u32x4 w = draw(a.seed, TAG_MEASURE, gen, i, s);
+        const int axis = measure_qutrit(a.qutrit + 6 * ((size_t)i * a.Q + s), w.x);
+        return (axis == 0 && q == 2) ? make_desc(KIND_NOT, (int)r, 0) : (uint16_t)0;
+    }
+    if (q == 0) return 0;
+    int c, t;
+    pair_of(a.n, (int)r - a.n, &c, &t);
+    const int kind = q == 1 ? KIND_CV : (q == 2 ? KIND_CNOT : KIND_CVDG);
+    return make_desc(kind, t, c);
+}
+
+// Segment index of Eq. 10 for circuit k, position pos of instance i.
+__device__ __forceinline__ uint32_t sample_slot(const LoopArgs& a, uint32_t gen, uint32_t i,
+                                                uint32_t k, uint32_t pos) {
+    const u32x4 w = draw(a.seed, TAG_SAMPLE, gen, i, k * (uint32_t)a.L + pos);
+    const uint32_t ind = scale_u32(w.x, (uint32_t)a.P);
+    const uint32_t region = scale_u32(w.y, (uint32_t)(a.n * a.n));
+    return region * (uint32_t)a.L * (uint32_t)a.P + ind * (uint32_t)a.L + pos;
+}
+
+// --------------------------------------------------------------------- init
+__global__ void qeqea_init_kernel(LoopArgs a, float amp) {
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t total = (size_t)a.I * a.S;
+    if (idx >= total) return;
+    const uint32_t i = (uint32_t)(idx / a.S), s = (uint32_t)(idx % a.S);
+    const u32x4 w = draw(a.seed, TAG_INIT, GEN_INIT, i, s);
+    a.theta[idx] = w.x;
+    a.best_theta[idx] = w.x;
+    a.best_f[idx] = -1.0f;
+    a.segfit[idx] = -1;
+    if (s < a.Q) {
+        float* q = a.qutrit + 6 * ((size_t)i * a.Q + s);
+        float* bq = a.best_qutrit + 6 * ((size_t)i * a.Q + s);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            q[c] = (c & 1) ? 0.0f : amp;
+            bq[c] = q[c];
+        }
+    }
+}
+
+__global__ void ga_init_kernel(LoopArgs a) {
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t per = (size_t)a.P * a.L;
+    if (idx >= (size_t)a.I * per) return;
+    const uint32_t i = (uint32_t)(idx / per), item = (uint32_t)(idx % per);
+    const u32x4 w = draw(a.seed, TAG_INIT, GEN_INIT, i, item);
+    a.genomes[0][idx] = lib_desc(a.lib, a.n, (int)scale_u32(w.x, (uint32_t)lib_size(a.lib, a.n)));
+}
+
+__global__ void inst_best_init_kernel(LoopArgs a) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.I) return;
+    a.inst_best_f[i] = -1.0f;
+    for (int l = 0; l < a.L; ++l) a.inst_best_gates[(size_t)i * a.L + l] = 0;
+}
+
+__global__ void fill_i32_kernel(int32_t* p, int64_t n, int32_t v) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx < n) p[idx] = v;
+}
+
+__global__ void gen_advance_kernel(uint64_t* g, uint64_t by) { *g += by; }
+__global__ void gen_set_kernel(uint64_t* g, uint64_t v) { *g = v; }
+
+// ---------------------------------------------------------------- sampling
+__global__ void qeqea_sample_kernel(LoopArgs a, uint64_t gen64, uint32_t* __restrict__ slots,
+                                    uint16_t* __restrict__ gates) {
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t per = (size_t)a.P * a.L;
+    if (idx >= (size_t)a.I * per) return;
+    const uint32_t gen = gen_of(a, gen64);
+    const uint32_t i = (uint32_t)(idx / per), rem = (uint32_t)(idx % per);
+    const uint32_t k = rem / a.L, pos = rem % a.L;
+    const uint32_t s = sample_slot(a, gen, i, k, pos);
+    slots[idx] = s;
+    gates[idx] = decode_slot(a, gen, i, s);
+}
+
+__global__ void ga_copy_kernel(LoopArgs a, uint64_t gen64, uint16_t* __restrict__ gates) {
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (size_t)a.I * a.P * a.L) return;
+    gates[idx] = a.genomes[gen_of(a, gen64) & 1][idx];
+}
+
+// -------------------------------------------- population evaluation (FP32)
+// One circuit per wavefront (register / per-lane layouts) or per workgroup
+// (LDS layout); the target is the circuit's instance target.
+template <int NQ, int W, bool SAMPLE>
+__device__ __forceinline__ void eval_circuit(const LoopArgs& a, uint32_t gen, uint32_t ci,
+                                             const uint16_t* gates_in, uint32_t* slots_out,
+                                             uint16_t* gates_out, float* f_out, bool writer) {
+    const uint32_t i = ci / (uint32_t)a.P, k = ci % (uint32_t)a.P;
+    const int lane = (int)lane_id();
+    const int L = a.L;
+    const float* T = a.target32 + (size_t)2 * i * ((size_t)1 << (2 * NQ));
+    auto src = [&](int ch) -> uint32_t {
+        const int p = ch * 64 + lane;
+        if (p >= L) return 0u;
+        if (!SAMPLE) return (uint32_t)gates_in[(size_t)ci * L + p];
+        const uint32_t s = sample_slot(a, gen, i, k, (uint32_t)p);
+        const uint16_t d = decode_slot(a, gen, i, s);
+        if (writer) {
+            slots_out[(size_t)ci * L + p] = s;
+            gates_out[(size_t)ci * L + p] = d;
+        }
+        return (uint32_t)d;
+    };
+    float fv;
+    bool ok;
+    if constexpr (W == 0) {
+        FitOut o;
+        ok = run_width<NQ, false>(NQ, T, L, src, nullptr, &o);
+        fv = o.f;
+    } else {
+        constexpr int N = 1 << NQ, CW = N / W;
+        __shared__ float2 M[N * N];
+        __shared__ float red[W][3];
+        float off;
+        float2 dg;
+        const int wave = (int)(threadIdx.x >> 6);
+        ok = run_lds_path<NQ, W, false>(M, T, L, src, &off, &dg);
+        const float offw = wave_sum(off), trw = wave_sum(dg.x), tiw = wave_sum(dg.y);
+        if (lane == 0) { red[wave][0] = offw; red[wave][1] = trw; red[wave][2] = tiw; }
+        __syncthreads();
+        float offs = 0.0f, tr = 0.0f, ti = 0.0f;
+#pragma unroll
+        for (int w = 0; w < W; ++w) { offs += red[w][0]; tr += red[w][1]; ti += red[w][2]; }
+        const float am = sqrtf(tr * tr + ti * ti);
+        float er = 1.0f, ei = 0.0f;
+        if (am > 0.0f) { er = tr / am; ei = ti / am; }
+        float dl = 0.0f;
+        if (lane < CW) { const float xr = dg.x - er, xi = dg.y - ei; dl = xr * xr + xi * xi; }
+        const float dw = wave_sum(dl);
+        __syncthreads();
+        if (lane == 0) red[wave][0] = dw;
+        __syncthreads();
+        float D = 0.0f;
+#pragma unroll
+        for (int w = 0; w < W; ++w) D += red[w][0];
+        const float q = fminf(fmaxf(0.5f * (offs + D) / (float)N, 0.0f), 1.0f);
+        fv = 1.0f - sqrtf(q);
+    }
+    if (!ok) fv = __builtin_nanf("");
+    if (writer && lane == 0) {
+        f_out[ci] = fv;
+        if (!ok) atomicOr(a.err, (uint32_t)QE_DEVERR_DESC);
+        else if (!(fv == fv)) atomicOr(a.err, (uint32_t)QE_DEVERR_NUMERIC);
+    }
+    // segment fitness: every slot this circuit used keeps the largest fitness
+    if (SAMPLE && writer && fv >= 0.0f) {
+        const int32_t fb = (int32_t)__float_as_uint(fv);
+        for (int p = lane; p < L; p += 64) {
+            const uint32_t s = sample_slot(a, gen, i, k, (uint32_t)p);
+            atomicMax(a.segfit + (size_t)i * a.S + s, fb);
+        }
+    }
+}
+
+template <int NQ, int W, bool SAMPLE>
+__global__ __launch_bounds__(256) void population_kernel(LoopArgs a, uint64_t gen64,
+                                                         const uint16_t* __restrict__ gates_in,
+                                                         uint32_t* __restrict__ slots_out,
+                                                         uint16_t* __restrict__ gates_out,
+                                                         float* __restrict__ f_out) {
+    const uint32_t gen = gen_of(a, gen64);
+    const uint32_t total = (uint32_t)a.I * (uint32_t)a.P;
+    if constexpr (W == 0) {
+        const uint32_t ci = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+        if (ci >= total) return;
+        eval_circuit<NQ, 0, SAMPLE>(a, gen, ci, gates_in, slots_out, gates_out, f_out, true);
+    } else {
+        const uint32_t ci = blockIdx.x;
+        if (ci >= total) return;
+        eval_circuit<NQ, W, SAMPLE>(a, gen, ci, gates_in, slots_out, gates_out, f_out,
+                                    threadIdx.x < 64);
+    }
+}
+
+// -------------------------------------------------------------- scatter-max
+__global__ void scatter_kernel(LoopArgs a, const uint32_t* __restrict__ slots,
+                               const float* __restrict__ f) {
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t per = (size_t)a.P * a.L;
+    if (idx >= (size_t)a.I * per) return;
+    const uint32_t i = (uint32_t)(idx / per);
+    const float fv = f[idx / a.L];
+    const uint32_t s = slots[idx];
+    if (!(fv >= 0.0f) || s >= a.S) return;
+    atomicMax(a.segfit + (size_t)i * a.S + s, (int32_t)__float_as_uint(fv));
+}
+
+// ------------------------------------------------------------------- update
+__device__ __forceinline__ bool mutated(const LoopArgs& a, uint32_t gen, uint32_t i, uint32_t ind,
+                                        bool* qutrit_mode) {
+    const u32x4 w = draw(a.seed, TAG_MUT_IND, gen, i, ind);
+    *qutrit_mode = (w.y & 1u) != 0;
+    return (uint64_t)w.x < a.thr_pm;
+}
+
+// Elitism for a used slot whose segment fitness is v.
+__device__ __forceinline__ void elitism(const LoopArgs& a, uint32_t i, uint32_t s, float v) {
+    const size_t o = (size_t)i * a.S + s;
+    const bool rot = s < a.Q;
+    float* q = a.qutrit + 6 * ((size_t)i * a.Q + s);
+    float* bq = a.best_qutrit + 6 * ((size_t)i * a.Q + s);
+    if (v > a.best_f[o]) {
+        a.best_f[o] = v;
+        a.best_theta[o] = a.theta[o];
+        if (rot)
+#pragma unroll
+            for (int c = 0; c < 6; ++c) bq[c] = q[c];
+    } else {
+        a.theta[o] = a.best_theta[o];
+        if (rot)
+#pragma unroll
+            for (int c = 0; c < 6; ++c) q[c] = bq[c];
+    }
+}
+
+// One SU(3) step (Eq. 12 with parameter j alone, value a*domain/4096).
+__device__ __forceinline__ void su3_step(float* q, int j, int ai, const float* tab) {
+    const float x0 = q[0], y0 = q[1], x1 = q[2], y1 = q[3], x2 = q[4], y2 = q[5];
+    if (j <= 2) {
+        const float c = tab[ai], s = tab[SU3_TAB + ai];
+        if (j == 0) {
+            q[0] = __fadd_rn(__fmul_rn(c, x0), __fmul_rn(s, x1));
+            q[1] = __fadd_rn(__fmul_rn(c, y0), __fmul_rn(s, y1));
+            q[2] = __fsub_rn(__fmul_rn(c, x1), __fmul_rn(s, x0));
+            q[3] = __fsub_rn(__fmul_rn(c, y1), __fmul_rn(s, y0));
+        } else if (j == 1) {
+            q[0] = __fadd_rn(__fmul_rn(c, x0), __fmul_rn(s, x2));
+            q[1] = __fadd_rn(__fmul_rn(c, y0), __fmul_rn(s, y2));
+            q[4] = __fsub_rn(__fmul_rn(c, x2), __fmul_rn(s, x0));
+            q[5] = __fsub_rn(__fmul_rn(c, y2), __fmul_rn(s, y0));
+        } else {
+            q[2] = __fsub_rn(__fmul_rn(c, x1), __fmul_rn(s, x2));
+            q[3] = __fsub_rn(__fmul_rn(c, y1), __fmul_rn(s, y2));
+            q[4] = __fadd_rn(__fmul_rn(s, x1), __fmul_rn(c, x2));
+            q[5] = __fadd_rn(__fmul_rn(s, y1), __fmul_rn(c, y2));
+        }
+    } else if (j <= 4) {
+        const float c = tab[2 * SU3_TAB + ai], s = tab[3 * SU3_TAB + ai];
+        if (j == 3) {
+            q[0] = __fsub_rn(__fmul_rn(c, x0), __fmul_rn(s, y0));
+            q[1] = __fadd_rn(__fmul_rn(s, x0), __fmul_rn(c, y0));
+        } else {
+            q[2] = __fsub_rn(__fmul_rn(c, x1), __fmul_rn(s, y1));
+            q[3] = __fadd_rn(__fmul_rn(s, x1), __fmul_rn(c, y1));
+        }
+        q[4] = __fadd_rn(__fmul_rn(c, x2), __fmul_rn(s, y2));
+        q[5] = __fsub_rn(__fmul_rn(c, y2), __fmul_rn(s, x2));
+    }
+}
+
+__device__ __forceinline__ void mutate_slot(const LoopArgs& a, uint32_t gen, uint32_t i,
+                                            uint32_t s, bool qutrit_mode) {
+    const size_t o = (size_t)i * a.S + s;
+    const float bf = a.best_f[o];
+    const float seg = bf < 0.0f ? 0.0f : bf;
+    const float om = __fsub_rn(1.0f, seg);
+    const u32x4 w = draw(a.seed, TAG_MUT_SLOT, gen, i, s);
+    if (!qutrit_mode) {
+        const uint32_t d = (uint32_t)floorf(__fmul_rn(om, a.r32));
+        a.theta[o] = (w.x & 1u) ? a.theta[o] - d : a.theta[o] + d;
+    } else {
+        const int j = (int)scale_u32(w.y, 8u);
+        const float u = __fmul_rn((float)(w.z >> 8), 0x1p-24f);
+        const float x = __fmul_rn(u, om);
+        const int ai = (int)floorf(__fmul_rn(x, 4096.0f));
+        su3_step(a.qutrit + 6 * ((size_t)i * a.Q + s), j, ai, a.su3_tab);
+    }
+}
+
+// Part A: used slots of individuals that do not mutate (one thread per
+// (circuit, position) entry; atomicExch claims each slot exactly once and
+// resets its segment fitness).  Part B: individuals that mutate (one
+// wavefront each): every slot is claimed, passes elitism if it was used,
+// then mutates.  Part C: best circuit per instance (one wavefront each).
+__global__ __launch_bounds__(256) void qeqea_update_kernel(LoopArgs a, uint64_t gen64,
+                                                           const uint32_t* __restrict__ slots,
+                                                           const uint16_t* __restrict__ gates,
+                                                           const float* __restrict__ f,
+                                                           uint32_t nA, uint32_t nB) {
+    const uint32_t gen = gen_of(a, gen64);
+    const uint32_t LP = (uint32_t)a.L * (uint32_t)a.P;
+    if (blockIdx.x < nA) {
+        const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+        const size_t per = (size_t)a.P * a.L;
+        if (idx >= (size_t)a.I * per) return;
+        const uint32_t i = (uint32_t)(idx / per);
+        const uint32_t s = slots[idx];
+        if (s >= a.S) return;
+        const uint32_t ind = (s % LP) / (uint32_t)a.L;
+        bool qm;
+        if (mutated(a, gen, i, ind, &qm)) return;
+        const int32_t v = atomicExch(a.segfit + (size_t)i * a.S + s, -1);
+        if (v >= 0) elitism(a, i, s, __int_as_float(v));
+    } else if (blockIdx.x < nA + nB) {
+        const uint32_t id = (blockIdx.x - nA) * 4 + (threadIdx.x >> 6);
+        if (id >= (uint32_t)a.I * (uint32_t)a.P) return;
+        const uint32_t i = id / (uint32_t)a.P, ind = id % (uint32_t)a.P;
+        bool qm;
+        if (!mutated(a, gen, i, ind, &qm)) return;
+        const uint32_t regions = qm ? (uint32_t)a.n : (uint32_t)(a.n * a.n);
+        const uint32_t cnt = regions * (uint32_t)a.L;
+        for (uint32_t e = lane_id(); e < cnt; e += 64) {
+            const uint32_t r = e / (uint32_t)a.L, pos = e % (uint32_t)a.L;
+            const uint32_t s = r * LP + ind * (uint32_t)a.L + pos;
+            const int32_t v = atomicExch(a.segfit + (size_t)i * a.S + s, -1);
+            if (v >= 0) elitism(a, i, s, __int_as_float(v));
+            mutate_slot(a, gen, i, s, qm);
+        }
+        if (qm) {
+            // qubit-only slots of a qutrit-mode individual still pass elitism
+            const uint32_t cnt2 = (uint32_t)(a.n * a.n - a.n) * (uint32_t)a.L;
+            for (uint32_t e = lane_id(); e < cnt2; e += 64) {
+                const uint32_t r = (uint32_t)a.n + e / (uint32_t)a.L, pos = e % (uint32_t)a.L;
+                const uint32_t s = r * LP + ind * (uint32_t)a.L + pos;
+                const int32_t v = atomicExch(a.segfit + (size_t)i * a.S + s, -1);
+                if (v >= 0) elitism(a, i, s, __int_as_float(v));
+            }
+        }
+    } else {
+        const uint32_t i = (blockIdx.x - nA - nB) * 4 + (threadIdx.x >> 6);
+        if (i >= (uint32_t)a.I) return;
+        const int lane = (int)lane_id();
+        float best = -1.0f;
+        int bi = 0x7FFFFFFF;
+        for (int k = lane; k < a.P; k += 64) {
+            const float v = f[(size_t)i * a.P + k];
+            if (v > best) { best = v; bi = k; }
+        }
+        for (int m = 32; m >= 1; m >>= 1) {
+            const float ob = __shfl_xor(best, m, 64);
+            const int oi = __shfl_xor(bi, m, 64);
+            if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+        }
+        if (best > a.inst_best_f[i]) {
+            const uint16_t* src = gates + ((size_t)i * a.P + bi) * a.L;
+            for (int l = lane; l < a.L; l += 64) a.inst_best_gates[(size_t)i * a.L + l] = src[l];
+            if (lane == 0) a.inst_best_f[i] = best;
+        }
+    }
+}
+
+// ----------------------------------------------------------------------- GA
+// One workgroup per population: SUS over integer weights floor(f * 2^24),
+// two-point crossover of children j and j + P/2, gene mutation, and the best
+// parent copied unchanged into child 0.  Reads genomes[gen & 1], writes
+// genomes[(gen + 1) & 1].
+constexpr int GA_MAX_P = 4096;
+
+__global__ __launch_bounds__(256) void ga_update_kernel(LoopArgs a, uint64_t gen64,
+                                                        const float* __restrict__ f) {
+    __shared__ unsigned long long pre[GA_MAX_P + 1];
+    __shared__ int32_t sel[GA_MAX_P];
+    __shared__ float bestv[4];
+    __shared__ int besti[4];
+    const uint32_t gen = gen_of(a, gen64);
+    const uint32_t i = blockIdx.x;
+    const int P = a.P, L = a.L, tid = threadIdx.x, nt = blockDim.x;
+    const uint16_t* cur = a.genomes[gen & 1] + (size_t)i * P * L;
+    uint16_t* nxt = a.genomes[(gen + 1) & 1] + (size_t)i * P * L;
+    const float* fi = f + (size_t)i * P;
+    // weights and best (lowest index among the maxima)
+    float best = -1.0f;
+    int bi = 0x7FFFFFFF;
+    for (int k = tid; k < P; k += nt) {
+        const float v = fi[k];
+        pre[k + 1] = (v >= 0.0f) ? (unsigned long long)(uint32_t)floorf(__fmul_rn(v, 16777216.0f)) : 0ull;
+        if (v > best) { best = v; bi = k; }
+    }
+    for (int m = 32; m >= 1; m >>= 1) {
+        const float ob = __shfl_xor(best, m, 64);
+        const int oi = __shfl_xor(bi, m, 64);
+        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+    }
+    if ((tid & 63) == 0) { bestv[tid >> 6] = best; besti[tid >> 6] = bi; }
+    if (tid == 0) pre[0] = 0;
+    __syncthreads();
+    if (tid == 0) {
+        for (int w = 1; w < (nt >> 6); ++w)
+            if (bestv[w] > best || (bestv[w] == best && besti[w] < bi)) { best = bestv[w]; bi = besti[w]; }
+        bestv[0] = best; besti[0] = bi;
+        // inclusive prefix (serial: P <= 4096 additions)
+        for (int k = 1; k <= P; ++k) pre[k] += pre[k - 1];
+        if (pre[P] == 0)
+            for (int k = 0; k <= P; ++k) pre[k] = (unsigned long long)k;
+    }
+    __syncthreads();
+    best = bestv[0];
+    bi = besti[0] == 0x7FFFFFFF ? 0 : besti[0];
+    const unsigned long long W = pre[P];
+    const uint32_t w0 = draw(a.seed, TAG_GA_SUS, gen, i, 0u).x;
+    const unsigned long long r = (unsigned long long)w0 * (W >> 32) +
+                                 (((unsigned long long)w0 * (W & 0xFFFFFFFFull)) >> 32);
+    for (int k = tid; k < P; k += nt) {
+        const unsigned long long ptr = (r + (unsigned long long)k * W) / (unsigned long long)P;
+        int lo = 0, hi = P - 1;        // first m with pre[m + 1] > ptr
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (pre[mid + 1] > ptr) hi = mid; else lo = mid + 1;
+        }
+        sel[k] = lo;
+    }
+    __syncthreads();
+    for (size_t e = tid; e < (size_t)P * L; e += nt) {
+        const int k = (int)(e / L), pos = (int)(e % L);
+        nxt[e] = cur[(size_t)sel[k] * L + pos];
+    }
+    __syncthreads();
+    const int half = P / 2;
+    for (int j = tid; j < half; j += nt) {
+        const u32x4 w = draw(a.seed, TAG_GA_XOVER, gen, i, (uint32_t)j);
+        if (!((uint64_t)w.x < a.thr_pc)) continue;
+        const int c1 = (int)scale_u32(w.y, (uint32_t)(L + 1)), c2 = (int)scale_u32(w.z, (uint32_t)(L + 1));
+        const int lo = min(c1, c2), hi = max(c1, c2);
+        for (int pos = lo; pos < hi; ++pos) {
+            const uint16_t t = nxt[(size_t)j * L + pos];
+            nxt[(size_t)j * L + pos] = nxt[(size_t)(j + half) * L + pos];
+            nxt[(size_t)(j + half) * L + pos] = t;
+        }
+    }
+    __syncthreads();
+    const uint32_t nl = (uint32_t)lib_size(a.lib, a.n);
+    for (size_t e = tid; e < (size_t)P * L; e += nt) {
+        const u32x4 w = draw(a.seed, TAG_GA_MUT, gen, i, (uint32_t)e);
+        if ((uint64_t)w.x < a.thr_pg) nxt[e] = lib_desc(a.lib, a.n, (int)scale_u32(w.y, nl));
+    }
+    __syncthreads();
+    for (int pos = tid; pos < L; pos += nt) nxt[pos] = cur[(size_t)bi * L + pos];
+    // best circuit ever seen by this population
+    if (best > a.inst_best_f[i]) {
+        for (int pos = tid; pos < L; pos += nt)
+            a.inst_best_gates[(size_t)i * L + pos] = cur[(size_t)bi * L + pos];
+        __syncthreads();
+        if (tid == 0) a.inst_best_f[i] = best;
+    }
+}
+
+// --------------------------------------------------------------- elite FP64
+// Top-k circuits of each population by (f descending, index ascending):
+// bitonic sort of P keys in LDS (P <= 4096).
+__global__ __launch_bounds__(256) void elite_select_kernel(LoopArgs a, const float* __restrict__ f,
+                                                           int k, int32_t* __restrict__ idx_out) {
+    __shared__ unsigned long long key[4096];
+    const int i = blockIdx.x, P = a.P, tid = threadIdx.x;
+    int Pp = 1;
+    while (Pp < P) Pp <<= 1;
+    for (int e = tid; e < Pp; e += blockDim.x) {
+        unsigned long long kv = ~0ull;
+        if (e < P) {
+            const float v = f[(size_t)i * P + e];
+            // non-negative floats order like their bit patterns; NaN last
+            const uint32_t ord = (v >= 0.0f) ? __float_as_uint(v) + 1u : 0u;
+            kv = ((unsigned long long)(0xFFFFFFFFu - ord) << 32) | (uint32_t)e;
+        }
+        key[e] = kv;
+    }
+    __syncthreads();
+    for (int size = 2; size <= Pp; size <<= 1)
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int e = tid; e < Pp; e += blockDim.x) {
+                const int o = e ^ stride;
+                if (o > e) {
+                    const bool up = (e & size) == 0;
+                    const unsigned long long x = key[e], y = key[o];
+                    if ((x > y) == up) { key[e] = y; key[o] = x; }
+                }
+            }
+            __syncthreads();
+        }
+    for (int e = tid; e < k; e += blockDim.x) idx_out[(size_t)i * k + e] = (int32_t)(key[e] & 0xFFFFFFFFu);
+}
+
+__global__ __launch_bounds__(256) void elite_eval_kernel(LoopArgs a, const uint16_t* __restrict__ gates,
+                                                         int k, const int32_t* __restrict__ idx,
+                                                         double* __restrict__ f64) {
+    const int i = blockIdx.x / k, e = blockIdx.x % k;
+    const int c = idx[(size_t)i * k + e];
+    uint32_t err = (c < 0 || c >= a.P) ? (uint32_t)QE_DEVERR_RANGE : 0u;
+    const uint16_t* g = gates + ((size_t)i * a.P + (err ? 0 : c)) * a.L;
+    const double* T = a.target64 + (size_t)2 * i * ((size_t)1 << (2 * a.n));
+    lds_generic_body<double, false>(a.n, a.L, g, T, err, f64 + blockIdx.x, nullptr, nullptr,
+                                    nullptr, a.err);
+}
+
+// Complex128 -> complex64 copy of the targets for the FP32 path.
+__global__ void c128_to_c64_kernel(const double* __restrict__ src, float* __restrict__ dst, int64_t n) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx < n) dst[idx] = (float)src[idx];
+}
+
+// ---------------------------------------------------------------- launchers
+static inline unsigned blocks(size_t n, unsigned bs) { return (unsigned)((n + bs - 1) / bs); }
+
+hipError_t launch_qeqea_init(const LoopArgs& a, hipStream_t s) {
+    qeqea_init_kernel<<<blocks((size_t)a.I * a.S, 256), 256, 0, s>>>(a, (float)(1.0 / sqrt(3.0)));
+    inst_best_init_kernel<<<blocks(a.I, 256), 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_ga_init(const LoopArgs& a, hipStream_t s) {
+    ga_init_kernel<<<blocks((size_t)a.I * a.P * a.L, 256), 256, 0, s>>>(a);
+    inst_best_init_kernel<<<blocks(a.I, 256), 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
+    if (n > 0) fill_i32_kernel<<<blocks((size_t)n, 256), 256, 0, s>>>(p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_c128_to_c64(const double* src, float* dst, int64_t n_reals, hipStream_t s) {
+    if (n_reals > 0) c128_to_c64_kernel<<<blocks((size_t)n_reals, 256), 256, 0, s>>>(src, dst, n_reals);
+    return hipGetLastError();
+}
+
+hipError_t launch_gen_advance(uint64_t* g, uint64_t by, hipStream_t s) {
+    gen_advance_kernel<<<1, 1, 0, s>>>(g, by);
+    return hipGetLastError();
+}
+
+hipError_t launch_gen_set(uint64_t* g, uint64_t v, hipStream_t s) {
+    gen_set_kernel<<<1, 1, 0, s>>>(g, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_qeqea_sample(const LoopArgs& a, uint64_t gen, uint32_t* slots, uint16_t* gates,
+                               hipStream_t s) {
+    qeqea_sample_kernel<<<blocks((size_t)a.I * a.P * a.L, 256), 256, 0, s>>>(a, gen, slots, gates);
+    return hipGetLastError();
+}
+
+hipError_t launch_ga_copy(const LoopArgs& a, uint64_t gen, uint16_t* gates, hipStream_t s) {
+    ga_copy_kernel<<<blocks((size_t)a.I * a.P * a.L, 256), 256, 0, s>>>(a, gen, gates);
+    return hipGetLastError();
+}
+
+template <bool SAMPLE>
+static void launch_population(const LoopArgs& a, uint64_t gen, const uint16_t* gin, uint32_t* sout,
+                              uint16_t* gout, float* f, hipStream_t s) {
+    const uint32_t total = (uint32_t)a.I * (uint32_t)a.P;
+    const bool lds = schedule_lds(a.n);
+    const unsigned wb = blocks(total, 4);
+    if (lds && a.n >= 4) {
+        switch (a.n) {
+            case 4: population_kernel<4, 1, SAMPLE><<<total, 64, 0, s>>>(a, gen, gin, sout, gout, f); break;
+            case 5: population_kernel<5, 2, SAMPLE><<<total, 128, 0, s>>>(a, gen, gin, sout, gout, f); break;
+            default: population_kernel<6, 4, SAMPLE><<<total, 256, 0, s>>>(a, gen, gin, sout, gout, f); break;
+        }
+        return;
+    }
+    switch (a.n) {
+        case 1: population_kernel<1, 0, SAMPLE><<<wb, 256, 0, s>>>(a, gen, gin, sout, gout, f); break;
+        case 2: population_kernel<2, 0, SAMPLE><<<wb, 256, 0, s>>>(a, gen, gin, sout, gout, f); break;
+        case 3: population_kernel<3, 0, SAMPLE><<<wb, 256, 0, s>>>(a, gen, gin, sout, gout, f); break;
+        case 4: population_kernel<4, 0, SAMPLE><<<wb, 256, 0, s>>>(a, gen, gin, sout, gout, f); break;
+        case 5: population_kernel<5, 0, SAMPLE><<<wb, 256, 0, s>>>(a, gen, gin, sout, gout, f); break;
+        default: population_kernel<6, 0, SAMPLE><<<wb, 256, 0, s>>>(a, gen, gin, sout, gout, f); break;
+    }
+}
+
+hipError_t launch_eval_population(const LoopArgs& a, const uint16_t* gates, float* f, hipStream_t s) {
+    launch_population<false>(a, 0, gates, nullptr, nullptr, f, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_ga_eval(const LoopArgs& a, uint64_t gen, float* f, hipStream_t s) {
+    // the population of generation gen is genomes[gen & 1]; the parity is
+    // resolved on the device for graph replays
+    LoopArgs b = a;
+    b.gen_ptr = nullptr;
+    if (a.gen_ptr) return hipErrorInvalidValue;   // callers use launch_ga_copy + eval in graphs
+    launch_population<false>(b, 0, a.genomes[gen & 1], nullptr, nullptr, f, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_qeqea_fused(const LoopArgs& a, uint64_t gen, uint32_t* slots, uint16_t* gates,
+                              float* f, hipStream_t s) {
+    launch_population<true>(a, gen, nullptr, slots, gates, f, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter(const LoopArgs& a, uint64_t gen, const uint32_t* slots, const float* f,
+                          hipStream_t s) {
+    (void)gen;
+    scatter_kernel<<<blocks((size_t)a.I * a.P * a.L, 256), 256, 0, s>>>(a, slots, f);
+    return hipGetLastError();
+}
+
+hipError_t launch_qeqea_update(const LoopArgs& a, uint64_t gen, const uint32_t* slots,
+                               const uint16_t* gates, const float* f, hipStream_t s) {
+    const uint32_t nA = blocks((size_t)a.I * a.P * a.L, 256);
+    const uint32_t nB = blocks((size_t)a.I * a.P, 4);
+    const uint32_t nC = blocks((size_t)a.I, 4);
+    qeqea_update_kernel<<<nA + nB + nC, 256, 0, s>>>(a, gen, slots, gates, f, nA, nB);
+    return hipGetLastError();
+}
+
+hipError_t launch_ga_update(const LoopArgs& a, uint64_t gen, const float* f, hipStream_t s) {
+    ga_update_kernel<<<a.I, 256, 0, s>>>(a, gen, f);
+    return hipGetLastError();
+}
+
+hipError_t launch_elite_select(const LoopArgs& a, const float* f, int k, int32_t* idx, hipStream_t s) {
+    elite_select_kernel<<<a.I, 256, 0, s>>>(a, f, k, idx);
+    return hipGetLastError();
+}
+
+hipError_t launch_elite_eval(const LoopArgs& a, const uint16_t* gates, int k, const int32_t* idx,
+                             double* f64, hipStream_t s) {
+    elite_eval_kernel<<<a.I * k, 256, 0, s>>>(a, gates, k, idx, f64);
+    return hipGetLastError();
+}
+
+}  // namespace qe

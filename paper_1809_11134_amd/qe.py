@@ -1,0 +1,352 @@
+"""Python binding of libqe (ctypes).  Argument marshalling only: every step of
+the path runs in the library's HIP kernels; torch supplies device memory and
+streams.  Importing works without a GPU; calling needs libqe.so and a GPU, and
+raises if either is missing (there is no CPU fallback)."""
+import ctypes
+import os
+import re
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libqe.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "qe.h")
+
+QE_OK, QE_ERR_INVALID, QE_ERR_UNSUPPORTED, QE_ERR_DEVICE, QE_ERR_OOM, QE_ERR_NUMERIC, QE_ERR_STATE = range(7)
+LIB_NCV, LIB_HT_NCV = 0, 1
+ALG_QEQEA, ALG_GA = 0, 1
+PATH_FP32, PATH_FP32_REG, PATH_FP32_LDS, PATH_MFMA_BF16, PATH_MFMA_FP16 = range(5)
+DEVERR_DESC, DEVERR_WIDTH, DEVERR_RANGE, DEVERR_NUMERIC = 1, 2, 4, 8
+
+
+class QeError(RuntimeError):
+    def __init__(self, fn, status, msg):
+        super().__init__(f"{fn} failed with status {status}: {msg}")
+        self.status = status
+
+
+class Batch(ctypes.Structure):
+    _fields_ = [("num_circuits", ctypes.c_int32), ("uniform_n", ctypes.c_int32),
+                ("n_qubits_dev", ctypes.c_void_p), ("uniform_L", ctypes.c_int32),
+                ("gate_offsets_dev", ctypes.c_void_p), ("gates_dev", ctypes.c_void_p),
+                ("num_gates", ctypes.c_int64), ("target_stride", ctypes.c_int64),
+                ("target_offsets_dev", ctypes.c_void_p), ("targets_dev", ctypes.c_void_p),
+                ("num_target_elems", ctypes.c_int64)]
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("n_qubits", ctypes.c_int32), ("library", ctypes.c_int32),
+                ("algorithm", ctypes.c_int32), ("size_of_individual", ctypes.c_int32),
+                ("size_of_population", ctypes.c_int32), ("n_instances", ctypes.c_int32),
+                ("prob_mutation", ctypes.c_float), ("mutation_range", ctypes.c_float),
+                ("ga_crossover_prob", ctypes.c_float), ("ga_gene_mutation_prob", ctypes.c_float),
+                ("seed", ctypes.c_uint64)]
+
+
+_lib = None
+_hip = None
+
+
+def header_functions():
+    """Names of the functions declared in include/qe.h."""
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(qe_[a-z0-9_]+)\s*\(", text)))
+
+
+def load():
+    """Loads libqe.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1809_11134_amd.build.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
+    P = ctypes.POINTER
+    sig = {
+        "qe_eval_fitness": [vp, P(Batch), i32, vp, vp, vp, vp],
+        "qe_eval_fitness_fp64": [P(Batch), vp, vp, vp, vp],
+        "qe_build_unitary": [P(Batch), i32, vp, i64, vp],
+        "qe_device_errors": [P(i32)],
+        "qe_create": [P(Problem), P(vp)],
+        "qe_destroy": [vp],
+        "qe_set_targets": [vp, vp, vp],
+        "qe_sample": [vp, u64, vp, vp, vp],
+        "qe_eval_population": [vp, vp, vp, vp],
+        "qe_update": [vp, u64, vp, vp, vp, vp],
+        "qe_generation": [vp, u64, vp, vp],
+        "qe_run_graph": [vp, u64, i32, vp, vp],
+        "qe_elite_recheck": [vp, vp, vp, i32, vp, vp, vp],
+        "qe_get_best": [vp, i32, vp, P(ctypes.c_float), P(ctypes.c_double)],
+        "qe_checkpoint": [vp, vp, P(ctypes.c_size_t)],
+        "qe_restore": [vp, vp, ctypes.c_size_t],
+        "qe_state_view": [vp, i32, P(vp), P(i64)],
+        "qe_lib_table": [i32, i32, vp],
+        "qe_set_schedule": [i32, i32],
+        "qe_get_schedule": [i32, P(i32)],
+    }
+    for name, args in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = i32
+    L.qe_lib_size.argtypes = [i32, i32]
+    L.qe_lib_size.restype = i32
+    L.qe_last_error.restype = ctypes.c_char_p
+    L.qe_version.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _call(name, *args):
+    st = getattr(load(), name)(*args)
+    if st != QE_OK:
+        raise QeError(name, st, load().qe_last_error().decode())
+    return st
+
+
+def _hiprt():
+    global _hip
+    if _hip is None:
+        _hip = ctypes.CDLL("libamdhip64.so")
+        _hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+        _hip.hipMemcpy.restype = ctypes.c_int
+    return _hip
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _dev(t, dtype):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if t.dtype != dtype:
+        t = t.to(dtype)
+    return t.contiguous()
+
+
+def _gates(t):
+    t = _dev(t, t.dtype if t.dtype == torch.int16 else torch.int32)
+    if t.dtype != torch.int16:
+        t = t.to(torch.int16)
+    return t.contiguous()
+
+
+def make_batch(gates, targets, n=None, L=None, nq=None, goff=None, toff=None, target_stride=None):
+    """Builds a qe_batch from device tensors.  gates: int16/int32 descriptors
+    ([B, L] for uniform lengths, flat with goff for uneven); targets: complex
+    tensor ([T, N, N] or flat); n: uniform width or None with nq (int8 [B]);
+    target_stride: complex elements between targets (0 = shared) or None with
+    toff (int64 [B])."""
+    keep = []
+    b = Batch()
+    g = _gates(gates)
+    keep.append(g)
+    if L is not None and goff is None:
+        B = g.numel() // L if L > 0 else 0
+        b.uniform_L = L
+    else:
+        goff = _dev(goff, torch.int32)
+        keep.append(goff)
+        B = goff.numel() - 1
+        b.uniform_L = 0
+        b.gate_offsets_dev = goff.data_ptr()
+    b.num_circuits = B
+    if n is not None:
+        b.uniform_n = n
+    else:
+        nq = _dev(nq, torch.int8)
+        keep.append(nq)
+        b.uniform_n = 0
+        b.n_qubits_dev = nq.data_ptr()
+    b.gates_dev = g.data_ptr() if g.numel() else None
+    b.num_gates = g.numel()
+    if targets is not None:
+        t = targets.contiguous()
+        keep.append(t)
+        b.targets_dev = t.data_ptr()
+        b.num_target_elems = t.numel()
+        if target_stride is not None:
+            b.target_stride = target_stride
+        else:
+            toff = _dev(toff, torch.int64)
+            keep.append(toff)
+            b.target_stride = -1
+            b.target_offsets_dev = toff.data_ptr()
+    return b, keep, B
+
+
+def eval_fitness(gates, targets, n=None, L=None, nq=None, goff=None, toff=None, target_stride=0,
+                 path=PATH_FP32, want_g=False, want_delta=False, stream=None):
+    """Eq. 11 fitness of a batch on the FP32 path.  targets complex64.
+    Returns (f, g or None, delta or None) as float32 device tensors."""
+    targets = targets.to(torch.complex64) if targets.dtype != torch.complex64 else targets
+    b, keep, B = make_batch(gates, targets, n, L, nq, goff, toff, target_stride)
+    dev = targets.device
+    f = torch.empty(B, dtype=torch.float32, device=dev)
+    g = torch.empty(B, dtype=torch.float32, device=dev) if want_g else None
+    d = torch.empty(B, dtype=torch.float32, device=dev) if want_delta else None
+    _call("qe_eval_fitness", None, ctypes.byref(b), path, _ptr(f), _ptr(g), _ptr(d), _stream(stream))
+    return f, g, d
+
+
+def eval_fitness_fp64(gates, targets, n=None, L=None, nq=None, goff=None, toff=None,
+                      target_stride=0, want_g=False, want_delta=False, stream=None):
+    targets = targets.to(torch.complex128) if targets.dtype != torch.complex128 else targets
+    b, keep, B = make_batch(gates, targets, n, L, nq, goff, toff, target_stride)
+    dev = targets.device
+    f = torch.empty(B, dtype=torch.float64, device=dev)
+    g = torch.empty(B, dtype=torch.float64, device=dev) if want_g else None
+    d = torch.empty(B, dtype=torch.float64, device=dev) if want_delta else None
+    _call("qe_eval_fitness_fp64", ctypes.byref(b), _ptr(f), _ptr(g), _ptr(d), _stream(stream))
+    return f, g, d
+
+
+def build_unitary(gates, n, L, precision=1, stream=None):
+    """Unitaries of B circuits of n wires and L gates: [B, N, N] complex."""
+    b, keep, B = make_batch(gates, None, n=n, L=L)
+    N = 1 << n
+    dtype = torch.complex128 if precision == 1 else torch.complex64
+    out = torch.empty((B, N, N), dtype=dtype, device=gates.device)
+    _call("qe_build_unitary", ctypes.byref(b), precision, _ptr(out), out.numel(), _stream(stream))
+    return out
+
+
+def device_errors():
+    v = ctypes.c_int32(0)
+    _call("qe_device_errors", ctypes.byref(v))
+    return v.value
+
+
+def lib_table(library, n):
+    size = load().qe_lib_size(library, n)
+    buf = (ctypes.c_uint16 * size)()
+    _call("qe_lib_table", library, n, buf)
+    return [int(x) for x in buf]
+
+
+def set_schedule(n, lds):
+    _call("qe_set_schedule", n, int(lds))
+
+
+def get_schedule(n):
+    v = ctypes.c_int32(0)
+    _call("qe_get_schedule", n, ctypes.byref(v))
+    return v.value
+
+
+class Context:
+    """A QEQEA or GA search: ctx-owned encoding on the current device."""
+
+    def __init__(self, n, library, algorithm, L, P, instances=1, prob_mutation=0.1,
+                 mutation_range=0.7853981633974483, ga_crossover_prob=0.9,
+                 ga_gene_mutation_prob=None, seed=0):
+        if ga_gene_mutation_prob is None:
+            ga_gene_mutation_prob = 1.0 / L
+        self.problem = Problem(n, library, algorithm, L, P, instances, prob_mutation,
+                               mutation_range, ga_crossover_prob, ga_gene_mutation_prob, seed)
+        self.n, self.L, self.P, self.I = n, L, P, instances
+        self.algorithm = algorithm
+        h = ctypes.c_void_p(0)
+        _call("qe_create", ctypes.byref(self.problem), ctypes.byref(h))
+        self.handle = h
+        self._keep = []
+
+    def close(self):
+        if self.handle:
+            _call("qe_destroy", self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def circuits(self):
+        return self.I * self.P
+
+    def set_targets(self, targets, stream=None):
+        t = targets.to(torch.complex128).contiguous()
+        self._keep = [t]
+        _call("qe_set_targets", self.handle, _ptr(t), _stream(stream))
+
+    def sample(self, gen, stream=None):
+        dev = torch.device("cuda", torch.cuda.current_device())
+        slots = torch.empty((self.circuits, self.L), dtype=torch.int32, device=dev)
+        gates = torch.empty((self.circuits, self.L), dtype=torch.int16, device=dev)
+        _call("qe_sample", self.handle, gen, _ptr(slots), _ptr(gates), _stream(stream))
+        return slots, gates
+
+    def eval_population(self, gates, stream=None):
+        f = torch.empty(self.circuits, dtype=torch.float32, device=gates.device)
+        _call("qe_eval_population", self.handle, _ptr(_gates(gates)), _ptr(f), _stream(stream))
+        return f
+
+    def update(self, gen, slots, gates, f, stream=None):
+        _call("qe_update", self.handle, gen, _ptr(slots), _ptr(_gates(gates)), _ptr(f.contiguous()),
+              _stream(stream))
+
+    def generation(self, gen, f=None, stream=None):
+        if f is None:
+            f = torch.empty(self.circuits, dtype=torch.float32,
+                            device=torch.device("cuda", torch.cuda.current_device()))
+        _call("qe_generation", self.handle, gen, _ptr(f), _stream(stream))
+        return f
+
+    def run_graph(self, first_gen, n_gen, f_hist=None, stream=None):
+        _call("qe_run_graph", self.handle, first_gen, n_gen, _ptr(f_hist), _stream(stream))
+
+    def elite_recheck(self, gates, f, k, stream=None):
+        idx = torch.empty((self.I, k), dtype=torch.int32, device=f.device)
+        f64 = torch.empty((self.I, k), dtype=torch.float64, device=f.device)
+        _call("qe_elite_recheck", self.handle, _ptr(_gates(gates)), _ptr(f.contiguous()), k,
+              _ptr(idx), _ptr(f64), _stream(stream))
+        return idx, f64
+
+    def get_best(self, instance=0, with_fp64=True):
+        gates = (ctypes.c_uint16 * self.L)()
+        f32 = ctypes.c_float(0)
+        f64 = ctypes.c_double(0)
+        _call("qe_get_best", self.handle, instance, gates, ctypes.byref(f32),
+              ctypes.byref(f64) if with_fp64 else None)
+        return [int(x) for x in gates], f32.value, (f64.value if with_fp64 else None)
+
+    def checkpoint(self):
+        size = ctypes.c_size_t(0)
+        _call("qe_checkpoint", self.handle, None, ctypes.byref(size))
+        buf = ctypes.create_string_buffer(size.value)
+        _call("qe_checkpoint", self.handle, buf, ctypes.byref(size))
+        return bytes(buf.raw[:size.value])
+
+    def restore(self, blob):
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        _call("qe_restore", self.handle, buf, len(blob))
+
+    _VIEWS = {"theta": (0, torch.int32), "qutrit": (1, torch.float32), "best_f": (2, torch.float32),
+              "best_theta": (3, torch.int32), "best_qutrit": (4, torch.float32),
+              "genomes0": (5, torch.int16), "genomes1": (6, torch.int16)}
+
+    def state(self, name):
+        """A device copy of a piece of the ctx-owned state."""
+        which, dtype = self._VIEWS[name]
+        p = ctypes.c_void_p(0)
+        n = ctypes.c_int64(0)
+        _call("qe_state_view", self.handle, which, ctypes.byref(p), ctypes.byref(n))
+        out = torch.empty(n.value, dtype=dtype, device=torch.device("cuda", torch.cuda.current_device()))
+        if n.value:
+            torch.cuda.synchronize()
+            rc = _hiprt().hipMemcpy(ctypes.c_void_p(out.data_ptr()), p, out.numel() * out.element_size(), 3)
+            if rc != 0:
+                raise RuntimeError(f"hipMemcpy failed ({rc})")
+        return out
