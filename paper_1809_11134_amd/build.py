@@ -1,6 +1,9 @@
 """Builds libqe.so (the HIP kernels and the C ABI) for gfx950 with hipcc.
 
 Flags:
+  -ffp-contract=off
+      one rounding per floating-point operation: the encoding updates and the
+      measurement must reproduce the oracle bit for bit;
   -Xclang -target-feature -Xclang -packed-fp32-ops
       no packed FP32 instructions are generated;
   -mllvm -simplifycfg-sink-common=false
@@ -18,7 +21,7 @@ LIB = os.path.join(HERE, "libqe.so")
 SOURCES = ["qe_api.hip", "qe_eval.hip", "qe_loop.hip"]
 ARCH = os.environ.get("QE_OFFLOAD_ARCH", "gfx950")
 
-FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-mllvm", "-simplifycfg-sink-common=false",
          "-I", os.path.join(ROOT, "include"), "-Wall"]

@@ -4,8 +4,9 @@
 // initialisation (Sec. IV-B) and the FP64 re-check of elite circuits.
 //
 // Everything that decides an integer or updates the encoding is written one
-// rounding per operation (floating-point contraction is switched off below)
-// so that it is reproducible bit for bit.
+// rounding per operation so that it is reproducible bit for bit: the library
+// is compiled with -ffp-contract=off (no multiply-add fusion anywhere) and the
+// pragma below repeats that for this file.
 #include "../../include/qe.h"
 #include "qe_eval_core.hpp"
 #include "qe_internal.hpp"
@@ -25,12 +26,12 @@ __device__ __forceinline__ int measure_qutrit(const float* q, uint32_t w) {
     const float2 a0 = *reinterpret_cast<const float2*>(q);
     const float2 a1 = *reinterpret_cast<const float2*>(q + 2);
     const float2 a2 = *reinterpret_cast<const float2*>(q + 4);
-    const float p0 = __fadd_rn(__fmul_rn(a0.x, a0.x), __fmul_rn(a0.y, a0.y));
-    const float p1 = __fadd_rn(__fmul_rn(a1.x, a1.x), __fmul_rn(a1.y, a1.y));
-    const float p2 = __fadd_rn(__fmul_rn(a2.x, a2.x), __fmul_rn(a2.y, a2.y));
-    const float c0 = p0, c1 = __fadd_rn(c0, p1), c2 = __fadd_rn(c1, p2);
-    const float u = __fmul_rn((float)(w >> 8), 0x1p-24f);
-    const float x = __fmul_rn(u, c2);
+    const float p0 = a0.x * a0.x + a0.y * a0.y;
+    const float p1 = a1.x * a1.x + a1.y * a1.y;
+    const float p2 = a2.x * a2.x + a2.y * a2.y;
+    const float c0 = p0, c1 = c0 + p1, c2 = c1 + p2;
+    const float u = (float)(w >> 8) * 0x1p-24f;
+    const float x = u * c2;
     return x < c0 ? 0 : (x < c1 ? 1 : 2);
 }
 
@@ -270,33 +271,24 @@ __device__ __forceinline__ void su3_step(float* q, int j, int ai, const float* t
     const float x0 = q[0], y0 = q[1], x1 = q[2], y1 = q[3], x2 = q[4], y2 = q[5];
     if (j <= 2) {
         const float c = tab[ai], s = tab[SU3_TAB + ai];
-        if (j == 0) {
-            q[0] = __fadd_rn(__fmul_rn(c, x0), __fmul_rn(s, x1));
-            q[1] = __fadd_rn(__fmul_rn(c, y0), __fmul_rn(s, y1));
-            q[2] = __fsub_rn(__fmul_rn(c, x1), __fmul_rn(s, x0));
-            q[3] = __fsub_rn(__fmul_rn(c, y1), __fmul_rn(s, y0));
-        } else if (j == 1) {
-            q[0] = __fadd_rn(__fmul_rn(c, x0), __fmul_rn(s, x2));
-            q[1] = __fadd_rn(__fmul_rn(c, y0), __fmul_rn(s, y2));
-            q[4] = __fsub_rn(__fmul_rn(c, x2), __fmul_rn(s, x0));
-            q[5] = __fsub_rn(__fmul_rn(c, y2), __fmul_rn(s, y0));
-        } else {
-            q[2] = __fsub_rn(__fmul_rn(c, x1), __fmul_rn(s, x2));
-            q[3] = __fsub_rn(__fmul_rn(c, y1), __fmul_rn(s, y2));
-            q[4] = __fadd_rn(__fmul_rn(s, x1), __fmul_rn(c, x2));
-            q[5] = __fadd_rn(__fmul_rn(s, y1), __fmul_rn(c, y2));
+        if (j == 0) {          // [[c, s, 0], [-s, c, 0], [0, 0, 1]]
+            q[0] = c * x0 + s * x1; q[1] = c * y0 + s * y1;
+            q[2] = c * x1 - s * x0; q[3] = c * y1 - s * y0;
+        } else if (j == 1) {   // [[c, 0, s], [0, 1, 0], [-s, 0, c]]
+            q[0] = c * x0 + s * x2; q[1] = c * y0 + s * y2;
+            q[4] = c * x2 - s * x0; q[5] = c * y2 - s * y0;
+        } else {               // [[1, 0, 0], [0, c, -s], [0, s, c]]
+            q[2] = c * x1 - s * x2; q[3] = c * y1 - s * y2;
+            q[4] = s * x1 + c * x2; q[5] = s * y1 + c * y2;
         }
     } else if (j <= 4) {
         const float c = tab[2 * SU3_TAB + ai], s = tab[3 * SU3_TAB + ai];
-        if (j == 3) {
-            q[0] = __fsub_rn(__fmul_rn(c, x0), __fmul_rn(s, y0));
-            q[1] = __fadd_rn(__fmul_rn(s, x0), __fmul_rn(c, y0));
-        } else {
-            q[2] = __fsub_rn(__fmul_rn(c, x1), __fmul_rn(s, y1));
-            q[3] = __fadd_rn(__fmul_rn(s, x1), __fmul_rn(c, y1));
+        if (j == 3) {          // q0 *= e^{i phi}
+            q[0] = c * x0 - s * y0; q[1] = s * x0 + c * y0;
+        } else {               // q1 *= e^{i phi}
+            q[2] = c * x1 - s * y1; q[3] = s * x1 + c * y1;
         }
-        q[4] = __fadd_rn(__fmul_rn(c, x2), __fmul_rn(s, y2));
-        q[5] = __fsub_rn(__fmul_rn(c, y2), __fmul_rn(s, x2));
+        q[4] = c * x2 + s * y2; q[5] = c * y2 - s * x2;   // q2 *= e^{-i phi}
     }
 }
 
@@ -305,16 +297,16 @@ __device__ __forceinline__ void mutate_slot(const LoopArgs& a, uint32_t gen, uin
     const size_t o = (size_t)i * a.S + s;
     const float bf = a.best_f[o];
     const float seg = bf < 0.0f ? 0.0f : bf;
-    const float om = __fsub_rn(1.0f, seg);
+    const float om = 1.0f - seg;
     const u32x4 w = draw(a.seed, TAG_MUT_SLOT, gen, i, s);
     if (!qutrit_mode) {
-        const uint32_t d = (uint32_t)floorf(__fmul_rn(om, a.r32));
+        const uint32_t d = (uint32_t)floorf(om * a.r32);
         a.theta[o] = (w.x & 1u) ? a.theta[o] - d : a.theta[o] + d;
     } else {
         const int j = (int)scale_u32(w.y, 8u);
-        const float u = __fmul_rn((float)(w.z >> 8), 0x1p-24f);
-        const float x = __fmul_rn(u, om);
-        const int ai = (int)floorf(__fmul_rn(x, 4096.0f));
+        const float u = (float)(w.z >> 8) * 0x1p-24f;
+        const float x = u * om;
+        const int ai = (int)floorf(x * 4096.0f);
         su3_step(a.qutrit + 6 * ((size_t)i * a.Q + s), j, ai, a.su3_tab);
     }
 }
@@ -415,7 +407,7 @@ __global__ __launch_bounds__(256) void ga_update_kernel(LoopArgs a, uint64_t gen
     int bi = 0x7FFFFFFF;
     for (int k = tid; k < P; k += nt) {
         const float v = fi[k];
-        pre[k + 1] = (v >= 0.0f) ? (unsigned long long)(uint32_t)floorf(__fmul_rn(v, 16777216.0f)) : 0ull;
+        pre[k + 1] = (v >= 0.0f) ? (unsigned long long)(uint32_t)floorf(v * 16777216.0f) : 0ull;
         if (v > best) { best = v; bi = k; }
     }
     for (int m = 32; m >= 1; m >>= 1) {

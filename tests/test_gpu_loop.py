@@ -1,0 +1,267 @@
+"""Bit-exact parity of the HIP circuit construction and update kernels with the
+CPU oracle (teacher-forced: the oracle update is given the GPU's pre-update
+state and the GPU's fitness values), plus the equivalence of the fused,
+step-by-step and graph-captured generation loops, elite FP64 re-check,
+best-circuit tracking and checkpoint / resume."""
+import numpy as np
+import pytest
+import torch
+
+from paper_1809_11134_amd import inputs, qe
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    qe.load()
+    return torch.device("cuda", 0)
+
+
+def targets_for(oracle, n, I, seed, permutation=True):
+    rng = np.random.default_rng(seed)
+    return np.stack([oracle.unitary(n, inputs.random_target_gates(rng, n, 12, lib=0,
+                                                                    permutation=permutation))
+                     for _ in range(I)])
+
+
+def qeqea_ctx(dev, oracle, n, L, P, I, seed, pm=0.3):
+    ctx = qe.Context(n, qe.LIB_NCV, qe.ALG_QEQEA, L, P, I, prob_mutation=pm,
+                     mutation_range=float(np.pi / 4), seed=seed)
+    T = targets_for(oracle, n, I, seed)
+    ctx.set_targets(torch.from_numpy(T).to(dev))
+    return ctx, T
+
+
+def gpu_state(ctx):
+    torch.cuda.synchronize()
+    return {k: ctx.state(k).cpu().numpy() for k in ("theta", "qutrit", "best_f", "best_theta",
+                                                    "best_qutrit")}
+
+
+def to_oracle(oracle, ctx, st):
+    o = oracle.QeqeaState(ctx.n, ctx.L, ctx.P, ctx.I, ctx.problem.seed)
+    o.theta[:] = st["theta"].view(np.uint32)
+    o.qutrit[:] = st["qutrit"]
+    o.best_f[:] = st["best_f"]
+    o.best_theta[:] = st["best_theta"].view(np.uint32)
+    o.best_qutrit[:] = st["best_qutrit"]
+    return o
+
+
+def assert_same_state(o, st):
+    assert np.array_equal(o.theta, st["theta"].view(np.uint32))
+    assert np.array_equal(o.best_theta, st["best_theta"].view(np.uint32))
+    assert np.array_equal(o.best_f.view(np.uint32), st["best_f"].view(np.uint32))
+    assert np.array_equal(o.qutrit.view(np.uint32), st["qutrit"].view(np.uint32))
+    assert np.array_equal(o.best_qutrit.view(np.uint32), st["best_qutrit"].view(np.uint32))
+
+
+@pytest.mark.parametrize("n", [2, 3, 4, 5, 6])
+def test_qeqea_init_and_sampling_bitexact(dev, oracle, n):
+    L, P, I, seed = 13, 24, 3, 4242 + n
+    ctx, _ = qeqea_ctx(dev, oracle, n, L, P, I, seed)
+    o = oracle.QeqeaState(n, L, P, I, seed)
+    assert_same_state(o, gpu_state(ctx))
+    for gen in (0, 1, 7, 2 ** 31 + 5):
+        slots, gates = ctx.sample(gen)
+        rs, rg = o.sample(gen)
+        assert np.array_equal(slots.cpu().numpy().view(np.uint32), rs)
+        assert np.array_equal(gates.cpu().numpy().view(np.uint16), rg)
+
+
+@pytest.mark.parametrize("n", [2, 3, 4, 5, 6])
+def test_qeqea_update_teacher_forced(dev, oracle, n):
+    L, P, I, seed = 11, 16, 2, 777 + n
+    pm = 0.45
+    ctx, T = qeqea_ctx(dev, oracle, n, L, P, I, seed, pm=pm)
+    modes = set()
+    for gen in range(6):
+        st = gpu_state(ctx)
+        o = to_oracle(oracle, ctx, st)
+        slots, gates = ctx.sample(gen)
+        rs, rg = o.sample(gen)
+        assert np.array_equal(slots.cpu().numpy().view(np.uint32), rs)
+        assert np.array_equal(gates.cpu().numpy().view(np.uint16), rg)
+        f = ctx.eval_population(gates)
+        fh = f.cpu().numpy()
+        ref = np.array([oracle.fitness(n, rg[c], T[c // P])[0] for c in range(I * P)])
+        assert np.abs(fh - ref).max() <= 1e-5
+        ctx.update(gen, slots, gates, f)
+        o.update(gen, pm, float(np.pi / 4), rs, fh)
+        assert_same_state(o, gpu_state(ctx))
+        # record which mutation modes this generation exercised
+        for i in range(I):
+            for ind in range(P):
+                w = oracle.philox([3, gen, i, ind], [seed & 0xFFFFFFFF, seed >> 32])
+                if w[0] < int(pm * 2 ** 32):
+                    modes.add(int(w[1] & 1))
+    assert modes == {0, 1}
+
+
+def run_steps(ctx, gens):
+    fs = []
+    for gen in gens:
+        slots, gates = ctx.sample(gen)
+        f = ctx.eval_population(gates)
+        ctx.update(gen, slots, gates, f)
+        fs.append(f.clone())
+    return fs
+
+
+@pytest.mark.parametrize("n", [3, 4, 5])
+def test_generation_and_graph_equal_steps(dev, oracle, n):
+    L, P, I, seed, G = 20, 32, 4, 99 + n, 5
+    a, _ = qeqea_ctx(dev, oracle, n, L, P, I, seed)
+    b, _ = qeqea_ctx(dev, oracle, n, L, P, I, seed)
+    c, _ = qeqea_ctx(dev, oracle, n, L, P, I, seed)
+    fa = run_steps(a, range(2 * G))
+    fb = [b.generation(gen).clone() for gen in range(2 * G)]
+    hist = torch.empty((G, I * P), dtype=torch.float32, device=dev)
+    fc = []
+    for rep in range(2):
+        c.run_graph(rep * G, G, hist)
+        torch.cuda.synchronize()
+        fc += [hist[j].clone() for j in range(G)]
+    sa, sb, sc = gpu_state(a), gpu_state(b), gpu_state(c)
+    for k in sa:
+        assert np.array_equal(sa[k], sb[k]) and np.array_equal(sa[k], sc[k]), k
+    for x, y, z in zip(fa, fb, fc):
+        assert torch.equal(x, y) and torch.equal(x, z)
+    ga = a.get_best(0, with_fp64=False)
+    assert ga[:2] == c.get_best(0, with_fp64=False)[:2]
+
+
+def test_graph_replays_are_stable(dev, oracle):
+    # several replays with eager work and synchronisation between them
+    n, L, P, I, seed = 4, 16, 64, 2, 5
+    a, _ = qeqea_ctx(dev, oracle, n, L, P, I, seed)
+    b, _ = qeqea_ctx(dev, oracle, n, L, P, I, seed)
+    for rep in range(4):
+        a.run_graph(3 * rep, 3)
+        torch.cuda.synchronize()
+        _ = torch.ones(1000, device=dev).sum().item()
+        for gen in range(3 * rep, 3 * rep + 3):
+            b.generation(gen)
+        sa, sb = gpu_state(a), gpu_state(b)
+        for k in sa:
+            assert np.array_equal(sa[k], sb[k]), (rep, k)
+
+
+def test_ga_teacher_forced(dev, oracle):
+    w = inputs.workload_ga_n3()
+    n, L, P = w["n"], w["L"], w["P"]
+    seed = w["seed"]
+    ctx = qe.Context(n, w["lib"], qe.ALG_GA, L, P, 1, seed=seed, ga_crossover_prob=0.9,
+                     ga_gene_mutation_prob=1.0 / L)
+    T = oracle.unitary(n, w["target_gates"][0])[None]
+    ctx.set_targets(torch.from_numpy(T).to(dev))
+    genomes = oracle.ga_init(n, w["lib"], L, P, 1, seed)
+    assert np.array_equal(ctx.state("genomes0").cpu().numpy().view(np.uint16).reshape(P, L), genomes)
+    best = -1.0
+    for gen in range(w["generations"]):
+        _, gates = ctx.sample(gen)
+        assert np.array_equal(gates.cpu().numpy().view(np.uint16), genomes)
+        f = ctx.eval_population(gates)
+        fh = f.cpu().numpy()
+        ref = np.array([oracle.fitness(n, genomes[k], T[0])[0] for k in range(P)])
+        assert np.abs(fh - ref).max() <= 1e-5
+        best = max(best, float(fh.max()))
+        ctx.update(gen, None, gates, f)
+        genomes = oracle.ga_update(n, w["lib"], L, P, 1, seed, gen, 0.9, 1.0 / L, fh, genomes)
+        torch.cuda.synchronize()
+        got = ctx.state("genomes1" if gen % 2 == 0 else "genomes0").cpu().numpy().view(np.uint16)
+        assert np.array_equal(got.reshape(P, L), genomes), gen
+    g, f32, f64 = ctx.get_best(0)
+    assert f32 == pytest.approx(best, abs=0)
+    assert abs(f64 - oracle.fitness(n, g, T[0])[0]) <= 1e-12
+    assert abs(f64 - f32) <= 1e-5
+
+
+def test_ga_graph_equals_generations(dev, oracle):
+    n, L, P, I, seed = 4, 12, 48, 3, 31
+    T = torch.from_numpy(targets_for(oracle, n, I, seed, permutation=False)).to(dev)
+    a = qe.Context(n, 0, qe.ALG_GA, L, P, I, seed=seed)
+    b = qe.Context(n, 0, qe.ALG_GA, L, P, I, seed=seed)
+    a.set_targets(T)
+    b.set_targets(T)
+    fa = [a.generation(gen).clone() for gen in range(6)]
+    hist = torch.empty((6, I * P), dtype=torch.float32, device=dev)
+    b.run_graph(0, 6, hist)
+    torch.cuda.synchronize()
+    for j in range(6):
+        assert torch.equal(fa[j], hist[j])
+    assert torch.equal(a.state("genomes0"), b.state("genomes0"))
+
+
+@pytest.mark.parametrize("n", [3, 5])
+def test_elite_recheck(dev, oracle, n):
+    L, P, I, seed, k = 16, 64, 3, 12 + n, 8
+    ctx, T = qeqea_ctx(dev, oracle, n, L, P, I, seed)
+    slots, gates = ctx.sample(0)
+    f = ctx.eval_population(gates)
+    idx, f64 = ctx.elite_recheck(gates, f, k)
+    fh, gh = f.cpu().numpy(), gates.cpu().numpy().view(np.uint16)
+    idx, f64 = idx.cpu().numpy(), f64.cpu().numpy()
+    for i in range(I):
+        fi = fh[i * P:(i + 1) * P]
+        want = sorted(range(P), key=lambda c: (-fi[c], c))[:k]
+        assert list(idx[i]) == want
+        for e in range(k):
+            ref = oracle.fitness(n, gh[i * P + idx[i, e]], T[i])[0]
+            assert abs((1 - f64[i, e]) ** 2 - (1 - ref) ** 2) <= 1e-12
+            assert abs(f64[i, e] - fi[idx[i, e]]) <= 1e-5
+
+
+def test_checkpoint_resume(dev, oracle):
+    n, L, P, I, seed = 4, 10, 32, 2, 2024
+    a, T = qeqea_ctx(dev, oracle, n, L, P, I, seed, pm=0.5)
+    for gen in range(3):
+        a.generation(gen)
+    blob = a.checkpoint()
+    fa = [a.generation(gen).clone() for gen in range(3, 7)]
+    sa = gpu_state(a)
+    b, _ = qeqea_ctx(dev, oracle, n, L, P, I, seed, pm=0.5)
+    b.restore(blob)
+    fb = [b.generation(gen).clone() for gen in range(3, 7)]
+    sb = gpu_state(b)
+    for k in sa:
+        assert np.array_equal(sa[k], sb[k]), k
+    for x, y in zip(fa, fb):
+        assert torch.equal(x, y)
+    assert a.get_best(1, with_fp64=False)[:2] == b.get_best(1, with_fp64=False)[:2]
+    other = qe.Context(n, 0, qe.ALG_QEQEA, L, P, I, prob_mutation=0.5, seed=seed + 1)
+    with pytest.raises(qe.QeError):
+        other.restore(blob)
+    with pytest.raises(qe.QeError):
+        a.restore(blob[:100])
+
+
+def test_get_best_tracks_maximum(dev, oracle):
+    n, L, P, I, seed = 3, 8, 64, 2, 606
+    ctx, T = qeqea_ctx(dev, oracle, n, L, P, I, seed, pm=0.2)
+    best = [-1.0] * I
+    best_gates = [None] * I
+    for gen in range(8):
+        slots, gates = ctx.sample(gen)
+        f = ctx.eval_population(gates)
+        ctx.update(gen, slots, gates, f)
+        fh, gh = f.cpu().numpy(), gates.cpu().numpy().view(np.uint16)
+        for i in range(I):
+            fi = fh[i * P:(i + 1) * P]
+            k = int(np.argmax(fi))
+            if fi[k] > best[i]:
+                best[i], best_gates[i] = float(fi[k]), list(gh[i * P + k])
+    for i in range(I):
+        g, f32, f64 = ctx.get_best(i)
+        assert f32 == best[i] and g == best_gates[i]
+        assert abs(f64 - oracle.fitness(n, g, T[i])[0]) <= 1e-12
+
+
+def test_state_requires_targets(dev):
+    ctx = qe.Context(3, 0, qe.ALG_QEQEA, 4, 4, 1, seed=1)
+    with pytest.raises(qe.QeError) as e:
+        ctx.generation(0)
+    assert e.value.status == qe.QE_ERR_STATE
