@@ -1,0 +1,214 @@
+#!/usr/bin/env python3
+"""Throughput of the QEQEA circuit-fitness hot path on one MI355X.
+
+Workload (seeded, synthetic): n = 4 wires, library {I, NOT, CNOT, CV, CV+},
+one QEQEA population whose encoding is sampled into P = 4096 circuits of
+L = 30 gates per generation; target = a random reversible permutation built
+from 12 NOT/CNOT gates (the paper's targets are small reversible gates).
+A step is one generation of the whole hot path: circuit construction by
+sampling (Sec. IV-D), Eq. 11 fitness of all P circuits (FP32), segment
+fitness / elitism / adaptive mutation (Secs. IV-E.1, IV-F).  The K timed
+generations run as one HIP graph; the final FP64 re-check of the last
+generation's 32 best circuits is inside the timed region.
+
+Prints one JSON line (the metric is circuit-fitness evaluations per second)
+with a roofline entry for the dominant kernel (the fused sampling + fitness
+kernel, timed per launch with HIP events) and the CPU oracle's rate on a
+bounded sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "circuit-fitness evals/sec (n=4..6), FP32 vs BF16-MFMA at stated fitness error"
+FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X, 256 CUs x 4 SIMD x 16 lanes x 2 x 2 (packed) x 2.4 GHz
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def source_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1809_11134_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as fh:
+            h.update(name.encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_flops(gates, n):
+    """Real floating-point operations the method needs for these circuits
+    (N = 2^n): a CV or CV+ gate updates the N^2/2 controlled entries of
+    U T^dagger at 6 flops each, H all N^2 entries at 4, T N^2/2 at 4; NOT,
+    CNOT and I only permute rows (0); the fitness reduction reads every entry
+    once (|m|^2 accumulated: 4 flops)."""
+    import numpy as np
+    NN = float(1 << (2 * n))
+    kinds = np.asarray(gates).astype(np.int64) & 15
+    per_kind = np.zeros(16)
+    per_kind[3] = per_kind[4] = 3.0 * NN
+    per_kind[5] = 4.0 * NN
+    per_kind[6] = 2.0 * NN
+    return float(per_kind[kinds].sum() + kinds.shape[0] * 4.0 * NN)
+
+
+def traffic_from_profiles(kernel_key, src_hash):
+    path = os.path.join(ROOT, "profiles", f"pmc_{kernel_key}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("source_hash") != src_hash:
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(w, T, seconds):
+    """The oracle (test infrastructure) on a bounded sample of the workload:
+    whole generations -- sampling, FP64 fitness of all P circuits (OpenMP
+    over circuits), update -- until `seconds` of wall time have passed."""
+    import numpy as np
+    from oracle import oracle as O
+    n, L, P = w["n"], w["L"], w["P"]
+    st = O.QeqeaState(n, L, P, 1, w["seed"])
+    nq = np.full(P, n, np.int8)
+    goff = np.arange(P + 1, dtype=np.int32) * L
+    toff = np.zeros(P, np.int64)
+    gens = 0
+    t0 = time.perf_counter()
+    while True:
+        slots, gates = st.sample(gens)
+        out = O.eval_batch(nq, goff, gates.ravel(), toff, T)
+        st.update(gens, 0.1, math.pi / 4, slots, out[:, 0].astype(np.float32))
+        gens += 1
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            break
+    return dict(value=gens * P / el, unit="evals/s", cores=O.num_threads(), kind="oracle",
+                sample=f"{gens} whole QEQEA generations of the n=4, P={P}, L={L} workload "
+                       f"({gens * P} circuit evaluations in FP64 over OpenMP threads, sampling "
+                       f"and update single-threaded), {el:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel-reps", type=int, default=50)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the hot path of this build runs on a single MI355X "
+              "(independent populations would shard across GPUs with no exchange; see the "
+              "design notes).  Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+    K, W = args.steps, args.warmup
+    if K < 1 or W < 1:
+        ap.error("--steps and --warmup must be >= 1")
+
+    import numpy as np
+    import torch
+    from paper_1809_11134_amd import inputs, qe
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    qe.load()
+    w = inputs.workload_qeqea_n4()
+    n, L, P, I = w["n"], w["L"], w["P"], w["instances"]
+    log(f"workload {w['name']}: n={n} L={L} P={P} instances={I}; steps={K} warmup={W}")
+
+    tg = torch.from_numpy(np.stack(w["target_gates"]).astype(np.int16)).to(dev)
+    T = qe.build_unitary(tg, n, tg.shape[1], precision=1)          # [I, N, N] complex128
+    ctx = qe.Context(n, w["lib"], qe.ALG_QEQEA, L, P, I, prob_mutation=0.1,
+                     mutation_range=math.pi / 4, seed=w["seed"])
+    ctx.set_targets(T)
+    f_warm = torch.empty((W, I * P), dtype=torch.float32, device=dev)
+    f_hist = torch.empty((K, I * P), dtype=torch.float32, device=dev)
+    ctx.graph_prepare(W, f_warm)
+    ctx.graph_prepare(K, f_hist)
+    ctx.run_graph(0, W, f_warm)
+    torch.cuda.synchronize()
+    log("warmup done")
+
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record()
+    ctx.run_graph(W, K, f_hist)
+    idx, f64 = ctx.elite_recheck(None, f_hist[K - 1], 32)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    assert qe.device_errors() == 0, "device error flags raised"
+    value = K * I * P / (ms / 1e3)
+    log(f"timed: {K} generations in {ms:.3f} ms (wall {wall * 1e3:.3f} ms) -> {value:.4g} evals/s")
+
+    # FP32 vs FP64 fitness error on the re-checked elites of the last generation
+    f32_el = f_hist[K - 1].view(I, P).gather(1, idx.long()).double()
+    fit_err = float((f32_el - f64).abs().max().item())
+
+    # dominant kernel: fused sampling + fitness, timed launch by launch
+    R = max(1, args.kernel_reps)
+    slots = torch.empty((I * P, L), dtype=torch.int32, device=dev)
+    gates = torch.empty((I * P, L), dtype=torch.int16, device=dev)
+    fk = torch.empty(I * P, dtype=torch.float32, device=dev)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(R)]
+    flops = 0.0
+    for r in range(R):
+        evs[r][0].record()
+        ctx.sample_eval(W + K + r, slots, gates, fk)
+        evs[r][1].record()
+        if r == R - 1:
+            torch.cuda.synchronize()
+            flops = algorithmic_flops(gates.cpu().numpy(), n)
+    torch.cuda.synchronize()
+    kern_ms = sum(a.elapsed_time(b) for a, b in evs) / R
+    achieved = flops / (kern_ms / 1e3) / 1e12
+    src = source_hash()
+    roofline = {"bound": "alu", "achieved": round(achieved, 4), "peak": FP32_VECTOR_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 6),
+                "traffic": traffic_from_profiles("qeqea_fused_n4", src),
+                "kernel": "population_kernel<4,0,true> (sampling + Eq. 11 fitness + segment max)",
+                "kernel_ms": round(kern_ms, 6), "algorithmic_flops_per_launch": flops}
+    log(f"dominant kernel: {kern_ms * 1e3:.2f} us/launch, {achieved:.3f} TFLOP/s algorithmic")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log(f"cpu baseline: oracle for ~{args.cpu_seconds:.0f} s")
+        Th = T[0].cpu().numpy()
+        cpu = cpu_baseline(w, Th, args.cpu_seconds)
+        log(f"cpu baseline: {cpu['value']:.4g} evals/s on {cpu['cores']} threads")
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "evals/s", "n_gpus": 1, "steps": K,
+        "warmup": W, "ms_per_step": ms / K, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": w["name"], "n_qubits": n, "library": "I,NOT,CNOT,CV,CV+",
+                   "algorithm": "QEQEA", "population": P, "layers": L, "instances": I,
+                   "path": "fp32", "graph": True, "elite_fp64_recheck": 32,
+                   "parallelism": "single GPU"},
+        "fitness_error_fp32_vs_fp64": fit_err,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "source_hash": src,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -198,6 +198,19 @@ qe_status qe_update(qe_ctx* ctx, uint64_t gen, const uint32_t* slots_dev,
  * Results equal qe_sample, qe_eval_population and qe_update in sequence. */
 qe_status qe_generation(qe_ctx* ctx, uint64_t gen, float* f_dev, void* stream);
 
+/* The first half of qe_generation for QEQEA, one kernel launch: circuit
+ * construction (as qe_sample, into slots_dev / gates_dev) fused with the
+ * fitness evaluation (f_dev) and the segment-fitness maximum that qe_update
+ * starts from.  qe_update(gen, slots, gates, f) afterwards completes the
+ * generation with the same result as qe_generation.  QEQEA only. */
+qe_status qe_sample_eval(qe_ctx* ctx, uint64_t gen, uint32_t* slots_dev, uint16_t* gates_dev,
+                         float* f_dev, void* stream);
+
+/* Captures and instantiates the graph that qe_run_graph(n_gen, f_hist_dev)
+ * replays, without running it (so that a later qe_run_graph does no capture
+ * work).  Syncs nothing; safe to call again (no-op when cached). */
+qe_status qe_graph_prepare(qe_ctx* ctx, int32_t n_gen, float* f_hist_dev);
+
 /* Runs generations first_gen .. first_gen + n_gen - 1 as one HIP graph
  * (captured on first use for this n_gen and f_hist_dev, then replayed);
  * f_hist_dev [n_gen][I*P] or NULL.  Same results as n_gen qe_generation
@@ -207,8 +220,10 @@ qe_status qe_run_graph(qe_ctx* ctx, uint64_t first_gen, int32_t n_gen, float* f_
 
 /* FP64 re-check of elite circuits: for each instance, the k circuits of
  * gates_dev with the highest f_dev (ties: lowest index) are re-evaluated in
- * FP64 against the complex128 target.  idx_dev [I][k] (int32, circuit index
- * within the instance), f64_dev [I][k].  1 <= k <= P. */
+ * FP64 against the complex128 target.  gates_dev NULL: the circuits of the
+ * last generation run by qe_generation / qe_run_graph (f_dev must then be
+ * that generation's fitness).  idx_dev [I][k] (int32, circuit index within
+ * the instance), f64_dev [I][k].  1 <= k <= P <= 4096. */
 qe_status qe_elite_recheck(qe_ctx* ctx, const uint16_t* gates_dev, const float* f_dev,
                            int32_t k, int32_t* idx_dev, double* f64_dev, void* stream);
 

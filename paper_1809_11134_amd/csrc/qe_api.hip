@@ -434,39 +434,62 @@ qe_status qe_generation(qe_ctx* c, uint64_t gen, float* f, void* stream) {
     return enqueue_generation(c, c->la, gen, f ? f : c->f, (hipStream_t)stream);
 }
 
+qe_status qe_sample_eval(qe_ctx* c, uint64_t gen, uint32_t* slots, uint16_t* gates, float* f,
+                         void* stream) {
+    QE_TRY(check_ctx(c, true));
+    if (c->prob.algorithm != QE_ALG_QEQEA) return fail(QE_ERR_UNSUPPORTED, "qe_sample_eval is QEQEA only");
+    if (!slots || !gates || !f) return fail(QE_ERR_INVALID, "NULL buffer");
+    QE_HIP(launch_qeqea_fused(c->la, gen, slots, gates, f, (hipStream_t)stream));
+    return QE_OK;
+}
+
+static qe_status graph_for(qe_ctx* c, int32_t n_gen, float* f_hist, hipGraphExec_t* out) {
+    auto key = std::make_pair((int)n_gen, f_hist);
+    auto it = c->graphs.find(key);
+    if (it != c->graphs.end()) { *out = it->second; return QE_OK; }
+    LoopArgs a = c->la;
+    a.gen_ptr = c->d_gen;
+    const size_t IP = (size_t)c->prob.n_instances * c->prob.size_of_population;
+    hipGraph_t g = nullptr;
+    QE_HIP(hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
+    qe_status st = QE_OK;
+    for (int j = 0; j < n_gen && st == QE_OK; ++j)
+        st = enqueue_generation(c, a, (uint64_t)j, f_hist ? f_hist + j * IP : c->f, c->capture_stream);
+    hipError_t e = hipStreamEndCapture(c->capture_stream, &g);
+    if (st != QE_OK) { if (g) hipGraphDestroy(g); return st; }
+    if (e != hipSuccess) return fail(QE_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(QE_ERR_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+    c->graphs.emplace(key, ex);
+    *out = ex;
+    return QE_OK;
+}
+
+qe_status qe_graph_prepare(qe_ctx* c, int32_t n_gen, float* f_hist) {
+    QE_TRY(check_ctx(c, true));
+    if (n_gen < 1) return fail(QE_ERR_INVALID, "n_gen must be >= 1");
+    hipGraphExec_t ex;
+    return graph_for(c, n_gen, f_hist, &ex);
+}
+
 qe_status qe_run_graph(qe_ctx* c, uint64_t first_gen, int32_t n_gen, float* f_hist, void* stream) {
     QE_TRY(check_ctx(c, true));
     if (n_gen < 1) return fail(QE_ERR_INVALID, "n_gen must be >= 1");
     hipStream_t s = (hipStream_t)stream;
-    auto key = std::make_pair((int)n_gen, f_hist);
-    auto it = c->graphs.find(key);
-    if (it == c->graphs.end()) {
-        LoopArgs a = c->la;
-        a.gen_ptr = c->d_gen;
-        const size_t IP = (size_t)c->prob.n_instances * c->prob.size_of_population;
-        hipGraph_t g = nullptr;
-        QE_HIP(hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
-        qe_status st = QE_OK;
-        for (int j = 0; j < n_gen && st == QE_OK; ++j)
-            st = enqueue_generation(c, a, (uint64_t)j, f_hist ? f_hist + j * IP : c->f, c->capture_stream);
-        hipError_t e = hipStreamEndCapture(c->capture_stream, &g);
-        if (st != QE_OK) { if (g) hipGraphDestroy(g); return st; }
-        if (e != hipSuccess) return fail(QE_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
-        hipGraphExec_t ex = nullptr;
-        e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-        hipGraphDestroy(g);
-        if (e != hipSuccess) return fail(QE_ERR_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
-        it = c->graphs.emplace(key, ex).first;
-    }
+    hipGraphExec_t ex;
+    QE_TRY(graph_for(c, n_gen, f_hist, &ex));
     QE_HIP(launch_gen_set(c->d_gen, first_gen, s));
-    QE_HIP(hipGraphLaunch(it->second, s));
+    QE_HIP(hipGraphLaunch(ex, s));
     return QE_OK;
 }
 
 qe_status qe_elite_recheck(qe_ctx* c, const uint16_t* gates, const float* f, int32_t k,
                            int32_t* idx, double* f64, void* stream) {
     QE_TRY(check_ctx(c, true));
-    if (!gates || !f || !idx || !f64) return fail(QE_ERR_INVALID, "NULL buffer");
+    if (!f || !idx || !f64) return fail(QE_ERR_INVALID, "NULL buffer");
+    if (!gates) gates = c->gates;
     if (k < 1 || k > c->prob.size_of_population) return fail(QE_ERR_INVALID, "k must be 1..P");
     if (c->prob.size_of_population > 4096) return fail(QE_ERR_UNSUPPORTED, "elite selection needs P <= 4096");
     hipStream_t s = (hipStream_t)stream;

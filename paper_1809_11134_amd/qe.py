@@ -77,6 +77,8 @@ def load():
         "qe_update": [vp, u64, vp, vp, vp, vp],
         "qe_generation": [vp, u64, vp, vp],
         "qe_run_graph": [vp, u64, i32, vp, vp],
+        "qe_sample_eval": [vp, u64, vp, vp, vp, vp],
+        "qe_graph_prepare": [vp, i32, vp],
         "qe_elite_recheck": [vp, vp, vp, i32, vp, vp, vp],
         "qe_get_best": [vp, i32, vp, P(ctypes.c_float), P(ctypes.c_double)],
         "qe_checkpoint": [vp, vp, P(ctypes.c_size_t)],
@@ -304,13 +306,28 @@ class Context:
         _call("qe_generation", self.handle, gen, _ptr(f), _stream(stream))
         return f
 
+    def sample_eval(self, gen, slots=None, gates=None, f=None, stream=None):
+        dev = torch.device("cuda", torch.cuda.current_device())
+        if slots is None:
+            slots = torch.empty((self.circuits, self.L), dtype=torch.int32, device=dev)
+        if gates is None:
+            gates = torch.empty((self.circuits, self.L), dtype=torch.int16, device=dev)
+        if f is None:
+            f = torch.empty(self.circuits, dtype=torch.float32, device=dev)
+        _call("qe_sample_eval", self.handle, gen, _ptr(slots), _ptr(gates), _ptr(f), _stream(stream))
+        return slots, gates, f
+
+    def graph_prepare(self, n_gen, f_hist=None):
+        _call("qe_graph_prepare", self.handle, n_gen, _ptr(f_hist))
+
     def run_graph(self, first_gen, n_gen, f_hist=None, stream=None):
         _call("qe_run_graph", self.handle, first_gen, n_gen, _ptr(f_hist), _stream(stream))
 
     def elite_recheck(self, gates, f, k, stream=None):
         idx = torch.empty((self.I, k), dtype=torch.int32, device=f.device)
         f64 = torch.empty((self.I, k), dtype=torch.float64, device=f.device)
-        _call("qe_elite_recheck", self.handle, _ptr(_gates(gates)), _ptr(f.contiguous()), k,
+        _call("qe_elite_recheck", self.handle, _ptr(_gates(gates) if gates is not None else None),
+              _ptr(f.contiguous()), k,
               _ptr(idx), _ptr(f64), _stream(stream))
         return idx, f64
 
