@@ -338,6 +338,7 @@ qe_status qe_create(const qe_problem* p, qe_ctx** out) {
     a.target32 = t32;
     a.target64 = t64;
     ALLOC(a.inst_best_f, I);
+    ALLOC(a.inst_key, I);
     ALLOC(a.inst_best_gates, I * L);
     ALLOC(c->slots, I * P * L);
     ALLOC(c->gates, I * P * L);

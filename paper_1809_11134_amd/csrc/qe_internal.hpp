@@ -48,7 +48,7 @@ struct LoopArgs {
     uint16_t* genomes[2];              // GA double buffer
     const float* target32;             // [I][N][N] complex64
     const double* target64;            // [I][N][N] complex128
-    uint64_t* inst_best_key;           // per instance (f bits << 32 | ~index) of best ever
+    unsigned long long* inst_key;      // per instance: max of (f bits << 32 | ~circuit) this generation
     float* inst_best_f;                // per instance
     uint16_t* inst_best_gates;         // [I][L]
     const float* su3_tab;              // [4][4096]: cos/sin of angles, cos/sin of phases

@@ -100,6 +100,7 @@ __global__ void inst_best_init_kernel(LoopArgs a) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.I) return;
     a.inst_best_f[i] = -1.0f;
+    a.inst_key[i] = 0ull;
     for (int l = 0; l < a.L; ++l) a.inst_best_gates[(size_t)i * a.L + l] = 0;
 }
 
@@ -142,11 +143,18 @@ __device__ __forceinline__ void eval_circuit(const LoopArgs& a, uint32_t gen, ui
     const int lane = (int)lane_id();
     const int L = a.L;
     const float* T = a.target32 + (size_t)2 * i * ((size_t)1 << (2 * NQ));
+    constexpr int KEEP = 4;                 // chunks of 64 slots kept for the scatter
+    uint32_t kept[KEEP];
+#pragma unroll
+    for (int c = 0; c < KEEP; ++c) kept[c] = 0xFFFFFFFFu;
     auto src = [&](int ch) -> uint32_t {
         const int p = ch * 64 + lane;
         if (p >= L) return 0u;
         if (!SAMPLE) return (uint32_t)gates_in[(size_t)ci * L + p];
         const uint32_t s = sample_slot(a, gen, i, k, (uint32_t)p);
+#pragma unroll
+        for (int c = 0; c < KEEP; ++c)
+            if (c == ch) kept[c] = s;
         const uint16_t d = decode_slot(a, gen, i, s);
         if (writer) {
             slots_out[(size_t)ci * L + p] = s;
@@ -195,13 +203,22 @@ __device__ __forceinline__ void eval_circuit(const LoopArgs& a, uint32_t gen, ui
         if (!ok) atomicOr(a.err, (uint32_t)QE_DEVERR_DESC);
         else if (!(fv == fv)) atomicOr(a.err, (uint32_t)QE_DEVERR_NUMERIC);
     }
-    // segment fitness: every slot this circuit used keeps the largest fitness
+    // segment fitness: every slot this circuit used keeps the largest
+    // fitness; the instance keeps its best circuit of the generation
     if (SAMPLE && writer && fv >= 0.0f) {
         const int32_t fb = (int32_t)__float_as_uint(fv);
-        for (int p = lane; p < L; p += 64) {
+#pragma unroll
+        for (int c = 0; c < KEEP; ++c) {
+            const int p = c * 64 + lane;
+            if (p < L) atomicMax(a.segfit + (size_t)i * a.S + kept[c], fb);
+        }
+        for (int p = KEEP * 64 + lane; p < L; p += 64) {
             const uint32_t s = sample_slot(a, gen, i, k, (uint32_t)p);
             atomicMax(a.segfit + (size_t)i * a.S + s, fb);
         }
+        if (lane == 0)
+            atomicMax(a.inst_key + i, ((unsigned long long)__float_as_uint(fv) << 32) |
+                                          (unsigned long long)(0xFFFFFFFFu - k));
     }
 }
 
@@ -236,6 +253,10 @@ __global__ void scatter_kernel(LoopArgs a, const uint32_t* __restrict__ slots,
     const uint32_t s = slots[idx];
     if (!(fv >= 0.0f) || s >= a.S) return;
     atomicMax(a.segfit + (size_t)i * a.S + s, (int32_t)__float_as_uint(fv));
+    const uint32_t k = (uint32_t)((idx / a.L) % a.P);
+    if (idx % a.L == 0)
+        atomicMax(a.inst_key + i, ((unsigned long long)__float_as_uint(fv) << 32) |
+                                      (unsigned long long)(0xFFFFFFFFu - k));
 }
 
 // ------------------------------------------------------------------- update
@@ -312,72 +333,65 @@ __device__ __forceinline__ void mutate_slot(const LoopArgs& a, uint32_t gen, uin
 }
 
 // Part A: used slots of individuals that do not mutate (one thread per
-// (circuit, position) entry; atomicExch claims each slot exactly once and
-// resets its segment fitness).  Part B: individuals that mutate (one
-// wavefront each): every slot is claimed, passes elitism if it was used,
-// then mutates.  Part C: best circuit per instance (one wavefront each).
-__global__ __launch_bounds__(256) void qeqea_update_kernel(LoopArgs a, uint64_t gen64,
-                                                           const uint32_t* __restrict__ slots,
-                                                           const uint16_t* __restrict__ gates,
-                                                           const float* __restrict__ f,
-                                                           uint32_t nA, uint32_t nB) {
+// (circuit, position) entry; several entries may name the same slot, so
+// atomicExch claims each slot exactly once and resets its segment fitness).
+// Part B: individuals that mutate (one workgroup each, owning all the
+// individual's slots, so plain loads suffice): every slot passes elitism if
+// it was used, then mutates (qubit mode: every slot; qutrit mode: rotation
+// slots).  Part C: the instance's best circuit of the generation (packed
+// key set by the fitness kernel) updates its best circuit ever.
+constexpr int UPD_BLOCK = 256;
+
+__global__ __launch_bounds__(UPD_BLOCK) void qeqea_update_kernel(LoopArgs a, uint64_t gen64,
+                                                                 const uint32_t* __restrict__ slots,
+                                                                 const uint16_t* __restrict__ gates,
+                                                                 uint32_t nA, uint32_t nB) {
     const uint32_t gen = gen_of(a, gen64);
-    const uint32_t LP = (uint32_t)a.L * (uint32_t)a.P;
+    const uint32_t L = (uint32_t)a.L, P = (uint32_t)a.P;
+    const uint32_t LP = L * P;
     if (blockIdx.x < nA) {
-        const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-        const size_t per = (size_t)a.P * a.L;
-        if (idx >= (size_t)a.I * per) return;
-        const uint32_t i = (uint32_t)(idx / per);
+        const uint32_t idx = blockIdx.x * UPD_BLOCK + threadIdx.x;
+        const uint32_t per = LP;
+        if (idx >= (uint32_t)a.I * per) return;
+        const uint32_t i = idx / per;
         const uint32_t s = slots[idx];
         if (s >= a.S) return;
-        const uint32_t ind = (s % LP) / (uint32_t)a.L;
+        const uint32_t ind = (s % LP) / L;
         bool qm;
         if (mutated(a, gen, i, ind, &qm)) return;
         const int32_t v = atomicExch(a.segfit + (size_t)i * a.S + s, -1);
         if (v >= 0) elitism(a, i, s, __int_as_float(v));
     } else if (blockIdx.x < nA + nB) {
-        const uint32_t id = (blockIdx.x - nA) * 4 + (threadIdx.x >> 6);
-        if (id >= (uint32_t)a.I * (uint32_t)a.P) return;
-        const uint32_t i = id / (uint32_t)a.P, ind = id % (uint32_t)a.P;
+        const uint32_t id = blockIdx.x - nA;
+        const uint32_t i = id / P, ind = id % P;
         bool qm;
         if (!mutated(a, gen, i, ind, &qm)) return;
-        const uint32_t regions = qm ? (uint32_t)a.n : (uint32_t)(a.n * a.n);
-        const uint32_t cnt = regions * (uint32_t)a.L;
-        for (uint32_t e = lane_id(); e < cnt; e += 64) {
-            const uint32_t r = e / (uint32_t)a.L, pos = e % (uint32_t)a.L;
-            const uint32_t s = r * LP + ind * (uint32_t)a.L + pos;
-            const int32_t v = atomicExch(a.segfit + (size_t)i * a.S + s, -1);
-            if (v >= 0) elitism(a, i, s, __int_as_float(v));
-            mutate_slot(a, gen, i, s, qm);
-        }
-        if (qm) {
-            // qubit-only slots of a qutrit-mode individual still pass elitism
-            const uint32_t cnt2 = (uint32_t)(a.n * a.n - a.n) * (uint32_t)a.L;
-            for (uint32_t e = lane_id(); e < cnt2; e += 64) {
-                const uint32_t r = (uint32_t)a.n + e / (uint32_t)a.L, pos = e % (uint32_t)a.L;
-                const uint32_t s = r * LP + ind * (uint32_t)a.L + pos;
-                const int32_t v = atomicExch(a.segfit + (size_t)i * a.S + s, -1);
-                if (v >= 0) elitism(a, i, s, __int_as_float(v));
+        const uint32_t regions = (uint32_t)(a.n * a.n);
+        const uint32_t rot = (uint32_t)a.n;
+        for (uint32_t e = threadIdx.x; e < regions * L; e += UPD_BLOCK) {
+            const uint32_t r = e / L, pos = e - r * L;
+            const uint32_t s = r * LP + ind * L + pos;
+            int32_t* sf = a.segfit + (size_t)i * a.S + s;
+            const int32_t v = *sf;
+            if (v >= 0) {
+                *sf = -1;
+                elitism(a, i, s, __int_as_float(v));
             }
+            if (!qm || r < rot) mutate_slot(a, gen, i, s, qm);
         }
     } else {
-        const uint32_t i = (blockIdx.x - nA - nB) * 4 + (threadIdx.x >> 6);
+        const uint32_t i = (blockIdx.x - nA - nB) * (UPD_BLOCK / 64) + (threadIdx.x >> 6);
         if (i >= (uint32_t)a.I) return;
         const int lane = (int)lane_id();
-        float best = -1.0f;
-        int bi = 0x7FFFFFFF;
-        for (int k = lane; k < a.P; k += 64) {
-            const float v = f[(size_t)i * a.P + k];
-            if (v > best) { best = v; bi = k; }
-        }
-        for (int m = 32; m >= 1; m >>= 1) {
-            const float ob = __shfl_xor(best, m, 64);
-            const int oi = __shfl_xor(bi, m, 64);
-            if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-        }
+        unsigned long long key = 0;
+        if (lane == 0) key = atomicExch(a.inst_key + i, 0ull);
+        key = __shfl(key, 0, 64);
+        if (key == 0) return;
+        const float best = __uint_as_float((uint32_t)(key >> 32));
+        const uint32_t k = 0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFu);
         if (best > a.inst_best_f[i]) {
-            const uint16_t* src = gates + ((size_t)i * a.P + bi) * a.L;
-            for (int l = lane; l < a.L; l += 64) a.inst_best_gates[(size_t)i * a.L + l] = src[l];
+            const uint16_t* src = gates + ((size_t)i * P + k) * L;
+            for (uint32_t l = lane; l < L; l += 64) a.inst_best_gates[(size_t)i * L + l] = src[l];
             if (lane == 0) a.inst_best_f[i] = best;
         }
     }
@@ -481,7 +495,7 @@ __global__ __launch_bounds__(256) void ga_update_kernel(LoopArgs a, uint64_t gen
 // --------------------------------------------------------------- elite FP64
 // Top-k circuits of each population by (f descending, index ascending):
 // bitonic sort of P keys in LDS (P <= 4096).
-__global__ __launch_bounds__(256) void elite_select_kernel(LoopArgs a, const float* __restrict__ f,
+__global__ __launch_bounds__(1024) void elite_select_kernel(LoopArgs a, const float* __restrict__ f,
                                                            int k, int32_t* __restrict__ idx_out) {
     __shared__ unsigned long long key[4096];
     const int i = blockIdx.x, P = a.P, tid = threadIdx.x;
@@ -631,10 +645,11 @@ hipError_t launch_scatter(const LoopArgs& a, uint64_t gen, const uint32_t* slots
 
 hipError_t launch_qeqea_update(const LoopArgs& a, uint64_t gen, const uint32_t* slots,
                                const uint16_t* gates, const float* f, hipStream_t s) {
-    const uint32_t nA = blocks((size_t)a.I * a.P * a.L, 256);
-    const uint32_t nB = blocks((size_t)a.I * a.P, 4);
-    const uint32_t nC = blocks((size_t)a.I, 4);
-    qeqea_update_kernel<<<nA + nB + nC, 256, 0, s>>>(a, gen, slots, gates, f, nA, nB);
+    (void)f;   // the fitness reached the update through segfit and inst_key
+    const uint32_t nA = blocks((size_t)a.I * a.P * a.L, UPD_BLOCK);
+    const uint32_t nB = (uint32_t)a.I * (uint32_t)a.P;
+    const uint32_t nC = blocks((size_t)a.I, UPD_BLOCK / 64);
+    qeqea_update_kernel<<<nA + nB + nC, UPD_BLOCK, 0, s>>>(a, gen, slots, gates, nA, nB);
     return hipGetLastError();
 }
 
@@ -644,7 +659,7 @@ hipError_t launch_ga_update(const LoopArgs& a, uint64_t gen, const float* f, hip
 }
 
 hipError_t launch_elite_select(const LoopArgs& a, const float* f, int k, int32_t* idx, hipStream_t s) {
-    elite_select_kernel<<<a.I, 256, 0, s>>>(a, f, k, idx);
+    elite_select_kernel<<<a.I, 1024, 0, s>>>(a, f, k, idx);
     return hipGetLastError();
 }
 
