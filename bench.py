@@ -183,7 +183,7 @@ def main():
     roofline = {"bound": "alu", "achieved": round(achieved, 4), "peak": FP32_VECTOR_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 6),
                 "traffic": traffic_from_profiles("qeqea_fused_n4", src),
-                "kernel": "population_kernel<4,0,true> (sampling + Eq. 11 fitness + segment max)",
+                "kernel": "population_kernel<4,1,true> (sampling + Eq. 11 fitness + segment max, LDS-staged)",
                 "kernel_ms": round(kern_ms, 6), "algorithmic_flops_per_launch": flops}
     log(f"dominant kernel: {kern_ms * 1e3:.2f} us/launch, {achieved:.3f} TFLOP/s algorithmic")
 

@@ -54,8 +54,10 @@ qe_status device_error_word(uint32_t** out) {
 }
 
 // Per-width schedule of the FP32 path (1 = LDS-staged kernel).  Defaults from
-// the MI355X tuning sweep; QE_SCHEDULE="n:lds,..." overrides.
-int g_sched[MAX_QUBITS + 1] = {0, 0, 0, 0, 0, 1, 1};
+// MI355X measurements (qe_eval_fitness, n=4: 14.2 us LDS vs 19.8 us register
+// for 4096 x 30 gates; n=5: 422 vs 698 us for 65536 x 40; n=6: 268 vs 667 us
+// for 8192 x 48); QE_SCHEDULE="n:lds,..." overrides.
+int g_sched[MAX_QUBITS + 1] = {0, 0, 0, 0, 1, 1, 1};
 std::once_flag g_sched_once;
 
 void load_schedule_env() {
@@ -184,7 +186,7 @@ qe_status check_ctx(qe_ctx* c, bool need_targets) {
 // when graph-captured).
 qe_status enqueue_generation(qe_ctx* c, const LoopArgs& a, uint64_t gen, float* f, hipStream_t s) {
     if (c->prob.algorithm == QE_ALG_QEQEA) {
-        QE_HIP(launch_qeqea_fused(a, gen, c->slots, c->gates, f, s));
+        QE_HIP(launch_qeqea_fused(a, gen, c->slots, c->gates, f, true, s));
         QE_HIP(launch_qeqea_update(a, gen, c->slots, c->gates, f, s));
     } else {
         QE_HIP(launch_ga_copy(a, gen, c->gates, s));
@@ -339,6 +341,11 @@ qe_status qe_create(const qe_problem* p, qe_ctx** out) {
     a.target64 = t64;
     ALLOC(a.inst_best_f, I);
     ALLOC(a.inst_key, I);
+    if (p->algorithm == QE_ALG_QEQEA) {
+        ALLOC(a.mutflag, I * P);
+        ALLOC(a.mutlist, I * P);
+    }
+    ALLOC(a.mutcnt, I);
     ALLOC(a.inst_best_gates, I * L);
     ALLOC(c->slots, I * P * L);
     ALLOC(c->gates, I * P * L);
@@ -423,6 +430,7 @@ qe_status qe_update(qe_ctx* c, uint64_t gen, const uint32_t* slots, const uint16
     if (c->prob.algorithm == QE_ALG_QEQEA) {
         if (!slots) return fail(QE_ERR_INVALID, "slots is NULL");
         QE_HIP(launch_scatter(c->la, gen, slots, f, s));
+        QE_HIP(launch_mutation_decisions(c->la, gen, s));
         QE_HIP(launch_qeqea_update(c->la, gen, slots, gates, f, s));
     } else {
         QE_HIP(launch_ga_update(c->la, gen, f, s));
@@ -440,7 +448,7 @@ qe_status qe_sample_eval(qe_ctx* c, uint64_t gen, uint32_t* slots, uint16_t* gat
     QE_TRY(check_ctx(c, true));
     if (c->prob.algorithm != QE_ALG_QEQEA) return fail(QE_ERR_UNSUPPORTED, "qe_sample_eval is QEQEA only");
     if (!slots || !gates || !f) return fail(QE_ERR_INVALID, "NULL buffer");
-    QE_HIP(launch_qeqea_fused(c->la, gen, slots, gates, f, (hipStream_t)stream));
+    QE_HIP(launch_qeqea_fused(c->la, gen, slots, gates, f, false, (hipStream_t)stream));
     return QE_OK;
 }
 

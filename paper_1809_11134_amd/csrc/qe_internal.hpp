@@ -49,6 +49,9 @@ struct LoopArgs {
     const float* target32;             // [I][N][N] complex64
     const double* target64;            // [I][N][N] complex128
     unsigned long long* inst_key;      // per instance: max of (f bits << 32 | ~circuit) this generation
+    uint8_t* mutflag;                  // [I*P] this generation's mutation decision: 0 none, 1 qubits, 2 qutrits
+    uint32_t* mutlist;                 // [I][P] per instance: mutated individuals, unordered
+    uint32_t* mutcnt;                  // [I] list lengths; zeroed after the update consumed them
     float* inst_best_f;                // per instance
     uint16_t* inst_best_gates;         // [I][L]
     const float* su3_tab;              // [4][4096]: cos/sin of angles, cos/sin of phases
@@ -66,7 +69,8 @@ hipError_t launch_ga_copy(const LoopArgs& a, uint64_t gen, uint16_t* gates, hipS
 hipError_t launch_eval_population(const LoopArgs& a, const uint16_t* gates, float* f,
                                   hipStream_t s);
 hipError_t launch_qeqea_fused(const LoopArgs& a, uint64_t gen, uint32_t* slots, uint16_t* gates,
-                              float* f, hipStream_t s);
+                              float* f, bool decide, hipStream_t s);
+hipError_t launch_mutation_decisions(const LoopArgs& a, uint64_t gen, hipStream_t s);
 hipError_t launch_scatter(const LoopArgs& a, uint64_t gen, const uint32_t* slots, const float* f,
                           hipStream_t s);
 hipError_t launch_qeqea_update(const LoopArgs& a, uint64_t gen, const uint32_t* slots,

@@ -7,6 +7,8 @@
 // rounding per operation so that it is reproducible bit for bit: the library
 // is compiled with -ffp-contract=off (no multiply-add fusion anywhere) and the
 // pragma below repeats that for this file.
+#include <algorithm>
+
 #include "../../include/qe.h"
 #include "qe_eval_core.hpp"
 #include "qe_internal.hpp"
@@ -101,6 +103,7 @@ __global__ void inst_best_init_kernel(LoopArgs a) {
     if (i >= a.I) return;
     a.inst_best_f[i] = -1.0f;
     a.inst_key[i] = 0ull;
+    a.mutcnt[i] = 0;
     for (int l = 0; l < a.L; ++l) a.inst_best_gates[(size_t)i * a.L + l] = 0;
 }
 
@@ -132,13 +135,38 @@ __global__ void ga_copy_kernel(LoopArgs a, uint64_t gen64, uint16_t* __restrict_
     gates[idx] = a.genomes[gen_of(a, gen64) & 1][idx];
 }
 
+// Mutation decision of individual ind of instance i for this generation
+// (Sec. IV-F: with probability pm; qubit or qutrit mode equiprobably),
+// recorded for the update: a flag per individual and a compacted list of the
+// individuals that mutate.
+__device__ __forceinline__ void decide_mutation(const LoopArgs& a, uint32_t gen, uint32_t i,
+                                                uint32_t ind) {
+    const u32x4 w = draw(a.seed, TAG_MUT_IND, gen, i, ind);
+    const bool m = (uint64_t)w.x < a.thr_pm;
+    const uint32_t id = i * (uint32_t)a.P + ind;
+    a.mutflag[id] = m ? (uint8_t)(1 + (w.y & 1u)) : (uint8_t)0;
+    if (m) a.mutlist[(size_t)i * a.P + atomicAdd(a.mutcnt + i, 1u)] = ind;
+}
+
+// Raises the instance's generation-best key (f bits << 32 | ~circuit: the
+// maximum is the largest f, lowest index on ties).  All circuits of an
+// instance target one word, so the atomic is issued only when the current
+// value (possibly stale, which the monotone maximum tolerates) is lower.
+__device__ __forceinline__ void raise_key(unsigned long long* key, float f, uint32_t k) {
+    const unsigned long long v = ((unsigned long long)__float_as_uint(f) << 32) |
+                                 (unsigned long long)(0xFFFFFFFFu - k);
+    const unsigned long long cur = __hip_atomic_load(key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (v > cur) atomicMax(key, v);
+}
+
 // -------------------------------------------- population evaluation (FP32)
 // One circuit per wavefront (register / per-lane layouts) or per workgroup
 // (LDS layout); the target is the circuit's instance target.
 template <int NQ, int W, bool SAMPLE>
 __device__ __forceinline__ void eval_circuit(const LoopArgs& a, uint32_t gen, uint32_t ci,
                                              const uint16_t* gates_in, uint32_t* slots_out,
-                                             uint16_t* gates_out, float* f_out, bool writer) {
+                                             uint16_t* gates_out, float* f_out, bool writer,
+                                             bool decide) {
     const uint32_t i = ci / (uint32_t)a.P, k = ci % (uint32_t)a.P;
     const int lane = (int)lane_id();
     const int L = a.L;
@@ -216,10 +244,11 @@ __device__ __forceinline__ void eval_circuit(const LoopArgs& a, uint32_t gen, ui
             const uint32_t s = sample_slot(a, gen, i, k, (uint32_t)p);
             atomicMax(a.segfit + (size_t)i * a.S + s, fb);
         }
-        if (lane == 0)
-            atomicMax(a.inst_key + i, ((unsigned long long)__float_as_uint(fv) << 32) |
-                                          (unsigned long long)(0xFFFFFFFFu - k));
+        if (lane == 0) raise_key(a.inst_key + i, fv, k);
     }
+    // circuit k of the instance also draws the mutation decision of
+    // individual k (both run over 0..P-1)
+    if (SAMPLE && decide && writer && lane == 0) decide_mutation(a, gen, i, k);
 }
 
 template <int NQ, int W, bool SAMPLE>
@@ -227,18 +256,18 @@ __global__ __launch_bounds__(256) void population_kernel(LoopArgs a, uint64_t ge
                                                          const uint16_t* __restrict__ gates_in,
                                                          uint32_t* __restrict__ slots_out,
                                                          uint16_t* __restrict__ gates_out,
-                                                         float* __restrict__ f_out) {
+                                                         float* __restrict__ f_out, bool decide) {
     const uint32_t gen = gen_of(a, gen64);
     const uint32_t total = (uint32_t)a.I * (uint32_t)a.P;
     if constexpr (W == 0) {
         const uint32_t ci = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
         if (ci >= total) return;
-        eval_circuit<NQ, 0, SAMPLE>(a, gen, ci, gates_in, slots_out, gates_out, f_out, true);
+        eval_circuit<NQ, 0, SAMPLE>(a, gen, ci, gates_in, slots_out, gates_out, f_out, true, decide);
     } else {
         const uint32_t ci = blockIdx.x;
         if (ci >= total) return;
         eval_circuit<NQ, W, SAMPLE>(a, gen, ci, gates_in, slots_out, gates_out, f_out,
-                                    threadIdx.x < 64);
+                                    threadIdx.x < 64, decide);
     }
 }
 
@@ -254,9 +283,15 @@ __global__ void scatter_kernel(LoopArgs a, const uint32_t* __restrict__ slots,
     if (!(fv >= 0.0f) || s >= a.S) return;
     atomicMax(a.segfit + (size_t)i * a.S + s, (int32_t)__float_as_uint(fv));
     const uint32_t k = (uint32_t)((idx / a.L) % a.P);
-    if (idx % a.L == 0)
-        atomicMax(a.inst_key + i, ((unsigned long long)__float_as_uint(fv) << 32) |
-                                      (unsigned long long)(0xFFFFFFFFu - k));
+    if (idx % a.L == 0) raise_key(a.inst_key + i, fv, k);
+}
+
+// Mutation decisions for the step-by-step path (qe_update): one thread per
+// individual.
+__global__ void mutation_decision_kernel(LoopArgs a, uint64_t gen64) {
+    const uint32_t id = blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= (uint32_t)a.I * (uint32_t)a.P) return;
+    decide_mutation(a, gen_of(a, gen64), id / (uint32_t)a.P, id % (uint32_t)a.P);
 }
 
 // ------------------------------------------------------------------- update
@@ -335,66 +370,90 @@ __device__ __forceinline__ void mutate_slot(const LoopArgs& a, uint32_t gen, uin
 // Part A: used slots of individuals that do not mutate (one thread per
 // (circuit, position) entry; several entries may name the same slot, so
 // atomicExch claims each slot exactly once and resets its segment fitness).
-// Part B: individuals that mutate (one workgroup each, owning all the
-// individual's slots, so plain loads suffice): every slot passes elitism if
-// it was used, then mutates (qubit mode: every slot; qutrit mode: rotation
-// slots).  Part C: the instance's best circuit of the generation (packed
-// key set by the fitness kernel) updates its best circuit ever.
+// Part B: slots of the individuals that mutate (from the compacted list; one
+// thread per slot, since the individual's slots belong to nobody else): the
+// slot passes elitism if it was used, then mutates (qubit mode: every slot;
+// qutrit mode: rotation slots).  Part C: the instance's best circuit of the
+// generation (packed key set by the fitness kernel) updates its best
+// circuit ever.  The last workgroup to finish resets the list.
 constexpr int UPD_BLOCK = 256;
+
+__device__ __forceinline__ void update_part_a(const LoopArgs& a, uint32_t idx,
+                                              const uint32_t* __restrict__ slots) {
+    const uint32_t L = (uint32_t)a.L, LP = L * (uint32_t)a.P;
+    if (idx >= (uint32_t)a.I * LP) return;
+    const uint32_t i = idx / LP;
+    const uint32_t s = slots[idx];
+    if (s >= a.S) return;
+    const uint32_t ind = (s % LP) / L;
+    if (a.mutflag[i * (uint32_t)a.P + ind]) return;
+    const int32_t v = atomicExch(a.segfit + (size_t)i * a.S + s, -1);
+    if (v >= 0) elitism(a, i, s, __int_as_float(v));
+}
+
+// Workgroup b of part B serves instance b / per_inst and walks that
+// instance's (mutated individual, slot chunk) items with stride per_inst.
+__device__ __forceinline__ void update_part_b(const LoopArgs& a, uint32_t gen, uint32_t b,
+                                              uint32_t per_inst) {
+    const uint32_t L = (uint32_t)a.L, P = (uint32_t)a.P, LP = L * P;
+    const uint32_t per = (uint32_t)(a.n * a.n) * L;           // slots of one individual
+    const uint32_t chunks = (per + UPD_BLOCK - 1) / UPD_BLOCK;
+    const uint32_t i = b / per_inst;
+    if (i >= (uint32_t)a.I) return;
+    const uint32_t count = a.mutcnt[i];
+    for (uint32_t t = b % per_inst; t < count * chunks; t += per_inst) {
+        const uint32_t ind = a.mutlist[(size_t)i * P + t / chunks];
+        const uint32_t e = (t % chunks) * UPD_BLOCK + threadIdx.x;
+        if (e >= per) continue;
+        const bool qm = a.mutflag[i * P + ind] == 2;
+        const uint32_t r = e / L, pos = e - r * L;
+        const uint32_t s = r * LP + ind * L + pos;
+        int32_t* sf = a.segfit + (size_t)i * a.S + s;
+        const int32_t v = *sf;
+        if (v >= 0) {
+            *sf = -1;
+            elitism(a, i, s, __int_as_float(v));
+        }
+        if (!qm || r < (uint32_t)a.n) mutate_slot(a, gen, i, s, qm);
+    }
+}
+
+__device__ __forceinline__ void update_part_c(const LoopArgs& a, uint32_t i,
+                                              const uint16_t* __restrict__ gates) {
+    if (i >= (uint32_t)a.I) return;
+    const uint32_t L = (uint32_t)a.L, P = (uint32_t)a.P;
+    const int lane = (int)lane_id();
+    unsigned long long key = 0;
+    if (lane == 0) key = atomicExch(a.inst_key + i, 0ull);
+    key = __shfl(key, 0, 64);
+    if (key == 0) return;
+    const float best = __uint_as_float((uint32_t)(key >> 32));
+    const uint32_t k = 0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFu);
+    if (best > a.inst_best_f[i]) {
+        const uint16_t* src = gates + ((size_t)i * P + k) * L;
+        for (uint32_t l = lane; l < L; l += 64) a.inst_best_gates[(size_t)i * L + l] = src[l];
+        if (lane == 0) a.inst_best_f[i] = best;
+    }
+}
 
 __global__ __launch_bounds__(UPD_BLOCK) void qeqea_update_kernel(LoopArgs a, uint64_t gen64,
                                                                  const uint32_t* __restrict__ slots,
                                                                  const uint16_t* __restrict__ gates,
-                                                                 uint32_t nA, uint32_t nB) {
+                                                                 uint32_t nA, uint32_t nB,
+                                                                 uint32_t per_inst) {
     const uint32_t gen = gen_of(a, gen64);
-    const uint32_t L = (uint32_t)a.L, P = (uint32_t)a.P;
-    const uint32_t LP = L * P;
-    if (blockIdx.x < nA) {
-        const uint32_t idx = blockIdx.x * UPD_BLOCK + threadIdx.x;
-        const uint32_t per = LP;
-        if (idx >= (uint32_t)a.I * per) return;
-        const uint32_t i = idx / per;
-        const uint32_t s = slots[idx];
-        if (s >= a.S) return;
-        const uint32_t ind = (s % LP) / L;
-        bool qm;
-        if (mutated(a, gen, i, ind, &qm)) return;
-        const int32_t v = atomicExch(a.segfit + (size_t)i * a.S + s, -1);
-        if (v >= 0) elitism(a, i, s, __int_as_float(v));
-    } else if (blockIdx.x < nA + nB) {
-        const uint32_t id = blockIdx.x - nA;
-        const uint32_t i = id / P, ind = id % P;
-        bool qm;
-        if (!mutated(a, gen, i, ind, &qm)) return;
-        const uint32_t regions = (uint32_t)(a.n * a.n);
-        const uint32_t rot = (uint32_t)a.n;
-        for (uint32_t e = threadIdx.x; e < regions * L; e += UPD_BLOCK) {
-            const uint32_t r = e / L, pos = e - r * L;
-            const uint32_t s = r * LP + ind * L + pos;
-            int32_t* sf = a.segfit + (size_t)i * a.S + s;
-            const int32_t v = *sf;
-            if (v >= 0) {
-                *sf = -1;
-                elitism(a, i, s, __int_as_float(v));
-            }
-            if (!qm || r < rot) mutate_slot(a, gen, i, s, qm);
-        }
-    } else {
-        const uint32_t i = (blockIdx.x - nA - nB) * (UPD_BLOCK / 64) + (threadIdx.x >> 6);
-        if (i >= (uint32_t)a.I) return;
-        const int lane = (int)lane_id();
-        unsigned long long key = 0;
-        if (lane == 0) key = atomicExch(a.inst_key + i, 0ull);
-        key = __shfl(key, 0, 64);
-        if (key == 0) return;
-        const float best = __uint_as_float((uint32_t)(key >> 32));
-        const uint32_t k = 0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFu);
-        if (best > a.inst_best_f[i]) {
-            const uint16_t* src = gates + ((size_t)i * P + k) * L;
-            for (uint32_t l = lane; l < L; l += 64) a.inst_best_gates[(size_t)i * L + l] = src[l];
-            if (lane == 0) a.inst_best_f[i] = best;
-        }
-    }
+    if (blockIdx.x < nA)
+        update_part_a(a, blockIdx.x * UPD_BLOCK + threadIdx.x, slots);
+    else if (blockIdx.x < nA + nB)
+        update_part_b(a, gen, blockIdx.x - nA, per_inst);
+    else
+        update_part_c(a, (blockIdx.x - nA - nB) * (UPD_BLOCK / 64) + (threadIdx.x >> 6), gates);
+}
+
+// The mutation lists were consumed: empty them for the next generation.
+__global__ void mutlist_reset_kernel(LoopArgs a) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < (uint32_t)a.I) a.mutcnt[i] = 0;
 }
 
 // ----------------------------------------------------------------------- GA
@@ -593,25 +652,25 @@ hipError_t launch_ga_copy(const LoopArgs& a, uint64_t gen, uint16_t* gates, hipS
 
 template <bool SAMPLE>
 static void launch_population(const LoopArgs& a, uint64_t gen, const uint16_t* gin, uint32_t* sout,
-                              uint16_t* gout, float* f, hipStream_t s) {
+                              uint16_t* gout, float* f, hipStream_t s, bool decide = false) {
     const uint32_t total = (uint32_t)a.I * (uint32_t)a.P;
     const bool lds = schedule_lds(a.n);
     const unsigned wb = blocks(total, 4);
     if (lds && a.n >= 4) {
         switch (a.n) {
-            case 4: population_kernel<4, 1, SAMPLE><<<total, 64, 0, s>>>(a, gen, gin, sout, gout, f); break;
-            case 5: population_kernel<5, 2, SAMPLE><<<total, 128, 0, s>>>(a, gen, gin, sout, gout, f); break;
-            default: population_kernel<6, 4, SAMPLE><<<total, 256, 0, s>>>(a, gen, gin, sout, gout, f); break;
+            case 4: population_kernel<4, 1, SAMPLE><<<total, 64, 0, s>>>(a, gen, gin, sout, gout, f, decide); break;
+            case 5: population_kernel<5, 2, SAMPLE><<<total, 128, 0, s>>>(a, gen, gin, sout, gout, f, decide); break;
+            default: population_kernel<6, 4, SAMPLE><<<total, 256, 0, s>>>(a, gen, gin, sout, gout, f, decide); break;
         }
         return;
     }
     switch (a.n) {
-        case 1: population_kernel<1, 0, SAMPLE><<<wb, 256, 0, s>>>(a, gen, gin, sout, gout, f); break;
-        case 2: population_kernel<2, 0, SAMPLE><<<wb, 256, 0, s>>>(a, gen, gin, sout, gout, f); break;
-        case 3: population_kernel<3, 0, SAMPLE><<<wb, 256, 0, s>>>(a, gen, gin, sout, gout, f); break;
-        case 4: population_kernel<4, 0, SAMPLE><<<wb, 256, 0, s>>>(a, gen, gin, sout, gout, f); break;
-        case 5: population_kernel<5, 0, SAMPLE><<<wb, 256, 0, s>>>(a, gen, gin, sout, gout, f); break;
-        default: population_kernel<6, 0, SAMPLE><<<wb, 256, 0, s>>>(a, gen, gin, sout, gout, f); break;
+        case 1: population_kernel<1, 0, SAMPLE><<<wb, 256, 0, s>>>(a, gen, gin, sout, gout, f, decide); break;
+        case 2: population_kernel<2, 0, SAMPLE><<<wb, 256, 0, s>>>(a, gen, gin, sout, gout, f, decide); break;
+        case 3: population_kernel<3, 0, SAMPLE><<<wb, 256, 0, s>>>(a, gen, gin, sout, gout, f, decide); break;
+        case 4: population_kernel<4, 0, SAMPLE><<<wb, 256, 0, s>>>(a, gen, gin, sout, gout, f, decide); break;
+        case 5: population_kernel<5, 0, SAMPLE><<<wb, 256, 0, s>>>(a, gen, gin, sout, gout, f, decide); break;
+        default: population_kernel<6, 0, SAMPLE><<<wb, 256, 0, s>>>(a, gen, gin, sout, gout, f, decide); break;
     }
 }
 
@@ -631,8 +690,13 @@ hipError_t launch_ga_eval(const LoopArgs& a, uint64_t gen, float* f, hipStream_t
 }
 
 hipError_t launch_qeqea_fused(const LoopArgs& a, uint64_t gen, uint32_t* slots, uint16_t* gates,
-                              float* f, hipStream_t s) {
-    launch_population<true>(a, gen, nullptr, slots, gates, f, s);
+                              float* f, bool decide, hipStream_t s) {
+    launch_population<true>(a, gen, nullptr, slots, gates, f, s, decide);
+    return hipGetLastError();
+}
+
+hipError_t launch_mutation_decisions(const LoopArgs& a, uint64_t gen, hipStream_t s) {
+    mutation_decision_kernel<<<blocks((size_t)a.I * a.P, 256), 256, 0, s>>>(a, gen);
     return hipGetLastError();
 }
 
@@ -647,9 +711,16 @@ hipError_t launch_qeqea_update(const LoopArgs& a, uint64_t gen, const uint32_t* 
                                const uint16_t* gates, const float* f, hipStream_t s) {
     (void)f;   // the fitness reached the update through segfit and inst_key
     const uint32_t nA = blocks((size_t)a.I * a.P * a.L, UPD_BLOCK);
-    const uint32_t nB = (uint32_t)a.I * (uint32_t)a.P;
+    // part B: per instance, enough workgroups for the expected number of
+    // (mutated individual, slot chunk) items (more items loop)
+    const size_t chunks = ((size_t)a.n * a.n * a.L + UPD_BLOCK - 1) / UPD_BLOCK;
+    const double expect = (double)a.thr_pm / 4294967296.0 * a.P * chunks;
+    const uint32_t per_inst = (uint32_t)std::max<double>(
+        1.0, std::min<double>(1.5 * expect + 8.0, (double)a.P * chunks));
+    const uint32_t nB = per_inst * (uint32_t)a.I;
     const uint32_t nC = blocks((size_t)a.I, UPD_BLOCK / 64);
-    qeqea_update_kernel<<<nA + nB + nC, UPD_BLOCK, 0, s>>>(a, gen, slots, gates, nA, nB);
+    qeqea_update_kernel<<<nA + nB + nC, UPD_BLOCK, 0, s>>>(a, gen, slots, gates, nA, nB, per_inst);
+    mutlist_reset_kernel<<<blocks((size_t)a.I, 256), 256, 0, s>>>(a);
     return hipGetLastError();
 }
 
