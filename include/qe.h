@@ -64,8 +64,11 @@ enum { QE_ALG_QEQEA = 0, QE_ALG_GA = 1 };
 enum { QE_PATH_FP32 = 0,        /* per-gate row updates, FP32, tuned schedule per width */
        QE_PATH_FP32_REG = 1,    /* forced: matrix held in registers, one wave per circuit */
        QE_PATH_FP32_LDS = 2,    /* forced: matrix staged in LDS, columns split over waves */
-       QE_PATH_MFMA_BF16 = 3,   /* fused gate blocks on MFMA, bf16 hi+lo (n >= 5) */
-       QE_PATH_MFMA_FP16 = 4 }; /* fused gate blocks on MFMA, fp16 hi+lo (n >= 5) */
+       QE_PATH_MFMA_BF16 = 3,   /* fused 4-wire gate blocks on MFMA, bf16 hi+lo, FP32
+                                   accumulation, columns renormalised after each block */
+       QE_PATH_MFMA_FP16 = 4,   /* same with fp16 hi+lo (lo scaled by 2^11) */
+       QE_PATH_MFMA_BF16_RAW = 5,  /* bf16 hi+lo without renormalisation */
+       QE_PATH_MFMA_FP16_RAW = 6 }; /* fp16 hi+lo without renormalisation */
 
 /* Device error flags (bitmask) raised by kernels. */
 enum { QE_DEVERR_DESC = 1,      /* invalid gate descriptor */
@@ -105,8 +108,9 @@ typedef struct {
 
 /* Fitness of every circuit of the batch against its target, Eq. 11 of
  * Sec. IV-E (the hot path).  path: QE_PATH_*.  f_dev [B] required; g_dev,
- * delta_dev [B] optional (NULL).  One wavefront per circuit; the 2^n x 2^n
- * product U T^dagger is built gate by gate from T^dagger.  Circuits whose
+ * delta_dev [B] optional (NULL).  The 2^n x 2^n product U T^dagger is built
+ * gate by gate from T^dagger (FP32 paths) or block by block (MFMA paths:
+ * uniform width 5 or 6 only, QE_ERR_UNSUPPORTED otherwise).  Circuits whose
  * width, gates or target are malformed get f = NaN (see qe_device_errors).
  * ctx may be NULL. */
 typedef struct qe_ctx qe_ctx;

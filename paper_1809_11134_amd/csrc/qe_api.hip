@@ -235,9 +235,16 @@ qe_status qe_eval_fitness(qe_ctx* ctx, const qe_batch* batch, int32_t path, floa
     (void)ctx;
     BatchArgs a;
     QE_TRY(to_args(batch, &a, true));
-    if (path < QE_PATH_FP32 || path > QE_PATH_MFMA_FP16) return fail(QE_ERR_INVALID, "unknown path");
-    if (path >= QE_PATH_MFMA_BF16) return fail(QE_ERR_UNSUPPORTED, "MFMA paths are not built");
+    if (path < QE_PATH_FP32 || path > QE_PATH_MFMA_FP16_RAW) return fail(QE_ERR_INVALID, "unknown path");
     if (a.B > 0 && !f_dev) return fail(QE_ERR_INVALID, "f_dev is NULL");
+    if (path >= QE_PATH_MFMA_BF16) {
+        if (a.uniform_n != 5 && a.uniform_n != 6)
+            return fail(QE_ERR_UNSUPPORTED, "MFMA paths need a uniform width of 5 or 6");
+        const bool fp16 = path == QE_PATH_MFMA_FP16 || path == QE_PATH_MFMA_FP16_RAW;
+        const bool renorm = path == QE_PATH_MFMA_BF16 || path == QE_PATH_MFMA_FP16;
+        QE_HIP(launch_eval_mfma(a, fp16, renorm, f_dev, g_dev, delta_dev, (hipStream_t)stream));
+        return QE_OK;
+    }
     QE_HIP(launch_eval_fp32(a, path, f_dev, g_dev, delta_dev, (hipStream_t)stream));
     return QE_OK;
 }

@@ -7,39 +7,8 @@ namespace qe {
 
 constexpr int WPB = 4;   // wavefronts (circuits) per workgroup
 
-struct Item {
-    int n, L;
-    const uint16_t* g;
-    int64_t toff;
-    uint32_t err;
-};
-
-// Resolves circuit b of a batch (wave-uniform) and checks it against the
-// buffer bounds; err != 0 means the circuit must not be evaluated.
 __device__ __forceinline__ Item resolve(const BatchArgs& a, int b, bool need_target = true) {
-    Item it;
-    it.err = 0;
-    it.n = a.uniform_n > 0 ? a.uniform_n : (int)a.nq[b];
-    it.L = 0;
-    it.g = a.gates;
-    it.toff = 0;
-    if (it.n < 1 || it.n > MAX_QUBITS) { it.err = QE_DEVERR_WIDTH; return it; }
-    int64_t start, end;
-    if (a.uniform_L > 0) {
-        start = (int64_t)b * a.uniform_L;
-        end = start + a.uniform_L;
-    } else {
-        start = a.goff[b];
-        end = a.goff[b + 1];
-    }
-    if (start < 0 || end < start || end > a.num_gates) { it.err = QE_DEVERR_RANGE; return it; }
-    it.L = (int)(end - start);
-    it.g = a.gates + start;
-    if (!need_target) return it;
-    const int64_t NN = (int64_t)1 << (2 * it.n);
-    it.toff = a.tstride >= 0 ? (int64_t)b * a.tstride : a.toff[b];
-    if (it.toff < 0 || it.toff + NN > a.num_telems) { it.err = QE_DEVERR_RANGE; return it; }
-    return it;
+    return resolve_item(a, b, need_target);
 }
 
 // ------------------------------------------------------- FP32, one wave each

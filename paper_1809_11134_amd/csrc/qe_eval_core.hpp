@@ -18,9 +18,47 @@
 // predicate.  Every gate body is then one of a handful of fully unrolled
 // register loops, and no shuffle or LDS traffic is needed for the arithmetic.
 #pragma once
+#include "../../include/qe.h"
 #include "qe_device.hpp"
+#include "qe_internal.hpp"
 
 namespace qe {
+
+// ------------------------------------------------------------ batch items
+struct Item {
+    int n, L;
+    const uint16_t* g;
+    int64_t toff;
+    uint32_t err;
+};
+
+// Resolves circuit b of a batch (wave-uniform) and checks it against the
+// buffer bounds; err != 0 means the circuit must not be evaluated.
+__device__ __forceinline__ Item resolve_item(const BatchArgs& a, int b, bool need_target) {
+    Item it;
+    it.err = 0;
+    it.n = a.uniform_n > 0 ? a.uniform_n : (int)a.nq[b];
+    it.L = 0;
+    it.g = a.gates;
+    it.toff = 0;
+    if (it.n < 1 || it.n > MAX_QUBITS) { it.err = QE_DEVERR_WIDTH; return it; }
+    int64_t start, end;
+    if (a.uniform_L > 0) {
+        start = (int64_t)b * a.uniform_L;
+        end = start + a.uniform_L;
+    } else {
+        start = a.goff[b];
+        end = a.goff[b + 1];
+    }
+    if (start < 0 || end < start || end > a.num_gates) { it.err = QE_DEVERR_RANGE; return it; }
+    it.L = (int)(end - start);
+    it.g = a.gates + start;
+    if (!need_target) return it;
+    const int64_t NN = (int64_t)1 << (2 * it.n);
+    it.toff = a.tstride >= 0 ? (int64_t)b * a.tstride : a.toff[b];
+    if (it.toff < 0 || it.toff + NN > a.num_telems) { it.err = QE_DEVERR_RANGE; return it; }
+    return it;
+}
 
 __device__ __forceinline__ float bits_f(uint32_t u) { return __uint_as_float(u); }
 __device__ __forceinline__ uint32_t f_bits(float f) { return __float_as_uint(f); }

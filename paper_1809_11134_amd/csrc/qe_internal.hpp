@@ -31,6 +31,10 @@ hipError_t launch_eval_lds(const BatchArgs& a, bool fp64, void* f, void* g, void
                            hipStream_t s);
 hipError_t launch_unitary(const BatchArgs& a, bool fp64, void* out, hipStream_t s);
 
+// mfma.hip: fused 4-wire gate blocks on MFMA (uniform width 5 or 6)
+hipError_t launch_eval_mfma(const BatchArgs& a, bool fp16, bool renorm, float* f, float* g,
+                            float* delta, hipStream_t s);
+
 // Encoding-state arguments of the QEQEA / GA loop kernels.
 struct LoopArgs {
     int32_t n, lib, L, P, I;

@@ -15,7 +15,8 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "qe.h")
 QE_OK, QE_ERR_INVALID, QE_ERR_UNSUPPORTED, QE_ERR_DEVICE, QE_ERR_OOM, QE_ERR_NUMERIC, QE_ERR_STATE = range(7)
 LIB_NCV, LIB_HT_NCV = 0, 1
 ALG_QEQEA, ALG_GA = 0, 1
-PATH_FP32, PATH_FP32_REG, PATH_FP32_LDS, PATH_MFMA_BF16, PATH_MFMA_FP16 = range(5)
+(PATH_FP32, PATH_FP32_REG, PATH_FP32_LDS, PATH_MFMA_BF16, PATH_MFMA_FP16, PATH_MFMA_BF16_RAW,
+ PATH_MFMA_FP16_RAW) = range(7)
 DEVERR_DESC, DEVERR_WIDTH, DEVERR_RANGE, DEVERR_NUMERIC = 1, 2, 4, 8
 
 

@@ -1,0 +1,74 @@
+"""The MFMA path (fused 4-wire gate blocks, bf16/fp16 hi+lo, FP32
+accumulation) against the CPU oracle.  Its error is stated rather than
+bounded by the FP32 tolerance; the tests check it stays within loose bounds
+and that the fp16 variant is the more accurate one."""
+import numpy as np
+import pytest
+import torch
+
+from paper_1809_11134_amd import inputs, qe
+
+pytestmark = pytest.mark.gpu
+MFMA_PATHS = [qe.PATH_MFMA_BF16, qe.PATH_MFMA_FP16, qe.PATH_MFMA_BF16_RAW, qe.PATH_MFMA_FP16_RAW]
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    qe.load()
+    return torch.device("cuda", 0)
+
+
+def run(oracle, dev, n, gates, T, path):
+    B, L = gates.shape
+    f, g, _ = qe.eval_fitness(torch.from_numpy(gates.astype(np.int16)).to(dev),
+                              torch.from_numpy(T).to(dev), n=n, L=L, target_stride=0, path=path,
+                              want_g=True)
+    ref = oracle.eval_batch(np.full(B, n, np.int8), np.arange(B + 1, dtype=np.int32) * L,
+                            gates.ravel(), np.zeros(B, np.int64), T)
+    return f.cpu().numpy().astype(np.float64), g.cpu().numpy().astype(np.float64), ref
+
+
+@pytest.mark.parametrize("n", [5, 6])
+@pytest.mark.parametrize("L", [1, 7, 48, 70])
+def test_mfma_close_to_oracle(dev, oracle, n, L):
+    rng = np.random.default_rng(40 + n + L)
+    B = 40
+    tg = inputs.random_target_gates(rng, n, 24, 1)
+    gates = np.concatenate([inputs.random_circuits(rng, B // 2, n, L, 1),
+                            inputs.planted_population(rng, tg, B // 2, n, L, 1, max_edits=3)])
+    T = oracle.unitary(n, tg)
+    print(f"n={n} L={L}", flush=True)
+    errs = {}
+    for path in MFMA_PATHS:
+        f, g, ref = run(oracle, dev, n, gates, T, path)
+        errs[path] = (np.abs(f - ref[:, 0]).max(), np.abs(g - ref[:, 1]).max())
+        assert np.all(np.isfinite(f))
+        assert errs[path][1] <= 2e-3, (path, errs[path])
+        assert errs[path][0] <= 2e-2, (path, errs[path])
+    assert errs[qe.PATH_MFMA_FP16][1] <= errs[qe.PATH_MFMA_BF16][1] + 1e-6
+    assert qe.device_errors() == 0
+
+
+def test_mfma_single_block_exact_permutations(dev, oracle):
+    # NOT/CNOT circuits on the first 4 wires are permutation blocks: every
+    # hi+lo product is exact, so the MFMA result matches the oracle closely
+    rng = np.random.default_rng(3)
+    n, L, B = 6, 12, 16
+    perm = np.array([d for d in inputs.permutation_gates(n)
+                     if ((d >> 4) & 15) < 4 and (((d & 15) == 1) or ((d >> 8) & 15) < 4)], np.uint16)
+    gates = perm[rng.integers(0, len(perm), (B, L))]
+    T = oracle.unitary(n, gates[0])
+    for path in MFMA_PATHS:
+        f, g, ref = run(oracle, dev, n, gates, T, path)
+        assert np.abs(f - ref[:, 0]).max() <= 1e-5
+        assert f[0] == pytest.approx(1.0, abs=1e-6)
+
+
+def test_mfma_rejects_other_widths(dev):
+    T = torch.eye(16, dtype=torch.complex64, device=dev)
+    g = torch.zeros((2, 3), dtype=torch.int16, device=dev)
+    with pytest.raises(qe.QeError) as e:
+        qe.eval_fitness(g, T, n=4, L=3, path=qe.PATH_MFMA_BF16)
+    assert e.value.status == qe.QE_ERR_UNSUPPORTED
