@@ -14,7 +14,11 @@ generation's 32 best circuits is inside the timed region.
 Prints one JSON line (the metric is circuit-fitness evaluations per second)
 with a roofline entry for the dominant kernel (the fused sampling + fitness
 kernel, timed per launch with HIP events) and the CPU oracle's rate on a
-bounded sample of the same workload.
+bounded sample of the same workload.  The "secondary" object adds the other
+workloads of the study: the n=6 precision study (FP32 against the bf16/fp16
+hi+lo MFMA paths, with their fitness error against the FP64 path, elite
+top-32 agreement and Kendall tau), 1024 QEQEA populations at n=5, and an
+uneven batch of widths 3..6 in one launch.
 """
 import argparse
 import hashlib
@@ -99,6 +103,110 @@ def cpu_baseline(w, T, seconds):
                        f"and update single-threaded), {el:.1f} s")
 
 
+def _events_us(fn, reps):
+    import torch
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(reps)]
+    fn()
+    torch.cuda.synchronize()
+    for a, b in evs:
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    t = sorted(a.elapsed_time(b) * 1e3 for a, b in evs)
+    return t[len(t) // 2]
+
+
+def secondary_precision(dev, reps=5):
+    """n=6, library {H,T,CNOT,CV,CV+}, 8192 circuits x 48 gates (3/4 planted
+    near the target): evaluations/s of each path and its fitness error against
+    the FP64 path, elite top-32 agreement (tie-aware) and Kendall tau."""
+    import numpy as np
+    import torch
+    from scipy.stats import kendalltau
+    from paper_1809_11134_amd import inputs, qe
+    w = inputs.workload_precision_n6()
+    n, L, P = w["n"], w["L"], w["P"]
+    g = torch.from_numpy(w["gates"].astype(np.int16)).to(dev)
+    tg = torch.from_numpy(w["target_gates"].astype(np.int16)[None]).to(dev)
+    T64 = qe.build_unitary(tg, n, tg.shape[1], precision=1)[0]
+    T32 = T64.to(torch.complex64)
+    f64 = qe.eval_fitness_fp64(g, T64, n=n, L=L)[0].cpu().numpy()
+    order64 = np.lexsort((np.arange(P), -f64))
+    cut = f64[order64[31]]
+    out = {"workload": w["name"], "reference": "FP64 path on the GPU", "paths": {}}
+    for name, path in (("fp32", qe.PATH_FP32), ("bf16_mfma", qe.PATH_MFMA_BF16),
+                       ("fp16_mfma", qe.PATH_MFMA_FP16), ("bf16_mfma_no_renorm", qe.PATH_MFMA_BF16_RAW),
+                       ("fp16_mfma_no_renorm", qe.PATH_MFMA_FP16_RAW)):
+        us = _events_us(lambda: qe.eval_fitness(g, T32, n=n, L=L, path=path), reps)
+        f = qe.eval_fitness(g, T32, n=n, L=L, path=path)[0].cpu().numpy().astype(np.float64)
+        err = np.abs(f - f64)
+        top = np.lexsort((np.arange(P), -f))[:32]
+        agree = int((f64[top] >= cut - 1e-6).sum())
+        out["paths"][name] = {"evals_per_s": P / (us * 1e-6), "kernel_us": us,
+                              "max_abs_df": float(err.max()), "p99_abs_df": float(np.quantile(err, 0.99)),
+                              "elite32_agreement": agree, "kendall_tau": float(kendalltau(f, f64)[0])}
+    return out
+
+
+def secondary_qeqea_n5(dev, gens=20):
+    """n=5, library {I,NOT,CNOT,CV,CV+}, 1024 QEQEA populations x 64 circuits x
+    40 gates (65536 evaluations per generation): a graph of `gens` whole
+    generations plus the FP64 re-check of each population's 32 best."""
+    import numpy as np
+    import torch
+    from paper_1809_11134_amd import inputs, qe
+    w = inputs.workload_qeqea_n5()
+    n, L, P, I = w["n"], w["L"], w["P"], w["instances"]
+    tg = torch.from_numpy(np.stack(w["target_gates"]).astype(np.int16)).to(dev)
+    T = qe.build_unitary(tg, n, tg.shape[1], precision=1)
+    ctx = qe.Context(n, w["lib"], qe.ALG_QEQEA, L, P, I, prob_mutation=0.1,
+                     mutation_range=math.pi / 4, seed=w["seed"])
+    ctx.set_targets(T)
+    hist = torch.empty((gens, I * P), dtype=torch.float32, device=dev)
+    ctx.graph_prepare(gens, hist)
+    ctx.run_graph(0, gens, hist)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    ctx.run_graph(gens, gens, hist)
+    idx, f64 = ctx.elite_recheck(None, hist[gens - 1], 32)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    f32 = hist[gens - 1].view(I, P).gather(1, idx.long()).double()
+    best = [ctx.get_best(i, with_fp64=False)[1] for i in range(4)]
+    ctx.close()
+    return {"workload": w["name"], "generations": gens, "evals_per_s": gens * I * P / (ms * 1e-3),
+            "ms_per_generation": ms / gens, "elite_fp32_vs_fp64_max_abs_df": float((f32 - f64).abs().max()),
+            "best_f_first_populations": best}
+
+
+def secondary_uneven(dev, reps=7):
+    """16384 circuits, width n ~ U{3..6} per population of 64, length
+    L ~ U[8,64] per circuit, per-population targets of library
+    {H,T,CNOT,CV,CV+}: one mixed-width launch."""
+    import numpy as np
+    import torch
+    from paper_1809_11134_amd import inputs, qe
+    w = inputs.workload_uneven()
+    nq, goff, gates = w["nq"], w["goff"], w["gates"]
+    mats, offs, off = [], [], 0
+    for n, tg in w["target_gates"]:
+        U = qe.build_unitary(torch.from_numpy(tg.astype(np.int16)[None]).to(dev), n, len(tg), precision=0)[0]
+        mats.append(U.reshape(-1))
+        offs.append(off)
+        off += U.numel()
+    flat = torch.cat(mats)
+    toff = torch.tensor(np.array(offs)[w["target_index"]], dtype=torch.int64, device=dev)
+    g = torch.from_numpy(gates.astype(np.int16)).to(dev)
+    nqd, goffd = torch.from_numpy(nq).to(dev), torch.from_numpy(goff).to(dev)
+    us = _events_us(lambda: qe.eval_fitness(g, flat, nq=nqd, goff=goffd, toff=toff, target_stride=None), reps)
+    return {"workload": w["name"], "circuits": len(nq), "evals_per_s": len(nq) / (us * 1e-6),
+            "kernel_us": us}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -107,6 +215,11 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=50)
+    ap.add_argument("--pmc-calibration-mb", type=int, default=0,
+                    help="after the run, copy a buffer of this many MiB (a plain copy kernel "
+                         "of known traffic that scales the FETCH_SIZE / WRITE_SIZE counters)")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="skip the n=6 precision study, the n=5 QEQEA loop and the uneven batch")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the hot path of this build runs on a single MI355X "
@@ -187,6 +300,24 @@ def main():
                 "kernel_ms": round(kern_ms, 6), "algorithmic_flops_per_launch": flops}
     log(f"dominant kernel: {kern_ms * 1e3:.2f} us/launch, {achieved:.3f} TFLOP/s algorithmic")
 
+    if args.pmc_calibration_mb > 0:
+        nb = args.pmc_calibration_mb << 20
+        src_buf = torch.ones(nb // 4, dtype=torch.float32, device=dev)
+        dst_buf = torch.empty_like(src_buf)
+        dst_buf.copy_(src_buf)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {args.pmc_calibration_mb} MiB read + {args.pmc_calibration_mb} MiB written")
+
+    secondary = None
+    if not args.no_secondary:
+        log("secondary: n=6 precision study (FP32 vs bf16/fp16 MFMA)")
+        secondary = {"precision_n6": secondary_precision(dev)}
+        log("secondary: n=5 QEQEA, 1024 populations")
+        secondary["qeqea_n5"] = secondary_qeqea_n5(dev)
+        log("secondary: uneven batch")
+        secondary["uneven"] = secondary_uneven(dev)
+        assert qe.device_errors() == 0, "device error flags raised"
+
     cpu = None
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle for ~{args.cpu_seconds:.0f} s")
@@ -205,6 +336,7 @@ def main():
         "fitness_error_fp32_vs_fp64": fit_err,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "secondary": secondary,
         "source_hash": src,
     }
     print(json.dumps(out), flush=True)

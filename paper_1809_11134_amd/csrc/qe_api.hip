@@ -1,5 +1,6 @@
 // libqe C ABI: argument validation, context ownership, launches, graph
 // capture of the generation loop, checkpoint / restore.
+#include <dlfcn.h>
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -53,6 +54,33 @@ qe_status device_error_word(uint32_t** out) {
     return QE_OK;
 }
 
+// Workspace for mixed-width batches, one per device, grown on demand (the
+// first call with a larger batch allocates; later calls do not).
+std::map<int, std::pair<int32_t*, size_t>> g_work;
+
+qe_status mix_workspace(int64_t B, int32_t** out) {
+    int dev = 0;
+    QE_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto& w = g_work[dev];
+    const size_t need = 32 + (size_t)B;
+    if (w.second < need) {
+        if (w.first) {
+            QE_HIP(hipDeviceSynchronize());
+            QE_HIP(hipFree(w.first));
+            w.first = nullptr;
+            w.second = 0;
+        }
+        int32_t* p = nullptr;
+        const size_t cap = need + need / 2;
+        QE_HIP(hipMalloc(&p, cap * sizeof(int32_t)));
+        w.first = p;
+        w.second = cap;
+    }
+    *out = w.first;
+    return QE_OK;
+}
+
 // Per-width schedule of the FP32 path (1 = LDS-staged kernel).  Defaults from
 // MI355X measurements (qe_eval_fitness, n=4: 14.2 us LDS vs 19.8 us register
 // for 4096 x 30 gates; n=5: 422 vs 698 us for 65536 x 40; n=6: 268 vs 667 us
@@ -60,7 +88,33 @@ qe_status device_error_word(uint32_t** out) {
 int g_sched[MAX_QUBITS + 1] = {0, 0, 0, 0, 1, 1, 1};
 std::once_flag g_sched_once;
 
+// Tuning table written by paper_1809_11134_amd/tune.py: lines "n lds" (comments
+// after '#').  Path: $QE_TUNE_TABLE, else tune_mi355x.txt next to libqe.so.
+void load_tune_table() {
+    std::string path;
+    if (const char* e = std::getenv("QE_TUNE_TABLE")) {
+        path = e;
+    } else {
+        Dl_info info;
+        if (dladdr((void*)&load_tune_table, &info) && info.dli_fname) {
+            std::string so(info.dli_fname);
+            const size_t slash = so.rfind('/');
+            path = (slash == std::string::npos ? std::string(".") : so.substr(0, slash)) + "/tune_mi355x.txt";
+        }
+    }
+    FILE* fh = path.empty() ? nullptr : std::fopen(path.c_str(), "r");
+    if (!fh) return;
+    char line[256];
+    while (std::fgets(line, sizeof line, fh)) {
+        int n = 0, l = 0;
+        if (line[0] == '#') continue;
+        if (std::sscanf(line, "%d %d", &n, &l) == 2 && n >= 1 && n <= MAX_QUBITS) g_sched[n] = l ? 1 : 0;
+    }
+    std::fclose(fh);
+}
+
 void load_schedule_env() {
+    load_tune_table();
     const char* s = std::getenv("QE_SCHEDULE");
     if (!s) return;
     std::string str(s);
@@ -245,7 +299,9 @@ qe_status qe_eval_fitness(qe_ctx* ctx, const qe_batch* batch, int32_t path, floa
         QE_HIP(launch_eval_mfma(a, fp16, renorm, f_dev, g_dev, delta_dev, (hipStream_t)stream));
         return QE_OK;
     }
-    QE_HIP(launch_eval_fp32(a, path, f_dev, g_dev, delta_dev, (hipStream_t)stream));
+    int32_t* work = nullptr;
+    if (a.uniform_n == 0 && path == QE_PATH_FP32 && a.B > 0) QE_TRY(mix_workspace(a.B, &work));
+    QE_HIP(launch_eval_fp32(a, path, f_dev, g_dev, delta_dev, work, (hipStream_t)stream));
     return QE_OK;
 }
 

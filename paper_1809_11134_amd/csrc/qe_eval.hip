@@ -130,6 +130,140 @@ __global__ __launch_bounds__(64 * W) void lds32_kernel(BatchArgs a, float* __res
     }
 }
 
+// ----------------------------------------------- mixed widths, one launch
+// Circuits of a mixed-width batch are ordered by width, widest first, by a
+// one-workgroup counting sort; one launch then gives every workgroup (4
+// wavefronts) one work item: a circuit of width 6 (4 waves), two of width 5
+// (2 waves each), or four of width <= 4 (one wave each; LDS-staged for 4,
+// one entry per lane below).  Workgroups are dispatched in index order, so
+// the heaviest items start first (longest-processing-time order).
+constexpr int MIX_BUCKETS = 7;          // widths 6..1, then malformed widths
+
+__device__ __forceinline__ int mix_bucket(int n) { return (n >= 1 && n <= MAX_QUBITS) ? 6 - n : 6; }
+__device__ __forceinline__ int mix_per_item(int k) { return k == 0 ? 1 : (k == 1 ? 2 : 4); }
+
+// meta: [0..7) first order position, [8..15) first item (8 entries, the last
+// the total), [16..23) count per bucket.
+__global__ __launch_bounds__(1024) void mix_bucket_kernel(BatchArgs a, int32_t* order, int32_t* meta) {
+    __shared__ int cnt[MIX_BUCKETS], cursor[MIX_BUCKETS];
+    const int tid = threadIdx.x;
+    if (tid < MIX_BUCKETS) cnt[tid] = 0;
+    __syncthreads();
+    for (int b = tid; b < a.B; b += blockDim.x) atomicAdd(&cnt[mix_bucket(a.nq[b])], 1);
+    __syncthreads();
+    if (tid == 0) {
+        int pos = 0, item = 0;
+        for (int k = 0; k < MIX_BUCKETS; ++k) {
+            meta[k] = pos;
+            meta[8 + k] = item;
+            meta[16 + k] = cnt[k];
+            cursor[k] = pos;
+            pos += cnt[k];
+            item += (cnt[k] + mix_per_item(k) - 1) / mix_per_item(k);
+        }
+        meta[8 + MIX_BUCKETS] = item;
+    }
+    __syncthreads();
+    for (int b = tid; b < a.B; b += blockDim.x) order[atomicAdd(&cursor[mix_bucket(a.nq[b])], 1)] = b;
+}
+
+template <int NQ, int W>
+__device__ __forceinline__ void mix_lds_item(const BatchArgs& a, int b, float2* M, float (*red)[3],
+                                             float* f, float* g, float* delta) {
+    const int lane = (int)lane_id(), wave = (int)(threadIdx.x >> 6);
+    Item it;
+    it.err = 1;
+    if (b >= 0) it = resolve(a, b);
+    bool ok = it.err == 0;
+    float off = 0.0f;
+    float2 dg = make_float2(0.0f, 0.0f);
+    if (ok) {
+        const uint16_t* gp = it.g;
+        const int L = it.L;
+        auto src = [&](int ch) -> uint32_t {
+            const int p = ch * 64 + lane;
+            return p < L ? (uint32_t)gp[p] : 0u;
+        };
+        const float* T = reinterpret_cast<const float*>(a.targets) + 2 * it.toff;
+        ok = run_lds_path<NQ, W, false>(M, T, L, src, &off, &dg, wave % W);
+        if (!ok) it.err = QE_DEVERR_DESC;
+    }
+    float gv, dv;
+    const float fv = group_fitness<W>(off, dg, red, 1 << NQ, &gv, &dv);
+    if (b >= 0 && wave % W == 0 && lane == 0) {
+        const float nan = __builtin_nanf("");
+        if (ok && !(fv == fv)) it.err = QE_DEVERR_NUMERIC;
+        f[b] = ok ? fv : nan;
+        if (g) g[b] = ok ? gv : nan;
+        if (delta) delta[b] = ok ? dv : nan;
+        if (it.err) atomicOr(a.err, it.err);
+    }
+}
+
+template <int NQ>
+__device__ __forceinline__ void mix_wave_item(const BatchArgs& a, int b, float* f, float* g,
+                                              float* delta) {
+    if (b < 0) return;
+    const int lane = (int)lane_id();
+    Item it = resolve(a, b);
+    FitOut o{__builtin_nanf(""), __builtin_nanf(""), __builtin_nanf("")};
+    if (it.err == 0) {
+        const uint16_t* gp = it.g;
+        const int L = it.L;
+        auto src = [&](int ch) -> uint32_t {
+            const int p = ch * 64 + lane;
+            return p < L ? (uint32_t)gp[p] : 0u;
+        };
+        const float* T = reinterpret_cast<const float*>(a.targets) + 2 * it.toff;
+        if (!run_small_path<NQ, false>(T, L, src, nullptr, &o)) {
+            it.err = QE_DEVERR_DESC;
+            o = FitOut{__builtin_nanf(""), __builtin_nanf(""), __builtin_nanf("")};
+        } else if (!(o.f == o.f)) {
+            it.err = QE_DEVERR_NUMERIC;
+        }
+    }
+    if (lane == 0) {
+        f[b] = o.f;
+        if (g) g[b] = o.g;
+        if (delta) delta[b] = o.delta;
+        if (it.err) atomicOr(a.err, it.err);
+    }
+}
+
+__global__ __launch_bounds__(256) void mix_kernel(BatchArgs a, const int32_t* __restrict__ order,
+                                                  const int32_t* __restrict__ meta,
+                                                  float* __restrict__ f, float* __restrict__ g,
+                                                  float* __restrict__ delta) {
+    __shared__ float2 M[4096];
+    __shared__ float red[4][3];
+    const int item = blockIdx.x;
+    if (item >= meta[8 + MIX_BUCKETS]) return;
+    int k = 0;
+    while (k + 1 < MIX_BUCKETS && item >= meta[8 + k + 1]) ++k;
+    const int wave = (int)(threadIdx.x >> 6);
+    const int per = mix_per_item(k);
+    const int local = (item - meta[8 + k]) * per;
+    const int sub = per == 1 ? 0 : (per == 2 ? wave >> 1 : wave);
+    const int b = local + sub < meta[16 + k] ? order[meta[k] + local + sub] : -1;
+    switch (k) {
+        case 0: mix_lds_item<6, 4>(a, b, M, red, f, g, delta); break;
+        case 1: mix_lds_item<5, 2>(a, b, M + sub * 1024, red, f, g, delta); break;
+        case 2: mix_lds_item<4, 1>(a, b, M + sub * 256, red, f, g, delta); break;
+        case 3: mix_wave_item<3>(a, b, f, g, delta); break;
+        case 4: mix_wave_item<2>(a, b, f, g, delta); break;
+        case 5: mix_wave_item<1>(a, b, f, g, delta); break;
+        default:
+            if (b >= 0 && lane_id() == 0) {
+                const float nan = __builtin_nanf("");
+                f[b] = nan;
+                if (g) g[b] = nan;
+                if (delta) delta[b] = nan;
+                atomicOr(a.err, (uint32_t)QE_DEVERR_WIDTH);
+            }
+            break;
+    }
+}
+
 // --------------------------------------------------------- generic LDS path
 template <typename Real, bool IDENT>
 __global__ __launch_bounds__(256) void lds_kernel(BatchArgs a, Real* __restrict__ f,
@@ -178,10 +312,16 @@ static void launch_width(const BatchArgs& a, int n, bool lds, float* f, float* g
 }
 
 hipError_t launch_eval_fp32(const BatchArgs& a, int path, float* f, float* g, float* delta,
-                            hipStream_t s) {
+                            int32_t* work, hipStream_t s) {
     if (a.B == 0) return hipSuccess;
     if (a.uniform_n > 0) {
         launch_width<false>(a, a.uniform_n, use_lds(a.uniform_n, path), f, g, delta, s);
+    } else if (path == QE_PATH_FP32 && work) {
+        // one launch over width-sorted work items (LDS-staged for n >= 4)
+        int32_t* meta = work;
+        int32_t* order = work + 32;
+        mix_bucket_kernel<<<1, 1024, 0, s>>>(a, order, meta);
+        mix_kernel<<<a.B, 256, 0, s>>>(a, order, meta, f, g, delta);
     } else {
         width_check_kernel<<<(a.B + 255) / 256, 256, 0, s>>>(a, f, g, delta);
         for (int n = 1; n <= MAX_QUBITS; ++n)

@@ -278,6 +278,7 @@ __device__ __forceinline__ bool run_register_path(const float* __restrict__ T, i
     const int lane = (int)lane_id();
     const int j = lane & (N - 1);
     const int lr = lane >> NQ;
+    const uint32_t dv0 = L > 0 ? src(0) : 0u;   // before the target: latencies overlap
     float re[E], im[E];
     if (IDENT) {
 #pragma unroll
@@ -307,7 +308,7 @@ __device__ __forceinline__ bool run_register_path(const float* __restrict__ T, i
     bool ok = true;
     const int chunks = (L + 63) >> 6;
     for (int ch = 0; ch < chunks; ++ch) {
-        const uint32_t dv = src(ch);
+        const uint32_t dv = ch == 0 ? dv0 : src(ch);
         const int cnt = min(64, L - ch * 64);
         const bool bad = (lane < cnt) && !desc_valid(dv, NQ);
         if (__ballot(bad)) { ok = false; break; }
@@ -384,6 +385,7 @@ __device__ __forceinline__ bool run_small_path(const float* __restrict__ T, int 
     const int lane = (int)lane_id();
     const bool live = lane < N * N;
     const int i = (lane >> NQ) & (N - 1), j = lane & (N - 1);
+    const uint32_t dv0 = L > 0 ? src(0) : 0u;   // before the target: latencies overlap
     float mr = 0.0f, mi = 0.0f;
     if (live) {
         if (IDENT) {
@@ -398,7 +400,7 @@ __device__ __forceinline__ bool run_small_path(const float* __restrict__ T, int 
     const float r = 0.70710678118654752f;
     const int chunks = (L + 63) >> 6;
     for (int ch = 0; ch < chunks; ++ch) {
-        const uint32_t dv = src(ch);
+        const uint32_t dv = ch == 0 ? dv0 : src(ch);
         const int cnt = min(64, L - ch * 64);
         const bool bad = (lane < cnt) && !desc_valid(dv, NQ);
         if (__ballot(bad)) { ok = false; break; }
@@ -529,13 +531,17 @@ __device__ __forceinline__ void lds_gate(float2* M, int j, int rg, int tpos, int
 // elements of the wave's columns (lane l < CW holds element (j, j)).
 template <int NQ, int W, bool IDENT, typename GateSrc>
 __device__ __forceinline__ bool run_lds_path(float2* M, const float* __restrict__ T, int L,
-                                             GateSrc&& src, float* off_out, float2* diag_out) {
+                                             GateSrc&& src, float* off_out, float2* diag_out,
+                                             int wave = -1) {
     constexpr int N = 1 << NQ, CW = N / W, RG = 64 / CW;
     static_assert(CW <= 64 && 64 % CW == 0 && N % RG == 0, "layout");
     const int lane = (int)lane_id();
-    const int wave = (int)(threadIdx.x >> 6);
+    if (wave < 0) wave = (int)(threadIdx.x >> 6);
     const int jl = lane % CW, rg = lane / CW;
     const int j = wave * CW + jl;
+    // the first chunk of descriptors is fetched (or sampled) before the
+    // target so that the two memory latencies overlap
+    const uint32_t dv0 = L > 0 ? src(0) : 0u;
     // M_0 = T^dagger (or I): M[r][j] = conj(T[j][r])
     const float2* T2 = reinterpret_cast<const float2*>(T);
 #pragma unroll
@@ -550,7 +556,7 @@ __device__ __forceinline__ bool run_lds_path(float2* M, const float* __restrict_
     bool ok = true;
     const int chunks = (L + 63) >> 6;
     for (int ch = 0; ch < chunks; ++ch) {
-        const uint32_t dv = src(ch);
+        const uint32_t dv = ch == 0 ? dv0 : src(ch);
         const int cnt = min(64, L - ch * 64);
         const bool bad = (lane < cnt) && !desc_valid(dv, NQ);
         if (__ballot(bad)) { ok = false; break; }
@@ -717,6 +723,41 @@ __device__ __forceinline__ void lds_generic_body(int n, int L, const uint16_t* g
         if (delta) *delta = ok ? dl : nan;
         if (err) atomicOr(errw, err);
     }
+}
+
+// Eq. 11 from the per-wave partial sums of the LDS-staged path, for the W
+// wavefronts gb .. gb+W-1 of a 4-wave workgroup that share a circuit (every
+// wavefront of the workgroup must call it: it contains workgroup barriers).
+// red: 4 x 3 floats of LDS.  Returns the fitness on every lane; g, delta out.
+template <int W>
+__device__ __forceinline__ float group_fitness(float off, float2 dg, float (*red)[3], int N,
+                                               float* g_out, float* delta_out) {
+    const int lane = (int)lane_id(), wave = (int)(threadIdx.x >> 6);
+    const int gb = (wave / W) * W, CW = N / W;
+    const float offw = wave_sum(off), trw = wave_sum(dg.x), tiw = wave_sum(dg.y);
+    __syncthreads();
+    if (lane == 0) { red[wave][0] = offw; red[wave][1] = trw; red[wave][2] = tiw; }
+    __syncthreads();
+    float offs = 0.0f, tr = 0.0f, ti = 0.0f;
+#pragma unroll
+    for (int w = 0; w < W; ++w) { offs += red[gb + w][0]; tr += red[gb + w][1]; ti += red[gb + w][2]; }
+    const float am = sqrtf(tr * tr + ti * ti);
+    float er = 1.0f, ei = 0.0f;
+    if (am > 0.0f) { er = tr / am; ei = ti / am; }
+    float dl = 0.0f;
+    if (lane < CW) { const float xr = dg.x - er, xi = dg.y - ei; dl = xr * xr + xi * xi; }
+    const float dw = wave_sum(dl);
+    __syncthreads();
+    if (lane == 0) red[wave][0] = dw;
+    __syncthreads();
+    float D = 0.0f;
+#pragma unroll
+    for (int w = 0; w < W; ++w) D += red[gb + w][0];
+    const float dlt = 0.5f * (offs + D);
+    const float q = fminf(fmaxf(dlt / (float)N, 0.0f), 1.0f);
+    *g_out = am / (float)N;
+    *delta_out = dlt;
+    return 1.0f - sqrtf(q);
 }
 
 template <bool IDENT, typename GateSrc>

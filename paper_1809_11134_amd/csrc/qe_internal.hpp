@@ -25,8 +25,10 @@ struct BatchArgs {
 bool schedule_lds(int n);
 
 // eval.hip
+// work: 32 + B int32 of device workspace for mixed-width batches (order of
+// circuits by width); NULL selects one filtered launch per width.
 hipError_t launch_eval_fp32(const BatchArgs& a, int path, float* f, float* g, float* delta,
-                            hipStream_t s);
+                            int32_t* work, hipStream_t s);
 hipError_t launch_eval_lds(const BatchArgs& a, bool fp64, void* f, void* g, void* delta,
                            hipStream_t s);
 hipError_t launch_unitary(const BatchArgs& a, bool fp64, void* out, hipStream_t s);
