@@ -73,7 +73,7 @@ enum { QE_PATH_FP32 = 0,        /* per-gate row updates, FP32, tuned schedule pe
 /* Device error flags (bitmask) raised by kernels. */
 enum { QE_DEVERR_DESC = 1,      /* invalid gate descriptor */
        QE_DEVERR_WIDTH = 2,     /* circuit width outside 1..6 */
-       QE_DEVERR_RANGE = 4,     /* gate or target offsets outside the buffers */
+       QE_DEVERR_RANGE = 4,     /* gate, target or mutation-list index outside its buffer */
        QE_DEVERR_NUMERIC = 8 }; /* NaN/Inf fitness */
 
 /* ------------------------------------------------------------------ batches */
@@ -137,7 +137,8 @@ qe_status qe_device_errors(int32_t* flags_host);
 /* Parameters of the evolutionary search (Sec. IV-B, IV-F, V-B):
  *   n_qubits (numberOfWires) 2..6 for QEQEA, 1..6 for GA; library QE_LIB_*;
  *   algorithm QE_ALG_*; size_of_individual L (circuit length) 1..1024;
- *   size_of_population P (circuits per instance per generation) 1..65536;
+ *   size_of_population P (circuits per instance per generation) 1..65536
+ *   (QEQEA 1..16384, GA 1..4096);
  *   n_instances I independent populations, each with its own target;
  *   prob_mutation (probabilityOfMutation, QEQEA) in [0, 1];
  *   mutation_range (mutationRange, radians) in [0, 2 pi);
@@ -159,8 +160,10 @@ typedef struct {
 } qe_problem;
 
 /* Creates a context on the current device: allocates the ctx-owned encoding
- * (QEQEA: (n + n(n-1)) * L * P u32 angles, n*L*P qutrits of 3 complex64, and
- * their best copies and fitness; GA: two L*P genome buffers) per instance,
+ * (QEQEA: (n + n(n-1)) * L * P slot records of 32 bytes (angle, best angle,
+ * best segment fitness, the generation's segment key) and n*L*P qutrit records of 64 bytes
+ * (3 complex64 amplitudes and their best copy); GA: two L*P genome buffers)
+ * per instance,
  * and initialises it as the population initialisation of Sec. IV-B (angles
  * from the Philox INIT stream, qutrits (1,1,1)/sqrt(3), no best yet).  Syncs. */
 qe_status qe_create(const qe_problem* problem, qe_ctx** ctx_out);
@@ -243,11 +246,16 @@ qe_status qe_get_best(qe_ctx* ctx, int32_t instance, uint16_t* gates_host, float
 qe_status qe_checkpoint(qe_ctx* ctx, void* buf_host, size_t* size);
 qe_status qe_restore(qe_ctx* ctx, const void* buf_host, size_t size);
 
-/* Raw views of the context-owned state (device pointers; sizes in elements)
- * for tests and inspection.  which: 0 theta (u32), 1 qutrit (f32, 6 per
- * qutrit), 2 best_f (f32), 3 best_theta (u32), 4 best_qutrit (f32),
- * 5 GA genomes of the current generation parity 0 (u16), 6 parity 1. */
-qe_status qe_state_view(qe_ctx* ctx, int32_t which, void** ptr_dev, int64_t* elems);
+/* Dense copy of one field of the context-owned state, for tests and
+ * inspection (the QEQEA state is stored per slot as one record, so each field
+ * is gathered).  which: 0 theta (u32, [I][S] slot order of Eq. 10), 1 qutrit
+ * amplitudes (f32, 6 per qutrit, [I][n*L*P]), 2 best_f (f32), 3 best_theta
+ * (u32), 4 best qutrit amplitudes (f32), 5 GA genomes of generation parity 0
+ * (u16, [I][P][L]), 6 parity 1.  *elems receives the field's size in
+ * elements (0 when the algorithm has no such field); with dst_dev non-NULL
+ * (device memory of that size, caller-owned) the copy is enqueued on
+ * `stream`.  Unknown which: QE_ERR_INVALID. */
+qe_status qe_state_read(qe_ctx* ctx, int32_t which, void* dst_dev, int64_t* elems, void* stream);
 
 /* Gate-library table used by the GA (instance index -> descriptor), host
  * output of qe_lib_size() entries. */

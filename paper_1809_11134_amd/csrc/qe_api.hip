@@ -202,6 +202,9 @@ struct qe_ctx {
     hipStream_t capture_stream = nullptr;
     std::map<std::pair<int, float*>, hipGraphExec_t> graphs;
     hipGraph_t last_graph = nullptr;
+    // the generation whose mutation decisions may be appended to the lists
+    // without emptying them first (the one after the last decided)
+    uint64_t next_decision_gen = 0;
 };
 
 namespace {
@@ -238,6 +241,17 @@ qe_status check_ctx(qe_ctx* c, bool need_targets) {
 
 // sample + eval + update of one generation (gen is relative to la.gen_ptr
 // when graph-captured).
+// Before the mutation decisions of generation `gen` (first of `count`
+// consecutive ones): the decision masks are cleared unless the previous
+// decisions were those of gen - 1, whose kernels cleared the mask of gen's
+// parity.
+qe_status prepare_decisions(qe_ctx* c, uint64_t gen, uint64_t count, hipStream_t s) {
+    if (c->prob.algorithm != QE_ALG_QEQEA) return QE_OK;
+    if (gen != c->next_decision_gen) QE_HIP(launch_mutmask_clear(c->la, s));
+    c->next_decision_gen = gen + count;
+    return QE_OK;
+}
+
 qe_status enqueue_generation(qe_ctx* c, const LoopArgs& a, uint64_t gen, float* f, hipStream_t s) {
     if (c->prob.algorithm == QE_ALG_QEQEA) {
         QE_HIP(launch_qeqea_fused(a, gen, c->slots, c->gates, f, true, s));
@@ -354,6 +368,8 @@ qe_status qe_create(const qe_problem* p, qe_ctx** out) {
     if (p->size_of_individual < 1 || p->size_of_individual > 1024) return fail(QE_ERR_INVALID, "L must be 1..1024");
     if (p->size_of_population < 1 || p->size_of_population > 65536) return fail(QE_ERR_INVALID, "P must be 1..65536");
     if (p->algorithm == QE_ALG_GA && p->size_of_population > 4096) return fail(QE_ERR_INVALID, "GA needs P <= 4096");
+    if (p->algorithm == QE_ALG_QEQEA && p->size_of_population > 16384)
+        return fail(QE_ERR_INVALID, "QEQEA needs P <= 16384");
     if (p->n_instances < 1) return fail(QE_ERR_INVALID, "n_instances must be >= 1");
     const double pi2 = 2.0 * 3.14159265358979323846;
     if (!(p->prob_mutation >= 0 && p->prob_mutation <= 1)) return fail(QE_ERR_INVALID, "prob_mutation must be in [0,1]");
@@ -385,12 +401,8 @@ qe_status qe_create(const qe_problem* p, qe_ctx** out) {
     const size_t NN = (size_t)c->N * c->N;
 #define ALLOC(ptr, n_) if (st == QE_OK) st = ctx_alloc(c, &(ptr), (n_))
     if (p->algorithm == QE_ALG_QEQEA) {
-        ALLOC(a.theta, I * S);
-        ALLOC(a.best_theta, I * S);
-        ALLOC(a.best_f, I * S);
-        ALLOC(a.segfit, I * S);
-        ALLOC(a.qutrit, I * Q * 6);
-        ALLOC(a.best_qutrit, I * Q * 6);
+        ALLOC(a.slot, I * S);
+        ALLOC(a.qrec, I * Q);
         ALLOC(a.su3_tab, (size_t)4 * SU3_TAB);
     } else {
         ALLOC(a.genomes[0], I * P * L);
@@ -403,12 +415,10 @@ qe_status qe_create(const qe_problem* p, qe_ctx** out) {
     a.target32 = t32;
     a.target64 = t64;
     ALLOC(a.inst_best_f, I);
-    ALLOC(a.inst_key, I);
     if (p->algorithm == QE_ALG_QEQEA) {
-        ALLOC(a.mutflag, I * P);
-        ALLOC(a.mutlist, I * P);
+        a.MW = (uint32_t)((P + 31) / 32);
+        ALLOC(a.mutmask, 2 * I * a.MW);
     }
-    ALLOC(a.mutcnt, I);
     ALLOC(a.inst_best_gates, I * L);
     ALLOC(c->slots, I * P * L);
     ALLOC(c->gates, I * P * L);
@@ -493,6 +503,7 @@ qe_status qe_update(qe_ctx* c, uint64_t gen, const uint32_t* slots, const uint16
     if (c->prob.algorithm == QE_ALG_QEQEA) {
         if (!slots) return fail(QE_ERR_INVALID, "slots is NULL");
         QE_HIP(launch_scatter(c->la, gen, slots, f, s));
+        QE_TRY(prepare_decisions(c, gen, 1, s));
         QE_HIP(launch_mutation_decisions(c->la, gen, s));
         QE_HIP(launch_qeqea_update(c->la, gen, slots, gates, f, s));
     } else {
@@ -503,6 +514,7 @@ qe_status qe_update(qe_ctx* c, uint64_t gen, const uint32_t* slots, const uint16
 
 qe_status qe_generation(qe_ctx* c, uint64_t gen, float* f, void* stream) {
     QE_TRY(check_ctx(c, true));
+    QE_TRY(prepare_decisions(c, gen, 1, (hipStream_t)stream));
     return enqueue_generation(c, c->la, gen, f ? f : c->f, (hipStream_t)stream);
 }
 
@@ -552,6 +564,7 @@ qe_status qe_run_graph(qe_ctx* c, uint64_t first_gen, int32_t n_gen, float* f_hi
     hipStream_t s = (hipStream_t)stream;
     hipGraphExec_t ex;
     QE_TRY(graph_for(c, n_gen, f_hist, &ex));
+    QE_TRY(prepare_decisions(c, first_gen, (uint64_t)n_gen, s));
     QE_HIP(launch_gen_set(c->d_gen, first_gen, s));
     QE_HIP(hipGraphLaunch(ex, s));
     return QE_OK;
@@ -617,12 +630,8 @@ std::vector<Section> state_sections(qe_ctx* c) {
     const size_t I = c->prob.n_instances, P = c->prob.size_of_population, L = c->prob.size_of_individual;
     std::vector<Section> v;
     if (c->prob.algorithm == QE_ALG_QEQEA) {
-        v.push_back({a.theta, I * c->S * 4});
-        v.push_back({a.best_theta, I * c->S * 4});
-        v.push_back({a.best_f, I * c->S * 4});
-        v.push_back({a.segfit, I * c->S * 4});
-        v.push_back({a.qutrit, I * c->Q * 24});
-        v.push_back({a.best_qutrit, I * c->Q * 24});
+        v.push_back({a.slot, I * c->S * sizeof(SlotRec)});
+        v.push_back({a.qrec, I * c->Q * sizeof(QutritRec)});
     } else {
         v.push_back({a.genomes[0], I * P * L * 2});
         v.push_back({a.genomes[1], I * P * L * 2});
@@ -652,8 +661,8 @@ qe_status qe_checkpoint(qe_ctx* c, void* buf, size_t* size) {
     if (*size < need) return fail(QE_ERR_INVALID, "checkpoint buffer too small");
     QE_HIP(hipDeviceSynchronize());
     CkptHeader h{};
-    std::memcpy(h.magic, "QECKPT01", 8);
-    h.version = 1;
+    std::memcpy(h.magic, "QECKPT02", 8);
+    h.version = 2;
     h.prob = c->prob;
     h.payload = payload;
     std::memcpy(buf, &h, sizeof(h));
@@ -671,7 +680,7 @@ qe_status qe_restore(qe_ctx* c, const void* buf, size_t size) {
     if (!buf || size < sizeof(CkptHeader)) return fail(QE_ERR_INVALID, "checkpoint too small");
     CkptHeader h;
     std::memcpy(&h, buf, sizeof(h));
-    if (std::memcmp(h.magic, "QECKPT01", 8) != 0 || h.version != 1)
+    if (std::memcmp(h.magic, "QECKPT02", 8) != 0 || h.version != 2)
         return fail(QE_ERR_INVALID, "not a libqe checkpoint");
     if (std::memcmp(&h.prob, &c->prob, sizeof(qe_problem)) != 0)
         return fail(QE_ERR_INVALID, "checkpoint was written for a different problem");
@@ -686,26 +695,31 @@ qe_status qe_restore(qe_ctx* c, const void* buf, size_t size) {
         p += s.bytes;
     }
     QE_HIP(hipDeviceSynchronize());
+    c->next_decision_gen = ~0ull;   // the decision masks start cleared again
     return QE_OK;
 }
 
-qe_status qe_state_view(qe_ctx* c, int32_t which, void** ptr, int64_t* elems) {
+qe_status qe_state_read(qe_ctx* c, int32_t which, void* dst, int64_t* elems, void* stream) {
     QE_TRY(check_ctx(c, false));
-    if (!ptr || !elems) return fail(QE_ERR_INVALID, "NULL output");
+    if (!elems) return fail(QE_ERR_INVALID, "elems is NULL");
     const LoopArgs& a = c->la;
     const size_t I = c->prob.n_instances, P = c->prob.size_of_population, L = c->prob.size_of_individual;
     const bool q = c->prob.algorithm == QE_ALG_QEQEA;
+    int64_t n = 0;
     switch (which) {
-        case 0: *ptr = a.theta; *elems = q ? (int64_t)(I * c->S) : 0; break;
-        case 1: *ptr = a.qutrit; *elems = q ? (int64_t)(I * c->Q * 6) : 0; break;
-        case 2: *ptr = a.best_f; *elems = q ? (int64_t)(I * c->S) : 0; break;
-        case 3: *ptr = a.best_theta; *elems = q ? (int64_t)(I * c->S) : 0; break;
-        case 4: *ptr = a.best_qutrit; *elems = q ? (int64_t)(I * c->Q * 6) : 0; break;
-        case 5: *ptr = a.genomes[0]; *elems = q ? 0 : (int64_t)(I * P * L); break;
-        case 6: *ptr = a.genomes[1]; *elems = q ? 0 : (int64_t)(I * P * L); break;
-        default: return fail(QE_ERR_INVALID, "unknown state view");
+        case 0: case 2: case 3: n = q ? (int64_t)(I * c->S) : 0; break;
+        case 1: case 4: n = q ? (int64_t)(I * c->Q * 6) : 0; break;
+        case 5: case 6: n = q ? 0 : (int64_t)(I * P * L); break;
+        default: return fail(QE_ERR_INVALID, "unknown state field");
     }
-    if (*elems == 0) *ptr = nullptr;
+    *elems = n;
+    if (!dst || n == 0) return QE_OK;
+    hipStream_t s = (hipStream_t)stream;
+    if (which >= 5)
+        QE_HIP(hipMemcpyAsync(dst, a.genomes[which - 5], (size_t)n * sizeof(uint16_t),
+                              hipMemcpyDeviceToDevice, s));
+    else
+        QE_HIP(launch_state_gather(a, which, dst, s));
     return QE_OK;
 }
 

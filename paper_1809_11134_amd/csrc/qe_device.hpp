@@ -56,10 +56,40 @@ __device__ __forceinline__ bool desc_valid(uint32_t d, int n) {
 }
 
 // ------------------------------------------------------------- wave reductions
+// Sums over the 64 lanes; every lane receives the same value.  All lanes must
+// be active.
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+
+// FP32 version without LDS round trips: DPP within rows of 16 lanes (lane
+// l ^ 1, l ^ 2, the mirror inside 8 lanes, the mirror inside 16), then the
+// row swaps of v_permlane16_swap / v_permlane32_swap.  Each step adds the
+// same two partial sums on both partner lanes, so the result is identical
+// everywhere.
+__device__ __forceinline__ float wave_sum(float v) {
+    v += dpp_mov<0xB1>(v);    // quad_perm [1,0,3,2]
+    v += dpp_mov<0x4E>(v);    // quad_perm [2,3,0,1]
+    v += dpp_mov<0x141>(v);   // row_half_mirror
+    v += dpp_mov<0x140>(v);   // row_mirror
+    {
+        const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v),
+                                                        false, false);
+        v = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+    {
+        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v),
+                                                        false, false);
+        v = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
     return v;
 }
 

@@ -463,69 +463,6 @@ __device__ __forceinline__ void wave_lds_fence() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <int NIT>
-__device__ __forceinline__ void lds_pass_load(const float2* M, int base0, int base1,
-                                              const int* off, float2* A, float2* B, bool needA) {
-#pragma unroll
-    for (int m = 0; m < NIT; ++m) {
-        if (needA) A[m] = M[base0 + off[m]];
-        B[m] = M[base1 + off[m]];
-    }
-}
-
-// One gate on this wave's columns.  tpos/cpos: bit positions of the target /
-// control in the row index (cpos < 0: uncontrolled).
-template <int NQ, int CW, int KIND>
-__device__ __forceinline__ void lds_gate(float2* M, int j, int rg, int tpos, int cpos) {
-    constexpr int N = 1 << NQ, RG = 64 / CW;
-    const int tb = 1 << tpos;
-    const bool ctl = cpos >= 0;
-    if (!ctl) {
-        constexpr int NIT = (N / 2) / RG;
-        int off[NIT];
-#pragma unroll
-        for (int m = 0; m < NIT; ++m) off[m] = ins0(m * RG, tpos) * N;
-        const int base0 = ins0(rg, tpos) * N + j, base1 = base0 + tb * N;
-        float2 A[NIT], B[NIT];
-        lds_pass_load<NIT>(M, base0, base1, off, A, B, KIND != KIND_T);
-        const float r = 0.70710678118654752f;
-#pragma unroll
-        for (int m = 0; m < NIT; ++m) {
-            float2 a = A[m], b = B[m];
-            if constexpr (KIND == KIND_NOT) {
-                M[base0 + off[m]] = b; M[base1 + off[m]] = a;
-            } else if constexpr (KIND == KIND_H) {
-                M[base0 + off[m]] = make_float2((a.x + b.x) * r, (a.y + b.y) * r);
-                M[base1 + off[m]] = make_float2((a.x - b.x) * r, (a.y - b.y) * r);
-            } else {   // T
-                M[base1 + off[m]] = make_float2((b.x - b.y) * r, (b.x + b.y) * r);
-            }
-        }
-    } else {
-        constexpr int NIT = (N / 4) / RG;
-        const int lo = min(tpos, cpos), hi = max(tpos, cpos), cb = 1 << cpos;
-        int off[NIT];
-#pragma unroll
-        for (int m = 0; m < NIT; ++m) off[m] = ins0(ins0(m * RG, lo), hi) * N;
-        const int base0 = (ins0(ins0(rg, lo), hi) | cb) * N + j, base1 = base0 + tb * N;
-        float2 A[NIT], B[NIT];
-        lds_pass_load<NIT>(M, base0, base1, off, A, B, true);
-#pragma unroll
-        for (int m = 0; m < NIT; ++m) {
-            const float2 a = A[m], b = B[m];
-            if constexpr (KIND == KIND_CNOT) {
-                M[base0 + off[m]] = b; M[base1 + off[m]] = a;
-            } else {
-                const float p = a.x + b.x, q = a.y + b.y, u = a.x - b.x, v = a.y - b.y;
-                const float2 x = make_float2(0.5f * (p - v), 0.5f * (q + u));
-                const float2 y = make_float2(0.5f * (p + v), 0.5f * (q - u));
-                if constexpr (KIND == KIND_CV) { M[base0 + off[m]] = x; M[base1 + off[m]] = y; }
-                else { M[base0 + off[m]] = y; M[base1 + off[m]] = x; }
-            }
-        }
-    }
-}
-
 // Runs the circuit on this wave's columns and, with `fit`, leaves per-wave
 // partial sums for the fitness: off-diagonal |m|^2, and the diagonal
 // elements of the wave's columns (lane l < CW holds element (j, j)).
@@ -534,45 +471,135 @@ __device__ __forceinline__ bool run_lds_path(float2* M, const float* __restrict_
                                              GateSrc&& src, float* off_out, float2* diag_out,
                                              int wave = -1) {
     constexpr int N = 1 << NQ, CW = N / W, RG = 64 / CW;
-    static_assert(CW <= 64 && 64 % CW == 0 && N % RG == 0, "layout");
+    static_assert(CW <= 64 && 64 % CW == 0 && N % RG == 0 && RG == 4, "layout: four row groups per wavefront");
     const int lane = (int)lane_id();
     if (wave < 0) wave = (int)(threadIdx.x >> 6);
     const int jl = lane % CW, rg = lane / CW;
     const int j = wave * CW + jl;
-    // the first chunk of descriptors is fetched (or sampled) before the
-    // target so that the two memory latencies overlap
-    const uint32_t dv0 = L > 0 ? src(0) : 0u;
-    // M_0 = T^dagger (or I): M[r][j] = conj(T[j][r])
+    // The target loads are issued first, then the first chunk of descriptors
+    // is fetched (or sampled, which may take dependent loads of its own), so
+    // that the latencies overlap; M_0 = T^dagger (or I): M[r][j] = conj(T[j][r]).
     const float2* T2 = reinterpret_cast<const float2*>(T);
+    float2 tv[N / RG];
 #pragma unroll
     for (int m = 0; m < N / RG; ++m) {
         const int r = m * RG + rg;
-        float2 v;
-        if (IDENT) v = make_float2(r == j ? 1.0f : 0.0f, 0.0f);
-        else { v = T2[(size_t)j * N + r]; v.y = -v.y; }
-        M[r * N + j] = v;
+        if (IDENT) tv[m] = make_float2(r == j ? 1.0f : 0.0f, 0.0f);
+        else tv[m] = T2[(size_t)j * N + r];
+    }
+    const uint32_t dv0 = L > 0 ? src(0) : 0u;
+#pragma unroll
+    for (int m = 0; m < N / RG; ++m) {
+        const int r = m * RG + rg;
+        M[r * N + j] = IDENT ? tv[m] : make_float2(tv[m].x, -tv[m].y);
     }
     wave_lds_fence();
     bool ok = true;
     const int chunks = (L + 63) >> 6;
+    // lane constants: byte offset of column j, and the two row-group bits as
+    // all-ones / all-zeros masks
+    const uint32_t jb = (uint32_t)j * 8u;
+    const uint32_t mb0 = (rg & 1) ? ~0u : 0u, mb1 = (rg & 2) ? ~0u : 0u;
+    auto at = [&](uint32_t byte_off) -> float2& {
+        return *reinterpret_cast<float2*>(reinterpret_cast<char*>(M) + byte_off);
+    };
+    constexpr uint32_t ROWB = NQ + 3;      // log2 of a row's byte stride (N * 8)
     for (int ch = 0; ch < chunks; ++ch) {
         const uint32_t dv = ch == 0 ? dv0 : src(ch);
         const int cnt = min(64, L - ch * 64);
         const bool bad = (lane < cnt) && !desc_valid(dv, NQ);
         if (__ballot(bad)) { ok = false; break; }
-        for (int g = 0; g < cnt; ++g) {
-            const uint32_t d = __builtin_amdgcn_readlane(dv, g);
-            const int kind = d & 15;
-            if (kind == KIND_I) continue;
-            const int tpos = NQ - 1 - (int)((d >> 4) & 15);
-            const int cpos = NQ - 1 - (int)((d >> 8) & 15);
-            switch (kind) {
-                case KIND_NOT: lds_gate<NQ, CW, KIND_NOT>(M, j, rg, tpos, -1); break;
-                case KIND_CNOT: lds_gate<NQ, CW, KIND_CNOT>(M, j, rg, tpos, cpos); break;
-                case KIND_CV: lds_gate<NQ, CW, KIND_CV>(M, j, rg, tpos, cpos); break;
-                case KIND_CVDG: lds_gate<NQ, CW, KIND_CVDG>(M, j, rg, tpos, cpos); break;
-                case KIND_H: lds_gate<NQ, CW, KIND_H>(M, j, rg, tpos, -1); break;
-                default: lds_gate<NQ, CW, KIND_T>(M, j, rg, tpos, -1); break;
+        // Gate program, one gate per lane (lane g: gate g of the chunk): the
+        // byte offsets in M of pair-index bits 0..4 once the target bit (and
+        // the control bit) are inserted as zeros, the control row offset and
+        // the partner row offset.  The loop then reads them with v_readlane
+        // and visits only the gates that are not I.
+        const int kind = (int)(dv & 15u);
+        const int tpos = NQ - 1 - (int)((dv >> 4) & 15u);
+        const int cpos = NQ - 1 - (int)((dv >> 8) & 15u);
+        const bool ctl = kind_controlled(kind);
+        const int lo = ctl ? min(tpos, cpos) : tpos, hi = ctl ? max(tpos, cpos) : tpos;
+        auto ins = [&](int x) -> uint32_t {
+            int y = ins0(x, lo);
+            if (ctl) y = ins0(y, hi);
+            return (uint32_t)y << ROWB;
+        };
+        const uint32_t R0 = ins(1), R1 = ins(2), R2 = ins(4), R3 = ins(8), R4 = ins(16);
+        const uint32_t CB = ctl ? (1u << (cpos + (int)ROWB)) : 0u, TB = 1u << (tpos + (int)ROWB);
+        uint64_t todo = __ballot(lane < cnt && kind != KIND_I);
+        while (todo) {
+            const int g = (int)__builtin_ctzll(todo);
+            todo &= todo - 1;
+            const int k = __builtin_amdgcn_readlane(kind, g);
+            const uint32_t r0 = __builtin_amdgcn_readlane(R0, g), r1 = __builtin_amdgcn_readlane(R1, g);
+            const uint32_t tb = __builtin_amdgcn_readlane(TB, g);
+            if (k >= KIND_CNOT && k <= KIND_CVDG) {
+                constexpr int NIT = (N / 4) / RG;
+                const uint32_t cb = __builtin_amdgcn_readlane(CB, g);
+                uint32_t offm[NIT];
+                offm[0] = 0u;
+                if constexpr (NIT > 1) offm[1] = __builtin_amdgcn_readlane(R2, g);
+                if constexpr (NIT > 2) {
+                    offm[2] = __builtin_amdgcn_readlane(R3, g);
+                    offm[3] = offm[1] | offm[2];
+                }
+                const uint32_t a0 = ((mb0 & r0) | (mb1 & r1)) + jb + cb, a1 = a0 + tb;
+                float2 A[NIT], B[NIT];
+#pragma unroll
+                for (int m = 0; m < NIT; ++m) { A[m] = at(a0 + offm[m]); B[m] = at(a1 + offm[m]); }
+                if (k == KIND_CNOT) {
+#pragma unroll
+                    for (int m = 0; m < NIT; ++m) { at(a0 + offm[m]) = B[m]; at(a1 + offm[m]) = A[m]; }
+                } else {
+                    // CV: (x, y) -> V (x, y); CV+ writes the two results the other
+                    // way round (V+ = X V X for the symmetric V)
+                    const uint32_t sw = k == KIND_CVDG ? tb : 0u;
+#pragma unroll
+                    for (int m = 0; m < NIT; ++m) {
+                        const float2 a = A[m], b = B[m];
+                        const float p = a.x + b.x, q = a.y + b.y, u = a.x - b.x, v = a.y - b.y;
+                        at(a0 + sw + offm[m]) = make_float2(0.5f * (p - v), 0.5f * (q + u));
+                        at(a1 - sw + offm[m]) = make_float2(0.5f * (p + v), 0.5f * (q - u));
+                    }
+                }
+            } else {
+                constexpr int NIT = (N / 2) / RG;
+                uint32_t offm[NIT];
+                offm[0] = 0u;
+                if constexpr (NIT > 1) offm[1] = __builtin_amdgcn_readlane(R2, g);
+                if constexpr (NIT > 2) {
+                    offm[2] = __builtin_amdgcn_readlane(R3, g);
+                    offm[3] = offm[1] | offm[2];
+                }
+                if constexpr (NIT > 4) {
+                    const uint32_t r4 = __builtin_amdgcn_readlane(R4, g);
+#pragma unroll
+                    for (int m = 4; m < 8; ++m) offm[m] = offm[m - 4] | r4;
+                }
+                const uint32_t a0 = ((mb0 & r0) | (mb1 & r1)) + jb, a1 = a0 + tb;
+                const float r = 0.70710678118654752f;
+                if (k == KIND_T) {
+#pragma unroll
+                    for (int m = 0; m < NIT; ++m) {
+                        const float2 b = at(a1 + offm[m]);
+                        at(a1 + offm[m]) = make_float2((b.x - b.y) * r, (b.x + b.y) * r);
+                    }
+                } else {
+                    float2 A[NIT], B[NIT];
+#pragma unroll
+                    for (int m = 0; m < NIT; ++m) { A[m] = at(a0 + offm[m]); B[m] = at(a1 + offm[m]); }
+                    if (k == KIND_NOT) {
+#pragma unroll
+                        for (int m = 0; m < NIT; ++m) { at(a0 + offm[m]) = B[m]; at(a1 + offm[m]) = A[m]; }
+                    } else {   // H
+#pragma unroll
+                        for (int m = 0; m < NIT; ++m) {
+                            const float2 a = A[m], b = B[m];
+                            at(a0 + offm[m]) = make_float2((a.x + b.x) * r, (a.y + b.y) * r);
+                            at(a1 + offm[m]) = make_float2((a.x - b.x) * r, (a.y - b.y) * r);
+                        }
+                    }
+                }
             }
             wave_lds_fence();
         }
@@ -726,8 +753,9 @@ __device__ __forceinline__ void lds_generic_body(int n, int L, const uint16_t* g
 }
 
 // Eq. 11 from the per-wave partial sums of the LDS-staged path, for the W
-// wavefronts gb .. gb+W-1 of a 4-wave workgroup that share a circuit (every
-// wavefront of the workgroup must call it: it contains workgroup barriers).
+// wavefronts gb .. gb+W-1 of a 4-wave workgroup that share a circuit (for
+// W > 1 every wavefront of the workgroup must call it: it contains workgroup
+// barriers; W = 1 uses none).
 // red: 4 x 3 floats of LDS.  Returns the fitness on every lane; g, delta out.
 template <int W>
 __device__ __forceinline__ float group_fitness(float off, float2 dg, float (*red)[3], int N,
@@ -735,6 +763,18 @@ __device__ __forceinline__ float group_fitness(float off, float2 dg, float (*red
     const int lane = (int)lane_id(), wave = (int)(threadIdx.x >> 6);
     const int gb = (wave / W) * W, CW = N / W;
     const float offw = wave_sum(off), trw = wave_sum(dg.x), tiw = wave_sum(dg.y);
+    if constexpr (W == 1) {   // one wavefront per circuit: no LDS exchange
+        const float am = sqrtf(trw * trw + tiw * tiw);
+        float er = 1.0f, ei = 0.0f;
+        if (am > 0.0f) { er = trw / am; ei = tiw / am; }
+        float dl = 0.0f;
+        if (lane < CW) { const float xr = dg.x - er, xi = dg.y - ei; dl = xr * xr + xi * xi; }
+        const float dlt = 0.5f * (offw + wave_sum(dl));
+        const float q = fminf(fmaxf(dlt / (float)N, 0.0f), 1.0f);
+        *g_out = am / (float)N;
+        *delta_out = dlt;
+        return 1.0f - sqrtf(q);
+    }
     __syncthreads();
     if (lane == 0) { red[wave][0] = offw; red[wave][1] = trw; red[wave][2] = tiw; }
     __syncthreads();

@@ -37,6 +37,33 @@ hipError_t launch_unitary(const BatchArgs& a, bool fp64, void* out, hipStream_t 
 hipError_t launch_eval_mfma(const BatchArgs& a, bool fp16, bool renorm, float* f, float* g,
                             float* delta, hipStream_t s);
 
+// Encoding state of one slot (Eq. 10 index), 32 bytes: every field the loop
+// reads or writes for a slot lies in one cache line, so a random slot access
+// costs one line.  `key` is the slot's best use in the current generation:
+// (f bits << 32) | ~circuit over the circuits that used it with a valid
+// fitness (a 64-bit maximum: largest f, lowest circuit on ties), 0 = unused.
+// Its high half is the segment fitness; the circuit it names owns the slot's
+// update.
+struct SlotRec {
+    uint32_t theta;        // qubit angle as a turn fraction (2^32 = 2 pi)
+    uint32_t best_theta;   // state of the best segment fitness seen
+    float best_f;          // best segment fitness seen, -1 = never used
+    uint32_t spare;
+    unsigned long long key;
+    unsigned long long spare2;
+};
+
+__device__ __forceinline__ unsigned long long seg_key(float f, uint32_t circuit) {
+    return ((unsigned long long)__float_as_uint(f) << 32) | (unsigned long long)(0xFFFFFFFFu - circuit);
+}
+
+// Qutrit of a rotation slot (s < n*L*P) and its best copy, one 64-byte line.
+struct QutritRec {
+    float q[6];            // three complex amplitudes (re, im)
+    float bq[6];
+    float pad[4];
+};
+
 // Encoding-state arguments of the QEQEA / GA loop kernels.
 struct LoopArgs {
     int32_t n, lib, L, P, I;
@@ -45,19 +72,18 @@ struct LoopArgs {
     float r32;                         // mutation step per unit (1 - segFit), in 2^-32 turns
     uint32_t S;                        // slots per instance: n*n*L*P
     uint32_t Q;                        // qutrits per instance: n*L*P
-    uint32_t* theta;
-    float* qutrit;
-    float* best_f;
-    uint32_t* best_theta;
-    float* best_qutrit;
-    int32_t* segfit;                   // fitness bits, -1 = unused
+    SlotRec* slot;                     // [I][S]
+    QutritRec* qrec;                   // [I][Q]
     uint16_t* genomes[2];              // GA double buffer
     const float* target32;             // [I][N][N] complex64
     const double* target64;            // [I][N][N] complex128
-    unsigned long long* inst_key;      // per instance: max of (f bits << 32 | ~circuit) this generation
-    uint8_t* mutflag;                  // [I*P] this generation's mutation decision: 0 none, 1 qubits, 2 qutrits
-    uint32_t* mutlist;                 // [I][P] per instance: mutated individuals, unordered
-    uint32_t* mutcnt;                  // [I] list lengths; zeroed after the update consumed them
+    // Mutation decisions as bitmaps, double-buffered by generation parity:
+    // generation g sets bit ind of mask g & 1 for every individual that
+    // mutates and clears mask (g + 1) & 1, which generation g - 1 consumed.
+    // The host clears both before a generation that does not follow the
+    // previous one.
+    uint32_t* mutmask;                 // [2][I][MW]
+    uint32_t MW;                       // words per instance: ceil(P / 32)
     float* inst_best_f;                // per instance
     uint16_t* inst_best_gates;         // [I][L]
     const float* su3_tab;              // [4][4096]: cos/sin of angles, cos/sin of phases
@@ -81,6 +107,10 @@ hipError_t launch_scatter(const LoopArgs& a, uint64_t gen, const uint32_t* slots
                           hipStream_t s);
 hipError_t launch_qeqea_update(const LoopArgs& a, uint64_t gen, const uint32_t* slots,
                                const uint16_t* gates, const float* f, hipStream_t s);
+hipError_t launch_mutmask_clear(const LoopArgs& a, hipStream_t s);
+// Dense copy of one field of the encoding state (which: 0 theta, 1 qutrit
+// amplitudes, 2 best_f, 3 best_theta, 4 best qutrit amplitudes).
+hipError_t launch_state_gather(const LoopArgs& a, int which, void* dst, hipStream_t s);
 hipError_t launch_ga_eval(const LoopArgs& a, uint64_t gen, float* f, hipStream_t s);
 hipError_t launch_ga_update(const LoopArgs& a, uint64_t gen, const float* f, hipStream_t s);
 hipError_t launch_c128_to_c64(const double* src, float* dst, int64_t n_reals, hipStream_t s);

@@ -44,11 +44,11 @@ __device__ __forceinline__ uint16_t decode_slot(const LoopArgs& a, uint32_t gen,
                                                 uint32_t s) {
     const uint32_t LP = (uint32_t)a.L * (uint32_t)a.P;
     const uint32_t r = s / LP;
-    const uint32_t th = a.theta[(size_t)i * a.S + s];
+    const uint32_t th = a.slot[(size_t)i * a.S + s].theta;
     const int q = (int)(((th + 0x20000000u) >> 30) & 3u);
     if (r < (uint32_t)a.n) {
         const u32x4 w = draw(a.seed, TAG_MEASURE, gen, i, s);
-        const int axis = measure_qutrit(a.qutrit + 6 * ((size_t)i * a.Q + s), w.x);
+        const int axis = measure_qutrit(a.qrec[(size_t)i * a.Q + s].q, w.x);
         return (axis == 0 && q == 2) ? make_desc(KIND_NOT, (int)r, 0) : (uint16_t)0;
     }
     if (q == 0) return 0;
@@ -58,13 +58,18 @@ __device__ __forceinline__ uint16_t decode_slot(const LoopArgs& a, uint32_t gen,
     return make_desc(kind, t, c);
 }
 
-// Segment index of Eq. 10 for circuit k, position pos of instance i.
-__device__ __forceinline__ uint32_t sample_slot(const LoopArgs& a, uint32_t gen, uint32_t i,
-                                                uint32_t k, uint32_t pos) {
-    const u32x4 w = draw(a.seed, TAG_SAMPLE, gen, i, k * (uint32_t)a.L + pos);
+// Segment index of Eq. 10 from the SAMPLE draw of position pos: the
+// individual and the region are drawn, the position is the circuit's own.
+__device__ __forceinline__ uint32_t slot_of_draw(const LoopArgs& a, const u32x4& w, uint32_t pos) {
     const uint32_t ind = scale_u32(w.x, (uint32_t)a.P);
     const uint32_t region = scale_u32(w.y, (uint32_t)(a.n * a.n));
     return region * (uint32_t)a.L * (uint32_t)a.P + ind * (uint32_t)a.L + pos;
+}
+
+// Segment index for circuit k, position pos of instance i.
+__device__ __forceinline__ uint32_t sample_slot(const LoopArgs& a, uint32_t gen, uint32_t i,
+                                                uint32_t k, uint32_t pos) {
+    return slot_of_draw(a, draw(a.seed, TAG_SAMPLE, gen, i, k * (uint32_t)a.L + pos), pos);
 }
 
 // --------------------------------------------------------------------- init
@@ -74,18 +79,24 @@ __global__ void qeqea_init_kernel(LoopArgs a, float amp) {
     if (idx >= total) return;
     const uint32_t i = (uint32_t)(idx / a.S), s = (uint32_t)(idx % a.S);
     const u32x4 w = draw(a.seed, TAG_INIT, GEN_INIT, i, s);
-    a.theta[idx] = w.x;
-    a.best_theta[idx] = w.x;
-    a.best_f[idx] = -1.0f;
-    a.segfit[idx] = -1;
+    SlotRec r;
+    r.theta = w.x;
+    r.best_theta = w.x;
+    r.best_f = -1.0f;
+    r.spare = 0u;
+    r.key = 0ull;
+    r.spare2 = 0ull;
+    a.slot[idx] = r;
     if (s < a.Q) {
-        float* q = a.qutrit + 6 * ((size_t)i * a.Q + s);
-        float* bq = a.best_qutrit + 6 * ((size_t)i * a.Q + s);
+        QutritRec q;
 #pragma unroll
         for (int c = 0; c < 6; ++c) {
-            q[c] = (c & 1) ? 0.0f : amp;
-            bq[c] = q[c];
+            q.q[c] = (c & 1) ? 0.0f : amp;
+            q.bq[c] = q.q[c];
         }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) q.pad[c] = 0.0f;
+        a.qrec[(size_t)i * a.Q + s] = q;
     }
 }
 
@@ -102,8 +113,9 @@ __global__ void inst_best_init_kernel(LoopArgs a) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.I) return;
     a.inst_best_f[i] = -1.0f;
-    a.inst_key[i] = 0ull;
-    a.mutcnt[i] = 0;
+    if (a.mutmask)
+        for (uint32_t w = 0; w < 2 * a.MW; ++w)
+            a.mutmask[((size_t)(w / a.MW) * a.I + i) * a.MW + w % a.MW] = 0u;
     for (int l = 0; l < a.L; ++l) a.inst_best_gates[(size_t)i * a.L + l] = 0;
 }
 
@@ -135,51 +147,67 @@ __global__ void ga_copy_kernel(LoopArgs a, uint64_t gen64, uint16_t* __restrict_
     gates[idx] = a.genomes[gen_of(a, gen64) & 1][idx];
 }
 
-// Mutation decision of individual ind of instance i for this generation
-// (Sec. IV-F: with probability pm; qubit or qutrit mode equiprobably),
-// recorded for the update: a flag per individual and a compacted list of the
-// individuals that mutate.
-__device__ __forceinline__ void decide_mutation(const LoopArgs& a, uint32_t gen, uint32_t i,
-                                                uint32_t ind) {
+// Mutation decision of an individual for this generation (Sec. IV-F: with
+// probability pm; qubit or qutrit mode equiprobably), from its MUT_IND draw.
+__device__ __forceinline__ bool mutates(const LoopArgs& a, uint32_t gen, uint32_t i, uint32_t ind,
+                                        bool* qutrit_mode = nullptr) {
     const u32x4 w = draw(a.seed, TAG_MUT_IND, gen, i, ind);
-    const bool m = (uint64_t)w.x < a.thr_pm;
-    const uint32_t id = i * (uint32_t)a.P + ind;
-    a.mutflag[id] = m ? (uint8_t)(1 + (w.y & 1u)) : (uint8_t)0;
-    if (m) a.mutlist[(size_t)i * a.P + atomicAdd(a.mutcnt + i, 1u)] = ind;
+    if (qutrit_mode) *qutrit_mode = (w.y & 1u) != 0;
+    return (uint64_t)w.x < a.thr_pm;
 }
 
-// Raises the instance's generation-best key (f bits << 32 | ~circuit: the
-// maximum is the largest f, lowest index on ties).  All circuits of an
-// instance target one word, so the atomic is issued only when the current
-// value (possibly stale, which the monotone maximum tolerates) is lower.
-__device__ __forceinline__ void raise_key(unsigned long long* key, float f, uint32_t k) {
-    const unsigned long long v = ((unsigned long long)__float_as_uint(f) << 32) |
-                                 (unsigned long long)(0xFFFFFFFFu - k);
-    const unsigned long long cur = __hip_atomic_load(key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (v > cur) atomicMax(key, v);
+__device__ __forceinline__ uint32_t* mask_of(const LoopArgs& a, uint32_t gen, uint32_t i) {
+    return a.mutmask + ((size_t)(gen & 1u) * a.I + i) * a.MW;
+}
+
+// Records that individual ind mutates in generation gen.
+__device__ __forceinline__ void mark_mutation(const LoopArgs& a, uint32_t gen, uint32_t i, uint32_t ind) {
+    atomicOr(mask_of(a, gen, i) + (ind >> 5), 1u << (ind & 31u));
+}
+
+// Individual ind's share of emptying the mask of the other parity.
+__device__ __forceinline__ void clear_next_mask(const LoopArgs& a, uint32_t gen, uint32_t i, uint32_t ind) {
+    if ((ind & 31u) == 0) mask_of(a, gen + 1u, i)[ind >> 5] = 0u;
 }
 
 // -------------------------------------------- population evaluation (FP32)
-// One circuit per wavefront (register / per-lane layouts) or per workgroup
-// (LDS layout); the target is the circuit's instance target.
+// One circuit per wavefront (register / per-lane layouts, and the LDS layout
+// with W = 1) or per workgroup (LDS layout, W > 1); the target is the
+// circuit's instance target.  With SAMPLE the circuit is first constructed
+// from the encoding (qe_sample) and afterwards every slot it used keeps the
+// largest (fitness, lowest circuit) key.  With
+// `decide` (the internal generation) circuit k also draws the mutation
+// decision of individual k (both run over 0..P-1) and empties its part of the
+// decision mask of the other generation parity.
 template <int NQ, int W, bool SAMPLE>
 __device__ __forceinline__ void eval_circuit(const LoopArgs& a, uint32_t gen, uint32_t ci,
                                              const uint16_t* gates_in, uint32_t* slots_out,
                                              uint16_t* gates_out, float* f_out, bool writer,
-                                             bool decide) {
+                                             bool decide, float2* M, float (*red)[3]) {
     const uint32_t i = ci / (uint32_t)a.P, k = ci % (uint32_t)a.P;
     const int lane = (int)lane_id();
     const int L = a.L;
     const float* T = a.target32 + (size_t)2 * i * ((size_t)1 << (2 * NQ));
+    if (SAMPLE && decide && writer && lane == 0) clear_next_mask(a, gen, i, k);
     constexpr int KEEP = 4;                 // chunks of 64 slots kept for the scatter
     uint32_t kept[KEEP];
 #pragma unroll
     for (int c = 0; c < KEEP; ++c) kept[c] = 0xFFFFFFFFu;
     auto src = [&](int ch) -> uint32_t {
         const int p = ch * 64 + lane;
-        if (p >= L) return 0u;
-        if (!SAMPLE) return (uint32_t)gates_in[(size_t)ci * L + p];
-        const uint32_t s = sample_slot(a, gen, i, k, (uint32_t)p);
+        if (!SAMPLE) return p < L ? (uint32_t)gates_in[(size_t)ci * L + p] : 0u;
+        const bool pos = p < L;
+        const bool dec = decide && writer && p == L;
+        if (!pos && !dec) return 0u;
+        // one Philox pass: position lanes draw their entry's individual and
+        // region, lane L the mutation decision of individual k
+        const u32x4 w = draw(a.seed, pos ? (uint32_t)TAG_SAMPLE : (uint32_t)TAG_MUT_IND, gen, i,
+                             pos ? k * (uint32_t)L + (uint32_t)p : k);
+        if (!pos) {
+            if ((uint64_t)w.x < a.thr_pm) mark_mutation(a, gen, i, k);
+            return 0u;
+        }
+        const uint32_t s = slot_of_draw(a, w, (uint32_t)p);
 #pragma unroll
         for (int c = 0; c < KEEP; ++c)
             if (c == ch) kept[c] = s;
@@ -197,33 +225,11 @@ __device__ __forceinline__ void eval_circuit(const LoopArgs& a, uint32_t gen, ui
         ok = run_width<NQ, false>(NQ, T, L, src, nullptr, &o);
         fv = o.f;
     } else {
-        constexpr int N = 1 << NQ, CW = N / W;
-        __shared__ float2 M[N * N];
-        __shared__ float red[W][3];
-        float off;
+        constexpr int N = 1 << NQ;
+        float off, gd, dd;
         float2 dg;
-        const int wave = (int)(threadIdx.x >> 6);
-        ok = run_lds_path<NQ, W, false>(M, T, L, src, &off, &dg);
-        const float offw = wave_sum(off), trw = wave_sum(dg.x), tiw = wave_sum(dg.y);
-        if (lane == 0) { red[wave][0] = offw; red[wave][1] = trw; red[wave][2] = tiw; }
-        __syncthreads();
-        float offs = 0.0f, tr = 0.0f, ti = 0.0f;
-#pragma unroll
-        for (int w = 0; w < W; ++w) { offs += red[w][0]; tr += red[w][1]; ti += red[w][2]; }
-        const float am = sqrtf(tr * tr + ti * ti);
-        float er = 1.0f, ei = 0.0f;
-        if (am > 0.0f) { er = tr / am; ei = ti / am; }
-        float dl = 0.0f;
-        if (lane < CW) { const float xr = dg.x - er, xi = dg.y - ei; dl = xr * xr + xi * xi; }
-        const float dw = wave_sum(dl);
-        __syncthreads();
-        if (lane == 0) red[wave][0] = dw;
-        __syncthreads();
-        float D = 0.0f;
-#pragma unroll
-        for (int w = 0; w < W; ++w) D += red[w][0];
-        const float q = fminf(fmaxf(0.5f * (offs + D) / (float)N, 0.0f), 1.0f);
-        fv = 1.0f - sqrtf(q);
+        ok = run_lds_path<NQ, W, false>(M, T, L, src, &off, &dg, W == 1 ? 0 : -1);
+        fv = group_fitness<W>(off, dg, red, N, &gd, &dd);
     }
     if (!ok) fv = __builtin_nanf("");
     if (writer && lane == 0) {
@@ -231,24 +237,22 @@ __device__ __forceinline__ void eval_circuit(const LoopArgs& a, uint32_t gen, ui
         if (!ok) atomicOr(a.err, (uint32_t)QE_DEVERR_DESC);
         else if (!(fv == fv)) atomicOr(a.err, (uint32_t)QE_DEVERR_NUMERIC);
     }
-    // segment fitness: every slot this circuit used keeps the largest
-    // fitness; the instance keeps its best circuit of the generation
+    // segment fitness: every slot this circuit used keeps the largest key
     if (SAMPLE && writer && fv >= 0.0f) {
-        const int32_t fb = (int32_t)__float_as_uint(fv);
+        const unsigned long long key = seg_key(fv, k);
 #pragma unroll
         for (int c = 0; c < KEEP; ++c) {
             const int p = c * 64 + lane;
-            if (p < L) atomicMax(a.segfit + (size_t)i * a.S + kept[c], fb);
+            if (p < L) atomicMax(&a.slot[(size_t)i * a.S + kept[c]].key, key);
         }
         for (int p = KEEP * 64 + lane; p < L; p += 64) {
             const uint32_t s = sample_slot(a, gen, i, k, (uint32_t)p);
-            atomicMax(a.segfit + (size_t)i * a.S + s, fb);
+            atomicMax(&a.slot[(size_t)i * a.S + s].key, key);
         }
-        if (lane == 0) raise_key(a.inst_key + i, fv, k);
     }
-    // circuit k of the instance also draws the mutation decision of
-    // individual k (both run over 0..P-1)
-    if (SAMPLE && decide && writer && lane == 0) decide_mutation(a, gen, i, k);
+    // a circuit length that fills whole wavefronts leaves no spare lane
+    if (SAMPLE && decide && writer && (L & 63) == 0 && lane == 0 && mutates(a, gen, i, k))
+        mark_mutation(a, gen, i, k);
 }
 
 template <int NQ, int W, bool SAMPLE>
@@ -262,16 +266,26 @@ __global__ __launch_bounds__(256) void population_kernel(LoopArgs a, uint64_t ge
     if constexpr (W == 0) {
         const uint32_t ci = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
         if (ci >= total) return;
-        eval_circuit<NQ, 0, SAMPLE>(a, gen, ci, gates_in, slots_out, gates_out, f_out, true, decide);
+        eval_circuit<NQ, 0, SAMPLE>(a, gen, ci, gates_in, slots_out, gates_out, f_out, true, decide,
+                                    nullptr, nullptr);
     } else {
-        const uint32_t ci = blockIdx.x;
+        // W = 1: four circuits per workgroup, one per wavefront (no barrier
+        // is shared, so a wavefront past the end may leave); W > 1: one
+        // circuit per workgroup of W wavefronts
+        constexpr int N = 1 << NQ, CPB = W == 1 ? 4 : 1;
+        __shared__ float2 M[CPB][N * N];
+        __shared__ float red[4][3];
+        const int wave = (int)(threadIdx.x >> 6);
+        const uint32_t ci = W == 1 ? blockIdx.x * CPB + (uint32_t)wave : blockIdx.x;
         if (ci >= total) return;
         eval_circuit<NQ, W, SAMPLE>(a, gen, ci, gates_in, slots_out, gates_out, f_out,
-                                    threadIdx.x < 64, decide);
+                                    W == 1 || threadIdx.x < 64, decide, M[W == 1 ? wave : 0], red);
     }
 }
 
 // -------------------------------------------------------------- scatter-max
+// Segment fitness for the step-by-step path (qe_update): every entry raises
+// its slot's key to its circuit's (fitness, index).
 __global__ void scatter_kernel(LoopArgs a, const uint32_t* __restrict__ slots,
                                const float* __restrict__ f) {
     const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -281,9 +295,7 @@ __global__ void scatter_kernel(LoopArgs a, const uint32_t* __restrict__ slots,
     const float fv = f[idx / a.L];
     const uint32_t s = slots[idx];
     if (!(fv >= 0.0f) || s >= a.S) return;
-    atomicMax(a.segfit + (size_t)i * a.S + s, (int32_t)__float_as_uint(fv));
-    const uint32_t k = (uint32_t)((idx / a.L) % a.P);
-    if (idx % a.L == 0) raise_key(a.inst_key + i, fv, k);
+    atomicMax(&a.slot[(size_t)i * a.S + s].key, seg_key(fv, (uint32_t)((idx / a.L) % a.P)));
 }
 
 // Mutation decisions for the step-by-step path (qe_update): one thread per
@@ -291,37 +303,17 @@ __global__ void scatter_kernel(LoopArgs a, const uint32_t* __restrict__ slots,
 __global__ void mutation_decision_kernel(LoopArgs a, uint64_t gen64) {
     const uint32_t id = blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= (uint32_t)a.I * (uint32_t)a.P) return;
-    decide_mutation(a, gen_of(a, gen64), id / (uint32_t)a.P, id % (uint32_t)a.P);
+    const uint32_t gen = gen_of(a, gen64), i = id / (uint32_t)a.P, ind = id % (uint32_t)a.P;
+    clear_next_mask(a, gen, i, ind);
+    if (mutates(a, gen, i, ind)) mark_mutation(a, gen, i, ind);
+}
+
+__global__ void mutmask_clear_kernel(LoopArgs a) {
+    const size_t w = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (w < (size_t)2 * a.I * a.MW) a.mutmask[w] = 0u;
 }
 
 // ------------------------------------------------------------------- update
-__device__ __forceinline__ bool mutated(const LoopArgs& a, uint32_t gen, uint32_t i, uint32_t ind,
-                                        bool* qutrit_mode) {
-    const u32x4 w = draw(a.seed, TAG_MUT_IND, gen, i, ind);
-    *qutrit_mode = (w.y & 1u) != 0;
-    return (uint64_t)w.x < a.thr_pm;
-}
-
-// Elitism for a used slot whose segment fitness is v.
-__device__ __forceinline__ void elitism(const LoopArgs& a, uint32_t i, uint32_t s, float v) {
-    const size_t o = (size_t)i * a.S + s;
-    const bool rot = s < a.Q;
-    float* q = a.qutrit + 6 * ((size_t)i * a.Q + s);
-    float* bq = a.best_qutrit + 6 * ((size_t)i * a.Q + s);
-    if (v > a.best_f[o]) {
-        a.best_f[o] = v;
-        a.best_theta[o] = a.theta[o];
-        if (rot)
-#pragma unroll
-            for (int c = 0; c < 6; ++c) bq[c] = q[c];
-    } else {
-        a.theta[o] = a.best_theta[o];
-        if (rot)
-#pragma unroll
-            for (int c = 0; c < 6; ++c) q[c] = bq[c];
-    }
-}
-
 // One SU(3) step (Eq. 12 with parameter j alone, value a*domain/4096).
 __device__ __forceinline__ void su3_step(float* q, int j, int ai, const float* tab) {
     const float x0 = q[0], y0 = q[1], x1 = q[2], y1 = q[3], x2 = q[4], y2 = q[5];
@@ -348,112 +340,242 @@ __device__ __forceinline__ void su3_step(float* q, int j, int ai, const float* t
     }
 }
 
-__device__ __forceinline__ void mutate_slot(const LoopArgs& a, uint32_t gen, uint32_t i,
-                                            uint32_t s, bool qutrit_mode) {
-    const size_t o = (size_t)i * a.S + s;
-    const float bf = a.best_f[o];
-    const float seg = bf < 0.0f ? 0.0f : bf;
+// Amplitudes of a qutrit record (the first 48 of its 64 bytes).
+struct QState {
+    float q[6], bq[6];
+};
+
+__device__ __forceinline__ QState load_qstate(const QutritRec* r) {
+    const float4* p = reinterpret_cast<const float4*>(r);
+    const float4 x = p[0], y = p[1], z = p[2];
+    return QState{{x.x, x.y, x.z, x.w, y.x, y.y}, {y.z, y.w, z.x, z.y, z.z, z.w}};
+}
+
+__device__ __forceinline__ void store_qstate(QutritRec* r, const QState& s) {
+    float4* p = reinterpret_cast<float4*>(r);
+    p[0] = make_float4(s.q[0], s.q[1], s.q[2], s.q[3]);
+    p[1] = make_float4(s.q[4], s.q[5], s.bq[0], s.bq[1]);
+    p[2] = make_float4(s.bq[2], s.bq[3], s.bq[4], s.bq[5]);
+}
+
+// Elitism (Sec. IV-E.1) of a used slot whose segment fitness is v: strictly
+// better -> the state becomes the best, otherwise the best state is restored.
+// Returns whether the best copy changed.
+__device__ __forceinline__ bool elitism(float v, SlotRec& r, QState& q, bool rot) {
+    if (v > r.best_f) {
+        r.best_f = v;
+        r.best_theta = r.theta;
+        if (rot)
+#pragma unroll
+            for (int c = 0; c < 6; ++c) q.bq[c] = q.q[c];
+        return true;
+    }
+    r.theta = r.best_theta;
+    if (rot)
+#pragma unroll
+        for (int c = 0; c < 6; ++c) q.q[c] = q.bq[c];
+    return false;
+}
+
+// Mutation of one slot (Sec. IV-F) with its own draw; segFit is the slot's
+// best fitness (0 if never used).  Qubit mode: theta +- floor((1 - segFit) *
+// range); qutrit mode: one SU(3) parameter step.
+__device__ __forceinline__ void mutate_state(const LoopArgs& a, uint32_t gen, uint32_t i, uint32_t s,
+                                             bool qutrit_mode, SlotRec& r, QState& q) {
+    const float seg = r.best_f < 0.0f ? 0.0f : r.best_f;
     const float om = 1.0f - seg;
     const u32x4 w = draw(a.seed, TAG_MUT_SLOT, gen, i, s);
     if (!qutrit_mode) {
         const uint32_t d = (uint32_t)floorf(om * a.r32);
-        a.theta[o] = (w.x & 1u) ? a.theta[o] - d : a.theta[o] + d;
+        r.theta = (w.x & 1u) ? r.theta - d : r.theta + d;
     } else {
         const int j = (int)scale_u32(w.y, 8u);
         const float u = (float)(w.z >> 8) * 0x1p-24f;
         const float x = u * om;
         const int ai = (int)floorf(x * 4096.0f);
-        su3_step(a.qutrit + 6 * ((size_t)i * a.Q + s), j, ai, a.su3_tab);
+        su3_step(q.q, j, ai, a.su3_tab);
     }
 }
 
-// Part A: used slots of individuals that do not mutate (one thread per
-// (circuit, position) entry; several entries may name the same slot, so
-// atomicExch claims each slot exactly once and resets its segment fitness).
-// Part B: slots of the individuals that mutate (from the compacted list; one
-// thread per slot, since the individual's slots belong to nobody else): the
-// slot passes elitism if it was used, then mutates (qubit mode: every slot;
-// qutrit mode: rotation slots).  Part C: the instance's best circuit of the
-// generation (packed key set by the fitness kernel) updates its best
-// circuit ever.  The last workgroup to finish resets the list.
+// Part C: the instance's best circuit of the generation (largest f, lowest
+// index; NaN never counts) updates its best circuit ever.  Part A: used slots
+// of individuals that do not mutate, one thread per (circuit, position)
+// entry; an entry handles its slot only if its circuit holds the slot's key.
+// Part B: every slot of the individuals that mutate
+// (one thread per slot, since the individual's slots belong to nobody else):
+// elitism if the slot was used, then mutation (qubit mode: every slot;
+// qutrit mode: rotation slots).  Part C comes first in the grid so that its
+// serial scan starts at once.
 constexpr int UPD_BLOCK = 256;
+constexpr int UPD_MAX_P = 16384;          // part B's list of mutated individuals lives in LDS
 
-__device__ __forceinline__ void update_part_a(const LoopArgs& a, uint32_t idx,
+__device__ __forceinline__ void update_part_a(const LoopArgs& a, uint32_t gen, uint32_t idx,
                                               const uint32_t* __restrict__ slots) {
     const uint32_t L = (uint32_t)a.L, LP = L * (uint32_t)a.P;
     if (idx >= (uint32_t)a.I * LP) return;
-    const uint32_t i = idx / LP;
+    const uint32_t i = idx / LP, k = (idx % LP) / L;
     const uint32_t s = slots[idx];
     if (s >= a.S) return;
     const uint32_t ind = (s % LP) / L;
-    if (a.mutflag[i * (uint32_t)a.P + ind]) return;
-    const int32_t v = atomicExch(a.segfit + (size_t)i * a.S + s, -1);
-    if (v >= 0) elitism(a, i, s, __int_as_float(v));
+    const size_t o = (size_t)i * a.S + s, oq = (size_t)i * a.Q + s;
+    const bool rot = s < a.Q;
+    SlotRec r = a.slot[o];
+    QState q{};
+    if (rot) q = load_qstate(a.qrec + oq);      // issued before ownership is known
+    // the entry owns the slot if its circuit holds the slot's key (a circuit
+    // uses a slot at most once: the slot fixes the position)
+    if (r.key == 0ull || (uint32_t)r.key != 0xFFFFFFFFu - k) return;
+    if (mutates(a, gen, i, ind)) return;
+    const float v = __uint_as_float((uint32_t)(r.key >> 32));
+    r.key = 0ull;
+    elitism(v, r, q, rot);
+    a.slot[o] = r;
+    if (rot) store_qstate(a.qrec + oq, q);
 }
 
-// Workgroup b of part B serves instance b / per_inst and walks that
-// instance's (mutated individual, slot chunk) items with stride per_inst.
+// Workgroup b of part B serves instance b / per_inst: it lists the
+// instance's mutated individuals in LDS from the decision mask, then walks
+// the (individual, slot chunk) items with stride per_inst.
 __device__ __forceinline__ void update_part_b(const LoopArgs& a, uint32_t gen, uint32_t b,
                                               uint32_t per_inst) {
+    extern __shared__ uint16_t list[];        // P entries (launch-time size)
+    __shared__ uint32_t total;
     const uint32_t L = (uint32_t)a.L, P = (uint32_t)a.P, LP = L * P;
     const uint32_t per = (uint32_t)(a.n * a.n) * L;           // slots of one individual
     const uint32_t chunks = (per + UPD_BLOCK - 1) / UPD_BLOCK;
     const uint32_t i = b / per_inst;
     if (i >= (uint32_t)a.I) return;
-    const uint32_t count = a.mutcnt[i];
+    if (threadIdx.x < 64) {
+        // wave 0: prefix count over the mask words, 64 at a time
+        const uint32_t* mask = mask_of(a, gen, i);
+        const int lane = (int)threadIdx.x;
+        uint32_t base = 0;
+        for (uint32_t w0 = 0; w0 < a.MW; w0 += 64) {
+            const uint32_t w = w0 + (uint32_t)lane;
+            uint32_t bits = w < a.MW ? mask[w] : 0u;
+            if (w == a.MW - 1 && (P & 31u)) bits &= (1u << (P & 31u)) - 1u;
+            const uint32_t c = (uint32_t)__popc(bits);
+            uint32_t incl = c;                  // inclusive scan over the wave
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const uint32_t o = (uint32_t)__shfl_up((int)incl, d, 64);
+                if (lane >= d) incl += o;
+            }
+            uint32_t pos = base + incl - c;
+            while (bits) {
+                const int bit = __ffs(bits) - 1;
+                list[pos++] = (uint16_t)(w * 32u + (uint32_t)bit);
+                bits &= bits - 1u;
+            }
+            base += (uint32_t)__shfl((int)incl, 63, 64);
+        }
+        if (lane == 0) total = base;
+    }
+    __syncthreads();
+    const uint32_t count = total;
     for (uint32_t t = b % per_inst; t < count * chunks; t += per_inst) {
-        const uint32_t ind = a.mutlist[(size_t)i * P + t / chunks];
+        const uint32_t ind = list[t / chunks];
         const uint32_t e = (t % chunks) * UPD_BLOCK + threadIdx.x;
         if (e >= per) continue;
-        const bool qm = a.mutflag[i * P + ind] == 2;
-        const uint32_t r = e / L, pos = e - r * L;
-        const uint32_t s = r * LP + ind * L + pos;
-        int32_t* sf = a.segfit + (size_t)i * a.S + s;
-        const int32_t v = *sf;
-        if (v >= 0) {
-            *sf = -1;
-            elitism(a, i, s, __int_as_float(v));
-        }
-        if (!qm || r < (uint32_t)a.n) mutate_slot(a, gen, i, s, qm);
+        const uint32_t r_ = e / L, pos = e - r_ * L;
+        const uint32_t s = r_ * LP + ind * L + pos;
+        const size_t o = (size_t)i * a.S + s, oq = (size_t)i * a.Q + s;
+        const bool rot = r_ < (uint32_t)a.n;
+        SlotRec r = a.slot[o];
+        QState q{};
+        if (rot) q = load_qstate(a.qrec + oq);
+        bool qm;
+        mutates(a, gen, i, ind, &qm);
+        const bool used = r.key != 0ull;
+        if (used) elitism(__uint_as_float((uint32_t)(r.key >> 32)), r, q, rot);
+        r.key = 0ull;
+        if (!qm || rot) mutate_state(a, gen, i, s, qm, r, q);
+        a.slot[o] = r;
+        if (rot && (used || qm)) store_qstate(a.qrec + oq, q);
     }
 }
 
-__device__ __forceinline__ void update_part_c(const LoopArgs& a, uint32_t i,
-                                              const uint16_t* __restrict__ gates) {
-    if (i >= (uint32_t)a.I) return;
+// Wavefronts per instance in part C: each lane scans at most 16 fitness
+// values per pass (P <= 1024: 1, P <= 2048: 2, else 4).
+__host__ __device__ inline int part_c_waves(int P) { return P > 2048 ? 4 : (P > 1024 ? 2 : 1); }
+
+__device__ __forceinline__ void update_part_c(const LoopArgs& a, uint32_t b,
+                                              const uint16_t* __restrict__ gates,
+                                              const float* __restrict__ f) {
+    __shared__ float cbest[4];
+    __shared__ uint32_t cidx[4];
     const uint32_t L = (uint32_t)a.L, P = (uint32_t)a.P;
-    const int lane = (int)lane_id();
-    unsigned long long key = 0;
-    if (lane == 0) key = atomicExch(a.inst_key + i, 0ull);
-    key = __shfl(key, 0, 64);
-    if (key == 0) return;
-    const float best = __uint_as_float((uint32_t)(key >> 32));
-    const uint32_t k = 0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFu);
-    if (best > a.inst_best_f[i]) {
-        const uint16_t* src = gates + ((size_t)i * P + k) * L;
-        for (uint32_t l = lane; l < L; l += 64) a.inst_best_gates[(size_t)i * L + l] = src[l];
-        if (lane == 0) a.inst_best_f[i] = best;
+    const int cw = part_c_waves(a.P);
+    const int lane = (int)lane_id(), wave = (int)(threadIdx.x >> 6), sub = wave % cw;
+    const uint32_t i = b * (uint32_t)(4 / cw) + (uint32_t)(wave / cw);
+    float best = -1.0f;
+    uint32_t bk = 0xFFFFFFFFu;
+    if (i < (uint32_t)a.I) {
+        const float* fi = f + (size_t)i * P;
+        const uint32_t step = 64u * (uint32_t)cw;
+        for (uint32_t k0 = (uint32_t)(sub * 64 + lane); k0 < P; k0 += 16 * step) {
+            float v[16];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const uint32_t k = k0 + (uint32_t)j * step;
+                v[j] = k < P ? fi[k] : -1.0f;
+            }
+#pragma unroll
+            for (int j = 0; j < 16; ++j)
+                if (v[j] > best) { best = v[j]; bk = k0 + (uint32_t)j * step; }
+        }
     }
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        const float ob = __shfl_xor(best, m, 64);
+        const uint32_t ok = (uint32_t)__shfl_xor((int)bk, m, 64);
+        if (ob > best || (ob == best && ok < bk)) { best = ob; bk = ok; }
+    }
+    if (cw > 1) {
+        if (lane == 0) { cbest[wave] = best; cidx[wave] = bk; }
+        __syncthreads();
+        if (sub != 0) return;
+        for (int w = 1; w < cw; ++w) {
+            const float ob = cbest[wave + w];
+            const uint32_t ok = cidx[wave + w];
+            if (ob > best || (ob == best && ok < bk)) { best = ob; bk = ok; }
+        }
+    }
+    if (i >= (uint32_t)a.I || bk == 0xFFFFFFFFu || !(best > a.inst_best_f[i])) return;
+    const uint16_t* src = gates + ((size_t)i * P + bk) * L;
+    for (uint32_t l = lane; l < L; l += 64) a.inst_best_gates[(size_t)i * L + l] = src[l];
+    if (lane == 0) a.inst_best_f[i] = best;
 }
 
 __global__ __launch_bounds__(UPD_BLOCK) void qeqea_update_kernel(LoopArgs a, uint64_t gen64,
                                                                  const uint32_t* __restrict__ slots,
                                                                  const uint16_t* __restrict__ gates,
-                                                                 uint32_t nA, uint32_t nB,
+                                                                 const float* __restrict__ f,
+                                                                 uint32_t nC, uint32_t nA,
                                                                  uint32_t per_inst) {
     const uint32_t gen = gen_of(a, gen64);
-    if (blockIdx.x < nA)
-        update_part_a(a, blockIdx.x * UPD_BLOCK + threadIdx.x, slots);
-    else if (blockIdx.x < nA + nB)
-        update_part_b(a, gen, blockIdx.x - nA, per_inst);
+    if (blockIdx.x < nC)
+        update_part_c(a, blockIdx.x, gates, f);
+    else if (blockIdx.x < nC + nA)
+        update_part_a(a, gen, (blockIdx.x - nC) * UPD_BLOCK + threadIdx.x, slots);
     else
-        update_part_c(a, (blockIdx.x - nA - nB) * (UPD_BLOCK / 64) + (threadIdx.x >> 6), gates);
+        update_part_b(a, gen, blockIdx.x - nC - nA, per_inst);
 }
 
-// The mutation lists were consumed: empty them for the next generation.
-__global__ void mutlist_reset_kernel(LoopArgs a) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < (uint32_t)a.I) a.mutcnt[i] = 0;
+// Dense copy of one field of the encoding state.
+__global__ void state_gather_kernel(LoopArgs a, int which, void* __restrict__ dst) {
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (which == 0 || which == 2 || which == 3) {
+        if (idx >= (size_t)a.I * a.S) return;
+        const SlotRec r = a.slot[idx];
+        if (which == 0) static_cast<uint32_t*>(dst)[idx] = r.theta;
+        else if (which == 2) static_cast<float*>(dst)[idx] = r.best_f;
+        else static_cast<uint32_t*>(dst)[idx] = r.best_theta;
+    } else {
+        if (idx >= (size_t)a.I * a.Q * 6) return;
+        const QutritRec& q = a.qrec[idx / 6];
+        static_cast<float*>(dst)[idx] = which == 1 ? q.q[idx % 6] : q.bq[idx % 6];
+    }
 }
 
 // ----------------------------------------------------------------------- GA
@@ -658,7 +780,7 @@ static void launch_population(const LoopArgs& a, uint64_t gen, const uint16_t* g
     const unsigned wb = blocks(total, 4);
     if (lds && a.n >= 4) {
         switch (a.n) {
-            case 4: population_kernel<4, 1, SAMPLE><<<total, 64, 0, s>>>(a, gen, gin, sout, gout, f, decide); break;
+            case 4: population_kernel<4, 1, SAMPLE><<<wb, 256, 0, s>>>(a, gen, gin, sout, gout, f, decide); break;
             case 5: population_kernel<5, 2, SAMPLE><<<total, 128, 0, s>>>(a, gen, gin, sout, gout, f, decide); break;
             default: population_kernel<6, 4, SAMPLE><<<total, 256, 0, s>>>(a, gen, gin, sout, gout, f, decide); break;
         }
@@ -709,7 +831,8 @@ hipError_t launch_scatter(const LoopArgs& a, uint64_t gen, const uint32_t* slots
 
 hipError_t launch_qeqea_update(const LoopArgs& a, uint64_t gen, const uint32_t* slots,
                                const uint16_t* gates, const float* f, hipStream_t s) {
-    (void)f;   // the fitness reached the update through segfit and inst_key
+    if (a.P > UPD_MAX_P) return hipErrorInvalidValue;
+    const uint32_t nC = blocks((size_t)a.I * part_c_waves(a.P), UPD_BLOCK / 64);
     const uint32_t nA = blocks((size_t)a.I * a.P * a.L, UPD_BLOCK);
     // part B: per instance, enough workgroups for the expected number of
     // (mutated individual, slot chunk) items (more items loop)
@@ -718,9 +841,20 @@ hipError_t launch_qeqea_update(const LoopArgs& a, uint64_t gen, const uint32_t* 
     const uint32_t per_inst = (uint32_t)std::max<double>(
         1.0, std::min<double>(1.5 * expect + 8.0, (double)a.P * chunks));
     const uint32_t nB = per_inst * (uint32_t)a.I;
-    const uint32_t nC = blocks((size_t)a.I, UPD_BLOCK / 64);
-    qeqea_update_kernel<<<nA + nB + nC, UPD_BLOCK, 0, s>>>(a, gen, slots, gates, nA, nB, per_inst);
-    mutlist_reset_kernel<<<blocks((size_t)a.I, 256), 256, 0, s>>>(a);
+    const size_t lds = ((size_t)a.P * sizeof(uint16_t) + 15) & ~(size_t)15;
+    qeqea_update_kernel<<<nC + nA + nB, UPD_BLOCK, lds, s>>>(a, gen, slots, gates, f, nC, nA, per_inst);
+    return hipGetLastError();
+}
+
+hipError_t launch_mutmask_clear(const LoopArgs& a, hipStream_t s) {
+    const size_t n = (size_t)2 * a.I * a.MW;
+    if (n) mutmask_clear_kernel<<<blocks(n, 256), 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_state_gather(const LoopArgs& a, int which, void* dst, hipStream_t s) {
+    const size_t n = (which == 1 || which == 4) ? (size_t)a.I * a.Q * 6 : (size_t)a.I * a.S;
+    if (n) state_gather_kernel<<<blocks(n, 256), 256, 0, s>>>(a, which, dst);
     return hipGetLastError();
 }
 

@@ -45,7 +45,6 @@ class Problem(ctypes.Structure):
 
 
 _lib = None
-_hip = None
 
 
 def header_functions():
@@ -84,7 +83,7 @@ def load():
         "qe_get_best": [vp, i32, vp, P(ctypes.c_float), P(ctypes.c_double)],
         "qe_checkpoint": [vp, vp, P(ctypes.c_size_t)],
         "qe_restore": [vp, vp, ctypes.c_size_t],
-        "qe_state_view": [vp, i32, P(vp), P(i64)],
+        "qe_state_read": [vp, i32, vp, P(i64), vp],
         "qe_lib_table": [i32, i32, vp],
         "qe_set_schedule": [i32, i32],
         "qe_get_schedule": [i32, P(i32)],
@@ -106,15 +105,6 @@ def _call(name, *args):
     if st != QE_OK:
         raise QeError(name, st, load().qe_last_error().decode())
     return st
-
-
-def _hiprt():
-    global _hip
-    if _hip is None:
-        _hip = ctypes.CDLL("libamdhip64.so")
-        _hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
-        _hip.hipMemcpy.restype = ctypes.c_int
-    return _hip
 
 
 def _stream(stream):
@@ -355,16 +345,12 @@ class Context:
               "best_theta": (3, torch.int32), "best_qutrit": (4, torch.float32),
               "genomes0": (5, torch.int16), "genomes1": (6, torch.int16)}
 
-    def state(self, name):
-        """A device copy of a piece of the ctx-owned state."""
+    def state(self, name, stream=None):
+        """A device copy of one field of the ctx-owned state."""
         which, dtype = self._VIEWS[name]
-        p = ctypes.c_void_p(0)
         n = ctypes.c_int64(0)
-        _call("qe_state_view", self.handle, which, ctypes.byref(p), ctypes.byref(n))
+        _call("qe_state_read", self.handle, which, None, ctypes.byref(n), None)
         out = torch.empty(n.value, dtype=dtype, device=torch.device("cuda", torch.cuda.current_device()))
         if n.value:
-            torch.cuda.synchronize()
-            rc = _hiprt().hipMemcpy(ctypes.c_void_p(out.data_ptr()), p, out.numel() * out.element_size(), 3)
-            if rc != 0:
-                raise RuntimeError(f"hipMemcpy failed ({rc})")
+            _call("qe_state_read", self.handle, which, _ptr(out), ctypes.byref(n), _stream(stream))
         return out
