@@ -33,6 +33,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "circuit-fitness evals/sec (n=4..6), FP32 vs BF16-MFMA at stated fitness error"
 FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X, 256 CUs x 4 SIMD x 16 lanes x 2 x 2 (packed) x 2.4 GHz
+LDS_PEAK_GBPS = 256 * 128 * 2.4   # MI355X LDS: 256 CUs x 128 B/clock x 2.4 GHz = 78643 GB/s
 
 
 def log(msg):
@@ -63,6 +64,22 @@ def algorithmic_flops(gates, n):
     per_kind[5] = 4.0 * NN
     per_kind[6] = 2.0 * NN
     return float(per_kind[kinds].sum() + kinds.shape[0] * 4.0 * NN)
+
+
+def algorithmic_lds_bytes(gates, n):
+    """LDS bytes the per-gate method must move for these circuits (N = 2^n):
+    every complex64 entry a gate changes is read and written once (16 B);
+    CV, CV+ and T change N^2/2 entries, H all N^2, NOT / CNOT / I none (a
+    row relabelling); plus one pass writing T^dagger and one reading the
+    result for the fitness (8 B per entry each)."""
+    import numpy as np
+    NN = float(1 << (2 * n))
+    kinds = np.asarray(gates).astype(np.int64) & 15
+    per_kind = np.zeros(16)
+    per_kind[3] = per_kind[4] = per_kind[6] = 8.0 * NN
+    per_kind[5] = 16.0 * NN
+    circuits = kinds.shape[0] if kinds.ndim > 1 else 1
+    return float(per_kind[kinds].sum() + circuits * 16.0 * NN)
 
 
 def traffic_from_profiles(kernel_key, src_hash):
@@ -220,11 +237,13 @@ def main():
                          "of known traffic that scales the FETCH_SIZE / WRITE_SIZE counters)")
     ap.add_argument("--no-secondary", action="store_true",
                     help="skip the n=6 precision study, the n=5 QEQEA loop and the uneven batch")
+    ap.add_argument("--secondary", default="precision,qeqea_n5,uneven",
+                    help="comma list of the secondary workloads to run (precision, qeqea_n5, uneven)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: the hot path of this build runs on a single MI355X "
-              "(independent populations would shard across GPUs with no exchange; see the "
-              "design notes).  Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU: the hot path runs on a single MI355X (independent "
+              "populations would shard across GPUs with no exchange).  Run with --gpus 1.",
+              file=sys.stderr)
         sys.exit(2)
     K, W = args.steps, args.warmup
     if K < 1 or W < 1:
@@ -281,24 +300,30 @@ def main():
     fk = torch.empty(I * P, dtype=torch.float32, device=dev)
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
            for _ in range(R)]
-    flops = 0.0
+    flops = lds_bytes = 0.0
     for r in range(R):
         evs[r][0].record()
         ctx.sample_eval(W + K + r, slots, gates, fk)
         evs[r][1].record()
         if r == R - 1:
             torch.cuda.synchronize()
-            flops = algorithmic_flops(gates.cpu().numpy(), n)
+            gh = gates.cpu().numpy()
+            flops = algorithmic_flops(gh, n)
+            lds_bytes = algorithmic_lds_bytes(gh, n)
     torch.cuda.synchronize()
     kern_ms = sum(a.elapsed_time(b) for a, b in evs) / R
-    achieved = flops / (kern_ms / 1e3) / 1e12
+    achieved = lds_bytes / (kern_ms / 1e3) / 1e9
+    alu = flops / (kern_ms / 1e3) / 1e12
     src = source_hash()
-    roofline = {"bound": "alu", "achieved": round(achieved, 4), "peak": FP32_VECTOR_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 6),
+    roofline = {"bound": "lds", "achieved": round(achieved, 2), "peak": round(LDS_PEAK_GBPS, 1),
+                "unit": "GB/s", "frac": round(achieved / LDS_PEAK_GBPS, 6),
                 "traffic": traffic_from_profiles("qeqea_fused_n4", src),
                 "kernel": "population_kernel<4,1,true> (sampling + Eq. 11 fitness + segment max, LDS-staged)",
-                "kernel_ms": round(kern_ms, 6), "algorithmic_flops_per_launch": flops}
-    log(f"dominant kernel: {kern_ms * 1e3:.2f} us/launch, {achieved:.3f} TFLOP/s algorithmic")
+                "kernel_ms": round(kern_ms, 6), "algorithmic_lds_bytes_per_launch": lds_bytes,
+                "algorithmic_flops_per_launch": flops, "alu_tflops": round(alu, 4),
+                "alu_frac": round(alu / FP32_VECTOR_PEAK_TFLOPS, 6)}
+    log(f"dominant kernel: {kern_ms * 1e3:.2f} us/launch, {achieved:.1f} GB/s algorithmic LDS "
+        f"({achieved / LDS_PEAK_GBPS:.3f} of peak), {alu:.3f} TFLOP/s")
 
     if args.pmc_calibration_mb > 0:
         nb = args.pmc_calibration_mb << 20
@@ -309,13 +334,21 @@ def main():
         log(f"calibration copy: {args.pmc_calibration_mb} MiB read + {args.pmc_calibration_mb} MiB written")
 
     secondary = None
-    if not args.no_secondary:
-        log("secondary: n=6 precision study (FP32 vs bf16/fp16 MFMA)")
-        secondary = {"precision_n6": secondary_precision(dev)}
-        log("secondary: n=5 QEQEA, 1024 populations")
-        secondary["qeqea_n5"] = secondary_qeqea_n5(dev)
-        log("secondary: uneven batch")
-        secondary["uneven"] = secondary_uneven(dev)
+    which = set() if args.no_secondary else {s.strip() for s in args.secondary.split(",") if s.strip()}
+    unknown = which - {"precision", "qeqea_n5", "uneven"}
+    if unknown:
+        ap.error(f"unknown secondary workloads: {sorted(unknown)}")
+    if which:
+        secondary = {}
+        if "precision" in which:
+            log("secondary: n=6 precision study (FP32 vs bf16/fp16 MFMA)")
+            secondary["precision_n6"] = secondary_precision(dev)
+        if "qeqea_n5" in which:
+            log("secondary: n=5 QEQEA, 1024 populations")
+            secondary["qeqea_n5"] = secondary_qeqea_n5(dev)
+        if "uneven" in which:
+            log("secondary: uneven batch")
+            secondary["uneven"] = secondary_uneven(dev)
         assert qe.device_errors() == 0, "device error flags raised"
 
     cpu = None

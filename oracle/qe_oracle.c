@@ -253,7 +253,7 @@ QEO_API int qeo_num_threads(void)
 }
 
 /* ------------------------------------------------------------------------ */
-/* Gate-library instances (enumeration order is a convention of this build): */
+/* Gate-library instances (the enumeration order is a convention of this library): */
 /*   library 0 {I, NOT, CNOT, CV, CV+}: I; NOT on wires 0..n-1; then for     */
 /*     every ordered pair (c, t), c != t, lexicographic: CNOT, CV, CV+.      */
 /*   library 1 {H, T, CNOT, CV, CV+}: H on wires 0..n-1; T on 0..n-1; then   */

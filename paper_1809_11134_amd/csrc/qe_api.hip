@@ -194,7 +194,6 @@ struct qe_ctx {
     bool targets_set = false;
     // ctx-owned device buffers
     std::vector<void*> owned;
-    uint32_t* slots = nullptr;    // [I*P*L] generation scratch
     uint16_t* gates = nullptr;    // [I*P*L]
     float* f = nullptr;           // [I*P]
     uint64_t* d_gen = nullptr;
@@ -254,8 +253,9 @@ qe_status prepare_decisions(qe_ctx* c, uint64_t gen, uint64_t count, hipStream_t
 
 qe_status enqueue_generation(qe_ctx* c, const LoopArgs& a, uint64_t gen, float* f, hipStream_t s) {
     if (c->prob.algorithm == QE_ALG_QEQEA) {
-        QE_HIP(launch_qeqea_fused(a, gen, c->slots, c->gates, f, true, s));
-        QE_HIP(launch_qeqea_update(a, gen, c->slots, c->gates, f, s));
+        // the update draws each entry's slot again instead of reading it
+        QE_HIP(launch_qeqea_fused(a, gen, nullptr, c->gates, f, true, s));
+        QE_HIP(launch_qeqea_update(a, gen, nullptr, c->gates, f, s));
     } else {
         QE_HIP(launch_ga_copy(a, gen, c->gates, s));
         QE_HIP(launch_eval_population(a, c->gates, f, s));
@@ -420,7 +420,6 @@ qe_status qe_create(const qe_problem* p, qe_ctx** out) {
         ALLOC(a.mutmask, 2 * I * a.MW);
     }
     ALLOC(a.inst_best_gates, I * L);
-    ALLOC(c->slots, I * P * L);
     ALLOC(c->gates, I * P * L);
     ALLOC(c->f, I * P);
     ALLOC(c->d_gen, 1);

@@ -105,6 +105,8 @@ hipError_t launch_qeqea_fused(const LoopArgs& a, uint64_t gen, uint32_t* slots, 
 hipError_t launch_mutation_decisions(const LoopArgs& a, uint64_t gen, hipStream_t s);
 hipError_t launch_scatter(const LoopArgs& a, uint64_t gen, const uint32_t* slots, const float* f,
                           hipStream_t s);
+// slots: the generation's slot indices [I*P*L], or NULL to draw them again
+// from the SAMPLE stream (the internal generation path).
 hipError_t launch_qeqea_update(const LoopArgs& a, uint64_t gen, const uint32_t* slots,
                                const uint16_t* gates, const float* f, hipStream_t s);
 hipError_t launch_mutmask_clear(const LoopArgs& a, hipStream_t s);

@@ -213,7 +213,7 @@ __device__ __forceinline__ void eval_circuit(const LoopArgs& a, uint32_t gen, ui
             if (c == ch) kept[c] = s;
         const uint16_t d = decode_slot(a, gen, i, s);
         if (writer) {
-            slots_out[(size_t)ci * L + p] = s;
+            if (slots_out) slots_out[(size_t)ci * L + p] = s;
             gates_out[(size_t)ci * L + p] = d;
         }
         return (uint32_t)d;
@@ -409,12 +409,14 @@ __device__ __forceinline__ void mutate_state(const LoopArgs& a, uint32_t gen, ui
 constexpr int UPD_BLOCK = 256;
 constexpr int UPD_MAX_P = 16384;          // part B's list of mutated individuals lives in LDS
 
+// slots NULL: the entry's slot is drawn again (the generation's own
+// sampling, which saves a dependent load); otherwise it is read.
 __device__ __forceinline__ void update_part_a(const LoopArgs& a, uint32_t gen, uint32_t idx,
                                               const uint32_t* __restrict__ slots) {
     const uint32_t L = (uint32_t)a.L, LP = L * (uint32_t)a.P;
     if (idx >= (uint32_t)a.I * LP) return;
     const uint32_t i = idx / LP, k = (idx % LP) / L;
-    const uint32_t s = slots[idx];
+    const uint32_t s = slots ? slots[idx] : sample_slot(a, gen, i, k, idx % L);
     if (s >= a.S) return;
     const uint32_t ind = (s % LP) / L;
     const size_t o = (size_t)i * a.S + s, oq = (size_t)i * a.Q + s;
@@ -446,13 +448,23 @@ __device__ __forceinline__ void update_part_b(const LoopArgs& a, uint32_t gen, u
     const uint32_t i = b / per_inst;
     if (i >= (uint32_t)a.I) return;
     if (threadIdx.x < 64) {
-        // wave 0: prefix count over the mask words, 64 at a time
+        // wave 0: prefix count over the mask words, 64 at a time (all the
+        // words, at most UPD_MAX_P / 32, are loaded first)
+        constexpr int MAXW = UPD_MAX_P / 32 / 64;
         const uint32_t* mask = mask_of(a, gen, i);
         const int lane = (int)threadIdx.x;
+        uint32_t words[MAXW];
+#pragma unroll
+        for (int q = 0; q < MAXW; ++q) {
+            const uint32_t w = (uint32_t)(q * 64 + lane);
+            words[q] = w < a.MW ? mask[w] : 0u;
+        }
         uint32_t base = 0;
-        for (uint32_t w0 = 0; w0 < a.MW; w0 += 64) {
-            const uint32_t w = w0 + (uint32_t)lane;
-            uint32_t bits = w < a.MW ? mask[w] : 0u;
+#pragma unroll
+        for (int q = 0; q < MAXW; ++q) {
+            if ((uint32_t)(q * 64) >= a.MW) break;
+            const uint32_t w = (uint32_t)(q * 64 + lane);
+            uint32_t bits = words[q];
             if (w == a.MW - 1 && (P & 31u)) bits &= (1u << (P & 31u)) - 1u;
             const uint32_t c = (uint32_t)__popc(bits);
             uint32_t incl = c;                  // inclusive scan over the wave
