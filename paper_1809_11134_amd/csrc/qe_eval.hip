@@ -70,6 +70,7 @@ __global__ __launch_bounds__(64 * W) void lds32_kernel(BatchArgs a, float* __res
                                                        float* __restrict__ U_out) {
     constexpr int N = 1 << NQ, CW = N / W;
     __shared__ float2 M[N * N];
+    __shared__ uint4 GT[W][GATE_TABLE];
     __shared__ float red[W][3];
     const int b = blockIdx.x;
     const int lane = (int)lane_id(), wave = (int)(threadIdx.x >> 6);
@@ -87,7 +88,7 @@ __global__ __launch_bounds__(64 * W) void lds32_kernel(BatchArgs a, float* __res
             return p < L ? (uint32_t)gp[p] : 0u;
         };
         const float* T = IDENT ? nullptr : reinterpret_cast<const float*>(a.targets) + 2 * it.toff;
-        ok = run_lds_path<NQ, W, IDENT>(M, T, L, src, IDENT ? nullptr : &off, &dg);
+        ok = run_lds_path<NQ, W, IDENT>(M, GT[wave], T, L, src, IDENT ? nullptr : &off, &dg);
         if (!ok) it.err = QE_DEVERR_DESC;
     }
     if (IDENT) {
@@ -168,8 +169,8 @@ __global__ __launch_bounds__(1024) void mix_bucket_kernel(BatchArgs a, int32_t* 
 }
 
 template <int NQ, int W>
-__device__ __forceinline__ void mix_lds_item(const BatchArgs& a, int b, float2* M, float (*red)[3],
-                                             float* f, float* g, float* delta) {
+__device__ __forceinline__ void mix_lds_item(const BatchArgs& a, int b, float2* M, uint4* gt,
+                                             float (*red)[3], float* f, float* g, float* delta) {
     const int lane = (int)lane_id(), wave = (int)(threadIdx.x >> 6);
     Item it;
     it.err = 1;
@@ -185,7 +186,7 @@ __device__ __forceinline__ void mix_lds_item(const BatchArgs& a, int b, float2* 
             return p < L ? (uint32_t)gp[p] : 0u;
         };
         const float* T = reinterpret_cast<const float*>(a.targets) + 2 * it.toff;
-        ok = run_lds_path<NQ, W, false>(M, T, L, src, &off, &dg, wave % W);
+        ok = run_lds_path<NQ, W, false>(M, gt, T, L, src, &off, &dg, wave % W);
         if (!ok) it.err = QE_DEVERR_DESC;
     }
     float gv, dv;
@@ -235,6 +236,7 @@ __global__ __launch_bounds__(256) void mix_kernel(BatchArgs a, const int32_t* __
                                                   float* __restrict__ f, float* __restrict__ g,
                                                   float* __restrict__ delta) {
     __shared__ float2 M[4096];
+    __shared__ uint4 GT[4][GATE_TABLE];
     __shared__ float red[4][3];
     const int item = blockIdx.x;
     if (item >= meta[8 + MIX_BUCKETS]) return;
@@ -246,9 +248,9 @@ __global__ __launch_bounds__(256) void mix_kernel(BatchArgs a, const int32_t* __
     const int sub = per == 1 ? 0 : (per == 2 ? wave >> 1 : wave);
     const int b = local + sub < meta[16 + k] ? order[meta[k] + local + sub] : -1;
     switch (k) {
-        case 0: mix_lds_item<6, 4>(a, b, M, red, f, g, delta); break;
-        case 1: mix_lds_item<5, 2>(a, b, M + sub * 1024, red, f, g, delta); break;
-        case 2: mix_lds_item<4, 1>(a, b, M + sub * 256, red, f, g, delta); break;
+        case 0: mix_lds_item<6, 4>(a, b, M, GT[wave], red, f, g, delta); break;
+        case 1: mix_lds_item<5, 2>(a, b, M + sub * 1024, GT[wave], red, f, g, delta); break;
+        case 2: mix_lds_item<4, 1>(a, b, M + sub * 256, GT[wave], red, f, g, delta); break;
         case 3: mix_wave_item<3>(a, b, f, g, delta); break;
         case 4: mix_wave_item<2>(a, b, f, g, delta); break;
         case 5: mix_wave_item<1>(a, b, f, g, delta); break;

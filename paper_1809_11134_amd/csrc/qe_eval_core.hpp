@@ -466,8 +466,11 @@ __device__ __forceinline__ void wave_lds_fence() {
 // Runs the circuit on this wave's columns and, with `fit`, leaves per-wave
 // partial sums for the fitness: off-diagonal |m|^2, and the diagonal
 // elements of the wave's columns (lane l < CW holds element (j, j)).
+// gt: this wavefront's gate table in LDS (GATE_TABLE uint4).
+constexpr int GATE_TABLE = 128;
+
 template <int NQ, int W, bool IDENT, typename GateSrc>
-__device__ __forceinline__ bool run_lds_path(float2* M, const float* __restrict__ T, int L,
+__device__ __forceinline__ bool run_lds_path(float2* M, uint4* gt, const float* __restrict__ T, int L,
                                              GateSrc&& src, float* off_out, float2* diag_out,
                                              int wave = -1) {
     constexpr int N = 1 << NQ, CW = N / W, RG = 64 / CW;
@@ -509,11 +512,13 @@ __device__ __forceinline__ bool run_lds_path(float2* M, const float* __restrict_
         const int cnt = min(64, L - ch * 64);
         const bool bad = (lane < cnt) && !desc_valid(dv, NQ);
         if (__ballot(bad)) { ok = false; break; }
-        // Gate program, one gate per lane (lane g: gate g of the chunk): the
-        // byte offsets in M of pair-index bits 0..4 once the target bit (and
-        // the control bit) are inserted as zeros, the control row offset and
-        // the partner row offset.  The loop then reads them with v_readlane
-        // and visits only the gates that are not I.
+        // Gate program: each lane computes the constants of its own gate (lane
+        // g: gate g of the chunk): the byte offsets in M of pair-index bits
+        // 0..4 once the target bit (and the control bit) are inserted as
+        // zeros, the control row offset and the partner row offset.  The
+        // non-identity gates are packed in order into this wave's LDS table
+        // (two uint4 per gate), which the loop reads with broadcast loads,
+        // one gate ahead.
         const int kind = (int)(dv & 15u);
         const int tpos = NQ - 1 - (int)((dv >> 4) & 15u);
         const int cpos = NQ - 1 - (int)((dv >> 8) & 15u);
@@ -524,26 +529,32 @@ __device__ __forceinline__ bool run_lds_path(float2* M, const float* __restrict_
             if (ctl) y = ins0(y, hi);
             return (uint32_t)y << ROWB;
         };
-        const uint32_t R0 = ins(1), R1 = ins(2), R2 = ins(4), R3 = ins(8), R4 = ins(16);
-        const uint32_t CB = ctl ? (1u << (cpos + (int)ROWB)) : 0u, TB = 1u << (tpos + (int)ROWB);
-        uint64_t todo = __ballot(lane < cnt && kind != KIND_I);
-        while (todo) {
-            const int g = (int)__builtin_ctzll(todo);
-            todo &= todo - 1;
-            const int k = __builtin_amdgcn_readlane(kind, g);
-            const uint32_t r0 = __builtin_amdgcn_readlane(R0, g), r1 = __builtin_amdgcn_readlane(R1, g);
-            const uint32_t tb = __builtin_amdgcn_readlane(TB, g);
+        const bool live = lane < cnt && kind != KIND_I;
+        const uint64_t live_mask = __ballot(live);
+        const int count = __popcll(live_mask);
+        if (live) {
+            const int rank = (int)__builtin_amdgcn_mbcnt_hi(
+                (uint32_t)(live_mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)live_mask, 0u));
+            gt[2 * rank] = make_uint4(ins(1), ins(2), ctl ? (1u << (cpos + (int)ROWB)) : 0u,
+                                      1u << (tpos + (int)ROWB));
+            gt[2 * rank + 1] = make_uint4((uint32_t)kind, ins(4), ins(8), ins(16));
+        }
+        wave_lds_fence();
+        // one gate from its table entry (E0, E1); `next` issues the load of
+        // the following entry once the addresses are known and before the
+        // data reads, so the entry is ready when its gate starts
+        auto apply = [&](const uint4 E0, const uint4 E1, auto&& next) {
+            const int k = __builtin_amdgcn_readfirstlane((int)E1.x);
+            const uint32_t rgo = (mb0 & E0.x) | (mb1 & E0.y);   // the row group's pair bits
+            const uint32_t tb = E0.w;
+            next();
             if (k >= KIND_CNOT && k <= KIND_CVDG) {
                 constexpr int NIT = (N / 4) / RG;
-                const uint32_t cb = __builtin_amdgcn_readlane(CB, g);
                 uint32_t offm[NIT];
                 offm[0] = 0u;
-                if constexpr (NIT > 1) offm[1] = __builtin_amdgcn_readlane(R2, g);
-                if constexpr (NIT > 2) {
-                    offm[2] = __builtin_amdgcn_readlane(R3, g);
-                    offm[3] = offm[1] | offm[2];
-                }
-                const uint32_t a0 = ((mb0 & r0) | (mb1 & r1)) + jb + cb, a1 = a0 + tb;
+                if constexpr (NIT > 1) offm[1] = E1.y;
+                if constexpr (NIT > 2) { offm[2] = E1.z; offm[3] = E1.y | E1.z; }
+                const uint32_t a0 = rgo + jb + E0.z, a1 = a0 + tb;
                 float2 A[NIT], B[NIT];
 #pragma unroll
                 for (int m = 0; m < NIT; ++m) { A[m] = at(a0 + offm[m]); B[m] = at(a1 + offm[m]); }
@@ -566,17 +577,13 @@ __device__ __forceinline__ bool run_lds_path(float2* M, const float* __restrict_
                 constexpr int NIT = (N / 2) / RG;
                 uint32_t offm[NIT];
                 offm[0] = 0u;
-                if constexpr (NIT > 1) offm[1] = __builtin_amdgcn_readlane(R2, g);
-                if constexpr (NIT > 2) {
-                    offm[2] = __builtin_amdgcn_readlane(R3, g);
-                    offm[3] = offm[1] | offm[2];
-                }
+                if constexpr (NIT > 1) offm[1] = E1.y;
+                if constexpr (NIT > 2) { offm[2] = E1.z; offm[3] = E1.y | E1.z; }
                 if constexpr (NIT > 4) {
-                    const uint32_t r4 = __builtin_amdgcn_readlane(R4, g);
 #pragma unroll
-                    for (int m = 4; m < 8; ++m) offm[m] = offm[m - 4] | r4;
+                    for (int m = 4; m < 8; ++m) offm[m] = offm[m - 4] | E1.w;
                 }
-                const uint32_t a0 = ((mb0 & r0) | (mb1 & r1)) + jb, a1 = a0 + tb;
+                const uint32_t a0 = rgo + jb, a1 = a0 + tb;
                 const float r = 0.70710678118654752f;
                 if (k == KIND_T) {
 #pragma unroll
@@ -601,6 +608,16 @@ __device__ __forceinline__ bool run_lds_path(float2* M, const float* __restrict_
                     }
                 }
             }
+        };
+        // two gates per iteration, each entry loaded one gate ahead (the
+        // unrolled pair keeps the prefetched entries in place)
+        uint4 a0e = make_uint4(0u, 0u, 0u, 0u), a1e = a0e, b0e = a0e, b1e = a0e;
+        if (count > 0) { a0e = gt[0]; a1e = gt[1]; }
+        for (int e = 0; e < count; e += 2) {
+            apply(a0e, a1e, [&] { if (e + 1 < count) { b0e = gt[2 * e + 2]; b1e = gt[2 * e + 3]; } });
+            wave_lds_fence();
+            if (e + 1 >= count) break;
+            apply(b0e, b1e, [&] { if (e + 2 < count) { a0e = gt[2 * e + 4]; a1e = gt[2 * e + 5]; } });
             wave_lds_fence();
         }
     }

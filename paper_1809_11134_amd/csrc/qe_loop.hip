@@ -183,7 +183,7 @@ template <int NQ, int W, bool SAMPLE>
 __device__ __forceinline__ void eval_circuit(const LoopArgs& a, uint32_t gen, uint32_t ci,
                                              const uint16_t* gates_in, uint32_t* slots_out,
                                              uint16_t* gates_out, float* f_out, bool writer,
-                                             bool decide, float2* M, float (*red)[3]) {
+                                             bool decide, float2* M, uint4* gt, float (*red)[3]) {
     const uint32_t i = ci / (uint32_t)a.P, k = ci % (uint32_t)a.P;
     const int lane = (int)lane_id();
     const int L = a.L;
@@ -228,7 +228,7 @@ __device__ __forceinline__ void eval_circuit(const LoopArgs& a, uint32_t gen, ui
         constexpr int N = 1 << NQ;
         float off, gd, dd;
         float2 dg;
-        ok = run_lds_path<NQ, W, false>(M, T, L, src, &off, &dg, W == 1 ? 0 : -1);
+        ok = run_lds_path<NQ, W, false>(M, gt, T, L, src, &off, &dg, W == 1 ? 0 : -1);
         fv = group_fitness<W>(off, dg, red, N, &gd, &dd);
     }
     if (!ok) fv = __builtin_nanf("");
@@ -267,19 +267,21 @@ __global__ __launch_bounds__(256) void population_kernel(LoopArgs a, uint64_t ge
         const uint32_t ci = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
         if (ci >= total) return;
         eval_circuit<NQ, 0, SAMPLE>(a, gen, ci, gates_in, slots_out, gates_out, f_out, true, decide,
-                                    nullptr, nullptr);
+                                    nullptr, nullptr, nullptr);
     } else {
         // W = 1: four circuits per workgroup, one per wavefront (no barrier
         // is shared, so a wavefront past the end may leave); W > 1: one
         // circuit per workgroup of W wavefronts
         constexpr int N = 1 << NQ, CPB = W == 1 ? 4 : 1;
         __shared__ float2 M[CPB][N * N];
+        __shared__ uint4 GT[W == 1 ? 4 : W][GATE_TABLE];
         __shared__ float red[4][3];
         const int wave = (int)(threadIdx.x >> 6);
         const uint32_t ci = W == 1 ? blockIdx.x * CPB + (uint32_t)wave : blockIdx.x;
         if (ci >= total) return;
         eval_circuit<NQ, W, SAMPLE>(a, gen, ci, gates_in, slots_out, gates_out, f_out,
-                                    W == 1 || threadIdx.x < 64, decide, M[W == 1 ? wave : 0], red);
+                                    W == 1 || threadIdx.x < 64, decide, M[W == 1 ? wave : 0], GT[wave],
+                                    red);
     }
 }
 

@@ -101,6 +101,56 @@ def test_qeqea_update_teacher_forced(dev, oracle, n):
     assert modes == {0, 1}
 
 
+@pytest.mark.parametrize("n", [3, 4, 5])
+def test_fused_generation_teacher_forced_any_order(dev, oracle, n):
+    # the internal generation path (fused kernel + update) against the oracle,
+    # over generation numbers that jump back and forth and repeat: the
+    # decision masks must be cleared whenever a generation does not follow
+    # the previous one
+    L, P, I, seed = 12, 40, 2, 1313 + n
+    pm = 0.4
+    ctx, T = qeqea_ctx(dev, oracle, n, L, P, I, seed, pm=pm)
+    for gen in (0, 1, 5, 5, 2, 3, 3, 4, 2 ** 31 + 1, 0):
+        o = to_oracle(oracle, ctx, gpu_state(ctx))
+        rs, rg = o.sample(gen)
+        f = ctx.generation(gen)
+        fh = f.cpu().numpy()
+        ref = np.array([oracle.fitness(n, rg[c], T[c // P])[0] for c in range(I * P)])
+        assert np.abs(fh - ref).max() <= 1e-5, gen
+        o.update(gen, pm, float(np.pi / 4), rs, fh)
+        assert_same_state(o, gpu_state(ctx))
+
+
+@pytest.mark.parametrize("n", [4, 6])
+def test_sample_eval_then_update_equals_generation(dev, oracle, n):
+    L, P, I, seed = 17, 48, 3, 4040 + n
+    a, _ = qeqea_ctx(dev, oracle, n, L, P, I, seed)
+    b, _ = qeqea_ctx(dev, oracle, n, L, P, I, seed)
+    for gen in range(4):
+        slots, gates, f = a.sample_eval(gen)
+        rs, rg = a.sample(gen)
+        assert torch.equal(slots, rs) and torch.equal(gates, rg)
+        a.update(gen, slots, gates, f)
+        fb = b.generation(gen)
+        assert torch.equal(f, fb)
+    sa, sb = gpu_state(a), gpu_state(b)
+    for k in sa:
+        assert np.array_equal(sa[k], sb[k]), k
+
+
+def test_state_read_fields(dev, oracle):
+    n, L, P, I, seed = 3, 5, 8, 2, 31
+    ctx, _ = qeqea_ctx(dev, oracle, n, L, P, I, seed)
+    S, Q = n * n * L * P, n * L * P
+    sizes = {"theta": I * S, "best_f": I * S, "best_theta": I * S, "qutrit": I * Q * 6,
+             "best_qutrit": I * Q * 6, "genomes0": 0, "genomes1": 0}
+    for name, size in sizes.items():
+        assert ctx.state(name).numel() == size, name
+    assert np.all(ctx.state("best_f").cpu().numpy() == -1.0)
+    with pytest.raises(qe.QeError):
+        qe._call("qe_state_read", ctx.handle, 7, None, qe.ctypes.byref(qe.ctypes.c_int64(0)), None)
+
+
 def run_steps(ctx, gens):
     fs = []
     for gen in gens:
