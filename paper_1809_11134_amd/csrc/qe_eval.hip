@@ -236,7 +236,6 @@ __global__ __launch_bounds__(256) void mix_kernel(BatchArgs a, const int32_t* __
                                                   float* __restrict__ f, float* __restrict__ g,
                                                   float* __restrict__ delta) {
     __shared__ float2 M[4096];
-    __shared__ uint4 GT[4][GATE_TABLE];
     __shared__ float red[4][3];
     const int item = blockIdx.x;
     if (item >= meta[8 + MIX_BUCKETS]) return;
@@ -248,9 +247,14 @@ __global__ __launch_bounds__(256) void mix_kernel(BatchArgs a, const int32_t* __
     const int sub = per == 1 ? 0 : (per == 2 ? wave >> 1 : wave);
     const int b = local + sub < meta[16 + k] ? order[meta[k] + local + sub] : -1;
     switch (k) {
-        case 0: mix_lds_item<6, 4>(a, b, M, GT[wave], red, f, g, delta); break;
-        case 1: mix_lds_item<5, 2>(a, b, M + sub * 1024, GT[wave], red, f, g, delta); break;
-        case 2: mix_lds_item<4, 1>(a, b, M + sub * 256, GT[wave], red, f, g, delta); break;
+        // (only the width-4 items use gate tables: they live in the part of
+        // M that four 16 x 16 matrices leave free)
+        case 0: mix_lds_item<6, 4>(a, b, M, nullptr, red, f, g, delta); break;
+        case 1: mix_lds_item<5, 2>(a, b, M + sub * 1024, nullptr, red, f, g, delta); break;
+        case 2:
+            mix_lds_item<4, 1>(a, b, M + sub * 256,
+                               reinterpret_cast<uint4*>(M + 1024) + wave * GATE_TABLE, red, f, g, delta);
+            break;
         case 3: mix_wave_item<3>(a, b, f, g, delta); break;
         case 4: mix_wave_item<2>(a, b, f, g, delta); break;
         case 5: mix_wave_item<1>(a, b, f, g, delta); break;

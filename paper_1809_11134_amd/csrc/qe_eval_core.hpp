@@ -507,6 +507,10 @@ __device__ __forceinline__ bool run_lds_path(float2* M, uint4* gt, const float* 
         return *reinterpret_cast<float2*>(reinterpret_cast<char*>(M) + byte_off);
     };
     constexpr uint32_t ROWB = NQ + 3;      // log2 of a row's byte stride (N * 8)
+    // pass offsets in use: R2 from 2 passes, R3 from 4, R4 from 8 (an
+    // uncontrolled gate has (N / 2) / RG passes)
+    constexpr bool NIT_USES_R2 = (N / 2) / RG > 1, NIT_USES_R3 = (N / 2) / RG > 2,
+                   NIT_USES_R4 = (N / 2) / RG > 4;
     for (int ch = 0; ch < chunks; ++ch) {
         const uint32_t dv = ch == 0 ? dv0 : src(ch);
         const int cnt = min(64, L - ch * 64);
@@ -515,10 +519,13 @@ __device__ __forceinline__ bool run_lds_path(float2* M, uint4* gt, const float* 
         // Gate program: each lane computes the constants of its own gate (lane
         // g: gate g of the chunk): the byte offsets in M of pair-index bits
         // 0..4 once the target bit (and the control bit) are inserted as
-        // zeros, the control row offset and the partner row offset.  The
-        // non-identity gates are packed in order into this wave's LDS table
-        // (two uint4 per gate), which the loop reads with broadcast loads,
-        // one gate ahead.
+        // zeros, the control row offset and the partner row offset.  With one
+        // wavefront per circuit (W = 1) the non-identity gates are packed in
+        // order into this wave's LDS table (two uint4 per gate), which the
+        // loop reads with broadcast loads one gate ahead; with W > 1 (LDS
+        // bandwidth is the bound there) the loop reads them from the lanes
+        // with v_readlane, visiting the set bits of a ballot of non-identity
+        // gates.
         const int kind = (int)(dv & 15u);
         const int tpos = NQ - 1 - (int)((dv >> 4) & 15u);
         const int cpos = NQ - 1 - (int)((dv >> 8) & 15u);
@@ -531,15 +538,9 @@ __device__ __forceinline__ bool run_lds_path(float2* M, uint4* gt, const float* 
         };
         const bool live = lane < cnt && kind != KIND_I;
         const uint64_t live_mask = __ballot(live);
-        const int count = __popcll(live_mask);
-        if (live) {
-            const int rank = (int)__builtin_amdgcn_mbcnt_hi(
-                (uint32_t)(live_mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)live_mask, 0u));
-            gt[2 * rank] = make_uint4(ins(1), ins(2), ctl ? (1u << (cpos + (int)ROWB)) : 0u,
-                                      1u << (tpos + (int)ROWB));
-            gt[2 * rank + 1] = make_uint4((uint32_t)kind, ins(4), ins(8), ins(16));
-        }
-        wave_lds_fence();
+        const uint4 G0 = make_uint4(ins(1), ins(2), ctl ? (1u << (cpos + (int)ROWB)) : 0u,
+                                    1u << (tpos + (int)ROWB));
+        const uint4 G1 = make_uint4((uint32_t)kind, ins(4), ins(8), ins(16));
         // one gate from its table entry (E0, E1); `next` issues the load of
         // the following entry once the addresses are known and before the
         // data reads, so the entry is ready when its gate starts
@@ -609,16 +610,39 @@ __device__ __forceinline__ bool run_lds_path(float2* M, uint4* gt, const float* 
                 }
             }
         };
-        // two gates per iteration, each entry loaded one gate ahead (the
-        // unrolled pair keeps the prefetched entries in place)
-        uint4 a0e = make_uint4(0u, 0u, 0u, 0u), a1e = a0e, b0e = a0e, b1e = a0e;
-        if (count > 0) { a0e = gt[0]; a1e = gt[1]; }
-        for (int e = 0; e < count; e += 2) {
-            apply(a0e, a1e, [&] { if (e + 1 < count) { b0e = gt[2 * e + 2]; b1e = gt[2 * e + 3]; } });
+        if constexpr (W == 1) {
+            const int count = __popcll(live_mask);
+            if (live) {
+                const int rank = (int)__builtin_amdgcn_mbcnt_hi(
+                    (uint32_t)(live_mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)live_mask, 0u));
+                gt[2 * rank] = G0;
+                gt[2 * rank + 1] = G1;
+            }
             wave_lds_fence();
-            if (e + 1 >= count) break;
-            apply(b0e, b1e, [&] { if (e + 2 < count) { a0e = gt[2 * e + 4]; a1e = gt[2 * e + 5]; } });
-            wave_lds_fence();
+            // two gates per iteration, each entry loaded one gate ahead (the
+            // unrolled pair keeps the prefetched entries in place)
+            uint4 a0e = make_uint4(0u, 0u, 0u, 0u), a1e = a0e, b0e = a0e, b1e = a0e;
+            if (count > 0) { a0e = gt[0]; a1e = gt[1]; }
+            for (int e = 0; e < count; e += 2) {
+                apply(a0e, a1e, [&] { if (e + 1 < count) { b0e = gt[2 * e + 2]; b1e = gt[2 * e + 3]; } });
+                wave_lds_fence();
+                if (e + 1 >= count) break;
+                apply(b0e, b1e, [&] { if (e + 2 < count) { a0e = gt[2 * e + 4]; a1e = gt[2 * e + 5]; } });
+                wave_lds_fence();
+            }
+        } else {
+            (void)gt;
+            uint64_t todo = live_mask;
+            while (todo) {
+                const int g = (int)__builtin_ctzll(todo);
+                todo &= todo - 1;
+                auto rl = [&](uint32_t v) { return (uint32_t)__builtin_amdgcn_readlane((int)v, g); };
+                const uint4 E0 = make_uint4(rl(G0.x), rl(G0.y), rl(G0.z), rl(G0.w));
+                const uint4 E1 = make_uint4(rl(G1.x), NIT_USES_R2 ? rl(G1.y) : 0u,
+                                            NIT_USES_R3 ? rl(G1.z) : 0u, NIT_USES_R4 ? rl(G1.w) : 0u);
+                apply(E0, E1, [] {});
+                wave_lds_fence();
+            }
         }
     }
     if (off_out) {

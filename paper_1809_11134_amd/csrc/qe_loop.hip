@@ -8,6 +8,7 @@
 // is compiled with -ffp-contract=off (no multiply-add fusion anywhere) and the
 // pragma below repeats that for this file.
 #include <algorithm>
+#include <cmath>
 
 #include "../../include/qe.h"
 #include "qe_eval_core.hpp"
@@ -504,7 +505,8 @@ __device__ __forceinline__ void update_part_b(const LoopArgs& a, uint32_t gen, u
         if (used) elitism(__uint_as_float((uint32_t)(r.key >> 32)), r, q, rot);
         r.key = 0ull;
         if (!qm || rot) mutate_state(a, gen, i, s, qm, r, q);
-        a.slot[o] = r;
+        // an unused slot in qutrit mode keeps its record (only the qutrit moves)
+        if (used || !qm) a.slot[o] = r;
         if (rot && (used || qm)) store_qstate(a.qrec + oq, q);
     }
 }
@@ -848,12 +850,14 @@ hipError_t launch_qeqea_update(const LoopArgs& a, uint64_t gen, const uint32_t* 
     if (a.P > UPD_MAX_P) return hipErrorInvalidValue;
     const uint32_t nC = blocks((size_t)a.I * part_c_waves(a.P), UPD_BLOCK / 64);
     const uint32_t nA = blocks((size_t)a.I * a.P * a.L, UPD_BLOCK);
-    // part B: per instance, enough workgroups for the expected number of
-    // (mutated individual, slot chunk) items (more items loop)
+    // part B: per instance, enough workgroups for the (mutated individual,
+    // slot chunk) items up to four standard deviations above the binomial
+    // mean (more items loop)
     const size_t chunks = ((size_t)a.n * a.n * a.L + UPD_BLOCK - 1) / UPD_BLOCK;
-    const double expect = (double)a.thr_pm / 4294967296.0 * a.P * chunks;
+    const double pm = (double)a.thr_pm / 4294967296.0;
+    const double expect = pm * a.P * chunks, sd = std::sqrt(a.P * pm * (1.0 - pm)) * chunks;
     const uint32_t per_inst = (uint32_t)std::max<double>(
-        1.0, std::min<double>(1.5 * expect + 8.0, (double)a.P * chunks));
+        1.0, std::min<double>(std::ceil(expect + 4.0 * sd + 8.0), (double)a.P * chunks));
     const uint32_t nB = per_inst * (uint32_t)a.I;
     const size_t lds = ((size_t)a.P * sizeof(uint16_t) + 15) & ~(size_t)15;
     qeqea_update_kernel<<<nC + nA + nB, UPD_BLOCK, lds, s>>>(a, gen, slots, gates, f, nC, nA, per_inst);
