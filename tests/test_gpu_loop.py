@@ -121,6 +121,27 @@ def test_fused_generation_teacher_forced_any_order(dev, oracle, n):
         assert_same_state(o, gpu_state(ctx))
 
 
+@pytest.mark.parametrize("n,L,P", [(4, 64, 20), (5, 70, 33), (3, 300, 12), (4, 31, 8), (6, 129, 9)])
+def test_fused_generation_long_circuits(dev, oracle, n, L, P):
+    # circuit lengths at and beyond one wavefront of positions (L = 64 leaves
+    # no spare lane for the mutation decision; L > 256 exceeds the slots a
+    # wavefront keeps for the key updates), populations that are not a
+    # multiple of the 32-bit decision words
+    I, seed, pm = 2, 5150 + L, 0.5
+    qe.device_errors()                      # start from a clear error word
+    ctx, T = qeqea_ctx(dev, oracle, n, L, P, I, seed, pm=pm)
+    for gen in range(3):
+        o = to_oracle(oracle, ctx, gpu_state(ctx))
+        rs, rg = o.sample(gen)
+        f = ctx.generation(gen)
+        fh = f.cpu().numpy()
+        ref = np.array([oracle.fitness(n, rg[c], T[c // P])[0] for c in range(I * P)])
+        assert np.abs(fh - ref).max() <= 1e-5, gen
+        o.update(gen, pm, float(np.pi / 4), rs, fh)
+        assert_same_state(o, gpu_state(ctx))
+    assert qe.device_errors() == 0
+
+
 @pytest.mark.parametrize("n", [4, 6])
 def test_sample_eval_then_update_equals_generation(dev, oracle, n):
     L, P, I, seed = 17, 48, 3, 4040 + n
