@@ -407,8 +407,8 @@ __device__ __forceinline__ void mutate_state(const LoopArgs& a, uint32_t gen, ui
 // Part B: every slot of the individuals that mutate
 // (one thread per slot, since the individual's slots belong to nobody else):
 // elitism if the slot was used, then mutation (qubit mode: every slot;
-// qutrit mode: rotation slots).  Part C comes first in the grid so that its
-// serial scan starts at once.
+// qutrit mode: rotation slots).  The grid holds part C, then part B (the
+// longest chains), then part A, so the longer work is dispatched first.
 constexpr int UPD_BLOCK = 256;
 constexpr int UPD_MAX_P = 16384;          // part B's list of mutated individuals lives in LDS
 
@@ -567,15 +567,15 @@ __global__ __launch_bounds__(UPD_BLOCK) void qeqea_update_kernel(LoopArgs a, uin
                                                                  const uint32_t* __restrict__ slots,
                                                                  const uint16_t* __restrict__ gates,
                                                                  const float* __restrict__ f,
-                                                                 uint32_t nC, uint32_t nA,
+                                                                 uint32_t nC, uint32_t nB,
                                                                  uint32_t per_inst) {
     const uint32_t gen = gen_of(a, gen64);
     if (blockIdx.x < nC)
         update_part_c(a, blockIdx.x, gates, f);
-    else if (blockIdx.x < nC + nA)
-        update_part_a(a, gen, (blockIdx.x - nC) * UPD_BLOCK + threadIdx.x, slots);
+    else if (blockIdx.x < nC + nB)
+        update_part_b(a, gen, blockIdx.x - nC, per_inst);
     else
-        update_part_b(a, gen, blockIdx.x - nC - nA, per_inst);
+        update_part_a(a, gen, (blockIdx.x - nC - nB) * UPD_BLOCK + threadIdx.x, slots);
 }
 
 // Dense copy of one field of the encoding state.
@@ -860,7 +860,7 @@ hipError_t launch_qeqea_update(const LoopArgs& a, uint64_t gen, const uint32_t* 
         1.0, std::min<double>(std::ceil(expect + 4.0 * sd + 8.0), (double)a.P * chunks));
     const uint32_t nB = per_inst * (uint32_t)a.I;
     const size_t lds = ((size_t)a.P * sizeof(uint16_t) + 15) & ~(size_t)15;
-    qeqea_update_kernel<<<nC + nA + nB, UPD_BLOCK, lds, s>>>(a, gen, slots, gates, f, nC, nA, per_inst);
+    qeqea_update_kernel<<<nC + nB + nA, UPD_BLOCK, lds, s>>>(a, gen, slots, gates, f, nC, nB, per_inst);
     return hipGetLastError();
 }
 
