@@ -17,6 +17,11 @@
 // bit (v_permlane16/32_swap); a lane-resident control becomes an exec
 // predicate.  Every gate body is then one of a handful of fully unrolled
 // register loops, and no shuffle or LDS traffic is needed for the arithmetic.
+//
+// LDS-staged layout (n = 4..6, the tuned default; run_lds_path): M lives in
+// LDS, W wavefronts split its columns, each lane updates the row pairs of one
+// column per pass, and the gate constants come from a per-chunk gate program.
+// One entry per lane (n <= 3; run_small_path): lane l holds M[l / N][l % N].
 #pragma once
 #include "../../include/qe.h"
 #include "qe_device.hpp"
@@ -451,8 +456,9 @@ __device__ __forceinline__ bool run_small_path(const float* __restrict__ T, int 
 // handles row pair pr = m*RG + rg (RG = 64 / CW), whose upper row index is
 // the pair index with a zero (and, for a controlled gate, a one) inserted at
 // the wire's bit position.  Insertion is additive over the disjoint bits of
-// m*RG and rg, so the per-lane part is computed once per gate and the pass
-// offset is wave-uniform.
+// m*RG and rg, so a gate is described by the inserted offsets of the pair-
+// index bits (rg's two bits per lane, m's bits per pass), computed for all the
+// gates of a chunk at once, one gate per lane.
 __device__ __forceinline__ int ins0(int x, int pos) {
     return ((x >> pos) << (pos + 1)) | (x & ((1 << pos) - 1));
 }
