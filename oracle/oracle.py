@@ -31,6 +31,7 @@ def lib():
         L.qeo_check_desc.argtypes = [c.c_int, c.c_uint16]
         L.qeo_unitary.argtypes = [c.c_int, c.c_int, u16p, f64p]
         L.qeo_fitness.argtypes = [c.c_int, c.c_int, u16p, f64p, f64p]
+        L.qeo_fitness_pi.argtypes = [c.c_int, c.c_int, u16p, f64p, f64p]
         L.qeo_eval_batch.argtypes = [c.c_int, i8p, i32p, u16p, i64p, f64p, f64p]
         L.qeo_num_threads.restype = c.c_int
         L.qeo_lib_size.argtypes = [c.c_int, c.c_int]
@@ -88,6 +89,18 @@ def fitness(n, gates, T):
     T = np.ascontiguousarray(T, np.complex128)
     out = np.zeros(4, np.float64)
     rc = lib().qeo_fitness(n, len(g), g, T.view(np.float64).ravel(), out)
+    if rc:
+        raise ValueError("bad gate descriptor")
+    return tuple(float(x) for x in out)
+
+
+def fitness_pi(n, gates, T):
+    """Phase-insensitive fitness: returns (fP, gP, radicand) for one circuit
+    against target T (gP = sum |U_ij|^2 |T_ij|^2 / 2^n)."""
+    g = np.ascontiguousarray(gates, np.uint16)
+    T = np.ascontiguousarray(T, np.complex128)
+    out = np.zeros(3, np.float64)
+    rc = lib().qeo_fitness_pi(n, len(g), g, T.view(np.float64).ravel(), out)
     if rc:
         raise ValueError("bad gate descriptor")
     return tuple(float(x) for x in out)

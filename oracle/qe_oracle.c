@@ -224,6 +224,48 @@ QEO_API int qeo_fitness(int n, int L, const uint16_t* gates, const double* T, do
     return rc;
 }
 
+/* Phase-insensitive fitness, the reading under which the paper's Table II
+ * figure (and its Table III accuracy) reproduces; Eq. 11 as printed stays the
+ * primary fitness:
+ *   gP  = sum_ij |S_ij|^2 |T_ij|^2 / size
+ *   rad = sum_ij |S_ij|^2 (1 - |T_ij|^2) / size  (= 1 - gP for unitary S,
+ *         whose rows have unit norm; free of cancellation near gP = 1)
+ *   fP  = 1 - sqrt(clamp(rad, 0, 1)).
+ * out = {fP, gP, rad}.  Pinned by a closed form, phase invariance,
+ * rad + gP = 1 and, for permutation targets, the off-diagonal energy of
+ * S T^dagger (tests). */
+static void fitness_pi_of(int n, const cplx* S, const cplx* T, double out[3])
+{
+    int N = 1 << n;
+    size_t NN = (size_t)N * N;
+    double gp = 0, rad = 0;
+    for (size_t k = 0; k < NN; ++k) {
+        double s2 = creal(S[k]) * creal(S[k]) + cimag(S[k]) * cimag(S[k]);
+        double t2 = creal(T[k]) * creal(T[k]) + cimag(T[k]) * cimag(T[k]);
+        gp += s2 * t2;
+        rad += s2 * (1.0 - t2);
+    }
+    gp /= N;
+    rad /= N;
+    double q = rad < 0 ? 0 : (rad > 1 ? 1 : rad);
+    out[0] = 1.0 - sqrt(q);
+    out[1] = gp;
+    out[2] = rad;
+}
+
+/* Phase-insensitive fitness of one circuit against target T.
+ * out = {fP, gP, rad}.  Returns 0 or -1 on a bad gate. */
+QEO_API int qeo_fitness_pi(int n, int L, const uint16_t* gates, const double* T, double out[3])
+{
+    int N = 1 << n;
+    cplx* S = (cplx*)malloc(sizeof(cplx) * N * N);
+    if (!S) return -2;
+    int rc = qeo_unitary(n, L, gates, (double*)S);
+    if (rc == 0) fitness_pi_of(n, S, (const cplx*)T, out);
+    free(S);
+    return rc;
+}
+
 /* A batch of circuits of uneven width and length: circuit b has n[b] wires,
  * gates[goff[b] .. goff[b+1]) and its target at targets + toff[b] (complex
  * elements).  out is [B][4] as in qeo_fitness.  Circuits run in parallel

@@ -226,3 +226,58 @@ def test_table2_reproduces_only_phase_insensitively():
     assert abs(np.abs(A - Tm).mean() - 0.02) < 0.005
     fP = 1 - math.sqrt(1 - (A * np.abs(Tm) ** 2).sum() / 8)
     assert abs(fP - 0.7047) < 1e-3
+
+
+# ------------------------------------------ phase-insensitive fitness (oracle)
+def test_phase_insensitive_closed_form(oracle):
+    # CV against CNOT on (control 0, target 1): |U|^2 is 1 on the identity
+    # block and 1/2 on the V block, so gP = (1 + 1 + 1/2 + 1/2) / 4 = 3/4 and
+    # fP = 1 - sqrt(1/4) = 1/2, where Eq. 11 gives 1 - sqrt(1 - sqrt(10)/4)
+    T = oracle.unitary(2, [d(CNOT, 1, 0)])
+    fP, gP, rad = oracle.fitness_pi(2, [d(CV, 1, 0)], T)
+    assert abs(gP - 0.75) < 1e-15 and abs(fP - 0.5) < 1e-15 and abs(rad - 0.25) < 1e-15
+    f = oracle.fitness(2, [d(CV, 1, 0)], T)[0]
+    assert abs(f - (1 - math.sqrt(1 - math.sqrt(10) / 4))) < 1e-12
+    # exact synthesis scores 1, a circuit with no overlap 0
+    assert oracle.fitness_pi(2, [d(CNOT, 1, 0)], T)[0] == 1.0
+    assert abs(oracle.fitness_pi(1, [d(NOT, 0)], np.eye(2))[0]) < 1e-15
+
+
+def test_phase_insensitive_ignores_diagonal_phases(oracle):
+    # T gates (diagonal phases) before or after a circuit leave |U_ij| and so
+    # fP unchanged, while the phase-sensitive Eq. 11 value moves
+    rng = np.random.default_rng(11)
+    lib1 = oracle.lib_table(1, 3)
+    tgt = perm_matrix(3, peres_fn)
+    moved = 0
+    for _ in range(40):
+        c = [int(x) for x in rng.choice(lib1, 6)]
+        ph = [d(TG, int(w)) for w in rng.integers(0, 3, 3)]
+        a = oracle.fitness_pi(3, c, tgt)
+        for v in (ph + c, c + ph, ph + c + ph):
+            b = oracle.fitness_pi(3, v, tgt)
+            assert abs(a[0] - b[0]) < 1e-12 and abs(a[1] - b[1]) < 1e-12
+        moved += abs(oracle.fitness(3, c + ph, tgt)[0] - oracle.fitness(3, c, tgt)[0]) > 1e-9
+    assert moved > 0
+
+
+def test_phase_insensitive_forms_agree(oracle):
+    # rad + gP = 1 for any target (unitarity of U); for a permutation target
+    # rad is the energy off the diagonal of U T^dagger / size
+    rng = np.random.default_rng(12)
+    for n in (1, 2, 3, 4):
+        lib = oracle.lib_table(1, n)
+        for _ in range(20):
+            c = [int(x) for x in rng.choice(lib, 9)]
+            U = oracle.unitary(n, c)
+            Tg = oracle.unitary(n, [int(x) for x in rng.choice(lib, 5)])
+            fP, gP, rad = oracle.fitness_pi(n, c, Tg)
+            assert abs(rad + gP - 1) < 1e-12
+            assert abs(gP - (np.abs(U) ** 2 * np.abs(Tg) ** 2).sum() / (1 << n)) < 1e-12
+            perm = rng.permutation(1 << n)
+            P = perm_matrix(n, lambda i: int(perm[i]))
+            fP, gP, rad = oracle.fitness_pi(n, c, P)
+            M = U @ P.conj().T
+            off = (np.abs(M) ** 2).sum() - (np.abs(np.diag(M)) ** 2).sum()
+            assert abs(rad - off / (1 << n)) < 1e-12
+            assert abs(fP - (1 - math.sqrt(max(0.0, min(1.0, off / (1 << n)))))) < 1e-12
