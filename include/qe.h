@@ -91,7 +91,21 @@ enum { QE_DEVERR_DESC = 1,      /* invalid gate descriptor */
  *                  targets + target_offsets[b] (int64, complex elements).
  *   targets        complex64 (FP32/MFMA paths) or complex128 (FP64 calls),
  *                  2^n x 2^n row-major per target.
- *   num_target_elems  complex elements in `targets` (bounds). */
+ *   num_target_elems  complex elements in `targets` (bounds).
+ *   fitness_mode   QE_FIT_EQ11 (0) or QE_FIT_PHASE_INSENSITIVE (1).
+ *
+ * Fitness modes.  QE_FIT_EQ11: Eq. 11 as printed, f = 1 - sqrt((2^n -
+ * |tr(T^dagger U)|) / 2^n), computed through the exact identity 2^n - |tr| =
+ * 1/2 ||U T^dagger - e^{i arg tr} I||_F^2 (g = |tr| / 2^n, delta = 2^n - |tr|).
+ * QE_FIT_PHASE_INSENSITIVE: f = 1 - sqrt(r) with r = sum_{i != j}
+ * |(U T^dagger)_ij|^2 / 2^n, clamped to [0, 1] (g = 1 - r, delta = 2^n r).
+ * For a unitary U, 1 - r = sum_i |(U T^dagger)_ii|^2 / 2^n, which for a
+ * permutation target T (the paper's targets) equals sum_ij |U_ij|^2
+ * |T_ij|^2 / 2^n, the phase-insensitive reading of Eq. 11 under which the
+ * paper's Table II figure reproduces; it ignores the global phase and
+ * phases applied after the circuit. */
+enum { QE_FIT_EQ11 = 0, QE_FIT_PHASE_INSENSITIVE = 1 };
+
 typedef struct {
     int32_t num_circuits;
     int32_t uniform_n;
@@ -104,10 +118,12 @@ typedef struct {
     const int64_t* target_offsets_dev;
     const void* targets_dev;
     int64_t num_target_elems;
+    int32_t fitness_mode;
 } qe_batch;
 
 /* Fitness of every circuit of the batch against its target, Eq. 11 of
- * Sec. IV-E (the hot path).  path: QE_PATH_*.  f_dev [B] required; g_dev,
+ * Sec. IV-E (the hot path; batch->fitness_mode selects the phase-insensitive
+ * mode).  path: QE_PATH_*.  f_dev [B] required; g_dev,
  * delta_dev [B] optional (NULL).  The 2^n x 2^n product U T^dagger is built
  * gate by gate from T^dagger (FP32 paths) or block by block (MFMA paths:
  * uniform width 5 or 6 only, QE_ERR_UNSUPPORTED otherwise).  Circuits whose
@@ -143,7 +159,8 @@ qe_status qe_device_errors(int32_t* flags_host);
  *   prob_mutation (probabilityOfMutation, QEQEA) in [0, 1];
  *   mutation_range (mutationRange, radians) in [0, 2 pi);
  *   ga_crossover_prob, ga_gene_mutation_prob in [0, 1] (GA);
- *   seed: the Philox4x32-10 key.
+ *   seed: the Philox4x32-10 key;
+ *   fitness_mode: QE_FIT_* (the fitness the search maximises; see qe_batch).
  * QEQEA uses the library {I, NOT, CNOT, CV, CV+} only. */
 typedef struct {
     int32_t n_qubits;
@@ -157,6 +174,7 @@ typedef struct {
     float ga_crossover_prob;
     float ga_gene_mutation_prob;
     uint64_t seed;
+    int32_t fitness_mode;
 } qe_problem;
 
 /* Creates a context on the current device: allocates the ctx-owned encoding

@@ -150,6 +150,8 @@ qe_status to_args(const qe_batch* b, BatchArgs* a, bool need_targets) {
     if (b->uniform_L > 0 && (int64_t)b->num_circuits * b->uniform_L > b->num_gates)
         return fail(QE_ERR_INVALID, "num_circuits * uniform_L exceeds num_gates");
     if (b->num_gates > 0 && !b->gates_dev) return fail(QE_ERR_INVALID, "gates_dev is NULL");
+    if (b->fitness_mode != QE_FIT_EQ11 && b->fitness_mode != QE_FIT_PHASE_INSENSITIVE)
+        return fail(QE_ERR_INVALID, "unknown fitness_mode");
     if (need_targets) {
         if (b->target_stride < 0 && b->num_circuits > 0 && !b->target_offsets_dev)
             return fail(QE_ERR_INVALID, "target_stride < 0 needs target_offsets_dev");
@@ -172,6 +174,7 @@ qe_status to_args(const qe_batch* b, BatchArgs* a, bool need_targets) {
     a->toff = b->target_offsets_dev;
     a->targets = b->targets_dev;
     a->num_telems = b->num_target_elems;
+    a->mode = b->fitness_mode;
     return device_error_word(&a->err);
 }
 
@@ -376,6 +379,8 @@ qe_status qe_create(const qe_problem* p, qe_ctx** out) {
     if (!(p->mutation_range >= 0 && p->mutation_range < pi2)) return fail(QE_ERR_INVALID, "mutation_range must be in [0, 2 pi)");
     if (!(p->ga_crossover_prob >= 0 && p->ga_crossover_prob <= 1)) return fail(QE_ERR_INVALID, "ga_crossover_prob must be in [0,1]");
     if (!(p->ga_gene_mutation_prob >= 0 && p->ga_gene_mutation_prob <= 1)) return fail(QE_ERR_INVALID, "ga_gene_mutation_prob must be in [0,1]");
+    if (p->fitness_mode != QE_FIT_EQ11 && p->fitness_mode != QE_FIT_PHASE_INSENSITIVE)
+        return fail(QE_ERR_INVALID, "unknown fitness_mode");
     const size_t L = p->size_of_individual, P = p->size_of_population, I = p->n_instances;
     const size_t S = (size_t)n * n * L * P, Q = (size_t)n * L * P;
     if ((uint64_t)S >= (1ull << 32) || I * P * L >= (1ull << 32))
@@ -391,6 +396,7 @@ qe_status qe_create(const qe_problem* p, qe_ctx** out) {
     LoopArgs& a = c->la;
     a.n = n; a.lib = p->library; a.L = (int)L; a.P = (int)P; a.I = (int)I;
     a.seed = p->seed;
+    a.fit_mode = p->fitness_mode;
     a.thr_pm = prob_threshold((double)p->prob_mutation);
     a.thr_pc = prob_threshold((double)p->ga_crossover_prob);
     a.thr_pg = prob_threshold((double)p->ga_gene_mutation_prob);
@@ -605,6 +611,7 @@ qe_status qe_get_best(qe_ctx* c, int32_t inst, uint16_t* gates_host, float* f32_
         b.target_stride = 0;
         b.targets_dev = c->la.target64 + (size_t)2 * inst * c->N * c->N;
         b.num_target_elems = (int64_t)c->N * c->N;
+        b.fitness_mode = c->prob.fitness_mode;
         double* d = nullptr;
         QE_HIP(hipMalloc(&d, sizeof(double)));
         qe_status st = qe_eval_fitness_fp64(&b, d, nullptr, nullptr, nullptr);

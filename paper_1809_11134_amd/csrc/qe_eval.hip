@@ -34,7 +34,7 @@ __global__ __launch_bounds__(64 * WPB) void wave_kernel(BatchArgs a, float* __re
             return p < L ? (uint32_t)gp[p] : 0u;
         };
         const float* T = reinterpret_cast<const float*>(a.targets) + 2 * it.toff;
-        const bool ok = run_width<NQ, false>(NQ, T, L, src, nullptr, &o);
+        const bool ok = run_width<NQ, false>(NQ, T, L, src, nullptr, &o, a.mode);
         if (!ok) {
             it.err = QE_DEVERR_DESC;
             o = FitOut{__builtin_nanf(""), __builtin_nanf(""), __builtin_nanf("")};
@@ -119,13 +119,14 @@ __global__ __launch_bounds__(64 * W) void lds32_kernel(BatchArgs a, float* __res
         float D = 0.0f;
 #pragma unroll
         for (int w = 0; w < W; ++w) D += red[w][0];
-        const float dlt = 0.5f * (offs + D);
+        float dlt = 0.5f * (offs + D);
         float q = fminf(fmaxf(dlt / (float)N, 0.0f), 1.0f);
-        float fv = 1.0f - sqrtf(q);
+        float fv = 1.0f - sqrtf(q), gv = am / (float)N;
+        if (a.mode == QE_FIT_PHASE_INSENSITIVE) fitness_pi(offs, N, &fv, &gv, &dlt);
         const float nan = __builtin_nanf("");
         if (ok && !(fv == fv)) it.err = QE_DEVERR_NUMERIC;
         f[b] = ok ? fv : nan;
-        if (g) g[b] = ok ? am / (float)N : nan;
+        if (g) g[b] = ok ? gv : nan;
         if (delta) delta[b] = ok ? dlt : nan;
         if (it.err) atomicOr(a.err, it.err);
     }
@@ -190,7 +191,7 @@ __device__ __forceinline__ void mix_lds_item(const BatchArgs& a, int b, float2* 
         if (!ok) it.err = QE_DEVERR_DESC;
     }
     float gv, dv;
-    const float fv = group_fitness<W>(off, dg, red, 1 << NQ, &gv, &dv);
+    const float fv = group_fitness<W>(off, dg, red, 1 << NQ, &gv, &dv, a.mode);
     if (b >= 0 && wave % W == 0 && lane == 0) {
         const float nan = __builtin_nanf("");
         if (ok && !(fv == fv)) it.err = QE_DEVERR_NUMERIC;
@@ -216,7 +217,7 @@ __device__ __forceinline__ void mix_wave_item(const BatchArgs& a, int b, float* 
             return p < L ? (uint32_t)gp[p] : 0u;
         };
         const float* T = reinterpret_cast<const float*>(a.targets) + 2 * it.toff;
-        if (!run_small_path<NQ, false>(T, L, src, nullptr, &o)) {
+        if (!run_small_path<NQ, false>(T, L, src, nullptr, &o, a.mode)) {
             it.err = QE_DEVERR_DESC;
             o = FitOut{__builtin_nanf(""), __builtin_nanf(""), __builtin_nanf("")};
         } else if (!(o.f == o.f)) {
@@ -281,7 +282,7 @@ __global__ __launch_bounds__(256) void lds_kernel(BatchArgs a, Real* __restrict_
     Real* U = nullptr;
     if (IDENT) U = U_out + (size_t)2 * ((size_t)1 << (2 * a.uniform_n)) * b;
     lds_generic_body<Real, IDENT>(it.n, it.L, it.g, T, it.err, f + (f ? b : 0),
-                                  g ? g + b : nullptr, delta ? delta + b : nullptr, U, a.err);
+                                  g ? g + b : nullptr, delta ? delta + b : nullptr, U, a.err, a.mode);
 }
 
 // ------------------------------------------------------------------ launchers

@@ -244,12 +244,31 @@ struct FitOut {
     float f, g, delta;
 };
 
+// Phase-insensitive fitness (QE_FIT_PHASE_INSENSITIVE) from the energy of M
+// off its diagonal: for unitary M, 1 - sum_i |M_ii|^2 / N = off / N, so the
+// radicand needs no subtraction.
+template <typename Real>
+__device__ __forceinline__ void fitness_pi(Real offs, int N, Real* f, Real* g, Real* delta) {
+    const Real r = offs / (Real)N;
+    const Real q = r < (Real)0 ? (Real)0 : (r > (Real)1 ? (Real)1 : r);
+    *f = (Real)1 - sqrt(q);
+    *g = (Real)1 - r;
+    *delta = offs;
+}
+
 // Reduction of M (held as per-lane partial sums: off-diagonal |m|^2 and the
-// lane's diagonal element, if any) into Eq. 11.
+// lane's diagonal element, if any) into Eq. 11, or (mode) the
+// phase-insensitive fitness.
 __device__ __forceinline__ FitOut finish_fitness(float off, float dre, float dim, bool hasd,
-                                                 int N) {
-    const float tre = wave_sum(dre), tim = wave_sum(dim);
+                                                 int N, int mode = QE_FIT_EQ11) {
     const float offs = wave_sum(off);
+    if (mode == QE_FIT_PHASE_INSENSITIVE) {
+        FitOut o;
+        fitness_pi(offs, N, &o.f, &o.g, &o.delta);
+        if (!(o.f == o.f)) o.f = __builtin_nanf("");
+        return o;
+    }
+    const float tre = wave_sum(dre), tim = wave_sum(dim);
     const float a = sqrtf(tre * tre + tim * tim);
     float er = 1.0f, ei = 0.0f;
     if (a > 0.0f) { er = tre / a; ei = tim / a; }
@@ -276,7 +295,8 @@ __device__ __forceinline__ FitOut finish_fitness(float off, float dre, float dim
 // Returns false if a descriptor was invalid (the result is then garbage).
 template <int NQ, bool IDENT, typename GateSrc>
 __device__ __forceinline__ bool run_register_path(const float* __restrict__ T, int L,
-                                                  GateSrc&& src, float* U_out, FitOut* fit) {
+                                                  GateSrc&& src, float* U_out, FitOut* fit,
+                                                  int mode = QE_FIT_EQ11) {
     constexpr int N = 1 << NQ;
     constexpr int E = N * N / 64;
     constexpr int EB = 2 * NQ - 6;
@@ -375,7 +395,7 @@ __device__ __forceinline__ bool run_register_path(const float* __restrict__ T, i
             dre = dg ? re[k] : dre;
             dim = dg ? im[k] : dim;
         }
-        *fit = finish_fitness(off, dre, dim, key >= 0, N);
+        *fit = finish_fitness(off, dre, dim, key >= 0, N, mode);
     }
     return ok;
 }
@@ -385,7 +405,7 @@ __device__ __forceinline__ bool run_register_path(const float* __restrict__ T, i
 // a lane xor.  Lanes >= N^2 hold nothing and only exchange among themselves.
 template <int NQ, bool IDENT, typename GateSrc>
 __device__ __forceinline__ bool run_small_path(const float* __restrict__ T, int L, GateSrc&& src,
-                                               float* U_out, FitOut* fit) {
+                                               float* U_out, FitOut* fit, int mode = QE_FIT_EQ11) {
     constexpr int N = 1 << NQ;
     const int lane = (int)lane_id();
     const bool live = lane < N * N;
@@ -442,7 +462,7 @@ __device__ __forceinline__ bool run_small_path(const float* __restrict__ T, int 
     if (fit) {
         const bool dg = live && (i == j);
         const float off = (live && !dg) ? mr * mr + mi * mi : 0.0f;
-        *fit = finish_fitness(off, dg ? mr : 0.0f, dg ? mi : 0.0f, dg, N);
+        *fit = finish_fitness(off, dg ? mr : 0.0f, dg ? mi : 0.0f, dg, N, mode);
     }
     return ok;
 }
@@ -710,7 +730,8 @@ __device__ __forceinline__ Real block_sum(Real v, Real* scratch) {
 template <typename Real, bool IDENT>
 __device__ __forceinline__ void lds_generic_body(int n, int L, const uint16_t* gates,
                                                  const Real* T, uint32_t err, Real* f, Real* g,
-                                                 Real* delta, Real* U, uint32_t* errw) {
+                                                 Real* delta, Real* U, uint32_t* errw,
+                                                 int mode = QE_FIT_EQ11) {
     __shared__ Real Mr[4096], Mi[4096];
     __shared__ Real red[8];
     const int tid = threadIdx.x, nt = blockDim.x;
@@ -787,13 +808,19 @@ __device__ __forceinline__ void lds_generic_body(int n, int L, const uint16_t* g
         }
     D = block_sum(D, red);
     if (tid == 0) {
-        const Real dl = (Real)0.5 * (off + D);
-        Real q = dl / (Real)N;
-        q = q < 0 ? (Real)0 : (q > 1 ? (Real)1 : q);
-        const Real fv = (Real)1 - sqrt(q);
+        Real fv, gv, dl;
+        if (mode == QE_FIT_PHASE_INSENSITIVE) {
+            fitness_pi(off, N, &fv, &gv, &dl);
+        } else {
+            dl = (Real)0.5 * (off + D);
+            Real q = dl / (Real)N;
+            q = q < 0 ? (Real)0 : (q > 1 ? (Real)1 : q);
+            fv = (Real)1 - sqrt(q);
+            gv = am / (Real)N;
+        }
         if (ok && !(fv == fv)) err = QE_DEVERR_NUMERIC;
         if (f) *f = ok ? fv : nan;
-        if (g) *g = ok ? am / (Real)N : nan;
+        if (g) *g = ok ? gv : nan;
         if (delta) *delta = ok ? dl : nan;
         if (err) atomicOr(errw, err);
     }
@@ -806,10 +833,25 @@ __device__ __forceinline__ void lds_generic_body(int n, int L, const uint16_t* g
 // red: 4 x 3 floats of LDS.  Returns the fitness on every lane; g, delta out.
 template <int W>
 __device__ __forceinline__ float group_fitness(float off, float2 dg, float (*red)[3], int N,
-                                               float* g_out, float* delta_out) {
+                                               float* g_out, float* delta_out,
+                                               int mode = QE_FIT_EQ11) {
     const int lane = (int)lane_id(), wave = (int)(threadIdx.x >> 6);
     const int gb = (wave / W) * W, CW = N / W;
     const float offw = wave_sum(off), trw = wave_sum(dg.x), tiw = wave_sum(dg.y);
+    if (mode == QE_FIT_PHASE_INSENSITIVE) {
+        float offs = offw;
+        if constexpr (W > 1) {
+            __syncthreads();
+            if (lane == 0) red[wave][0] = offw;
+            __syncthreads();
+            offs = 0.0f;
+#pragma unroll
+            for (int w = 0; w < W; ++w) offs += red[gb + w][0];
+        }
+        float fv;
+        fitness_pi(offs, N, &fv, g_out, delta_out);
+        return fv;
+    }
     if constexpr (W == 1) {   // one wavefront per circuit: no LDS exchange
         const float am = sqrtf(trw * trw + tiw * tiw);
         float er = 1.0f, ei = 0.0f;
@@ -849,23 +891,23 @@ __device__ __forceinline__ float group_fitness(float off, float2 dg, float (*red
 
 template <bool IDENT, typename GateSrc>
 __device__ __forceinline__ bool run_any_width(int n, const float* __restrict__ T, int L,
-                                              GateSrc&& src, float* U_out, FitOut* fit) {
+                                              GateSrc&& src, float* U_out, FitOut* fit, int mode) {
     switch (n) {
-        case 1: return run_small_path<1, IDENT>(T, L, src, U_out, fit);
-        case 2: return run_small_path<2, IDENT>(T, L, src, U_out, fit);
-        case 3: return run_small_path<3, IDENT>(T, L, src, U_out, fit);
-        case 4: return run_register_path<4, IDENT>(T, L, src, U_out, fit);
-        case 5: return run_register_path<5, IDENT>(T, L, src, U_out, fit);
-        default: return run_register_path<6, IDENT>(T, L, src, U_out, fit);
+        case 1: return run_small_path<1, IDENT>(T, L, src, U_out, fit, mode);
+        case 2: return run_small_path<2, IDENT>(T, L, src, U_out, fit, mode);
+        case 3: return run_small_path<3, IDENT>(T, L, src, U_out, fit, mode);
+        case 4: return run_register_path<4, IDENT>(T, L, src, U_out, fit, mode);
+        case 5: return run_register_path<5, IDENT>(T, L, src, U_out, fit, mode);
+        default: return run_register_path<6, IDENT>(T, L, src, U_out, fit, mode);
     }
 }
 
 template <int NQ, bool IDENT, typename GateSrc>
 __device__ __forceinline__ bool run_width(int n, const float* __restrict__ T, int L, GateSrc&& src,
-                                          float* U_out, FitOut* fit) {
-    if constexpr (NQ == 0) return run_any_width<IDENT>(n, T, L, src, U_out, fit);
-    else if constexpr (NQ <= 3) return run_small_path<NQ, IDENT>(T, L, src, U_out, fit);
-    else return run_register_path<NQ, IDENT>(T, L, src, U_out, fit);
+                                          float* U_out, FitOut* fit, int mode = QE_FIT_EQ11) {
+    if constexpr (NQ == 0) return run_any_width<IDENT>(n, T, L, src, U_out, fit, mode);
+    else if constexpr (NQ <= 3) return run_small_path<NQ, IDENT>(T, L, src, U_out, fit, mode);
+    else return run_register_path<NQ, IDENT>(T, L, src, U_out, fit, mode);
 }
 
 }  // namespace qe

@@ -18,6 +18,7 @@ struct BatchArgs {
     const int64_t* toff;
     const void* targets;
     int64_t num_telems;
+    int32_t mode;           // QE_FIT_*
     uint32_t* err;          // device error word (atomicOr of QE_DEVERR_*)
 };
 
@@ -67,6 +68,7 @@ struct QutritRec {
 // Encoding-state arguments of the QEQEA / GA loop kernels.
 struct LoopArgs {
     int32_t n, lib, L, P, I;
+    int32_t fit_mode;                  // QE_FIT_*
     uint64_t seed;
     uint64_t thr_pm, thr_pc, thr_pg;   // probability thresholds, floor(p * 2^32)
     float r32;                         // mutation step per unit (1 - segFit), in 2^-32 turns

@@ -223,14 +223,14 @@ __device__ __forceinline__ void eval_circuit(const LoopArgs& a, uint32_t gen, ui
     bool ok;
     if constexpr (W == 0) {
         FitOut o;
-        ok = run_width<NQ, false>(NQ, T, L, src, nullptr, &o);
+        ok = run_width<NQ, false>(NQ, T, L, src, nullptr, &o, a.fit_mode);
         fv = o.f;
     } else {
         constexpr int N = 1 << NQ;
         float off, gd, dd;
         float2 dg;
         ok = run_lds_path<NQ, W, false>(M, gt, T, L, src, &off, &dg, W == 1 ? 0 : -1);
-        fv = group_fitness<W>(off, dg, red, N, &gd, &dd);
+        fv = group_fitness<W>(off, dg, red, N, &gd, &dd, a.fit_mode);
     }
     if (!ok) fv = __builtin_nanf("");
     if (writer && lane == 0) {
@@ -733,7 +733,7 @@ __global__ __launch_bounds__(256) void elite_eval_kernel(LoopArgs a, const uint1
     const uint16_t* g = gates + ((size_t)i * a.P + (err ? 0 : c)) * a.L;
     const double* T = a.target64 + (size_t)2 * i * ((size_t)1 << (2 * a.n));
     lds_generic_body<double, false>(a.n, a.L, g, T, err, f64 + blockIdx.x, nullptr, nullptr,
-                                    nullptr, a.err);
+                                    nullptr, a.err, a.fit_mode);
 }
 
 // Complex128 -> complex64 copy of the targets for the FP32 path.

@@ -298,13 +298,14 @@ __global__ __launch_bounds__(64 * (1 << (NQ - 4))) void mfma_kernel(BatchArgs a,
         float D = 0.0f;
 #pragma unroll
         for (int w = 0; w < W; ++w) D += red[w][0];
-        const float dlt = 0.5f * (offs + D);
+        float dlt = 0.5f * (offs + D);
         const float q = fminf(fmaxf(dlt / (float)N, 0.0f), 1.0f);
-        const float fv = 1.0f - sqrtf(q);
+        float fv = 1.0f - sqrtf(q), gv = am / (float)N;
+        if (a.mode == QE_FIT_PHASE_INSENSITIVE) fitness_pi(offs, N, &fv, &gv, &dlt);
         const float nan = __builtin_nanf("");
         if (ok && !(fv == fv)) it.err = QE_DEVERR_NUMERIC;
         f[b] = ok ? fv : nan;
-        if (g) g[b] = ok ? am / (float)N : nan;
+        if (g) g[b] = ok ? gv : nan;
         if (delta) delta[b] = ok ? dlt : nan;
         if (it.err) atomicOr(a.err, it.err);
     }

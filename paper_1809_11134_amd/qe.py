@@ -15,6 +15,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "qe.h")
 QE_OK, QE_ERR_INVALID, QE_ERR_UNSUPPORTED, QE_ERR_DEVICE, QE_ERR_OOM, QE_ERR_NUMERIC, QE_ERR_STATE = range(7)
 LIB_NCV, LIB_HT_NCV = 0, 1
 ALG_QEQEA, ALG_GA = 0, 1
+FIT_EQ11, FIT_PHASE_INSENSITIVE = 0, 1
 (PATH_FP32, PATH_FP32_REG, PATH_FP32_LDS, PATH_MFMA_BF16, PATH_MFMA_FP16, PATH_MFMA_BF16_RAW,
  PATH_MFMA_FP16_RAW) = range(7)
 DEVERR_DESC, DEVERR_WIDTH, DEVERR_RANGE, DEVERR_NUMERIC = 1, 2, 4, 8
@@ -32,7 +33,7 @@ class Batch(ctypes.Structure):
                 ("gate_offsets_dev", ctypes.c_void_p), ("gates_dev", ctypes.c_void_p),
                 ("num_gates", ctypes.c_int64), ("target_stride", ctypes.c_int64),
                 ("target_offsets_dev", ctypes.c_void_p), ("targets_dev", ctypes.c_void_p),
-                ("num_target_elems", ctypes.c_int64)]
+                ("num_target_elems", ctypes.c_int64), ("fitness_mode", ctypes.c_int32)]
 
 
 class Problem(ctypes.Structure):
@@ -41,7 +42,7 @@ class Problem(ctypes.Structure):
                 ("size_of_population", ctypes.c_int32), ("n_instances", ctypes.c_int32),
                 ("prob_mutation", ctypes.c_float), ("mutation_range", ctypes.c_float),
                 ("ga_crossover_prob", ctypes.c_float), ("ga_gene_mutation_prob", ctypes.c_float),
-                ("seed", ctypes.c_uint64)]
+                ("seed", ctypes.c_uint64), ("fitness_mode", ctypes.c_int32)]
 
 
 _lib = None
@@ -134,7 +135,8 @@ def _gates(t):
     return t.contiguous()
 
 
-def make_batch(gates, targets, n=None, L=None, nq=None, goff=None, toff=None, target_stride=None):
+def make_batch(gates, targets, n=None, L=None, nq=None, goff=None, toff=None, target_stride=None,
+               fitness_mode=0):
     """Builds a qe_batch from device tensors.  gates: int16/int32 descriptors
     ([B, L] for uniform lengths, flat with goff for uneven); targets: complex
     tensor ([T, N, N] or flat); n: uniform width or None with nq (int8 [B]);
@@ -163,6 +165,7 @@ def make_batch(gates, targets, n=None, L=None, nq=None, goff=None, toff=None, ta
         b.n_qubits_dev = nq.data_ptr()
     b.gates_dev = g.data_ptr() if g.numel() else None
     b.num_gates = g.numel()
+    b.fitness_mode = fitness_mode
     if targets is not None:
         t = targets.contiguous()
         keep.append(t)
@@ -179,11 +182,12 @@ def make_batch(gates, targets, n=None, L=None, nq=None, goff=None, toff=None, ta
 
 
 def eval_fitness(gates, targets, n=None, L=None, nq=None, goff=None, toff=None, target_stride=0,
-                 path=PATH_FP32, want_g=False, want_delta=False, stream=None):
-    """Eq. 11 fitness of a batch on the FP32 path.  targets complex64.
-    Returns (f, g or None, delta or None) as float32 device tensors."""
+                 path=PATH_FP32, want_g=False, want_delta=False, stream=None, fitness_mode=0):
+    """Eq. 11 fitness (or, with fitness_mode=FIT_PHASE_INSENSITIVE, the
+    phase-insensitive fitness) of a batch on the FP32 or MFMA paths.  targets
+    complex64.  Returns (f, g or None, delta or None) as float32 tensors."""
     targets = targets.to(torch.complex64) if targets.dtype != torch.complex64 else targets
-    b, keep, B = make_batch(gates, targets, n, L, nq, goff, toff, target_stride)
+    b, keep, B = make_batch(gates, targets, n, L, nq, goff, toff, target_stride, fitness_mode)
     dev = targets.device
     f = torch.empty(B, dtype=torch.float32, device=dev)
     g = torch.empty(B, dtype=torch.float32, device=dev) if want_g else None
@@ -193,9 +197,9 @@ def eval_fitness(gates, targets, n=None, L=None, nq=None, goff=None, toff=None, 
 
 
 def eval_fitness_fp64(gates, targets, n=None, L=None, nq=None, goff=None, toff=None,
-                      target_stride=0, want_g=False, want_delta=False, stream=None):
+                      target_stride=0, want_g=False, want_delta=False, stream=None, fitness_mode=0):
     targets = targets.to(torch.complex128) if targets.dtype != torch.complex128 else targets
-    b, keep, B = make_batch(gates, targets, n, L, nq, goff, toff, target_stride)
+    b, keep, B = make_batch(gates, targets, n, L, nq, goff, toff, target_stride, fitness_mode)
     dev = targets.device
     f = torch.empty(B, dtype=torch.float64, device=dev)
     g = torch.empty(B, dtype=torch.float64, device=dev) if want_g else None
@@ -242,11 +246,12 @@ class Context:
 
     def __init__(self, n, library, algorithm, L, P, instances=1, prob_mutation=0.1,
                  mutation_range=0.7853981633974483, ga_crossover_prob=0.9,
-                 ga_gene_mutation_prob=None, seed=0):
+                 ga_gene_mutation_prob=None, seed=0, fitness_mode=0):
         if ga_gene_mutation_prob is None:
             ga_gene_mutation_prob = 1.0 / L
         self.problem = Problem(n, library, algorithm, L, P, instances, prob_mutation,
-                               mutation_range, ga_crossover_prob, ga_gene_mutation_prob, seed)
+                               mutation_range, ga_crossover_prob, ga_gene_mutation_prob, seed,
+                               fitness_mode)
         self.n, self.L, self.P, self.I = n, L, P, instances
         self.algorithm = algorithm
         h = ctypes.c_void_p(0)

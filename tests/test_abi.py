@@ -37,7 +37,8 @@ def test_lib_tables_match_oracle(oracle):
 def _problem(**kw):
     base = dict(n_qubits=3, library=0, algorithm=0, size_of_individual=10,
                 size_of_population=8, n_instances=1, prob_mutation=0.1,
-                mutation_range=0.78, ga_crossover_prob=0.9, ga_gene_mutation_prob=0.1, seed=1)
+                mutation_range=0.78, ga_crossover_prob=0.9, ga_gene_mutation_prob=0.1, seed=1,
+                fitness_mode=0)
     base.update(kw)
     return qe.Problem(*[base[f] for f, _ in qe.Problem._fields_])
 
@@ -58,6 +59,8 @@ def _problem(**kw):
     (dict(prob_mutation=float("nan")), qe.QE_ERR_INVALID),
     (dict(mutation_range=7.0), qe.QE_ERR_INVALID),
     (dict(ga_crossover_prob=-0.1), qe.QE_ERR_INVALID),
+    (dict(fitness_mode=5), qe.QE_ERR_INVALID),
+    (dict(fitness_mode=-1), qe.QE_ERR_INVALID),
 ])
 def test_create_rejects_bad_problems(lib, kw, status):
     h = ctypes.c_void_p(0)
