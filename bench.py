@@ -167,6 +167,37 @@ def secondary_precision(dev, reps=5):
     return out
 
 
+def secondary_phase_insensitive(dev, gens=100):
+    """The bench workload (n=4, P=4096, L=30) with the search maximising the
+    phase-insensitive fitness (QE_FIT_PHASE_INSENSITIVE): a graph of `gens`
+    whole generations."""
+    import numpy as np
+    import torch
+    from paper_1809_11134_amd import inputs, qe
+    w = inputs.workload_qeqea_n4()
+    n, L, P, I = w["n"], w["L"], w["P"], w["instances"]
+    tg = torch.from_numpy(np.stack(w["target_gates"]).astype(np.int16)).to(dev)
+    T = qe.build_unitary(tg, n, tg.shape[1], precision=1)
+    ctx = qe.Context(n, w["lib"], qe.ALG_QEQEA, L, P, I, prob_mutation=0.1,
+                     mutation_range=math.pi / 4, seed=w["seed"], fitness_mode=qe.FIT_PHASE_INSENSITIVE)
+    ctx.set_targets(T)
+    hist = torch.empty((gens, I * P), dtype=torch.float32, device=dev)
+    ctx.graph_prepare(gens, hist)
+    ctx.run_graph(0, gens, hist)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    ctx.run_graph(gens, gens, hist)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    best = ctx.get_best(0)
+    ctx.close()
+    return {"workload": w["name"] + "_phase_insensitive", "generations": gens,
+            "evals_per_s": gens * I * P / (ms * 1e-3), "ms_per_generation": ms / gens,
+            "best_f_fp32": best[1], "best_f_fp64": best[2]}
+
+
 def secondary_qeqea_n5(dev, gens=20):
     """n=5, library {I,NOT,CNOT,CV,CV+}, 1024 QEQEA populations x 64 circuits x
     40 gates (65536 evaluations per generation): a graph of `gens` whole
@@ -237,8 +268,9 @@ def main():
                          "of known traffic that scales the FETCH_SIZE / WRITE_SIZE counters)")
     ap.add_argument("--no-secondary", action="store_true",
                     help="skip the n=6 precision study, the n=5 QEQEA loop and the uneven batch")
-    ap.add_argument("--secondary", default="precision,qeqea_n5,uneven",
-                    help="comma list of the secondary workloads to run (precision, qeqea_n5, uneven)")
+    ap.add_argument("--secondary", default="precision,qeqea_n5,uneven,phase_insensitive",
+                    help="comma list of the secondary workloads to run (precision, qeqea_n5, "
+                         "uneven, phase_insensitive)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the hot path runs on a single MI355X (independent "
@@ -336,7 +368,7 @@ def main():
 
     secondary = None
     which = set() if args.no_secondary else {s.strip() for s in args.secondary.split(",") if s.strip()}
-    unknown = which - {"precision", "qeqea_n5", "uneven"}
+    unknown = which - {"precision", "qeqea_n5", "uneven", "phase_insensitive"}
     if unknown:
         ap.error(f"unknown secondary workloads: {sorted(unknown)}")
     if which:
@@ -350,6 +382,9 @@ def main():
         if "uneven" in which:
             log("secondary: uneven batch")
             secondary["uneven"] = secondary_uneven(dev)
+        if "phase_insensitive" in which:
+            log("secondary: bench workload with the phase-insensitive fitness")
+            secondary["phase_insensitive"] = secondary_phase_insensitive(dev)
         assert qe.device_errors() == 0, "device error flags raised"
 
     cpu = None

@@ -281,3 +281,24 @@ def test_phase_insensitive_forms_agree(oracle):
             off = (np.abs(M) ** 2).sum() - (np.abs(np.diag(M)) ** 2).sum()
             assert abs(rad - off / (1 << n)) < 1e-12
             assert abs(fP - (1 - math.sqrt(max(0.0, min(1.0, off / (1 << n)))))) < 1e-12
+
+
+def cccnot_fn(i):
+    b = [(i >> (3 - w)) & 1 for w in range(4)]
+    b[0] ^= b[1] & b[2] & b[3]
+    return (b[0] << 3) | (b[1] << 2) | (b[2] << 1) | b[3]
+
+
+def test_table3_cccnot_value_is_the_identity_plateau(oracle):
+    # Table III prints 0.6464 for the QEQEA on CCCNOT (stopped at the
+    # generation limit).  Under the phase-insensitive reading that is exactly
+    # the fitness of a circuit agreeing with CCCNOT on 14 of its 16 basis
+    # states -- the identity, for one: 1 - sqrt(2/16) = 0.64645
+    T = perm_matrix(4, cccnot_fn)
+    fP, gP, rad = oracle.fitness_pi(4, [0, 0, 0], T)
+    assert abs(gP - 14 / 16) < 1e-15 and abs(rad - 2 / 16) < 1e-15
+    assert abs(fP - (1 - math.sqrt(2 / 16))) < 1e-15
+    assert round(fP, 4) == 0.6464
+    # (for the identity the trace is 14 as well, so Eq. 11 as printed agrees;
+    # the readings differ on circuits with relative phases)
+    assert abs(oracle.fitness(4, [0, 0, 0], T)[0] - (1 - math.sqrt(2 / 16))) < 1e-12
