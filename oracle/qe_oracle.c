@@ -11,7 +11,8 @@
  * What is computed, and in which precision:
  *   - circuit unitaries and the fitness of Eq. 11 (Sec. IV-E) in IEEE double,
  *     by one left-multiplication per gate, the gate embedded on its wires with
- *     the big-endian register convention of Eqs. 1-2 (Sec. III);
+ *     the big-endian register convention of Eqs. 1-2 (Sec. III), for the
+ *     discrete libraries and for the Ising gate model (Eqs. 3-6);
  *   - the counter-based random numbers (Philox4x32-10, Salmon et al., SC'11);
  *   - circuit construction by sampling (Sec. IV-D, Eq. 10), qutrit
  *     measurement (Sec. IV-A/IV-C step 1), segment fitness and elitism
@@ -91,7 +92,8 @@ static uint32_t scale_u32(uint32_t w, uint32_t range)
 /* basis-state index: the first Kronecker factor is the most significant     */
 /* one (Eq. 1), so X on the first qubit exchanges the two halves (Eq. 2).    */
 /* ------------------------------------------------------------------------ */
-enum { K_I = 0, K_NOT = 1, K_CNOT = 2, K_CV = 3, K_CVDG = 4, K_H = 5, K_T = 6 };
+enum { K_I = 0, K_NOT = 1, K_CNOT = 2, K_CV = 3, K_CVDG = 4, K_H = 5, K_T = 6,
+       K_RX = 7, K_RY = 8, K_RZ = 9, K_ZZ = 10 };
 
 static uint16_t mkdesc(int kind, int tgt, int ctl)
 {
@@ -136,6 +138,79 @@ QEO_API int qeo_check_desc(int n, uint16_t d)
     return 0;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Ising gate model (Sec. III, Eqs. 3-6): R_x, R_y, R_z on the target wire    */
+/* and the two-qubit interaction J on the wire pair (target, control field).  */
+/* Every gate carries an angle, a u32 fraction of a full turn:               */
+/* theta = 2 pi u / 2^32 (exact in double), so angles live in [0, 2 pi) and  */
+/* wrap modulo 2 pi as the mutation of Sec. IV-F requires.                   */
+/* ------------------------------------------------------------------------ */
+static int is_ising(int kind) { return kind >= K_RX && kind <= K_ZZ; }
+
+static double angle_of(uint32_t u) { return 2.0 * PI * ((double)u / 4294967296.0); }
+
+/* Returns 0 if the descriptor names a valid gate of either model on n wires
+ * (J needs two distinct wires). */
+QEO_API int qeo_check_desc_ising(int n, uint16_t d)
+{
+    int kind = d & 15, t = (d >> 4) & 15, c = (d >> 8) & 15;
+    if (!is_ising(kind)) return qeo_check_desc(n, d);
+    if (d >> 12) return -1;
+    if (t >= n) return -1;
+    if (kind == K_ZZ && (c >= n || c == t)) return -1;
+    return 0;
+}
+
+/* Eqs. 3-5: R_x(theta) = [[cos, -i sin], [-i sin, cos]],
+ * R_y(theta) = [[cos, -sin], [sin, cos]], R_z(theta) = diag(e^{-i theta/2},
+ * e^{i theta/2}), cos and sin of theta / 2. */
+static void rotation_matrix(int kind, double th, cplx G[2][2])
+{
+    double c = cos(th / 2.0), s = sin(th / 2.0);
+    if (kind == K_RX) {
+        G[0][0] = c; G[0][1] = -I * s; G[1][0] = -I * s; G[1][1] = c;
+    } else if (kind == K_RY) {
+        G[0][0] = c; G[0][1] = -s; G[1][0] = s; G[1][1] = c;
+    } else {
+        G[0][0] = cexp(-I * th / 2.0); G[0][1] = 0; G[1][0] = 0; G[1][1] = cexp(I * th / 2.0);
+    }
+}
+
+/* M <- G M for an Ising gate d with angle u.  The rotations transform row
+ * pairs like any single-qubit gate.  J on wires (a, b) is diagonal: by
+ * Eq. 6, read with the exponent i theta (the printed e^{theta} lacks the i
+ * that unitarity needs), J = e^{-i theta/2} diag(1, e^{i theta}, e^{i theta},
+ * 1) on the two wires, so row i is multiplied by e^{-i theta/2} when the two
+ * wire bits of i agree and by e^{-i theta/2} e^{i theta} when they differ. */
+static void apply_ising(int n, uint16_t d, uint32_t u, cplx* M)
+{
+    int kind = d & 15;
+    int N = 1 << n;
+    int t = (d >> 4) & 15, c = (d >> 8) & 15;
+    double th = angle_of(u);
+    if (kind == K_ZZ) {
+        cplx same = cexp(-I * th / 2.0), diff = cexp(-I * th / 2.0) * cexp(I * th);
+        for (int i = 0; i < N; ++i) {
+            int ba = (i >> (n - 1 - t)) & 1, bb = (i >> (n - 1 - c)) & 1;
+            cplx z = ba == bb ? same : diff;
+            for (int j = 0; j < N; ++j) M[(size_t)i * N + j] *= z;
+        }
+        return;
+    }
+    int tb = 1 << (n - 1 - t);
+    cplx G[2][2];
+    rotation_matrix(kind, th, G);
+    for (int i0 = 0; i0 < N; ++i0) {
+        if (i0 & tb) continue;
+        int i1 = i0 | tb;
+        for (int j = 0; j < N; ++j) {
+            cplx a = M[(size_t)i0 * N + j], b = M[(size_t)i1 * N + j];
+            M[(size_t)i0 * N + j] = G[0][0] * a + G[0][1] * b;
+            M[(size_t)i1 * N + j] = G[1][0] * a + G[1][1] * b;
+        }
+    }
+}
+
 /* M <- G M for the gate d embedded on n wires; M is N x N, row-major.
  * Row pairs (i0, i1 = i0 | target bit) are transformed by the 2x2 matrix;
  * a controlled gate leaves rows whose control bit is 0 unchanged. */
@@ -161,19 +236,28 @@ static void apply_gate(int n, uint16_t d, cplx* M)
     }
 }
 
-/* U = G_{L-1} ... G_1 G_0: the gate listed first acts first.
+/* U = G_{L-1} ... G_1 G_0: the gate listed first acts first.  angles[l]
+ * is the angle of gate l (u32 turn fraction; read for Ising kinds only);
+ * with angles NULL only the discrete kinds are valid.
  * Output U (N*N complex doubles, row-major). Returns 0, or -1 on a bad gate. */
-QEO_API int qeo_unitary(int n, int L, const uint16_t* gates, double* U_out)
+QEO_API int qeo_unitary_ang(int n, int L, const uint16_t* gates, const uint32_t* angles,
+                            double* U_out)
 {
     int N = 1 << n;
     cplx* U = (cplx*)U_out;
     for (int i = 0; i < N * N; ++i) U[i] = 0;
     for (int i = 0; i < N; ++i) U[(size_t)i * N + i] = 1;
     for (int l = 0; l < L; ++l) {
-        if (qeo_check_desc(n, gates[l])) return -1;
-        apply_gate(n, gates[l], U);
+        if (angles ? qeo_check_desc_ising(n, gates[l]) : qeo_check_desc(n, gates[l])) return -1;
+        if (is_ising(gates[l] & 15)) apply_ising(n, gates[l], angles[l], U);
+        else apply_gate(n, gates[l], U);
     }
     return 0;
+}
+
+QEO_API int qeo_unitary(int n, int L, const uint16_t* gates, double* U_out)
+{
+    return qeo_unitary_ang(n, L, gates, NULL, U_out);
 }
 
 /* Eq. 11 of Sec. IV-E: fitness(S) = 1 - sqrt((size - |tr(S^dagger T)|) / size),
@@ -211,17 +295,24 @@ static void fitness_of(int n, const cplx* S, const cplx* T, double out[4])
     out[3] = f_tr;
 }
 
-/* Fitness of one circuit against target T (N*N complex doubles).
- * out = {f, g, delta, f_trace}.  Returns 0 or -1 on a bad gate. */
-QEO_API int qeo_fitness(int n, int L, const uint16_t* gates, const double* T, double out[4])
+/* Fitness of one circuit against target T (N*N complex doubles); angles as
+ * in qeo_unitary_ang.  out = {f, g, delta, f_trace}.  Returns 0 or -1 on a
+ * bad gate. */
+QEO_API int qeo_fitness_ang(int n, int L, const uint16_t* gates, const uint32_t* angles,
+                            const double* T, double out[4])
 {
     int N = 1 << n;
     cplx* S = (cplx*)malloc(sizeof(cplx) * N * N);
     if (!S) return -2;
-    int rc = qeo_unitary(n, L, gates, (double*)S);
+    int rc = qeo_unitary_ang(n, L, gates, angles, (double*)S);
     if (rc == 0) fitness_of(n, S, (const cplx*)T, out);
     free(S);
     return rc;
+}
+
+QEO_API int qeo_fitness(int n, int L, const uint16_t* gates, const double* T, double out[4])
+{
+    return qeo_fitness_ang(n, L, gates, NULL, T, out);
 }
 
 /* Phase-insensitive fitness, the reading under which the paper's Table II
@@ -253,17 +344,23 @@ static void fitness_pi_of(int n, const cplx* S, const cplx* T, double out[3])
     out[2] = rad;
 }
 
-/* Phase-insensitive fitness of one circuit against target T.
- * out = {fP, gP, rad}.  Returns 0 or -1 on a bad gate. */
-QEO_API int qeo_fitness_pi(int n, int L, const uint16_t* gates, const double* T, double out[3])
+/* Phase-insensitive fitness of one circuit against target T; angles as in
+ * qeo_unitary_ang.  out = {fP, gP, rad}.  Returns 0 or -1 on a bad gate. */
+QEO_API int qeo_fitness_pi_ang(int n, int L, const uint16_t* gates, const uint32_t* angles,
+                               const double* T, double out[3])
 {
     int N = 1 << n;
     cplx* S = (cplx*)malloc(sizeof(cplx) * N * N);
     if (!S) return -2;
-    int rc = qeo_unitary(n, L, gates, (double*)S);
+    int rc = qeo_unitary_ang(n, L, gates, angles, (double*)S);
     if (rc == 0) fitness_pi_of(n, S, (const cplx*)T, out);
     free(S);
     return rc;
+}
+
+QEO_API int qeo_fitness_pi(int n, int L, const uint16_t* gates, const double* T, double out[3])
+{
+    return qeo_fitness_pi_ang(n, L, gates, NULL, T, out);
 }
 
 /* A batch of circuits of uneven width and length: circuit b has n[b] wires,
@@ -279,6 +376,33 @@ QEO_API int qeo_eval_batch(int B, const int8_t* nq, const int32_t* goff, const u
     for (int b = 0; b < B; ++b) {
         int rc = qeo_fitness(nq[b], goff[b + 1] - goff[b], gates + goff[b],
                              targets + 2 * toff[b], out + 4 * (size_t)b);
+        if (rc) bad++;
+    }
+    return bad;
+}
+
+/* The same over circuits with angles (angles parallel to gates, NULL for
+ * discrete circuits) and either fitness: mode 0 Eq. 11, out [B][4] =
+ * {f, g, delta, f_trace}; mode 1 the phase-insensitive fitness, out [B][4] =
+ * {fP, gP, rad, 0}.  Returns the number of circuits with a bad gate. */
+QEO_API int qeo_eval_batch_ang(int B, const int8_t* nq, const int32_t* goff, const uint16_t* gates,
+                               const uint32_t* angles, const int64_t* toff, const double* targets,
+                               int mode, double* out)
+{
+    int bad = 0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(+ : bad)
+    for (int b = 0; b < B; ++b) {
+        const uint32_t* ab = angles ? angles + goff[b] : NULL;
+        double* o = out + 4 * (size_t)b;
+        int rc;
+        if (mode == 1) {
+            o[3] = 0.0;
+            rc = qeo_fitness_pi_ang(nq[b], goff[b + 1] - goff[b], gates + goff[b], ab,
+                                    targets + 2 * toff[b], o);
+        } else {
+            rc = qeo_fitness_ang(nq[b], goff[b + 1] - goff[b], gates + goff[b], ab,
+                                 targets + 2 * toff[b], o);
+        }
         if (rc) bad++;
     }
     return bad;
@@ -329,12 +453,30 @@ QEO_API uint16_t qeo_lib_desc(int lib, int n, int idx)
 
 /* ------------------------------------------------------------------------ */
 /* QEQEA encoding (Sec. IV-B, Fig. 4): per population instance, R = n + K    */
-/* regions of L*P qubits (K = n(n-1) ordered wire pairs for the directed     */
-/* library gates), rotation regions r < n first; qutrits only for rotation   */
-/* slots.  Slot index s = r*L*P + ind*L + pos (Eq. 10).                      */
+/* regions of L*P qubits, rotation regions r < n first; qutrits only for     */
+/* rotation slots.  K counts the interaction templates: the C(n,2) unordered */
+/* wire pairs for the Ising library (library 2), the n(n-1) ordered pairs    */
+/* for the directed gates of libraries 0 and 1.                              */
+/* Slot index s = r*L*P + ind*L + pos (Eq. 10).                              */
 /* Qubit angle: u32 fraction of a full turn.  Qutrit: 3 complex amplitudes   */
 /* stored as 6 floats (re0, im0, re1, im1, re2, im2).                        */
 /* ------------------------------------------------------------------------ */
+enum { LIB_ISING = 2 };
+
+QEO_API int qeo_regions(int n, int lib)
+{
+    return lib == LIB_ISING ? n + n * (n - 1) / 2 : n * n;
+}
+
+/* Unordered wire pair k (a < b), lexicographic: (0,1), (0,2), ..., (1,2), ... */
+static void upair_of(int n, int k, int* a, int* b)
+{
+    int x = 0;
+    while (k >= n - 1 - x) { k -= n - 1 - x; ++x; }
+    *a = x;
+    *b = x + 1 + k;
+}
+
 QEO_API uint32_t qeo_segment_index(int L, int P, int region, int ind, int pos)
 {
     return (uint32_t)region * (uint32_t)L * (uint32_t)P + (uint32_t)ind * (uint32_t)L + (uint32_t)pos;
@@ -363,22 +505,39 @@ QEO_API int qeo_measure(const float* q, uint32_t w)
 /* Quarter-turn index of a u32 angle, rounded to the nearest quarter. */
 static int quarter(uint32_t theta) { return (int)(((theta + 0x20000000u) >> 30) & 3u); }
 
-/* Decode slot s of instance inst into a gate (reading of Secs. IV-A and
- * IV-C for a discrete library): a rotation slot on wire w becomes NOT_w when
- * the measured axis is x and the angle is a half turn (R_x(pi) = -iX), else
- * the identity; a template slot on pair (c, t) becomes the controlled
- * V^q, q the angle in quarter turns: I, CV, CNOT, CV+. */
-static uint16_t decode_slot(int n, int L, int P, uint64_t seed, uint32_t gen, uint32_t inst,
-                            uint32_t s, const uint32_t* theta, const float* qutrit)
+/* Decode slot s of instance inst into a gate.
+ * Ising library (Secs. IV-A, IV-C): a rotation slot on wire w becomes the
+ * rotation about the measured axis (x, y, z for outcomes 0, 1, 2) on w, a
+ * template slot on the unordered pair (a, b) the interaction J on (a, b);
+ * either takes the slot's angle (*angle).
+ * Discrete libraries (the reading for {I, NOT, CNOT, CV, CV+}): a rotation
+ * slot on wire w becomes NOT_w when the measured axis is x and the angle is
+ * a half turn (R_x(pi) = -iX), else the identity; a template slot on pair
+ * (c, t) becomes the controlled V^q, q the angle in quarter turns: I, CV,
+ * CNOT, CV+ (*angle = 0). */
+QEO_API uint16_t qeo_decode_slot(int n, int lib, int L, int P, uint64_t seed, uint32_t gen,
+                                 uint32_t inst, uint32_t s, const uint32_t* theta,
+                                 const float* qutrit, uint32_t* angle)
 {
     uint32_t LP = (uint32_t)L * (uint32_t)P;
     uint32_t r = s / LP;
     int q = quarter(theta[s]);
+    *angle = 0;
     if (r < (uint32_t)n) {
         uint32_t w[4];
         draw(seed, TAG_MEASURE, gen, inst, s, w);
         int axis = qeo_measure(qutrit + 6 * (size_t)s, w[0]);
+        if (lib == LIB_ISING) {
+            *angle = theta[s];
+            return mkdesc(K_RX + axis, (int)r, 0);
+        }
         return (axis == 0 && q == 2) ? mkdesc(K_NOT, (int)r, 0) : mkdesc(K_I, 0, 0);
+    }
+    if (lib == LIB_ISING) {
+        int a, b;
+        upair_of(n, (int)(r - n), &a, &b);
+        *angle = theta[s];
+        return mkdesc(K_ZZ, a, b);
     }
     int c, t;
     pair_of(n, (int)(r - n), &c, &t);
@@ -390,14 +549,14 @@ static uint16_t decode_slot(int n, int L, int P, uint64_t seed, uint32_t gen, ui
  * instance and each position pos, draw whichIndividual in [0, P) and
  * whichRotationOrInteraction in [0, R), form the segment index of Eq. 10 and
  * decode that segment.  theta is [inst][S], qutrit [inst][n*L*P][6];
- * slots and gates are [inst][P][L].  Parity: bit-exact (Eq. 10 pinned by
- * the Table I example). */
-QEO_API void qeo_qeqea_sample(int n, int L, int P, int I_, uint64_t seed, uint64_t gen64,
+ * slots, gates and angles (may be NULL) are [inst][P][L].  Parity: bit-exact
+ * (Eq. 10 pinned by the Table I example). */
+QEO_API void qeo_qeqea_sample(int n, int lib, int L, int P, int I_, uint64_t seed, uint64_t gen64,
                               const uint32_t* theta, const float* qutrit,
-                              uint32_t* slots, uint16_t* gates)
+                              uint32_t* slots, uint16_t* gates, uint32_t* angles)
 {
     uint32_t gen = (uint32_t)gen64;
-    uint32_t R = (uint32_t)(n * n);
+    uint32_t R = (uint32_t)qeo_regions(n, lib);
     size_t S = (size_t)R * L * P, Q = (size_t)n * L * P;
     for (int i = 0; i < I_; ++i) {
         for (int k = 0; k < P; ++k) {
@@ -409,8 +568,10 @@ QEO_API void qeo_qeqea_sample(int n, int L, int P, int I_, uint64_t seed, uint64
                 uint32_t s = qeo_segment_index(L, P, (int)region, (int)ind, pos);
                 size_t o = ((size_t)i * P + k) * L + pos;
                 slots[o] = s;
-                gates[o] = decode_slot(n, L, P, seed, gen, (uint32_t)i, s, theta + i * S,
-                                       qutrit + 6 * i * Q);
+                uint32_t ang;
+                gates[o] = qeo_decode_slot(n, lib, L, P, seed, gen, (uint32_t)i, s, theta + i * S,
+                                           qutrit + 6 * i * Q, &ang);
+                if (angles) angles[o] = ang;
             }
         }
     }
@@ -418,11 +579,11 @@ QEO_API void qeo_qeqea_sample(int n, int L, int P, int I_, uint64_t seed, uint64
 
 /* Initial encoding: angles from the INIT stream, qutrits in the uniform
  * superposition (1,1,1)/sqrt(3), no best recorded yet (-1). */
-QEO_API void qeo_qeqea_init(int n, int L, int P, int I_, uint64_t seed, uint32_t* theta,
+QEO_API void qeo_qeqea_init(int n, int lib, int L, int P, int I_, uint64_t seed, uint32_t* theta,
                             float* qutrit, float* best_f, uint32_t* best_theta,
                             float* best_qutrit)
 {
-    size_t S = (size_t)n * n * L * P, Q = (size_t)n * L * P;
+    size_t S = (size_t)qeo_regions(n, lib) * L * P, Q = (size_t)n * L * P;
     float a = (float)(1.0 / sqrt(3.0));
     for (int i = 0; i < I_; ++i) {
         for (size_t s = 0; s < S; ++s) {
@@ -538,13 +699,13 @@ static uint64_t prob_threshold(double p)
  * slots [inst][P][L] from qeo_qeqea_sample, f [inst][P] circuit fitness.
  * State arrays are updated in place.  Parity: bit-exact vs the GPU; the
  * trajectory itself is "parity unpinned" by the paper (invariants only). */
-QEO_API void qeo_qeqea_update(int n, int L, int P, int I_, uint64_t seed, uint64_t gen64,
+QEO_API void qeo_qeqea_update(int n, int lib, int L, int P, int I_, uint64_t seed, uint64_t gen64,
                               float pm, float range, const uint32_t* slots, const float* f,
                               uint32_t* theta, float* qutrit, float* best_f,
                               uint32_t* best_theta, float* best_qutrit)
 {
     uint32_t gen = (uint32_t)gen64;
-    uint32_t R = (uint32_t)(n * n);
+    uint32_t R = (uint32_t)qeo_regions(n, lib);
     size_t S = (size_t)R * L * P, Q = (size_t)n * L * P;
     uint64_t thr = prob_threshold((double)pm);
     float r32 = (float)((double)range / (2.0 * PI) * 4294967296.0);
