@@ -5,13 +5,21 @@
  * of candidate circuits (Sec. IV-E, Eq. 11), circuit construction by sampling
  * the qubit/qutrit encoding (Sec. IV-D, Eq. 10), segment fitness, elitism and
  * adaptive mutation (Secs. IV-E.1, IV-F, Eq. 12), and the GA operators of
- * Sec. V-B.
+ * Sec. V-B, for discrete gate libraries and for the Ising gate model of
+ * Sec. III (Eqs. 3-6).
  *
  * Conventions shared by every entry point
  *  - Gate descriptor (uint16): kind in bits 0-3, target wire in bits 4-7,
  *    control wire in bits 8-11, bits 12-15 zero.  Kinds: 0 I, 1 NOT, 2 CNOT,
  *    3 CV, 4 CV+ (V = sqrt(NOT)), 5 H, 6 T.  Single-qubit kinds ignore the
  *    control field.
+ *  - Ising kinds (Sec. III): 7 R_x, 8 R_y, 9 R_z (Eqs. 3-5) on the target
+ *    wire, 10 the interaction J (Eq. 6, read with the exponent i theta:
+ *    exp(-i theta/2 Z_a Z_b), a diagonal of e^{-+i theta/2}) on the wires
+ *    a = target field, b = control field (a != b).  Each carries an angle:
+ *    a uint32 fraction of a full turn, theta = 2 pi u / 2^32, in an array
+ *    parallel to the descriptors ("angles"); without one these kinds are
+ *    invalid descriptors.
  *  - Wire w of an n-wire register is bit (n-1-w) of a basis-state index: the
  *    first Kronecker factor is the most significant (Eqs. 1-2).
  *  - A circuit g_0 .. g_{L-1} denotes U = G_{L-1} ... G_0 (g_0 acts first).
@@ -59,7 +67,8 @@ enum {
 };
 
 enum { QE_LIB_NCV = 0,      /* {I, NOT, CNOT, CV, CV+} */
-       QE_LIB_HT_NCV = 1 }; /* {H, T, CNOT, CV, CV+}   */
+       QE_LIB_HT_NCV = 1,   /* {H, T, CNOT, CV, CV+}   */
+       QE_LIB_ISING = 2 };  /* {R_x, R_y, R_z, J} with angles (QEQEA only) */
 enum { QE_ALG_QEQEA = 0, QE_ALG_GA = 1 };
 enum { QE_PATH_FP32 = 0,        /* per-gate row updates, FP32, tuned schedule per width */
        QE_PATH_FP32_REG = 1,    /* forced: matrix held in registers, one wave per circuit */
@@ -93,6 +102,11 @@ enum { QE_DEVERR_DESC = 1,      /* invalid gate descriptor */
  *                  2^n x 2^n row-major per target.
  *   num_target_elems  complex elements in `targets` (bounds).
  *   fitness_mode   QE_FIT_EQ11 (0) or QE_FIT_PHASE_INSENSITIVE (1).
+ *   angles_dev     NULL (discrete gates only), or one uint32 angle per entry
+ *                  of gates_dev (same indexing), read for the Ising kinds.
+ *                  Angled batches run on QE_PATH_FP32 / QE_PATH_FP32_LDS
+ *                  and the FP64 calls; the register and MFMA paths return
+ *                  QE_ERR_UNSUPPORTED for them.
  *
  * Fitness modes.  QE_FIT_EQ11: Eq. 11 as printed, f = 1 - sqrt((2^n -
  * |tr(T^dagger U)|) / 2^n), computed through the exact identity 2^n - |tr| =
@@ -119,6 +133,7 @@ typedef struct {
     const void* targets_dev;
     int64_t num_target_elems;
     int32_t fitness_mode;
+    const uint32_t* angles_dev;
 } qe_batch;
 
 /* Fitness of every circuit of the batch against its target, Eq. 11 of
@@ -161,7 +176,9 @@ qe_status qe_device_errors(int32_t* flags_host);
  *   ga_crossover_prob, ga_gene_mutation_prob in [0, 1] (GA);
  *   seed: the Philox4x32-10 key;
  *   fitness_mode: QE_FIT_* (the fitness the search maximises; see qe_batch).
- * QEQEA uses the library {I, NOT, CNOT, CV, CV+} only. */
+ * QEQEA decodes to the library {I, NOT, CNOT, CV, CV+} or to the Ising
+ * library; the GA takes the discrete libraries only (its genome holds no
+ * angles). */
 typedef struct {
     int32_t n_qubits;
     int32_t library;
@@ -178,10 +195,12 @@ typedef struct {
 } qe_problem;
 
 /* Creates a context on the current device: allocates the ctx-owned encoding
- * (QEQEA: (n + n(n-1)) * L * P slot records of 32 bytes (angle, best angle,
- * best segment fitness, the generation's segment key) and n*L*P qutrit records of 64 bytes
- * (3 complex64 amplitudes and their best copy); GA: two L*P genome buffers)
- * per instance,
+ * (QEQEA: R * L * P slot records of 32 bytes (angle, best angle, best
+ * segment fitness, the generation's segment key), R = n + n(n-1) regions for
+ * {I, NOT, CNOT, CV, CV+} (one template per ordered wire pair) or
+ * n + n(n-1)/2 for the Ising library (one per unordered pair), and n*L*P
+ * qutrit records of 64 bytes (3 complex64 amplitudes and their best copy);
+ * GA: two L*P genome buffers) per instance,
  * and initialises it as the population initialisation of Sec. IV-B (angles
  * from the Philox INIT stream, qutrits (1,1,1)/sqrt(3), no best yet).  Syncs. */
 qe_status qe_create(const qe_problem* problem, qe_ctx** ctx_out);
@@ -196,16 +215,21 @@ qe_status qe_set_targets(qe_ctx* ctx, const void* targets_c128_dev, void* stream
  * k < P and position pos < L, draws whichIndividual and
  * whichRotationOrInteraction from the Philox SAMPLE stream of generation
  * `gen`, forms the segment index of Eq. 10 into slots_dev[(i*P+k)*L + pos]
- * and decodes that segment (qutrit measured by the Born rule, angle rounded
- * to quarter turns) into gates_dev[(i*P+k)*L + pos].  GA: copies the current
- * population (slots_dev may be NULL). */
+ * and decodes that segment into gates_dev[(i*P+k)*L + pos]: the qutrit of a
+ * rotation slot is measured by the Born rule; for the Ising library the
+ * gate is the rotation about the measured axis (or J on the template's
+ * pair) and takes the slot's angle (written to angles_dev, required then);
+ * for {I, NOT, CNOT, CV, CV+} the angle is rounded to quarter turns
+ * (angles_dev ignored, may be NULL).  GA: copies the current population
+ * (slots_dev may be NULL). */
 qe_status qe_sample(qe_ctx* ctx, uint64_t gen, uint32_t* slots_dev, uint16_t* gates_dev,
-                    void* stream);
+                    uint32_t* angles_dev, void* stream);
 
-/* Fitness of the I*P circuits in gates_dev against each instance's target
- * (FP32 path); f_dev [I*P]. */
-qe_status qe_eval_population(qe_ctx* ctx, const uint16_t* gates_dev, float* f_dev,
-                             void* stream);
+/* Fitness of the I*P circuits in gates_dev (with angles_dev for the Ising
+ * library, NULL otherwise) against each instance's target (FP32 path);
+ * f_dev [I*P]. */
+qe_status qe_eval_population(qe_ctx* ctx, const uint16_t* gates_dev, const uint32_t* angles_dev,
+                             float* f_dev, void* stream);
 
 /* One update step (Secs. IV-E.1, IV-F; GA: Sec. V-B).  QEQEA: every slot used
  * in generation `gen` takes the largest fitness of the circuits it built;
@@ -213,10 +237,12 @@ qe_status qe_eval_population(qe_ctx* ctx, const uint16_t* gates_dev, float* f_de
  * reverts to it; each individual mutates with prob_mutation (all qubits by
  * +-(1 - segFit) * mutation_range, or all qutrits by one SU(3) step of
  * Eq. 12, equiprobably).  GA: SUS selection, two-point crossover, gene
- * mutation, best individual kept.  slots_dev/gates_dev/f_dev as produced by
- * qe_sample and qe_eval_population for the same `gen`. */
+ * mutation, best individual kept.  slots_dev/gates_dev/angles_dev/f_dev as
+ * produced by qe_sample and qe_eval_population for the same `gen`
+ * (angles_dev: Ising library only, NULL otherwise). */
 qe_status qe_update(qe_ctx* ctx, uint64_t gen, const uint32_t* slots_dev,
-                    const uint16_t* gates_dev, const float* f_dev, void* stream);
+                    const uint16_t* gates_dev, const uint32_t* angles_dev, const float* f_dev,
+                    void* stream);
 
 /* sample + eval + update of generation `gen` in two kernel launches (QEQEA)
  * or two (GA); f_dev [I*P] receives the generation's fitness (may be NULL).
@@ -226,10 +252,11 @@ qe_status qe_generation(qe_ctx* ctx, uint64_t gen, float* f_dev, void* stream);
 /* The first half of qe_generation for QEQEA, one kernel launch: circuit
  * construction (as qe_sample, into slots_dev / gates_dev) fused with the
  * fitness evaluation (f_dev) and the segment-fitness maximum that qe_update
- * starts from.  qe_update(gen, slots, gates, f) afterwards completes the
- * generation with the same result as qe_generation.  QEQEA only. */
+ * starts from.  qe_update(gen, slots, gates, angles, f) afterwards completes
+ * the generation with the same result as qe_generation.  angles_dev as in
+ * qe_sample.  QEQEA only. */
 qe_status qe_sample_eval(qe_ctx* ctx, uint64_t gen, uint32_t* slots_dev, uint16_t* gates_dev,
-                         float* f_dev, void* stream);
+                         uint32_t* angles_dev, float* f_dev, void* stream);
 
 /* Captures and instantiates the graph that qe_run_graph(n_gen, f_hist_dev)
  * replays, without running it (so that a later qe_run_graph does no capture
@@ -247,16 +274,20 @@ qe_status qe_run_graph(qe_ctx* ctx, uint64_t first_gen, int32_t n_gen, float* f_
  * gates_dev with the highest f_dev (ties: lowest index) are re-evaluated in
  * FP64 against the complex128 target.  gates_dev NULL: the circuits of the
  * last generation run by qe_generation / qe_run_graph (f_dev must then be
- * that generation's fitness).  idx_dev [I][k] (int32, circuit index within
- * the instance), f64_dev [I][k].  1 <= k <= P <= 4096. */
-qe_status qe_elite_recheck(qe_ctx* ctx, const uint16_t* gates_dev, const float* f_dev,
-                           int32_t k, int32_t* idx_dev, double* f64_dev, void* stream);
+ * that generation's fitness; angles_dev is ignored).  angles_dev: the
+ * circuits' angles (Ising library, required with gates_dev), NULL
+ * otherwise.  idx_dev [I][k] (int32, circuit index within the instance),
+ * f64_dev [I][k].  1 <= k <= P <= 4096. */
+qe_status qe_elite_recheck(qe_ctx* ctx, const uint16_t* gates_dev, const uint32_t* angles_dev,
+                           const float* f_dev, int32_t k, int32_t* idx_dev, double* f64_dev,
+                           void* stream);
 
 /* Best circuit seen so far by instance `instance` (over every generation run
- * through qe_update / qe_generation / qe_run_graph): its L gates, its FP32
- * fitness and its FP64 re-evaluated fitness.  Syncs the device. */
-qe_status qe_get_best(qe_ctx* ctx, int32_t instance, uint16_t* gates_host, float* f32_host,
-                      double* f64_host);
+ * through qe_update / qe_generation / qe_run_graph): its L gates, their
+ * angles (Ising library; zeros otherwise), its FP32 fitness and its FP64
+ * re-evaluated fitness.  Any output may be NULL.  Syncs the device. */
+qe_status qe_get_best(qe_ctx* ctx, int32_t instance, uint16_t* gates_host, uint32_t* angles_host,
+                      float* f32_host, double* f64_host);
 
 /* Checkpoint / restore of the whole encoding state (bit-exact; the run is a
  * pure function of the state, the seed and the generation index).  With
@@ -276,7 +307,8 @@ qe_status qe_restore(qe_ctx* ctx, const void* buf_host, size_t size);
 qe_status qe_state_read(qe_ctx* ctx, int32_t which, void* dst_dev, int64_t* elems, void* stream);
 
 /* Gate-library table used by the GA (instance index -> descriptor), host
- * output of qe_lib_size() entries. */
+ * output of qe_lib_size() entries; discrete libraries only (qe_lib_size
+ * returns -1 and qe_lib_table QE_ERR_INVALID for the others). */
 int32_t qe_lib_size(int32_t library, int32_t n_qubits);
 qe_status qe_lib_table(int32_t library, int32_t n_qubits, uint16_t* table_host);
 

@@ -175,6 +175,7 @@ qe_status to_args(const qe_batch* b, BatchArgs* a, bool need_targets) {
     a->targets = b->targets_dev;
     a->num_telems = b->num_target_elems;
     a->mode = b->fitness_mode;
+    a->angles = b->angles_dev;
     return device_error_word(&a->err);
 }
 
@@ -198,6 +199,7 @@ struct qe_ctx {
     // ctx-owned device buffers
     std::vector<void*> owned;
     uint16_t* gates = nullptr;    // [I*P*L]
+    uint32_t* angles = nullptr;   // [I*P*L] (Ising library)
     float* f = nullptr;           // [I*P]
     uint64_t* d_gen = nullptr;
     int32_t* elite_idx = nullptr;
@@ -257,11 +259,11 @@ qe_status prepare_decisions(qe_ctx* c, uint64_t gen, uint64_t count, hipStream_t
 qe_status enqueue_generation(qe_ctx* c, const LoopArgs& a, uint64_t gen, float* f, hipStream_t s) {
     if (c->prob.algorithm == QE_ALG_QEQEA) {
         // the update draws each entry's slot again instead of reading it
-        QE_HIP(launch_qeqea_fused(a, gen, nullptr, c->gates, f, true, s));
-        QE_HIP(launch_qeqea_update(a, gen, nullptr, c->gates, f, s));
+        QE_HIP(launch_qeqea_fused(a, gen, nullptr, c->gates, c->angles, f, true, s));
+        QE_HIP(launch_qeqea_update(a, gen, nullptr, c->gates, c->angles, f, s));
     } else {
         QE_HIP(launch_ga_copy(a, gen, c->gates, s));
-        QE_HIP(launch_eval_population(a, c->gates, f, s));
+        QE_HIP(launch_eval_population(a, c->gates, nullptr, f, s));
         QE_HIP(launch_ga_update(a, gen, f, s));
     }
     return QE_OK;
@@ -308,6 +310,8 @@ qe_status qe_eval_fitness(qe_ctx* ctx, const qe_batch* batch, int32_t path, floa
     QE_TRY(to_args(batch, &a, true));
     if (path < QE_PATH_FP32 || path > QE_PATH_MFMA_FP16_RAW) return fail(QE_ERR_INVALID, "unknown path");
     if (a.B > 0 && !f_dev) return fail(QE_ERR_INVALID, "f_dev is NULL");
+    if (a.angles && path != QE_PATH_FP32 && path != QE_PATH_FP32_LDS)
+        return fail(QE_ERR_UNSUPPORTED, "angled (Ising) batches run on QE_PATH_FP32 / QE_PATH_FP32_LDS");
     if (path >= QE_PATH_MFMA_BF16) {
         if (a.uniform_n != 5 && a.uniform_n != 6)
             return fail(QE_ERR_UNSUPPORTED, "MFMA paths need a uniform width of 5 or 6");
@@ -362,12 +366,15 @@ qe_status qe_create(const qe_problem* p, qe_ctx** out) {
     if (!p || !out) return fail(QE_ERR_INVALID, "NULL argument");
     *out = nullptr;
     const int n = p->n_qubits;
-    if (p->library != QE_LIB_NCV && p->library != QE_LIB_HT_NCV) return fail(QE_ERR_INVALID, "unknown library");
+    if (p->library != QE_LIB_NCV && p->library != QE_LIB_HT_NCV && p->library != QE_LIB_ISING)
+        return fail(QE_ERR_INVALID, "unknown library");
     if (p->algorithm != QE_ALG_QEQEA && p->algorithm != QE_ALG_GA) return fail(QE_ERR_INVALID, "unknown algorithm");
     if (n < 1 || n > MAX_QUBITS) return fail(QE_ERR_INVALID, "n_qubits must be 1..6");
     if (p->algorithm == QE_ALG_QEQEA && n < 2) return fail(QE_ERR_INVALID, "QEQEA needs n_qubits >= 2");
-    if (p->algorithm == QE_ALG_QEQEA && p->library != QE_LIB_NCV)
-        return fail(QE_ERR_UNSUPPORTED, "QEQEA decodes to the library {I, NOT, CNOT, CV, CV+} only");
+    if (p->algorithm == QE_ALG_QEQEA && p->library == QE_LIB_HT_NCV)
+        return fail(QE_ERR_UNSUPPORTED, "QEQEA decodes to {I, NOT, CNOT, CV, CV+} or the Ising library");
+    if (p->algorithm == QE_ALG_GA && p->library == QE_LIB_ISING)
+        return fail(QE_ERR_UNSUPPORTED, "the GA genome holds no angles: discrete libraries only");
     if (p->size_of_individual < 1 || p->size_of_individual > 1024) return fail(QE_ERR_INVALID, "L must be 1..1024");
     if (p->size_of_population < 1 || p->size_of_population > 65536) return fail(QE_ERR_INVALID, "P must be 1..65536");
     if (p->algorithm == QE_ALG_GA && p->size_of_population > 4096) return fail(QE_ERR_INVALID, "GA needs P <= 4096");
@@ -382,7 +389,8 @@ qe_status qe_create(const qe_problem* p, qe_ctx** out) {
     if (p->fitness_mode != QE_FIT_EQ11 && p->fitness_mode != QE_FIT_PHASE_INSENSITIVE)
         return fail(QE_ERR_INVALID, "unknown fitness_mode");
     const size_t L = p->size_of_individual, P = p->size_of_population, I = p->n_instances;
-    const size_t S = (size_t)n * n * L * P, Q = (size_t)n * L * P;
+    const size_t R = (size_t)regions(n, p->library);
+    const size_t S = R * L * P, Q = (size_t)n * L * P;
     if ((uint64_t)S >= (1ull << 32) || I * P * L >= (1ull << 32))
         return fail(QE_ERR_INVALID, "encoding too large (slot indices are 32-bit)");
     if (I > (1u << 31) / P) return fail(QE_ERR_INVALID, "too many instances");
@@ -401,6 +409,7 @@ qe_status qe_create(const qe_problem* p, qe_ctx** out) {
     a.thr_pc = prob_threshold((double)p->ga_crossover_prob);
     a.thr_pg = prob_threshold((double)p->ga_gene_mutation_prob);
     a.r32 = (float)((double)p->mutation_range / pi2 * 4294967296.0);
+    a.R = (uint32_t)R;
     a.S = (uint32_t)S;
     a.Q = (uint32_t)Q;
     qe_status st = QE_OK;
@@ -426,7 +435,9 @@ qe_status qe_create(const qe_problem* p, qe_ctx** out) {
         ALLOC(a.mutmask, 2 * I * a.MW);
     }
     ALLOC(a.inst_best_gates, I * L);
+    ALLOC(a.inst_best_angles, I * L);
     ALLOC(c->gates, I * P * L);
+    if (p->library == QE_LIB_ISING) ALLOC(c->angles, I * P * L);
     ALLOC(c->f, I * P);
     ALLOC(c->d_gen, 1);
     ALLOC(c->elite_idx, I * P);
@@ -480,37 +491,47 @@ qe_status qe_set_targets(qe_ctx* c, const void* t, void* stream) {
     return QE_OK;
 }
 
-qe_status qe_sample(qe_ctx* c, uint64_t gen, uint32_t* slots, uint16_t* gates, void* stream) {
+namespace {
+bool is_ising(const qe_ctx* c) { return c->prob.library == QE_LIB_ISING; }
+}  // namespace
+
+qe_status qe_sample(qe_ctx* c, uint64_t gen, uint32_t* slots, uint16_t* gates, uint32_t* angles,
+                    void* stream) {
     QE_TRY(check_ctx(c, false));
     if (!gates) return fail(QE_ERR_INVALID, "gates is NULL");
+    if (is_ising(c) && !angles) return fail(QE_ERR_INVALID, "the Ising library needs angles_dev");
     LoopArgs a = c->la;
     if (c->prob.algorithm == QE_ALG_QEQEA) {
         if (!slots) return fail(QE_ERR_INVALID, "slots is NULL");
-        QE_HIP(launch_qeqea_sample(a, gen, slots, gates, (hipStream_t)stream));
+        QE_HIP(launch_qeqea_sample(a, gen, slots, gates, is_ising(c) ? angles : nullptr,
+                                   (hipStream_t)stream));
     } else {
         QE_HIP(launch_ga_copy(a, gen, gates, (hipStream_t)stream));
     }
     return QE_OK;
 }
 
-qe_status qe_eval_population(qe_ctx* c, const uint16_t* gates, float* f, void* stream) {
+qe_status qe_eval_population(qe_ctx* c, const uint16_t* gates, const uint32_t* angles, float* f,
+                             void* stream) {
     QE_TRY(check_ctx(c, true));
     if (!gates || !f) return fail(QE_ERR_INVALID, "NULL buffer");
-    QE_HIP(launch_eval_population(c->la, gates, f, (hipStream_t)stream));
+    if (is_ising(c) && !angles) return fail(QE_ERR_INVALID, "the Ising library needs angles_dev");
+    QE_HIP(launch_eval_population(c->la, gates, is_ising(c) ? angles : nullptr, f, (hipStream_t)stream));
     return QE_OK;
 }
 
 qe_status qe_update(qe_ctx* c, uint64_t gen, const uint32_t* slots, const uint16_t* gates,
-                    const float* f, void* stream) {
+                    const uint32_t* angles, const float* f, void* stream) {
     QE_TRY(check_ctx(c, false));
     if (!f || !gates) return fail(QE_ERR_INVALID, "NULL buffer");
+    if (is_ising(c) && !angles) return fail(QE_ERR_INVALID, "the Ising library needs angles_dev");
     hipStream_t s = (hipStream_t)stream;
     if (c->prob.algorithm == QE_ALG_QEQEA) {
         if (!slots) return fail(QE_ERR_INVALID, "slots is NULL");
         QE_HIP(launch_scatter(c->la, gen, slots, f, s));
         QE_TRY(prepare_decisions(c, gen, 1, s));
         QE_HIP(launch_mutation_decisions(c->la, gen, s));
-        QE_HIP(launch_qeqea_update(c->la, gen, slots, gates, f, s));
+        QE_HIP(launch_qeqea_update(c->la, gen, slots, gates, is_ising(c) ? angles : nullptr, f, s));
     } else {
         QE_HIP(launch_ga_update(c->la, gen, f, s));
     }
@@ -523,12 +544,14 @@ qe_status qe_generation(qe_ctx* c, uint64_t gen, float* f, void* stream) {
     return enqueue_generation(c, c->la, gen, f ? f : c->f, (hipStream_t)stream);
 }
 
-qe_status qe_sample_eval(qe_ctx* c, uint64_t gen, uint32_t* slots, uint16_t* gates, float* f,
-                         void* stream) {
+qe_status qe_sample_eval(qe_ctx* c, uint64_t gen, uint32_t* slots, uint16_t* gates,
+                         uint32_t* angles, float* f, void* stream) {
     QE_TRY(check_ctx(c, true));
     if (c->prob.algorithm != QE_ALG_QEQEA) return fail(QE_ERR_UNSUPPORTED, "qe_sample_eval is QEQEA only");
     if (!slots || !gates || !f) return fail(QE_ERR_INVALID, "NULL buffer");
-    QE_HIP(launch_qeqea_fused(c->la, gen, slots, gates, f, false, (hipStream_t)stream));
+    if (is_ising(c) && !angles) return fail(QE_ERR_INVALID, "the Ising library needs angles_dev");
+    QE_HIP(launch_qeqea_fused(c->la, gen, slots, gates, is_ising(c) ? angles : nullptr, f, false,
+                              (hipStream_t)stream));
     return QE_OK;
 }
 
@@ -575,21 +598,27 @@ qe_status qe_run_graph(qe_ctx* c, uint64_t first_gen, int32_t n_gen, float* f_hi
     return QE_OK;
 }
 
-qe_status qe_elite_recheck(qe_ctx* c, const uint16_t* gates, const float* f, int32_t k,
-                           int32_t* idx, double* f64, void* stream) {
+qe_status qe_elite_recheck(qe_ctx* c, const uint16_t* gates, const uint32_t* angles, const float* f,
+                           int32_t k, int32_t* idx, double* f64, void* stream) {
     QE_TRY(check_ctx(c, true));
     if (!f || !idx || !f64) return fail(QE_ERR_INVALID, "NULL buffer");
-    if (!gates) gates = c->gates;
+    if (!gates) {
+        gates = c->gates;
+        angles = c->angles;
+    } else if (is_ising(c) && !angles) {
+        return fail(QE_ERR_INVALID, "the Ising library needs angles_dev");
+    }
+    if (!is_ising(c)) angles = nullptr;
     if (k < 1 || k > c->prob.size_of_population) return fail(QE_ERR_INVALID, "k must be 1..P");
     if (c->prob.size_of_population > 4096) return fail(QE_ERR_UNSUPPORTED, "elite selection needs P <= 4096");
     hipStream_t s = (hipStream_t)stream;
     QE_HIP(launch_elite_select(c->la, f, k, idx, s));
-    QE_HIP(launch_elite_eval(c->la, gates, k, idx, f64, s));
+    QE_HIP(launch_elite_eval(c->la, gates, angles, k, idx, f64, s));
     return QE_OK;
 }
 
-qe_status qe_get_best(qe_ctx* c, int32_t inst, uint16_t* gates_host, float* f32_host,
-                      double* f64_host) {
+qe_status qe_get_best(qe_ctx* c, int32_t inst, uint16_t* gates_host, uint32_t* angles_host,
+                      float* f32_host, double* f64_host) {
     QE_TRY(check_ctx(c, false));
     if (inst < 0 || inst >= c->prob.n_instances) return fail(QE_ERR_INVALID, "instance out of range");
     QE_HIP(hipDeviceSynchronize());
@@ -598,6 +627,9 @@ qe_status qe_get_best(qe_ctx* c, int32_t inst, uint16_t* gates_host, float* f32_
     QE_HIP(hipMemcpy(&fv, c->la.inst_best_f + inst, sizeof(float), hipMemcpyDeviceToHost));
     if (gates_host)
         QE_HIP(hipMemcpy(gates_host, c->la.inst_best_gates + (size_t)inst * L, L * sizeof(uint16_t),
+                         hipMemcpyDeviceToHost));
+    if (angles_host)
+        QE_HIP(hipMemcpy(angles_host, c->la.inst_best_angles + (size_t)inst * L, L * sizeof(uint32_t),
                          hipMemcpyDeviceToHost));
     if (f32_host) *f32_host = fv;
     if (f64_host) {
@@ -612,6 +644,7 @@ qe_status qe_get_best(qe_ctx* c, int32_t inst, uint16_t* gates_host, float* f32_
         b.targets_dev = c->la.target64 + (size_t)2 * inst * c->N * c->N;
         b.num_target_elems = (int64_t)c->N * c->N;
         b.fitness_mode = c->prob.fitness_mode;
+        b.angles_dev = is_ising(c) ? c->la.inst_best_angles + (size_t)inst * L : nullptr;
         double* d = nullptr;
         QE_HIP(hipMalloc(&d, sizeof(double)));
         qe_status st = qe_eval_fitness_fp64(&b, d, nullptr, nullptr, nullptr);
@@ -644,6 +677,7 @@ std::vector<Section> state_sections(qe_ctx* c) {
     }
     v.push_back({a.inst_best_f, I * 4});
     v.push_back({a.inst_best_gates, I * L * 2});
+    v.push_back({a.inst_best_angles, I * L * 4});
     return v;
 }
 
@@ -667,8 +701,8 @@ qe_status qe_checkpoint(qe_ctx* c, void* buf, size_t* size) {
     if (*size < need) return fail(QE_ERR_INVALID, "checkpoint buffer too small");
     QE_HIP(hipDeviceSynchronize());
     CkptHeader h{};
-    std::memcpy(h.magic, "QECKPT02", 8);
-    h.version = 2;
+    std::memcpy(h.magic, "QECKPT03", 8);
+    h.version = 3;
     h.prob = c->prob;
     h.payload = payload;
     std::memcpy(buf, &h, sizeof(h));
@@ -686,7 +720,7 @@ qe_status qe_restore(qe_ctx* c, const void* buf, size_t size) {
     if (!buf || size < sizeof(CkptHeader)) return fail(QE_ERR_INVALID, "checkpoint too small");
     CkptHeader h;
     std::memcpy(&h, buf, sizeof(h));
-    if (std::memcmp(h.magic, "QECKPT02", 8) != 0 || h.version != 2)
+    if (std::memcmp(h.magic, "QECKPT03", 8) != 0 || h.version != 3)
         return fail(QE_ERR_INVALID, "not a libqe checkpoint");
     if (std::memcmp(&h.prob, &c->prob, sizeof(qe_problem)) != 0)
         return fail(QE_ERR_INVALID, "checkpoint was written for a different problem");

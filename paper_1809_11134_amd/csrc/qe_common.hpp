@@ -10,11 +10,17 @@
 
 namespace qe {
 
-// Gate kinds of a descriptor (bits 0-3).
+// Gate kinds of a descriptor (bits 0-3): the discrete libraries, then the
+// Ising model of Sec. III (Eqs. 3-6), whose gates carry an angle: R_x, R_y,
+// R_z on the target wire and the interaction J on the wire pair (target,
+// control field).
 enum : int { KIND_I = 0, KIND_NOT = 1, KIND_CNOT = 2, KIND_CV = 3, KIND_CVDG = 4, KIND_H = 5,
-             KIND_T = 6 };
+             KIND_T = 6, KIND_RX = 7, KIND_RY = 8, KIND_RZ = 9, KIND_ZZ = 10 };
 
 QE_HD inline bool kind_controlled(int k) { return k == KIND_CNOT || k == KIND_CV || k == KIND_CVDG; }
+QE_HD inline bool kind_ising(int k) { return k >= KIND_RX && k <= KIND_ZZ; }
+// Gates on two wires: the controlled kinds and the interaction.
+QE_HD inline bool kind_two_wire(int k) { return kind_controlled(k) || k == KIND_ZZ; }
 QE_HD inline uint16_t make_desc(int kind, int tgt, int ctl) {
     return (uint16_t)(kind | (tgt << 4) | (ctl << 8));
 }
@@ -48,6 +54,26 @@ QE_HD inline uint16_t lib_desc(int lib, int n, int idx) {
     pair_of(n, p, &c, &t);
     const int kind = which == 0 ? KIND_CNOT : (which == 1 ? KIND_CV : KIND_CVDG);
     return make_desc(kind, t, c);
+}
+
+// Ising library (Secs. IV-A to IV-C): a rotation slot per wire and an
+// interaction template per unordered wire pair.
+constexpr int LIB_ISING = 2;
+
+// Encoding regions of Eq. 10: n rotation regions, then one per template
+// (the C(n,2) unordered pairs of the Ising library, the n(n-1) ordered
+// pairs of the directed library gates).
+QE_HD inline int regions(int n, int lib) { return lib == LIB_ISING ? n + n * (n - 1) / 2 : n * n; }
+
+// Unordered wire pair k (a < b), lexicographic: (0,1), (0,2), ..., (1,2), ...
+QE_HD inline void upair_of(int n, int k, int* a, int* b) {
+    int x = 0;
+    while (k >= n - 1 - x) {
+        k -= n - 1 - x;
+        ++x;
+    }
+    *a = x;
+    *b = x + 1 + k;
 }
 
 constexpr int MAX_QUBITS = 6;

@@ -45,14 +45,40 @@ __device__ __forceinline__ int desc_kind(uint32_t d) { return d & 15; }
 __device__ __forceinline__ int desc_tgt(uint32_t d) { return (d >> 4) & 15; }
 __device__ __forceinline__ int desc_ctl(uint32_t d) { return (d >> 8) & 15; }
 
+// ISING: the circuit carries angles, so the Ising kinds are valid too.
+template <bool ISING = false>
 __device__ __forceinline__ bool desc_valid(uint32_t d, int n) {
     const int k = d & 15, t = (d >> 4) & 15, c = (d >> 8) & 15;
     if (d >> 12) return false;
-    if (k > KIND_T) return false;
+    if (k > (ISING ? KIND_ZZ : KIND_T)) return false;
     if (k == KIND_I) return true;
     if (t >= n) return false;
-    if (kind_controlled(k) && (c >= n || c == t)) return false;
+    if (kind_two_wire(k) && (c >= n || c == t)) return false;
     return true;
+}
+
+// ------------------------------------------------------------ gate angles
+// cos and sin of theta / 2 for an angle stored as a u32 turn fraction
+// (theta = 2 pi u / 2^32).  theta / 2 = q pi/2 + pi r / 2^32 with q the
+// nearest whole number of quarter turns (0, 1 or 2) and |r| <= 2^30, so the
+// reduced argument lies in [-pi/4, pi/4] and is rounded once when r is
+// converted; sincospi avoids a rounded multiple of pi.
+__device__ __forceinline__ void half_angle(uint32_t u, float* c, float* s) {
+    const uint32_t q = (uint32_t)(((uint64_t)u + 0x40000000ull) >> 31);
+    const int32_t r = (int32_t)(u - (q << 31));
+    float sr, cr;
+    sincospif((float)r * 0x1p-32f, &sr, &cr);
+    *c = q == 0 ? cr : (q == 1 ? -sr : -cr);
+    *s = q == 0 ? sr : (q == 1 ? cr : -sr);
+}
+
+__device__ __forceinline__ void half_angle(uint32_t u, double* c, double* s) {
+    const uint32_t q = (uint32_t)(((uint64_t)u + 0x40000000ull) >> 31);
+    const int32_t r = (int32_t)(u - (q << 31));
+    double sr, cr;
+    sincospi((double)r * 0x1p-32, &sr, &cr);
+    *c = q == 0 ? cr : (q == 1 ? -sr : -cr);
+    *s = q == 0 ? sr : (q == 1 ? cr : -sr);
 }
 
 // ------------------------------------------------------------- wave reductions

@@ -11,11 +11,22 @@ __device__ __forceinline__ Item resolve(const BatchArgs& a, int b, bool need_tar
     return resolve_item(a, b, need_target);
 }
 
+// Gate p of a circuit as its gate source returns it: the descriptor, or
+// with ANG the descriptor and its angle (0 beyond the circuit).
+template <bool ANG>
+__device__ __forceinline__ auto batch_gate(const Item& it, int p) {
+    if constexpr (ANG)
+        return p < it.L ? make_uint2((uint32_t)it.g[p], it.ang[p]) : make_uint2(0u, 0u);
+    else
+        return p < it.L ? (uint32_t)it.g[p] : 0u;
+}
+
 // ------------------------------------------------------- FP32, one wave each
 // Register-resident path (n = 4..6) or one-element-per-lane path (n <= 3);
 // WPB circuits per workgroup.  FILTER: a mixed-width batch is served by one
-// launch per width, each skipping the circuits of other widths.
-template <int NQ, bool FILTER>
+// launch per width, each skipping the circuits of other widths.  ANG: the
+// batch carries angles (one-element-per-lane path only).
+template <int NQ, bool FILTER, bool ANG = false>
 __global__ __launch_bounds__(64 * WPB) void wave_kernel(BatchArgs a, float* __restrict__ f,
                                                         float* __restrict__ g,
                                                         float* __restrict__ delta) {
@@ -27,13 +38,10 @@ __global__ __launch_bounds__(64 * WPB) void wave_kernel(BatchArgs a, float* __re
     if (it.err == 0 && it.n != NQ) it.err = QE_DEVERR_WIDTH;
     FitOut o{__builtin_nanf(""), __builtin_nanf(""), __builtin_nanf("")};
     if (it.err == 0) {
-        const uint16_t* gp = it.g;
         const int L = it.L;
-        auto src = [&](int ch) -> uint32_t {
-            const int p = ch * 64 + lane;
-            return p < L ? (uint32_t)gp[p] : 0u;
-        };
+        auto src = [&](int ch) { return batch_gate<ANG>(it, ch * 64 + lane); };
         const float* T = reinterpret_cast<const float*>(a.targets) + 2 * it.toff;
+        static_assert(!ANG || NQ <= 3, "angled circuits of 4 or more wires take the LDS-staged path");
         const bool ok = run_width<NQ, false>(NQ, T, L, src, nullptr, &o, a.mode);
         if (!ok) {
             it.err = QE_DEVERR_DESC;
@@ -63,14 +71,14 @@ __global__ void width_check_kernel(BatchArgs a, float* f, float* g, float* delta
 }
 
 // LDS-staged path, W wavefronts per circuit (see run_lds_path).
-template <int NQ, int W, bool FILTER, bool IDENT>
+template <int NQ, int W, bool FILTER, bool IDENT, bool ANG = false>
 __global__ __launch_bounds__(64 * W) void lds32_kernel(BatchArgs a, float* __restrict__ f,
                                                        float* __restrict__ g,
                                                        float* __restrict__ delta,
                                                        float* __restrict__ U_out) {
     constexpr int N = 1 << NQ, CW = N / W;
     __shared__ float2 M[N * N];
-    __shared__ uint4 GT[W][GATE_TABLE];
+    __shared__ uint4 GT[W][ANG ? GATE_TABLE_ANGLED : GATE_TABLE];
     __shared__ float red[W][3];
     const int b = blockIdx.x;
     const int lane = (int)lane_id(), wave = (int)(threadIdx.x >> 6);
@@ -81,12 +89,8 @@ __global__ __launch_bounds__(64 * W) void lds32_kernel(BatchArgs a, float* __res
     float off = 0.0f;
     float2 dg = make_float2(0.0f, 0.0f);
     if (ok) {
-        const uint16_t* gp = it.g;
         const int L = it.L;
-        auto src = [&](int ch) -> uint32_t {
-            const int p = ch * 64 + lane;
-            return p < L ? (uint32_t)gp[p] : 0u;
-        };
+        auto src = [&](int ch) { return batch_gate<ANG>(it, ch * 64 + lane); };
         const float* T = IDENT ? nullptr : reinterpret_cast<const float*>(a.targets) + 2 * it.toff;
         ok = run_lds_path<NQ, W, IDENT>(M, GT[wave], T, L, src, IDENT ? nullptr : &off, &dg);
         if (!ok) it.err = QE_DEVERR_DESC;
@@ -281,7 +285,7 @@ __global__ __launch_bounds__(256) void lds_kernel(BatchArgs a, Real* __restrict_
     const Real* T = (IDENT || it.err) ? nullptr : reinterpret_cast<const Real*>(a.targets) + 2 * it.toff;
     Real* U = nullptr;
     if (IDENT) U = U_out + (size_t)2 * ((size_t)1 << (2 * a.uniform_n)) * b;
-    lds_generic_body<Real, IDENT>(it.n, it.L, it.g, T, it.err, f + (f ? b : 0),
+    lds_generic_body<Real, IDENT>(it.n, it.L, it.g, it.ang, T, it.err, f + (f ? b : 0),
                                   g ? g + b : nullptr, delta ? delta + b : nullptr, U, a.err, a.mode);
 }
 
@@ -296,10 +300,23 @@ static bool use_lds(int n, int path) {
     return schedule_lds(n);
 }
 
-template <bool FILTER>
+// Angled batches (ANG): the one-element-per-lane kernel for n <= 3 and the
+// LDS-staged one above (the register-resident path has no Ising kinds).
+template <bool FILTER, bool ANG = false>
 static void launch_width(const BatchArgs& a, int n, bool lds, float* f, float* g, float* delta,
                          hipStream_t s) {
     const dim3 wgrid((a.B + WPB - 1) / WPB), wblock(64 * WPB);
+    if constexpr (ANG) {
+        switch (n) {
+            case 1: wave_kernel<1, FILTER, true><<<wgrid, wblock, 0, s>>>(a, f, g, delta); break;
+            case 2: wave_kernel<2, FILTER, true><<<wgrid, wblock, 0, s>>>(a, f, g, delta); break;
+            case 3: wave_kernel<3, FILTER, true><<<wgrid, wblock, 0, s>>>(a, f, g, delta); break;
+            case 4: lds32_kernel<4, 1, FILTER, false, true><<<a.B, 64, 0, s>>>(a, f, g, delta, nullptr); break;
+            case 5: lds32_kernel<5, 2, FILTER, false, true><<<a.B, 128, 0, s>>>(a, f, g, delta, nullptr); break;
+            default: lds32_kernel<6, 4, FILTER, false, true><<<a.B, 256, 0, s>>>(a, f, g, delta, nullptr); break;
+        }
+        return;
+    }
     if (lds) {
         switch (n) {
             case 4: lds32_kernel<4, 1, FILTER, false><<<a.B, 64, 0, s>>>(a, f, g, delta, nullptr); break;
@@ -321,7 +338,14 @@ static void launch_width(const BatchArgs& a, int n, bool lds, float* f, float* g
 hipError_t launch_eval_fp32(const BatchArgs& a, int path, float* f, float* g, float* delta,
                             int32_t* work, hipStream_t s) {
     if (a.B == 0) return hipSuccess;
-    if (a.uniform_n > 0) {
+    if (a.angles) {
+        if (a.uniform_n > 0) {
+            launch_width<false, true>(a, a.uniform_n, true, f, g, delta, s);
+        } else {
+            width_check_kernel<<<(a.B + 255) / 256, 256, 0, s>>>(a, f, g, delta);
+            for (int n = 1; n <= MAX_QUBITS; ++n) launch_width<true, true>(a, n, true, f, g, delta, s);
+        }
+    } else if (a.uniform_n > 0) {
         launch_width<false>(a, a.uniform_n, use_lds(a.uniform_n, path), f, g, delta, s);
     } else if (path == QE_PATH_FP32 && work) {
         // one launch over width-sorted work items (LDS-staged for n >= 4)
@@ -359,9 +383,18 @@ hipError_t launch_unitary(const BatchArgs& a, bool fp64, void* out, hipStream_t 
             case 1: lds_kernel<float, true><<<a.B, 256, 0, s>>>(a, nullptr, nullptr, nullptr, o); break;
             case 2: lds_kernel<float, true><<<a.B, 256, 0, s>>>(a, nullptr, nullptr, nullptr, o); break;
             case 3: lds_kernel<float, true><<<a.B, 256, 0, s>>>(a, nullptr, nullptr, nullptr, o); break;
-            case 4: lds32_kernel<4, 1, false, true><<<a.B, 64, 0, s>>>(a, nullptr, nullptr, nullptr, o); break;
-            case 5: lds32_kernel<5, 2, false, true><<<a.B, 128, 0, s>>>(a, nullptr, nullptr, nullptr, o); break;
-            default: lds32_kernel<6, 4, false, true><<<a.B, 256, 0, s>>>(a, nullptr, nullptr, nullptr, o); break;
+            case 4:
+                if (a.angles) lds32_kernel<4, 1, false, true, true><<<a.B, 64, 0, s>>>(a, nullptr, nullptr, nullptr, o);
+                else lds32_kernel<4, 1, false, true><<<a.B, 64, 0, s>>>(a, nullptr, nullptr, nullptr, o);
+                break;
+            case 5:
+                if (a.angles) lds32_kernel<5, 2, false, true, true><<<a.B, 128, 0, s>>>(a, nullptr, nullptr, nullptr, o);
+                else lds32_kernel<5, 2, false, true><<<a.B, 128, 0, s>>>(a, nullptr, nullptr, nullptr, o);
+                break;
+            default:
+                if (a.angles) lds32_kernel<6, 4, false, true, true><<<a.B, 256, 0, s>>>(a, nullptr, nullptr, nullptr, o);
+                else lds32_kernel<6, 4, false, true><<<a.B, 256, 0, s>>>(a, nullptr, nullptr, nullptr, o);
+                break;
         }
     }
     return hipGetLastError();

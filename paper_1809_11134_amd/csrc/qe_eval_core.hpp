@@ -22,7 +22,16 @@
 // LDS, W wavefronts split its columns, each lane updates the row pairs of one
 // column per pass, and the gate constants come from a per-chunk gate program.
 // One entry per lane (n <= 3; run_small_path): lane l holds M[l / N][l % N].
+//
+// Gate sources.  A path reads the circuit through a callable src(chunk) that
+// returns this lane's gate of the chunk: a uint32 descriptor for the
+// discrete libraries, or a uint2 {descriptor, angle} when the circuit may
+// hold Ising gates (kinds 7-10, angle a u32 turn fraction).  The angled
+// form compiles the Ising kinds in; the register-resident path takes the
+// discrete form only.
 #pragma once
+#include <type_traits>
+
 #include "../../include/qe.h"
 #include "qe_device.hpp"
 #include "qe_internal.hpp"
@@ -33,6 +42,7 @@ namespace qe {
 struct Item {
     int n, L;
     const uint16_t* g;
+    const uint32_t* ang;   // the circuit's angles, or null
     int64_t toff;
     uint32_t err;
 };
@@ -45,6 +55,7 @@ __device__ __forceinline__ Item resolve_item(const BatchArgs& a, int b, bool nee
     it.n = a.uniform_n > 0 ? a.uniform_n : (int)a.nq[b];
     it.L = 0;
     it.g = a.gates;
+    it.ang = a.angles;
     it.toff = 0;
     if (it.n < 1 || it.n > MAX_QUBITS) { it.err = QE_DEVERR_WIDTH; return it; }
     int64_t start, end;
@@ -58,6 +69,7 @@ __device__ __forceinline__ Item resolve_item(const BatchArgs& a, int b, bool nee
     if (start < 0 || end < start || end > a.num_gates) { it.err = QE_DEVERR_RANGE; return it; }
     it.L = (int)(end - start);
     it.g = a.gates + start;
+    it.ang = a.angles ? a.angles + start : nullptr;
     if (!need_target) return it;
     const int64_t NN = (int64_t)1 << (2 * it.n);
     it.toff = a.tstride >= 0 ? (int64_t)b * a.tstride : a.toff[b];
@@ -66,6 +78,26 @@ __device__ __forceinline__ Item resolve_item(const BatchArgs& a, int b, bool nee
 }
 
 __device__ __forceinline__ float bits_f(uint32_t u) { return __uint_as_float(u); }
+
+// ---------------------------------------------------------- gate sources
+template <typename GateSrc>
+constexpr bool src_angled() {
+    return std::is_same<std::decay_t<decltype(std::declval<GateSrc&>()(0))>, uint2>::value;
+}
+__device__ __forceinline__ uint32_t desc_of(uint32_t v) { return v; }
+__device__ __forceinline__ uint32_t desc_of(uint2 v) { return v.x; }
+__device__ __forceinline__ uint32_t angle_of(uint32_t) { return 0u; }
+__device__ __forceinline__ uint32_t angle_of(uint2 v) { return v.y; }
+
+// Ising gate on a pair of rows (a: target bit 0, b: target bit 1) with
+// c, s = cos, sin of theta / 2 (Eqs. 3-5): R_x mixes with -i s, R_y with
+// -+ s, R_z multiplies a by e^{-i theta/2} and b by e^{i theta/2}.
+__device__ __forceinline__ float2 phase_minus(float2 x, float c, float s) {   // x (c - i s)
+    return make_float2(c * x.x + s * x.y, c * x.y - s * x.x);
+}
+__device__ __forceinline__ float2 phase_plus(float2 x, float c, float s) {    // x (c + i s)
+    return make_float2(c * x.x - s * x.y, c * x.y + s * x.x);
+}
 __device__ __forceinline__ uint32_t f_bits(float f) { return __float_as_uint(f); }
 
 // ----------------------------------------------------------- lane-bit swaps
@@ -407,10 +439,12 @@ template <int NQ, bool IDENT, typename GateSrc>
 __device__ __forceinline__ bool run_small_path(const float* __restrict__ T, int L, GateSrc&& src,
                                                float* U_out, FitOut* fit, int mode = QE_FIT_EQ11) {
     constexpr int N = 1 << NQ;
+    constexpr bool ANG = src_angled<GateSrc>();
+    using SrcT = std::decay_t<decltype(src(0))>;
     const int lane = (int)lane_id();
     const bool live = lane < N * N;
     const int i = (lane >> NQ) & (N - 1), j = lane & (N - 1);
-    const uint32_t dv0 = L > 0 ? src(0) : 0u;   // before the target: latencies overlap
+    const SrcT dv0 = L > 0 ? src(0) : SrcT{};   // before the target: latencies overlap
     float mr = 0.0f, mi = 0.0f;
     if (live) {
         if (IDENT) {
@@ -425,10 +459,15 @@ __device__ __forceinline__ bool run_small_path(const float* __restrict__ T, int 
     const float r = 0.70710678118654752f;
     const int chunks = (L + 63) >> 6;
     for (int ch = 0; ch < chunks; ++ch) {
-        const uint32_t dv = ch == 0 ? dv0 : src(ch);
+        const SrcT dvv = ch == 0 ? dv0 : src(ch);
+        const uint32_t dv = desc_of(dvv);
         const int cnt = min(64, L - ch * 64);
-        const bool bad = (lane < cnt) && !desc_valid(dv, NQ);
+        const bool bad = (lane < cnt) && !desc_valid<ANG>(dv, NQ);
         if (__ballot(bad)) { ok = false; break; }
+        // angled gates: lane g computes cos, sin of half of gate g's angle
+        float gc = 1.0f, gs = 0.0f;
+        if constexpr (ANG)
+            if (lane < cnt && kind_ising((int)(dv & 15u))) half_angle(angle_of(dvv), &gc, &gs);
         for (int g = 0; g < cnt; ++g) {
             const uint32_t d = __builtin_amdgcn_readlane(dv, g);
             const int kind = d & 15;
@@ -436,8 +475,35 @@ __device__ __forceinline__ bool run_small_path(const float* __restrict__ T, int 
             const int t = (d >> 4) & 15;
             const int tb = 1 << (NQ - 1 - t);
             const int mask = tb << NQ;
-            const float pr = __shfl_xor(mr, mask, 64), pi = __shfl_xor(mi, mask, 64);
             const bool hi = (i & tb) != 0;
+            if constexpr (ANG) {
+                if (kind >= KIND_RX) {
+                    const float c = bits_f(__builtin_amdgcn_readlane(f_bits(gc), g));
+                    const float s = bits_f(__builtin_amdgcn_readlane(f_bits(gs), g));
+                    if (kind == KIND_RZ || kind == KIND_ZZ) {
+                        // diagonal: e^{-i theta/2} where the (two-wire) parity is
+                        // even, e^{i theta/2} where it is odd
+                        bool odd = hi;
+                        if (kind == KIND_ZZ) odd = ((i >> (NQ - 1 - t)) ^ (i >> (NQ - 1 - (int)((d >> 8) & 15)))) & 1;
+                        const float sg = odd ? s : -s;
+                        const float br = mr, bi = mi;
+                        mr = c * br - sg * bi;
+                        mi = c * bi + sg * br;
+                    } else {
+                        const float pr = __shfl_xor(mr, mask, 64), pi = __shfl_xor(mi, mask, 64);
+                        if (kind == KIND_RX) {       // c m - i s p on both rows
+                            mr = c * mr + s * pi;
+                            mi = c * mi - s * pr;
+                        } else {                     // c m -+ s p (R_y)
+                            const float sg = hi ? s : -s;
+                            mr = c * mr + sg * pr;
+                            mi = c * mi + sg * pi;
+                        }
+                    }
+                    continue;
+                }
+            }
+            const float pr = __shfl_xor(mr, mask, 64), pi = __shfl_xor(mi, mask, 64);
             bool on = true;
             if (kind_controlled(kind)) on = (i >> (NQ - 1 - ((d >> 8) & 15))) & 1;
             if (!on) continue;
@@ -492,14 +558,19 @@ __device__ __forceinline__ void wave_lds_fence() {
 // Runs the circuit on this wave's columns and, with `fit`, leaves per-wave
 // partial sums for the fitness: off-diagonal |m|^2, and the diagonal
 // elements of the wave's columns (lane l < CW holds element (j, j)).
-// gt: this wavefront's gate table in LDS (GATE_TABLE uint4).
+// gt: this wavefront's gate table in LDS (GATE_TABLE uint4, or
+// GATE_TABLE_ANGLED for angled gate sources).
 constexpr int GATE_TABLE = 128;
+constexpr int GATE_TABLE_ANGLED = 192;
 
 template <int NQ, int W, bool IDENT, typename GateSrc>
 __device__ __forceinline__ bool run_lds_path(float2* M, uint4* gt, const float* __restrict__ T, int L,
                                              GateSrc&& src, float* off_out, float2* diag_out,
                                              int wave = -1) {
     constexpr int N = 1 << NQ, CW = N / W, RG = 64 / CW;
+    constexpr bool ANG = src_angled<GateSrc>();
+    constexpr int ES = ANG ? 3 : 2;        // uint4 per gate-table entry
+    using SrcT = std::decay_t<decltype(src(0))>;
     static_assert(CW <= 64 && 64 % CW == 0 && N % RG == 0 && RG == 4, "layout: four row groups per wavefront");
     const int lane = (int)lane_id();
     if (wave < 0) wave = (int)(threadIdx.x >> 6);
@@ -516,7 +587,7 @@ __device__ __forceinline__ bool run_lds_path(float2* M, uint4* gt, const float* 
         if (IDENT) tv[m] = make_float2(r == j ? 1.0f : 0.0f, 0.0f);
         else tv[m] = T2[(size_t)j * N + r];
     }
-    const uint32_t dv0 = L > 0 ? src(0) : 0u;
+    const SrcT dv0 = L > 0 ? src(0) : SrcT{};
 #pragma unroll
     for (int m = 0; m < N / RG; ++m) {
         const int r = m * RG + rg;
@@ -538,9 +609,10 @@ __device__ __forceinline__ bool run_lds_path(float2* M, uint4* gt, const float* 
     constexpr bool NIT_USES_R2 = (N / 2) / RG > 1, NIT_USES_R3 = (N / 2) / RG > 2,
                    NIT_USES_R4 = (N / 2) / RG > 4;
     for (int ch = 0; ch < chunks; ++ch) {
-        const uint32_t dv = ch == 0 ? dv0 : src(ch);
+        const SrcT dvv = ch == 0 ? dv0 : src(ch);
+        const uint32_t dv = desc_of(dvv);
         const int cnt = min(64, L - ch * 64);
-        const bool bad = (lane < cnt) && !desc_valid(dv, NQ);
+        const bool bad = (lane < cnt) && !desc_valid<ANG>(dv, NQ);
         if (__ballot(bad)) { ok = false; break; }
         // Gate program: each lane computes the constants of its own gate (lane
         // g: gate g of the chunk): the byte offsets in M of pair-index bits
@@ -551,11 +623,13 @@ __device__ __forceinline__ bool run_lds_path(float2* M, uint4* gt, const float* 
         // loop reads with broadcast loads one gate ahead; with W > 1 (LDS
         // bandwidth is the bound there) the loop reads them from the lanes
         // with v_readlane, visiting the set bits of a ballot of non-identity
-        // gates.
+        // gates.  Angled gates add a third word pair: cos and sin of half the
+        // gate's angle.  The interaction inserts both of its wires' bits like
+        // a controlled gate; its "control" offset is its second wire.
         const int kind = (int)(dv & 15u);
         const int tpos = NQ - 1 - (int)((dv >> 4) & 15u);
         const int cpos = NQ - 1 - (int)((dv >> 8) & 15u);
-        const bool ctl = kind_controlled(kind);
+        const bool ctl = kind_two_wire(kind);
         const int lo = ctl ? min(tpos, cpos) : tpos, hi = ctl ? max(tpos, cpos) : tpos;
         auto ins = [&](int x) -> uint32_t {
             int y = ins0(x, lo);
@@ -567,14 +641,88 @@ __device__ __forceinline__ bool run_lds_path(float2* M, uint4* gt, const float* 
         const uint4 G0 = make_uint4(ins(1), ins(2), ctl ? (1u << (cpos + (int)ROWB)) : 0u,
                                     1u << (tpos + (int)ROWB));
         const uint4 G1 = make_uint4((uint32_t)kind, ins(4), ins(8), ins(16));
-        // one gate from its table entry (E0, E1); `next` issues the load of
-        // the following entry once the addresses are known and before the
+        uint4 G2 = make_uint4(f_bits(1.0f), 0u, 0u, 0u);
+        if constexpr (ANG) {
+            if (live && kind_ising(kind)) {
+                float gc, gs;
+                half_angle(angle_of(dvv), &gc, &gs);
+                G2 = make_uint4(f_bits(gc), f_bits(gs), 0u, 0u);
+            }
+        }
+        // one gate from its table entry (E0, E1, E2); `next` issues the load
+        // of the following entry once the addresses are known and before the
         // data reads, so the entry is ready when its gate starts
-        auto apply = [&](const uint4 E0, const uint4 E1, auto&& next) {
+        auto apply = [&](const uint4 E0, const uint4 E1, const uint4 E2, auto&& next) {
             const int k = __builtin_amdgcn_readfirstlane((int)E1.x);
             const uint32_t rgo = (mb0 & E0.x) | (mb1 & E0.y);   // the row group's pair bits
             const uint32_t tb = E0.w;
             next();
+            if constexpr (ANG) {
+                if (k >= KIND_RX) {
+                    const float c = bits_f(E2.x), s = bits_f(E2.y);
+                    if (k == KIND_ZZ) {
+                        // diagonal: rows whose two wire bits agree take
+                        // e^{-i theta/2}, the others e^{i theta/2}
+                        constexpr int NIT = (N / 4) / RG;
+                        uint32_t offm[NIT];
+                        offm[0] = 0u;
+                        if constexpr (NIT > 1) offm[1] = E1.y;
+                        if constexpr (NIT > 2) { offm[2] = E1.z; offm[3] = E1.y | E1.z; }
+                        const uint32_t a0 = rgo + jb, cb = E0.z;
+                        float2 X[NIT][4];
+#pragma unroll
+                        for (int m = 0; m < NIT; ++m) {
+                            X[m][0] = at(a0 + offm[m]);
+                            X[m][1] = at(a0 + cb + offm[m]);
+                            X[m][2] = at(a0 + tb + offm[m]);
+                            X[m][3] = at(a0 + cb + tb + offm[m]);
+                        }
+#pragma unroll
+                        for (int m = 0; m < NIT; ++m) {
+                            at(a0 + offm[m]) = phase_minus(X[m][0], c, s);
+                            at(a0 + cb + offm[m]) = phase_plus(X[m][1], c, s);
+                            at(a0 + tb + offm[m]) = phase_plus(X[m][2], c, s);
+                            at(a0 + cb + tb + offm[m]) = phase_minus(X[m][3], c, s);
+                        }
+                        return;
+                    }
+                    constexpr int NIT = (N / 2) / RG;
+                    uint32_t offm[NIT];
+                    offm[0] = 0u;
+                    if constexpr (NIT > 1) offm[1] = E1.y;
+                    if constexpr (NIT > 2) { offm[2] = E1.z; offm[3] = E1.y | E1.z; }
+                    if constexpr (NIT > 4) {
+#pragma unroll
+                        for (int m = 4; m < 8; ++m) offm[m] = offm[m - 4] | E1.w;
+                    }
+                    const uint32_t a0 = rgo + jb, a1 = a0 + tb;
+                    float2 A[NIT], B[NIT];
+#pragma unroll
+                    for (int m = 0; m < NIT; ++m) { A[m] = at(a0 + offm[m]); B[m] = at(a1 + offm[m]); }
+                    if (k == KIND_RZ) {
+#pragma unroll
+                        for (int m = 0; m < NIT; ++m) {
+                            at(a0 + offm[m]) = phase_minus(A[m], c, s);
+                            at(a1 + offm[m]) = phase_plus(B[m], c, s);
+                        }
+                    } else if (k == KIND_RX) {   // a' = c a - i s b, b' = c b - i s a
+#pragma unroll
+                        for (int m = 0; m < NIT; ++m) {
+                            const float2 a = A[m], b = B[m];
+                            at(a0 + offm[m]) = make_float2(c * a.x + s * b.y, c * a.y - s * b.x);
+                            at(a1 + offm[m]) = make_float2(c * b.x + s * a.y, c * b.y - s * a.x);
+                        }
+                    } else {                     // R_y: a' = c a - s b, b' = s a + c b
+#pragma unroll
+                        for (int m = 0; m < NIT; ++m) {
+                            const float2 a = A[m], b = B[m];
+                            at(a0 + offm[m]) = make_float2(c * a.x - s * b.x, c * a.y - s * b.y);
+                            at(a1 + offm[m]) = make_float2(s * a.x + c * b.x, s * a.y + c * b.y);
+                        }
+                    }
+                    return;
+                }
+            }
             if (k >= KIND_CNOT && k <= KIND_CVDG) {
                 constexpr int NIT = (N / 4) / RG;
                 uint32_t offm[NIT];
@@ -641,19 +789,25 @@ __device__ __forceinline__ bool run_lds_path(float2* M, uint4* gt, const float* 
             if (live) {
                 const int rank = (int)__builtin_amdgcn_mbcnt_hi(
                     (uint32_t)(live_mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)live_mask, 0u));
-                gt[2 * rank] = G0;
-                gt[2 * rank + 1] = G1;
+                gt[ES * rank] = G0;
+                gt[ES * rank + 1] = G1;
+                if constexpr (ANG) gt[ES * rank + 2] = G2;
             }
             wave_lds_fence();
             // two gates per iteration, each entry loaded one gate ahead (the
             // unrolled pair keeps the prefetched entries in place)
-            uint4 a0e = make_uint4(0u, 0u, 0u, 0u), a1e = a0e, b0e = a0e, b1e = a0e;
-            if (count > 0) { a0e = gt[0]; a1e = gt[1]; }
+            uint4 a0e = make_uint4(0u, 0u, 0u, 0u), a1e = a0e, a2e = a0e, b0e = a0e, b1e = a0e, b2e = a0e;
+            auto fetch = [&](int e, uint4& x0, uint4& x1, uint4& x2) {
+                x0 = gt[ES * e];
+                x1 = gt[ES * e + 1];
+                if constexpr (ANG) x2 = gt[ES * e + 2];
+            };
+            if (count > 0) fetch(0, a0e, a1e, a2e);
             for (int e = 0; e < count; e += 2) {
-                apply(a0e, a1e, [&] { if (e + 1 < count) { b0e = gt[2 * e + 2]; b1e = gt[2 * e + 3]; } });
+                apply(a0e, a1e, a2e, [&] { if (e + 1 < count) fetch(e + 1, b0e, b1e, b2e); });
                 wave_lds_fence();
                 if (e + 1 >= count) break;
-                apply(b0e, b1e, [&] { if (e + 2 < count) { a0e = gt[2 * e + 4]; a1e = gt[2 * e + 5]; } });
+                apply(b0e, b1e, b2e, [&] { if (e + 2 < count) fetch(e + 2, a0e, a1e, a2e); });
                 wave_lds_fence();
             }
         } else {
@@ -666,7 +820,8 @@ __device__ __forceinline__ bool run_lds_path(float2* M, uint4* gt, const float* 
                 const uint4 E0 = make_uint4(rl(G0.x), rl(G0.y), rl(G0.z), rl(G0.w));
                 const uint4 E1 = make_uint4(rl(G1.x), NIT_USES_R2 ? rl(G1.y) : 0u,
                                             NIT_USES_R3 ? rl(G1.z) : 0u, NIT_USES_R4 ? rl(G1.w) : 0u);
-                apply(E0, E1, [] {});
+                const uint4 E2 = ANG ? make_uint4(rl(G2.x), rl(G2.y), 0u, 0u) : G2;
+                apply(E0, E1, E2, [] {});
                 wave_lds_fence();
             }
         }
@@ -715,6 +870,20 @@ __device__ __forceinline__ void gate_coeffs(int kind, Cplx<Real> G[4]) {
     }
 }
 
+// Coefficients [[G0, G1], [G2, G3]] of a rotation (Eqs. 3-5) from c, s =
+// cos, sin of half its angle.
+template <typename Real>
+__device__ __forceinline__ void rotation_coeffs(int kind, Real c, Real s, Cplx<Real> G[4]) {
+    const Real z = (Real)0;
+    if (kind == KIND_RX) {
+        G[0] = {c, z}; G[1] = {z, -s}; G[2] = {z, -s}; G[3] = {c, z};
+    } else if (kind == KIND_RY) {
+        G[0] = {c, z}; G[1] = {-s, z}; G[2] = {s, z}; G[3] = {c, z};
+    } else {   // R_z
+        G[0] = {c, -s}; G[1] = {z, z}; G[2] = {z, z}; G[3] = {c, s};
+    }
+}
+
 template <typename Real>
 __device__ __forceinline__ Real block_sum(Real v, Real* scratch) {
     v = wave_sum(v);
@@ -727,11 +896,13 @@ __device__ __forceinline__ Real block_sum(Real v, Real* scratch) {
     return t;
 }
 
+// angles: the gates' angles (u32 turn fractions, parallel to gates) or
+// NULL, in which case the Ising kinds are invalid descriptors.
 template <typename Real, bool IDENT>
 __device__ __forceinline__ void lds_generic_body(int n, int L, const uint16_t* gates,
-                                                 const Real* T, uint32_t err, Real* f, Real* g,
-                                                 Real* delta, Real* U, uint32_t* errw,
-                                                 int mode = QE_FIT_EQ11) {
+                                                 const uint32_t* angles, const Real* T, uint32_t err,
+                                                 Real* f, Real* g, Real* delta, Real* U,
+                                                 uint32_t* errw, int mode = QE_FIT_EQ11) {
     __shared__ Real Mr[4096], Mi[4096];
     __shared__ Real red[8];
     const int tid = threadIdx.x, nt = blockDim.x;
@@ -752,14 +923,34 @@ __device__ __forceinline__ void lds_generic_body(int n, int L, const uint16_t* g
         __syncthreads();
         for (int l = 0; l < L; ++l) {
             const uint32_t d = gates[l];
-            if (!desc_valid(d, n)) { ok = false; break; }
+            if (angles ? !desc_valid<true>(d, n) : !desc_valid(d, n)) { ok = false; break; }
             const int kind = d & 15;
             if (kind == KIND_I) continue;
             const int tpos = n - 1 - (int)((d >> 4) & 15);
             const int tb = 1 << tpos;
-            const int cb = kind_controlled(kind) ? 1 << (n - 1 - (int)((d >> 8) & 15)) : 0;
             Cplx<Real> G[4];
-            gate_coeffs<Real>(kind, G);
+            if (kind_ising(kind)) {
+                Real c, s;
+                half_angle(angles[l], &c, &s);
+                if (kind == KIND_ZZ) {
+                    // diagonal: e^{-i theta/2} where the two wire bits agree,
+                    // e^{i theta/2} where they differ
+                    const int cpos = n - 1 - (int)((d >> 8) & 15);
+                    for (int e = tid; e < NN; e += nt) {
+                        const int i = e / N;
+                        const Real sg = (((i >> tpos) ^ (i >> cpos)) & 1) ? s : -s;
+                        const Real ar = Mr[e], ai = Mi[e];
+                        Mr[e] = c * ar - sg * ai;
+                        Mi[e] = c * ai + sg * ar;
+                    }
+                    __syncthreads();
+                    continue;
+                }
+                rotation_coeffs<Real>(kind, c, s, G);
+            } else {
+                gate_coeffs<Real>(kind, G);
+            }
+            const int cb = kind_controlled(kind) ? 1 << (n - 1 - (int)((d >> 8) & 15)) : 0;
             for (int e = tid; e < NN / 2; e += nt) {
                 const int p = e / N, j = e % N;
                 const int i0 = ((p >> tpos) << (tpos + 1)) | (p & (tb - 1));

@@ -19,6 +19,7 @@ struct BatchArgs {
     const void* targets;
     int64_t num_telems;
     int32_t mode;           // QE_FIT_*
+    const uint32_t* angles; // per-gate angles (u32 turn fractions, parallel to gates) or null
     uint32_t* err;          // device error word (atomicOr of QE_DEVERR_*)
 };
 
@@ -72,7 +73,8 @@ struct LoopArgs {
     uint64_t seed;
     uint64_t thr_pm, thr_pc, thr_pg;   // probability thresholds, floor(p * 2^32)
     float r32;                         // mutation step per unit (1 - segFit), in 2^-32 turns
-    uint32_t S;                        // slots per instance: n*n*L*P
+    uint32_t R;                        // regions of Eq. 10 (rotations, then templates)
+    uint32_t S;                        // slots per instance: R*L*P
     uint32_t Q;                        // qutrits per instance: n*L*P
     SlotRec* slot;                     // [I][S]
     QutritRec* qrec;                   // [I][Q]
@@ -88,6 +90,7 @@ struct LoopArgs {
     uint32_t MW;                       // words per instance: ceil(P / 32)
     float* inst_best_f;                // per instance
     uint16_t* inst_best_gates;         // [I][L]
+    uint32_t* inst_best_angles;        // [I][L] (Ising library; zero otherwise)
     const float* su3_tab;              // [4][4096]: cos/sin of angles, cos/sin of phases
     const uint64_t* gen_ptr;           // device generation base (graphs) or null
     uint32_t* err;
@@ -97,20 +100,23 @@ struct LoopArgs {
 hipError_t launch_qeqea_init(const LoopArgs& a, hipStream_t s);
 hipError_t launch_ga_init(const LoopArgs& a, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
+// angles: the circuits' gate angles [I*P*L] (written for the Ising library,
+// read by the evaluation and the update), null for the discrete libraries.
 hipError_t launch_qeqea_sample(const LoopArgs& a, uint64_t gen, uint32_t* slots, uint16_t* gates,
-                               hipStream_t s);
+                               uint32_t* angles, hipStream_t s);
 hipError_t launch_ga_copy(const LoopArgs& a, uint64_t gen, uint16_t* gates, hipStream_t s);
-hipError_t launch_eval_population(const LoopArgs& a, const uint16_t* gates, float* f,
-                                  hipStream_t s);
+hipError_t launch_eval_population(const LoopArgs& a, const uint16_t* gates, const uint32_t* angles,
+                                  float* f, hipStream_t s);
 hipError_t launch_qeqea_fused(const LoopArgs& a, uint64_t gen, uint32_t* slots, uint16_t* gates,
-                              float* f, bool decide, hipStream_t s);
+                              uint32_t* angles, float* f, bool decide, hipStream_t s);
 hipError_t launch_mutation_decisions(const LoopArgs& a, uint64_t gen, hipStream_t s);
 hipError_t launch_scatter(const LoopArgs& a, uint64_t gen, const uint32_t* slots, const float* f,
                           hipStream_t s);
 // slots: the generation's slot indices [I*P*L], or NULL to draw them again
 // from the SAMPLE stream (the internal generation path).
 hipError_t launch_qeqea_update(const LoopArgs& a, uint64_t gen, const uint32_t* slots,
-                               const uint16_t* gates, const float* f, hipStream_t s);
+                               const uint16_t* gates, const uint32_t* angles, const float* f,
+                               hipStream_t s);
 hipError_t launch_mutmask_clear(const LoopArgs& a, hipStream_t s);
 // Dense copy of one field of the encoding state (which: 0 theta, 1 qutrit
 // amplitudes, 2 best_f, 3 best_theta, 4 best qutrit amplitudes).
@@ -122,7 +128,7 @@ hipError_t launch_gen_advance(uint64_t* gen_ptr, uint64_t by, hipStream_t s);
 hipError_t launch_gen_set(uint64_t* gen_ptr, uint64_t v, hipStream_t s);
 hipError_t launch_elite_select(const LoopArgs& a, const float* f, int k, int32_t* idx,
                                hipStream_t s);
-hipError_t launch_elite_eval(const LoopArgs& a, const uint16_t* gates, int k, const int32_t* idx,
-                             double* f64, hipStream_t s);
+hipError_t launch_elite_eval(const LoopArgs& a, const uint16_t* gates, const uint32_t* angles, int k,
+                             const int32_t* idx, double* f64, hipStream_t s);
 
 }  // namespace qe

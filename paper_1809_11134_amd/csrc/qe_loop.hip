@@ -9,6 +9,7 @@
 // pragma below repeats that for this file.
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "../../include/qe.h"
 #include "qe_eval_core.hpp"
@@ -59,11 +60,29 @@ __device__ __forceinline__ uint16_t decode_slot(const LoopArgs& a, uint32_t gen,
     return make_desc(kind, t, c);
 }
 
+// Ising library (Secs. IV-A, IV-C): a rotation slot on wire w becomes the
+// rotation about the measured axis (outcome 0, 1, 2 = x, y, z) on w, a
+// template slot on the unordered pair (a, b) the interaction J on (a, b);
+// both take the slot's angle.  Returns {descriptor, angle}.
+__device__ __forceinline__ uint2 decode_ising(const LoopArgs& a, uint32_t gen, uint32_t i, uint32_t s) {
+    const uint32_t LP = (uint32_t)a.L * (uint32_t)a.P;
+    const uint32_t r = s / LP;
+    const uint32_t th = a.slot[(size_t)i * a.S + s].theta;
+    if (r < (uint32_t)a.n) {
+        const u32x4 w = draw(a.seed, TAG_MEASURE, gen, i, s);
+        const int axis = measure_qutrit(a.qrec[(size_t)i * a.Q + s].q, w.x);
+        return make_uint2(make_desc(KIND_RX + axis, (int)r, 0), th);
+    }
+    int pa, pb;
+    upair_of(a.n, (int)r - a.n, &pa, &pb);
+    return make_uint2(make_desc(KIND_ZZ, pa, pb), th);
+}
+
 // Segment index of Eq. 10 from the SAMPLE draw of position pos: the
 // individual and the region are drawn, the position is the circuit's own.
 __device__ __forceinline__ uint32_t slot_of_draw(const LoopArgs& a, const u32x4& w, uint32_t pos) {
     const uint32_t ind = scale_u32(w.x, (uint32_t)a.P);
-    const uint32_t region = scale_u32(w.y, (uint32_t)(a.n * a.n));
+    const uint32_t region = scale_u32(w.y, a.R);
     return region * (uint32_t)a.L * (uint32_t)a.P + ind * (uint32_t)a.L + pos;
 }
 
@@ -117,7 +136,10 @@ __global__ void inst_best_init_kernel(LoopArgs a) {
     if (a.mutmask)
         for (uint32_t w = 0; w < 2 * a.MW; ++w)
             a.mutmask[((size_t)(w / a.MW) * a.I + i) * a.MW + w % a.MW] = 0u;
-    for (int l = 0; l < a.L; ++l) a.inst_best_gates[(size_t)i * a.L + l] = 0;
+    for (int l = 0; l < a.L; ++l) {
+        a.inst_best_gates[(size_t)i * a.L + l] = 0;
+        a.inst_best_angles[(size_t)i * a.L + l] = 0u;
+    }
 }
 
 __global__ void fill_i32_kernel(int32_t* p, int64_t n, int32_t v) {
@@ -130,7 +152,7 @@ __global__ void gen_set_kernel(uint64_t* g, uint64_t v) { *g = v; }
 
 // ---------------------------------------------------------------- sampling
 __global__ void qeqea_sample_kernel(LoopArgs a, uint64_t gen64, uint32_t* __restrict__ slots,
-                                    uint16_t* __restrict__ gates) {
+                                    uint16_t* __restrict__ gates, uint32_t* __restrict__ angles) {
     const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     const size_t per = (size_t)a.P * a.L;
     if (idx >= (size_t)a.I * per) return;
@@ -139,7 +161,13 @@ __global__ void qeqea_sample_kernel(LoopArgs a, uint64_t gen64, uint32_t* __rest
     const uint32_t k = rem / a.L, pos = rem % a.L;
     const uint32_t s = sample_slot(a, gen, i, k, pos);
     slots[idx] = s;
-    gates[idx] = decode_slot(a, gen, i, s);
+    if (a.lib == LIB_ISING) {
+        const uint2 g = decode_ising(a, gen, i, s);
+        gates[idx] = (uint16_t)g.x;
+        if (angles) angles[idx] = g.y;
+    } else {
+        gates[idx] = decode_slot(a, gen, i, s);
+    }
 }
 
 __global__ void ga_copy_kernel(LoopArgs a, uint64_t gen64, uint16_t* __restrict__ gates) {
@@ -180,10 +208,13 @@ __device__ __forceinline__ void clear_next_mask(const LoopArgs& a, uint32_t gen,
 // `decide` (the internal generation) circuit k also draws the mutation
 // decision of individual k (both run over 0..P-1) and empties its part of the
 // decision mask of the other generation parity.
-template <int NQ, int W, bool SAMPLE>
+// ISING: circuits of the Ising library, whose gates carry angles (read from
+// angles_in, or with SAMPLE decoded and written to angles_out).
+template <int NQ, int W, bool SAMPLE, bool ISING>
 __device__ __forceinline__ void eval_circuit(const LoopArgs& a, uint32_t gen, uint32_t ci,
-                                             const uint16_t* gates_in, uint32_t* slots_out,
-                                             uint16_t* gates_out, float* f_out, bool writer,
+                                             const uint16_t* gates_in, const uint32_t* angles_in,
+                                             uint32_t* slots_out, uint16_t* gates_out,
+                                             uint32_t* angles_out, float* f_out, bool writer,
                                              bool decide, float2* M, uint4* gt, float (*red)[3]) {
     const uint32_t i = ci / (uint32_t)a.P, k = ci % (uint32_t)a.P;
     const int lane = (int)lane_id();
@@ -194,30 +225,47 @@ __device__ __forceinline__ void eval_circuit(const LoopArgs& a, uint32_t gen, ui
     uint32_t kept[KEEP];
 #pragma unroll
     for (int c = 0; c < KEEP; ++c) kept[c] = 0xFFFFFFFFu;
-    auto src = [&](int ch) -> uint32_t {
+    using SrcT = std::conditional_t<ISING, uint2, uint32_t>;
+    auto src = [&](int ch) -> SrcT {
         const int p = ch * 64 + lane;
-        if (!SAMPLE) return p < L ? (uint32_t)gates_in[(size_t)ci * L + p] : 0u;
+        if constexpr (!SAMPLE) {
+            if constexpr (ISING)
+                return p < L ? make_uint2((uint32_t)gates_in[(size_t)ci * L + p], angles_in[(size_t)ci * L + p])
+                             : make_uint2(0u, 0u);
+            else
+                return p < L ? (uint32_t)gates_in[(size_t)ci * L + p] : 0u;
+        }
         const bool pos = p < L;
         const bool dec = decide && writer && p == L;
-        if (!pos && !dec) return 0u;
+        if (!pos && !dec) return SrcT{};
         // one Philox pass: position lanes draw their entry's individual and
         // region, lane L the mutation decision of individual k
         const u32x4 w = draw(a.seed, pos ? (uint32_t)TAG_SAMPLE : (uint32_t)TAG_MUT_IND, gen, i,
                              pos ? k * (uint32_t)L + (uint32_t)p : k);
         if (!pos) {
             if ((uint64_t)w.x < a.thr_pm) mark_mutation(a, gen, i, k);
-            return 0u;
+            return SrcT{};
         }
         const uint32_t s = slot_of_draw(a, w, (uint32_t)p);
 #pragma unroll
         for (int c = 0; c < KEEP; ++c)
             if (c == ch) kept[c] = s;
-        const uint16_t d = decode_slot(a, gen, i, s);
-        if (writer) {
-            if (slots_out) slots_out[(size_t)ci * L + p] = s;
-            gates_out[(size_t)ci * L + p] = d;
+        if constexpr (ISING) {
+            const uint2 g = decode_ising(a, gen, i, s);
+            if (writer) {
+                if (slots_out) slots_out[(size_t)ci * L + p] = s;
+                gates_out[(size_t)ci * L + p] = (uint16_t)g.x;
+                angles_out[(size_t)ci * L + p] = g.y;
+            }
+            return g;
+        } else {
+            const uint16_t d = decode_slot(a, gen, i, s);
+            if (writer) {
+                if (slots_out) slots_out[(size_t)ci * L + p] = s;
+                gates_out[(size_t)ci * L + p] = d;
+            }
+            return (uint32_t)d;
         }
-        return (uint32_t)d;
     };
     float fv;
     bool ok;
@@ -256,33 +304,36 @@ __device__ __forceinline__ void eval_circuit(const LoopArgs& a, uint32_t gen, ui
         mark_mutation(a, gen, i, k);
 }
 
-template <int NQ, int W, bool SAMPLE>
+template <int NQ, int W, bool SAMPLE, bool ISING = false>
 __global__ __launch_bounds__(256) void population_kernel(LoopArgs a, uint64_t gen64,
                                                          const uint16_t* __restrict__ gates_in,
+                                                         const uint32_t* __restrict__ angles_in,
                                                          uint32_t* __restrict__ slots_out,
                                                          uint16_t* __restrict__ gates_out,
+                                                         uint32_t* __restrict__ angles_out,
                                                          float* __restrict__ f_out, bool decide) {
     const uint32_t gen = gen_of(a, gen64);
     const uint32_t total = (uint32_t)a.I * (uint32_t)a.P;
     if constexpr (W == 0) {
+        static_assert(!ISING || NQ <= 3, "Ising circuits of 4 or more wires take the LDS-staged path");
         const uint32_t ci = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
         if (ci >= total) return;
-        eval_circuit<NQ, 0, SAMPLE>(a, gen, ci, gates_in, slots_out, gates_out, f_out, true, decide,
-                                    nullptr, nullptr, nullptr);
+        eval_circuit<NQ, 0, SAMPLE, ISING>(a, gen, ci, gates_in, angles_in, slots_out, gates_out,
+                                           angles_out, f_out, true, decide, nullptr, nullptr, nullptr);
     } else {
         // W = 1: four circuits per workgroup, one per wavefront (no barrier
         // is shared, so a wavefront past the end may leave); W > 1: one
         // circuit per workgroup of W wavefronts
         constexpr int N = 1 << NQ, CPB = W == 1 ? 4 : 1;
         __shared__ float2 M[CPB][N * N];
-        __shared__ uint4 GT[W == 1 ? 4 : W][GATE_TABLE];
+        __shared__ uint4 GT[W == 1 ? 4 : W][ISING ? GATE_TABLE_ANGLED : GATE_TABLE];
         __shared__ float red[4][3];
         const int wave = (int)(threadIdx.x >> 6);
         const uint32_t ci = W == 1 ? blockIdx.x * CPB + (uint32_t)wave : blockIdx.x;
         if (ci >= total) return;
-        eval_circuit<NQ, W, SAMPLE>(a, gen, ci, gates_in, slots_out, gates_out, f_out,
-                                    W == 1 || threadIdx.x < 64, decide, M[W == 1 ? wave : 0], GT[wave],
-                                    red);
+        eval_circuit<NQ, W, SAMPLE, ISING>(a, gen, ci, gates_in, angles_in, slots_out, gates_out,
+                                           angles_out, f_out, W == 1 || threadIdx.x < 64, decide,
+                                           M[W == 1 ? wave : 0], GT[wave], red);
     }
 }
 
@@ -446,7 +497,7 @@ __device__ __forceinline__ void update_part_b(const LoopArgs& a, uint32_t gen, u
     extern __shared__ uint16_t list[];        // P entries (launch-time size)
     __shared__ uint32_t total;
     const uint32_t L = (uint32_t)a.L, P = (uint32_t)a.P, LP = L * P;
-    const uint32_t per = (uint32_t)(a.n * a.n) * L;           // slots of one individual
+    const uint32_t per = a.R * L;                               // slots of one individual
     const uint32_t chunks = (per + UPD_BLOCK - 1) / UPD_BLOCK;
     const uint32_t i = b / per_inst;
     if (i >= (uint32_t)a.I) return;
@@ -517,6 +568,7 @@ __host__ __device__ inline int part_c_waves(int P) { return P > 2048 ? 4 : (P > 
 
 __device__ __forceinline__ void update_part_c(const LoopArgs& a, uint32_t b,
                                               const uint16_t* __restrict__ gates,
+                                              const uint32_t* __restrict__ angles,
                                               const float* __restrict__ f) {
     __shared__ float cbest[4];
     __shared__ uint32_t cidx[4];
@@ -558,20 +610,24 @@ __device__ __forceinline__ void update_part_c(const LoopArgs& a, uint32_t b,
         }
     }
     if (i >= (uint32_t)a.I || bk == 0xFFFFFFFFu || !(best > a.inst_best_f[i])) return;
-    const uint16_t* src = gates + ((size_t)i * P + bk) * L;
-    for (uint32_t l = lane; l < L; l += 64) a.inst_best_gates[(size_t)i * L + l] = src[l];
+    const size_t row = ((size_t)i * P + bk) * L;
+    for (uint32_t l = lane; l < L; l += 64) {
+        a.inst_best_gates[(size_t)i * L + l] = gates[row + l];
+        if (angles) a.inst_best_angles[(size_t)i * L + l] = angles[row + l];
+    }
     if (lane == 0) a.inst_best_f[i] = best;
 }
 
 __global__ __launch_bounds__(UPD_BLOCK) void qeqea_update_kernel(LoopArgs a, uint64_t gen64,
                                                                  const uint32_t* __restrict__ slots,
                                                                  const uint16_t* __restrict__ gates,
+                                                                 const uint32_t* __restrict__ angles,
                                                                  const float* __restrict__ f,
                                                                  uint32_t nC, uint32_t nB,
                                                                  uint32_t per_inst) {
     const uint32_t gen = gen_of(a, gen64);
     if (blockIdx.x < nC)
-        update_part_c(a, blockIdx.x, gates, f);
+        update_part_c(a, blockIdx.x, gates, angles, f);
     else if (blockIdx.x < nC + nB)
         update_part_b(a, gen, blockIdx.x - nC, per_inst);
     else
@@ -725,15 +781,16 @@ __global__ __launch_bounds__(1024) void elite_select_kernel(LoopArgs a, const fl
 }
 
 __global__ __launch_bounds__(256) void elite_eval_kernel(LoopArgs a, const uint16_t* __restrict__ gates,
+                                                         const uint32_t* __restrict__ angles,
                                                          int k, const int32_t* __restrict__ idx,
                                                          double* __restrict__ f64) {
     const int i = blockIdx.x / k, e = blockIdx.x % k;
     const int c = idx[(size_t)i * k + e];
     uint32_t err = (c < 0 || c >= a.P) ? (uint32_t)QE_DEVERR_RANGE : 0u;
-    const uint16_t* g = gates + ((size_t)i * a.P + (err ? 0 : c)) * a.L;
+    const size_t row = ((size_t)i * a.P + (err ? 0 : c)) * a.L;
     const double* T = a.target64 + (size_t)2 * i * ((size_t)1 << (2 * a.n));
-    lds_generic_body<double, false>(a.n, a.L, g, T, err, f64 + blockIdx.x, nullptr, nullptr,
-                                    nullptr, a.err, a.fit_mode);
+    lds_generic_body<double, false>(a.n, a.L, gates + row, angles ? angles + row : nullptr, T, err,
+                                    f64 + blockIdx.x, nullptr, nullptr, nullptr, a.err, a.fit_mode);
 }
 
 // Complex128 -> complex64 copy of the targets for the FP32 path.
@@ -778,8 +835,8 @@ hipError_t launch_gen_set(uint64_t* g, uint64_t v, hipStream_t s) {
 }
 
 hipError_t launch_qeqea_sample(const LoopArgs& a, uint64_t gen, uint32_t* slots, uint16_t* gates,
-                               hipStream_t s) {
-    qeqea_sample_kernel<<<blocks((size_t)a.I * a.P * a.L, 256), 256, 0, s>>>(a, gen, slots, gates);
+                               uint32_t* angles, hipStream_t s) {
+    qeqea_sample_kernel<<<blocks((size_t)a.I * a.P * a.L, 256), 256, 0, s>>>(a, gen, slots, gates, angles);
     return hipGetLastError();
 }
 
@@ -789,31 +846,44 @@ hipError_t launch_ga_copy(const LoopArgs& a, uint64_t gen, uint16_t* gates, hipS
 }
 
 template <bool SAMPLE>
-static void launch_population(const LoopArgs& a, uint64_t gen, const uint16_t* gin, uint32_t* sout,
-                              uint16_t* gout, float* f, hipStream_t s, bool decide = false) {
+static void launch_population(const LoopArgs& a, uint64_t gen, const uint16_t* gin, const uint32_t* ain,
+                              uint32_t* sout, uint16_t* gout, uint32_t* aout, float* f, hipStream_t s,
+                              bool decide = false) {
     const uint32_t total = (uint32_t)a.I * (uint32_t)a.P;
-    const bool lds = schedule_lds(a.n);
     const unsigned wb = blocks(total, 4);
+    if (a.lib == LIB_ISING) {
+        // one wavefront per circuit below 4 wires, the LDS-staged layout above
+        switch (a.n) {
+            case 2: population_kernel<2, 0, SAMPLE, true><<<wb, 256, 0, s>>>(a, gen, gin, ain, sout, gout, aout, f, decide); break;
+            case 3: population_kernel<3, 0, SAMPLE, true><<<wb, 256, 0, s>>>(a, gen, gin, ain, sout, gout, aout, f, decide); break;
+            case 4: population_kernel<4, 1, SAMPLE, true><<<wb, 256, 0, s>>>(a, gen, gin, ain, sout, gout, aout, f, decide); break;
+            case 5: population_kernel<5, 2, SAMPLE, true><<<total, 128, 0, s>>>(a, gen, gin, ain, sout, gout, aout, f, decide); break;
+            default: population_kernel<6, 4, SAMPLE, true><<<total, 256, 0, s>>>(a, gen, gin, ain, sout, gout, aout, f, decide); break;
+        }
+        return;
+    }
+    const bool lds = schedule_lds(a.n);
     if (lds && a.n >= 4) {
         switch (a.n) {
-            case 4: population_kernel<4, 1, SAMPLE><<<wb, 256, 0, s>>>(a, gen, gin, sout, gout, f, decide); break;
-            case 5: population_kernel<5, 2, SAMPLE><<<total, 128, 0, s>>>(a, gen, gin, sout, gout, f, decide); break;
-            default: population_kernel<6, 4, SAMPLE><<<total, 256, 0, s>>>(a, gen, gin, sout, gout, f, decide); break;
+            case 4: population_kernel<4, 1, SAMPLE><<<wb, 256, 0, s>>>(a, gen, gin, ain, sout, gout, aout, f, decide); break;
+            case 5: population_kernel<5, 2, SAMPLE><<<total, 128, 0, s>>>(a, gen, gin, ain, sout, gout, aout, f, decide); break;
+            default: population_kernel<6, 4, SAMPLE><<<total, 256, 0, s>>>(a, gen, gin, ain, sout, gout, aout, f, decide); break;
         }
         return;
     }
     switch (a.n) {
-        case 1: population_kernel<1, 0, SAMPLE><<<wb, 256, 0, s>>>(a, gen, gin, sout, gout, f, decide); break;
-        case 2: population_kernel<2, 0, SAMPLE><<<wb, 256, 0, s>>>(a, gen, gin, sout, gout, f, decide); break;
-        case 3: population_kernel<3, 0, SAMPLE><<<wb, 256, 0, s>>>(a, gen, gin, sout, gout, f, decide); break;
-        case 4: population_kernel<4, 0, SAMPLE><<<wb, 256, 0, s>>>(a, gen, gin, sout, gout, f, decide); break;
-        case 5: population_kernel<5, 0, SAMPLE><<<wb, 256, 0, s>>>(a, gen, gin, sout, gout, f, decide); break;
-        default: population_kernel<6, 0, SAMPLE><<<wb, 256, 0, s>>>(a, gen, gin, sout, gout, f, decide); break;
+        case 1: population_kernel<1, 0, SAMPLE><<<wb, 256, 0, s>>>(a, gen, gin, ain, sout, gout, aout, f, decide); break;
+        case 2: population_kernel<2, 0, SAMPLE><<<wb, 256, 0, s>>>(a, gen, gin, ain, sout, gout, aout, f, decide); break;
+        case 3: population_kernel<3, 0, SAMPLE><<<wb, 256, 0, s>>>(a, gen, gin, ain, sout, gout, aout, f, decide); break;
+        case 4: population_kernel<4, 0, SAMPLE><<<wb, 256, 0, s>>>(a, gen, gin, ain, sout, gout, aout, f, decide); break;
+        case 5: population_kernel<5, 0, SAMPLE><<<wb, 256, 0, s>>>(a, gen, gin, ain, sout, gout, aout, f, decide); break;
+        default: population_kernel<6, 0, SAMPLE><<<wb, 256, 0, s>>>(a, gen, gin, ain, sout, gout, aout, f, decide); break;
     }
 }
 
-hipError_t launch_eval_population(const LoopArgs& a, const uint16_t* gates, float* f, hipStream_t s) {
-    launch_population<false>(a, 0, gates, nullptr, nullptr, f, s);
+hipError_t launch_eval_population(const LoopArgs& a, const uint16_t* gates, const uint32_t* angles,
+                                  float* f, hipStream_t s) {
+    launch_population<false>(a, 0, gates, angles, nullptr, nullptr, nullptr, f, s);
     return hipGetLastError();
 }
 
@@ -823,13 +893,13 @@ hipError_t launch_ga_eval(const LoopArgs& a, uint64_t gen, float* f, hipStream_t
     LoopArgs b = a;
     b.gen_ptr = nullptr;
     if (a.gen_ptr) return hipErrorInvalidValue;   // callers use launch_ga_copy + eval in graphs
-    launch_population<false>(b, 0, a.genomes[gen & 1], nullptr, nullptr, f, s);
+    launch_population<false>(b, 0, a.genomes[gen & 1], nullptr, nullptr, nullptr, nullptr, f, s);
     return hipGetLastError();
 }
 
 hipError_t launch_qeqea_fused(const LoopArgs& a, uint64_t gen, uint32_t* slots, uint16_t* gates,
-                              float* f, bool decide, hipStream_t s) {
-    launch_population<true>(a, gen, nullptr, slots, gates, f, s, decide);
+                              uint32_t* angles, float* f, bool decide, hipStream_t s) {
+    launch_population<true>(a, gen, nullptr, nullptr, slots, gates, angles, f, s, decide);
     return hipGetLastError();
 }
 
@@ -846,21 +916,23 @@ hipError_t launch_scatter(const LoopArgs& a, uint64_t gen, const uint32_t* slots
 }
 
 hipError_t launch_qeqea_update(const LoopArgs& a, uint64_t gen, const uint32_t* slots,
-                               const uint16_t* gates, const float* f, hipStream_t s) {
+                               const uint16_t* gates, const uint32_t* angles, const float* f,
+                               hipStream_t s) {
     if (a.P > UPD_MAX_P) return hipErrorInvalidValue;
     const uint32_t nC = blocks((size_t)a.I * part_c_waves(a.P), UPD_BLOCK / 64);
     const uint32_t nA = blocks((size_t)a.I * a.P * a.L, UPD_BLOCK);
     // part B: per instance, enough workgroups for the (mutated individual,
     // slot chunk) items up to four standard deviations above the binomial
     // mean (more items loop)
-    const size_t chunks = ((size_t)a.n * a.n * a.L + UPD_BLOCK - 1) / UPD_BLOCK;
+    const size_t chunks = ((size_t)a.R * a.L + UPD_BLOCK - 1) / UPD_BLOCK;
     const double pm = (double)a.thr_pm / 4294967296.0;
     const double expect = pm * a.P * chunks, sd = std::sqrt(a.P * pm * (1.0 - pm)) * chunks;
     const uint32_t per_inst = (uint32_t)std::max<double>(
         1.0, std::min<double>(std::ceil(expect + 4.0 * sd + 8.0), (double)a.P * chunks));
     const uint32_t nB = per_inst * (uint32_t)a.I;
     const size_t lds = ((size_t)a.P * sizeof(uint16_t) + 15) & ~(size_t)15;
-    qeqea_update_kernel<<<nC + nB + nA, UPD_BLOCK, lds, s>>>(a, gen, slots, gates, f, nC, nB, per_inst);
+    qeqea_update_kernel<<<nC + nB + nA, UPD_BLOCK, lds, s>>>(a, gen, slots, gates, angles, f, nC, nB,
+                                                             per_inst);
     return hipGetLastError();
 }
 
@@ -886,9 +958,9 @@ hipError_t launch_elite_select(const LoopArgs& a, const float* f, int k, int32_t
     return hipGetLastError();
 }
 
-hipError_t launch_elite_eval(const LoopArgs& a, const uint16_t* gates, int k, const int32_t* idx,
-                             double* f64, hipStream_t s) {
-    elite_eval_kernel<<<a.I * k, 256, 0, s>>>(a, gates, k, idx, f64);
+hipError_t launch_elite_eval(const LoopArgs& a, const uint16_t* gates, const uint32_t* angles, int k,
+                             const int32_t* idx, double* f64, hipStream_t s) {
+    elite_eval_kernel<<<a.I * k, 256, 0, s>>>(a, gates, angles, k, idx, f64);
     return hipGetLastError();
 }
 

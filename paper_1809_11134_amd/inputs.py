@@ -6,7 +6,9 @@ This module holds none of the method's arithmetic: it only draws gate lists
 built from the drawn gate lists by whichever side consumes them.
 
 Descriptor layout: kind in bits 0-3, target wire in bits 4-7, control wire in
-bits 8-11.  Kinds: 0 I, 1 NOT, 2 CNOT, 3 CV, 4 CV+, 5 H, 6 T.
+bits 8-11.  Kinds: 0 I, 1 NOT, 2 CNOT, 3 CV, 4 CV+, 5 H, 6 T; the Ising kinds
+7 R_x, 8 R_y, 9 R_z, 10 J (second wire in the control field) carry an angle,
+a u32 fraction of a full turn, drawn here as raw 32-bit integers.
 
 The paper's own workloads are small reversible targets (CNOT, Toffoli,
 Peres, CCCNOT; Sec. V, Tables I-III) reached by short circuits of library
@@ -17,8 +19,14 @@ batch sizes of the throughput study.
 import numpy as np
 
 I_, NOT, CNOT, CV, CVDG, H, T = range(7)
+RX, RY, RZ, ZZ = 7, 8, 9, 10
 LIB_NCV = 0      # {I, NOT, CNOT, CV, CV+}
 LIB_HT_NCV = 1   # {H, T, CNOT, CV, CV+}
+LIB_ISING = 2    # {R_x, R_y, R_z, J} with angles
+
+# angles that sit on the quarter-turn boundaries of the half-angle reduction
+EDGE_ANGLES = np.array([0, 1, (1 << 30) - 1, 1 << 30, (1 << 31) - 1, 1 << 31, 3 << 30,
+                        (3 << 30) - 1, 0xFFFFFFFF], np.uint32)
 
 SEED_BASE = 1809111340
 
@@ -82,6 +90,32 @@ def planted_population(rng, target_gates, count, n, L, lib, max_edits=8):
         g = (g + [desc(I_)] * L)[:L]
         out[k] = g
     return out
+
+
+def random_ising_circuits(rng, count, n, L, discrete_frac=0.0, edge_frac=0.1):
+    """(gates [count, L] uint16, angles [count, L] uint32): each gate is a
+    rotation about x, y or z on a random wire or (n >= 2) an interaction on
+    a random unordered wire pair, with a uniform 32-bit angle (a fraction
+    edge_frac of them taken from EDGE_ANGLES); a fraction discrete_frac of
+    the gates are drawn from {H, T, CNOT, CV, CV+} instead (angle 0)."""
+    kinds = [RX, RY, RZ] + ([ZZ] if n >= 2 else [])
+    disc = library(LIB_HT_NCV, n)
+    gates = np.zeros((count, L), np.uint16)
+    angles = rng.integers(0, 1 << 32, size=(count, L), dtype=np.uint64).astype(np.uint32)
+    edge = rng.random((count, L)) < edge_frac
+    angles[edge] = EDGE_ANGLES[rng.integers(0, len(EDGE_ANGLES), size=int(edge.sum()))]
+    for c in range(count):
+        for p in range(L):
+            if rng.random() < discrete_frac:
+                gates[c, p] = disc[rng.integers(0, len(disc))]
+                angles[c, p] = 0
+                continue
+            k = int(kinds[rng.integers(0, len(kinds))])
+            a = int(rng.integers(0, n))
+            b = int(rng.integers(0, n - 1)) if n >= 2 else 0
+            b = b + 1 if b >= a else b
+            gates[c, p] = desc(k, a, b if k == ZZ else 0)
+    return gates, angles
 
 
 # ----------------------------------------------------------------- workloads
@@ -153,3 +187,16 @@ def workload_qeqea_n5(instances=1024, P=64, L=40):
                 target_gates=[random_target_gates(rng, 5, 16, permutation=True)
                               for _ in range(instances)],
                 seed=SEED_BASE + 5)
+
+
+def workload_qeqea_ising_n4(P=4096, L=30, instances=1):
+    """n=4, the Ising library of Sec. III (rotations about x, y, z and the
+    interaction on each of the 6 wire pairs), QEQEA with P=4096 circuits of
+    30 gates per generation; target = product of 12 random NOT/CNOT gates
+    (a reversible permutation, as the paper's targets are)."""
+    rng = np.random.default_rng(SEED_BASE + 6)
+    return dict(name="qeqea_ising_n4_p4096_l30", n=4, lib=LIB_ISING, algorithm="qeqea", P=P, L=L,
+                instances=instances, generations=100,
+                target_gates=[random_target_gates(rng, 4, 12, permutation=True)
+                              for _ in range(instances)],
+                seed=SEED_BASE + 6)

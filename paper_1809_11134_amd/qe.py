@@ -13,7 +13,8 @@ LIB_PATH = os.path.join(HERE, "libqe.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "qe.h")
 
 QE_OK, QE_ERR_INVALID, QE_ERR_UNSUPPORTED, QE_ERR_DEVICE, QE_ERR_OOM, QE_ERR_NUMERIC, QE_ERR_STATE = range(7)
-LIB_NCV, LIB_HT_NCV = 0, 1
+LIB_NCV, LIB_HT_NCV, LIB_ISING = 0, 1, 2
+KIND_RX, KIND_RY, KIND_RZ, KIND_ZZ = 7, 8, 9, 10     # Ising kinds; angles are u32 turn fractions
 ALG_QEQEA, ALG_GA = 0, 1
 FIT_EQ11, FIT_PHASE_INSENSITIVE = 0, 1
 (PATH_FP32, PATH_FP32_REG, PATH_FP32_LDS, PATH_MFMA_BF16, PATH_MFMA_FP16, PATH_MFMA_BF16_RAW,
@@ -33,7 +34,8 @@ class Batch(ctypes.Structure):
                 ("gate_offsets_dev", ctypes.c_void_p), ("gates_dev", ctypes.c_void_p),
                 ("num_gates", ctypes.c_int64), ("target_stride", ctypes.c_int64),
                 ("target_offsets_dev", ctypes.c_void_p), ("targets_dev", ctypes.c_void_p),
-                ("num_target_elems", ctypes.c_int64), ("fitness_mode", ctypes.c_int32)]
+                ("num_target_elems", ctypes.c_int64), ("fitness_mode", ctypes.c_int32),
+                ("angles_dev", ctypes.c_void_p)]
 
 
 class Problem(ctypes.Structure):
@@ -73,15 +75,15 @@ def load():
         "qe_create": [P(Problem), P(vp)],
         "qe_destroy": [vp],
         "qe_set_targets": [vp, vp, vp],
-        "qe_sample": [vp, u64, vp, vp, vp],
-        "qe_eval_population": [vp, vp, vp, vp],
-        "qe_update": [vp, u64, vp, vp, vp, vp],
+        "qe_sample": [vp, u64, vp, vp, vp, vp],
+        "qe_eval_population": [vp, vp, vp, vp, vp],
+        "qe_update": [vp, u64, vp, vp, vp, vp, vp],
         "qe_generation": [vp, u64, vp, vp],
         "qe_run_graph": [vp, u64, i32, vp, vp],
-        "qe_sample_eval": [vp, u64, vp, vp, vp, vp],
+        "qe_sample_eval": [vp, u64, vp, vp, vp, vp, vp],
         "qe_graph_prepare": [vp, i32, vp],
-        "qe_elite_recheck": [vp, vp, vp, i32, vp, vp, vp],
-        "qe_get_best": [vp, i32, vp, P(ctypes.c_float), P(ctypes.c_double)],
+        "qe_elite_recheck": [vp, vp, vp, vp, i32, vp, vp, vp],
+        "qe_get_best": [vp, i32, vp, vp, P(ctypes.c_float), P(ctypes.c_double)],
         "qe_checkpoint": [vp, vp, P(ctypes.c_size_t)],
         "qe_restore": [vp, vp, ctypes.c_size_t],
         "qe_state_read": [vp, i32, vp, P(i64), vp],
@@ -135,17 +137,36 @@ def _gates(t):
     return t.contiguous()
 
 
+def _angles(t):
+    """Device angles as int32 storage of the u32 turn fractions."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if t.dtype != torch.int32:
+        t = t.to(torch.int64) & 0xFFFFFFFF
+        t = torch.where(t >= 1 << 31, t - (1 << 32), t).to(torch.int32)
+    return t.contiguous()
+
+
 def make_batch(gates, targets, n=None, L=None, nq=None, goff=None, toff=None, target_stride=None,
-               fitness_mode=0):
+               fitness_mode=0, angles=None):
     """Builds a qe_batch from device tensors.  gates: int16/int32 descriptors
     ([B, L] for uniform lengths, flat with goff for uneven); targets: complex
     tensor ([T, N, N] or flat); n: uniform width or None with nq (int8 [B]);
     target_stride: complex elements between targets (0 = shared) or None with
-    toff (int64 [B])."""
+    toff (int64 [B]); angles: None, or one u32 turn fraction per gate (int32
+    storage, same shape as gates) for circuits with Ising gates."""
     keep = []
     b = Batch()
     g = _gates(gates)
     keep.append(g)
+    a = _angles(angles)
+    if a is not None:
+        if a.numel() != g.numel():
+            raise ValueError("one angle per gate")
+        keep.append(a)
+        b.angles_dev = a.data_ptr() if a.numel() else None
     if L is not None and goff is None:
         B = g.numel() // L if L > 0 else 0
         b.uniform_L = L
@@ -182,12 +203,14 @@ def make_batch(gates, targets, n=None, L=None, nq=None, goff=None, toff=None, ta
 
 
 def eval_fitness(gates, targets, n=None, L=None, nq=None, goff=None, toff=None, target_stride=0,
-                 path=PATH_FP32, want_g=False, want_delta=False, stream=None, fitness_mode=0):
+                 path=PATH_FP32, want_g=False, want_delta=False, stream=None, fitness_mode=0,
+                 angles=None):
     """Eq. 11 fitness (or, with fitness_mode=FIT_PHASE_INSENSITIVE, the
     phase-insensitive fitness) of a batch on the FP32 or MFMA paths.  targets
-    complex64.  Returns (f, g or None, delta or None) as float32 tensors."""
+    complex64; angles as in make_batch.  Returns (f, g or None, delta or None)
+    as float32 tensors."""
     targets = targets.to(torch.complex64) if targets.dtype != torch.complex64 else targets
-    b, keep, B = make_batch(gates, targets, n, L, nq, goff, toff, target_stride, fitness_mode)
+    b, keep, B = make_batch(gates, targets, n, L, nq, goff, toff, target_stride, fitness_mode, angles)
     dev = targets.device
     f = torch.empty(B, dtype=torch.float32, device=dev)
     g = torch.empty(B, dtype=torch.float32, device=dev) if want_g else None
@@ -197,9 +220,10 @@ def eval_fitness(gates, targets, n=None, L=None, nq=None, goff=None, toff=None, 
 
 
 def eval_fitness_fp64(gates, targets, n=None, L=None, nq=None, goff=None, toff=None,
-                      target_stride=0, want_g=False, want_delta=False, stream=None, fitness_mode=0):
+                      target_stride=0, want_g=False, want_delta=False, stream=None, fitness_mode=0,
+                      angles=None):
     targets = targets.to(torch.complex128) if targets.dtype != torch.complex128 else targets
-    b, keep, B = make_batch(gates, targets, n, L, nq, goff, toff, target_stride, fitness_mode)
+    b, keep, B = make_batch(gates, targets, n, L, nq, goff, toff, target_stride, fitness_mode, angles)
     dev = targets.device
     f = torch.empty(B, dtype=torch.float64, device=dev)
     g = torch.empty(B, dtype=torch.float64, device=dev) if want_g else None
@@ -208,9 +232,9 @@ def eval_fitness_fp64(gates, targets, n=None, L=None, nq=None, goff=None, toff=N
     return f, g, d
 
 
-def build_unitary(gates, n, L, precision=1, stream=None):
+def build_unitary(gates, n, L, precision=1, stream=None, angles=None):
     """Unitaries of B circuits of n wires and L gates: [B, N, N] complex."""
-    b, keep, B = make_batch(gates, None, n=n, L=L)
+    b, keep, B = make_batch(gates, None, n=n, L=L, angles=angles)
     N = 1 << n
     dtype = torch.complex128 if precision == 1 else torch.complex64
     out = torch.empty((B, N, N), dtype=dtype, device=gates.device)
@@ -254,6 +278,7 @@ class Context:
                                fitness_mode)
         self.n, self.L, self.P, self.I = n, L, P, instances
         self.algorithm = algorithm
+        self.ising = library == LIB_ISING
         h = ctypes.c_void_p(0)
         _call("qe_create", ctypes.byref(self.problem), ctypes.byref(h))
         self.handle = h
@@ -279,21 +304,30 @@ class Context:
         self._keep = [t]
         _call("qe_set_targets", self.handle, _ptr(t), _stream(stream))
 
+    def _new_angles(self):
+        if not self.ising:
+            return None
+        return torch.empty((self.circuits, self.L), dtype=torch.int32,
+                           device=torch.device("cuda", torch.cuda.current_device()))
+
     def sample(self, gen, stream=None):
+        """(slots, gates), and for the Ising library (slots, gates, angles)."""
         dev = torch.device("cuda", torch.cuda.current_device())
         slots = torch.empty((self.circuits, self.L), dtype=torch.int32, device=dev)
         gates = torch.empty((self.circuits, self.L), dtype=torch.int16, device=dev)
-        _call("qe_sample", self.handle, gen, _ptr(slots), _ptr(gates), _stream(stream))
-        return slots, gates
+        angles = self._new_angles()
+        _call("qe_sample", self.handle, gen, _ptr(slots), _ptr(gates), _ptr(angles), _stream(stream))
+        return (slots, gates, angles) if self.ising else (slots, gates)
 
-    def eval_population(self, gates, stream=None):
+    def eval_population(self, gates, angles=None, stream=None):
         f = torch.empty(self.circuits, dtype=torch.float32, device=gates.device)
-        _call("qe_eval_population", self.handle, _ptr(_gates(gates)), _ptr(f), _stream(stream))
+        _call("qe_eval_population", self.handle, _ptr(_gates(gates)), _ptr(_angles(angles)), _ptr(f),
+              _stream(stream))
         return f
 
-    def update(self, gen, slots, gates, f, stream=None):
-        _call("qe_update", self.handle, gen, _ptr(slots), _ptr(_gates(gates)), _ptr(f.contiguous()),
-              _stream(stream))
+    def update(self, gen, slots, gates, f, angles=None, stream=None):
+        _call("qe_update", self.handle, gen, _ptr(slots), _ptr(_gates(gates)), _ptr(_angles(angles)),
+              _ptr(f.contiguous()), _stream(stream))
 
     def generation(self, gen, f=None, stream=None):
         if f is None:
@@ -302,7 +336,8 @@ class Context:
         _call("qe_generation", self.handle, gen, _ptr(f), _stream(stream))
         return f
 
-    def sample_eval(self, gen, slots=None, gates=None, f=None, stream=None):
+    def sample_eval(self, gen, slots=None, gates=None, f=None, stream=None, angles=None):
+        """(slots, gates, f), and for the Ising library (slots, gates, angles, f)."""
         dev = torch.device("cuda", torch.cuda.current_device())
         if slots is None:
             slots = torch.empty((self.circuits, self.L), dtype=torch.int32, device=dev)
@@ -310,8 +345,11 @@ class Context:
             gates = torch.empty((self.circuits, self.L), dtype=torch.int16, device=dev)
         if f is None:
             f = torch.empty(self.circuits, dtype=torch.float32, device=dev)
-        _call("qe_sample_eval", self.handle, gen, _ptr(slots), _ptr(gates), _ptr(f), _stream(stream))
-        return slots, gates, f
+        if angles is None:
+            angles = self._new_angles()
+        _call("qe_sample_eval", self.handle, gen, _ptr(slots), _ptr(gates), _ptr(angles), _ptr(f),
+              _stream(stream))
+        return (slots, gates, angles, f) if self.ising else (slots, gates, f)
 
     def graph_prepare(self, n_gen, f_hist=None):
         _call("qe_graph_prepare", self.handle, n_gen, _ptr(f_hist))
@@ -319,21 +357,24 @@ class Context:
     def run_graph(self, first_gen, n_gen, f_hist=None, stream=None):
         _call("qe_run_graph", self.handle, first_gen, n_gen, _ptr(f_hist), _stream(stream))
 
-    def elite_recheck(self, gates, f, k, stream=None):
+    def elite_recheck(self, gates, f, k, stream=None, angles=None):
         idx = torch.empty((self.I, k), dtype=torch.int32, device=f.device)
         f64 = torch.empty((self.I, k), dtype=torch.float64, device=f.device)
         _call("qe_elite_recheck", self.handle, _ptr(_gates(gates) if gates is not None else None),
-              _ptr(f.contiguous()), k,
+              _ptr(_angles(angles)), _ptr(f.contiguous()), k,
               _ptr(idx), _ptr(f64), _stream(stream))
         return idx, f64
 
-    def get_best(self, instance=0, with_fp64=True):
+    def get_best(self, instance=0, with_fp64=True, with_angles=False):
+        """(gates, f32, f64 or None), with_angles adding the gates' angles."""
         gates = (ctypes.c_uint16 * self.L)()
+        angles = (ctypes.c_uint32 * self.L)()
         f32 = ctypes.c_float(0)
         f64 = ctypes.c_double(0)
-        _call("qe_get_best", self.handle, instance, gates, ctypes.byref(f32),
+        _call("qe_get_best", self.handle, instance, gates, angles, ctypes.byref(f32),
               ctypes.byref(f64) if with_fp64 else None)
-        return [int(x) for x in gates], f32.value, (f64.value if with_fp64 else None)
+        out = ([int(x) for x in gates], f32.value, (f64.value if with_fp64 else None))
+        return out + ([int(x) for x in angles],) if with_angles else out
 
     def checkpoint(self):
         size = ctypes.c_size_t(0)

@@ -47,7 +47,8 @@ def _problem(**kw):
     (dict(n_qubits=0), qe.QE_ERR_INVALID),
     (dict(n_qubits=7), qe.QE_ERR_INVALID),
     (dict(n_qubits=1), qe.QE_ERR_INVALID),                  # QEQEA needs a wire pair
-    (dict(library=1), qe.QE_ERR_UNSUPPORTED),               # QEQEA decodes to library 0
+    (dict(library=1), qe.QE_ERR_UNSUPPORTED),               # QEQEA decodes to library 0 or 2
+    (dict(library=2, algorithm=1), qe.QE_ERR_UNSUPPORTED),  # the GA genome holds no angles
     (dict(library=5), qe.QE_ERR_INVALID),
     (dict(algorithm=3), qe.QE_ERR_INVALID),
     (dict(size_of_individual=0), qe.QE_ERR_INVALID),
