@@ -54,8 +54,10 @@ def algorithmic_flops(gates, n):
     """Real floating-point operations the method needs for these circuits
     (N = 2^n): a CV or CV+ gate updates the N^2/2 controlled entries of
     U T^dagger at 6 flops each, H all N^2 entries at 4, T N^2/2 at 4; NOT,
-    CNOT and I only permute rows (0); the fitness reduction reads every entry
-    once (|m|^2 accumulated: 4 flops)."""
+    CNOT and I only permute rows (0); an Ising gate (R_x, R_y, R_z, J)
+    updates all N^2 entries at 6 (two real outputs of two products and a
+    sum); the fitness reduction reads every entry once (|m|^2 accumulated:
+    4 flops)."""
     import numpy as np
     NN = float(1 << (2 * n))
     kinds = np.asarray(gates).astype(np.int64) & 15
@@ -63,21 +65,24 @@ def algorithmic_flops(gates, n):
     per_kind[3] = per_kind[4] = 3.0 * NN
     per_kind[5] = 4.0 * NN
     per_kind[6] = 2.0 * NN
+    per_kind[7:11] = 6.0 * NN
     return float(per_kind[kinds].sum() + kinds.shape[0] * 4.0 * NN)
 
 
 def algorithmic_lds_bytes(gates, n):
     """LDS bytes the per-gate method must move for these circuits (N = 2^n):
     every complex64 entry a gate changes is read and written once (16 B);
-    CV, CV+ and T change N^2/2 entries, H all N^2, NOT / CNOT / I none (a
-    row relabelling); plus one pass writing T^dagger and one reading the
-    result for the fitness (8 B per entry each)."""
+    CV, CV+ and T change N^2/2 entries, H and the Ising gates (R_x, R_y, R_z,
+    J) all N^2, NOT / CNOT / I none (a row relabelling); plus one pass
+    writing T^dagger and one reading the result for the fitness (8 B per
+    entry each)."""
     import numpy as np
     NN = float(1 << (2 * n))
     kinds = np.asarray(gates).astype(np.int64) & 15
     per_kind = np.zeros(16)
     per_kind[3] = per_kind[4] = per_kind[6] = 8.0 * NN
     per_kind[5] = 16.0 * NN
+    per_kind[7:11] = 16.0 * NN
     circuits = kinds.shape[0] if kinds.ndim > 1 else 1
     return float(per_kind[kinds].sum() + circuits * 16.0 * NN)
 
@@ -198,6 +203,55 @@ def secondary_phase_insensitive(dev, gens=100):
             "best_f_fp32": best[1], "best_f_fp64": best[2]}
 
 
+def secondary_qeqea_ising(dev, gens=100, reps=50):
+    """The bench shape (n=4, P=4096, L=30) with the Ising library of Sec. III
+    (rotations about the measured axis and interactions, continuous angles):
+    a graph of `gens` whole generations, and the fused sampling + fitness
+    kernel timed over `reps` back-to-back launches with its LDS roofline."""
+    import numpy as np
+    import torch
+    from paper_1809_11134_amd import inputs, qe
+    w = inputs.workload_qeqea_ising_n4()
+    n, L, P, I = w["n"], w["L"], w["P"], w["instances"]
+    tg = torch.from_numpy(np.stack(w["target_gates"]).astype(np.int16)).to(dev)
+    T = qe.build_unitary(tg, n, tg.shape[1], precision=1)
+    ctx = qe.Context(n, w["lib"], qe.ALG_QEQEA, L, P, I, prob_mutation=0.1,
+                     mutation_range=math.pi / 4, seed=w["seed"])
+    ctx.set_targets(T)
+    hist = torch.empty((gens, I * P), dtype=torch.float32, device=dev)
+    ctx.graph_prepare(gens, hist)
+    ctx.run_graph(0, gens, hist)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    ctx.run_graph(gens, gens, hist)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    slots, gates, angles, fk = ctx.sample_eval(2 * gens)
+    torch.cuda.synchronize()
+    e0.record()
+    for r in range(reps):
+        ctx.sample_eval(2 * gens + 1 + r, slots, gates, fk, angles=angles)
+    e1.record()
+    torch.cuda.synchronize()
+    kern_ms = e0.elapsed_time(e1) / reps
+    gh = gates.cpu().numpy()
+    lds = algorithmic_lds_bytes(gh, n)
+    flops = algorithmic_flops(gh, n)
+    achieved = lds / (kern_ms / 1e3) / 1e9
+    best = ctx.get_best(0)
+    ctx.close()
+    return {"workload": w["name"], "generations": gens,
+            "evals_per_s": gens * I * P / (ms * 1e-3), "ms_per_generation": ms / gens,
+            "kernel": "population_kernel<4,1,true,true> (sampling + Ising decode + Eq. 11 fitness "
+                      "+ segment max, LDS-staged)",
+            "kernel_us": kern_ms * 1e3, "algorithmic_lds_bytes_per_launch": lds,
+            "lds_gbps": achieved, "lds_frac": achieved / LDS_PEAK_GBPS,
+            "alu_tflops": flops / (kern_ms / 1e3) / 1e12,
+            "best_f_fp32": best[1], "best_f_fp64": best[2]}
+
+
 def secondary_qeqea_n5(dev, gens=20):
     """n=5, library {I,NOT,CNOT,CV,CV+}, 1024 QEQEA populations x 64 circuits x
     40 gates (65536 evaluations per generation): a graph of `gens` whole
@@ -267,10 +321,10 @@ def main():
                     help="after the run, copy a buffer of this many MiB (a plain copy kernel "
                          "of known traffic that scales the FETCH_SIZE / WRITE_SIZE counters)")
     ap.add_argument("--no-secondary", action="store_true",
-                    help="skip the n=6 precision study, the n=5 QEQEA loop and the uneven batch")
-    ap.add_argument("--secondary", default="precision,qeqea_n5,uneven,phase_insensitive",
+                    help="skip the secondary workloads")
+    ap.add_argument("--secondary", default="precision,qeqea_n5,uneven,phase_insensitive,ising",
                     help="comma list of the secondary workloads to run (precision, qeqea_n5, "
-                         "uneven, phase_insensitive)")
+                         "uneven, phase_insensitive, ising)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the hot path runs on a single MI355X (independent "
@@ -368,7 +422,7 @@ def main():
 
     secondary = None
     which = set() if args.no_secondary else {s.strip() for s in args.secondary.split(",") if s.strip()}
-    unknown = which - {"precision", "qeqea_n5", "uneven", "phase_insensitive"}
+    unknown = which - {"precision", "qeqea_n5", "uneven", "phase_insensitive", "ising"}
     if unknown:
         ap.error(f"unknown secondary workloads: {sorted(unknown)}")
     if which:
@@ -385,6 +439,9 @@ def main():
         if "phase_insensitive" in which:
             log("secondary: bench workload with the phase-insensitive fitness")
             secondary["phase_insensitive"] = secondary_phase_insensitive(dev)
+        if "ising" in which:
+            log("secondary: bench shape with the Ising library")
+            secondary["qeqea_ising_n4"] = secondary_qeqea_ising(dev)
         assert qe.device_errors() == 0, "device error flags raised"
 
     cpu = None

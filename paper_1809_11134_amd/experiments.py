@@ -14,6 +14,13 @@ Every generation runs on the GPU through libqe (HIP graphs of whole
 generations); this module only builds the targets and records the results.
 
     python -m paper_1809_11134_amd.experiments --targets cnot,toffoli,peres
+
+With --library ising the QEQEA searches the Ising gate model of Sec. III
+(rotations about x, y, z and the interaction J, continuous angles), the
+model of the paper's own runs; Table I's configuration is
+
+    python -m paper_1809_11134_amd.experiments --targets cnot --algorithms qeqea \
+        --library ising --L 3 --P 1
 """
 import argparse
 import json
@@ -81,13 +88,14 @@ def target_unitary(name):
 
 def run(name, algorithm, L, P, generations, chunk=50, fitness_mode=qe.FIT_PHASE_INSENSITIVE,
         seed=1809111340, pm=0.1, mutation_range=math.pi / 4, thresholds=(0.9, 0.99, 1.0),
-        dev=None):
+        dev=None, library=qe.LIB_NCV):
     """One search; returns a dict with the best fitness after every chunk of
     generations and the first generation (upper bound, in chunks) at which
-    the best fitness reached each threshold."""
+    the best fitness reached each threshold.  library: qe.LIB_NCV or (QEQEA
+    only) qe.LIB_ISING, the gate model of the paper's own runs."""
     dev = dev or torch.device("cuda", torch.cuda.current_device())
     n, T = target_unitary(name)
-    ctx = qe.Context(n, qe.LIB_NCV, algorithm, L, P, 1, prob_mutation=pm,
+    ctx = qe.Context(n, library, algorithm, L, P, 1, prob_mutation=pm,
                      mutation_range=mutation_range, seed=seed, fitness_mode=fitness_mode)
     ctx.set_targets(torch.from_numpy(T[None]).to(dev))
     curve, reached = [], {}
@@ -105,12 +113,19 @@ def run(name, algorithm, L, P, generations, chunk=50, fitness_mode=qe.FIT_PHASE_
         if f32 >= 1.0 - 1e-6:
             break
     seconds = time.perf_counter() - t0
-    gates, f32, f64 = ctx.get_best(0)
+    gates, f32, f64, angles = ctx.get_best(0, with_angles=True)
     ctx.close()
+    if library == qe.LIB_ISING:
+        # (kind, wire, second wire, theta in radians) per gate
+        best = [(g & 15, (g >> 4) & 15, (g >> 8) & 15, round(a * 2 * math.pi / 2 ** 32, 6))
+                for g, a in zip(gates, angles)]
+    else:
+        best = [g for g in gates if g & 15]
     return {"target": name, "n": n, "algorithm": "QEQEA" if algorithm == qe.ALG_QEQEA else "GA",
+            "library": "ising" if library == qe.LIB_ISING else "ncv",
             "fitness": "phase_insensitive" if fitness_mode == qe.FIT_PHASE_INSENSITIVE else "eq11",
             "L": L, "P": P, "generations": gen, "seconds": seconds, "best_f_fp32": f32,
-            "best_f_fp64": f64, "best_circuit": [g for g in gates if g & 15],
+            "best_f_fp64": f64, "best_circuit": best,
             "first_generation_reaching": {str(k): v for k, v in sorted(reached.items())},
             "curve": curve}
 
@@ -123,6 +138,9 @@ def main(argv=None):
     ap.add_argument("--P", type=int, default=256)
     ap.add_argument("--L", type=int, default=0, help="circuit length (0: 4 + 4 n)")
     ap.add_argument("--fitness", choices=("phase_insensitive", "eq11"), default="phase_insensitive")
+    ap.add_argument("--library", choices=("ncv", "ising"), default="ncv",
+                    help="gate library of the QEQEA (the GA runs on ncv only)")
+    ap.add_argument("--chunk", type=int, default=50, help="generations between best-fitness reads")
     ap.add_argument("--seed", type=int, default=1809111340)
     args = ap.parse_args(argv)
     if not torch.cuda.is_available():
@@ -133,9 +151,13 @@ def main(argv=None):
     for name in [t for t in args.targets.split(",") if t]:
         n = TARGETS[name][0]
         L = args.L or 4 + 4 * n
+        lib = qe.LIB_ISING if args.library == "ising" else qe.LIB_NCV
         for alg in [a for a in args.algorithms.split(",") if a]:
+            if alg == "ga" and lib == qe.LIB_ISING:
+                continue
             r = run(name, qe.ALG_QEQEA if alg == "qeqea" else qe.ALG_GA, L, args.P,
-                    args.generations, fitness_mode=mode, seed=args.seed)
+                    args.generations, chunk=args.chunk, fitness_mode=mode, seed=args.seed,
+                    library=lib)
             print(json.dumps(r), flush=True)
     return 0
 
