@@ -252,6 +252,59 @@ def secondary_qeqea_ising(dev, gens=100, reps=50):
             "best_f_fp32": best[1], "best_f_fp64": best[2]}
 
 
+def dense_flops(gates, n):
+    """FP32 work of the dense segment-matrix scheme (Sec. IV-C, steps 3-5) for
+    these circuits: each non-identity gate is one N x N by N x N complex
+    product, 8 N^3 real operations (4 multiply-add pairs per complex
+    multiply-add); the Kronecker expansion and the fitness reduction are
+    lower order and not counted."""
+    import numpy as np
+    kinds = np.asarray(gates).astype(np.int64) & 15
+    return float(np.count_nonzero(kinds) * 8.0 * float(1 << (3 * n)))
+
+
+def secondary_dense(dev, reps=5):
+    """Ablation: the paper's dense segment matrices against the per-gate row
+    updates on the same circuits -- the bench shape (4096 circuits of 30
+    gates, n=4, library {I,NOT,CNOT,CV,CV+}) and 1024 circuits of the n=6
+    precision workload (48 gates, library {H,T,CNOT,CV,CV+})."""
+    import ctypes
+
+    import numpy as np
+    import torch
+    from paper_1809_11134_amd import inputs, qe
+    out = {}
+    rng = np.random.default_rng(inputs.SEED_BASE + 7)
+    pw = inputs.workload_precision_n6()
+    for name, n, gates, tgates in (
+            ("n4_p4096_l30", 4, inputs.random_circuits(rng, 4096, 4, 30, inputs.LIB_NCV),
+             inputs.random_target_gates(rng, 4, 12, permutation=True)),
+            ("n6_p1024_l48", 6, pw["gates"][:1024], pw["target_gates"])):
+        L = gates.shape[1]
+        gd = torch.from_numpy(np.ascontiguousarray(gates).view(np.int16)).to(dev)
+        T = qe.build_unitary(torch.from_numpy(np.asarray(tgates, np.uint16).view(np.int16)[None]).to(dev),
+                             n, len(tgates), precision=0)[0]
+        batch, keep, B = qe.make_batch(gd, T, n=n, L=L, target_stride=0)
+        res = {}
+        for path, key in ((qe.PATH_FP32, "per_gate"), (qe.PATH_DENSE, "dense")):
+            f = torch.empty(B, dtype=torch.float32, device=dev)
+            launch = lambda: qe._call("qe_eval_fitness", None, ctypes.byref(batch), path, qe._ptr(f),
+                                      None, None, qe._stream(None))
+            us = _events_us(launch, reps)
+            res[key] = {"us_per_launch": us, "evals_per_s": B / (us * 1e-6), "f": f}
+        fl = dense_flops(gates, n)
+        d_us = res["dense"]["us_per_launch"]
+        out[name] = {"per_gate_us": res["per_gate"]["us_per_launch"], "dense_us": d_us,
+                     "per_gate_evals_per_s": res["per_gate"]["evals_per_s"],
+                     "dense_evals_per_s": res["dense"]["evals_per_s"],
+                     "per_gate_speedup": d_us / res["per_gate"]["us_per_launch"],
+                     "dense_flops_per_launch": fl, "dense_tflops": fl / (d_us * 1e-6) / 1e12,
+                     "dense_alu_frac": fl / (d_us * 1e-6) / 1e12 / FP32_VECTOR_PEAK_TFLOPS,
+                     "max_abs_df_dense_vs_per_gate":
+                         float((res["dense"]["f"] - res["per_gate"]["f"]).abs().max())}
+    return out
+
+
 def secondary_qeqea_n5(dev, gens=20):
     """n=5, library {I,NOT,CNOT,CV,CV+}, 1024 QEQEA populations x 64 circuits x
     40 gates (65536 evaluations per generation): a graph of `gens` whole
@@ -322,9 +375,9 @@ def main():
                          "of known traffic that scales the FETCH_SIZE / WRITE_SIZE counters)")
     ap.add_argument("--no-secondary", action="store_true",
                     help="skip the secondary workloads")
-    ap.add_argument("--secondary", default="precision,qeqea_n5,uneven,phase_insensitive,ising",
+    ap.add_argument("--secondary", default="precision,qeqea_n5,uneven,phase_insensitive,ising,dense",
                     help="comma list of the secondary workloads to run (precision, qeqea_n5, "
-                         "uneven, phase_insensitive, ising)")
+                         "uneven, phase_insensitive, ising, dense)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the hot path runs on a single MI355X (independent "
@@ -422,7 +475,7 @@ def main():
 
     secondary = None
     which = set() if args.no_secondary else {s.strip() for s in args.secondary.split(",") if s.strip()}
-    unknown = which - {"precision", "qeqea_n5", "uneven", "phase_insensitive", "ising"}
+    unknown = which - {"precision", "qeqea_n5", "uneven", "phase_insensitive", "ising", "dense"}
     if unknown:
         ap.error(f"unknown secondary workloads: {sorted(unknown)}")
     if which:
@@ -442,6 +495,9 @@ def main():
         if "ising" in which:
             log("secondary: bench shape with the Ising library")
             secondary["qeqea_ising_n4"] = secondary_qeqea_ising(dev)
+        if "dense" in which:
+            log("secondary: dense segment-matrix ablation")
+            secondary["dense_ablation"] = secondary_dense(dev)
         assert qe.device_errors() == 0, "device error flags raised"
 
     cpu = None

@@ -77,7 +77,10 @@ enum { QE_PATH_FP32 = 0,        /* per-gate row updates, FP32, tuned schedule pe
                                    accumulation, columns renormalised after each block */
        QE_PATH_MFMA_FP16 = 4,   /* same with fp16 hi+lo (lo scaled by 2^11) */
        QE_PATH_MFMA_BF16_RAW = 5,  /* bf16 hi+lo without renormalisation */
-       QE_PATH_MFMA_FP16_RAW = 6 }; /* fp16 hi+lo without renormalisation */
+       QE_PATH_MFMA_FP16_RAW = 6,  /* fp16 hi+lo without renormalisation */
+       QE_PATH_DENSE = 7 };        /* ablation: the paper's segment matrices (Sec. IV-C,
+                                      steps 3-5), every gate expanded by Kronecker products
+                                      to 2^n x 2^n and multiplied densely, FP32, any widths */
 
 /* Device error flags (bitmask) raised by kernels. */
 enum { QE_DEVERR_DESC = 1,      /* invalid gate descriptor */
@@ -104,9 +107,9 @@ enum { QE_DEVERR_DESC = 1,      /* invalid gate descriptor */
  *   fitness_mode   QE_FIT_EQ11 (0) or QE_FIT_PHASE_INSENSITIVE (1).
  *   angles_dev     NULL (discrete gates only), or one uint32 angle per entry
  *                  of gates_dev (same indexing), read for the Ising kinds.
- *                  Angled batches run on QE_PATH_FP32 / QE_PATH_FP32_LDS
- *                  and the FP64 calls; the register and MFMA paths return
- *                  QE_ERR_UNSUPPORTED for them.
+ *                  Angled batches run on QE_PATH_FP32 / QE_PATH_FP32_LDS /
+ *                  QE_PATH_DENSE and the FP64 calls; the register and MFMA
+ *                  paths return QE_ERR_UNSUPPORTED for them.
  *
  * Fitness modes.  QE_FIT_EQ11: Eq. 11 as printed, f = 1 - sqrt((2^n -
  * |tr(T^dagger U)|) / 2^n), computed through the exact identity 2^n - |tr| =
@@ -140,8 +143,9 @@ typedef struct {
  * Sec. IV-E (the hot path; batch->fitness_mode selects the phase-insensitive
  * mode).  path: QE_PATH_*.  f_dev [B] required; g_dev,
  * delta_dev [B] optional (NULL).  The 2^n x 2^n product U T^dagger is built
- * gate by gate from T^dagger (FP32 paths) or block by block (MFMA paths:
- * uniform width 5 or 6 only, QE_ERR_UNSUPPORTED otherwise).  Circuits whose
+ * gate by gate from T^dagger (FP32 paths), block by block (MFMA paths:
+ * uniform width 5 or 6 only, QE_ERR_UNSUPPORTED otherwise) or segment matrix
+ * by segment matrix (QE_PATH_DENSE, the paper's scheme, N^3 work per gate).  Circuits whose
  * width, gates or target are malformed get f = NaN (see qe_device_errors).
  * ctx may be NULL. */
 typedef struct qe_ctx qe_ctx;

@@ -308,10 +308,15 @@ qe_status qe_eval_fitness(qe_ctx* ctx, const qe_batch* batch, int32_t path, floa
     (void)ctx;
     BatchArgs a;
     QE_TRY(to_args(batch, &a, true));
-    if (path < QE_PATH_FP32 || path > QE_PATH_MFMA_FP16_RAW) return fail(QE_ERR_INVALID, "unknown path");
+    if (path < QE_PATH_FP32 || path > QE_PATH_DENSE) return fail(QE_ERR_INVALID, "unknown path");
     if (a.B > 0 && !f_dev) return fail(QE_ERR_INVALID, "f_dev is NULL");
-    if (a.angles && path != QE_PATH_FP32 && path != QE_PATH_FP32_LDS)
-        return fail(QE_ERR_UNSUPPORTED, "angled (Ising) batches run on QE_PATH_FP32 / QE_PATH_FP32_LDS");
+    if (a.angles && path != QE_PATH_FP32 && path != QE_PATH_FP32_LDS && path != QE_PATH_DENSE)
+        return fail(QE_ERR_UNSUPPORTED,
+                    "angled (Ising) batches run on QE_PATH_FP32 / QE_PATH_FP32_LDS / QE_PATH_DENSE");
+    if (path == QE_PATH_DENSE) {
+        QE_HIP(launch_eval_dense(a, f_dev, g_dev, delta_dev, (hipStream_t)stream));
+        return QE_OK;
+    }
     if (path >= QE_PATH_MFMA_BF16) {
         if (a.uniform_n != 5 && a.uniform_n != 6)
             return fail(QE_ERR_UNSUPPORTED, "MFMA paths need a uniform width of 5 or 6");

@@ -896,6 +896,56 @@ __device__ __forceinline__ Real block_sum(Real v, Real* scratch) {
     return t;
 }
 
+// Eq. 11 (or the phase-insensitive fitness) of the N x N matrix M held in
+// LDS as separate real / imaginary arrays, reduced over the workgroup.  ok
+// false: the circuit was malformed (err says why) and NaN is written.
+// red: 8 values of LDS scratch.  Every thread of the workgroup must call it.
+template <typename Real>
+__device__ __forceinline__ void lds_fitness(const Real* Mr, const Real* Mi, int N, bool ok, uint32_t err,
+                                            Real* f, Real* g, Real* delta, uint32_t* errw, int mode,
+                                            Real* red) {
+    const int tid = threadIdx.x, nt = blockDim.x, NN = N * N;
+    const Real nan = (Real)__builtin_nan("");
+    Real off = 0, tr = 0, ti = 0;
+    if (ok) {
+        for (int e = tid; e < NN; e += nt) {
+            const int i = e / N, j = e % N;
+            if (i == j) { tr += Mr[e]; ti += Mi[e]; }
+            else off += Mr[e] * Mr[e] + Mi[e] * Mi[e];
+        }
+    }
+    tr = block_sum(tr, red);
+    ti = block_sum(ti, red);
+    off = block_sum(off, red);
+    const Real am = sqrt(tr * tr + ti * ti);
+    Real er = 1, ei = 0;
+    if (am > 0) { er = tr / am; ei = ti / am; }
+    Real D = 0;
+    if (ok)
+        for (int i = tid; i < N; i += nt) {
+            const Real xr = Mr[i * N + i] - er, xi = Mi[i * N + i] - ei;
+            D += xr * xr + xi * xi;
+        }
+    D = block_sum(D, red);
+    if (tid == 0) {
+        Real fv, gv, dl;
+        if (mode == QE_FIT_PHASE_INSENSITIVE) {
+            fitness_pi(off, N, &fv, &gv, &dl);
+        } else {
+            dl = (Real)0.5 * (off + D);
+            Real q = dl / (Real)N;
+            q = q < 0 ? (Real)0 : (q > 1 ? (Real)1 : q);
+            fv = (Real)1 - sqrt(q);
+            gv = am / (Real)N;
+        }
+        if (ok && !(fv == fv)) err = QE_DEVERR_NUMERIC;
+        if (f) *f = ok ? fv : nan;
+        if (g) *g = ok ? gv : nan;
+        if (delta) *delta = ok ? dl : nan;
+        if (err) atomicOr(errw, err);
+    }
+}
+
 // angles: the gates' angles (u32 turn fractions, parallel to gates) or
 // NULL, in which case the Ising kinds are invalid descriptors.
 template <typename Real, bool IDENT>
@@ -977,44 +1027,7 @@ __device__ __forceinline__ void lds_generic_body(int n, int L, const uint16_t* g
         if (tid == 0 && err) atomicOr(errw, err);
         return;
     }
-    Real off = 0, tr = 0, ti = 0;
-    if (ok) {
-        for (int e = tid; e < NN; e += nt) {
-            const int i = e / N, j = e % N;
-            if (i == j) { tr += Mr[e]; ti += Mi[e]; }
-            else off += Mr[e] * Mr[e] + Mi[e] * Mi[e];
-        }
-    }
-    tr = block_sum(tr, red);
-    ti = block_sum(ti, red);
-    off = block_sum(off, red);
-    const Real am = sqrt(tr * tr + ti * ti);
-    Real er = 1, ei = 0;
-    if (am > 0) { er = tr / am; ei = ti / am; }
-    Real D = 0;
-    if (ok)
-        for (int i = tid; i < N; i += nt) {
-            const Real xr = Mr[i * N + i] - er, xi = Mi[i * N + i] - ei;
-            D += xr * xr + xi * xi;
-        }
-    D = block_sum(D, red);
-    if (tid == 0) {
-        Real fv, gv, dl;
-        if (mode == QE_FIT_PHASE_INSENSITIVE) {
-            fitness_pi(off, N, &fv, &gv, &dl);
-        } else {
-            dl = (Real)0.5 * (off + D);
-            Real q = dl / (Real)N;
-            q = q < 0 ? (Real)0 : (q > 1 ? (Real)1 : q);
-            fv = (Real)1 - sqrt(q);
-            gv = am / (Real)N;
-        }
-        if (ok && !(fv == fv)) err = QE_DEVERR_NUMERIC;
-        if (f) *f = ok ? fv : nan;
-        if (g) *g = ok ? gv : nan;
-        if (delta) *delta = ok ? dl : nan;
-        if (err) atomicOr(errw, err);
-    }
+    lds_fitness<Real>(Mr, Mi, N, ok, err, f, g, delta, errw, mode, red);
 }
 
 // Eq. 11 from the per-wave partial sums of the LDS-staged path, for the W

@@ -35,6 +35,10 @@ hipError_t launch_eval_lds(const BatchArgs& a, bool fp64, void* f, void* g, void
                            hipStream_t s);
 hipError_t launch_unitary(const BatchArgs& a, bool fp64, void* out, hipStream_t s);
 
+// dense.hip: every gate expanded to its full segment matrix and multiplied
+// (the paper's steps 3-5; an ablation baseline, any widths, angles allowed)
+hipError_t launch_eval_dense(const BatchArgs& a, float* f, float* g, float* delta, hipStream_t s);
+
 // mfma.hip: fused 4-wire gate blocks on MFMA (uniform width 5 or 6)
 hipError_t launch_eval_mfma(const BatchArgs& a, bool fp16, bool renorm, float* f, float* g,
                             float* delta, hipStream_t s);

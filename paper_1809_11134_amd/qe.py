@@ -18,7 +18,7 @@ KIND_RX, KIND_RY, KIND_RZ, KIND_ZZ = 7, 8, 9, 10     # Ising kinds; angles are u
 ALG_QEQEA, ALG_GA = 0, 1
 FIT_EQ11, FIT_PHASE_INSENSITIVE = 0, 1
 (PATH_FP32, PATH_FP32_REG, PATH_FP32_LDS, PATH_MFMA_BF16, PATH_MFMA_FP16, PATH_MFMA_BF16_RAW,
- PATH_MFMA_FP16_RAW) = range(7)
+ PATH_MFMA_FP16_RAW, PATH_DENSE) = range(8)
 DEVERR_DESC, DEVERR_WIDTH, DEVERR_RANGE, DEVERR_NUMERIC = 1, 2, 4, 8
 
 

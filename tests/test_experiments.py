@@ -36,3 +36,19 @@ def test_short_run_solves_cnot():
     assert r["best_f_fp64"] == pytest.approx(1.0, abs=1e-12)
     assert r["first_generation_reaching"]["1.0"] <= 400
     assert r["curve"] and all(0 <= f <= 1 for _, f in r["curve"])
+
+
+@pytest.mark.gpu
+def test_short_ising_run_reports_angled_best_circuit():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    qe.load()
+    r = experiments.run("cnot", qe.ALG_QEQEA, L=3, P=16, generations=200, chunk=50,
+                        library=qe.LIB_ISING)
+    assert r["library"] == "ising" and len(r["best_circuit"]) == 3
+    for kind, a, b, theta in r["best_circuit"]:
+        assert kind in (7, 8, 9, 10) and 0 <= theta < 2 * np.pi + 1e-6
+    assert abs(r["best_f_fp32"] - r["best_f_fp64"]) <= 1e-5
+    fs = [f for _, f in r["curve"]]
+    assert fs == sorted(fs)                          # the best so far never decreases
+
