@@ -577,8 +577,15 @@ static qe_status graph_for(qe_ctx* c, int32_t n_gen, float* f_hist, hipGraphExec
     if (e != hipSuccess) return fail(QE_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
     hipGraphExec_t ex = nullptr;
     e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);
     if (e != hipSuccess) return fail(QE_ERR_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+    // upload now, so that the first replay does not pay for it
+    e = hipGraphUpload(ex, c->capture_stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->capture_stream);
+    if (e != hipSuccess) {
+        (void)hipGraphExecDestroy(ex);
+        return fail(QE_ERR_DEVICE, std::string("graph upload: ") + hipGetErrorString(e));
+    }
     c->graphs.emplace(key, ex);
     *out = ex;
     return QE_OK;

@@ -545,6 +545,17 @@ __device__ __forceinline__ bool run_small_path(const float* __restrict__ T, int 
 // m*RG and rg, so a gate is described by the inserted offsets of the pair-
 // index bits (rg's two bits per lane, m's bits per pass), computed for all the
 // gates of a chunk at once, one gate per lane.
+//
+// Row relabelling: NOT and CNOT only permute rows, and the permutations they
+// generate are affine maps over GF(2) of the row index.  Instead of moving
+// rows, the path keeps the map phi from logical to stored rows (phi(r) =
+// A r + b, A held as its columns, 6 bits each, in a 64-bit word): NOT on row
+// bit p adds column p of A to b, CNOT with control bit pc and target bit pt
+// adds column pt to column pc.  Every other gate addresses its logical rows
+// through phi, which is linear in the pair-index bits, so its offsets are
+// the images of the logical ones and combine by XOR.  The fitness reads the
+// diagonal entry of column j at stored row phi(j).  (Unitary outputs keep
+// the rows in place: IDENT moves them.)
 __device__ __forceinline__ int ins0(int x, int pos) {
     return ((x >> pos) << (pos + 1)) | (x & ((1 << pos) - 1));
 }
@@ -604,6 +615,13 @@ __device__ __forceinline__ bool run_lds_path(float2* M, uint4* gt, const float* 
         return *reinterpret_cast<float2*>(reinterpret_cast<char*>(M) + byte_off);
     };
     constexpr uint32_t ROWB = NQ + 3;      // log2 of a row's byte stride (N * 8)
+    constexpr bool RELABEL = !IDENT;
+    // the logical-to-stored row map (wave-uniform): column p of A in bits
+    // 6p..6p+5, translation b
+    uint64_t Amap = 0;
+#pragma unroll
+    for (int p = 0; p < NQ; ++p) Amap |= (uint64_t)(1u << p) << (6 * p);
+    uint32_t bmap = 0;
     // pass offsets in use: R2 from 2 passes, R3 from 4, R4 from 8 (an
     // uncontrolled gate has (N / 2) / RG passes)
     constexpr bool NIT_USES_R2 = (N / 2) / RG > 1, NIT_USES_R3 = (N / 2) / RG > 2,
@@ -631,16 +649,42 @@ __device__ __forceinline__ bool run_lds_path(float2* M, uint4* gt, const float* 
         const int cpos = NQ - 1 - (int)((dv >> 8) & 15u);
         const bool ctl = kind_two_wire(kind);
         const int lo = ctl ? min(tpos, cpos) : tpos, hi = ctl ? max(tpos, cpos) : tpos;
+        const bool perm = RELABEL && (kind == KIND_NOT || kind == KIND_CNOT);
+        // fold this chunk's NOT / CNOT into the row map, in circuit order; each
+        // lane keeps the map in force at its own gate
+        uint64_t myA = Amap;
+        uint32_t myB = bmap;
+        if constexpr (RELABEL) {
+            uint64_t pm = __ballot(lane < cnt && perm);
+            while (pm) {
+                const int g = (int)__builtin_ctzll(pm);
+                pm &= pm - 1;
+                const uint32_t d = (uint32_t)__builtin_amdgcn_readlane((int)dv, g);
+                const int pt = NQ - 1 - (int)((d >> 4) & 15u);
+                const uint32_t colt = (uint32_t)(Amap >> (6 * pt)) & 63u;
+                if ((d & 15u) == (uint32_t)KIND_NOT) {
+                    bmap ^= colt;
+                } else {
+                    const int pc = NQ - 1 - (int)((d >> 8) & 15u);
+                    Amap ^= (uint64_t)colt << (6 * pc);
+                }
+                if (lane > g) { myA = Amap; myB = bmap; }
+            }
+        }
+        // stored byte offset of logical row bit q under the lane's map
+        auto colb = [&](int q) -> uint32_t { return ((uint32_t)(myA >> (6 * q)) & 63u) << ROWB; };
+        // insertion of the gate's zero bits, then the image of the single
+        // logical row bit that pair-index bit x lands on
         auto ins = [&](int x) -> uint32_t {
             int y = ins0(x, lo);
             if (ctl) y = ins0(y, hi);
-            return (uint32_t)y << ROWB;
+            return colb(__builtin_ctz((uint32_t)y));
         };
-        const bool live = lane < cnt && kind != KIND_I;
+        const bool live = lane < cnt && kind != KIND_I && !perm;
         const uint64_t live_mask = __ballot(live);
-        const uint4 G0 = make_uint4(ins(1), ins(2), ctl ? (1u << (cpos + (int)ROWB)) : 0u,
-                                    1u << (tpos + (int)ROWB));
-        const uint4 G1 = make_uint4((uint32_t)kind, ins(4), ins(8), ins(16));
+        const uint4 G0 = make_uint4(ins(1), ins(2), ctl ? colb(cpos) : 0u, colb(tpos));
+        const uint4 G1 = make_uint4((uint32_t)kind | ((myB << ROWB) << 16), NIT_USES_R2 ? ins(4) : 0u,
+                                    NIT_USES_R3 ? ins(8) : 0u, NIT_USES_R4 ? ins(16) : 0u);
         uint4 G2 = make_uint4(f_bits(1.0f), 0u, 0u, 0u);
         if constexpr (ANG) {
             if (live && kind_ising(kind)) {
@@ -653,8 +697,10 @@ __device__ __forceinline__ bool run_lds_path(float2* M, uint4* gt, const float* 
         // of the following entry once the addresses are known and before the
         // data reads, so the entry is ready when its gate starts
         auto apply = [&](const uint4 E0, const uint4 E1, const uint4 E2, auto&& next) {
-            const int k = __builtin_amdgcn_readfirstlane((int)E1.x);
-            const uint32_t rgo = (mb0 & E0.x) | (mb1 & E0.y);   // the row group's pair bits
+            const uint32_t kx = (uint32_t)__builtin_amdgcn_readfirstlane((int)E1.x);
+            const int k = (int)(kx & 15u);
+            // the row group's pair bits and the map's translation
+            const uint32_t rgo = (mb0 & E0.x) ^ (mb1 & E0.y) ^ (kx >> 16);
             const uint32_t tb = E0.w;
             next();
             if constexpr (ANG) {
@@ -667,22 +713,22 @@ __device__ __forceinline__ bool run_lds_path(float2* M, uint4* gt, const float* 
                         uint32_t offm[NIT];
                         offm[0] = 0u;
                         if constexpr (NIT > 1) offm[1] = E1.y;
-                        if constexpr (NIT > 2) { offm[2] = E1.z; offm[3] = E1.y | E1.z; }
-                        const uint32_t a0 = rgo + jb, cb = E0.z;
+                        if constexpr (NIT > 2) { offm[2] = E1.z; offm[3] = E1.y ^ E1.z; }
+                        const uint32_t a0 = rgo ^ jb, cb = E0.z;
                         float2 X[NIT][4];
 #pragma unroll
                         for (int m = 0; m < NIT; ++m) {
-                            X[m][0] = at(a0 + offm[m]);
-                            X[m][1] = at(a0 + cb + offm[m]);
-                            X[m][2] = at(a0 + tb + offm[m]);
-                            X[m][3] = at(a0 + cb + tb + offm[m]);
+                            X[m][0] = at(a0 ^ offm[m]);
+                            X[m][1] = at(a0 ^ cb ^ offm[m]);
+                            X[m][2] = at(a0 ^ tb ^ offm[m]);
+                            X[m][3] = at(a0 ^ cb ^ tb ^ offm[m]);
                         }
 #pragma unroll
                         for (int m = 0; m < NIT; ++m) {
-                            at(a0 + offm[m]) = phase_minus(X[m][0], c, s);
-                            at(a0 + cb + offm[m]) = phase_plus(X[m][1], c, s);
-                            at(a0 + tb + offm[m]) = phase_plus(X[m][2], c, s);
-                            at(a0 + cb + tb + offm[m]) = phase_minus(X[m][3], c, s);
+                            at(a0 ^ offm[m]) = phase_minus(X[m][0], c, s);
+                            at(a0 ^ cb ^ offm[m]) = phase_plus(X[m][1], c, s);
+                            at(a0 ^ tb ^ offm[m]) = phase_plus(X[m][2], c, s);
+                            at(a0 ^ cb ^ tb ^ offm[m]) = phase_minus(X[m][3], c, s);
                         }
                         return;
                     }
@@ -690,34 +736,34 @@ __device__ __forceinline__ bool run_lds_path(float2* M, uint4* gt, const float* 
                     uint32_t offm[NIT];
                     offm[0] = 0u;
                     if constexpr (NIT > 1) offm[1] = E1.y;
-                    if constexpr (NIT > 2) { offm[2] = E1.z; offm[3] = E1.y | E1.z; }
+                    if constexpr (NIT > 2) { offm[2] = E1.z; offm[3] = E1.y ^ E1.z; }
                     if constexpr (NIT > 4) {
 #pragma unroll
-                        for (int m = 4; m < 8; ++m) offm[m] = offm[m - 4] | E1.w;
+                        for (int m = 4; m < 8; ++m) offm[m] = offm[m - 4] ^ E1.w;
                     }
-                    const uint32_t a0 = rgo + jb, a1 = a0 + tb;
+                    const uint32_t a0 = rgo ^ jb, a1 = a0 ^ tb;
                     float2 A[NIT], B[NIT];
 #pragma unroll
-                    for (int m = 0; m < NIT; ++m) { A[m] = at(a0 + offm[m]); B[m] = at(a1 + offm[m]); }
+                    for (int m = 0; m < NIT; ++m) { A[m] = at(a0 ^ offm[m]); B[m] = at(a1 ^ offm[m]); }
                     if (k == KIND_RZ) {
 #pragma unroll
                         for (int m = 0; m < NIT; ++m) {
-                            at(a0 + offm[m]) = phase_minus(A[m], c, s);
-                            at(a1 + offm[m]) = phase_plus(B[m], c, s);
+                            at(a0 ^ offm[m]) = phase_minus(A[m], c, s);
+                            at(a1 ^ offm[m]) = phase_plus(B[m], c, s);
                         }
                     } else if (k == KIND_RX) {   // a' = c a - i s b, b' = c b - i s a
 #pragma unroll
                         for (int m = 0; m < NIT; ++m) {
                             const float2 a = A[m], b = B[m];
-                            at(a0 + offm[m]) = make_float2(c * a.x + s * b.y, c * a.y - s * b.x);
-                            at(a1 + offm[m]) = make_float2(c * b.x + s * a.y, c * b.y - s * a.x);
+                            at(a0 ^ offm[m]) = make_float2(c * a.x + s * b.y, c * a.y - s * b.x);
+                            at(a1 ^ offm[m]) = make_float2(c * b.x + s * a.y, c * b.y - s * a.x);
                         }
                     } else {                     // R_y: a' = c a - s b, b' = s a + c b
 #pragma unroll
                         for (int m = 0; m < NIT; ++m) {
                             const float2 a = A[m], b = B[m];
-                            at(a0 + offm[m]) = make_float2(c * a.x - s * b.x, c * a.y - s * b.y);
-                            at(a1 + offm[m]) = make_float2(s * a.x + c * b.x, s * a.y + c * b.y);
+                            at(a0 ^ offm[m]) = make_float2(c * a.x - s * b.x, c * a.y - s * b.y);
+                            at(a1 ^ offm[m]) = make_float2(s * a.x + c * b.x, s * a.y + c * b.y);
                         }
                     }
                     return;
@@ -728,14 +774,14 @@ __device__ __forceinline__ bool run_lds_path(float2* M, uint4* gt, const float* 
                 uint32_t offm[NIT];
                 offm[0] = 0u;
                 if constexpr (NIT > 1) offm[1] = E1.y;
-                if constexpr (NIT > 2) { offm[2] = E1.z; offm[3] = E1.y | E1.z; }
-                const uint32_t a0 = rgo + jb + E0.z, a1 = a0 + tb;
+                if constexpr (NIT > 2) { offm[2] = E1.z; offm[3] = E1.y ^ E1.z; }
+                const uint32_t a0 = rgo ^ jb ^ E0.z, a1 = a0 ^ tb;
                 float2 A[NIT], B[NIT];
 #pragma unroll
-                for (int m = 0; m < NIT; ++m) { A[m] = at(a0 + offm[m]); B[m] = at(a1 + offm[m]); }
+                for (int m = 0; m < NIT; ++m) { A[m] = at(a0 ^ offm[m]); B[m] = at(a1 ^ offm[m]); }
                 if (k == KIND_CNOT) {
 #pragma unroll
-                    for (int m = 0; m < NIT; ++m) { at(a0 + offm[m]) = B[m]; at(a1 + offm[m]) = A[m]; }
+                    for (int m = 0; m < NIT; ++m) { at(a0 ^ offm[m]) = B[m]; at(a1 ^ offm[m]) = A[m]; }
                 } else {
                     // CV: (x, y) -> V (x, y); CV+ writes the two results the other
                     // way round (V+ = X V X for the symmetric V)
@@ -744,8 +790,8 @@ __device__ __forceinline__ bool run_lds_path(float2* M, uint4* gt, const float* 
                     for (int m = 0; m < NIT; ++m) {
                         const float2 a = A[m], b = B[m];
                         const float p = a.x + b.x, q = a.y + b.y, u = a.x - b.x, v = a.y - b.y;
-                        at(a0 + sw + offm[m]) = make_float2(0.5f * (p - v), 0.5f * (q + u));
-                        at(a1 - sw + offm[m]) = make_float2(0.5f * (p + v), 0.5f * (q - u));
+                        at(a0 ^ sw ^ offm[m]) = make_float2(0.5f * (p - v), 0.5f * (q + u));
+                        at(a1 ^ sw ^ offm[m]) = make_float2(0.5f * (p + v), 0.5f * (q - u));
                     }
                 }
             } else {
@@ -753,32 +799,32 @@ __device__ __forceinline__ bool run_lds_path(float2* M, uint4* gt, const float* 
                 uint32_t offm[NIT];
                 offm[0] = 0u;
                 if constexpr (NIT > 1) offm[1] = E1.y;
-                if constexpr (NIT > 2) { offm[2] = E1.z; offm[3] = E1.y | E1.z; }
+                if constexpr (NIT > 2) { offm[2] = E1.z; offm[3] = E1.y ^ E1.z; }
                 if constexpr (NIT > 4) {
 #pragma unroll
-                    for (int m = 4; m < 8; ++m) offm[m] = offm[m - 4] | E1.w;
+                    for (int m = 4; m < 8; ++m) offm[m] = offm[m - 4] ^ E1.w;
                 }
-                const uint32_t a0 = rgo + jb, a1 = a0 + tb;
+                const uint32_t a0 = rgo ^ jb, a1 = a0 ^ tb;
                 const float r = 0.70710678118654752f;
                 if (k == KIND_T) {
 #pragma unroll
                     for (int m = 0; m < NIT; ++m) {
-                        const float2 b = at(a1 + offm[m]);
-                        at(a1 + offm[m]) = make_float2((b.x - b.y) * r, (b.x + b.y) * r);
+                        const float2 b = at(a1 ^ offm[m]);
+                        at(a1 ^ offm[m]) = make_float2((b.x - b.y) * r, (b.x + b.y) * r);
                     }
                 } else {
                     float2 A[NIT], B[NIT];
 #pragma unroll
-                    for (int m = 0; m < NIT; ++m) { A[m] = at(a0 + offm[m]); B[m] = at(a1 + offm[m]); }
+                    for (int m = 0; m < NIT; ++m) { A[m] = at(a0 ^ offm[m]); B[m] = at(a1 ^ offm[m]); }
                     if (k == KIND_NOT) {
 #pragma unroll
-                        for (int m = 0; m < NIT; ++m) { at(a0 + offm[m]) = B[m]; at(a1 + offm[m]) = A[m]; }
+                        for (int m = 0; m < NIT; ++m) { at(a0 ^ offm[m]) = B[m]; at(a1 ^ offm[m]) = A[m]; }
                     } else {   // H
 #pragma unroll
                         for (int m = 0; m < NIT; ++m) {
                             const float2 a = A[m], b = B[m];
-                            at(a0 + offm[m]) = make_float2((a.x + b.x) * r, (a.y + b.y) * r);
-                            at(a1 + offm[m]) = make_float2((a.x - b.x) * r, (a.y - b.y) * r);
+                            at(a0 ^ offm[m]) = make_float2((a.x + b.x) * r, (a.y + b.y) * r);
+                            at(a1 ^ offm[m]) = make_float2((a.x - b.x) * r, (a.y - b.y) * r);
                         }
                     }
                 }
@@ -827,15 +873,20 @@ __device__ __forceinline__ bool run_lds_path(float2* M, uint4* gt, const float* 
         }
     }
     if (off_out) {
+        // logical entry (j, j) is stored in row phi(j) = A j + b
+        int pj = (int)bmap;
+#pragma unroll
+        for (int p = 0; p < NQ; ++p)
+            if ((j >> p) & 1) pj ^= (int)((Amap >> (6 * p)) & 63u);
         float off = 0.0f;
 #pragma unroll
         for (int m = 0; m < N / RG; ++m) {
             const int r = m * RG + rg;
             const float2 v = M[r * N + j];
-            off += (r == j) ? 0.0f : v.x * v.x + v.y * v.y;
+            off += (r == pj) ? 0.0f : v.x * v.x + v.y * v.y;
         }
         *off_out = off;
-        *diag_out = (lane < CW) ? M[j * N + j] : make_float2(0.0f, 0.0f);
+        *diag_out = (lane < CW) ? M[pj * N + j] : make_float2(0.0f, 0.0f);
     }
     return ok;
 }
