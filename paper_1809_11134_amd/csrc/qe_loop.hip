@@ -746,38 +746,74 @@ __global__ __launch_bounds__(256) void ga_update_kernel(LoopArgs a, uint64_t gen
 }
 
 // --------------------------------------------------------------- elite FP64
-// Top-k circuits of each population by (f descending, index ascending):
-// bitonic sort of P keys in LDS (P <= 4096).
+// Top-k circuits of each population by (f descending, index ascending): a
+// bitonic sort of the 4096 (padded) keys of the population, four per thread.
+// Exchanges at strides 1 and 2 stay in a thread's registers, strides 4..128
+// within a wavefront (shuffles of the partner lane), and only strides of 256
+// and more go through LDS with workgroup barriers (10 of the 78 stages).
+constexpr int ELITE_KEYS = 4096;
+
+__device__ __forceinline__ unsigned long long cas_keep(unsigned long long v, unsigned long long p,
+                                                       bool lower, bool asc) {
+    // the element at the lower index of an ascending pair keeps the minimum
+    const bool take_min = lower == asc;
+    return take_min ? (p < v ? p : v) : (p > v ? p : v);
+}
+
 __global__ __launch_bounds__(1024) void elite_select_kernel(LoopArgs a, const float* __restrict__ f,
                                                            int k, int32_t* __restrict__ idx_out) {
-    __shared__ unsigned long long key[4096];
+    __shared__ unsigned long long key[ELITE_KEYS];
     const int i = blockIdx.x, P = a.P, tid = threadIdx.x;
-    int Pp = 1;
-    while (Pp < P) Pp <<= 1;
-    for (int e = tid; e < Pp; e += blockDim.x) {
+    unsigned long long v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int e = 4 * tid + q;
         unsigned long long kv = ~0ull;
         if (e < P) {
-            const float v = f[(size_t)i * P + e];
+            const float x = f[(size_t)i * P + e];
             // non-negative floats order like their bit patterns; NaN last
-            const uint32_t ord = (v >= 0.0f) ? __float_as_uint(v) + 1u : 0u;
+            const uint32_t ord = (x >= 0.0f) ? __float_as_uint(x) + 1u : 0u;
             kv = ((unsigned long long)(0xFFFFFFFFu - ord) << 32) | (uint32_t)e;
         }
-        key[e] = kv;
+        v[q] = kv;
     }
-    __syncthreads();
-    for (int size = 2; size <= Pp; size <<= 1)
+    for (int size = 2; size <= ELITE_KEYS; size <<= 1) {
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int e = tid; e < Pp; e += blockDim.x) {
-                const int o = e ^ stride;
-                if (o > e) {
-                    const bool up = (e & size) == 0;
-                    const unsigned long long x = key[e], y = key[o];
-                    if ((x > y) == up) { key[e] = y; key[o] = x; }
+            if (stride >= 256) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) key[4 * tid + q] = v[q];
+                __syncthreads();
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int e = 4 * tid + q;
+                    v[q] = cas_keep(v[q], key[e ^ stride], (e & stride) == 0, (e & size) == 0);
                 }
+                __syncthreads();
+            } else if (stride >= 4) {
+                const int lm = stride >> 2;          // partner lane offset
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int e = 4 * tid + q;
+                    const unsigned long long p = __shfl_xor(v[q], lm, 64);
+                    v[q] = cas_keep(v[q], p, (e & stride) == 0, (e & size) == 0);
+                }
+            } else {
+                unsigned long long w[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int e = 4 * tid + q;
+                    w[q] = cas_keep(v[q], v[q ^ stride], (e & stride) == 0, (e & size) == 0);
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) v[q] = w[q];
             }
-            __syncthreads();
         }
-    for (int e = tid; e < k; e += blockDim.x) idx_out[(size_t)i * k + e] = (int32_t)(key[e] & 0xFFFFFFFFu);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int e = 4 * tid + q;
+        if (e < k) idx_out[(size_t)i * k + e] = (int32_t)(v[q] & 0xFFFFFFFFu);
+    }
 }
 
 __global__ __launch_bounds__(256) void elite_eval_kernel(LoopArgs a, const uint16_t* __restrict__ gates,

@@ -286,6 +286,23 @@ def test_elite_recheck(dev, oracle, n):
             assert abs(f64[i, e] - fi[idx[i, e]]) <= 1e-5
 
 
+@pytest.mark.parametrize("P,k", [(4096, 4096), (3000, 1000), (1, 1)])
+def test_elite_selection_orders_whole_populations(dev, oracle, P, k):
+    # the selection sorts (f desc, index asc) over every stage of its network:
+    # in-register, in-wavefront and through LDS; ties are frequent here
+    n, L, I = 3, 6, 2
+    ctx, T = qeqea_ctx(dev, oracle, n, L, P, I, 77 + P)
+    slots, gates = ctx.sample(0)
+    f = ctx.eval_population(gates)
+    f[::7] = float("nan")                      # NaN sorts last
+    idx, _ = ctx.elite_recheck(gates, f, k)
+    fh, idx = f.cpu().numpy(), idx.cpu().numpy()
+    for i in range(I):
+        fi = fh[i * P:(i + 1) * P]
+        key = lambda c: (1, 0.0, c) if np.isnan(fi[c]) else (0, -fi[c], c)
+        assert list(idx[i]) == sorted(range(P), key=key)[:k]
+
+
 def test_checkpoint_resume(dev, oracle):
     n, L, P, I, seed = 4, 10, 32, 2, 2024
     a, T = qeqea_ctx(dev, oracle, n, L, P, I, seed, pm=0.5)
