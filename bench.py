@@ -125,6 +125,19 @@ def cpu_baseline(w, T, seconds):
                        f"and update single-threaded), {el:.1f} s")
 
 
+def _timed_eval(batch, path, B, reps, dev):
+    """Median duration of one qe_eval_fitness launch (preallocated output,
+    launched through the C ABI), and the output."""
+    import ctypes
+
+    import torch
+    from paper_1809_11134_amd import qe
+    f = torch.empty(B, dtype=torch.float32, device=dev)
+    launch = lambda: qe._call("qe_eval_fitness", None, ctypes.byref(batch), path, qe._ptr(f), None,
+                              None, qe._stream(None))
+    return _events_us(launch, reps), f
+
+
 def _events_us(fn, reps):
     import torch
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
@@ -158,17 +171,23 @@ def secondary_precision(dev, reps=5):
     order64 = np.lexsort((np.arange(P), -f64))
     cut = f64[order64[31]]
     out = {"workload": w["name"], "reference": "FP64 path on the GPU", "paths": {}}
+    batch, keep, _ = qe.make_batch(g, T32, n=n, L=L, target_stride=0)
+    lds = algorithmic_lds_bytes(w["gates"], n)
     for name, path in (("fp32", qe.PATH_FP32), ("bf16_mfma", qe.PATH_MFMA_BF16),
                        ("fp16_mfma", qe.PATH_MFMA_FP16), ("bf16_mfma_no_renorm", qe.PATH_MFMA_BF16_RAW),
                        ("fp16_mfma_no_renorm", qe.PATH_MFMA_FP16_RAW)):
-        us = _events_us(lambda: qe.eval_fitness(g, T32, n=n, L=L, path=path), reps)
-        f = qe.eval_fitness(g, T32, n=n, L=L, path=path)[0].cpu().numpy().astype(np.float64)
+        us, fd = _timed_eval(batch, path, P, reps, dev)
+        f = fd.cpu().numpy().astype(np.float64)
         err = np.abs(f - f64)
         top = np.lexsort((np.arange(P), -f))[:32]
         agree = int((f64[top] >= cut - 1e-6).sum())
         out["paths"][name] = {"evals_per_s": P / (us * 1e-6), "kernel_us": us,
                               "max_abs_df": float(err.max()), "p99_abs_df": float(np.quantile(err, 0.99)),
                               "elite32_agreement": agree, "kendall_tau": float(kendalltau(f, f64)[0])}
+        if path == qe.PATH_FP32:
+            # the per-gate model's LDS bytes for these circuits against the LDS peak
+            out["paths"][name]["algorithmic_lds_bytes"] = lds
+            out["paths"][name]["lds_frac"] = lds / (us * 1e-6) / 1e9 / LDS_PEAK_GBPS
     return out
 
 
@@ -357,9 +376,19 @@ def secondary_uneven(dev, reps=7):
     toff = torch.tensor(np.array(offs)[w["target_index"]], dtype=torch.int64, device=dev)
     g = torch.from_numpy(gates.astype(np.int16)).to(dev)
     nqd, goffd = torch.from_numpy(nq).to(dev), torch.from_numpy(goff).to(dev)
-    us = _events_us(lambda: qe.eval_fitness(g, flat, nq=nqd, goff=goffd, toff=toff, target_stride=None), reps)
+    batch, keep, B = qe.make_batch(g, flat, nq=nqd, goff=goffd, toff=toff, target_stride=None)
+    us, _ = _timed_eval(batch, qe.PATH_FP32, B, reps, dev)
+    # the per-gate model's LDS bytes, width by width
+    lds = 0.0
+    for n in range(1, 7):
+        rows = np.nonzero(nq == n)[0]
+        if len(rows) == 0:
+            continue
+        flat_g = np.concatenate([gates[goff[b]:goff[b + 1]] for b in rows])
+        lds += algorithmic_lds_bytes(flat_g, n) + (len(rows) - 1) * 16.0 * float(1 << (2 * n))
     return {"workload": w["name"], "circuits": len(nq), "evals_per_s": len(nq) / (us * 1e-6),
-            "kernel_us": us}
+            "kernel_us": us, "algorithmic_lds_bytes": lds,
+            "lds_frac": lds / (us * 1e-6) / 1e9 / LDS_PEAK_GBPS}
 
 
 def main():
@@ -458,7 +487,7 @@ def main():
     roofline = {"bound": "lds", "achieved": round(achieved, 2), "peak": round(LDS_PEAK_GBPS, 1),
                 "unit": "GB/s", "frac": round(achieved / LDS_PEAK_GBPS, 6),
                 "traffic": traffic_from_profiles("qeqea_fused_n4", src),
-                "kernel": "population_kernel<4,1,true> (sampling + Eq. 11 fitness + segment max, LDS-staged)",
+                "kernel": "population_kernel<4,1,true,false> (sampling + Eq. 11 fitness + segment max, LDS-staged)",
                 "kernel_ms": round(kern_ms, 6), "algorithmic_lds_bytes_per_launch": lds_bytes,
                 "algorithmic_flops_per_launch": flops, "alu_tflops": round(alu, 4),
                 "alu_frac": round(alu / FP32_VECTOR_PEAK_TFLOPS, 6)}

@@ -478,10 +478,12 @@ __device__ __forceinline__ void update_part_a(const LoopArgs& a, uint32_t gen, u
     SlotRec r = a.slot[o];
     QState q{};
     if (rot) q = load_qstate(a.qrec + oq);      // issued before ownership is known
+    // the individual's mutation decision is drawn while the loads are in flight
+    const bool mut = mutates(a, gen, i, ind);
     // the entry owns the slot if its circuit holds the slot's key (a circuit
     // uses a slot at most once: the slot fixes the position)
     if (r.key == 0ull || (uint32_t)r.key != 0xFFFFFFFFu - k) return;
-    if (mutates(a, gen, i, ind)) return;
+    if (mut) return;
     const float v = __uint_as_float((uint32_t)(r.key >> 32));
     r.key = 0ull;
     elitism(v, r, q, rot);
