@@ -570,11 +570,14 @@ __device__ __forceinline__ void wave_lds_fence() {
 // partial sums for the fitness: off-diagonal |m|^2, and the diagonal
 // elements of the wave's columns (lane l < CW holds element (j, j)).
 // gt: this wavefront's gate table in LDS (GATE_TABLE uint4, or
-// GATE_TABLE_ANGLED for angled gate sources).
+// GATE_TABLE_ANGLED for angled gate sources).  NCV: the source only yields
+// kinds of {I, NOT, CNOT, CV, CV+} (circuits decoded by the QEQEA sampler);
+// with the row relabelling only CV and CV+ then move data, and the gate body
+// needs no kind dispatch.
 constexpr int GATE_TABLE = 128;
 constexpr int GATE_TABLE_ANGLED = 192;
 
-template <int NQ, int W, bool IDENT, typename GateSrc>
+template <int NQ, int W, bool IDENT, bool NCV = false, typename GateSrc>
 __device__ __forceinline__ bool run_lds_path(float2* M, uint4* gt, const float* __restrict__ T, int L,
                                              GateSrc&& src, float* off_out, float2* diag_out,
                                              int wave = -1) {
@@ -769,7 +772,8 @@ __device__ __forceinline__ bool run_lds_path(float2* M, uint4* gt, const float* 
                     return;
                 }
             }
-            if (k >= KIND_CNOT && k <= KIND_CVDG) {
+            static_assert(!NCV || (RELABEL && !ANG), "the NCV body needs the relabelling");
+            if (NCV || (k >= KIND_CNOT && k <= KIND_CVDG)) {
                 constexpr int NIT = (N / 4) / RG;
                 uint32_t offm[NIT];
                 offm[0] = 0u;
@@ -779,7 +783,8 @@ __device__ __forceinline__ bool run_lds_path(float2* M, uint4* gt, const float* 
                 float2 A[NIT], B[NIT];
 #pragma unroll
                 for (int m = 0; m < NIT; ++m) { A[m] = at(a0 ^ offm[m]); B[m] = at(a1 ^ offm[m]); }
-                if (k == KIND_CNOT) {
+                // (with the row relabelling, NOT and CNOT never get here)
+                if (!RELABEL && !NCV && k == KIND_CNOT) {
 #pragma unroll
                     for (int m = 0; m < NIT; ++m) { at(a0 ^ offm[m]) = B[m]; at(a1 ^ offm[m]) = A[m]; }
                 } else {
@@ -816,7 +821,7 @@ __device__ __forceinline__ bool run_lds_path(float2* M, uint4* gt, const float* 
                     float2 A[NIT], B[NIT];
 #pragma unroll
                     for (int m = 0; m < NIT; ++m) { A[m] = at(a0 ^ offm[m]); B[m] = at(a1 ^ offm[m]); }
-                    if (k == KIND_NOT) {
+                    if (!RELABEL && k == KIND_NOT) {
 #pragma unroll
                         for (int m = 0; m < NIT; ++m) { at(a0 ^ offm[m]) = B[m]; at(a1 ^ offm[m]) = A[m]; }
                     } else {   // H

@@ -277,7 +277,9 @@ __device__ __forceinline__ void eval_circuit(const LoopArgs& a, uint32_t gen, ui
         constexpr int N = 1 << NQ;
         float off, gd, dd;
         float2 dg;
-        ok = run_lds_path<NQ, W, false>(M, gt, T, L, src, &off, &dg, W == 1 ? 0 : -1);
+        // circuits the sampler decodes hold only {I, NOT, CNOT, CV, CV+}
+        constexpr bool NCV = SAMPLE && !ISING;
+        ok = run_lds_path<NQ, W, false, NCV>(M, gt, T, L, src, &off, &dg, W == 1 ? 0 : -1);
         fv = group_fitness<W>(off, dg, red, N, &gd, &dd, a.fit_mode);
     }
     if (!ok) fv = __builtin_nanf("");
