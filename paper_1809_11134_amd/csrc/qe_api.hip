@@ -224,10 +224,12 @@ qe_status ctx_alloc(qe_ctx* c, T** p, size_t elems) {
     return QE_OK;
 }
 
+// Releases everything the context owns (best effort: a failing release
+// cannot be undone, and the remaining ones still run).
 void free_ctx(qe_ctx* c) {
-    for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second);
-    if (c->capture_stream) hipStreamDestroy(c->capture_stream);
-    for (void* p : c->owned) hipFree(p);
+    for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
+    for (void* p : c->owned) (void)hipFree(p);
     delete c;
 }
 
@@ -236,6 +238,8 @@ void free_ctx(qe_ctx* c) {
         qe_status s_ = (x);              \
         if (s_ != QE_OK) return s_;      \
     } while (0)
+
+bool is_ising(const qe_ctx* c) { return c->prob.library == QE_LIB_ISING; }
 
 qe_status check_ctx(qe_ctx* c, bool need_targets) {
     if (!c) return fail(QE_ERR_INVALID, "ctx is NULL");
@@ -480,8 +484,9 @@ qe_status qe_create(const qe_problem* p, qe_ctx** out) {
 
 qe_status qe_destroy(qe_ctx* c) {
     if (!c) return fail(QE_ERR_INVALID, "ctx is NULL");
-    hipDeviceSynchronize();
+    const hipError_t e = hipDeviceSynchronize();   // work still queued may use the buffers
     free_ctx(c);
+    if (e != hipSuccess) return fail(QE_ERR_DEVICE, std::string("hipDeviceSynchronize: ") + hipGetErrorString(e));
     return QE_OK;
 }
 
@@ -495,10 +500,6 @@ qe_status qe_set_targets(qe_ctx* c, const void* t, void* stream) {
     c->targets_set = true;
     return QE_OK;
 }
-
-namespace {
-bool is_ising(const qe_ctx* c) { return c->prob.library == QE_LIB_ISING; }
-}  // namespace
 
 qe_status qe_sample(qe_ctx* c, uint64_t gen, uint32_t* slots, uint16_t* gates, uint32_t* angles,
                     void* stream) {
@@ -573,7 +574,7 @@ static qe_status graph_for(qe_ctx* c, int32_t n_gen, float* f_hist, hipGraphExec
     for (int j = 0; j < n_gen && st == QE_OK; ++j)
         st = enqueue_generation(c, a, (uint64_t)j, f_hist ? f_hist + j * IP : c->f, c->capture_stream);
     hipError_t e = hipStreamEndCapture(c->capture_stream, &g);
-    if (st != QE_OK) { if (g) hipGraphDestroy(g); return st; }
+    if (st != QE_OK) { if (g) (void)hipGraphDestroy(g); return st; }
     if (e != hipSuccess) return fail(QE_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
     hipGraphExec_t ex = nullptr;
     e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
@@ -661,13 +662,15 @@ qe_status qe_get_best(qe_ctx* c, int32_t inst, uint16_t* gates_host, uint32_t* a
         QE_HIP(hipMalloc(&d, sizeof(double)));
         qe_status st = qe_eval_fitness_fp64(&b, d, nullptr, nullptr, nullptr);
         hipError_t e = st == QE_OK ? hipMemcpy(f64_host, d, sizeof(double), hipMemcpyDeviceToHost) : hipSuccess;
-        hipFree(d);
+        (void)hipFree(d);
         if (st != QE_OK) return st;
         if (e != hipSuccess) return fail(QE_ERR_DEVICE, hipGetErrorString(e));
     }
     if (!(fv == fv)) return fail(QE_ERR_NUMERIC, "best fitness is NaN");
     return QE_OK;
 }
+
+}  // extern "C"
 
 // ------------------------------------------------------ checkpoint / restore
 namespace {
@@ -701,6 +704,8 @@ struct CkptHeader {
     uint64_t payload;
 };
 }  // namespace
+
+extern "C" {
 
 qe_status qe_checkpoint(qe_ctx* c, void* buf, size_t* size) {
     QE_TRY(check_ctx(c, false));
