@@ -351,10 +351,24 @@ def secondary_qeqea_n5(dev, gens=20):
     ms = e0.elapsed_time(e1)
     f32 = hist[gens - 1].view(I, P).gather(1, idx.long()).double()
     best = [ctx.get_best(i, with_fp64=False)[1] for i in range(4)]
+    # the fused sampling + fitness kernel alone, against the LDS peak
+    slots, gates, fk = ctx.sample_eval(2 * gens)
+    torch.cuda.synchronize()
+    reps = 10
+    e0.record()
+    for r in range(reps):
+        ctx.sample_eval(2 * gens + 1 + r, slots, gates, fk)
+    e1.record()
+    torch.cuda.synchronize()
+    kern_ms = e0.elapsed_time(e1) / reps
+    lds = algorithmic_lds_bytes(gates.cpu().numpy(), n)
     ctx.close()
     return {"workload": w["name"], "generations": gens, "evals_per_s": gens * I * P / (ms * 1e-3),
             "ms_per_generation": ms / gens, "elite_fp32_vs_fp64_max_abs_df": float((f32 - f64).abs().max()),
-            "best_f_first_populations": best}
+            "best_f_first_populations": best,
+            "fused_kernel": "population_kernel<5,2,true,false>", "fused_kernel_us": kern_ms * 1e3,
+            "algorithmic_lds_bytes_per_launch": lds,
+            "lds_frac": lds / (kern_ms * 1e-3) / 1e9 / LDS_PEAK_GBPS}
 
 
 def secondary_uneven(dev, reps=7):

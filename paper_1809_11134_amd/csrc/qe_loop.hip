@@ -963,12 +963,16 @@ hipError_t launch_qeqea_update(const LoopArgs& a, uint64_t gen, const uint32_t* 
     const uint32_t nA = blocks((size_t)a.I * a.P * a.L, UPD_BLOCK);
     // part B: per instance, enough workgroups for the (mutated individual,
     // slot chunk) items up to four standard deviations above the binomial
-    // mean (more items loop)
+    // mean (more items loop).  With many instances the grid holds far more
+    // workgroups than the GPU runs at once and the total is close to its mean,
+    // so the slack only adds workgroups that find nothing to do: then each
+    // instance gets its mean and the busier ones loop.
     const size_t chunks = ((size_t)a.R * a.L + UPD_BLOCK - 1) / UPD_BLOCK;
     const double pm = (double)a.thr_pm / 4294967296.0;
     const double expect = pm * a.P * chunks, sd = std::sqrt(a.P * pm * (1.0 - pm)) * chunks;
+    const double slack = expect * a.I > 8192.0 ? 1.0 : 4.0 * sd + 8.0;
     const uint32_t per_inst = (uint32_t)std::max<double>(
-        1.0, std::min<double>(std::ceil(expect + 4.0 * sd + 8.0), (double)a.P * chunks));
+        1.0, std::min<double>(std::ceil(expect + slack), (double)a.P * chunks));
     const uint32_t nB = per_inst * (uint32_t)a.I;
     const size_t lds = ((size_t)a.P * sizeof(uint16_t) + 15) & ~(size_t)15;
     qeqea_update_kernel<<<nC + nB + nA, UPD_BLOCK, lds, s>>>(a, gen, slots, gates, angles, f, nC, nB,
