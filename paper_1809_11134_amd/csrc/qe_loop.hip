@@ -26,10 +26,7 @@ __device__ __forceinline__ uint32_t gen_of(const LoopArgs& a, uint64_t gen) {
 // ------------------------------------------------------------- measurement
 // Born-rule measurement of a qutrit (3 complex amplitudes, unnormalised):
 // u in [0,1) from the top 24 bits of w scales the cumulative weights.
-__device__ __forceinline__ int measure_qutrit(const float* q, uint32_t w) {
-    const float2 a0 = *reinterpret_cast<const float2*>(q);
-    const float2 a1 = *reinterpret_cast<const float2*>(q + 2);
-    const float2 a2 = *reinterpret_cast<const float2*>(q + 4);
+__device__ __forceinline__ int measure_amps(float2 a0, float2 a1, float2 a2, uint32_t w) {
     const float p0 = a0.x * a0.x + a0.y * a0.y;
     const float p1 = a1.x * a1.x + a1.y * a1.y;
     const float p2 = a2.x * a2.x + a2.y * a2.y;
@@ -39,6 +36,32 @@ __device__ __forceinline__ int measure_qutrit(const float* q, uint32_t w) {
     return x < c0 ? 0 : (x < c1 ? 1 : 2);
 }
 
+// An empty instruction sequence that reads v: the value must exist at this
+// point, so the compiler can neither drop the work that produces it nor sink
+// that work into a later branch.
+__device__ __forceinline__ void anchor(float v) { asm volatile("" ::"v"(v)); }
+__device__ __forceinline__ void anchor(uint32_t v) { asm volatile("" ::"v"(v)); }
+
+// The state a slot's decode reads: its angle and, for a rotation slot, its
+// qutrit amplitudes.  Both loads are issued by every lane before either
+// value is used (a template slot reads qutrit 0 of its instance, one cached
+// line, and ignores it), so the gather costs one random-access latency, not
+// two in sequence.
+struct SlotState {
+    uint32_t theta;
+    float2 q0, q1, q2;
+};
+
+__device__ __forceinline__ SlotState load_slot_state(const LoopArgs& a, uint32_t i, uint32_t s, bool rot) {
+    SlotState st;
+    st.theta = a.slot[(size_t)i * a.S + s].theta;
+    const float2* q = reinterpret_cast<const float2*>(a.qrec[(size_t)i * a.Q + (rot ? s : 0u)].q);
+    st.q0 = q[0];
+    st.q1 = q[1];
+    st.q2 = q[2];
+    return st;
+}
+
 // Decodes slot s of instance i: rotation slot -> NOT on its wire when the
 // measured axis is x and the angle rounds to a half turn, else I; template
 // slot (c, t) -> controlled V^q with q the angle in quarter turns.
@@ -46,13 +69,17 @@ __device__ __forceinline__ uint16_t decode_slot(const LoopArgs& a, uint32_t gen,
                                                 uint32_t s) {
     const uint32_t LP = (uint32_t)a.L * (uint32_t)a.P;
     const uint32_t r = s / LP;
-    const uint32_t th = a.slot[(size_t)i * a.S + s].theta;
-    const int q = (int)(((th + 0x20000000u) >> 30) & 3u);
-    if (r < (uint32_t)a.n) {
-        const u32x4 w = draw(a.seed, TAG_MEASURE, gen, i, s);
-        const int axis = measure_qutrit(a.qrec[(size_t)i * a.Q + s].q, w.x);
-        return (axis == 0 && q == 2) ? make_desc(KIND_NOT, (int)r, 0) : (uint16_t)0;
-    }
+    const bool rot = r < (uint32_t)a.n;
+    const SlotState st = load_slot_state(a, i, s, rot);
+    // every lane measures (a wavefront with any rotation slot runs the draw
+    // anyway) while the loads are in flight; template slots ignore the outcome
+    const u32x4 w = draw(a.seed, TAG_MEASURE, gen, i, s);
+    anchor(w.x);
+    anchor(st.q0.x);
+    anchor(st.q2.x);
+    const int axis = measure_amps(st.q0, st.q1, st.q2, w.x);
+    const int q = (int)(((st.theta + 0x20000000u) >> 30) & 3u);
+    if (rot) return (axis == 0 && q == 2) ? make_desc(KIND_NOT, (int)r, 0) : (uint16_t)0;
     if (q == 0) return 0;
     int c, t;
     pair_of(a.n, (int)r - a.n, &c, &t);
@@ -67,15 +94,17 @@ __device__ __forceinline__ uint16_t decode_slot(const LoopArgs& a, uint32_t gen,
 __device__ __forceinline__ uint2 decode_ising(const LoopArgs& a, uint32_t gen, uint32_t i, uint32_t s) {
     const uint32_t LP = (uint32_t)a.L * (uint32_t)a.P;
     const uint32_t r = s / LP;
-    const uint32_t th = a.slot[(size_t)i * a.S + s].theta;
-    if (r < (uint32_t)a.n) {
-        const u32x4 w = draw(a.seed, TAG_MEASURE, gen, i, s);
-        const int axis = measure_qutrit(a.qrec[(size_t)i * a.Q + s].q, w.x);
-        return make_uint2(make_desc(KIND_RX + axis, (int)r, 0), th);
-    }
+    const bool rot = r < (uint32_t)a.n;
+    const SlotState st = load_slot_state(a, i, s, rot);
+    const u32x4 w = draw(a.seed, TAG_MEASURE, gen, i, s);   // every lane, as in decode_slot
+    anchor(w.x);
+    anchor(st.q0.x);
+    anchor(st.q2.x);
+    const int axis = measure_amps(st.q0, st.q1, st.q2, w.x);
+    if (rot) return make_uint2(make_desc(KIND_RX + axis, (int)r, 0), st.theta);
     int pa, pb;
     upair_of(a.n, (int)r - a.n, &pa, &pb);
-    return make_uint2(make_desc(KIND_ZZ, pa, pb), th);
+    return make_uint2(make_desc(KIND_ZZ, pa, pb), st.theta);
 }
 
 // Segment index of Eq. 10 from the SAMPLE draw of position pos: the
