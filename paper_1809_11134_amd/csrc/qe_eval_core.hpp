@@ -629,6 +629,9 @@ __device__ __forceinline__ bool run_lds_path(float2* M, uint4* gt, const float* 
     // uncontrolled gate has (N / 2) / RG passes)
     constexpr bool NIT_USES_R2 = (N / 2) / RG > 1, NIT_USES_R3 = (N / 2) / RG > 2,
                    NIT_USES_R4 = (N / 2) / RG > 4;
+    // CV body of one wavefront per circuit (a gate table of per-row-group
+    // offsets and signs)
+    constexpr bool CVB = NCV && W == 1;
     for (int ch = 0; ch < chunks; ++ch) {
         const SrcT dvv = ch == 0 ? dv0 : src(ch);
         const uint32_t dv = desc_of(dvv);
@@ -835,7 +838,67 @@ __device__ __forceinline__ bool run_lds_path(float2* M, uint4* gt, const float* 
                 }
             }
         };
-        if constexpr (W == 1) {
+        if constexpr (CVB) {
+            // Only CV and CV+ move data (NOT and CNOT live in the row map).
+            // Entry e of the table: words 0..3 hold, for row group rg, the
+            // stored byte offset of the first row of the group's pair (pair
+            // index bits 0, 1 = rg inserted, the control row and the map's
+            // translation folded in), so that a lane reads its own word; then
+            // the target row offset, the sign s (CV: +1, CV+: -1) and the
+            // offsets of pair-index bits 2 and 3.  With a, b the two rows of a
+            // pair, p + iq = a + b and u + iv = a - b, V maps (a, b) to
+            // ((p - v + i(q + u)) / 2, (p + v + i(q - u)) / 2); V+ is V with u,
+            // v negated, hence the sign as an exact +-1 factor of a fused
+            // multiply-add (each result rounds once, as p - v does).
+            constexpr int NITC = (N / 4) / RG;
+            const int count = __popcll(live_mask);
+            if (live) {
+                const int rank = (int)__builtin_amdgcn_mbcnt_hi(
+                    (uint32_t)(live_mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)live_mask, 0u));
+                const uint32_t base = (myB << ROWB) ^ colb(cpos), i1 = ins(1), i2 = ins(2);
+                gt[2 * rank] = make_uint4(base, base ^ i1, base ^ i2, base ^ i1 ^ i2);
+                gt[2 * rank + 1] = make_uint4(colb(tpos), f_bits(kind == KIND_CVDG ? -1.0f : 1.0f),
+                                              NITC > 1 ? ins(4) : 0u, NITC > 2 ? ins(8) : 0u);
+            }
+            wave_lds_fence();
+            const uint32_t* gw = reinterpret_cast<const uint32_t*>(gt) + rg;   // entry 0, this row group
+            char* Mj = reinterpret_cast<char*>(M) + jb;                        // column j
+            auto el = [&](uint32_t off) -> float2& { return *reinterpret_cast<float2*>(Mj + off); };
+            auto cv = [&](const uint32_t T0, const uint4 E, auto&& next) {
+                const uint32_t T1 = T0 ^ E.x;
+                const float sg = bits_f(E.y);
+                uint32_t offm[NITC];
+                offm[0] = 0u;
+                if constexpr (NITC > 1) offm[1] = E.z;
+                if constexpr (NITC > 2) { offm[2] = E.w; offm[3] = E.z ^ E.w; }
+                next();
+                float2 A[NITC], B[NITC];
+#pragma unroll
+                for (int m = 0; m < NITC; ++m) { A[m] = el(T0 ^ offm[m]); B[m] = el(T1 ^ offm[m]); }
+#pragma unroll
+                for (int m = 0; m < NITC; ++m) {
+                    const float2 a = A[m], b = B[m];
+                    const float p = a.x + b.x, q = a.y + b.y, u = a.x - b.x, v = a.y - b.y;
+                    el(T0 ^ offm[m]) = make_float2(0.5f * __builtin_fmaf(sg, -v, p), 0.5f * __builtin_fmaf(sg, u, q));
+                    el(T1 ^ offm[m]) = make_float2(0.5f * __builtin_fmaf(sg, v, p), 0.5f * __builtin_fmaf(sg, -u, q));
+                }
+            };
+            // two gates per iteration, each entry loaded one gate ahead
+            uint32_t ta = 0u, tb2 = 0u;
+            uint4 ea = make_uint4(0u, 0u, 0u, 0u), eb = ea;
+            if (count > 0) { ta = gw[0]; ea = gt[1]; }
+            // lgkmcnt(0): the first entry is in place before the loop, so that
+            // inside it only the data reads are waited for (the entry of the
+            // next gate is issued ahead of them and arrives first)
+            __builtin_amdgcn_s_waitcnt(0xC07F);
+            for (int e = 0; e < count; e += 2) {
+                cv(ta, ea, [&] { if (e + 1 < count) { tb2 = gw[8 * (e + 1)]; eb = gt[2 * (e + 1) + 1]; } });
+                wave_lds_fence();
+                if (e + 1 >= count) break;
+                cv(tb2, eb, [&] { if (e + 2 < count) { ta = gw[8 * (e + 2)]; ea = gt[2 * (e + 2) + 1]; } });
+                wave_lds_fence();
+            }
+        } else if constexpr (W == 1) {
             const int count = __popcll(live_mask);
             if (live) {
                 const int rank = (int)__builtin_amdgcn_mbcnt_hi(

@@ -159,6 +159,28 @@ def test_sample_eval_then_update_equals_generation(dev, oracle, n):
         assert np.array_equal(sa[k], sb[k]), k
 
 
+@pytest.mark.parametrize("L", [20, 64, 65, 150])
+def test_fused_fitness_equals_eval_bitwise(dev, oracle, L):
+    # n = 4 circuits in the fused kernel take a CV/CV+-only body (per-row-
+    # group offsets from the gate table, CV+ as CV with a sign): its fitness
+    # must round exactly as the evaluation kernel's does, over one, two and
+    # three chunks of 64 positions, and match the oracle
+    n, P, I, seed = 4, 40, 2, 6060 + L
+    a, T = qeqea_ctx(dev, oracle, n, L, P, I, seed)
+    for gen in range(3):
+        slots, gates, f = a.sample_eval(gen)
+        fe = a.eval_population(gates)
+        assert torch.equal(f, fe), gen
+        g = gates.cpu().numpy().view(np.uint16)
+        ref = np.array([oracle.fitness(n, g[c], T[c // P])[0] for c in range(I * P)])
+        assert np.abs(f.cpu().numpy() - ref).max() <= 1e-5, gen
+        a.update(gen, slots, gates, f)
+    # many data-moving gates per chunk (the largest scale factors)
+    kinds = (g & 15)
+    assert ((kinds == inputs.CV) | (kinds == inputs.CVDG)).sum(1).max() >= min(L, 64) // 3
+    assert qe.device_errors() == 0
+
+
 def test_state_read_fields(dev, oracle):
     n, L, P, I, seed = 3, 5, 8, 2, 31
     ctx, _ = qeqea_ctx(dev, oracle, n, L, P, I, seed)
