@@ -632,6 +632,36 @@ __device__ __forceinline__ bool run_lds_path(float2* M, uint4* gt, const float* 
     // CV body of one wavefront per circuit (a gate table of per-row-group
     // offsets and signs)
     constexpr bool CVB = NCV && W == 1;
+    // CV or CV+ of sampled NCV circuits on the lane's pairs (T0 ^ o, T0 ^ tb ^ o)
+    // of column j, o over the offsets of pair-index bits 2 and 3 (o2, o3),
+    // written back in place.  With a, b the two rows of a pair, p + iq = a + b
+    // and u + iv = a - b, V maps (a, b) to ((p - v + i(q + u)) / 2,
+    // (p + v + i(q - u)) / 2); V+ is V with u, v negated.  Each result is one
+    // fused multiply-add of the exact halves p / 2, q / 2 and the exact factor
+    // +-1/2 (CV +, CV+ -): it rounds (p - v) / 2 once, which is 0.5 times p - v
+    // rounded.  `next` runs once the addresses are known, before the data reads.
+    char* const Mj = reinterpret_cast<char*>(M) + jb;
+    auto el = [&](uint32_t off) -> float2& { return *reinterpret_cast<float2*>(Mj + off); };
+    auto cv_gate = [&](const uint32_t T0, const uint32_t tb, const float hs, const uint32_t o2,
+                       const uint32_t o3, auto&& next) {
+        constexpr int NITC = (N / 4) / RG;
+        const uint32_t T1 = T0 ^ tb;
+        uint32_t offm[NITC];
+        offm[0] = 0u;
+        if constexpr (NITC > 1) offm[1] = o2;
+        if constexpr (NITC > 2) { offm[2] = o3; offm[3] = o2 ^ o3; }
+        next();
+        float2 A[NITC], B[NITC];
+#pragma unroll
+        for (int m = 0; m < NITC; ++m) { A[m] = el(T0 ^ offm[m]); B[m] = el(T1 ^ offm[m]); }
+#pragma unroll
+        for (int m = 0; m < NITC; ++m) {
+            const float2 a = A[m], b = B[m];
+            const float ph = 0.5f * (a.x + b.x), qh = 0.5f * (a.y + b.y), u = a.x - b.x, v = a.y - b.y;
+            el(T0 ^ offm[m]) = make_float2(__builtin_fmaf(hs, -v, ph), __builtin_fmaf(hs, u, qh));
+            el(T1 ^ offm[m]) = make_float2(__builtin_fmaf(hs, v, ph), __builtin_fmaf(hs, -u, qh));
+        }
+    };
     for (int ch = 0; ch < chunks; ++ch) {
         const SrcT dvv = ch == 0 ? dv0 : src(ch);
         const uint32_t dv = desc_of(dvv);
@@ -844,12 +874,8 @@ __device__ __forceinline__ bool run_lds_path(float2* M, uint4* gt, const float* 
             // stored byte offset of the first row of the group's pair (pair
             // index bits 0, 1 = rg inserted, the control row and the map's
             // translation folded in), so that a lane reads its own word; then
-            // the target row offset, the sign s (CV: +1, CV+: -1) and the
-            // offsets of pair-index bits 2 and 3.  With a, b the two rows of a
-            // pair, p + iq = a + b and u + iv = a - b, V maps (a, b) to
-            // ((p - v + i(q + u)) / 2, (p + v + i(q - u)) / 2); V+ is V with u,
-            // v negated, hence the sign as an exact +-1 factor of a fused
-            // multiply-add (each result rounds once, as p - v does).
+            // the target row offset, the signed half (CV: 1/2, CV+: -1/2) and
+            // the offsets of pair-index bits 2 and 3.
             constexpr int NITC = (N / 4) / RG;
             const int count = __popcll(live_mask);
             if (live) {
@@ -857,31 +883,13 @@ __device__ __forceinline__ bool run_lds_path(float2* M, uint4* gt, const float* 
                     (uint32_t)(live_mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)live_mask, 0u));
                 const uint32_t base = (myB << ROWB) ^ colb(cpos), i1 = ins(1), i2 = ins(2);
                 gt[2 * rank] = make_uint4(base, base ^ i1, base ^ i2, base ^ i1 ^ i2);
-                gt[2 * rank + 1] = make_uint4(colb(tpos), f_bits(kind == KIND_CVDG ? -1.0f : 1.0f),
+                gt[2 * rank + 1] = make_uint4(colb(tpos), f_bits(kind == KIND_CVDG ? -0.5f : 0.5f),
                                               NITC > 1 ? ins(4) : 0u, NITC > 2 ? ins(8) : 0u);
             }
             wave_lds_fence();
             const uint32_t* gw = reinterpret_cast<const uint32_t*>(gt) + rg;   // entry 0, this row group
-            char* Mj = reinterpret_cast<char*>(M) + jb;                        // column j
-            auto el = [&](uint32_t off) -> float2& { return *reinterpret_cast<float2*>(Mj + off); };
             auto cv = [&](const uint32_t T0, const uint4 E, auto&& next) {
-                const uint32_t T1 = T0 ^ E.x;
-                const float sg = bits_f(E.y);
-                uint32_t offm[NITC];
-                offm[0] = 0u;
-                if constexpr (NITC > 1) offm[1] = E.z;
-                if constexpr (NITC > 2) { offm[2] = E.w; offm[3] = E.z ^ E.w; }
-                next();
-                float2 A[NITC], B[NITC];
-#pragma unroll
-                for (int m = 0; m < NITC; ++m) { A[m] = el(T0 ^ offm[m]); B[m] = el(T1 ^ offm[m]); }
-#pragma unroll
-                for (int m = 0; m < NITC; ++m) {
-                    const float2 a = A[m], b = B[m];
-                    const float p = a.x + b.x, q = a.y + b.y, u = a.x - b.x, v = a.y - b.y;
-                    el(T0 ^ offm[m]) = make_float2(0.5f * __builtin_fmaf(sg, -v, p), 0.5f * __builtin_fmaf(sg, u, q));
-                    el(T1 ^ offm[m]) = make_float2(0.5f * __builtin_fmaf(sg, v, p), 0.5f * __builtin_fmaf(sg, -u, q));
-                }
+                cv_gate(T0, E.x, bits_f(E.y), E.z, E.w, next);
             };
             // two gates per iteration, each entry loaded one gate ahead
             uint32_t ta = 0u, tb2 = 0u;
@@ -922,6 +930,31 @@ __device__ __forceinline__ bool run_lds_path(float2* M, uint4* gt, const float* 
                 wave_lds_fence();
                 if (e + 1 >= count) break;
                 apply(b0e, b1e, b2e, [&] { if (e + 2 < count) fetch(e + 2, a0e, a1e, a2e); });
+                wave_lds_fence();
+            }
+        } else if constexpr (NCV) {
+            // W > 1: the CV body with each gate's constants read from the lane
+            // that owns it (the row group's offset from the base and the
+            // offsets of pair-index bits 0, 1; the sign in the target word's
+            // top bit, free since offsets stay below 2^15)
+            (void)gt;
+            constexpr int NITC = (N / 4) / RG;
+            const uint32_t gbase = (myB << ROWB) ^ colb(cpos), gi1 = ins(1), gi2 = ins(2);
+            const uint32_t gtw = colb(tpos) | (kind == KIND_CVDG ? 0x80000000u : 0u);
+            const uint32_t go2 = NITC > 1 ? ins(4) : 0u, go3 = NITC > 2 ? ins(8) : 0u;
+            // the row-group masks as plain registers, so that each selection is
+            // one AND with the scalar offset (not a move and a select)
+            uint32_t m0 = mb0, m1 = mb1;
+            asm volatile("" : "+v"(m0), "+v"(m1));
+            uint64_t todo = live_mask;
+            while (todo) {
+                const int g = (int)__builtin_ctzll(todo);
+                todo &= todo - 1;
+                auto rl = [&](uint32_t v) { return (uint32_t)__builtin_amdgcn_readlane((int)v, g); };
+                const uint32_t T0 = rl(gbase) ^ (m0 & rl(gi1)) ^ (m1 & rl(gi2));
+                const uint32_t tw = rl(gtw);
+                cv_gate(T0, tw & 0x7FFFFFFFu, (tw >> 31) ? -0.5f : 0.5f, NITC > 1 ? rl(go2) : 0u,
+                        NITC > 2 ? rl(go3) : 0u, [] {});
                 wave_lds_fence();
             }
         } else {
