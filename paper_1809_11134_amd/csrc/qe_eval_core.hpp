@@ -821,15 +821,17 @@ __device__ __forceinline__ bool run_lds_path(float2* M, uint4* gt, const float* 
 #pragma unroll
                     for (int m = 0; m < NIT; ++m) { at(a0 ^ offm[m]) = B[m]; at(a1 ^ offm[m]) = A[m]; }
                 } else {
-                    // CV: (x, y) -> V (x, y); CV+ writes the two results the other
-                    // way round (V+ = X V X for the symmetric V)
-                    const uint32_t sw = k == KIND_CVDG ? tb : 0u;
+                    // CV: (a, b) -> V (a, b); CV+ is CV with a - b negated: one
+                    // fused multiply-add of the exact halves and the factor
+                    // +-1/2 per result, as in the CV body of sampled circuits
+                    const float hs = k == KIND_CVDG ? -0.5f : 0.5f;
 #pragma unroll
                     for (int m = 0; m < NIT; ++m) {
                         const float2 a = A[m], b = B[m];
-                        const float p = a.x + b.x, q = a.y + b.y, u = a.x - b.x, v = a.y - b.y;
-                        at(a0 ^ sw ^ offm[m]) = make_float2(0.5f * (p - v), 0.5f * (q + u));
-                        at(a1 ^ sw ^ offm[m]) = make_float2(0.5f * (p + v), 0.5f * (q - u));
+                        const float ph = 0.5f * (a.x + b.x), qh = 0.5f * (a.y + b.y), u = a.x - b.x,
+                                    v = a.y - b.y;
+                        at(a0 ^ offm[m]) = make_float2(__builtin_fmaf(hs, -v, ph), __builtin_fmaf(hs, u, qh));
+                        at(a1 ^ offm[m]) = make_float2(__builtin_fmaf(hs, v, ph), __builtin_fmaf(hs, -u, qh));
                     }
                 }
             } else {
