@@ -613,7 +613,10 @@ __device__ __forceinline__ bool run_lds_path(float2* M, uint4* gt, const float* 
     // lane constants: byte offset of column j, and the two row-group bits as
     // all-ones / all-zeros masks
     const uint32_t jb = (uint32_t)j * 8u;
-    const uint32_t mb0 = (rg & 1) ? ~0u : 0u, mb1 = (rg & 2) ? ~0u : 0u;
+    uint32_t mb0 = (rg & 1) ? ~0u : 0u, mb1 = (rg & 2) ? ~0u : 0u;
+    // as plain registers, so that selecting a gate's offset is one AND with a
+    // scalar operand (a known 0 / ~0 mask becomes a move and a select)
+    asm volatile("" : "+v"(mb0), "+v"(mb1));
     auto at = [&](uint32_t byte_off) -> float2& {
         return *reinterpret_cast<float2*>(reinterpret_cast<char*>(M) + byte_off);
     };
@@ -944,16 +947,12 @@ __device__ __forceinline__ bool run_lds_path(float2* M, uint4* gt, const float* 
             const uint32_t gbase = (myB << ROWB) ^ colb(cpos), gi1 = ins(1), gi2 = ins(2);
             const uint32_t gtw = colb(tpos) | (kind == KIND_CVDG ? 0x80000000u : 0u);
             const uint32_t go2 = NITC > 1 ? ins(4) : 0u, go3 = NITC > 2 ? ins(8) : 0u;
-            // the row-group masks as plain registers, so that each selection is
-            // one AND with the scalar offset (not a move and a select)
-            uint32_t m0 = mb0, m1 = mb1;
-            asm volatile("" : "+v"(m0), "+v"(m1));
             uint64_t todo = live_mask;
             while (todo) {
                 const int g = (int)__builtin_ctzll(todo);
                 todo &= todo - 1;
                 auto rl = [&](uint32_t v) { return (uint32_t)__builtin_amdgcn_readlane((int)v, g); };
-                const uint32_t T0 = rl(gbase) ^ (m0 & rl(gi1)) ^ (m1 & rl(gi2));
+                const uint32_t T0 = rl(gbase) ^ (mb0 & rl(gi1)) ^ (mb1 & rl(gi2));
                 const uint32_t tw = rl(gtw);
                 cv_gate(T0, tw & 0x7FFFFFFFu, (tw >> 31) ? -0.5f : 0.5f, NITC > 1 ? rl(go2) : 0u,
                         NITC > 2 ? rl(go3) : 0u, [] {});
