@@ -137,40 +137,56 @@ __global__ __launch_bounds__(64 * W) void lds32_kernel(BatchArgs a, float* __res
 }
 
 // ----------------------------------------------- mixed widths, one launch
-// Circuits of a mixed-width batch are ordered by width, widest first, by a
-// one-workgroup counting sort; one launch then gives every workgroup (4
-// wavefronts) one work item: a circuit of width 6 (4 waves), two of width 5
-// (2 waves each), or four of width <= 4 (one wave each; LDS-staged for 4,
-// one entry per lane below).  Workgroups are dispatched in index order, so
-// the heaviest items start first (longest-processing-time order).
+// Circuits of a mixed-width batch are ordered by cost, widest first and,
+// within a width, longest first (classes of 8 gates), by a one-workgroup
+// counting sort; one launch then gives every workgroup (4 wavefronts) one
+// work item: a circuit of width 6 (4 waves), two of width 5 (2 waves each),
+// or four of width <= 4 (one wave each; LDS-staged for 4, one entry per lane
+// below), so an item's circuits have similar lengths.  Workgroups are
+// dispatched in index order, so the heaviest items start first
+// (longest-processing-time order).
 constexpr int MIX_BUCKETS = 7;          // widths 6..1, then malformed widths
+constexpr int MIX_LCLASSES = 16;        // lengths >= 120, 112..119, ..., 8..15, < 8
 
 __device__ __forceinline__ int mix_bucket(int n) { return (n >= 1 && n <= MAX_QUBITS) ? 6 - n : 6; }
+
+// Sort key of circuit b: width bucket, then length class (longest first; a
+// malformed range only lands in some class, the item reports it).
+__device__ __forceinline__ int mix_key(const BatchArgs& a, int b) {
+    const int64_t len = a.uniform_L > 0 ? (int64_t)a.uniform_L : (int64_t)a.goff[b + 1] - a.goff[b];
+    const int lc = len >= 120 ? 0 : (len < 8 ? MIX_LCLASSES - 1 : MIX_LCLASSES - 1 - (int)(len >> 3));
+    return mix_bucket(a.nq[b]) * MIX_LCLASSES + lc;
+}
 __device__ __forceinline__ int mix_per_item(int k) { return k == 0 ? 1 : (k == 1 ? 2 : 4); }
 
 // meta: [0..7) first order position, [8..15) first item (8 entries, the last
 // the total), [16..23) count per bucket.
 __global__ __launch_bounds__(1024) void mix_bucket_kernel(BatchArgs a, int32_t* order, int32_t* meta) {
-    __shared__ int cnt[MIX_BUCKETS], cursor[MIX_BUCKETS];
+    constexpr int K = MIX_BUCKETS * MIX_LCLASSES;
+    __shared__ int cnt[K], cursor[K];
     const int tid = threadIdx.x;
-    if (tid < MIX_BUCKETS) cnt[tid] = 0;
+    for (int k = tid; k < K; k += blockDim.x) cnt[k] = 0;
     __syncthreads();
-    for (int b = tid; b < a.B; b += blockDim.x) atomicAdd(&cnt[mix_bucket(a.nq[b])], 1);
+    for (int b = tid; b < a.B; b += blockDim.x) atomicAdd(&cnt[mix_key(a, b)], 1);
     __syncthreads();
     if (tid == 0) {
         int pos = 0, item = 0;
         for (int k = 0; k < MIX_BUCKETS; ++k) {
             meta[k] = pos;
             meta[8 + k] = item;
-            meta[16 + k] = cnt[k];
-            cursor[k] = pos;
-            pos += cnt[k];
-            item += (cnt[k] + mix_per_item(k) - 1) / mix_per_item(k);
+            int c = 0;
+            for (int l = 0; l < MIX_LCLASSES; ++l) {
+                cursor[k * MIX_LCLASSES + l] = pos + c;
+                c += cnt[k * MIX_LCLASSES + l];
+            }
+            meta[16 + k] = c;
+            pos += c;
+            item += (c + mix_per_item(k) - 1) / mix_per_item(k);
         }
         meta[8 + MIX_BUCKETS] = item;
     }
     __syncthreads();
-    for (int b = tid; b < a.B; b += blockDim.x) order[atomicAdd(&cursor[mix_bucket(a.nq[b])], 1)] = b;
+    for (int b = tid; b < a.B; b += blockDim.x) order[atomicAdd(&cursor[mix_key(a, b)], 1)] = b;
 }
 
 template <int NQ, int W>
