@@ -238,13 +238,17 @@ __device__ __forceinline__ void clear_next_mask(const LoopArgs& a, uint32_t gen,
 // decision of individual k (both run over 0..P-1) and empties its part of the
 // decision mask of the other generation parity.
 // ISING: circuits of the Ising library, whose gates carry angles (read from
-// angles_in, or with SAMPLE decoded and written to angles_out).
+// angles_in, or with SAMPLE decoded and written to angles_out).  With W > 1
+// and SAMPLE only the first wavefront samples; the others take its
+// descriptors from xch (two buffers of 64 entries, by chunk parity, so one
+// barrier per chunk separates a chunk's writes from the next chunk's).
 template <int NQ, int W, bool SAMPLE, bool ISING>
 __device__ __forceinline__ void eval_circuit(const LoopArgs& a, uint32_t gen, uint32_t ci,
                                              const uint16_t* gates_in, const uint32_t* angles_in,
                                              uint32_t* slots_out, uint16_t* gates_out,
                                              uint32_t* angles_out, float* f_out, bool writer,
-                                             bool decide, float2* M, uint4* gt, float (*red)[3]) {
+                                             bool decide, float2* M, uint4* gt, float (*red)[3],
+                                             void* xch = nullptr) {
     const uint32_t i = ci / (uint32_t)a.P, k = ci % (uint32_t)a.P;
     const int lane = (int)lane_id();
     const int L = a.L;
@@ -255,7 +259,7 @@ __device__ __forceinline__ void eval_circuit(const LoopArgs& a, uint32_t gen, ui
 #pragma unroll
     for (int c = 0; c < KEEP; ++c) kept[c] = 0xFFFFFFFFu;
     using SrcT = std::conditional_t<ISING, uint2, uint32_t>;
-    auto src = [&](int ch) -> SrcT {
+    auto own = [&](int ch) -> SrcT {
         const int p = ch * 64 + lane;
         if constexpr (!SAMPLE) {
             if constexpr (ISING)
@@ -294,6 +298,23 @@ __device__ __forceinline__ void eval_circuit(const LoopArgs& a, uint32_t gen, ui
                 gates_out[(size_t)ci * L + p] = d;
             }
             return (uint32_t)d;
+        }
+    };
+    // the circuit's descriptors, chunk ch (every wavefront of the circuit
+    // calls this the same number of times: the chunk loop is uniform)
+    auto src = [&](int ch) -> SrcT {
+        if constexpr (SAMPLE && W > 1) {
+            SrcT* buf = reinterpret_cast<SrcT*>(xch) + (ch & 1) * 64;
+            const bool first = threadIdx.x < 64;
+            SrcT d{};
+            if (first) {
+                d = own(ch);
+                buf[lane] = d;
+            }
+            __syncthreads();
+            return first ? d : buf[lane];
+        } else {
+            return own(ch);
         }
     };
     float fv;
@@ -362,9 +383,12 @@ __global__ __launch_bounds__(256) void population_kernel(LoopArgs a, uint64_t ge
         const int wave = (int)(threadIdx.x >> 6);
         const uint32_t ci = W == 1 ? blockIdx.x * CPB + (uint32_t)wave : blockIdx.x;
         if (ci >= total) return;
+        // (W > 1: the gate tables are unused, the first one is the
+        // descriptor exchange)
         eval_circuit<NQ, W, SAMPLE, ISING>(a, gen, ci, gates_in, angles_in, slots_out, gates_out,
                                            angles_out, f_out, W == 1 || threadIdx.x < 64, decide,
-                                           M[W == 1 ? wave : 0], GT[wave], red);
+                                           M[W == 1 ? wave : 0], GT[wave], red,
+                                           W == 1 ? nullptr : static_cast<void*>(GT[0]));
     }
 }
 
