@@ -533,8 +533,10 @@ __device__ __forceinline__ void update_part_a(const LoopArgs& a, uint32_t gen, u
     SlotRec r = a.slot[o];
     QState q{};
     if (rot) q = load_qstate(a.qrec + oq);      // issued before ownership is known
-    // the individual's mutation decision is drawn while the loads are in flight
-    const bool mut = mutates(a, gen, i, ind);
+    // the individual's mutation decision, from the generation's decision mask
+    // (its word is loaded with the records)
+    const uint32_t mw = mask_of(a, gen, i)[ind >> 5];
+    const bool mut = ((mw >> (ind & 31u)) & 1u) != 0u;
     // the entry owns the slot if its circuit holds the slot's key (a circuit
     // uses a slot at most once: the slot fixes the position)
     if (r.key == 0ull || (uint32_t)r.key != 0xFFFFFFFFu - k) return;
@@ -597,7 +599,9 @@ __device__ __forceinline__ void update_part_b(const LoopArgs& a, uint32_t gen, u
     __syncthreads();
     const uint32_t count = total;
     for (uint32_t t = b % per_inst; t < count * chunks; t += per_inst) {
-        const uint32_t ind = list[t / chunks];
+        // (every thread of the workgroup serves the same individual: its
+        // decision is drawn once per wavefront, on the scalar unit)
+        const uint32_t ind = (uint32_t)__builtin_amdgcn_readfirstlane((int)list[t / chunks]);
         const uint32_t e = (t % chunks) * UPD_BLOCK + threadIdx.x;
         if (e >= per) continue;
         const uint32_t r_ = e / L, pos = e - r_ * L;
