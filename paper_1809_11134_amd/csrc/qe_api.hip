@@ -202,7 +202,7 @@ struct qe_ctx {
     uint32_t* angles = nullptr;   // [I*P*L] (Ising library)
     float* f = nullptr;           // [I*P]
     uint64_t* d_gen = nullptr;
-    int32_t* elite_idx = nullptr;
+    unsigned long long* elite_cand = nullptr;   // candidates of the tiled elite selection
     hipStream_t capture_stream = nullptr;
     std::map<std::pair<int, float*>, hipGraphExec_t> graphs;
     hipGraph_t last_graph = nullptr;
@@ -449,7 +449,7 @@ qe_status qe_create(const qe_problem* p, qe_ctx** out) {
     if (p->library == QE_LIB_ISING) ALLOC(c->angles, I * P * L);
     ALLOC(c->f, I * P);
     ALLOC(c->d_gen, 1);
-    ALLOC(c->elite_idx, I * P);
+    ALLOC(c->elite_cand, (int64_t)elite_cand_keys(I, P));
 #undef ALLOC
     if (st == QE_OK) st = device_error_word(&a.err);
     if (st != QE_OK) { std::string m = g_last_error; free_ctx(c); return fail(st, m); }
@@ -625,7 +625,7 @@ qe_status qe_elite_recheck(qe_ctx* c, const uint16_t* gates, const uint32_t* ang
     if (k < 1 || k > c->prob.size_of_population) return fail(QE_ERR_INVALID, "k must be 1..P");
     if (c->prob.size_of_population > 4096) return fail(QE_ERR_UNSUPPORTED, "elite selection needs P <= 4096");
     hipStream_t s = (hipStream_t)stream;
-    QE_HIP(launch_elite_select(c->la, f, k, idx, s));
+    QE_HIP(launch_elite_select(c->la, f, k, idx, c->elite_cand, s));
     QE_HIP(launch_elite_eval(c->la, gates, angles, k, idx, f64, s));
     return QE_OK;
 }

@@ -130,8 +130,10 @@ hipError_t launch_ga_update(const LoopArgs& a, uint64_t gen, const float* f, hip
 hipError_t launch_c128_to_c64(const double* src, float* dst, int64_t n_reals, hipStream_t s);
 hipError_t launch_gen_advance(uint64_t* gen_ptr, uint64_t by, hipStream_t s);
 hipError_t launch_gen_set(uint64_t* gen_ptr, uint64_t v, hipStream_t s);
+// cand: elite_cand_keys(I, P) 64-bit keys of device workspace.
+size_t elite_cand_keys(int I, int P);
 hipError_t launch_elite_select(const LoopArgs& a, const float* f, int k, int32_t* idx,
-                               hipStream_t s);
+                               unsigned long long* cand, hipStream_t s);
 hipError_t launch_elite_eval(const LoopArgs& a, const uint16_t* gates, const uint32_t* angles, int k,
                              const int32_t* idx, double* f64, hipStream_t s);
 

@@ -807,12 +807,20 @@ __global__ __launch_bounds__(256) void ga_update_kernel(LoopArgs a, uint64_t gen
 }
 
 // --------------------------------------------------------------- elite FP64
-// Top-k circuits of each population by (f descending, index ascending): a
-// bitonic sort of the 4096 (padded) keys of the population, four per thread.
-// Exchanges at strides 1 and 2 stay in a thread's registers, strides 4..128
-// within a wavefront (shuffles of the partner lane), and only strides of 256
-// and more go through LDS with workgroup barriers (10 of the 78 stages).
-constexpr int ELITE_KEYS = 4096;
+// Top-k circuits of each population by (f descending, index ascending), as
+// ascending 64-bit keys (NaN and padding last).  Bitonic sorts of four keys
+// per thread: exchanges at strides 1 and 2 stay in a thread's registers,
+// strides 4..128 within a wavefront (shuffles of the partner lane), and only
+// strides of 256 and more go through LDS with workgroup barriers.
+//   tiles: one wavefront per 256 circuits sorts its tile; with one tile it
+//          writes the result, otherwise its first k keys (k <= 64);
+//   merge: one workgroup per population sorts the tiles' candidates;
+//   whole: one workgroup per population sorts all P keys (k > 64).
+// Spreading the tiles over the GPU keeps the common case (k = 32 of 4096)
+// off a single compute unit.
+constexpr int ELITE_TILE = 256;
+constexpr int ELITE_MAX_TILE_K = 64;
+enum EliteMode { ELITE_TILES = 0, ELITE_MERGE = 1, ELITE_WHOLE = 2 };
 
 __device__ __forceinline__ unsigned long long cas_keep(unsigned long long v, unsigned long long p,
                                                        bool lower, bool asc) {
@@ -821,33 +829,27 @@ __device__ __forceinline__ unsigned long long cas_keep(unsigned long long v, uns
     return take_min ? (p < v ? p : v) : (p > v ? p : v);
 }
 
-__global__ __launch_bounds__(1024) void elite_select_kernel(LoopArgs a, const float* __restrict__ f,
-                                                           int k, int32_t* __restrict__ idx_out) {
-    __shared__ unsigned long long key[ELITE_KEYS];
-    const int i = blockIdx.x, P = a.P, tid = threadIdx.x;
-    unsigned long long v[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int e = 4 * tid + q;
-        unsigned long long kv = ~0ull;
-        if (e < P) {
-            const float x = f[(size_t)i * P + e];
-            // non-negative floats order like their bit patterns; NaN last
-            const uint32_t ord = (x >= 0.0f) ? __float_as_uint(x) + 1u : 0u;
-            kv = ((unsigned long long)(0xFFFFFFFFu - ord) << 32) | (uint32_t)e;
-        }
-        v[q] = kv;
-    }
-    for (int size = 2; size <= ELITE_KEYS; size <<= 1) {
+__device__ __forceinline__ unsigned long long elite_key(float x, uint32_t c) {
+    // non-negative floats order like their bit patterns; NaN last
+    const uint32_t ord = (x >= 0.0f) ? __float_as_uint(x) + 1u : 0u;
+    return ((unsigned long long)(0xFFFFFFFFu - ord) << 32) | c;
+}
+
+// Ascending bitonic sort of the 4 * blockDim.x keys held four per thread
+// (key 4 * tid + q in v[q]); blockDim.x is a power of two >= 64 and lds holds
+// 4 * blockDim.x keys.
+__device__ __forceinline__ void bitonic_sort4(unsigned long long v[4], unsigned long long* lds) {
+    const int tid = threadIdx.x, nk = 4 * (int)blockDim.x;
+    for (int size = 2; size <= nk; size <<= 1) {
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
             if (stride >= 256) {
 #pragma unroll
-                for (int q = 0; q < 4; ++q) key[4 * tid + q] = v[q];
+                for (int q = 0; q < 4; ++q) lds[4 * tid + q] = v[q];
                 __syncthreads();
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int e = 4 * tid + q;
-                    v[q] = cas_keep(v[q], key[e ^ stride], (e & stride) == 0, (e & size) == 0);
+                    v[q] = cas_keep(v[q], lds[e ^ stride], (e & stride) == 0, (e & size) == 0);
                 }
                 __syncthreads();
             } else if (stride >= 4) {
@@ -870,10 +872,37 @@ __global__ __launch_bounds__(1024) void elite_select_kernel(LoopArgs a, const fl
             }
         }
     }
+}
+
+// T: tiles per population; cand: [I][T][k] keys (tiles and merge, T > 1).
+template <int MODE>
+__global__ __launch_bounds__(1024) void elite_select_kernel(LoopArgs a, const float* __restrict__ f,
+                                                           int k, int T, unsigned long long* cand,
+                                                           int32_t* __restrict__ idx_out) {
+    extern __shared__ unsigned long long elite_lds[];
+    const int tid = threadIdx.x, P = a.P;
+    const int i = MODE == ELITE_TILES ? (int)blockIdx.x / T : (int)blockIdx.x;
+    const int t = MODE == ELITE_TILES ? (int)blockIdx.x % T : 0;
+    unsigned long long v[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int e = 4 * tid + q;
-        if (e < k) idx_out[(size_t)i * k + e] = (int32_t)(v[q] & 0xFFFFFFFFu);
+        unsigned long long kv = ~0ull;
+        if constexpr (MODE == ELITE_MERGE) {
+            if (e < T * k) kv = cand[(size_t)i * T * k + e];
+        } else {
+            const int c = t * ELITE_TILE + e;     // (whole: t = 0, e over the population)
+            if (c < P) kv = elite_key(f[(size_t)i * P + c], (uint32_t)c);
+        }
+        v[q] = kv;
+    }
+    bitonic_sort4(v, elite_lds);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int e = 4 * tid + q;
+        if (e >= k) continue;
+        if (MODE == ELITE_TILES && T > 1) cand[((size_t)i * T + t) * k + e] = v[q];
+        else idx_out[(size_t)i * k + e] = (int32_t)(v[q] & 0xFFFFFFFFu);
     }
 }
 
@@ -1054,8 +1083,25 @@ hipError_t launch_ga_update(const LoopArgs& a, uint64_t gen, const float* f, hip
     return hipGetLastError();
 }
 
-hipError_t launch_elite_select(const LoopArgs& a, const float* f, int k, int32_t* idx, hipStream_t s) {
-    elite_select_kernel<<<a.I, 1024, 0, s>>>(a, f, k, idx);
+size_t elite_cand_keys(int I, int P) {
+    return (size_t)I * (size_t)((P + ELITE_TILE - 1) / ELITE_TILE) * ELITE_MAX_TILE_K;
+}
+
+hipError_t launch_elite_select(const LoopArgs& a, const float* f, int k, int32_t* idx,
+                               unsigned long long* cand, hipStream_t s) {
+    auto np2 = [](int x) { int v = 1; while (v < x) v <<= 1; return v; };
+    const int T = (a.P + ELITE_TILE - 1) / ELITE_TILE;
+    if (T == 1 || k <= ELITE_MAX_TILE_K) {
+        elite_select_kernel<ELITE_TILES><<<a.I * T, ELITE_TILE / 4, ELITE_TILE * 8, s>>>(a, f, k, T, cand,
+                                                                                          idx);
+        if (T > 1) {
+            const int nk = std::max(ELITE_TILE, np2(T * k));
+            elite_select_kernel<ELITE_MERGE><<<a.I, nk / 4, (size_t)nk * 8, s>>>(a, f, k, T, cand, idx);
+        }
+    } else {
+        const int nk = std::max(ELITE_TILE, np2(a.P));
+        elite_select_kernel<ELITE_WHOLE><<<a.I, nk / 4, (size_t)nk * 8, s>>>(a, f, k, T, nullptr, idx);
+    }
     return hipGetLastError();
 }
 

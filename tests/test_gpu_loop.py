@@ -308,10 +308,13 @@ def test_elite_recheck(dev, oracle, n):
             assert abs(f64[i, e] - fi[idx[i, e]]) <= 1e-5
 
 
-@pytest.mark.parametrize("P,k", [(4096, 4096), (3000, 1000), (1, 1)])
+@pytest.mark.parametrize("P,k", [(4096, 4096), (3000, 1000), (1, 1), (4096, 32), (4096, 64),
+                                 (257, 64), (300, 7), (256, 256), (512, 65)])
 def test_elite_selection_orders_whole_populations(dev, oracle, P, k):
     # the selection sorts (f desc, index asc) over every stage of its network:
-    # in-register, in-wavefront and through LDS; ties are frequent here
+    # in-register, in-wavefront and through LDS; ties are frequent here.  One
+    # tile of 256 circuits, tiles whose top k (<= 64) are merged (a partial
+    # last tile included), and the whole-population sort for larger k
     n, L, I = 3, 6, 2
     ctx, T = qeqea_ctx(dev, oracle, n, L, P, I, 77 + P)
     slots, gates = ctx.sample(0)
