@@ -896,7 +896,9 @@ __device__ __forceinline__ bool run_lds_path(float2* M, uint4* gt, const float* 
             auto cv = [&](const uint32_t T0, const uint4 E, auto&& next) {
                 cv_gate(T0, E.x, bits_f(E.y), E.z, E.w, next);
             };
-            // two gates per iteration, each entry loaded one gate ahead
+            // whole pairs of gates per iteration (no exit test between them),
+            // each entry loaded one gate ahead; the second prefetch is clamped
+            // to the last entry, and an odd last gate runs after the loop
             uint32_t ta = 0u, tb2 = 0u;
             uint4 ea = make_uint4(0u, 0u, 0u, 0u), eb = ea;
             if (count > 0) { ta = gw[0]; ea = gt[1]; }
@@ -904,11 +906,16 @@ __device__ __forceinline__ bool run_lds_path(float2* M, uint4* gt, const float* 
             // inside it only the data reads are waited for (the entry of the
             // next gate is issued ahead of them and arrives first)
             __builtin_amdgcn_s_waitcnt(0xC07F);
-            for (int e = 0; e < count; e += 2) {
-                cv(ta, ea, [&] { if (e + 1 < count) { tb2 = gw[8 * (e + 1)]; eb = gt[2 * (e + 1) + 1]; } });
+            int e = 0;
+            for (; e + 2 <= count; e += 2) {
+                cv(ta, ea, [&] { tb2 = gw[8 * (e + 1)]; eb = gt[2 * (e + 1) + 1]; });
                 wave_lds_fence();
-                if (e + 1 >= count) break;
-                cv(tb2, eb, [&] { if (e + 2 < count) { ta = gw[8 * (e + 2)]; ea = gt[2 * (e + 2) + 1]; } });
+                const int e2 = min(e + 2, count - 1);
+                cv(tb2, eb, [&] { ta = gw[8 * e2]; ea = gt[2 * e2 + 1]; });
+                wave_lds_fence();
+            }
+            if (e < count) {
+                cv(ta, ea, [] {});
                 wave_lds_fence();
             }
         } else if constexpr (W == 1) {
