@@ -928,8 +928,10 @@ __device__ __forceinline__ bool run_lds_path(float2* M, uint4* gt, const float* 
                 if constexpr (ANG) gt[ES * rank + 2] = G2;
             }
             wave_lds_fence();
-            // two gates per iteration, each entry loaded one gate ahead (the
-            // unrolled pair keeps the prefetched entries in place)
+            // whole pairs of gates per iteration, each entry loaded one gate
+            // ahead (the unrolled pair keeps the prefetched entries in place;
+            // the second prefetch is clamped to the last entry, an odd last
+            // gate runs after the loop)
             uint4 a0e = make_uint4(0u, 0u, 0u, 0u), a1e = a0e, a2e = a0e, b0e = a0e, b1e = a0e, b2e = a0e;
             auto fetch = [&](int e, uint4& x0, uint4& x1, uint4& x2) {
                 x0 = gt[ES * e];
@@ -937,11 +939,16 @@ __device__ __forceinline__ bool run_lds_path(float2* M, uint4* gt, const float* 
                 if constexpr (ANG) x2 = gt[ES * e + 2];
             };
             if (count > 0) fetch(0, a0e, a1e, a2e);
-            for (int e = 0; e < count; e += 2) {
-                apply(a0e, a1e, a2e, [&] { if (e + 1 < count) fetch(e + 1, b0e, b1e, b2e); });
+            int e = 0;
+            for (; e + 2 <= count; e += 2) {
+                apply(a0e, a1e, a2e, [&] { fetch(e + 1, b0e, b1e, b2e); });
                 wave_lds_fence();
-                if (e + 1 >= count) break;
-                apply(b0e, b1e, b2e, [&] { if (e + 2 < count) fetch(e + 2, a0e, a1e, a2e); });
+                const int e2 = min(e + 2, count - 1);
+                apply(b0e, b1e, b2e, [&] { fetch(e2, a0e, a1e, a2e); });
+                wave_lds_fence();
+            }
+            if (e < count) {
+                apply(a0e, a1e, a2e, [] {});
                 wave_lds_fence();
             }
         } else if constexpr (NCV) {
