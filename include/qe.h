@@ -281,7 +281,8 @@ qe_status qe_run_graph(qe_ctx* ctx, uint64_t first_gen, int32_t n_gen, float* f_
  * that generation's fitness; angles_dev is ignored).  angles_dev: the
  * circuits' angles (Ising library, required with gates_dev), NULL
  * otherwise.  idx_dev [I][k] (int32, circuit index within the instance),
- * f64_dev [I][k].  1 <= k <= P <= 4096. */
+ * f64_dev [I][k].  1 <= k <= P <= 4096.  The selection uses a workspace the
+ * context owns, so re-checks on one context must not overlap (one stream). */
 qe_status qe_elite_recheck(qe_ctx* ctx, const uint16_t* gates_dev, const uint32_t* angles_dev,
                            const float* f_dev, int32_t k, int32_t* idx_dev, double* f64_dev,
                            void* stream);
