@@ -1,0 +1,155 @@
+"""Parity at the benchmark sizes, in the launch configurations the benchmark
+times, on its seeded synthetic workloads:
+
+* n=4 QEQEA, 4096 circuits x 30 gates: one generation through the HIP graph
+  (fused sampling + fitness kernel, then the update), teacher-forced against
+  the oracle: slots, gates and the whole encoding state bit for bit, the
+  fitness of every circuit within the FP32 bar;
+* n=5 QEQEA, 1024 populations x 64 circuits x 40 gates: the fused kernel's
+  first generation against the oracle's sampling (bit for bit) and fitness
+  (every circuit), and against the evaluation kernel (bit for bit);
+* n=6, 8192 circuits x 48 gates: the FP32 path on every circuit within the
+  FP32 bar, the BF16 hi+lo MFMA path within its stated loose bounds;
+* 16384 circuits of widths 3..6 and lengths 8..64 in one mixed-width launch
+  (the cost-sorted queue), every circuit within the FP32 bar.
+
+Targets and expected values come from the oracle only."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from paper_1809_11134_amd import inputs, qe
+
+pytestmark = pytest.mark.gpu
+TOL32 = 1e-5
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    qe.load()
+    return torch.device("cuda", 0)
+
+
+def state_of(ctx):
+    torch.cuda.synchronize()
+    return {k: ctx.state(k).cpu().numpy() for k in ("theta", "qutrit", "best_f", "best_theta",
+                                                    "best_qutrit")}
+
+
+def oracle_from(oracle, ctx, st):
+    o = oracle.QeqeaState(ctx.n, ctx.L, ctx.P, ctx.I, ctx.problem.seed)
+    o.theta[:] = st["theta"].view(np.uint32)
+    o.qutrit[:] = st["qutrit"]
+    o.best_f[:] = st["best_f"]
+    o.best_theta[:] = st["best_theta"].view(np.uint32)
+    o.best_qutrit[:] = st["best_qutrit"]
+    return o
+
+
+def oracle_fitness(oracle, n, gates, T, P):
+    """FP64 fitness of every circuit (rows of gates; circuit c uses target c // P)."""
+    B, L = gates.shape
+    N2 = 1 << (2 * n)
+    return oracle.eval_batch(np.full(B, n, np.int8), np.arange(B + 1, dtype=np.int32) * L,
+                             np.ascontiguousarray(gates).ravel(),
+                             (np.arange(B, dtype=np.int64) // P) * N2, T.reshape(-1))[:, 0]
+
+
+def test_qeqea_n4_bench_generation_through_graph(dev, oracle):
+    w = inputs.workload_qeqea_n4()
+    n, L, P, I, seed = w["n"], w["L"], w["P"], w["instances"], w["seed"]
+    print(f"full size {w['name']}: graph generation against the oracle", flush=True)
+    T = np.stack([oracle.unitary(n, g) for g in w["target_gates"]])
+    ctx = qe.Context(n, w["lib"], qe.ALG_QEQEA, L, P, I, prob_mutation=0.1,
+                     mutation_range=math.pi / 4, seed=seed)
+    ctx.set_targets(torch.from_numpy(T).to(dev))
+    ctx.run_graph(0, 5)                      # move the state off its initial values
+    o = oracle_from(oracle, ctx, state_of(ctx))
+    gen = 5
+    rs, rg = o.sample(gen)
+    hist = torch.empty((1, I * P), dtype=torch.float32, device=dev)
+    ctx.run_graph(gen, 1, hist)
+    fh = hist[0].cpu().numpy()
+    ref = oracle_fitness(oracle, n, rg, T, P)
+    assert np.abs(fh - ref).max() <= TOL32
+    o.update(gen, 0.1, math.pi / 4, rs, fh)
+    st = state_of(ctx)
+    assert np.array_equal(o.theta, st["theta"].view(np.uint32))
+    assert np.array_equal(o.best_theta, st["best_theta"].view(np.uint32))
+    assert np.array_equal(o.best_f.view(np.uint32), st["best_f"].view(np.uint32))
+    assert np.array_equal(o.qutrit.view(np.uint32), st["qutrit"].view(np.uint32))
+    assert np.array_equal(o.best_qutrit.view(np.uint32), st["best_qutrit"].view(np.uint32))
+    # the next generation's fused kernel (as qe_sample_eval launches it)
+    slots, gates, f = ctx.sample_eval(gen + 1)
+    rs2, rg2 = o.sample(gen + 1)
+    assert np.array_equal(slots.cpu().numpy().view(np.uint32), rs2)
+    assert np.array_equal(gates.cpu().numpy().view(np.uint16), rg2)
+    assert torch.equal(f, ctx.eval_population(gates))
+    assert qe.device_errors() == 0
+    ctx.close()
+
+
+def test_qeqea_n5_bench_first_generation(dev, oracle):
+    w = inputs.workload_qeqea_n5()
+    n, L, P, I, seed = w["n"], w["L"], w["P"], w["instances"], w["seed"]
+    print(f"full size {w['name']}: fused kernel against the oracle", flush=True)
+    T = np.stack([oracle.unitary(n, g) for g in w["target_gates"]])
+    ctx = qe.Context(n, w["lib"], qe.ALG_QEQEA, L, P, I, prob_mutation=0.1,
+                     mutation_range=math.pi / 4, seed=seed)
+    ctx.set_targets(torch.from_numpy(T).to(dev))
+    slots, gates, f = ctx.sample_eval(0)
+    o = oracle.QeqeaState(n, L, P, I, seed)   # the initial encoding, built by the oracle
+    rs, rg = o.sample(0)
+    assert np.array_equal(slots.cpu().numpy().view(np.uint32), rs)
+    assert np.array_equal(gates.cpu().numpy().view(np.uint16), rg)
+    assert torch.equal(f, ctx.eval_population(gates))
+    assert np.abs(f.cpu().numpy() - oracle_fitness(oracle, n, rg, T, P)).max() <= TOL32
+    # a few graph generations on top: finite fitness in [0, 1], FP64 elites agree
+    hist = torch.empty((3, I * P), dtype=torch.float32, device=dev)
+    ctx.run_graph(0, 3, hist)
+    hh = hist.cpu().numpy()
+    assert np.all(np.isfinite(hh)) and hh.min() >= 0.0 and hh.max() <= 1.0
+    idx, f64 = ctx.elite_recheck(None, hist[2], 32)
+    ih = idx.cpu().numpy()
+    f32 = hh[2].reshape(I, P)[np.arange(I)[:, None], ih]
+    assert np.abs(f32 - f64.cpu().numpy()).max() <= TOL32
+    assert qe.device_errors() == 0
+    ctx.close()
+
+
+def test_precision_n6_bench_batch(dev, oracle):
+    w = inputs.workload_precision_n6()
+    n, L, P = w["n"], w["L"], w["P"]
+    print(f"full size {w['name']}: FP32 and BF16 MFMA paths against the oracle", flush=True)
+    T = oracle.unitary(n, w["target_gates"])
+    gates = w["gates"]
+    ref = oracle_fitness(oracle, n, gates, T[None], P)
+    g = torch.from_numpy(gates.astype(np.int16)).to(dev)
+    Td = torch.from_numpy(T).to(dev)
+    for path, tol in ((qe.PATH_FP32, TOL32), (qe.PATH_MFMA_BF16, 2e-2)):
+        f, _, _ = qe.eval_fitness(g, Td, n=n, L=L, target_stride=0, path=path)
+        err = np.abs(f.cpu().numpy().astype(np.float64) - ref)
+        print(f"path {path}: max |df| {err.max():.2e}", flush=True)
+        assert err.max() <= tol, path
+    assert qe.device_errors() == 0
+
+
+def test_uneven_bench_batch(dev, oracle):
+    w = inputs.workload_uneven()
+    nq, goff, gates = w["nq"], w["goff"], w["gates"]
+    print(f"full size {w['name']}: {len(nq)} circuits in one mixed-width launch", flush=True)
+    tmats = [oracle.unitary(n, tg) for n, tg in w["target_gates"]]
+    toff_pop = np.cumsum([0] + [m.size for m in tmats])[:-1]
+    toff = toff_pop[w["target_index"]].astype(np.int64)
+    flat = np.concatenate([m.ravel() for m in tmats])
+    ref = oracle.eval_batch(nq, goff, gates, toff, flat)
+    f, _, _ = qe.eval_fitness(torch.from_numpy(gates.astype(np.int16)).to(dev),
+                              torch.from_numpy(flat).to(dev),
+                              nq=torch.from_numpy(nq).to(dev), goff=torch.from_numpy(goff).to(dev),
+                              toff=torch.from_numpy(toff).to(dev), target_stride=None)
+    assert np.abs(f.cpu().numpy() - ref[:, 0]).max() <= TOL32
+    assert qe.device_errors() == 0
