@@ -169,19 +169,33 @@ __global__ __launch_bounds__(1024) void mix_bucket_kernel(BatchArgs a, int32_t* 
     __syncthreads();
     for (int b = tid; b < a.B; b += blockDim.x) atomicAdd(&cnt[mix_key(a, b)], 1);
     __syncthreads();
+    static_assert(K <= 128, "two keys per lane of one wavefront");
+    if (tid < 64) {
+        // exclusive prefix sum of the K counts over one wavefront, two per lane
+        const int k0 = 2 * tid;
+        const int c0 = k0 < K ? cnt[k0] : 0, c1 = k0 + 1 < K ? cnt[k0 + 1] : 0;
+        int incl = c0 + c1;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int o = __shfl_up(incl, d, 64);
+            if (tid >= d) incl += o;
+        }
+        const int excl = incl - c0 - c1;
+        if (k0 < K) cursor[k0] = excl;
+        if (k0 + 1 < K) cursor[k0 + 1] = excl + c0;
+    }
+    __syncthreads();
     if (tid == 0) {
-        int pos = 0, item = 0;
+        // per width: first order position, first item, count (every circuit
+        // has a key, so the last width ends at B)
+        int item = 0;
         for (int k = 0; k < MIX_BUCKETS; ++k) {
+            const int pos = cursor[k * MIX_LCLASSES];
+            const int end = k + 1 < MIX_BUCKETS ? cursor[(k + 1) * MIX_LCLASSES] : a.B;
             meta[k] = pos;
             meta[8 + k] = item;
-            int c = 0;
-            for (int l = 0; l < MIX_LCLASSES; ++l) {
-                cursor[k * MIX_LCLASSES + l] = pos + c;
-                c += cnt[k * MIX_LCLASSES + l];
-            }
-            meta[16 + k] = c;
-            pos += c;
-            item += (c + mix_per_item(k) - 1) / mix_per_item(k);
+            meta[16 + k] = end - pos;
+            item += (end - pos + mix_per_item(k) - 1) / mix_per_item(k);
         }
         meta[8 + MIX_BUCKETS] = item;
     }
