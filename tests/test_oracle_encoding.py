@@ -259,3 +259,199 @@ def test_ga_update_invariants(oracle):
     g3 = oracle.ga_update(n, lib, L, P, I, 41, 0, 0.0, 1.0, f, g0)
     assert set(int(x) for x in g3.ravel()) <= tab
     assert not np.array_equal(g3, sel_src)
+
+
+# ------------------------------------------------ adaptive mutation (Sec. IV-F)
+# With pm = 1 every individual mutates, in qubit or qutrit mode (equiprobably).
+# A state with no used slot (every circuit fitness negative) leaves elitism
+# out, so the change from the call is the mutation alone.  Qutrits start as
+# (1, 1, 1) (real), so that every one-parameter step of Eq. 12 that is not
+# the identity changes a component, and both the parameter j and the step
+# index a can be read back from the result.
+def _mutate_once(oracle, seg, n=3, L=16, P=256, gen=0, seed=77, mrange=math.pi / 4):
+    st = oracle.QeqeaState(n, L, P, 1, seed=seed)
+    st.best_f[:] = np.float32(seg)
+    st.qutrit[:] = np.tile(np.array([1, 0, 1, 0, 1, 0], np.float32), n * L * P)
+    st.best_qutrit[:] = st.qutrit
+    before = st.copy()
+    st.update(gen, 1.0, mrange, np.zeros((P, L), np.uint32), np.full(P, -1, np.float32))
+    return before, st
+
+
+def _individual_slots(n, L, P, ind, R):
+    return np.array([r * L * P + ind * L + pos for r in range(R) for pos in range(L)])
+
+
+def _read_su3_step(q):
+    """(j, a) of a one-parameter step applied to (1, 1, 1), or (None, 0)
+    when the qutrit is unchanged (j >= 5, or a = 0)."""
+    one = np.array([1, 0, 1, 0, 1, 0], np.float32)
+    if np.array_equal(q, one):
+        return None, 0
+    z = q[0::2].astype(float) + 1j * q[1::2].astype(float)
+    same = [z[k] == 1 for k in range(3)]
+    if np.any(q[1::2] != 0):                       # a phase step
+        j = 3 if not same[0] else 4
+        c, s = (z[0].real, z[0].imag) if j == 3 else (z[1].real, z[1].imag)
+        return j, int(round((math.atan2(s, c) % (2 * math.pi)) / (2 * math.pi) * 4096)) % 4096
+    if same[2]:
+        j, A, B = 0, z[0].real, z[1].real          # (c + s, c - s)
+    elif same[1]:
+        j, A, B = 1, z[0].real, z[2].real
+    else:
+        j, A, B = 2, z[2].real, z[1].real
+    c, s = (A + B) / 2, (A - B) / 2
+    return j, int(round(math.atan2(s, c) / (math.pi / 2) * 4096))
+
+
+def test_mutation_full_fitness_changes_nothing(oracle):
+    # Sec. IV-F: the mutation is proportional to the error; a slot whose
+    # segment fitness is 1 does not move, in either mode
+    before, after = _mutate_once(oracle, 1.0)
+    assert np.array_equal(after.theta, before.theta)
+    assert np.array_equal(after.qutrit, before.qutrit)
+    assert np.array_equal(after.best_f, before.best_f)
+
+
+@pytest.mark.parametrize("seg", [-1.0, 0.0, 0.25, 0.9])
+def test_qutrit_step_scales_with_error(oracle, seg):
+    # Eq. 12 with one parameter j (of 8) set to a * domain / 4096, with the
+    # step index a uniform on [0, (1 - segFit) * 4096] (segFit of an unused
+    # slot is 0).  The qutrit-mode individuals are the ones whose angles did
+    # not move.
+    n, L, P = 3, 16, 256
+    R = n * n
+    before, after = _mutate_once(oracle, seg, n, L, P)
+    om = 1.0 - max(seg, 0.0)
+    amax = math.floor(float(np.float32(om)) * 4096)
+    qmode, js, avals = 0, [], []
+    for ind in range(P):
+        sl = _individual_slots(n, L, P, ind, R)
+        if np.any(after.theta[sl] != before.theta[sl]):
+            continue
+        qmode += 1
+        for s in sl[sl < n * L * P]:
+            j, a = _read_su3_step(after.qutrit[6 * s:6 * s + 6])
+            js.append(-1 if j is None else j)
+            if j is not None:
+                avals.append(a)
+    # the mode is a fair coin per individual
+    assert abs(qmode - P / 2) <= 5 * math.sqrt(P / 4)
+    js = np.array(js)
+    N = len(js)
+    # j uniform over the 8 parameters: each of j = 0..4 one eighth, the three
+    # phases that only multiply sine terms (identity) three eighths
+    counts = np.array([(js == j).sum() for j in range(5)] + [(js == -1).sum()], float)
+    exp = N * np.array([1, 1, 1, 1, 1, 3]) / 8.0
+    assert ((counts - exp) ** 2 / exp).sum() < 30          # 5 dof, p ~ 1e-5
+    av = np.array(avals, float)
+    assert av.min() >= 0 and av.max() <= amax
+    assert av.max() >= 0.95 * amax                          # the range is filled
+    # uniform on [0, amax]: eight equal bins
+    h = np.bincount(np.minimum((av / (amax + 1) * 8).astype(int), 7), minlength=8)
+    e = len(av) / 8.0
+    assert ((h - e) ** 2 / e).sum() < 35                    # 7 dof, p ~ 1e-5
+
+
+@pytest.mark.parametrize("seg", [-1.0, 0.0, 0.25, 0.9])
+def test_qubit_step_is_error_times_range(oracle, seg):
+    # Qubit mode: every slot of the individual moves by +-(1 - segFit) *
+    # mutationRange (angles as u32 turn fractions), the sign a fair coin
+    n, L, P = 3, 16, 256
+    R = n * n
+    mrange = math.pi / 4
+    before, after = _mutate_once(oracle, seg, n, L, P, mrange=mrange)
+    om = 1.0 - max(seg, 0.0)
+    step = om * mrange / (2 * math.pi) * 2 ** 32
+    plus = minus = 0
+    for ind in range(P):
+        sl = _individual_slots(n, L, P, ind, R)
+        dth = (after.theta[sl].astype(np.int64) - before.theta[sl].astype(np.int64)) % (1 << 32)
+        if not np.any(dth):
+            continue                                         # qutrit mode
+        up = dth < (1 << 31)
+        mag = np.where(up, dth, (1 << 32) - dth)
+        assert np.all(np.abs(mag - step) <= step * 2 ** -20 + 1)
+        plus += int(up.sum())
+        minus += int((~up).sum())
+    tot = plus + minus
+    assert tot > 0 and abs(plus - tot / 2) <= 5 * math.sqrt(tot / 4)
+
+
+# ------------------------------------------------------- GA rates (Sec. V-B)
+def _distinct_population(oracle, I, P, L, n=6, lib=1):
+    # every parent has a different gene at every position (n = 6, library
+    # {H, T, CNOT, CV, CV+}: 102 instances >= P), so any exchange of genes
+    # between two children is visible
+    tab = oracle.lib_table(lib, n)
+    assert P <= len(tab)
+    g = np.zeros((I * P, L), np.uint16)
+    for i in range(I):
+        for k in range(P):
+            for pos in range(L):
+                g[i * P + k, pos] = tab[(k + 7 * pos + 3 * i) % len(tab)]
+    return g, len(tab)
+
+
+def test_ga_equal_fitness_selects_every_parent_once(oracle):
+    I, P, L = 4, 64, 10
+    g0, _ = _distinct_population(oracle, I, P, L)
+    f = np.full(I * P, 0.5, np.float32)
+    g1 = oracle.ga_update(6, 1, L, P, I, 5, 0, 0.0, 0.0, f, g0)
+    assert np.array_equal(g1, g0)
+
+
+def test_ga_two_point_crossover_rate(oracle):
+    # pc = 0.9: a pair is crossed with probability pc; the exchanged genes of
+    # a crossed pair are one contiguous run [lo, hi) between two cut points
+    # drawn uniformly from 0..L (equal cuts exchange nothing)
+    I, P, L, pc = 32, 64, 10, 0.9
+    g0, _ = _distinct_population(oracle, I, P, L)
+    f = np.full(I * P, 0.5, np.float32)
+    half = P // 2
+    visible, lengths, pairs = 0, [], 0
+    for gen in range(4):
+        g2 = oracle.ga_update(6, 1, L, P, I, 9, gen, pc, 0.0, f, g0)
+        for i in range(I):
+            for j in range(1, half):
+                a, b = i * P + j, i * P + j + half
+                diff = np.nonzero(g2[a] != g0[a])[0]
+                assert np.array_equal(diff, np.nonzero(g2[b] != g0[b])[0])
+                assert np.array_equal(g2[a][diff], g0[b][diff])
+                assert np.array_equal(g2[b][diff], g0[a][diff])
+                pairs += 1
+                if len(diff):
+                    assert diff[-1] - diff[0] + 1 == len(diff)   # one contiguous run
+                    visible += 1
+                    lengths.append(len(diff))
+    p_vis = pc * (1 - 1 / (L + 1))
+    assert abs(visible - pairs * p_vis) <= 5 * math.sqrt(pairs * p_vis * (1 - p_vis))
+    # |a - b| for two uniform cuts in 0..L, given a != b: mean (L + 2) / 3
+    d = np.arange(1, L + 1)
+    pd = 2.0 * (L + 1 - d) / (L + 1) ** 2
+    pd /= pd.sum()
+    mean, var = (d * pd).sum(), ((d - (d * pd).sum()) ** 2 * pd).sum()
+    assert abs(np.mean(lengths) - mean) <= 5 * math.sqrt(var / len(lengths))
+    assert abs(mean - (L + 2) / 3) < 1e-12
+
+
+def test_ga_gene_mutation_rate(oracle):
+    # pg = 1/L: each gene is redrawn with probability pg, uniformly from the
+    # library (so it stays the same with probability 1/|library|); child 0
+    # is the best parent, unchanged
+    I, P, L = 32, 64, 10
+    pg = 1.0 / L
+    g0, nl = _distinct_population(oracle, I, P, L)
+    tab = set(int(x) for x in oracle.lib_table(1, 6))
+    f = np.full(I * P, 0.5, np.float32)
+    changed, genes = 0, 0
+    for gen in range(4):
+        g3 = oracle.ga_update(6, 1, L, P, I, 13, gen, 0.0, pg, f, g0)
+        assert set(int(x) for x in g3.ravel()) <= tab
+        for i in range(I):
+            assert np.array_equal(g3[i * P], g0[i * P])
+            blk = slice(i * P + 1, (i + 1) * P)
+            changed += int((g3[blk] != g0[blk]).sum())
+            genes += (P - 1) * L
+    p = pg * (1 - 1 / nl)
+    assert abs(changed - genes * p) <= 5 * math.sqrt(genes * p * (1 - p))

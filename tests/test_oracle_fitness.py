@@ -174,17 +174,46 @@ def _best_over_sequences(oracle, T, length):
     return out[:, 0]
 
 
+def _argmax_count(f, m):
+    return int((f >= m - 1e-9).sum())
+
+
 def test_brute_force_ncv_costs(oracle):
-    # Exhaustive search over <= 4 gates (I pads shorter circuits): Peres is
-    # reached exactly with 4 NCV gates, Toffoli is not reached (its NCV cost
-    # is 5).
-    f_tof = _best_over_sequences(oracle, perm_matrix(3, toffoli_fn), 4)
-    f_per = _best_over_sequences(oracle, perm_matrix(3, peres_fn), 4)
-    assert f_tof.max() < 1 - 1e-6
-    assert f_per.max() == pytest.approx(1, abs=1e-12)
+    # Exhaustive search over <= 3 and <= 4 gates of the 22 NCV instances on 3
+    # wires (I pads shorter circuits).  Toffoli (NCV cost 5) is not reached:
+    # the best circuits score exactly the closed form of a CV gate against
+    # the identity, 1 - sqrt(1 - sqrt(10)/4) (the best partial realisation
+    # agrees with Toffoli on the 6 basis states whose controls are not both
+    # set and applies a CV-like block to the other two), reached by 36
+    # sequences of length 3 and 544 of length 4.  Peres (NCV cost 4) is
+    # reached by exactly 8 sequences of 4 gates and not within 3 (best: the
+    # same CV value, 14 sequences).  Among the 10 648 length-3 sequences the
+    # fitness against Toffoli takes 52 distinct values.
+    best_cv = 1 - math.sqrt(1 - math.sqrt(10) / 4)
+    assert abs(best_cv - 0.542364) < 5e-7
+    f_tof3 = _best_over_sequences(oracle, perm_matrix(3, toffoli_fn), 3)
+    f_tof4 = _best_over_sequences(oracle, perm_matrix(3, toffoli_fn), 4)
     f_per3 = _best_over_sequences(oracle, perm_matrix(3, peres_fn), 3)
-    assert f_per3.max() < 1 - 1e-6
-    assert np.all(f_tof >= 0) and np.all(f_tof <= 1)
+    f_per4 = _best_over_sequences(oracle, perm_matrix(3, peres_fn), 4)
+    for f, m, cnt in ((f_tof3, best_cv, 36), (f_tof4, best_cv, 544), (f_per3, best_cv, 14),
+                      (f_per4, 1.0, 8)):
+        assert abs(f.max() - m) < 1e-12
+        assert _argmax_count(f, f.max()) == cnt
+    assert len(np.unique(np.round(f_tof3, 9))) == 52
+    assert np.all(f_tof4 >= 0) and np.all(f_tof4 <= 1)
+
+
+def test_brute_force_distinct_unitaries(oracle):
+    # The 10 648 length-3 NCV sequences on 3 wires realise 3 806 distinct
+    # unitaries, also 3 806 up to a global phase.
+    tab = oracle.lib_table(0, 3)
+    exact, upto_phase = set(), set()
+    for s in itertools.product(range(len(tab)), repeat=3):
+        U = oracle.unitary(3, tab[list(s)]).ravel()
+        exact.add((np.round(U, 9) + 0.0).tobytes())
+        k = int(np.argmax(np.abs(U) > 1e-9))
+        upto_phase.add((np.round(U * (abs(U[k]) / U[k]), 9) + 0.0).tobytes())
+    assert len(exact) == 3806 and len(upto_phase) == 3806
 
 
 def test_batch_matches_single(oracle):
