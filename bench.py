@@ -1,24 +1,32 @@
 #!/usr/bin/env python3
 """Throughput of the QEQEA circuit-fitness hot path on one MI355X.
 
-Workload (seeded, synthetic): n = 4 wires, library {I, NOT, CNOT, CV, CV+},
-one QEQEA population whose encoding is sampled into P = 4096 circuits of
-L = 30 gates per generation; target = a random reversible permutation built
-from 12 NOT/CNOT gates (the paper's targets are small reversible gates).
-A step is one generation of the whole hot path: circuit construction by
-sampling (Sec. IV-D), Eq. 11 fitness of all P circuits (FP32), segment
-fitness / elitism / adaptive mutation (Secs. IV-E.1, IV-F).  The K timed
-generations run as one HIP graph; the final FP64 re-check of the last
-generation's 32 best circuits is inside the timed region.
+Headline workload (seeded, synthetic): n = 5 wires, library {I, NOT, CNOT,
+CV, CV+}, 1024 independent QEQEA populations, each sampled into P = 64
+circuits of L = 40 gates per generation (65536 circuit evaluations per
+generation); each population's target is a random reversible permutation
+built from 16 NOT/CNOT gates (the paper's targets are small reversible
+gates).  A step is one generation of the whole hot path: circuit
+construction by sampling the encoding (Sec. IV-D, Eq. 10, qutrit
+measurement), Eq. 11 fitness of every circuit (FP32 per-gate path), segment
+fitness, elitism and adaptive mutation (Secs. IV-E.1, IV-F, Eq. 12).  K
+generations run as one HIP graph followed by the FP64 re-check of each
+population's 32 best circuits of the last generation; after W warm-up
+generations the same graph and re-check run once untimed, then three timed
+replays (each exactly K generations plus the re-check, bracketed by device
+synchronisations and HIP events) give the median.
 
 Prints one JSON line (the metric is circuit-fitness evaluations per second)
 with a roofline entry for the dominant kernel (the fused sampling + fitness
-kernel, timed per launch with HIP events) and the CPU oracle's rate on a
-bounded sample of the same workload.  The "secondary" object adds the other
-workloads of the study: the n=6 precision study (FP32 against the bf16/fp16
-hi+lo MFMA paths, with their fitness error against the FP64 path, elite
-top-32 agreement and Kendall tau), 1024 QEQEA populations at n=5, and an
-uneven batch of widths 3..6 in one launch.
+kernel, against the LDS bandwidth measured by a probe kernel in the same
+run) and one for the update kernel (against HBM), each timed launch by launch
+with HIP events on the launch stream, and the CPU oracle's rate on a bounded
+sample of the same workload on one host core and on all of them.  The
+"secondary" object adds the other workloads of the study: the n=6 precision
+study (FP32 against the bf16/fp16 hi+lo MFMA paths, with their fitness error
+against the FP64 path, elite top-32 agreement and Kendall tau), one n=4
+population of 4096 circuits, a mixed-width GA batch, and the Ising,
+phase-insensitive and dense-ablation variants.
 """
 import argparse
 import hashlib
@@ -33,7 +41,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "circuit-fitness evals/sec (n=4..6), FP32 vs BF16-MFMA at stated fitness error"
 FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X, 256 CUs x 4 SIMD x 16 lanes x 2 x 2 (packed) x 2.4 GHz
-LDS_PEAK_GBPS = 256 * 128 * 2.4   # MI355X LDS: 256 CUs x 128 B/clock x 2.4 GHz = 78643 GB/s
+LDS_SPEC_GBPS = 256 * 128 * 2.4   # MI355X LDS from unit counts: 256 CUs x 128 B/clock x 2.4 GHz
+HBM_PEAK_GBPS = 8000.0            # MI355X HBM3E, published
+# The LDS peak the rooflines divide by: the best rate of the LDS probe kernel
+# measured in this run (set by main), the unit-count figure until then.
+LDS_PEAK_GBPS = LDS_SPEC_GBPS
 
 
 def log(msg):
@@ -98,43 +110,74 @@ def traffic_from_profiles(kernel_key, src_hash):
     return d.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(w, T, seconds):
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, seconds, instances=16):
     """The oracle (test infrastructure) on a bounded sample of the workload:
-    whole generations -- sampling, FP64 fitness of all P circuits (OpenMP
-    over circuits), update -- until `seconds` of wall time have passed."""
+    whole QEQEA generations of the first `instances` populations -- sampling,
+    FP64 fitness of their circuits (OpenMP over circuits), update -- for
+    about seconds / 2 on one thread, then on all the threads OpenMP gives
+    it.  The populations are independent and their encodings do not depend
+    on how many are run, so the sample is part of the same search."""
     import numpy as np
     from oracle import oracle as O
-    n, L, P = w["n"], w["L"], w["P"]
-    st = O.QeqeaState(n, L, P, 1, w["seed"])
-    nq = np.full(P, n, np.int8)
-    goff = np.arange(P + 1, dtype=np.int32) * L
-    toff = np.zeros(P, np.int64)
-    gens = 0
-    t0 = time.perf_counter()
-    while True:
-        slots, gates = st.sample(gens)
-        out = O.eval_batch(nq, goff, gates.ravel(), toff, T)
-        st.update(gens, 0.1, math.pi / 4, slots, out[:, 0].astype(np.float32))
-        gens += 1
-        el = time.perf_counter() - t0
-        if el >= seconds:
-            break
-    return dict(value=gens * P / el, unit="evals/s", cores=O.num_threads(), kind="oracle",
-                sample=f"{gens} whole QEQEA generations of the n=4, P={P}, L={L} workload "
-                       f"({gens * P} circuit evaluations in FP64 over OpenMP threads, sampling "
-                       f"and update single-threaded), {el:.1f} s")
+    n, L, P, seed = w["n"], w["L"], w["P"], w["seed"]
+    I = min(instances, w["instances"])
+    N = 1 << n
+    T = np.concatenate([O.unitary(n, np.asarray(tg, np.uint16)).reshape(1, N, N)
+                        for tg in w["target_gates"][:I]])
+    nq = np.full(I * P, n, np.int8)
+    goff = np.arange(I * P + 1, dtype=np.int32) * L
+    toff = (np.arange(I * P, dtype=np.int64) // P) * (N * N)
+    all_threads = O.num_threads()
+
+    def run(threads, budget):
+        O.set_num_threads(threads)
+        st = O.QeqeaState(n, L, P, I, seed)
+        gens = 0
+        t0 = time.perf_counter()
+        while True:
+            slots, gates = st.sample(gens)
+            out = O.eval_batch(nq, goff, gates.ravel(), toff, T)
+            st.update(gens, 0.1, math.pi / 4, slots, out[:, 0].astype(np.float32))
+            gens += 1
+            el = time.perf_counter() - t0
+            if el >= budget:
+                return gens, el
+
+    g1, e1 = run(1, seconds / 2)
+    ga, ea = run(all_threads, seconds / 2)
+    O.set_num_threads(all_threads)
+    return dict(value=ga * I * P / ea, unit="evals/s", cores=all_threads, kind="oracle",
+                value_1core=g1 * I * P / e1, cpu_model=cpu_model(), host_cpus=os.cpu_count(),
+                sample=f"whole QEQEA generations of {I} of the {w['instances']} populations of "
+                       f"{w['name']} ({I * P} circuits per generation; FP64 fitness over OpenMP "
+                       f"threads, sampling and update single-threaded): {g1} generations in "
+                       f"{e1:.1f} s on 1 thread, {ga} in {ea:.1f} s on {all_threads} threads")
 
 
 def _timed_eval(batch, path, B, reps, dev):
-    """Median duration of one qe_eval_fitness launch (preallocated output,
-    launched through the C ABI), and the output."""
+    """Median duration of one evaluation launch (preallocated output and
+    workspace, launched through the C ABI: qe_eval_fitness_ws, so that a
+    mixed-width batch takes the cost-sorted single launch), and the
+    output."""
     import ctypes
 
     import torch
     from paper_1809_11134_amd import qe
     f = torch.empty(B, dtype=torch.float32, device=dev)
-    launch = lambda: qe._call("qe_eval_fitness", None, ctypes.byref(batch), path, qe._ptr(f), None,
-                              None, qe._stream(None))
+    ws = qe.eval_workspace(B, dev)
+    launch = lambda: qe._call("qe_eval_fitness_ws", ctypes.byref(batch), path, qe._ptr(f), None,
+                              None, qe._ptr(ws), ws.numel() * 4, qe._stream(None))
     return _events_us(launch, reps), f
 
 
@@ -324,20 +367,184 @@ def secondary_dense(dev, reps=5):
     return out
 
 
-def secondary_qeqea_n5(dev, gens=20):
-    """n=5, library {I,NOT,CNOT,CV,CV+}, 1024 QEQEA populations x 64 circuits x
-    40 gates (65536 evaluations per generation): a graph of `gens` whole
-    generations plus the FP64 re-check of each population's 32 best."""
+def measure_lds_peak(dev, reps=5):
+    """LDS bandwidth of the probe kernel (16-byte accesses, no bank
+    conflicts, five 32 KB workgroups per compute unit): reads, writes, and a
+    copy within LDS; GB/s of each (median of `reps` launches)."""
+    import torch
+    from paper_1809_11134_amd import qe
+    wg, iters = 256 * 5 * 4, 256
+    sink = torch.empty(wg * 256, dtype=torch.int32, device=dev)
+    out = {}
+    for mode, name in ((0, "read_b128"), (1, "write_b128"), (2, "copy_b128")):
+        nbytes = qe.probe_lds(mode, wg, iters, sink)
+        us = _events_us(lambda: qe.probe_lds(mode, wg, iters, sink), reps)
+        out[name] = round(nbytes / (us * 1e-6) / 1e9, 1)
+    return out
+
+
+def qeqea_context(w, dev, fitness_mode=0):
+    import numpy as np
+    import torch
+    from paper_1809_11134_amd import qe
+    n, L, P, I = w["n"], w["L"], w["P"], w["instances"]
+    tg = torch.from_numpy(np.stack(w["target_gates"]).astype(np.int16)).to(dev)
+    T = qe.build_unitary(tg, n, tg.shape[1], precision=1)          # [I, N, N] complex128
+    ctx = qe.Context(n, w["lib"], qe.ALG_QEQEA, L, P, I, prob_mutation=0.1,
+                     mutation_range=math.pi / 4, seed=w["seed"], fitness_mode=fitness_mode)
+    ctx.set_targets(T)
+    return ctx
+
+
+def qeqea_graph_run(ctx, K, W, dev, reps=3, elite_k=32):
+    """W warm-up generations (their own graph), then the K-generation graph
+    and the FP64 re-check of each population's elite_k best once untimed,
+    then `reps` timed replays of both (generations continue where the last
+    run stopped).  Returns (median ms per replay, all replay times in ms,
+    the next generation index, FP32 vs FP64 error of the last re-check)."""
+    import torch
+    IP = ctx.I * ctx.P
+    f_warm = torch.empty((W, IP), dtype=torch.float32, device=dev)
+    f_hist = torch.empty((K, IP), dtype=torch.float32, device=dev)
+    ctx.graph_prepare(W, f_warm)
+    ctx.graph_prepare(K, f_hist)
+    ctx.run_graph(0, W, f_warm)
+    gen = W
+    ctx.run_graph(gen, K, f_hist)
+    ctx.elite_recheck(None, f_hist[K - 1], elite_k)
+    gen += K
+    torch.cuda.synchronize()
+    times = []
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        e0.record()
+        ctx.run_graph(gen, K, f_hist)
+        idx, f64 = ctx.elite_recheck(None, f_hist[K - 1], elite_k)
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+        gen += K
+    f32 = f_hist[K - 1].view(ctx.I, ctx.P).gather(1, idx.long()).double()
+    err = float((f32 - f64).abs().max().item())
+    return sorted(times)[len(times) // 2], times, gen, err
+
+
+def time_generation_kernels(ctx, gen0, R, dev):
+    """The two kernels of a generation as the graph launches them, timed
+    with HIP events on the launch stream: R fused sampling + fitness kernels
+    (qe_sample_eval without slot output) back to back between two events give
+    its mean duration; then R generations of the fused kernel followed by
+    the update kernel (qe_update right after it) between two events, less
+    R fused durations, give the update kernel's.  Returns (fused us, update
+    us, the last generation's gates, next generation index)."""
+    import torch
+    IP = ctx.I * ctx.P
+    gates = torch.empty((IP, ctx.L), dtype=torch.int16, device=dev)
+    f = torch.empty(IP, dtype=torch.float32, device=dev)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    gen = gen0
+    ctx.sample_eval(gen, None, gates, f, keep_slots=False)
+    ctx.update(gen, None, gates, f)
+    gen += 1
+    torch.cuda.synchronize()
+    e0.record()
+    for r in range(R):
+        ctx.sample_eval(gen + r, None, gates, f, keep_slots=False)
+    e1.record()
+    torch.cuda.synchronize()
+    fused = e0.elapsed_time(e1) / R * 1e3
+    # the update of the last of those generations, then R whole generations
+    ctx.update(gen + R - 1, None, gates, f)
+    gen += R
+    torch.cuda.synchronize()
+    e0.record()
+    for r in range(R):
+        ctx.sample_eval(gen + r, None, gates, f, keep_slots=False)
+        ctx.update(gen + r, None, gates, f)
+    e1.record()
+    torch.cuda.synchronize()
+    pair = e0.elapsed_time(e1) / R * 1e3
+    return fused, pair - fused, gates, gen + R
+
+
+def update_algorithmic_bytes(ctx, gen, dev):
+    """HBM bytes the update of generation `gen` must move (the per-unit
+    figures are those of the design notes): for every distinct used slot,
+    elitism reads its segment fitness, angle, best angle and best fitness
+    and writes two of them (24 B), a rotation slot also reads its qutrit and
+    best qutrit and writes one (72 B); every slot of a mutating individual in
+    qubit mode reads its angle and best fitness and writes the angle (12 B,
+    R*L slots), every rotation slot of one in qutrit mode reads its qutrit and
+    best fitness and writes the qutrit (52 B, n*L slots), the two modes
+    equiprobable; the generation's best circuit reads the P fitness values
+    (4 B each).  Counts come from the generation's own slots and decision
+    bitmaps (it is sampled here, then updated)."""
+    import numpy as np
+    import torch
+    IP = ctx.I * ctx.P
+    slots = torch.empty((IP, ctx.L), dtype=torch.int32, device=dev)
+    gates = torch.empty((IP, ctx.L), dtype=torch.int16, device=dev)
+    f = torch.empty(IP, dtype=torch.float32, device=dev)
+    ctx.sample_eval(gen, slots, gates, f)
+    masks = ctx.state("mutation_masks")
+    ctx.update(gen, None, gates, f)
+    torch.cuda.synchronize()
+    sl = slots.cpu().numpy().view(np.uint32).reshape(ctx.I, ctx.P * ctx.L).astype(np.int64)
+    Q = ctx.n * ctx.L * ctx.P
+    R = ctx.n + ctx.n * (ctx.n - 1)
+    inst = np.arange(ctx.I, dtype=np.int64)[:, None] * (R * ctx.L * ctx.P)
+    used = np.unique((sl + inst).ravel())
+    used_rot = int(np.count_nonzero((used % (R * ctx.L * ctx.P)) < Q))
+    mw = (ctx.P + 31) // 32
+    m = masks.cpu().numpy().view(np.uint32).reshape(2, ctx.I, mw)[gen & 1]
+    bits = np.unpackbits(m.view(np.uint8), bitorder="little").reshape(ctx.I, mw * 32)[:, :ctx.P]
+    mutated = int(bits.sum())
+    per_mut = 0.5 * (R * ctx.L * 12.0) + 0.5 * (ctx.n * ctx.L * 52.0)
+    total = used.size * 24.0 + used_rot * 72.0 + mutated * per_mut + IP * 4.0
+    return total, {"used_slots": int(used.size), "used_rotation_slots": used_rot,
+                   "mutated_individuals": mutated}
+
+
+def secondary_qeqea_n4(dev, K, W):
+    """n=4, library {I,NOT,CNOT,CV,CV+}, one QEQEA population of 4096
+    circuits x 30 gates: the graph of K generations + the FP64 re-check
+    (timed as the headline), and its fused kernel against the LDS peak."""
+    from paper_1809_11134_amd import inputs
+    w = inputs.workload_qeqea_n4()
+    ctx = qeqea_context(w, dev)
+    ms, times, gen, err = qeqea_graph_run(ctx, K, W, dev)
+    fused_us, upd_us, gates, _ = time_generation_kernels(ctx, gen, 50, dev)
+    lds = algorithmic_lds_bytes(gates.cpu().numpy(), w["n"])
+    ctx.close()
+    return {"workload": w["name"], "generations": K, "evals_per_s": K * w["P"] / (ms * 1e-3),
+            "ms_per_generation": ms / K, "replay_ms": times, "elite_fp32_vs_fp64_max_abs_df": err,
+            "fused_kernel": "population_kernel<4,1,true,false>", "fused_kernel_us": fused_us,
+            "update_kernel_us": upd_us, "algorithmic_lds_bytes_per_launch": lds,
+            "lds_frac": lds / (fused_us * 1e-6) / 1e9 / LDS_PEAK_GBPS,
+            "traffic": traffic_from_profiles("qeqea_fused_n4", source_hash())}
+
+
+def secondary_mixed_ga(dev, gens=50, reps=10):
+    """256 GA populations of 64 circuits, population i on n_i ~ U{3..6}
+    wires with genomes of L_i ~ U[8,64] gates of {H,T,CNOT,CV,CV+} and its
+    own target (16384 evaluations per generation): the graph of `gens`
+    generations (genome copy, one cost-sorted evaluation launch, the GA
+    update of every population), and the evaluation launch alone against the
+    LDS peak."""
     import numpy as np
     import torch
     from paper_1809_11134_amd import inputs, qe
-    w = inputs.workload_qeqea_n5()
-    n, L, P, I = w["n"], w["L"], w["P"], w["instances"]
-    tg = torch.from_numpy(np.stack(w["target_gates"]).astype(np.int16)).to(dev)
-    T = qe.build_unitary(tg, n, tg.shape[1], precision=1)
-    ctx = qe.Context(n, w["lib"], qe.ALG_QEQEA, L, P, I, prob_mutation=0.1,
-                     mutation_range=math.pi / 4, seed=w["seed"])
-    ctx.set_targets(T)
+    w = inputs.workload_mixed_ga()
+    P, I = w["P"], w["instances"]
+    mats = [qe.build_unitary(torch.from_numpy(tg.astype(np.int16)[None]).to(dev), n, len(tg),
+                             precision=1)[0].reshape(-1)
+            for n, tg in zip(w["widths"], w["target_gates"])]
+    ctx = qe.Context(0, w["lib"], qe.ALG_GA, 0, P, seed=w["seed"], widths=w["widths"],
+                     lengths=w["lengths"])
+    ctx.set_targets(torch.cat(mats))
     hist = torch.empty((gens, I * P), dtype=torch.float32, device=dev)
     ctx.graph_prepare(gens, hist)
     ctx.run_graph(0, gens, hist)
@@ -345,30 +552,29 @@ def secondary_qeqea_n5(dev, gens=20):
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     ctx.run_graph(gens, gens, hist)
-    idx, f64 = ctx.elite_recheck(None, hist[gens - 1], 32)
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
-    f32 = hist[gens - 1].view(I, P).gather(1, idx.long()).double()
-    best = [ctx.get_best(i, with_fp64=False)[1] for i in range(4)]
-    # the fused sampling + fitness kernel alone, against the LDS peak
-    slots, gates, fk = ctx.sample_eval(2 * gens)
+    _, gates = ctx.sample(2 * gens)
+    f = ctx.eval_population(gates)
     torch.cuda.synchronize()
-    reps = 10
     e0.record()
-    for r in range(reps):
-        ctx.sample_eval(2 * gens + 1 + r, slots, gates, fk)
+    for _ in range(reps):
+        ctx.eval_population(gates)
     e1.record()
     torch.cuda.synchronize()
-    kern_ms = e0.elapsed_time(e1) / reps
-    lds = algorithmic_lds_bytes(gates.cpu().numpy(), n)
+    eval_us = e0.elapsed_time(e1) / reps * 1e3
+    flat = gates.cpu().numpy().view(np.uint16)
+    lds, o = 0.0, 0
+    for n, L in zip(w["widths"], w["lengths"]):
+        lds += algorithmic_lds_bytes(flat[o:o + P * L].reshape(P, L), n)
+        o += P * L
+    best = max(ctx.get_best(i, with_fp64=False)[1] for i in range(I))
     ctx.close()
     return {"workload": w["name"], "generations": gens, "evals_per_s": gens * I * P / (ms * 1e-3),
-            "ms_per_generation": ms / gens, "elite_fp32_vs_fp64_max_abs_df": float((f32 - f64).abs().max()),
-            "best_f_first_populations": best,
-            "fused_kernel": "population_kernel<5,2,true,false>", "fused_kernel_us": kern_ms * 1e3,
-            "algorithmic_lds_bytes_per_launch": lds,
-            "lds_frac": lds / (kern_ms * 1e-3) / 1e9 / LDS_PEAK_GBPS}
+            "ms_per_generation": ms / gens, "eval_kernel": "mix_kernel (cost order fixed at creation)",
+            "eval_kernel_us": eval_us, "algorithmic_lds_bytes_per_launch": lds,
+            "lds_frac": lds / (eval_us * 1e-6) / 1e9 / LDS_PEAK_GBPS, "best_f": best}
 
 
 def secondary_uneven(dev, reps=7):
@@ -406,21 +612,24 @@ def secondary_uneven(dev, reps=7):
 
 
 def main():
+    global LDS_PEAK_GBPS
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--timed-replays", type=int, default=3,
+                    help="timed replays of the K-generation graph (the median is reported)")
+    ap.add_argument("--cpu-seconds", type=float, default=16.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--kernel-reps", type=int, default=50)
+    ap.add_argument("--kernel-reps", type=int, default=10)
     ap.add_argument("--pmc-calibration-mb", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB (a plain copy kernel "
                          "of known traffic that scales the FETCH_SIZE / WRITE_SIZE counters)")
     ap.add_argument("--no-secondary", action="store_true",
                     help="skip the secondary workloads")
-    ap.add_argument("--secondary", default="precision,qeqea_n5,uneven,phase_insensitive,ising,dense",
-                    help="comma list of the secondary workloads to run (precision, qeqea_n5, "
-                         "uneven, phase_insensitive, ising, dense)")
+    ap.add_argument("--secondary", default="precision,qeqea_n4,uneven,mixed_ga,phase_insensitive,ising,dense",
+                    help="comma list of the secondary workloads to run (precision, qeqea_n4, "
+                         "uneven, mixed_ga, phase_insensitive, ising, dense)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the hot path runs on a single MI355X (independent "
@@ -431,7 +640,6 @@ def main():
     if K < 1 or W < 1:
         ap.error("--steps and --warmup must be >= 1")
 
-    import numpy as np
     import torch
     from paper_1809_11134_amd import inputs, qe
 
@@ -439,74 +647,62 @@ def main():
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     qe.load()
-    w = inputs.workload_qeqea_n4()
+    src = source_hash()
+
+    # the per-gate kernels read and write every element they touch once, so
+    # their LDS ceiling is the probe's copy rate (equal reads and writes)
+    lds_probe = measure_lds_peak(dev)
+    LDS_PEAK_GBPS = lds_probe["copy_b128"]
+    log(f"LDS probe: {lds_probe} GB/s -> peak {LDS_PEAK_GBPS:.0f} GB/s for equal reads and writes "
+        f"({LDS_PEAK_GBPS / LDS_SPEC_GBPS:.3f} of the unit-count figure)")
+
+    w = inputs.workload_qeqea_n5()
     n, L, P, I = w["n"], w["L"], w["P"], w["instances"]
     log(f"workload {w['name']}: n={n} L={L} P={P} instances={I}; steps={K} warmup={W}")
-
-    tg = torch.from_numpy(np.stack(w["target_gates"]).astype(np.int16)).to(dev)
-    T = qe.build_unitary(tg, n, tg.shape[1], precision=1)          # [I, N, N] complex128
-    ctx = qe.Context(n, w["lib"], qe.ALG_QEQEA, L, P, I, prob_mutation=0.1,
-                     mutation_range=math.pi / 4, seed=w["seed"])
-    ctx.set_targets(T)
-    f_warm = torch.empty((W, I * P), dtype=torch.float32, device=dev)
-    f_hist = torch.empty((K, I * P), dtype=torch.float32, device=dev)
-    ctx.graph_prepare(W, f_warm)
-    ctx.graph_prepare(K, f_hist)
-    ctx.run_graph(0, W, f_warm)
-    torch.cuda.synchronize()
-    log("warmup done")
-
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
+    ctx = qeqea_context(w, dev)
     t0 = time.perf_counter()
-    e0.record()
-    ctx.run_graph(W, K, f_hist)
-    idx, f64 = ctx.elite_recheck(None, f_hist[K - 1], 32)
-    e1.record()
-    torch.cuda.synchronize()
+    ms, times, gen, fit_err = qeqea_graph_run(ctx, K, W, dev, reps=max(1, args.timed_replays))
     wall = time.perf_counter() - t0
-    ms = e0.elapsed_time(e1)
     assert qe.device_errors() == 0, "device error flags raised"
     value = K * I * P / (ms / 1e3)
-    log(f"timed: {K} generations in {ms:.3f} ms (wall {wall * 1e3:.3f} ms) -> {value:.4g} evals/s")
+    log(f"timed: {K} generations + elite re-check, replays {['%.3f' % t for t in times]} ms "
+        f"(median {ms:.3f} ms) -> {value:.4g} evals/s")
 
-    # FP32 vs FP64 fitness error on the re-checked elites of the last generation
-    f32_el = f_hist[K - 1].view(I, P).gather(1, idx.long()).double()
-    fit_err = float((f32_el - f64).abs().max().item())
-
-    # dominant kernel: fused sampling + fitness, timed launch by launch
+    # the generation's two kernels, launch by launch
     R = max(1, args.kernel_reps)
-    slots = torch.empty((I * P, L), dtype=torch.int32, device=dev)
-    gates = torch.empty((I * P, L), dtype=torch.int16, device=dev)
-    fk = torch.empty(I * P, dtype=torch.float32, device=dev)
-    # R launches back to back on the current stream between two events: the
-    # average duration per launch, as a kernel trace reports it
-    k0 = torch.cuda.Event(enable_timing=True)
-    k1 = torch.cuda.Event(enable_timing=True)
-    ctx.sample_eval(W + K, slots, gates, fk)
-    torch.cuda.synchronize()
-    k0.record()
-    for r in range(R):
-        ctx.sample_eval(W + K + r, slots, gates, fk)
-    k1.record()
-    torch.cuda.synchronize()
-    kern_ms = k0.elapsed_time(k1) / R
+    fused_us, upd_us, gates, gen = time_generation_kernels(ctx, gen, R, dev)
     gh = gates.cpu().numpy()
     flops = algorithmic_flops(gh, n)
     lds_bytes = algorithmic_lds_bytes(gh, n)
-    achieved = lds_bytes / (kern_ms / 1e3) / 1e9
-    alu = flops / (kern_ms / 1e3) / 1e12
-    src = source_hash()
+    achieved = lds_bytes / (fused_us * 1e-6) / 1e9
+    alu = flops / (fused_us * 1e-6) / 1e12
     roofline = {"bound": "lds", "achieved": round(achieved, 2), "peak": round(LDS_PEAK_GBPS, 1),
                 "unit": "GB/s", "frac": round(achieved / LDS_PEAK_GBPS, 6),
-                "traffic": traffic_from_profiles("qeqea_fused_n4", src),
-                "kernel": "population_kernel<4,1,true,false> (sampling + Eq. 11 fitness + segment max, LDS-staged)",
-                "kernel_ms": round(kern_ms, 6), "algorithmic_lds_bytes_per_launch": lds_bytes,
+                "traffic": traffic_from_profiles("qeqea_fused_n5", src),
+                "kernel": "population_kernel<5,2,true,false> (sampling + Eq. 11 fitness + segment "
+                          "max + mutation decisions, LDS-staged, two wavefronts per circuit)",
+                "kernel_us": round(fused_us, 3), "algorithmic_lds_bytes_per_launch": lds_bytes,
+                "peak_source": "LDS probe kernel in this run, copy mode (each 16-byte word read and "
+                               "written once, the mix of the per-gate updates)",
+                "lds_probe_gbps": lds_probe,
+                "frac_of_read_peak": round(achieved / lds_probe["read_b128"], 6),
+                "frac_of_unit_count_peak": round(achieved / LDS_SPEC_GBPS, 6),
                 "algorithmic_flops_per_launch": flops, "alu_tflops": round(alu, 4),
                 "alu_frac": round(alu / FP32_VECTOR_PEAK_TFLOPS, 6)}
-    log(f"dominant kernel: {kern_ms * 1e3:.2f} us/launch, {achieved:.1f} GB/s algorithmic LDS "
-        f"({achieved / LDS_PEAK_GBPS:.3f} of peak), {alu:.3f} TFLOP/s")
+    log(f"fused kernel: {fused_us:.2f} us/launch, {achieved:.1f} GB/s algorithmic LDS "
+        f"({achieved / LDS_PEAK_GBPS:.3f} of the measured peak)")
+    upd_bytes, upd_counts = update_algorithmic_bytes(ctx, gen, dev)
+    gen += 1
+    upd_ach = upd_bytes / (upd_us * 1e-6) / 1e9
+    roofline_update = {"bound": "hbm", "achieved": round(upd_ach, 2), "peak": HBM_PEAK_GBPS,
+                       "unit": "GB/s", "frac": round(upd_ach / HBM_PEAK_GBPS, 6),
+                       "traffic": traffic_from_profiles("qeqea_update_n5", src),
+                       "kernel": "qeqea_update_kernel (segment fitness, elitism, mutation, best circuit)",
+                       "kernel_us": round(upd_us, 3), "algorithmic_hbm_bytes_per_launch": upd_bytes,
+                       "units": upd_counts}
+    log(f"update kernel: {upd_us:.2f} us/launch, {upd_ach:.1f} GB/s algorithmic HBM "
+        f"({upd_ach / HBM_PEAK_GBPS:.3f} of peak)")
+    ctx.close()
 
     if args.pmc_calibration_mb > 0:
         nb = args.pmc_calibration_mb << 20
@@ -517,26 +713,29 @@ def main():
         log(f"calibration copy: {args.pmc_calibration_mb} MiB read + {args.pmc_calibration_mb} MiB written")
 
     secondary = None
+    known = {"precision", "qeqea_n4", "uneven", "mixed_ga", "phase_insensitive", "ising", "dense"}
     which = set() if args.no_secondary else {s.strip() for s in args.secondary.split(",") if s.strip()}
-    unknown = which - {"precision", "qeqea_n5", "uneven", "phase_insensitive", "ising", "dense"}
-    if unknown:
-        ap.error(f"unknown secondary workloads: {sorted(unknown)}")
+    if which - known:
+        ap.error(f"unknown secondary workloads: {sorted(which - known)}")
     if which:
         secondary = {}
         if "precision" in which:
             log("secondary: n=6 precision study (FP32 vs bf16/fp16 MFMA)")
             secondary["precision_n6"] = secondary_precision(dev)
-        if "qeqea_n5" in which:
-            log("secondary: n=5 QEQEA, 1024 populations")
-            secondary["qeqea_n5"] = secondary_qeqea_n5(dev)
+        if "qeqea_n4" in which:
+            log("secondary: n=4 QEQEA, one population of 4096")
+            secondary["qeqea_n4"] = secondary_qeqea_n4(dev, K, W)
         if "uneven" in which:
             log("secondary: uneven batch")
             secondary["uneven"] = secondary_uneven(dev)
+        if "mixed_ga" in which:
+            log("secondary: mixed-width GA populations, 50-generation graph")
+            secondary["mixed_ga"] = secondary_mixed_ga(dev)
         if "phase_insensitive" in which:
-            log("secondary: bench workload with the phase-insensitive fitness")
+            log("secondary: n=4 workload with the phase-insensitive fitness")
             secondary["phase_insensitive"] = secondary_phase_insensitive(dev)
         if "ising" in which:
-            log("secondary: bench shape with the Ising library")
+            log("secondary: n=4 shape with the Ising library")
             secondary["qeqea_ising_n4"] = secondary_qeqea_ising(dev)
         if "dense" in which:
             log("secondary: dense segment-matrix ablation")
@@ -546,23 +745,26 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle for ~{args.cpu_seconds:.0f} s")
-        Th = T[0].cpu().numpy()
-        cpu = cpu_baseline(w, Th, args.cpu_seconds)
-        log(f"cpu baseline: {cpu['value']:.4g} evals/s on {cpu['cores']} threads")
+        cpu = cpu_baseline(w, args.cpu_seconds)
+        log(f"cpu baseline: {cpu['value']:.4g} evals/s on {cpu['cores']} threads, "
+            f"{cpu['value_1core']:.4g} on one ({cpu['cpu_model']})")
 
     out = {
         "metric": METRIC, "value": value, "unit": "evals/s", "n_gpus": 1, "steps": K,
         "warmup": W, "ms_per_step": ms / K, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": w["name"], "n_qubits": n, "library": "I,NOT,CNOT,CV,CV+",
-                   "algorithm": "QEQEA", "population": P, "layers": L, "instances": I,
-                   "path": "fp32", "graph": True, "elite_fp64_recheck": 32,
+                   "algorithm": "QEQEA", "instances": I, "population": P, "layers": L,
+                   "evals_per_generation": I * P, "path": "fp32", "graph": True,
+                   "elite_fp64_recheck": 32, "timed_replays_ms": times,
                    "parallelism": "single GPU"},
         "fitness_error_fp32_vs_fp64": fit_err,
         "roofline": roofline,
+        "roofline_update": roofline_update,
         "cpu_baseline": cpu,
         "secondary": secondary,
         "source_hash": src,
+        "wall_s_timed_phase": round(wall, 3),
     }
     print(json.dumps(out), flush=True)
 

@@ -151,6 +151,26 @@ typedef struct {
 typedef struct qe_ctx qe_ctx;
 qe_status qe_eval_fitness(qe_ctx* ctx, const qe_batch* batch, int32_t path, float* f_dev,
                           float* g_dev, float* delta_dev, void* stream);
+/* How a mixed-width batch (uniform_n == 0) runs on QE_PATH_FP32: with a
+ * workspace, in one launch whose workgroups take the circuits in cost order
+ * (widest first, then longest first), the order computed on the device into
+ * the workspace; without one, in one launch per width.  Both give the same
+ * results.  qe_eval_fitness uses the workspace of ctx when ctx is a context
+ * of mixed populations (qe_create_mixed) and the batch fits it (calls on one
+ * context must then not overlap); it allocates nothing and never
+ * synchronises. */
+
+/* Bytes of device workspace qe_eval_fitness_ws needs for num_circuits
+ * circuits (0 for num_circuits < 0). */
+size_t qe_eval_workspace_bytes(int32_t num_circuits);
+
+/* qe_eval_fitness with a caller-owned device workspace of workspace_bytes
+ * bytes (at least qe_eval_workspace_bytes(batch->num_circuits), else
+ * QE_ERR_INVALID), used by mixed-width batches on QE_PATH_FP32 and ignored
+ * otherwise.  Calls sharing a workspace must not overlap. */
+qe_status qe_eval_fitness_ws(const qe_batch* batch, int32_t path, float* f_dev, float* g_dev,
+                             float* delta_dev, void* workspace_dev, size_t workspace_bytes,
+                             void* stream);
 
 /* The same fitness in FP64 (targets complex128), for re-checking elite
  * circuits; f_dev required, g_dev/delta_dev optional. */
@@ -210,6 +230,26 @@ typedef struct {
 qe_status qe_create(const qe_problem* problem, qe_ctx** ctx_out);
 qe_status qe_destroy(qe_ctx* ctx);
 
+/* A GA search (Sec. V-B) over I = problem->n_instances independent
+ * populations of P circuits each, population i on n_qubits_host[i] wires
+ * (1..6) with genomes of lengths_host[i] genes (1..1024): the uneven batches
+ * of circuits built in parallel (Sec. IV-D) evaluated in one launch per
+ * generation, the circuits taken in cost order (widest, then longest first;
+ * the order is fixed by the widths and lengths and computed here once).
+ * problem->algorithm must be QE_ALG_GA, library QE_LIB_NCV or QE_LIB_HT_NCV;
+ * problem->n_qubits and size_of_individual are ignored and stored as the
+ * largest width and length.  Genomes of population i are drawn from the
+ * INIT stream with instance index i over the library of its own width, as
+ * a context of that width alone would draw them.  Targets
+ * (qe_set_targets) are packed: population i's 2^n_i x 2^n_i matrix follows
+ * those of populations 0..i-1.  Every call taking a context accepts a mixed
+ * one, with these layouts: circuits of population i (qe_sample,
+ * qe_eval_population, qe_update, qe_elite_recheck gates) start at gene
+ * P * (L_0 + ... + L_{i-1}), circuit k of it at that plus k * L_i; fitness
+ * arrays stay [I][P]; qe_get_best returns L_i gates.  Syncs. */
+qe_status qe_create_mixed(const qe_problem* problem, const int32_t* n_qubits_host,
+                          const int32_t* lengths_host, qe_ctx** ctx_out);
+
 /* Copies the I targets ([I][2^n][2^n] complex128, device) into the context
  * (kept in complex128 for the FP64 re-check and in complex64 for the hot
  * path).  Must precede sample/eval/update/generation.  Asynchronous. */
@@ -243,7 +283,10 @@ qe_status qe_eval_population(qe_ctx* ctx, const uint16_t* gates_dev, const uint3
  * Eq. 12, equiprobably).  GA: SUS selection, two-point crossover, gene
  * mutation, best individual kept.  slots_dev/gates_dev/angles_dev/f_dev as
  * produced by qe_sample and qe_eval_population for the same `gen`
- * (angles_dev: Ising library only, NULL otherwise). */
+ * (angles_dev: Ising library only, NULL otherwise).  QEQEA with slots_dev
+ * NULL: allowed only right after qe_sample_eval(gen) on this context (else
+ * QE_ERR_STATE); the slot indices are then drawn again from the SAMPLE
+ * stream, and the segment keys and decisions that call left are used. */
 qe_status qe_update(qe_ctx* ctx, uint64_t gen, const uint32_t* slots_dev,
                     const uint16_t* gates_dev, const uint32_t* angles_dev, const float* f_dev,
                     void* stream);
@@ -253,12 +296,15 @@ qe_status qe_update(qe_ctx* ctx, uint64_t gen, const uint32_t* slots_dev,
  * Results equal qe_sample, qe_eval_population and qe_update in sequence. */
 qe_status qe_generation(qe_ctx* ctx, uint64_t gen, float* f_dev, void* stream);
 
-/* The first half of qe_generation for QEQEA, one kernel launch: circuit
- * construction (as qe_sample, into slots_dev / gates_dev) fused with the
- * fitness evaluation (f_dev) and the segment-fitness maximum that qe_update
- * starts from.  qe_update(gen, slots, gates, angles, f) afterwards completes
- * the generation with the same result as qe_generation.  angles_dev as in
- * qe_sample.  QEQEA only. */
+/* The first half of qe_generation for QEQEA, one kernel launch (the one
+ * qe_generation and qe_run_graph launch): circuit construction (as
+ * qe_sample, into gates_dev, and into slots_dev unless it is NULL) fused with
+ * the fitness evaluation (f_dev), the segment-fitness maximum that qe_update
+ * starts from and the generation's mutation decisions (Sec. IV-F).
+ * qe_update(gen, slots, gates, angles, f) afterwards completes the
+ * generation with the same result as qe_generation; with slots_dev NULL
+ * there, it is the second kernel launch of qe_generation alone.  angles_dev
+ * as in qe_sample.  QEQEA only. */
 qe_status qe_sample_eval(qe_ctx* ctx, uint64_t gen, uint32_t* slots_dev, uint16_t* gates_dev,
                          uint32_t* angles_dev, float* f_dev, void* stream);
 
@@ -305,7 +351,9 @@ qe_status qe_restore(qe_ctx* ctx, const void* buf_host, size_t size);
  * is gathered).  which: 0 theta (u32, [I][S] slot order of Eq. 10), 1 qutrit
  * amplitudes (f32, 6 per qutrit, [I][n*L*P]), 2 best_f (f32), 3 best_theta
  * (u32), 4 best qutrit amplitudes (f32), 5 GA genomes of generation parity 0
- * (u16, [I][P][L]), 6 parity 1.  *elems receives the field's size in
+ * (u16, [I][P][L]), 6 parity 1, 7 QEQEA mutation decisions (u32 bitmaps
+ * [2][I][ceil(P/32)]: bit ind of map g & 1 is set when individual ind
+ * mutates in generation g).  *elems receives the field's size in
  * elements (0 when the algorithm has no such field); with dst_dev non-NULL
  * (device memory of that size, caller-owned) the copy is enqueued on
  * `stream`.  Unknown which: QE_ERR_INVALID. */
@@ -324,6 +372,19 @@ qe_status qe_lib_table(int32_t library, int32_t n_qubits, uint16_t* table_host);
  * variable QE_SCHEDULE="n:lds,n:lds,...". */
 qe_status qe_set_schedule(int32_t n_qubits, int32_t lds);
 qe_status qe_get_schedule(int32_t n_qubits, int32_t* lds);
+
+/* Measurement helper (not part of the method): the LDS bandwidth the GPU
+ * sustains, the denominator of the per-gate kernels' LDS rooflines.  Launches
+ * `workgroups` workgroups of 256 threads, each owning 32 KB of LDS, whose
+ * threads run `iters` iterations of eight conflict-free 16-byte LDS accesses
+ * (every wavefront instruction moves one contiguous kilobyte).  mode 0:
+ * reads (ds_read_b128); 1: writes (ds_write_b128); 2: a read and a write of
+ * each word (a copy within LDS).  sink_dev: caller-owned device memory of
+ * workgroups * 256 uint32 (written, so no access can be optimised away).
+ * *bytes_host (may be NULL) receives the LDS bytes the launch moves (reads
+ * plus writes).  Asynchronous on `stream`; time it with events. */
+qe_status qe_probe_lds(int32_t mode, int32_t workgroups, int32_t iters, uint32_t* sink_dev,
+                       double* bytes_host, void* stream);
 
 const char* qe_last_error(void);
 const char* qe_version(void);

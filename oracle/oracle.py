@@ -43,6 +43,7 @@ def lib():
                                       ctypes.POINTER(c.c_uint32)]
         L.qeo_decode_slot.restype = c.c_uint16
         L.qeo_num_threads.restype = c.c_int
+        L.qeo_set_num_threads.argtypes = [c.c_int]
         L.qeo_lib_size.argtypes = [c.c_int, c.c_int]
         L.qeo_lib_desc.argtypes = [c.c_int, c.c_int, c.c_int]
         L.qeo_lib_desc.restype = c.c_uint16
@@ -60,6 +61,10 @@ def lib():
                                        u32p, f32p, f32p, u32p, f32p]
         L.qeo_ga_init.argtypes = [c.c_int, c.c_int, c.c_int, c.c_int, c.c_int, c.c_uint64,
                                   u16p]
+        L.qeo_ga_init_at.argtypes = [c.c_int, c.c_int, c.c_int, c.c_int, c.c_int, c.c_uint64,
+                                     u16p]
+        L.qeo_ga_update_at.argtypes = [c.c_int, c.c_int, c.c_int, c.c_int, c.c_int, c.c_uint64,
+                                       c.c_uint64, c.c_float, c.c_float, f32p, u16p]
         L.qeo_ga_sus.argtypes = [c.c_int, f32p, c.c_uint32, i32p]
         L.qeo_ga_update.argtypes = [c.c_int, c.c_int, c.c_int, c.c_int, c.c_int, c.c_uint64,
                                     c.c_uint64, c.c_float, c.c_float, f32p, u16p]
@@ -180,6 +185,10 @@ def num_threads():
     return lib().qeo_num_threads()
 
 
+def set_num_threads(n):
+    lib().qeo_set_num_threads(int(n))
+
+
 # --------------------------------------------------------------------- libraries
 def lib_size(library, n):
     return lib().qeo_lib_size(library, n)
@@ -286,3 +295,19 @@ def ga_update(n, library, L, P, I, seed, gen, pc, pg, f, genomes):
     lib().qeo_ga_update(n, library, L, P, I, seed, gen, pc, pg,
                         np.ascontiguousarray(f, np.float32).ravel(), g)
     return g.reshape(I * P, L)
+
+
+def ga_init_at(n, library, L, P, inst, seed):
+    """Initial genomes [P, L] of population `inst` (the populations of a
+    search are independent, each with its own width and length)."""
+    g = np.zeros(P * L, np.uint16)
+    lib().qeo_ga_init_at(n, library, L, P, inst, seed, g)
+    return g.reshape(P, L)
+
+
+def ga_update_at(n, library, L, P, inst, seed, gen, pc, pg, f, genomes):
+    """One GA generation of population `inst`: f [P], genomes [P, L]."""
+    g = np.ascontiguousarray(genomes, np.uint16).ravel().copy()
+    lib().qeo_ga_update_at(n, library, L, P, inst, seed, gen, pc, pg,
+                           np.ascontiguousarray(f, np.float32).ravel(), g)
+    return g.reshape(P, L)

@@ -418,6 +418,16 @@ QEO_API int qeo_num_threads(void)
 #endif
 }
 
+/* Sets the thread count of the batch evaluator (timing on one core). */
+QEO_API void qeo_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------------ */
 /* Gate-library instances (the enumeration order is a convention of this library): */
 /*   library 0 {I, NOT, CNOT, CV, CV+}: I; NOT on wires 0..n-1; then for     */
@@ -777,17 +787,22 @@ QEO_API void qeo_qeqea_update(int n, int lib, int L, int P, int I_, uint64_t see
 /* SUS counts and crossover gene multisets are pinned by invariants; the     */
 /* trajectory is "parity unpinned" by the paper.                             */
 /* ------------------------------------------------------------------------ */
-QEO_API void qeo_ga_init(int n, int lib, int L, int P, int I_, uint64_t seed, uint16_t* genomes)
+/* Initial genomes of population `inst` (P x L, uniform library instances
+ * from the INIT stream). */
+QEO_API void qeo_ga_init_at(int n, int lib, int L, int P, int inst, uint64_t seed, uint16_t* genomes)
 {
     uint32_t nl = (uint32_t)qeo_lib_size(lib, n);
-    for (int i = 0; i < I_; ++i)
-        for (int k = 0; k < P; ++k)
-            for (int pos = 0; pos < L; ++pos) {
-                uint32_t w[4];
-                draw(seed, TAG_INIT, 0xFFFFFFFFu, (uint32_t)i, (uint32_t)(k * L + pos), w);
-                genomes[((size_t)i * P + k) * L + pos] =
-                    qeo_lib_desc(lib, n, (int)scale_u32(w[0], nl));
-            }
+    for (int k = 0; k < P; ++k)
+        for (int pos = 0; pos < L; ++pos) {
+            uint32_t w[4];
+            draw(seed, TAG_INIT, 0xFFFFFFFFu, (uint32_t)inst, (uint32_t)(k * L + pos), w);
+            genomes[(size_t)k * L + pos] = qeo_lib_desc(lib, n, (int)scale_u32(w[0], nl));
+        }
+}
+
+QEO_API void qeo_ga_init(int n, int lib, int L, int P, int I_, uint64_t seed, uint16_t* genomes)
+{
+    for (int i = 0; i < I_; ++i) qeo_ga_init_at(n, lib, L, P, i, seed, genomes + (size_t)i * P * L);
 }
 
 /* SUS over integer weights w_k = floor(f_k * 2^24): P equally spaced
@@ -815,51 +830,58 @@ QEO_API void qeo_ga_sus(int P, const float* f, uint32_t w0, int32_t* sel)
     free(pre);
 }
 
-QEO_API void qeo_ga_update(int n, int lib, int L, int P, int I_, uint64_t seed, uint64_t gen64,
-                           float pc, float pg, const float* f, uint16_t* genomes)
+/* One generation of the GA on population `inst` (its P fitness values fi and
+ * its P x L genomes gi, updated in place). */
+QEO_API void qeo_ga_update_at(int n, int lib, int L, int P, int inst, uint64_t seed, uint64_t gen64,
+                              float pc, float pg, const float* fi, uint16_t* gi)
 {
     uint32_t gen = (uint32_t)gen64;
     uint32_t nl = (uint32_t)qeo_lib_size(lib, n);
     uint64_t thr_c = prob_threshold((double)pc), thr_g = prob_threshold((double)pg);
     int32_t* sel = (int32_t*)malloc(sizeof(int32_t) * P);
     uint16_t* child = (uint16_t*)malloc(sizeof(uint16_t) * (size_t)P * L);
-    for (int i = 0; i < I_; ++i) {
-        const float* fi = f + (size_t)i * P;
-        uint16_t* gi = genomes + (size_t)i * P * L;
-        int best = 0;                           /* lowest index among the maxima */
-        float bv = -1.0f;                       /* NaN never counts */
-        for (int k = 0; k < P; ++k)
-            if (fi[k] > bv) { bv = fi[k]; best = k; }
-        uint32_t w[4];
-        draw(seed, TAG_GA_SUS, gen, (uint32_t)i, 0u, w);
-        qeo_ga_sus(P, fi, w[0], sel);
-        for (int k = 0; k < P; ++k)
-            memcpy(child + (size_t)k * L, gi + (size_t)sel[k] * L, sizeof(uint16_t) * L);
-        /* two-point crossover: pair j mates children j and j + P/2 */
-        int half = P / 2;
-        for (int j = 0; j < half; ++j) {
-            draw(seed, TAG_GA_XOVER, gen, (uint32_t)i, (uint32_t)j, w);
-            if (!((uint64_t)w[0] < thr_c)) continue;
-            int a = (int)scale_u32(w[1], (uint32_t)(L + 1));
-            int b = (int)scale_u32(w[2], (uint32_t)(L + 1));
-            int lo = a < b ? a : b, hi = a < b ? b : a;
-            for (int pos = lo; pos < hi; ++pos) {
-                uint16_t t = child[(size_t)j * L + pos];
-                child[(size_t)j * L + pos] = child[(size_t)(j + half) * L + pos];
-                child[(size_t)(j + half) * L + pos] = t;
-            }
+    uint32_t i = (uint32_t)inst;
+    int best = 0;                           /* lowest index among the maxima */
+    float bv = -1.0f;                       /* NaN never counts */
+    for (int k = 0; k < P; ++k)
+        if (fi[k] > bv) { bv = fi[k]; best = k; }
+    uint32_t w[4];
+    draw(seed, TAG_GA_SUS, gen, i, 0u, w);
+    qeo_ga_sus(P, fi, w[0], sel);
+    for (int k = 0; k < P; ++k)
+        memcpy(child + (size_t)k * L, gi + (size_t)sel[k] * L, sizeof(uint16_t) * L);
+    /* two-point crossover: pair j mates children j and j + P/2 */
+    int half = P / 2;
+    for (int j = 0; j < half; ++j) {
+        draw(seed, TAG_GA_XOVER, gen, i, (uint32_t)j, w);
+        if (!((uint64_t)w[0] < thr_c)) continue;
+        int a = (int)scale_u32(w[1], (uint32_t)(L + 1));
+        int b = (int)scale_u32(w[2], (uint32_t)(L + 1));
+        int lo = a < b ? a : b, hi = a < b ? b : a;
+        for (int pos = lo; pos < hi; ++pos) {
+            uint16_t t = child[(size_t)j * L + pos];
+            child[(size_t)j * L + pos] = child[(size_t)(j + half) * L + pos];
+            child[(size_t)(j + half) * L + pos] = t;
         }
-        /* gene mutation: a gene is replaced by a uniformly drawn instance */
-        for (int k = 0; k < P; ++k)
-            for (int pos = 0; pos < L; ++pos) {
-                draw(seed, TAG_GA_MUT, gen, (uint32_t)i, (uint32_t)(k * L + pos), w);
-                if ((uint64_t)w[0] < thr_g)
-                    child[(size_t)k * L + pos] = qeo_lib_desc(lib, n, (int)scale_u32(w[1], nl));
-            }
-        /* elitism: the best individual survives unchanged in position 0 */
-        memcpy(child, gi + (size_t)best * L, sizeof(uint16_t) * L);
-        memcpy(gi, child, sizeof(uint16_t) * (size_t)P * L);
     }
+    /* gene mutation: a gene is replaced by a uniformly drawn instance */
+    for (int k = 0; k < P; ++k)
+        for (int pos = 0; pos < L; ++pos) {
+            draw(seed, TAG_GA_MUT, gen, i, (uint32_t)(k * L + pos), w);
+            if ((uint64_t)w[0] < thr_g)
+                child[(size_t)k * L + pos] = qeo_lib_desc(lib, n, (int)scale_u32(w[1], nl));
+        }
+    /* elitism: the best individual survives unchanged in position 0 */
+    memcpy(child, gi + (size_t)best * L, sizeof(uint16_t) * L);
+    memcpy(gi, child, sizeof(uint16_t) * (size_t)P * L);
     free(sel);
     free(child);
+}
+
+QEO_API void qeo_ga_update(int n, int lib, int L, int P, int I_, uint64_t seed, uint64_t gen64,
+                           float pc, float pg, const float* f, uint16_t* genomes)
+{
+    for (int i = 0; i < I_; ++i)
+        qeo_ga_update_at(n, lib, L, P, i, seed, gen64, pc, pg, f + (size_t)i * P,
+                         genomes + (size_t)i * P * L);
 }

@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libqe.so")
-SOURCES = ["qe_api.hip", "qe_eval.hip", "qe_loop.hip", "qe_mfma.hip", "qe_dense.hip"]
+SOURCES = ["qe_api.hip", "qe_eval.hip", "qe_loop.hip", "qe_mfma.hip", "qe_dense.hip", "qe_probe.hip"]
 ARCH = os.environ.get("QE_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=off",

@@ -35,7 +35,12 @@ qe_status fail(qe_status st, const std::string& msg) {
             return fail(QE_ERR_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
-// One device error word per device, allocated on first use.
+// The device error word: a module global, so every device holds its own copy,
+// zero from the moment the code object is loaded.  Its device address is
+// resolved once per device (no allocation, no synchronisation, so calls that
+// raise errors can be captured in graphs).
+__device__ uint32_t g_dev_err_word;
+
 std::mutex g_mu;
 std::map<int, uint32_t*> g_err_words;
 
@@ -46,38 +51,9 @@ qe_status device_error_word(uint32_t** out) {
     auto it = g_err_words.find(dev);
     if (it != g_err_words.end()) { *out = it->second; return QE_OK; }
     uint32_t* p = nullptr;
-    QE_HIP(hipMalloc(&p, sizeof(uint32_t)));
-    QE_HIP(hipMemset(p, 0, sizeof(uint32_t)));
-    QE_HIP(hipDeviceSynchronize());
+    QE_HIP(hipGetSymbolAddress((void**)&p, HIP_SYMBOL(g_dev_err_word)));
     g_err_words[dev] = p;
     *out = p;
-    return QE_OK;
-}
-
-// Workspace for mixed-width batches, one per device, grown on demand (the
-// first call with a larger batch allocates; later calls do not).
-std::map<int, std::pair<int32_t*, size_t>> g_work;
-
-qe_status mix_workspace(int64_t B, int32_t** out) {
-    int dev = 0;
-    QE_HIP(hipGetDevice(&dev));
-    std::lock_guard<std::mutex> lk(g_mu);
-    auto& w = g_work[dev];
-    const size_t need = 32 + (size_t)B;
-    if (w.second < need) {
-        if (w.first) {
-            QE_HIP(hipDeviceSynchronize());
-            QE_HIP(hipFree(w.first));
-            w.first = nullptr;
-            w.second = 0;
-        }
-        int32_t* p = nullptr;
-        const size_t cap = need + need / 2;
-        QE_HIP(hipMalloc(&p, cap * sizeof(int32_t)));
-        w.first = p;
-        w.second = cap;
-    }
-    *out = w.first;
     return QE_OK;
 }
 
@@ -209,6 +185,26 @@ struct qe_ctx {
     // the generation whose mutation decisions may be appended to the lists
     // without emptying them first (the one after the last decided)
     uint64_t next_decision_gen = 0;
+    // the generation of the last qe_sample_eval (its segment keys and mutation
+    // decisions are in place for qe_update), -1 when another call came since
+    int64_t fused_gen = -1;
+    // mixed GA populations (qe_create_mixed): per population width, genome
+    // length and target offset (host copies), genes per genome buffer,
+    // complex elements of the targets; per circuit width, gate offsets and
+    // target offsets for the evaluation; the cost order of the circuits
+    // (fixed by widths and lengths, computed once) and a workspace that
+    // qe_eval_fitness may use for other mixed batches
+    bool mixed = false;
+    std::vector<int32_t> inst_n, inst_L;
+    std::vector<int64_t> inst_toff;
+    int64_t genes = 0;
+    int64_t target_elems = 0;
+    int8_t* circ_n = nullptr;
+    int32_t* circ_goff = nullptr;
+    int64_t* circ_toff = nullptr;
+    int32_t* mix_order = nullptr;
+    int32_t* mix_eval_work = nullptr;
+    size_t mix_work_bytes = 0;
 };
 
 namespace {
@@ -260,6 +256,27 @@ qe_status prepare_decisions(qe_ctx* c, uint64_t gen, uint64_t count, hipStream_t
     return QE_OK;
 }
 
+// The evaluation batch of a mixed context's I*P circuits (genomes in `gates`,
+// laid out as the genome buffers).
+BatchArgs mixed_batch(const qe_ctx* c, const uint16_t* gates) {
+    BatchArgs b{};
+    b.B = c->prob.n_instances * c->prob.size_of_population;
+    b.uniform_n = 0;
+    b.nq = c->circ_n;
+    b.uniform_L = 0;
+    b.goff = c->circ_goff;
+    b.gates = gates;
+    b.num_gates = c->genes;
+    b.tstride = -1;
+    b.toff = c->circ_toff;
+    b.targets = c->la.target32;
+    b.num_telems = c->target_elems;
+    b.mode = c->prob.fitness_mode;
+    b.angles = nullptr;
+    b.err = c->la.err;
+    return b;
+}
+
 qe_status enqueue_generation(qe_ctx* c, const LoopArgs& a, uint64_t gen, float* f, hipStream_t s) {
     if (c->prob.algorithm == QE_ALG_QEQEA) {
         // the update draws each entry's slot again instead of reading it
@@ -267,7 +284,8 @@ qe_status enqueue_generation(qe_ctx* c, const LoopArgs& a, uint64_t gen, float* 
         QE_HIP(launch_qeqea_update(a, gen, nullptr, c->gates, c->angles, f, s));
     } else {
         QE_HIP(launch_ga_copy(a, gen, c->gates, s));
-        QE_HIP(launch_eval_population(a, c->gates, nullptr, f, s));
+        if (c->mixed) QE_HIP(launch_mix_eval(mixed_batch(c, c->gates), c->mix_order, f, nullptr, nullptr, s));
+        else QE_HIP(launch_eval_population(a, c->gates, nullptr, f, s));
         QE_HIP(launch_ga_update(a, gen, f, s));
     }
     return QE_OK;
@@ -307,9 +325,20 @@ qe_status qe_get_schedule(int32_t n, int32_t* lds) {
 }
 
 // ------------------------------------------------------------------- eval
-qe_status qe_eval_fitness(qe_ctx* ctx, const qe_batch* batch, int32_t path, float* f_dev,
-                          float* g_dev, float* delta_dev, void* stream) {
-    (void)ctx;
+size_t qe_eval_workspace_bytes(int32_t num_circuits) {
+    return num_circuits < 0 ? 0 : ((size_t)MIX_WORK_META + (size_t)num_circuits) * sizeof(int32_t);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Shared by the evaluation entry points: `work` (MIX_WORK_META + B int32 of
+// device memory, or NULL) holds the order and item table of the cost-sorted
+// single launch of a mixed-width FP32 batch; without it such a batch runs
+// as one filtered launch per width.
+qe_status eval_fitness_impl(const qe_batch* batch, int32_t path, float* f_dev, float* g_dev,
+                            float* delta_dev, int32_t* work, size_t work_bytes, void* stream) {
     BatchArgs a;
     QE_TRY(to_args(batch, &a, true));
     if (path < QE_PATH_FP32 || path > QE_PATH_DENSE) return fail(QE_ERR_INVALID, "unknown path");
@@ -329,10 +358,36 @@ qe_status qe_eval_fitness(qe_ctx* ctx, const qe_batch* batch, int32_t path, floa
         QE_HIP(launch_eval_mfma(a, fp16, renorm, f_dev, g_dev, delta_dev, (hipStream_t)stream));
         return QE_OK;
     }
-    int32_t* work = nullptr;
-    if (a.uniform_n == 0 && path == QE_PATH_FP32 && a.B > 0) QE_TRY(mix_workspace(a.B, &work));
+    if (work && work_bytes < qe_eval_workspace_bytes(a.B))
+        return fail(QE_ERR_INVALID, "workspace smaller than qe_eval_workspace_bytes(num_circuits)");
+    if (a.uniform_n != 0 || path != QE_PATH_FP32) work = nullptr;
     QE_HIP(launch_eval_fp32(a, path, f_dev, g_dev, delta_dev, work, (hipStream_t)stream));
     return QE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+qe_status qe_eval_fitness(qe_ctx* ctx, const qe_batch* batch, int32_t path, float* f_dev,
+                          float* g_dev, float* delta_dev, void* stream) {
+    // a mixed-width context lends its workspace when the batch fits it
+    int32_t* work = nullptr;
+    size_t bytes = 0;
+    if (ctx && ctx->mix_eval_work && batch && batch->num_circuits >= 0 &&
+        qe_eval_workspace_bytes(batch->num_circuits) <= ctx->mix_work_bytes) {
+        work = ctx->mix_eval_work;
+        bytes = ctx->mix_work_bytes;
+    }
+    return eval_fitness_impl(batch, path, f_dev, g_dev, delta_dev, work, bytes, stream);
+}
+
+qe_status qe_eval_fitness_ws(const qe_batch* batch, int32_t path, float* f_dev, float* g_dev,
+                             float* delta_dev, void* workspace_dev, size_t workspace_bytes,
+                             void* stream) {
+    if (!workspace_dev) return fail(QE_ERR_INVALID, "workspace_dev is NULL");
+    return eval_fitness_impl(batch, path, f_dev, g_dev, delta_dev, (int32_t*)workspace_dev,
+                             workspace_bytes, stream);
 }
 
 qe_status qe_eval_fitness_fp64(const qe_batch* batch, double* f_dev, double* g_dev,
@@ -371,9 +426,38 @@ qe_status qe_device_errors(int32_t* flags_host) {
 }
 
 // ------------------------------------------------------------------ context
-qe_status qe_create(const qe_problem* p, qe_ctx** out) {
-    if (!p || !out) return fail(QE_ERR_INVALID, "NULL argument");
+}  // extern "C"
+
+namespace {
+
+// qe_create, and qe_create_mixed when inst_n / inst_L (host, I entries) are
+// given: then every population has its own width and genome length, and
+// the problem's n_qubits and size_of_individual are replaced by the maxima.
+qe_status create_impl(const qe_problem* p_in, const int32_t* inst_n, const int32_t* inst_L, qe_ctx** out) {
+    if (!p_in || !out) return fail(QE_ERR_INVALID, "NULL argument");
     *out = nullptr;
+    qe_problem pm = *p_in;
+    const qe_problem* p = &pm;
+    const bool mixed = inst_n != nullptr;
+    int64_t genes_per_ind = 0, target_elems = 0;
+    if (mixed) {
+        if (!inst_L) return fail(QE_ERR_INVALID, "inst_L is NULL");
+        if (p->algorithm != QE_ALG_GA) return fail(QE_ERR_UNSUPPORTED, "mixed widths and lengths: GA only");
+        if (p->library != QE_LIB_NCV && p->library != QE_LIB_HT_NCV)
+            return fail(QE_ERR_UNSUPPORTED, "mixed populations take the discrete libraries");
+        if (p->n_instances < 1 || p->n_instances > (1 << 20)) return fail(QE_ERR_INVALID, "n_instances must be 1..2^20");
+        int nmax = 1, lmax = 1;
+        for (int i = 0; i < p->n_instances; ++i) {
+            if (inst_n[i] < 1 || inst_n[i] > MAX_QUBITS) return fail(QE_ERR_INVALID, "every width must be 1..6");
+            if (inst_L[i] < 1 || inst_L[i] > 1024) return fail(QE_ERR_INVALID, "every genome length must be 1..1024");
+            nmax = std::max(nmax, (int)inst_n[i]);
+            lmax = std::max(lmax, (int)inst_L[i]);
+            genes_per_ind += inst_L[i];
+            target_elems += (int64_t)1 << (2 * inst_n[i]);
+        }
+        pm.n_qubits = nmax;
+        pm.size_of_individual = lmax;
+    }
     const int n = p->n_qubits;
     if (p->library != QE_LIB_NCV && p->library != QE_LIB_HT_NCV && p->library != QE_LIB_ISING)
         return fail(QE_ERR_INVALID, "unknown library");
@@ -403,9 +487,25 @@ qe_status qe_create(const qe_problem* p, qe_ctx** out) {
     if ((uint64_t)S >= (1ull << 32) || I * P * L >= (1ull << 32))
         return fail(QE_ERR_INVALID, "encoding too large (slot indices are 32-bit)");
     if (I > (1u << 31) / P) return fail(QE_ERR_INVALID, "too many instances");
+    const int64_t genes = mixed ? genes_per_ind * (int64_t)P : (int64_t)(I * P * L);
+    if (!mixed) target_elems = (int64_t)I << (2 * n);
 
     qe_ctx* c = new qe_ctx();
-    c->prob = *p;
+    // stored field by field over zeroed bytes, so that checkpoint headers
+    // hold no stray padding
+    std::memset(&c->prob, 0, sizeof(c->prob));
+    c->prob.n_qubits = p->n_qubits;
+    c->prob.library = p->library;
+    c->prob.algorithm = p->algorithm;
+    c->prob.size_of_individual = p->size_of_individual;
+    c->prob.size_of_population = p->size_of_population;
+    c->prob.n_instances = p->n_instances;
+    c->prob.prob_mutation = p->prob_mutation;
+    c->prob.mutation_range = p->mutation_range;
+    c->prob.ga_crossover_prob = p->ga_crossover_prob;
+    c->prob.ga_gene_mutation_prob = p->ga_gene_mutation_prob;
+    c->prob.seed = p->seed;
+    c->prob.fitness_mode = p->fitness_mode;
     if (hipGetDevice(&c->device) != hipSuccess) { free_ctx(c); return fail(QE_ERR_DEVICE, "hipGetDevice"); }
     c->N = 1 << n;
     c->S = S;
@@ -421,21 +521,24 @@ qe_status qe_create(const qe_problem* p, qe_ctx** out) {
     a.R = (uint32_t)R;
     a.S = (uint32_t)S;
     a.Q = (uint32_t)Q;
+    a.genes = genes;
+    c->genes = genes;
+    c->target_elems = target_elems;
+    c->mixed = mixed;
     qe_status st = QE_OK;
-    const size_t NN = (size_t)c->N * c->N;
 #define ALLOC(ptr, n_) if (st == QE_OK) st = ctx_alloc(c, &(ptr), (n_))
     if (p->algorithm == QE_ALG_QEQEA) {
         ALLOC(a.slot, I * S);
         ALLOC(a.qrec, I * Q);
         ALLOC(a.su3_tab, (size_t)4 * SU3_TAB);
     } else {
-        ALLOC(a.genomes[0], I * P * L);
-        ALLOC(a.genomes[1], I * P * L);
+        ALLOC(a.genomes[0], (size_t)genes);
+        ALLOC(a.genomes[1], (size_t)genes);
     }
     float* t32 = nullptr;
     double* t64 = nullptr;
-    ALLOC(t32, I * NN * 2);
-    ALLOC(t64, I * NN * 2);
+    ALLOC(t32, (size_t)target_elems * 2);
+    ALLOC(t64, (size_t)target_elems * 2);
     a.target32 = t32;
     a.target64 = t64;
     ALLOC(a.inst_best_f, I);
@@ -445,16 +548,72 @@ qe_status qe_create(const qe_problem* p, qe_ctx** out) {
     }
     ALLOC(a.inst_best_gates, I * L);
     ALLOC(a.inst_best_angles, I * L);
-    ALLOC(c->gates, I * P * L);
+    ALLOC(c->gates, (size_t)genes);
     if (p->library == QE_LIB_ISING) ALLOC(c->angles, I * P * L);
     ALLOC(c->f, I * P);
     ALLOC(c->d_gen, 1);
     ALLOC(c->elite_cand, (int64_t)elite_cand_keys(I, P));
+    // mixed populations: per population and per circuit tables
+    std::vector<int32_t> h_cgoff;
+    std::vector<int64_t> h_goff, h_ctoff;
+    std::vector<int8_t> h_cn;
+    int32_t *d_in = nullptr, *d_iL = nullptr;
+    int64_t *d_igoff = nullptr, *d_itoff = nullptr;
+    if (mixed) {
+        c->inst_n.assign(inst_n, inst_n + I);
+        c->inst_L.assign(inst_L, inst_L + I);
+        c->inst_toff.resize(I);
+        h_goff.resize(I);
+        h_cn.resize(I * P);
+        h_cgoff.resize(I * P + 1);
+        h_ctoff.resize(I * P);
+        int64_t go = 0, to = 0;
+        for (size_t i = 0; i < I; ++i) {
+            h_goff[i] = go;
+            c->inst_toff[i] = to;
+            for (size_t k = 0; k < P; ++k) {
+                h_cn[i * P + k] = (int8_t)inst_n[i];
+                h_cgoff[i * P + k] = (int32_t)(go + (int64_t)k * inst_L[i]);
+                h_ctoff[i * P + k] = to;
+            }
+            go += (int64_t)P * inst_L[i];
+            to += (int64_t)1 << (2 * inst_n[i]);
+        }
+        h_cgoff[I * P] = (int32_t)go;
+        ALLOC(d_in, I);
+        ALLOC(d_iL, I);
+        ALLOC(d_igoff, I);
+        ALLOC(d_itoff, I);
+        ALLOC(c->circ_n, I * P);
+        ALLOC(c->circ_goff, I * P + 1);
+        ALLOC(c->circ_toff, I * P);
+        c->mix_work_bytes = qe_eval_workspace_bytes((int32_t)(I * P));
+        ALLOC(c->mix_order, c->mix_work_bytes / sizeof(int32_t));
+        ALLOC(c->mix_eval_work, c->mix_work_bytes / sizeof(int32_t));
+        a.inst_n = d_in;
+        a.inst_L = d_iL;
+        a.inst_goff = d_igoff;
+        a.inst_toff = d_itoff;
+    }
 #undef ALLOC
     if (st == QE_OK) st = device_error_word(&a.err);
     if (st != QE_OK) { std::string m = g_last_error; free_ctx(c); return fail(st, m); }
     a.gen_ptr = nullptr;
     hipError_t e = hipSuccess;
+    if (mixed) {
+        e = hipMemcpy(d_in, inst_n, I * sizeof(int32_t), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(d_iL, inst_L, I * sizeof(int32_t), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(d_igoff, h_goff.data(), I * sizeof(int64_t), hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(d_itoff, c->inst_toff.data(), I * sizeof(int64_t), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(c->circ_n, h_cn.data(), I * P, hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(c->circ_goff, h_cgoff.data(), (I * P + 1) * sizeof(int32_t), hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(c->circ_toff, h_ctoff.data(), I * P * sizeof(int64_t), hipMemcpyHostToDevice);
+        // the cost order of the circuits: widths and lengths never change
+        if (e == hipSuccess) e = launch_mix_sort(mixed_batch(c, c->gates), c->mix_order, nullptr);
+    }
     if (p->algorithm == QE_ALG_QEQEA) {
         // SU(3) step tables: cos/sin of a*domain/4096, domain pi/2 (angles)
         // and 2 pi (phases), computed in double, rounded to float.
@@ -467,9 +626,10 @@ qe_status qe_create(const qe_problem* p, qe_ctx** out) {
             tab[2 * SU3_TAB + k] = (float)std::cos(ph);
             tab[3 * SU3_TAB + k] = (float)std::sin(ph);
         }
-        e = hipMemcpy((void*)a.su3_tab, tab.data(), tab.size() * sizeof(float), hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy((void*)a.su3_tab, tab.data(), tab.size() * sizeof(float), hipMemcpyHostToDevice);
         if (e == hipSuccess) e = launch_qeqea_init(a, nullptr);
-    } else {
+    } else if (e == hipSuccess) {
         e = launch_ga_init(a, nullptr);
     }
     if (e == hipSuccess) e = hipDeviceSynchronize();
@@ -480,6 +640,18 @@ qe_status qe_create(const qe_problem* p, qe_ctx** out) {
     }
     *out = c;
     return QE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+qe_status qe_create(const qe_problem* p, qe_ctx** out) { return create_impl(p, nullptr, nullptr, out); }
+
+qe_status qe_create_mixed(const qe_problem* p, const int32_t* n_qubits_host, const int32_t* lengths_host,
+                          qe_ctx** out) {
+    if (!n_qubits_host || !lengths_host) return fail(QE_ERR_INVALID, "NULL width or length table");
+    return create_impl(p, n_qubits_host, lengths_host, out);
 }
 
 qe_status qe_destroy(qe_ctx* c) {
@@ -493,7 +665,7 @@ qe_status qe_destroy(qe_ctx* c) {
 qe_status qe_set_targets(qe_ctx* c, const void* t, void* stream) {
     QE_TRY(check_ctx(c, false));
     if (!t) return fail(QE_ERR_INVALID, "targets is NULL");
-    const size_t reals = (size_t)c->prob.n_instances * c->N * c->N * 2;
+    const size_t reals = (size_t)c->target_elems * 2;
     hipStream_t s = (hipStream_t)stream;
     QE_HIP(hipMemcpyAsync((void*)c->la.target64, t, reals * sizeof(double), hipMemcpyDeviceToDevice, s));
     QE_HIP(launch_c128_to_c64(c->la.target64, (float*)c->la.target32, (int64_t)reals, s));
@@ -522,7 +694,10 @@ qe_status qe_eval_population(qe_ctx* c, const uint16_t* gates, const uint32_t* a
     QE_TRY(check_ctx(c, true));
     if (!gates || !f) return fail(QE_ERR_INVALID, "NULL buffer");
     if (is_ising(c) && !angles) return fail(QE_ERR_INVALID, "the Ising library needs angles_dev");
-    QE_HIP(launch_eval_population(c->la, gates, is_ising(c) ? angles : nullptr, f, (hipStream_t)stream));
+    if (c->mixed)
+        QE_HIP(launch_mix_eval(mixed_batch(c, gates), c->mix_order, f, nullptr, nullptr, (hipStream_t)stream));
+    else
+        QE_HIP(launch_eval_population(c->la, gates, is_ising(c) ? angles : nullptr, f, (hipStream_t)stream));
     return QE_OK;
 }
 
@@ -532,11 +707,16 @@ qe_status qe_update(qe_ctx* c, uint64_t gen, const uint32_t* slots, const uint16
     if (!f || !gates) return fail(QE_ERR_INVALID, "NULL buffer");
     if (is_ising(c) && !angles) return fail(QE_ERR_INVALID, "the Ising library needs angles_dev");
     hipStream_t s = (hipStream_t)stream;
+    const bool fused = c->fused_gen >= 0 && (uint64_t)c->fused_gen == gen;
+    c->fused_gen = -1;
     if (c->prob.algorithm == QE_ALG_QEQEA) {
-        if (!slots) return fail(QE_ERR_INVALID, "slots is NULL");
-        QE_HIP(launch_scatter(c->la, gen, slots, f, s));
-        QE_TRY(prepare_decisions(c, gen, 1, s));
-        QE_HIP(launch_mutation_decisions(c->la, gen, s));
+        if (!slots && !fused)
+            return fail(QE_ERR_STATE, "slots_dev NULL needs qe_sample_eval of the same generation just before");
+        if (slots) QE_HIP(launch_scatter(c->la, gen, slots, f, s));
+        if (!fused) {
+            QE_TRY(prepare_decisions(c, gen, 1, s));
+            QE_HIP(launch_mutation_decisions(c->la, gen, s));
+        }
         QE_HIP(launch_qeqea_update(c->la, gen, slots, gates, is_ising(c) ? angles : nullptr, f, s));
     } else {
         QE_HIP(launch_ga_update(c->la, gen, f, s));
@@ -546,6 +726,7 @@ qe_status qe_update(qe_ctx* c, uint64_t gen, const uint32_t* slots, const uint16
 
 qe_status qe_generation(qe_ctx* c, uint64_t gen, float* f, void* stream) {
     QE_TRY(check_ctx(c, true));
+    c->fused_gen = -1;
     QE_TRY(prepare_decisions(c, gen, 1, (hipStream_t)stream));
     return enqueue_generation(c, c->la, gen, f ? f : c->f, (hipStream_t)stream);
 }
@@ -554,10 +735,13 @@ qe_status qe_sample_eval(qe_ctx* c, uint64_t gen, uint32_t* slots, uint16_t* gat
                          uint32_t* angles, float* f, void* stream) {
     QE_TRY(check_ctx(c, true));
     if (c->prob.algorithm != QE_ALG_QEQEA) return fail(QE_ERR_UNSUPPORTED, "qe_sample_eval is QEQEA only");
-    if (!slots || !gates || !f) return fail(QE_ERR_INVALID, "NULL buffer");
+    if (!gates || !f) return fail(QE_ERR_INVALID, "NULL buffer");
     if (is_ising(c) && !angles) return fail(QE_ERR_INVALID, "the Ising library needs angles_dev");
-    QE_HIP(launch_qeqea_fused(c->la, gen, slots, gates, is_ising(c) ? angles : nullptr, f, false,
+    // the generation's mutation decisions are drawn here, as in qe_generation
+    QE_TRY(prepare_decisions(c, gen, 1, (hipStream_t)stream));
+    QE_HIP(launch_qeqea_fused(c->la, gen, slots, gates, is_ising(c) ? angles : nullptr, f, true,
                               (hipStream_t)stream));
+    c->fused_gen = (int64_t)gen;
     return QE_OK;
 }
 
@@ -605,6 +789,7 @@ qe_status qe_run_graph(qe_ctx* c, uint64_t first_gen, int32_t n_gen, float* f_hi
     hipStream_t s = (hipStream_t)stream;
     hipGraphExec_t ex;
     QE_TRY(graph_for(c, n_gen, f_hist, &ex));
+    c->fused_gen = -1;
     QE_TRY(prepare_decisions(c, first_gen, (uint64_t)n_gen, s));
     QE_HIP(launch_gen_set(c->d_gen, first_gen, s));
     QE_HIP(hipGraphLaunch(ex, s));
@@ -635,29 +820,34 @@ qe_status qe_get_best(qe_ctx* c, int32_t inst, uint16_t* gates_host, uint32_t* a
     QE_TRY(check_ctx(c, false));
     if (inst < 0 || inst >= c->prob.n_instances) return fail(QE_ERR_INVALID, "instance out of range");
     QE_HIP(hipDeviceSynchronize());
-    const int L = c->prob.size_of_individual;
+    // rows of the best-circuit table hold size_of_individual entries (the
+    // longest genome of mixed populations); population inst uses its own L
+    const int row = c->prob.size_of_individual;
+    const int L = c->mixed ? c->inst_L[inst] : row;
+    const int n = c->mixed ? c->inst_n[inst] : c->prob.n_qubits;
+    const int64_t toff = c->mixed ? c->inst_toff[inst] : (int64_t)inst * c->N * c->N;
     float fv = 0;
     QE_HIP(hipMemcpy(&fv, c->la.inst_best_f + inst, sizeof(float), hipMemcpyDeviceToHost));
     if (gates_host)
-        QE_HIP(hipMemcpy(gates_host, c->la.inst_best_gates + (size_t)inst * L, L * sizeof(uint16_t),
+        QE_HIP(hipMemcpy(gates_host, c->la.inst_best_gates + (size_t)inst * row, L * sizeof(uint16_t),
                          hipMemcpyDeviceToHost));
     if (angles_host)
-        QE_HIP(hipMemcpy(angles_host, c->la.inst_best_angles + (size_t)inst * L, L * sizeof(uint32_t),
+        QE_HIP(hipMemcpy(angles_host, c->la.inst_best_angles + (size_t)inst * row, L * sizeof(uint32_t),
                          hipMemcpyDeviceToHost));
     if (f32_host) *f32_host = fv;
     if (f64_host) {
         if (!c->targets_set) return fail(QE_ERR_STATE, "qe_set_targets has not been called");
         qe_batch b{};
         b.num_circuits = 1;
-        b.uniform_n = c->prob.n_qubits;
+        b.uniform_n = n;
         b.uniform_L = L;
-        b.gates_dev = c->la.inst_best_gates + (size_t)inst * L;
+        b.gates_dev = c->la.inst_best_gates + (size_t)inst * row;
         b.num_gates = L;
         b.target_stride = 0;
-        b.targets_dev = c->la.target64 + (size_t)2 * inst * c->N * c->N;
-        b.num_target_elems = (int64_t)c->N * c->N;
+        b.targets_dev = c->la.target64 + (size_t)2 * toff;
+        b.num_target_elems = (int64_t)1 << (2 * n);
         b.fitness_mode = c->prob.fitness_mode;
-        b.angles_dev = is_ising(c) ? c->la.inst_best_angles + (size_t)inst * L : nullptr;
+        b.angles_dev = is_ising(c) ? c->la.inst_best_angles + (size_t)inst * row : nullptr;
         double* d = nullptr;
         QE_HIP(hipMalloc(&d, sizeof(double)));
         qe_status st = qe_eval_fitness_fp64(&b, d, nullptr, nullptr, nullptr);
@@ -681,14 +871,14 @@ struct Section {
 
 std::vector<Section> state_sections(qe_ctx* c) {
     const LoopArgs& a = c->la;
-    const size_t I = c->prob.n_instances, P = c->prob.size_of_population, L = c->prob.size_of_individual;
+    const size_t I = c->prob.n_instances, L = c->prob.size_of_individual;
     std::vector<Section> v;
     if (c->prob.algorithm == QE_ALG_QEQEA) {
         v.push_back({a.slot, I * c->S * sizeof(SlotRec)});
         v.push_back({a.qrec, I * c->Q * sizeof(QutritRec)});
     } else {
-        v.push_back({a.genomes[0], I * P * L * 2});
-        v.push_back({a.genomes[1], I * P * L * 2});
+        v.push_back({a.genomes[0], (size_t)c->genes * 2});
+        v.push_back({a.genomes[1], (size_t)c->genes * 2});
     }
     v.push_back({a.inst_best_f, I * 4});
     v.push_back({a.inst_best_gates, I * L * 2});
@@ -696,10 +886,35 @@ std::vector<Section> state_sections(qe_ctx* c) {
     return v;
 }
 
+// Field by field (a caller's struct may carry arbitrary padding bytes, and
+// +0 and -0 are the same parameter value).
+bool same_problem(const qe_problem& x, const qe_problem& y) {
+    return x.n_qubits == y.n_qubits && x.library == y.library && x.algorithm == y.algorithm &&
+           x.size_of_individual == y.size_of_individual &&
+           x.size_of_population == y.size_of_population && x.n_instances == y.n_instances &&
+           x.prob_mutation == y.prob_mutation && x.mutation_range == y.mutation_range &&
+           x.ga_crossover_prob == y.ga_crossover_prob &&
+           x.ga_gene_mutation_prob == y.ga_gene_mutation_prob && x.seed == y.seed &&
+           x.fitness_mode == y.fitness_mode;
+}
+
+// Identifies the per-population widths and lengths of a mixed context
+// (FNV-1a over both tables, never 0); 0 for a uniform one.
+uint32_t layout_tag(const qe_ctx* c) {
+    if (!c->mixed) return 0u;
+    uint32_t h = 2166136261u;
+    auto mix = [&h](int32_t v) {
+        for (int b = 0; b < 4; ++b) { h ^= (uint32_t)(v >> (8 * b)) & 0xFFu; h *= 16777619u; }
+    };
+    for (int32_t v : c->inst_n) mix(v);
+    for (int32_t v : c->inst_L) mix(v);
+    return h | 1u;
+}
+
 struct CkptHeader {
     char magic[8];
     uint32_t version;
-    uint32_t reserved;
+    uint32_t layout;       // layout_tag of the context
     qe_problem prob;
     uint64_t payload;
 };
@@ -721,6 +936,7 @@ qe_status qe_checkpoint(qe_ctx* c, void* buf, size_t* size) {
     std::memcpy(h.magic, "QECKPT03", 8);
     h.version = 3;
     h.prob = c->prob;
+    h.layout = layout_tag(c);
     h.payload = payload;
     std::memcpy(buf, &h, sizeof(h));
     char* p = static_cast<char*>(buf) + sizeof(h);
@@ -739,8 +955,9 @@ qe_status qe_restore(qe_ctx* c, const void* buf, size_t size) {
     std::memcpy(&h, buf, sizeof(h));
     if (std::memcmp(h.magic, "QECKPT03", 8) != 0 || h.version != 3)
         return fail(QE_ERR_INVALID, "not a libqe checkpoint");
-    if (std::memcmp(&h.prob, &c->prob, sizeof(qe_problem)) != 0)
+    if (!same_problem(h.prob, c->prob) || h.layout != layout_tag(c))
         return fail(QE_ERR_INVALID, "checkpoint was written for a different problem");
+    c->fused_gen = -1;
     auto secs = state_sections(c);
     size_t payload = 0;
     for (auto& s : secs) payload += s.bytes;
@@ -760,19 +977,22 @@ qe_status qe_state_read(qe_ctx* c, int32_t which, void* dst, int64_t* elems, voi
     QE_TRY(check_ctx(c, false));
     if (!elems) return fail(QE_ERR_INVALID, "elems is NULL");
     const LoopArgs& a = c->la;
-    const size_t I = c->prob.n_instances, P = c->prob.size_of_population, L = c->prob.size_of_individual;
+    const size_t I = c->prob.n_instances;
     const bool q = c->prob.algorithm == QE_ALG_QEQEA;
     int64_t n = 0;
     switch (which) {
         case 0: case 2: case 3: n = q ? (int64_t)(I * c->S) : 0; break;
         case 1: case 4: n = q ? (int64_t)(I * c->Q * 6) : 0; break;
-        case 5: case 6: n = q ? 0 : (int64_t)(I * P * L); break;
+        case 5: case 6: n = q ? 0 : c->genes; break;
+        case 7: n = q ? (int64_t)(2 * I * a.MW) : 0; break;
         default: return fail(QE_ERR_INVALID, "unknown state field");
     }
     *elems = n;
     if (!dst || n == 0) return QE_OK;
     hipStream_t s = (hipStream_t)stream;
-    if (which >= 5)
+    if (which == 7)
+        QE_HIP(hipMemcpyAsync(dst, a.mutmask, (size_t)n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+    else if (which >= 5)
         QE_HIP(hipMemcpyAsync(dst, a.genomes[which - 5], (size_t)n * sizeof(uint16_t),
                               hipMemcpyDeviceToDevice, s));
     else

@@ -280,7 +280,8 @@ __global__ __launch_bounds__(256) void mix_kernel(BatchArgs a, const int32_t* __
     const int per = mix_per_item(k);
     const int local = (item - meta[8 + k]) * per;
     const int sub = per == 1 ? 0 : (per == 2 ? wave >> 1 : wave);
-    const int b = local + sub < meta[16 + k] ? order[meta[k] + local + sub] : -1;
+    int b = local + sub < meta[16 + k] ? order[meta[k] + local + sub] : -1;
+    if (b >= a.B) b = -1;        // an order written for another batch never indexes past this one
     switch (k) {
         // (only the width-4 items use gate tables: they live in the part of
         // M that four 16 x 16 matrices leave free)
@@ -315,8 +316,17 @@ __global__ __launch_bounds__(256) void lds_kernel(BatchArgs a, Real* __restrict_
     const Real* T = (IDENT || it.err) ? nullptr : reinterpret_cast<const Real*>(a.targets) + 2 * it.toff;
     Real* U = nullptr;
     if (IDENT) U = U_out + (size_t)2 * ((size_t)1 << (2 * a.uniform_n)) * b;
+    // dynamic LDS: two planes of 4^n reals for the batch's (largest) width
+    Real* Mr = generic_lds<Real>();
+    Real* Mi = Mr + ((size_t)1 << (2 * (a.uniform_n > 0 ? a.uniform_n : MAX_QUBITS)));
     lds_generic_body<Real, IDENT>(it.n, it.L, it.g, it.ang, T, it.err, f + (f ? b : 0),
-                                  g ? g + b : nullptr, delta ? delta + b : nullptr, U, a.err, a.mode);
+                                  g ? g + b : nullptr, delta ? delta + b : nullptr, U, a.err, a.mode,
+                                  Mr, Mi);
+}
+
+// LDS bytes of lds_kernel for a batch
+static size_t lds_kernel_bytes(const BatchArgs& a, size_t real_bytes) {
+    return generic_lds_bytes(a.uniform_n > 0 ? a.uniform_n : MAX_QUBITS, real_bytes);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -379,10 +389,8 @@ hipError_t launch_eval_fp32(const BatchArgs& a, int path, float* f, float* g, fl
         launch_width<false>(a, a.uniform_n, use_lds(a.uniform_n, path), f, g, delta, s);
     } else if (path == QE_PATH_FP32 && work) {
         // one launch over width-sorted work items (LDS-staged for n >= 4)
-        int32_t* meta = work;
-        int32_t* order = work + 32;
-        mix_bucket_kernel<<<1, 1024, 0, s>>>(a, order, meta);
-        mix_kernel<<<a.B, 256, 0, s>>>(a, order, meta, f, g, delta);
+        mix_bucket_kernel<<<1, 1024, 0, s>>>(a, work + MIX_WORK_META, work);
+        mix_kernel<<<a.B, 256, 0, s>>>(a, work + MIX_WORK_META, work, f, g, delta);
     } else {
         width_check_kernel<<<(a.B + 255) / 256, 256, 0, s>>>(a, f, g, delta);
         for (int n = 1; n <= MAX_QUBITS; ++n)
@@ -391,28 +399,40 @@ hipError_t launch_eval_fp32(const BatchArgs& a, int path, float* f, float* g, fl
     return hipGetLastError();
 }
 
+hipError_t launch_mix_sort(const BatchArgs& a, int32_t* work, hipStream_t s) {
+    if (a.B > 0) mix_bucket_kernel<<<1, 1024, 0, s>>>(a, work + MIX_WORK_META, work);
+    return hipGetLastError();
+}
+
+hipError_t launch_mix_eval(const BatchArgs& a, const int32_t* work, float* f, float* g, float* delta,
+                           hipStream_t s) {
+    if (a.B > 0) mix_kernel<<<a.B, 256, 0, s>>>(a, work + MIX_WORK_META, work, f, g, delta);
+    return hipGetLastError();
+}
+
 hipError_t launch_eval_lds(const BatchArgs& a, bool fp64, void* f, void* g, void* delta,
                            hipStream_t s) {
     if (a.B == 0) return hipSuccess;
     if (fp64)
-        lds_kernel<double, false><<<a.B, 256, 0, s>>>(a, (double*)f, (double*)g, (double*)delta,
-                                                      nullptr);
+        lds_kernel<double, false><<<a.B, 256, lds_kernel_bytes(a, 8), s>>>(a, (double*)f, (double*)g,
+                                                                           (double*)delta, nullptr);
     else
-        lds_kernel<float, false><<<a.B, 256, 0, s>>>(a, (float*)f, (float*)g, (float*)delta,
-                                                     nullptr);
+        lds_kernel<float, false><<<a.B, 256, lds_kernel_bytes(a, 4), s>>>(a, (float*)f, (float*)g,
+                                                                          (float*)delta, nullptr);
     return hipGetLastError();
 }
 
 hipError_t launch_unitary(const BatchArgs& a, bool fp64, void* out, hipStream_t s) {
     if (a.B == 0) return hipSuccess;
     if (fp64) {
-        lds_kernel<double, true><<<a.B, 256, 0, s>>>(a, nullptr, nullptr, nullptr, (double*)out);
+        lds_kernel<double, true><<<a.B, 256, lds_kernel_bytes(a, 8), s>>>(a, nullptr, nullptr, nullptr,
+                                                                          (double*)out);
     } else {
         float* o = (float*)out;
         switch (a.uniform_n) {
-            case 1: lds_kernel<float, true><<<a.B, 256, 0, s>>>(a, nullptr, nullptr, nullptr, o); break;
-            case 2: lds_kernel<float, true><<<a.B, 256, 0, s>>>(a, nullptr, nullptr, nullptr, o); break;
-            case 3: lds_kernel<float, true><<<a.B, 256, 0, s>>>(a, nullptr, nullptr, nullptr, o); break;
+            case 1: lds_kernel<float, true><<<a.B, 256, lds_kernel_bytes(a, 4), s>>>(a, nullptr, nullptr, nullptr, o); break;
+            case 2: lds_kernel<float, true><<<a.B, 256, lds_kernel_bytes(a, 4), s>>>(a, nullptr, nullptr, nullptr, o); break;
+            case 3: lds_kernel<float, true><<<a.B, 256, lds_kernel_bytes(a, 4), s>>>(a, nullptr, nullptr, nullptr, o); break;
             case 4:
                 if (a.angles) lds32_kernel<4, 1, false, true, true><<<a.B, 64, 0, s>>>(a, nullptr, nullptr, nullptr, o);
                 else lds32_kernel<4, 1, false, true><<<a.B, 64, 0, s>>>(a, nullptr, nullptr, nullptr, o);

@@ -1076,7 +1076,7 @@ __device__ __forceinline__ void lds_fitness(const Real* Mr, const Real* Mi, int 
     Real off = 0, tr = 0, ti = 0;
     if (ok) {
         for (int e = tid; e < NN; e += nt) {
-            const int i = e / N, j = e % N;
+            const int i = e / N, j = e - i * N;
             if (i == j) { tr += Mr[e]; ti += Mi[e]; }
             else off += Mr[e] * Mr[e] + Mi[e] * Mi[e];
         }
@@ -1113,22 +1113,34 @@ __device__ __forceinline__ void lds_fitness(const Real* Mr, const Real* Mi, int 
     }
 }
 
+// Dynamic LDS of the generic-body kernels: two planes of 4^n reals.
+template <typename Real>
+__device__ __forceinline__ Real* generic_lds() {
+    extern __shared__ __align__(16) unsigned char qe_generic_lds[];
+    return reinterpret_cast<Real*>(qe_generic_lds);
+}
+__host__ __device__ inline size_t generic_lds_bytes(int n, size_t real_bytes) {
+    return (size_t)2 * ((size_t)1 << (2 * n)) * real_bytes;
+}
+
 // angles: the gates' angles (u32 turn fractions, parallel to gates) or
-// NULL, in which case the Ising kinds are invalid descriptors.
+// NULL, in which case the Ising kinds are invalid descriptors.  Mr, Mi: LDS
+// for the real and imaginary parts of the 2^n x 2^n matrix (the caller sizes
+// them for its widths).
 template <typename Real, bool IDENT>
 __device__ __forceinline__ void lds_generic_body(int n, int L, const uint16_t* gates,
                                                  const uint32_t* angles, const Real* T, uint32_t err,
                                                  Real* f, Real* g, Real* delta, Real* U,
-                                                 uint32_t* errw, int mode = QE_FIT_EQ11) {
-    __shared__ Real Mr[4096], Mi[4096];
+                                                 uint32_t* errw, int mode, Real* Mr, Real* Mi) {
     __shared__ Real red[8];
     const int tid = threadIdx.x, nt = blockDim.x;
-    const int N = 1 << (err == QE_DEVERR_WIDTH ? 1 : n);
+    const int lg = err == QE_DEVERR_WIDTH ? 1 : n;     // log2 of the matrix size
+    const int N = 1 << lg;
     const int NN = N * N;
     bool ok = err == 0;
     if (ok) {
         for (int e = tid; e < NN; e += nt) {
-            const int i = e / N, j = e % N;
+            const int i = e >> lg, j = e & (N - 1);
             if (IDENT) {
                 Mr[e] = (i == j) ? (Real)1 : (Real)0;
                 Mi[e] = 0;
@@ -1154,7 +1166,7 @@ __device__ __forceinline__ void lds_generic_body(int n, int L, const uint16_t* g
                     // e^{i theta/2} where they differ
                     const int cpos = n - 1 - (int)((d >> 8) & 15);
                     for (int e = tid; e < NN; e += nt) {
-                        const int i = e / N;
+                        const int i = e >> lg;
                         const Real sg = (((i >> tpos) ^ (i >> cpos)) & 1) ? s : -s;
                         const Real ar = Mr[e], ai = Mi[e];
                         Mr[e] = c * ar - sg * ai;
@@ -1169,7 +1181,7 @@ __device__ __forceinline__ void lds_generic_body(int n, int L, const uint16_t* g
             }
             const int cb = kind_controlled(kind) ? 1 << (n - 1 - (int)((d >> 8) & 15)) : 0;
             for (int e = tid; e < NN / 2; e += nt) {
-                const int p = e / N, j = e % N;
+                const int p = e >> lg, j = e & (N - 1);
                 const int i0 = ((p >> tpos) << (tpos + 1)) | (p & (tb - 1));
                 if (cb && !(i0 & cb)) continue;
                 const int i1 = i0 | tb;

@@ -26,11 +26,22 @@ struct BatchArgs {
 // api.hip: per-width schedule of the FP32 path (true = LDS-staged kernel)
 bool schedule_lds(int n);
 
+// Workspace of a mixed-width batch: MIX_WORK_META int32 of item table, then
+// the B circuit indices in cost order.
+constexpr int MIX_WORK_META = 32;
+
 // eval.hip
-// work: 32 + B int32 of device workspace for mixed-width batches (order of
-// circuits by width); NULL selects one filtered launch per width.
+// work: MIX_WORK_META + B int32 of device workspace for mixed-width batches
+// (order of circuits by width and length); NULL selects one filtered launch
+// per width.
 hipError_t launch_eval_fp32(const BatchArgs& a, int path, float* f, float* g, float* delta,
                             int32_t* work, hipStream_t s);
+// The two halves of the sorted mixed-width launch: the cost order of the
+// batch's circuits into work (it depends only on widths and lengths), and
+// the evaluation of a batch in an order computed before.
+hipError_t launch_mix_sort(const BatchArgs& a, int32_t* work, hipStream_t s);
+hipError_t launch_mix_eval(const BatchArgs& a, const int32_t* work, float* f, float* g, float* delta,
+                           hipStream_t s);
 hipError_t launch_eval_lds(const BatchArgs& a, bool fp64, void* f, void* g, void* delta,
                            hipStream_t s);
 hipError_t launch_unitary(const BatchArgs& a, bool fp64, void* out, hipStream_t s);
@@ -93,11 +104,20 @@ struct LoopArgs {
     uint32_t* mutmask;                 // [2][I][MW]
     uint32_t MW;                       // words per instance: ceil(P / 32)
     float* inst_best_f;                // per instance
-    uint16_t* inst_best_gates;         // [I][L]
+    uint16_t* inst_best_gates;         // [I][L] (L = the longest genome of a mixed GA)
     uint32_t* inst_best_angles;        // [I][L] (Ising library; zero otherwise)
     const float* su3_tab;              // [4][4096]: cos/sin of angles, cos/sin of phases
     const uint64_t* gen_ptr;           // device generation base (graphs) or null
     uint32_t* err;
+    // Mixed GA populations (null otherwise): population i has inst_n[i]
+    // wires and genomes of inst_L[i] genes; its P genomes start at gene
+    // inst_goff[i] of each genome buffer, its target at complex element
+    // inst_toff[i] of the target buffers.  n and L then hold the maxima.
+    const int32_t* inst_n;
+    const int32_t* inst_L;
+    const int64_t* inst_goff;
+    const int64_t* inst_toff;
+    int64_t genes;                     // genes per genome buffer (all populations)
 };
 
 // loop.hip

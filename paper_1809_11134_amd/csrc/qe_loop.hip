@@ -158,6 +158,19 @@ __global__ void ga_init_kernel(LoopArgs a) {
     a.genomes[0][idx] = lib_desc(a.lib, a.n, (int)scale_u32(w.x, (uint32_t)lib_size(a.lib, a.n)));
 }
 
+// Mixed populations: workgroup i draws the P x inst_L[i] genes of population
+// i over the library of its own width.
+__global__ void ga_init_mixed_kernel(LoopArgs a) {
+    const uint32_t i = blockIdx.x;
+    const int n = a.inst_n[i];
+    const uint32_t per = (uint32_t)a.P * (uint32_t)a.inst_L[i], nl = (uint32_t)lib_size(a.lib, n);
+    uint16_t* g = a.genomes[0] + a.inst_goff[i];
+    for (uint32_t item = threadIdx.x; item < per; item += blockDim.x) {
+        const u32x4 w = draw(a.seed, TAG_INIT, GEN_INIT, i, item);
+        g[item] = lib_desc(a.lib, n, (int)scale_u32(w.x, nl));
+    }
+}
+
 __global__ void inst_best_init_kernel(LoopArgs a) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.I) return;
@@ -201,7 +214,7 @@ __global__ void qeqea_sample_kernel(LoopArgs a, uint64_t gen64, uint32_t* __rest
 
 __global__ void ga_copy_kernel(LoopArgs a, uint64_t gen64, uint16_t* __restrict__ gates) {
     const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (size_t)a.I * a.P * a.L) return;
+    if (idx >= (size_t)a.genes) return;
     gates[idx] = a.genomes[gen_of(a, gen64) & 1][idx];
 }
 
@@ -726,9 +739,13 @@ __global__ __launch_bounds__(256) void ga_update_kernel(LoopArgs a, uint64_t gen
     __shared__ int besti[4];
     const uint32_t gen = gen_of(a, gen64);
     const uint32_t i = blockIdx.x;
-    const int P = a.P, L = a.L, tid = threadIdx.x, nt = blockDim.x;
-    const uint16_t* cur = a.genomes[gen & 1] + (size_t)i * P * L;
-    uint16_t* nxt = a.genomes[(gen + 1) & 1] + (size_t)i * P * L;
+    const int P = a.P, tid = threadIdx.x, nt = blockDim.x;
+    // population i's width, genome length and genomes (mixed populations
+    // carry their own)
+    const int n = a.inst_n ? a.inst_n[i] : a.n, L = a.inst_L ? a.inst_L[i] : a.L;
+    const size_t base = a.inst_goff ? (size_t)a.inst_goff[i] : (size_t)i * P * L;
+    const uint16_t* cur = a.genomes[gen & 1] + base;
+    uint16_t* nxt = a.genomes[(gen + 1) & 1] + base;
     const float* fi = f + (size_t)i * P;
     // weights and best (lowest index among the maxima)
     float best = -1.0f;
@@ -790,17 +807,17 @@ __global__ __launch_bounds__(256) void ga_update_kernel(LoopArgs a, uint64_t gen
         }
     }
     __syncthreads();
-    const uint32_t nl = (uint32_t)lib_size(a.lib, a.n);
+    const uint32_t nl = (uint32_t)lib_size(a.lib, n);
     for (size_t e = tid; e < (size_t)P * L; e += nt) {
         const u32x4 w = draw(a.seed, TAG_GA_MUT, gen, i, (uint32_t)e);
-        if ((uint64_t)w.x < a.thr_pg) nxt[e] = lib_desc(a.lib, a.n, (int)scale_u32(w.y, nl));
+        if ((uint64_t)w.x < a.thr_pg) nxt[e] = lib_desc(a.lib, n, (int)scale_u32(w.y, nl));
     }
     __syncthreads();
     for (int pos = tid; pos < L; pos += nt) nxt[pos] = cur[(size_t)bi * L + pos];
-    // best circuit ever seen by this population
+    // best circuit ever seen by this population (rows of a.L entries)
     if (best > a.inst_best_f[i]) {
         for (int pos = tid; pos < L; pos += nt)
-            a.inst_best_gates[(size_t)i * L + pos] = cur[(size_t)bi * L + pos];
+            a.inst_best_gates[(size_t)i * a.L + pos] = cur[(size_t)bi * L + pos];
         __syncthreads();
         if (tid == 0) a.inst_best_f[i] = best;
     }
@@ -913,10 +930,13 @@ __global__ __launch_bounds__(256) void elite_eval_kernel(LoopArgs a, const uint1
     const int i = blockIdx.x / k, e = blockIdx.x % k;
     const int c = idx[(size_t)i * k + e];
     uint32_t err = (c < 0 || c >= a.P) ? (uint32_t)QE_DEVERR_RANGE : 0u;
-    const size_t row = ((size_t)i * a.P + (err ? 0 : c)) * a.L;
-    const double* T = a.target64 + (size_t)2 * i * ((size_t)1 << (2 * a.n));
-    lds_generic_body<double, false>(a.n, a.L, gates + row, angles ? angles + row : nullptr, T, err,
-                                    f64 + blockIdx.x, nullptr, nullptr, nullptr, a.err, a.fit_mode);
+    const int n = a.inst_n ? a.inst_n[i] : a.n, L = a.inst_L ? a.inst_L[i] : a.L;
+    const size_t row = (a.inst_goff ? (size_t)a.inst_goff[i] : (size_t)i * a.P * L) + (size_t)(err ? 0 : c) * L;
+    const double* T = a.target64 + 2 * (a.inst_toff ? (size_t)a.inst_toff[i] : (size_t)i << (2 * n));
+    double* Mr = generic_lds<double>();         // dynamic LDS for the context's largest width
+    lds_generic_body<double, false>(n, L, gates + row, angles ? angles + row : nullptr, T, err,
+                                    f64 + blockIdx.x, nullptr, nullptr, nullptr, a.err, a.fit_mode,
+                                    Mr, Mr + ((size_t)1 << (2 * a.n)));
 }
 
 // Complex128 -> complex64 copy of the targets for the FP32 path.
@@ -935,7 +955,8 @@ hipError_t launch_qeqea_init(const LoopArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_ga_init(const LoopArgs& a, hipStream_t s) {
-    ga_init_kernel<<<blocks((size_t)a.I * a.P * a.L, 256), 256, 0, s>>>(a);
+    if (a.inst_n) ga_init_mixed_kernel<<<a.I, 256, 0, s>>>(a);
+    else ga_init_kernel<<<blocks((size_t)a.I * a.P * a.L, 256), 256, 0, s>>>(a);
     inst_best_init_kernel<<<blocks(a.I, 256), 256, 0, s>>>(a);
     return hipGetLastError();
 }
@@ -967,7 +988,7 @@ hipError_t launch_qeqea_sample(const LoopArgs& a, uint64_t gen, uint32_t* slots,
 }
 
 hipError_t launch_ga_copy(const LoopArgs& a, uint64_t gen, uint16_t* gates, hipStream_t s) {
-    ga_copy_kernel<<<blocks((size_t)a.I * a.P * a.L, 256), 256, 0, s>>>(a, gen, gates);
+    ga_copy_kernel<<<blocks((size_t)a.genes, 256), 256, 0, s>>>(a, gen, gates);
     return hipGetLastError();
 }
 
@@ -1107,7 +1128,7 @@ hipError_t launch_elite_select(const LoopArgs& a, const float* f, int k, int32_t
 
 hipError_t launch_elite_eval(const LoopArgs& a, const uint16_t* gates, const uint32_t* angles, int k,
                              const int32_t* idx, double* f64, hipStream_t s) {
-    elite_eval_kernel<<<a.I * k, 256, 0, s>>>(a, gates, angles, k, idx, f64);
+    elite_eval_kernel<<<a.I * k, 256, generic_lds_bytes(a.n, sizeof(double)), s>>>(a, gates, angles, k, idx, f64);
     return hipGetLastError();
 }
 

@@ -162,6 +162,24 @@ def workload_uneven(count=16384, per_population=64, seed_offset=3):
                 target_index=np.array(tidx, np.int64))
 
 
+def workload_mixed_ga(populations=256, P=64, seed_offset=8):
+    """Mixed GA search: `populations` independent GA populations of P
+    circuits, population i on n_i ~ U{3..6} wires with genomes of
+    L_i ~ U[8,64] gates of {H,T,CNOT,CV,CV+}, its target a product of
+    U[8,40] gates of the same library (16384 evaluations per generation at
+    the defaults), 50 generations."""
+    rng = np.random.default_rng(SEED_BASE + seed_offset)
+    widths, lengths, tgt = [], [], []
+    for _ in range(populations):
+        n = int(rng.integers(3, 7))
+        widths.append(n)
+        lengths.append(int(rng.integers(8, 65)))
+        tgt.append(random_target_gates(rng, n, int(rng.integers(8, 41)), LIB_HT_NCV))
+    return dict(name=f"mixed_ga_i{populations}_p{P}", lib=LIB_HT_NCV, algorithm="ga", P=P,
+                instances=populations, generations=50, widths=widths, lengths=lengths,
+                target_gates=tgt, seed=SEED_BASE + seed_offset)
+
+
 def workload_precision_n6(P=8192, L=48):
     """n=6, library {H,T,CNOT,CV,CV+}, P=8192 circuits x 48 gates, target =
     product of 40 library gates.  A quarter of the circuits are uniform

@@ -90,6 +90,9 @@ def load():
         "qe_lib_table": [i32, i32, vp],
         "qe_set_schedule": [i32, i32],
         "qe_get_schedule": [i32, P(i32)],
+        "qe_probe_lds": [i32, i32, i32, vp, P(ctypes.c_double), vp],
+        "qe_create_mixed": [P(Problem), vp, vp, P(vp)],
+        "qe_eval_fitness_ws": [P(Batch), i32, vp, vp, vp, vp, ctypes.c_size_t, vp],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -97,6 +100,8 @@ def load():
         fn.restype = i32
     L.qe_lib_size.argtypes = [i32, i32]
     L.qe_lib_size.restype = i32
+    L.qe_eval_workspace_bytes.argtypes = [i32]
+    L.qe_eval_workspace_bytes.restype = ctypes.c_size_t
     L.qe_last_error.restype = ctypes.c_char_p
     L.qe_version.restype = ctypes.c_char_p
     _lib = L
@@ -202,20 +207,36 @@ def make_batch(gates, targets, n=None, L=None, nq=None, goff=None, toff=None, ta
     return b, keep, B
 
 
+def eval_workspace(B, device):
+    """A device workspace for qe_eval_fitness_ws of B circuits (torch memory)."""
+    nbytes = load().qe_eval_workspace_bytes(B)
+    return torch.empty((nbytes + 3) // 4, dtype=torch.int32, device=device)
+
+
 def eval_fitness(gates, targets, n=None, L=None, nq=None, goff=None, toff=None, target_stride=0,
                  path=PATH_FP32, want_g=False, want_delta=False, stream=None, fitness_mode=0,
-                 angles=None):
+                 angles=None, workspace=True, ctx=None):
     """Eq. 11 fitness (or, with fitness_mode=FIT_PHASE_INSENSITIVE, the
     phase-insensitive fitness) of a batch on the FP32 or MFMA paths.  targets
-    complex64; angles as in make_batch.  Returns (f, g or None, delta or None)
-    as float32 tensors."""
+    complex64; angles as in make_batch.  A mixed-width batch takes the
+    cost-sorted single launch with a workspace (workspace=True: allocated
+    here; or a tensor from eval_workspace) and one launch per width with
+    workspace=False (qe_eval_fitness, lent ctx's workspace when ctx is a
+    mixed context).  Returns (f, g or None, delta or None) as float32
+    tensors."""
     targets = targets.to(torch.complex64) if targets.dtype != torch.complex64 else targets
     b, keep, B = make_batch(gates, targets, n, L, nq, goff, toff, target_stride, fitness_mode, angles)
     dev = targets.device
     f = torch.empty(B, dtype=torch.float32, device=dev)
     g = torch.empty(B, dtype=torch.float32, device=dev) if want_g else None
     d = torch.empty(B, dtype=torch.float32, device=dev) if want_delta else None
-    _call("qe_eval_fitness", None, ctypes.byref(b), path, _ptr(f), _ptr(g), _ptr(d), _stream(stream))
+    if workspace is not False and n is None:
+        ws = eval_workspace(B, dev) if workspace is True else workspace
+        _call("qe_eval_fitness_ws", ctypes.byref(b), path, _ptr(f), _ptr(g), _ptr(d), _ptr(ws),
+              ws.numel() * 4, _stream(stream))
+    else:
+        h = ctx.handle if ctx is not None else None
+        _call("qe_eval_fitness", h, ctypes.byref(b), path, _ptr(f), _ptr(g), _ptr(d), _stream(stream))
     return f, g, d
 
 
@@ -266,11 +287,20 @@ def get_schedule(n):
 
 
 class Context:
-    """A QEQEA or GA search: ctx-owned encoding on the current device."""
+    """A QEQEA or GA search: ctx-owned encoding on the current device.
+    widths / lengths (lists of I entries, GA only): populations of their own
+    width and genome length (qe_create_mixed); n and L are then ignored."""
 
     def __init__(self, n, library, algorithm, L, P, instances=1, prob_mutation=0.1,
                  mutation_range=0.7853981633974483, ga_crossover_prob=0.9,
-                 ga_gene_mutation_prob=None, seed=0, fitness_mode=0):
+                 ga_gene_mutation_prob=None, seed=0, fitness_mode=0, widths=None, lengths=None):
+        self.mixed = widths is not None
+        if self.mixed:
+            instances = len(widths)
+            if lengths is None or len(lengths) != instances:
+                raise ValueError("one genome length per population")
+            n, L = max(widths), max(lengths)
+            self.widths, self.lengths = [int(x) for x in widths], [int(x) for x in lengths]
         if ga_gene_mutation_prob is None:
             ga_gene_mutation_prob = 1.0 / L
         self.problem = Problem(n, library, algorithm, L, P, instances, prob_mutation,
@@ -280,7 +310,14 @@ class Context:
         self.algorithm = algorithm
         self.ising = library == LIB_ISING
         h = ctypes.c_void_p(0)
-        _call("qe_create", ctypes.byref(self.problem), ctypes.byref(h))
+        if self.mixed:
+            wn = (ctypes.c_int32 * instances)(*self.widths)
+            wl = (ctypes.c_int32 * instances)(*self.lengths)
+            _call("qe_create_mixed", ctypes.byref(self.problem), wn, wl, ctypes.byref(h))
+            self.genes = P * sum(self.lengths)
+        else:
+            _call("qe_create", ctypes.byref(self.problem), ctypes.byref(h))
+            self.genes = instances * P * L
         self.handle = h
         self._keep = []
 
@@ -311,10 +348,12 @@ class Context:
                            device=torch.device("cuda", torch.cuda.current_device()))
 
     def sample(self, gen, stream=None):
-        """(slots, gates), and for the Ising library (slots, gates, angles)."""
+        """(slots, gates), and for the Ising library (slots, gates, angles).
+        Mixed populations: gates is flat, population by population."""
         dev = torch.device("cuda", torch.cuda.current_device())
         slots = torch.empty((self.circuits, self.L), dtype=torch.int32, device=dev)
-        gates = torch.empty((self.circuits, self.L), dtype=torch.int16, device=dev)
+        shape = (self.genes,) if self.mixed else (self.circuits, self.L)
+        gates = torch.empty(shape, dtype=torch.int16, device=dev)
         angles = self._new_angles()
         _call("qe_sample", self.handle, gen, _ptr(slots), _ptr(gates), _ptr(angles), _stream(stream))
         return (slots, gates, angles) if self.ising else (slots, gates)
@@ -326,6 +365,8 @@ class Context:
         return f
 
     def update(self, gen, slots, gates, f, angles=None, stream=None):
+        """slots None: right after sample_eval(gen), which left the segment
+        keys and decisions (the slots are drawn again)."""
         _call("qe_update", self.handle, gen, _ptr(slots), _ptr(_gates(gates)), _ptr(_angles(angles)),
               _ptr(f.contiguous()), _stream(stream))
 
@@ -336,10 +377,12 @@ class Context:
         _call("qe_generation", self.handle, gen, _ptr(f), _stream(stream))
         return f
 
-    def sample_eval(self, gen, slots=None, gates=None, f=None, stream=None, angles=None):
-        """(slots, gates, f), and for the Ising library (slots, gates, angles, f)."""
+    def sample_eval(self, gen, slots=None, gates=None, f=None, stream=None, angles=None,
+                    keep_slots=True):
+        """(slots, gates, f), and for the Ising library (slots, gates, angles, f);
+        keep_slots=False leaves the slot indices out (slots is None)."""
         dev = torch.device("cuda", torch.cuda.current_device())
-        if slots is None:
+        if slots is None and keep_slots:
             slots = torch.empty((self.circuits, self.L), dtype=torch.int32, device=dev)
         if gates is None:
             gates = torch.empty((self.circuits, self.L), dtype=torch.int16, device=dev)
@@ -373,8 +416,9 @@ class Context:
         f64 = ctypes.c_double(0)
         _call("qe_get_best", self.handle, instance, gates, angles, ctypes.byref(f32),
               ctypes.byref(f64) if with_fp64 else None)
-        out = ([int(x) for x in gates], f32.value, (f64.value if with_fp64 else None))
-        return out + ([int(x) for x in angles],) if with_angles else out
+        L = self.lengths[instance] if self.mixed else self.L
+        out = ([int(x) for x in gates[:L]], f32.value, (f64.value if with_fp64 else None))
+        return out + ([int(x) for x in angles[:L]],) if with_angles else out
 
     def checkpoint(self):
         size = ctypes.c_size_t(0)
@@ -389,7 +433,8 @@ class Context:
 
     _VIEWS = {"theta": (0, torch.int32), "qutrit": (1, torch.float32), "best_f": (2, torch.float32),
               "best_theta": (3, torch.int32), "best_qutrit": (4, torch.float32),
-              "genomes0": (5, torch.int16), "genomes1": (6, torch.int16)}
+              "genomes0": (5, torch.int16), "genomes1": (6, torch.int16),
+              "mutation_masks": (7, torch.int32)}
 
     def state(self, name, stream=None):
         """A device copy of one field of the ctx-owned state."""
@@ -400,3 +445,11 @@ class Context:
         if n.value:
             _call("qe_state_read", self.handle, which, _ptr(out), ctypes.byref(n), _stream(stream))
         return out
+
+
+def probe_lds(mode, workgroups, iters, sink, stream=None):
+    """Launches the LDS bandwidth probe (mode 0 read, 1 write, 2 copy);
+    returns the LDS bytes the launch moves."""
+    b = ctypes.c_double(0)
+    _call("qe_probe_lds", mode, workgroups, iters, _ptr(sink), ctypes.byref(b), _stream(stream))
+    return b.value

@@ -186,12 +186,36 @@ def test_state_read_fields(dev, oracle):
     ctx, _ = qeqea_ctx(dev, oracle, n, L, P, I, seed)
     S, Q = n * n * L * P, n * L * P
     sizes = {"theta": I * S, "best_f": I * S, "best_theta": I * S, "qutrit": I * Q * 6,
-             "best_qutrit": I * Q * 6, "genomes0": 0, "genomes1": 0}
+             "best_qutrit": I * Q * 6, "genomes0": 0, "genomes1": 0,
+             "mutation_masks": 2 * I * ((P + 31) // 32)}
     for name, size in sizes.items():
         assert ctx.state(name).numel() == size, name
     assert np.all(ctx.state("best_f").cpu().numpy() == -1.0)
     with pytest.raises(qe.QeError):
-        qe._call("qe_state_read", ctx.handle, 7, None, qe.ctypes.byref(qe.ctypes.c_int64(0)), None)
+        qe._call("qe_state_read", ctx.handle, 8, None, qe.ctypes.byref(qe.ctypes.c_int64(0)), None)
+
+
+def test_mutation_masks_hold_the_decisions(dev, oracle):
+    """After qe_sample_eval of generation gen, the decision bitmaps (state
+    field 7) mark exactly the individuals whose MUT_IND draw falls below the
+    mutation threshold, and qe_update without slots (the generation's second
+    kernel alone) leaves the state the oracle's update gives."""
+    n, L, P, I, seed, pm = 3, 6, 40, 3, 57, 0.3
+    ctx, T = qeqea_ctx(dev, oracle, n, L, P, I, seed, pm=pm)
+    thr = int(np.floor(pm * 2 ** 32))
+    for gen in range(4):
+        o = to_oracle(oracle, ctx, gpu_state(ctx))
+        slots, gates, f = ctx.sample_eval(gen)
+        masks = ctx.state("mutation_masks").cpu().numpy().view(np.uint32).reshape(2, I, -1)[gen & 1]
+        bits = np.unpackbits(masks.view(np.uint8), bitorder="little").reshape(I, -1)[:, :P]
+        want = np.array([[oracle.philox([3, gen, i, ind], [seed & 0xFFFFFFFF, seed >> 32])[0] < thr
+                          for ind in range(P)] for i in range(I)])
+        assert np.array_equal(bits.astype(bool), want), gen
+        ctx.update(gen, None, gates, f)
+        o.update(gen, pm, float(np.pi / 4), slots.cpu().numpy().view(np.uint32), f.cpu().numpy())
+        assert_same_state(o, gpu_state(ctx))
+    with pytest.raises(qe.QeError):      # no qe_sample_eval of that generation just before
+        ctx.update(9, None, gates, f)
 
 
 def run_steps(ctx, gens):
