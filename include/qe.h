@@ -172,6 +172,20 @@ qe_status qe_eval_fitness_ws(const qe_batch* batch, int32_t path, float* f_dev, 
                              float* delta_dev, void* workspace_dev, size_t workspace_bytes,
                              void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * qe_eval_fitness_ws without a workspace argument.  The workspace is a
+ * fixed device array inside the library, one per GPU, held until the
+ * process ends (4 * (32 + QE_NOALLOC_MAX_CIRCUITS) bytes); the call
+ * allocates nothing and frees nothing.  A mixed-width batch of more than
+ * QE_NOALLOC_MAX_CIRCUITS circuits on QE_PATH_FP32 returns QE_ERR_INVALID
+ * (nothing is launched).  Every call on one GPU shares that array: calls
+ * that overlap on one GPU (other streams, other threads) race and must be
+ * ordered by the caller.  Results equal qe_eval_fitness_ws. */
+#define QE_NOALLOC_MAX_CIRCUITS 262144
+qe_status qe_eval_fitness_noalloc(const qe_batch* batch, int32_t path, float* f_dev, float* g_dev,
+                                  float* delta_dev, void* stream);
+
 /* The same fitness in FP64 (targets complex128), for re-checking elite
  * circuits; f_dev required, g_dev/delta_dev optional. */
 qe_status qe_eval_fitness_fp64(const qe_batch* batch, double* f_dev, double* g_dev,

@@ -57,6 +57,32 @@ qe_status device_error_word(uint32_t** out) {
     return QE_OK;
 }
 
+// Scratch of the allocation-free evaluation (qe_eval_fitness_noalloc): the
+// item table and cost order of a mixed-width batch of at most
+// QE_NOALLOC_MAX_CIRCUITS circuits.  A module global: each device holds its
+// own copy, at its own address, until the process ends.  Host code never
+// passes the array's name to a kernel (in host code it is only a stand-in
+// for the symbol): it uses the device address that hipGetSymbolAddress
+// gives, resolved once per device on the entry point's first call there.
+// Nothing in it must start at zero: the sort kernel writes every entry the
+// evaluation kernel reads.  All calls on one device share it.
+static __device__ __align__(256) int32_t scratch[MIX_WORK_META + QE_NOALLOC_MAX_CIRCUITS];
+std::map<int, int32_t*> g_scratch;
+
+qe_status noalloc_scratch(int32_t** out) {
+    int dev = 0;
+    QE_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_scratch.find(dev);
+    if (it != g_scratch.end()) { *out = it->second; return QE_OK; }
+    int32_t* p = nullptr;
+    QE_HIP(hipGetSymbolAddress((void**)&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(QE_ERR_DEVICE, "hipGetSymbolAddress gave no address for the scratch array");
+    g_scratch[dev] = p;
+    *out = p;
+    return QE_OK;
+}
+
 // Per-width schedule of the FP32 path (1 = LDS-staged kernel).  Defaults from
 // MI355X measurements (qe_eval_fitness, n=4: 14.2 us LDS vs 19.8 us register
 // for 4096 x 30 gates; n=5: 422 vs 698 us for 65536 x 40; n=6: 268 vs 667 us
@@ -380,6 +406,18 @@ qe_status qe_eval_fitness(qe_ctx* ctx, const qe_batch* batch, int32_t path, floa
         bytes = ctx->mix_work_bytes;
     }
     return eval_fitness_impl(batch, path, f_dev, g_dev, delta_dev, work, bytes, stream);
+}
+
+qe_status qe_eval_fitness_noalloc(const qe_batch* batch, int32_t path, float* f_dev, float* g_dev,
+                                  float* delta_dev, void* stream) {
+    if (batch && batch->uniform_n == 0 && path == QE_PATH_FP32 && batch->num_circuits > QE_NOALLOC_MAX_CIRCUITS)
+        return fail(QE_ERR_INVALID, "qe_eval_fitness_noalloc: a mixed-width batch of more than "
+                                    "QE_NOALLOC_MAX_CIRCUITS (" + std::to_string(QE_NOALLOC_MAX_CIRCUITS) +
+                                    ") circuits");
+    int32_t* work = nullptr;
+    QE_TRY(noalloc_scratch(&work));
+    return eval_fitness_impl(batch, path, f_dev, g_dev, delta_dev, work,
+                             ((size_t)MIX_WORK_META + QE_NOALLOC_MAX_CIRCUITS) * sizeof(int32_t), stream);
 }
 
 qe_status qe_eval_fitness_ws(const qe_batch* batch, int32_t path, float* f_dev, float* g_dev,

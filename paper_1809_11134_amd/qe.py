@@ -93,6 +93,7 @@ def load():
         "qe_probe_lds": [i32, i32, i32, vp, P(ctypes.c_double), vp],
         "qe_create_mixed": [P(Problem), vp, vp, P(vp)],
         "qe_eval_fitness_ws": [P(Batch), i32, vp, vp, vp, vp, ctypes.c_size_t, vp],
+        "qe_eval_fitness_noalloc": [P(Batch), i32, vp, vp, vp, vp],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
