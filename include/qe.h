@@ -233,7 +233,7 @@ typedef struct {
 } qe_problem;
 
 /* Creates a context on the current device: allocates the ctx-owned encoding
- * (QEQEA: R * L * P slot records of 32 bytes (angle, best angle, best
+ * (QEQEA: R * L * P slot records of 16 bytes (angle, best angle, best
  * segment fitness, the generation's segment key), R = n + n(n-1) regions for
  * {I, NOT, CNOT, CV, CV+} (one template per ordered wire pair) or
  * n + n(n-1)/2 for the Ising library (one per unordered pair), and n*L*P

@@ -971,8 +971,8 @@ qe_status qe_checkpoint(qe_ctx* c, void* buf, size_t* size) {
     if (*size < need) return fail(QE_ERR_INVALID, "checkpoint buffer too small");
     QE_HIP(hipDeviceSynchronize());
     CkptHeader h{};
-    std::memcpy(h.magic, "QECKPT03", 8);
-    h.version = 3;
+    std::memcpy(h.magic, "QECKPT04", 8);
+    h.version = 4;
     h.prob = c->prob;
     h.layout = layout_tag(c);
     h.payload = payload;
@@ -991,7 +991,7 @@ qe_status qe_restore(qe_ctx* c, const void* buf, size_t size) {
     if (!buf || size < sizeof(CkptHeader)) return fail(QE_ERR_INVALID, "checkpoint too small");
     CkptHeader h;
     std::memcpy(&h, buf, sizeof(h));
-    if (std::memcmp(h.magic, "QECKPT03", 8) != 0 || h.version != 3)
+    if (std::memcmp(h.magic, "QECKPT04", 8) != 0 || h.version != 4)
         return fail(QE_ERR_INVALID, "not a libqe checkpoint");
     if (!same_problem(h.prob, c->prob) || h.layout != layout_tag(c))
         return fail(QE_ERR_INVALID, "checkpoint was written for a different problem");

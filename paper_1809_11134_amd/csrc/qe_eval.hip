@@ -157,7 +157,7 @@ __device__ __forceinline__ int mix_key(const BatchArgs& a, int b) {
     const int lc = len >= 120 ? 0 : (len < 8 ? MIX_LCLASSES - 1 : MIX_LCLASSES - 1 - (int)(len >> 3));
     return mix_bucket(a.nq[b]) * MIX_LCLASSES + lc;
 }
-__device__ __forceinline__ int mix_per_item(int k) { return k == 0 ? 1 : (k == 1 ? 2 : 4); }
+__device__ __forceinline__ int mix_per_item(int k) { return k == 0 ? 1 : 4; }
 
 // meta: [0..7) first order position, [8..15) first item (8 entries, the last
 // the total), [16..23) count per bucket.
@@ -271,6 +271,7 @@ __global__ __launch_bounds__(256) void mix_kernel(BatchArgs a, const int32_t* __
                                                   float* __restrict__ f, float* __restrict__ g,
                                                   float* __restrict__ delta) {
     __shared__ float2 M[4096];
+    __shared__ uint4 GT[4][GATE_TABLE];
     __shared__ float red[4][3];
     const int item = blockIdx.x;
     if (item >= meta[8 + MIX_BUCKETS]) return;
@@ -283,14 +284,10 @@ __global__ __launch_bounds__(256) void mix_kernel(BatchArgs a, const int32_t* __
     int b = local + sub < meta[16 + k] ? order[meta[k] + local + sub] : -1;
     if (b >= a.B) b = -1;        // an order written for another batch never indexes past this one
     switch (k) {
-        // (only the width-4 items use gate tables: they live in the part of
-        // M that four 16 x 16 matrices leave free)
+        // (widths 4 and 5 run one circuit per wavefront, each with its gate table)
         case 0: mix_lds_item<6, 4>(a, b, M, nullptr, red, f, g, delta); break;
-        case 1: mix_lds_item<5, 2>(a, b, M + sub * 1024, nullptr, red, f, g, delta); break;
-        case 2:
-            mix_lds_item<4, 1>(a, b, M + sub * 256,
-                               reinterpret_cast<uint4*>(M + 1024) + wave * GATE_TABLE, red, f, g, delta);
-            break;
+        case 1: mix_lds_item<5, 1>(a, b, M + sub * 1024, GT[wave], red, f, g, delta); break;
+        case 2: mix_lds_item<4, 1>(a, b, M + sub * 256, GT[wave], red, f, g, delta); break;
         case 3: mix_wave_item<3>(a, b, f, g, delta); break;
         case 4: mix_wave_item<2>(a, b, f, g, delta); break;
         case 5: mix_wave_item<1>(a, b, f, g, delta); break;
@@ -352,7 +349,7 @@ static void launch_width(const BatchArgs& a, int n, bool lds, float* f, float* g
             case 2: wave_kernel<2, FILTER, true><<<wgrid, wblock, 0, s>>>(a, f, g, delta); break;
             case 3: wave_kernel<3, FILTER, true><<<wgrid, wblock, 0, s>>>(a, f, g, delta); break;
             case 4: lds32_kernel<4, 1, FILTER, false, true><<<a.B, 64, 0, s>>>(a, f, g, delta, nullptr); break;
-            case 5: lds32_kernel<5, 2, FILTER, false, true><<<a.B, 128, 0, s>>>(a, f, g, delta, nullptr); break;
+            case 5: lds32_kernel<5, 1, FILTER, false, true><<<a.B, 64, 0, s>>>(a, f, g, delta, nullptr); break;
             default: lds32_kernel<6, 4, FILTER, false, true><<<a.B, 256, 0, s>>>(a, f, g, delta, nullptr); break;
         }
         return;
@@ -360,7 +357,7 @@ static void launch_width(const BatchArgs& a, int n, bool lds, float* f, float* g
     if (lds) {
         switch (n) {
             case 4: lds32_kernel<4, 1, FILTER, false><<<a.B, 64, 0, s>>>(a, f, g, delta, nullptr); break;
-            case 5: lds32_kernel<5, 2, FILTER, false><<<a.B, 128, 0, s>>>(a, f, g, delta, nullptr); break;
+            case 5: lds32_kernel<5, 1, FILTER, false><<<a.B, 64, 0, s>>>(a, f, g, delta, nullptr); break;
             default: lds32_kernel<6, 4, FILTER, false><<<a.B, 256, 0, s>>>(a, f, g, delta, nullptr); break;
         }
         return;
@@ -438,8 +435,8 @@ hipError_t launch_unitary(const BatchArgs& a, bool fp64, void* out, hipStream_t 
                 else lds32_kernel<4, 1, false, true><<<a.B, 64, 0, s>>>(a, nullptr, nullptr, nullptr, o);
                 break;
             case 5:
-                if (a.angles) lds32_kernel<5, 2, false, true, true><<<a.B, 128, 0, s>>>(a, nullptr, nullptr, nullptr, o);
-                else lds32_kernel<5, 2, false, true><<<a.B, 128, 0, s>>>(a, nullptr, nullptr, nullptr, o);
+                if (a.angles) lds32_kernel<5, 1, false, true, true><<<a.B, 64, 0, s>>>(a, nullptr, nullptr, nullptr, o);
+                else lds32_kernel<5, 1, false, true><<<a.B, 64, 0, s>>>(a, nullptr, nullptr, nullptr, o);
                 break;
             default:
                 if (a.angles) lds32_kernel<6, 4, false, true, true><<<a.B, 256, 0, s>>>(a, nullptr, nullptr, nullptr, o);

@@ -585,7 +585,12 @@ __device__ __forceinline__ bool run_lds_path(float2* M, uint4* gt, const float* 
     constexpr bool ANG = src_angled<GateSrc>();
     constexpr int ES = ANG ? 3 : 2;        // uint4 per gate-table entry
     using SrcT = std::decay_t<decltype(src(0))>;
-    static_assert(CW <= 64 && 64 % CW == 0 && N % RG == 0 && RG == 4, "layout: four row groups per wavefront");
+    // four row groups per wavefront (16 columns: n = 4, or n = 5, 6 split over
+    // 2 or 4 wavefronts), or two (32 columns: n = 5 in one wavefront, whose
+    // half-wavefronts then read whole 256-byte rows, free of bank conflicts)
+    static_assert(CW <= 64 && 64 % CW == 0 && N % RG == 0 && (RG == 4 || RG == 2),
+                  "layout: two or four row groups per wavefront");
+    static_assert((N / 2) / RG <= 8, "at most three pass bits");
     const int lane = (int)lane_id();
     if (wave < 0) wave = (int)(threadIdx.x >> 6);
     const int jl = lane % CW, rg = lane / CW;
@@ -610,8 +615,8 @@ __device__ __forceinline__ bool run_lds_path(float2* M, uint4* gt, const float* 
     wave_lds_fence();
     bool ok = true;
     const int chunks = (L + 63) >> 6;
-    // lane constants: byte offset of column j, and the two row-group bits as
-    // all-ones / all-zeros masks
+    // lane constants: byte offset of column j, and the row-group bits (pair
+    // index bits 0 and, with four groups, 1) as all-ones / all-zeros masks
     const uint32_t jb = (uint32_t)j * 8u;
     uint32_t mb0 = (rg & 1) ? ~0u : 0u, mb1 = (rg & 2) ? ~0u : 0u;
     // as plain registers, so that selecting a gate's offset is one AND with a
@@ -721,9 +726,11 @@ __device__ __forceinline__ bool run_lds_path(float2* M, uint4* gt, const float* 
         };
         const bool live = lane < cnt && kind != KIND_I && !perm;
         const uint64_t live_mask = __ballot(live);
-        const uint4 G0 = make_uint4(ins(1), ins(2), ctl ? colb(cpos) : 0u, colb(tpos));
-        const uint4 G1 = make_uint4((uint32_t)kind | ((myB << ROWB) << 16), NIT_USES_R2 ? ins(4) : 0u,
-                                    NIT_USES_R3 ? ins(8) : 0u, NIT_USES_R4 ? ins(16) : 0u);
+        // the row group selects pair-index bits 0 (and 1); the passes walk
+        // the pair-index bits above them
+        const uint4 G0 = make_uint4(ins(1), RG == 4 ? ins(2) : 0u, ctl ? colb(cpos) : 0u, colb(tpos));
+        const uint4 G1 = make_uint4((uint32_t)kind | ((myB << ROWB) << 16), NIT_USES_R2 ? ins(RG) : 0u,
+                                    NIT_USES_R3 ? ins(2 * RG) : 0u, NIT_USES_R4 ? ins(4 * RG) : 0u);
         uint4 G2 = make_uint4(f_bits(1.0f), 0u, 0u, 0u);
         if constexpr (ANG) {
             if (live && kind_ising(kind)) {
@@ -886,10 +893,10 @@ __device__ __forceinline__ bool run_lds_path(float2* M, uint4* gt, const float* 
             if (live) {
                 const int rank = (int)__builtin_amdgcn_mbcnt_hi(
                     (uint32_t)(live_mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)live_mask, 0u));
-                const uint32_t base = (myB << ROWB) ^ colb(cpos), i1 = ins(1), i2 = ins(2);
+                const uint32_t base = (myB << ROWB) ^ colb(cpos), i1 = ins(1), i2 = RG == 4 ? ins(2) : 0u;
                 gt[2 * rank] = make_uint4(base, base ^ i1, base ^ i2, base ^ i1 ^ i2);
                 gt[2 * rank + 1] = make_uint4(colb(tpos), f_bits(kind == KIND_CVDG ? -0.5f : 0.5f),
-                                              NITC > 1 ? ins(4) : 0u, NITC > 2 ? ins(8) : 0u);
+                                              NITC > 1 ? ins(RG) : 0u, NITC > 2 ? ins(2 * RG) : 0u);
             }
             wave_lds_fence();
             const uint32_t* gw = reinterpret_cast<const uint32_t*>(gt) + rg;   // entry 0, this row group
@@ -958,9 +965,9 @@ __device__ __forceinline__ bool run_lds_path(float2* M, uint4* gt, const float* 
             // top bit, free since offsets stay below 2^15)
             (void)gt;
             constexpr int NITC = (N / 4) / RG;
-            const uint32_t gbase = (myB << ROWB) ^ colb(cpos), gi1 = ins(1), gi2 = ins(2);
+            const uint32_t gbase = (myB << ROWB) ^ colb(cpos), gi1 = ins(1), gi2 = RG == 4 ? ins(2) : 0u;
             const uint32_t gtw = colb(tpos) | (kind == KIND_CVDG ? 0x80000000u : 0u);
-            const uint32_t go2 = NITC > 1 ? ins(4) : 0u, go3 = NITC > 2 ? ins(8) : 0u;
+            const uint32_t go2 = NITC > 1 ? ins(RG) : 0u, go3 = NITC > 2 ? ins(2 * RG) : 0u;
             uint64_t todo = live_mask;
             while (todo) {
                 const int g = (int)__builtin_ctzll(todo);
@@ -994,12 +1001,19 @@ __device__ __forceinline__ bool run_lds_path(float2* M, uint4* gt, const float* 
 #pragma unroll
         for (int p = 0; p < NQ; ++p)
             if ((j >> p) & 1) pj ^= (int)((Amap >> (6 * p)) & 63u);
+        // every read is issued before any is used (the reads are kept
+        // unconditional: a read under the diagonal test would wait for each
+        // in turn)
+        float2 vv[N / RG];
+#pragma unroll
+        for (int m = 0; m < N / RG; ++m) vv[m] = M[(m * RG + rg) * N + j];
+#pragma unroll
+        for (int m = 0; m < N / RG; ++m) asm volatile("" ::"v"(vv[m].x), "v"(vv[m].y));
         float off = 0.0f;
 #pragma unroll
         for (int m = 0; m < N / RG; ++m) {
             const int r = m * RG + rg;
-            const float2 v = M[r * N + j];
-            off += (r == pj) ? 0.0f : v.x * v.x + v.y * v.y;
+            off += (r == pj) ? 0.0f : vv[m].x * vv[m].x + vv[m].y * vv[m].y;
         }
         *off_out = off;
         *diag_out = (lane < CW) ? M[pj * N + j] : make_float2(0.0f, 0.0f);

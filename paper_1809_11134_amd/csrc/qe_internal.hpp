@@ -54,25 +54,24 @@ hipError_t launch_eval_dense(const BatchArgs& a, float* f, float* g, float* delt
 hipError_t launch_eval_mfma(const BatchArgs& a, bool fp16, bool renorm, float* f, float* g,
                             float* delta, hipStream_t s);
 
-// Encoding state of one slot (Eq. 10 index), 32 bytes: every field the loop
-// reads or writes for a slot lies in one cache line, so a random slot access
-// costs one line.  `key` is the slot's best use in the current generation:
-// (f bits << 32) | ~circuit over the circuits that used it with a valid
-// fitness (a 64-bit maximum: largest f, lowest circuit on ties), 0 = unused.
-// Its high half is the segment fitness; the circuit it names owns the slot's
-// update.
+// Encoding state of one slot (Eq. 10 index), 16 bytes (eight to a 128-byte
+// line): every field the loop reads or writes for a slot lies in one line,
+// so a random slot access costs one line.  `key` is the slot's segment
+// fitness in the current generation (Sec. IV-E.1: the largest fitness of the
+// circuits that used it), as the bits of that non-negative float plus one
+// (so unsigned order is float order), 0 = unused.  Any circuit whose fitness
+// equals it may apply the slot's elitism: the update is the same for all of
+// them, so repeats leave the same state.
 struct SlotRec {
     uint32_t theta;        // qubit angle as a turn fraction (2^32 = 2 pi)
     uint32_t best_theta;   // state of the best segment fitness seen
     float best_f;          // best segment fitness seen, -1 = never used
-    uint32_t spare;
-    unsigned long long key;
-    unsigned long long spare2;
+    uint32_t key;
 };
+static_assert(sizeof(SlotRec) == 16, "slot records are 16 bytes");
 
-__device__ __forceinline__ unsigned long long seg_key(float f, uint32_t circuit) {
-    return ((unsigned long long)__float_as_uint(f) << 32) | (unsigned long long)(0xFFFFFFFFu - circuit);
-}
+__device__ __forceinline__ uint32_t seg_key(float f) { return __float_as_uint(f) + 1u; }
+__device__ __forceinline__ float seg_fitness(uint32_t key) { return __uint_as_float(key - 1u); }
 
 // Qutrit of a rotation slot (s < n*L*P) and its best copy, one 64-byte line.
 struct QutritRec {

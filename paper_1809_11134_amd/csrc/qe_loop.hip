@@ -132,9 +132,7 @@ __global__ void qeqea_init_kernel(LoopArgs a, float amp) {
     r.theta = w.x;
     r.best_theta = w.x;
     r.best_f = -1.0f;
-    r.spare = 0u;
-    r.key = 0ull;
-    r.spare2 = 0ull;
+    r.key = 0u;
     a.slot[idx] = r;
     if (s < a.Q) {
         QutritRec q;
@@ -246,7 +244,7 @@ __device__ __forceinline__ void clear_next_mask(const LoopArgs& a, uint32_t gen,
 // with W = 1) or per workgroup (LDS layout, W > 1); the target is the
 // circuit's instance target.  With SAMPLE the circuit is first constructed
 // from the encoding (qe_sample) and afterwards every slot it used keeps the
-// largest (fitness, lowest circuit) key.  With
+// largest fitness of the circuits that used it (its segment key).  With
 // `decide` (the internal generation) circuit k also draws the mutation
 // decision of individual k (both run over 0..P-1) and empties its part of the
 // decision mask of the other generation parity.
@@ -353,7 +351,7 @@ __device__ __forceinline__ void eval_circuit(const LoopArgs& a, uint32_t gen, ui
     }
     // segment fitness: every slot this circuit used keeps the largest key
     if (SAMPLE && writer && fv >= 0.0f) {
-        const unsigned long long key = seg_key(fv, k);
+        const uint32_t key = seg_key(fv);
 #pragma unroll
         for (int c = 0; c < KEEP; ++c) {
             const int p = c * 64 + lane;
@@ -417,7 +415,7 @@ __global__ void scatter_kernel(LoopArgs a, const uint32_t* __restrict__ slots,
     const float fv = f[idx / a.L];
     const uint32_t s = slots[idx];
     if (!(fv >= 0.0f) || s >= a.S) return;
-    atomicMax(&a.slot[(size_t)i * a.S + s].key, seg_key(fv, (uint32_t)((idx / a.L) % a.P)));
+    atomicMax(&a.slot[(size_t)i * a.S + s].key, seg_key(fv));
 }
 
 // Mutation decisions for the step-by-step path (qe_update): one thread per
@@ -534,10 +532,12 @@ constexpr int UPD_MAX_P = 16384;          // part B's list of mutated individual
 // slots NULL: the entry's slot is drawn again (the generation's own
 // sampling, which saves a dependent load); otherwise it is read.
 __device__ __forceinline__ void update_part_a(const LoopArgs& a, uint32_t gen, uint32_t idx,
-                                              const uint32_t* __restrict__ slots) {
+                                              const uint32_t* __restrict__ slots,
+                                              const float* __restrict__ f) {
     const uint32_t L = (uint32_t)a.L, LP = L * (uint32_t)a.P;
     if (idx >= (uint32_t)a.I * LP) return;
     const uint32_t i = idx / LP, k = (idx % LP) / L;
+    const float fk = f[idx / L];                // the entry's circuit's fitness
     const uint32_t s = slots ? slots[idx] : sample_slot(a, gen, i, k, idx % L);
     if (s >= a.S) return;
     const uint32_t ind = (s % LP) / L;
@@ -550,12 +550,13 @@ __device__ __forceinline__ void update_part_a(const LoopArgs& a, uint32_t gen, u
     // (its word is loaded with the records)
     const uint32_t mw = mask_of(a, gen, i)[ind >> 5];
     const bool mut = ((mw >> (ind & 31u)) & 1u) != 0u;
-    // the entry owns the slot if its circuit holds the slot's key (a circuit
-    // uses a slot at most once: the slot fixes the position)
-    if (r.key == 0ull || (uint32_t)r.key != 0xFFFFFFFFu - k) return;
+    // the entry takes the slot if its circuit's fitness is the slot's segment
+    // fitness (when several circuits share that fitness, each applies the
+    // same elitism to the same record, which leaves the same state)
+    if (r.key == 0u || !(fk >= 0.0f) || r.key != seg_key(fk)) return;
     if (mut) return;
-    const float v = __uint_as_float((uint32_t)(r.key >> 32));
-    r.key = 0ull;
+    const float v = seg_fitness(r.key);
+    r.key = 0u;
     elitism(v, r, q, rot);
     a.slot[o] = r;
     if (rot) store_qstate(a.qrec + oq, q);
@@ -626,9 +627,9 @@ __device__ __forceinline__ void update_part_b(const LoopArgs& a, uint32_t gen, u
         if (rot) q = load_qstate(a.qrec + oq);
         bool qm;
         mutates(a, gen, i, ind, &qm);
-        const bool used = r.key != 0ull;
-        if (used) elitism(__uint_as_float((uint32_t)(r.key >> 32)), r, q, rot);
-        r.key = 0ull;
+        const bool used = r.key != 0u;
+        if (used) elitism(seg_fitness(r.key), r, q, rot);
+        r.key = 0u;
         if (!qm || rot) mutate_state(a, gen, i, s, qm, r, q);
         // an unused slot in qutrit mode keeps its record (only the qutrit moves)
         if (used || !qm) a.slot[o] = r;
@@ -705,7 +706,7 @@ __global__ __launch_bounds__(UPD_BLOCK) void qeqea_update_kernel(LoopArgs a, uin
     else if (blockIdx.x < nC + nB)
         update_part_b(a, gen, blockIdx.x - nC, per_inst);
     else
-        update_part_a(a, gen, (blockIdx.x - nC - nB) * UPD_BLOCK + threadIdx.x, slots);
+        update_part_a(a, gen, (blockIdx.x - nC - nB) * UPD_BLOCK + threadIdx.x, slots, f);
 }
 
 // Dense copy of one field of the encoding state.
@@ -1004,7 +1005,7 @@ static void launch_population(const LoopArgs& a, uint64_t gen, const uint16_t* g
             case 2: population_kernel<2, 0, SAMPLE, true><<<wb, 256, 0, s>>>(a, gen, gin, ain, sout, gout, aout, f, decide); break;
             case 3: population_kernel<3, 0, SAMPLE, true><<<wb, 256, 0, s>>>(a, gen, gin, ain, sout, gout, aout, f, decide); break;
             case 4: population_kernel<4, 1, SAMPLE, true><<<wb, 256, 0, s>>>(a, gen, gin, ain, sout, gout, aout, f, decide); break;
-            case 5: population_kernel<5, 2, SAMPLE, true><<<total, 128, 0, s>>>(a, gen, gin, ain, sout, gout, aout, f, decide); break;
+            case 5: population_kernel<5, 1, SAMPLE, true><<<wb, 256, 0, s>>>(a, gen, gin, ain, sout, gout, aout, f, decide); break;
             default: population_kernel<6, 4, SAMPLE, true><<<total, 256, 0, s>>>(a, gen, gin, ain, sout, gout, aout, f, decide); break;
         }
         return;
@@ -1013,7 +1014,7 @@ static void launch_population(const LoopArgs& a, uint64_t gen, const uint16_t* g
     if (lds && a.n >= 4) {
         switch (a.n) {
             case 4: population_kernel<4, 1, SAMPLE><<<wb, 256, 0, s>>>(a, gen, gin, ain, sout, gout, aout, f, decide); break;
-            case 5: population_kernel<5, 2, SAMPLE><<<total, 128, 0, s>>>(a, gen, gin, ain, sout, gout, aout, f, decide); break;
+            case 5: population_kernel<5, 1, SAMPLE><<<wb, 256, 0, s>>>(a, gen, gin, ain, sout, gout, aout, f, decide); break;
             default: population_kernel<6, 4, SAMPLE><<<total, 256, 0, s>>>(a, gen, gin, ain, sout, gout, aout, f, decide); break;
         }
         return;
