@@ -705,8 +705,9 @@ __global__ __launch_bounds__(UPD_BLOCK) void qeqea_update_kernel(LoopArgs a, uin
         update_part_c(a, blockIdx.x, gates, angles, f);
     else if (blockIdx.x < nC + nB)
         update_part_b(a, gen, blockIdx.x - nC, per_inst);
-    else
-        update_part_a(a, gen, (blockIdx.x - nC - nB) * UPD_BLOCK + threadIdx.x, slots, f);
+    else   // part A from the last entries back: the records the fused kernel
+           // touched last are the likeliest to be in the memory-side cache
+        update_part_a(a, gen, (gridDim.x - 1u - blockIdx.x) * UPD_BLOCK + threadIdx.x, slots, f);
 }
 
 // Dense copy of one field of the encoding state.
