@@ -86,7 +86,9 @@ enum { QE_PATH_FP32 = 0,        /* per-gate row updates, FP32, tuned schedule pe
 enum { QE_DEVERR_DESC = 1,      /* invalid gate descriptor */
        QE_DEVERR_WIDTH = 2,     /* circuit width outside 1..6 */
        QE_DEVERR_RANGE = 4,     /* gate, target or mutation-list index outside its buffer */
-       QE_DEVERR_NUMERIC = 8 }; /* NaN/Inf fitness */
+       QE_DEVERR_NUMERIC = 8,   /* NaN/Inf fitness */
+       QE_DEVERR_TARGET = 16 }; /* phase-insensitive fitness of a target with an
+                                   entry of modulus strictly between 0 and 1 */
 
 /* ------------------------------------------------------------------ batches */
 /* A batch of circuits to evaluate (Sec. IV-E).  Host struct; the arrays it
@@ -120,7 +122,11 @@ enum { QE_DEVERR_DESC = 1,      /* invalid gate descriptor */
  * permutation target T (the paper's targets) equals sum_ij |U_ij|^2
  * |T_ij|^2 / 2^n, the phase-insensitive reading of Eq. 11 under which the
  * paper's Table II figure reproduces; it ignores the global phase and
- * phases applied after the circuit. */
+ * phases applied after the circuit.  The two agree exactly when every entry
+ * of T has modulus 0 or 1 (a permutation with phases, as the paper's targets
+ * are); the evaluation calls check each target in this mode and give a
+ * circuit whose target has an entry of modulus strictly between 0 and 1 (by
+ * more than 1e-5, FP64 calls 1e-9) f = g = delta = NaN and QE_DEVERR_TARGET. */
 enum { QE_FIT_EQ11 = 0, QE_FIT_PHASE_INSENSITIVE = 1 };
 
 typedef struct {
@@ -266,7 +272,10 @@ qe_status qe_create_mixed(const qe_problem* problem, const int32_t* n_qubits_hos
 
 /* Copies the I targets ([I][2^n][2^n] complex128, device) into the context
  * (kept in complex128 for the FP64 re-check and in complex64 for the hot
- * path).  Must precede sample/eval/update/generation.  Asynchronous. */
+ * path).  Must precede sample/eval/update/generation.  Asynchronous, except
+ * for a context whose fitness_mode is QE_FIT_PHASE_INSENSITIVE: then it
+ * checks every target (modulus 0 or 1 entries, see qe_batch), syncs, and
+ * returns QE_ERR_UNSUPPORTED (targets not taken) if one fails. */
 qe_status qe_set_targets(qe_ctx* ctx, const void* targets_c128_dev, void* stream);
 
 /* Circuit construction (Sec. IV-D).  QEQEA: for each instance i, circuit

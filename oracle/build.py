@@ -11,14 +11,22 @@ SRC = os.path.join(HERE, "qe_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
 
-def build_oracle(verbose: bool = False) -> str:
+SAN_LIB = os.path.join(HERE, "liboracle_san.so")
+
+
+def build_oracle(verbose: bool = False, sanitize: bool = False) -> str:
+    """sanitize: an AddressSanitizer + UndefinedBehaviorSanitizer build
+    (liboracle_san.so; every finding aborts), for the sanitizer test."""
+    out = SAN_LIB if sanitize else LIB
+    san = (["-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer", "-g"]
+           if sanitize else [])
     cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
-           "-fPIC", "-shared", "-Wall", "-Wextra", SRC, "-o", LIB + ".tmp", "-lm"]
+           "-fPIC", "-shared", "-Wall", "-Wextra", *san, SRC, "-o", out + ".tmp", "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
-    return LIB
+    os.replace(out + ".tmp", out)
+    return out
 
 
 if __name__ == "__main__":

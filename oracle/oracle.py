@@ -16,9 +16,10 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_build.LIB):
+        path = os.environ.get("QE_ORACLE_LIB", _build.LIB)   # e.g. the sanitizer build
+        if path == _build.LIB and not os.path.exists(path):
             _build.build_oracle()
-        L = ctypes.CDLL(_build.LIB)
+        L = ctypes.CDLL(path)
         u32p = np.ctypeslib.ndpointer(np.uint32, flags="C_CONTIGUOUS")
         u16p = np.ctypeslib.ndpointer(np.uint16, flags="C_CONTIGUOUS")
         f32p = np.ctypeslib.ndpointer(np.float32, flags="C_CONTIGUOUS")

@@ -27,8 +27,15 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=
          "-I", os.path.join(ROOT, "include"), "-Wall"]
 
 
-def _compile(src, obj, verbose):
-    cmd = ["hipcc", *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+# host code under AddressSanitizer and UndefinedBehaviorSanitizer (the device
+# code is built as usual): libqe_san.so, for the sanitizer test on the CPU
+SAN_LIB = os.path.join(HERE, "libqe_san.so")
+SAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-sanitize-recover=all", "-Xarch_host", "-fno-omit-frame-pointer"]
+
+
+def _compile(src, obj, verbose, extra=()):
+    cmd = ["hipcc", *FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -38,19 +45,21 @@ def _compile(src, obj, verbose):
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    objdir = os.path.join(HERE, "_build")
+def build(verbose: bool = False, sanitize: bool = False) -> str:
+    objdir = os.path.join(HERE, "_build_san" if sanitize else "_build")
+    out = SAN_LIB if sanitize else LIB
+    extra = SAN_FLAGS if sanitize else ()
     os.makedirs(objdir, exist_ok=True)
     objs = [os.path.join(objdir, s.replace(".hip", ".o")) for s in SOURCES]
     with concurrent.futures.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        list(ex.map(lambda so: _compile(so[0], so[1], verbose), zip(SOURCES, objs)))
-    tmp = LIB + ".tmp"
-    cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
+        list(ex.map(lambda so: _compile(so[0], so[1], verbose, extra), zip(SOURCES, objs)))
+    tmp = out + ".tmp"
+    cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", *extra, *objs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

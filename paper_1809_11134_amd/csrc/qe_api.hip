@@ -231,6 +231,7 @@ struct qe_ctx {
     int32_t* mix_order = nullptr;
     int32_t* mix_eval_work = nullptr;
     size_t mix_work_bytes = 0;
+    uint32_t* check_word = nullptr;   // flags of the phase-insensitive target check
 };
 
 namespace {
@@ -372,22 +373,22 @@ qe_status eval_fitness_impl(const qe_batch* batch, int32_t path, float* f_dev, f
     if (a.angles && path != QE_PATH_FP32 && path != QE_PATH_FP32_LDS && path != QE_PATH_DENSE)
         return fail(QE_ERR_UNSUPPORTED,
                     "angled (Ising) batches run on QE_PATH_FP32 / QE_PATH_FP32_LDS / QE_PATH_DENSE");
-    if (path == QE_PATH_DENSE) {
-        QE_HIP(launch_eval_dense(a, f_dev, g_dev, delta_dev, (hipStream_t)stream));
-        return QE_OK;
-    }
-    if (path >= QE_PATH_MFMA_BF16) {
-        if (a.uniform_n != 5 && a.uniform_n != 6)
-            return fail(QE_ERR_UNSUPPORTED, "MFMA paths need a uniform width of 5 or 6");
-        const bool fp16 = path == QE_PATH_MFMA_FP16 || path == QE_PATH_MFMA_FP16_RAW;
-        const bool renorm = path == QE_PATH_MFMA_BF16 || path == QE_PATH_MFMA_FP16;
-        QE_HIP(launch_eval_mfma(a, fp16, renorm, f_dev, g_dev, delta_dev, (hipStream_t)stream));
-        return QE_OK;
-    }
+    if (path >= QE_PATH_MFMA_BF16 && path != QE_PATH_DENSE && a.uniform_n != 5 && a.uniform_n != 6)
+        return fail(QE_ERR_UNSUPPORTED, "MFMA paths need a uniform width of 5 or 6");
     if (work && work_bytes < qe_eval_workspace_bytes(a.B))
         return fail(QE_ERR_INVALID, "workspace smaller than qe_eval_workspace_bytes(num_circuits)");
-    if (a.uniform_n != 0 || path != QE_PATH_FP32) work = nullptr;
-    QE_HIP(launch_eval_fp32(a, path, f_dev, g_dev, delta_dev, work, (hipStream_t)stream));
+    const hipStream_t s = (hipStream_t)stream;
+    if (path == QE_PATH_DENSE) {
+        QE_HIP(launch_eval_dense(a, f_dev, g_dev, delta_dev, s));
+    } else if (path >= QE_PATH_MFMA_BF16) {
+        const bool fp16 = path == QE_PATH_MFMA_FP16 || path == QE_PATH_MFMA_FP16_RAW;
+        const bool renorm = path == QE_PATH_MFMA_BF16 || path == QE_PATH_MFMA_FP16;
+        QE_HIP(launch_eval_mfma(a, fp16, renorm, f_dev, g_dev, delta_dev, s));
+    } else {
+        if (a.uniform_n != 0 || path != QE_PATH_FP32) work = nullptr;
+        QE_HIP(launch_eval_fp32(a, path, f_dev, g_dev, delta_dev, work, s));
+    }
+    QE_HIP(launch_target_check(a, false, f_dev, g_dev, delta_dev, s));
     return QE_OK;
 }
 
@@ -434,6 +435,7 @@ qe_status qe_eval_fitness_fp64(const qe_batch* batch, double* f_dev, double* g_d
     QE_TRY(to_args(batch, &a, true));
     if (a.B > 0 && !f_dev) return fail(QE_ERR_INVALID, "f_dev is NULL");
     QE_HIP(launch_eval_lds(a, true, f_dev, g_dev, delta_dev, (hipStream_t)stream));
+    QE_HIP(launch_target_check(a, true, f_dev, g_dev, delta_dev, (hipStream_t)stream));
     return QE_OK;
 }
 
@@ -591,6 +593,7 @@ qe_status create_impl(const qe_problem* p_in, const int32_t* inst_n, const int32
     ALLOC(c->f, I * P);
     ALLOC(c->d_gen, 1);
     ALLOC(c->elite_cand, (int64_t)elite_cand_keys(I, P));
+    ALLOC(c->check_word, 1);
     // mixed populations: per population and per circuit tables
     std::vector<int32_t> h_cgoff;
     std::vector<int64_t> h_goff, h_ctoff;
@@ -705,6 +708,33 @@ qe_status qe_set_targets(qe_ctx* c, const void* t, void* stream) {
     if (!t) return fail(QE_ERR_INVALID, "targets is NULL");
     const size_t reals = (size_t)c->target_elems * 2;
     hipStream_t s = (hipStream_t)stream;
+    if (c->prob.fitness_mode == QE_FIT_PHASE_INSENSITIVE) {
+        // the mode needs targets whose entries have modulus 0 or 1: check them
+        // in place, before they are taken
+        BatchArgs b{};
+        if (c->mixed) {
+            b = mixed_batch(c, c->gates);
+        } else {
+            b.B = c->prob.n_instances;
+            b.uniform_n = c->prob.n_qubits;
+            b.uniform_L = 1;
+            b.gates = c->gates;
+            b.num_gates = b.B;
+            b.tstride = (int64_t)c->N * c->N;
+            b.num_telems = c->target_elems;
+        }
+        b.targets = t;
+        b.mode = QE_FIT_PHASE_INSENSITIVE;
+        b.err = c->check_word;
+        uint32_t flags = 0;
+        QE_HIP(hipMemsetAsync(c->check_word, 0, sizeof(uint32_t), s));
+        QE_HIP(launch_target_check(b, true, c->f, nullptr, nullptr, s));
+        QE_HIP(hipMemcpyAsync(&flags, c->check_word, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        QE_HIP(hipStreamSynchronize(s));
+        if (flags & QE_DEVERR_TARGET)
+            return fail(QE_ERR_UNSUPPORTED, "the phase-insensitive fitness needs targets whose entries have "
+                                            "modulus 0 or 1 (permutations with phases)");
+    }
     QE_HIP(hipMemcpyAsync((void*)c->la.target64, t, reals * sizeof(double), hipMemcpyDeviceToDevice, s));
     QE_HIP(launch_c128_to_c64(c->la.target64, (float*)c->la.target32, (int64_t)reals, s));
     c->targets_set = true;

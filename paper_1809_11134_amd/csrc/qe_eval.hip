@@ -396,6 +396,53 @@ hipError_t launch_eval_fp32(const BatchArgs& a, int path, float* f, float* g, fl
     return hipGetLastError();
 }
 
+// The phase-insensitive fitness is sum |U_ij|^2 |T_ij|^2 / 2^n; the kernels
+// evaluate it as the diagonal overlap of U T^dagger, which equals it exactly
+// when every entry of T has modulus 0 or 1.  One wavefront per circuit (one in
+// all for a shared target) checks the target; a circuit whose target has an
+// entry of modulus strictly between gets NaN and QE_DEVERR_TARGET.  Runs
+// after the evaluation, whose outputs it overwrites.
+template <typename Real>
+__global__ void target_check_kernel(BatchArgs a, Real* f, Real* g, Real* delta) {
+    const int lane = (int)lane_id();
+    const bool shared = a.tstride == 0 && a.uniform_n > 0;
+    const int b = shared ? 0 : (int)(blockIdx.x * 4 + (threadIdx.x >> 6));
+    if (b >= a.B || (shared && (blockIdx.x > 0 || threadIdx.x >= 64))) return;
+    const Item it = resolve(a, b, true);
+    if (it.err) return;                    // malformed circuits report already
+    const int NN = 1 << (2 * it.n);
+    const Real* T = reinterpret_cast<const Real*>(a.targets) + 2 * it.toff;
+    const Real tol = sizeof(Real) == 8 ? (Real)1e-9 : (Real)1e-5;
+    bool bad = false;
+    for (int e = lane; e < NN; e += 64) {
+        const Real x = T[2 * e], y = T[2 * e + 1];
+        const Real m = x * x + y * y;
+        if (!(m <= tol || (m - (Real)1 <= tol && (Real)1 - m <= tol))) bad = true;
+    }
+    if (__ballot(bad) == 0ull) return;
+    const Real nan = (Real)__builtin_nan("");
+    auto mark = [&](int c) {
+        f[c] = nan;
+        if (g) g[c] = nan;
+        if (delta) delta[c] = nan;
+    };
+    if (shared) {
+        for (int c = lane; c < a.B; c += 64) mark(c);
+    } else if (lane == 0) {
+        mark(b);
+    }
+    if (lane == 0) atomicOr(a.err, (uint32_t)QE_DEVERR_TARGET);
+}
+
+hipError_t launch_target_check(const BatchArgs& a, bool fp64, void* f, void* g, void* delta,
+                               hipStream_t s) {
+    if (a.B == 0 || a.mode != QE_FIT_PHASE_INSENSITIVE) return hipSuccess;
+    const unsigned grid = (a.tstride == 0 && a.uniform_n > 0) ? 1u : (unsigned)((a.B + 3) / 4);
+    if (fp64) target_check_kernel<double><<<grid, 256, 0, s>>>(a, (double*)f, (double*)g, (double*)delta);
+    else target_check_kernel<float><<<grid, 256, 0, s>>>(a, (float*)f, (float*)g, (float*)delta);
+    return hipGetLastError();
+}
+
 hipError_t launch_mix_sort(const BatchArgs& a, int32_t* work, hipStream_t s) {
     if (a.B > 0) mix_bucket_kernel<<<1, 1024, 0, s>>>(a, work + MIX_WORK_META, work);
     return hipGetLastError();

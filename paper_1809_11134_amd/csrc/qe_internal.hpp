@@ -36,6 +36,11 @@ constexpr int MIX_WORK_META = 32;
 // per width.
 hipError_t launch_eval_fp32(const BatchArgs& a, int path, float* f, float* g, float* delta,
                             int32_t* work, hipStream_t s);
+// Phase-insensitive mode only (a no-op otherwise): marks circuits whose
+// target has an entry of modulus strictly between 0 and 1 (NaN outputs,
+// QE_DEVERR_TARGET); launched after the evaluation.
+hipError_t launch_target_check(const BatchArgs& a, bool fp64, void* f, void* g, void* delta,
+                               hipStream_t s);
 // The two halves of the sorted mixed-width launch: the cost order of the
 // batch's circuits into work (it depends only on widths and lengths), and
 // the evaluation of a batch in an order computed before.

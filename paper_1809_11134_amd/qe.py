@@ -19,7 +19,7 @@ ALG_QEQEA, ALG_GA = 0, 1
 FIT_EQ11, FIT_PHASE_INSENSITIVE = 0, 1
 (PATH_FP32, PATH_FP32_REG, PATH_FP32_LDS, PATH_MFMA_BF16, PATH_MFMA_FP16, PATH_MFMA_BF16_RAW,
  PATH_MFMA_FP16_RAW, PATH_DENSE) = range(8)
-DEVERR_DESC, DEVERR_WIDTH, DEVERR_RANGE, DEVERR_NUMERIC = 1, 2, 4, 8
+DEVERR_DESC, DEVERR_WIDTH, DEVERR_RANGE, DEVERR_NUMERIC, DEVERR_TARGET = 1, 2, 4, 8, 16
 
 
 class QeError(RuntimeError):
@@ -62,9 +62,10 @@ def load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(LIB_PATH):
-        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1809_11134_amd.build.build()")
-    L = ctypes.CDLL(LIB_PATH)
+    path = os.environ.get("QE_LIB", LIB_PATH)     # e.g. the host-sanitizer build
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with paper_1809_11134_amd.build.build()")
+    L = ctypes.CDLL(path)
     vp, i32, i64, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
     P = ctypes.POINTER
     sig = {

@@ -183,3 +183,69 @@ def test_unknown_mode_rejected(dev):
         qe.eval_fitness(g, T, n=2, L=3, fitness_mode=2)
     with pytest.raises(qe.QeError):
         qe.Context(3, qe.LIB_NCV, qe.ALG_QEQEA, 4, 8, 1, fitness_mode=7)
+
+
+@pytest.mark.parametrize("n", [2, 4, 5])
+def test_monomial_targets_with_phases(dev, oracle, n):
+    """Targets that are permutations with phases (CNOT, NOT and T gates: every
+    entry of modulus 0 or 1) are where the kernels' diagonal overlap equals
+    the oracle's sum |U_ij|^2 |T_ij|^2: parity on every FP32 path and FP64."""
+    rng = np.random.default_rng(900 + n)
+    tab = np.concatenate([inputs.permutation_gates(n),
+                          np.array([inputs.desc(inputs.T, w) for w in range(n)], np.uint16)])
+    tg = tab[rng.integers(0, len(tab), 14)]
+    T = oracle.unitary(n, tg)
+    B, L = 40, 24
+    gates = population(rng, n, 1, B, L, tg)
+    ref = oracle_pi(oracle, n, gates, T)[:, 0]
+    for path in FP32_PATHS:
+        f, _, _ = qe.eval_fitness(t16(gates, dev), torch.from_numpy(T).to(dev), n=n, L=L,
+                                  target_stride=0, path=path, fitness_mode=PI)
+        assert np.abs(f.cpu().numpy().astype(np.float64) - ref).max() <= TOL32, path
+    f64, _, _ = qe.eval_fitness_fp64(t16(gates, dev), torch.from_numpy(T).to(dev), n=n, L=L,
+                                     target_stride=0, fitness_mode=PI)
+    assert np.abs(f64.cpu().numpy() - ref).max() <= TOL64
+    assert qe.device_errors() == 0
+
+
+def test_other_targets_are_refused(dev, oracle):
+    """A target with entries of modulus strictly between 0 and 1 (library
+    {H,T,CNOT,CV,CV+}): the phase-insensitive evaluation gives NaN and
+    QE_DEVERR_TARGET for its circuits (FP32 and FP64 calls), only for them;
+    a context in that mode refuses such targets."""
+    rng = np.random.default_rng(77)
+    n, L, B = 4, 12, 8
+    good = oracle.unitary(n, perm_gates(rng, n))
+    bad = oracle.unitary(n, inputs.random_target_gates(rng, n, 10, lib=1))
+    assert np.any((np.abs(bad) ** 2 > 1e-3) & (np.abs(bad) ** 2 < 1 - 1e-3))
+    gates = inputs.random_circuits(rng, B, n, L, 1)
+    targets = np.stack([good, bad])
+    toff = torch.tensor([0 if b % 2 == 0 else 256 for b in range(B)], dtype=torch.int64, device=dev)
+    nq = torch.full((B,), n, dtype=torch.int8, device=dev)
+    goff = torch.arange(B + 1, dtype=torch.int32, device=dev) * L
+    for fp64 in (False, True):
+        fn = qe.eval_fitness_fp64 if fp64 else qe.eval_fitness
+        f, g, d = fn(t16(gates, dev), torch.from_numpy(targets).to(dev), nq=nq, goff=goff, toff=toff,
+                     target_stride=None, fitness_mode=PI, want_g=True, want_delta=True)
+        fh = f.cpu().numpy()
+        assert np.all(np.isnan(fh[1::2])) and np.all(np.isnan(g.cpu().numpy()[1::2]))
+        assert np.all(np.isfinite(fh[0::2]))
+        assert qe.device_errors() == qe.DEVERR_TARGET
+    # one shared target
+    f, _, _ = qe.eval_fitness(t16(gates, dev), torch.from_numpy(bad).to(dev), n=n, L=L,
+                              target_stride=0, fitness_mode=PI)
+    assert np.all(np.isnan(f.cpu().numpy()))
+    assert qe.device_errors() == qe.DEVERR_TARGET
+    # Eq. 11 takes any target
+    f, _, _ = qe.eval_fitness(t16(gates, dev), torch.from_numpy(bad).to(dev), n=n, L=L, target_stride=0)
+    assert np.all(np.isfinite(f.cpu().numpy()))
+    assert qe.device_errors() == 0
+    ctx = qe.Context(n, 0, qe.ALG_GA, L, 16, 2, seed=3, fitness_mode=PI)
+    with pytest.raises(qe.QeError) as e:
+        ctx.set_targets(torch.from_numpy(targets).to(dev))
+    assert e.value.status == qe.QE_ERR_UNSUPPORTED
+    ctx.set_targets(torch.from_numpy(np.stack([good, good])).to(dev))
+    ctx.generation(0)
+    torch.cuda.synchronize()
+    assert qe.device_errors() == 0
+    ctx.close()

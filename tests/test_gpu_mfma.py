@@ -1,7 +1,11 @@
 """The MFMA path (fused 4-wire gate blocks, bf16/fp16 hi+lo, FP32
 accumulation) against the CPU oracle.  Its error is stated rather than
-bounded by the FP32 tolerance; the tests check it stays within loose bounds
-and that the fp16 variant is the more accurate one."""
+bounded by the FP32 tolerance of 1e-5; the bounds here are about ten times
+the largest error measured on MI355X over these cases and the n=6 benchmark
+batch (|df|: bf16 1.3e-6, bf16 without renormalisation 1.7e-6, fp16 1.1e-7,
+fp16 without renormalisation 2.0e-7), so a regression in the split products
+or the renormalisation shows, and the fp16 variant must be the more
+accurate one."""
 import numpy as np
 import pytest
 import torch
@@ -10,6 +14,9 @@ from paper_1809_11134_amd import inputs, qe
 
 pytestmark = pytest.mark.gpu
 MFMA_PATHS = [qe.PATH_MFMA_BF16, qe.PATH_MFMA_FP16, qe.PATH_MFMA_BF16_RAW, qe.PATH_MFMA_FP16_RAW]
+# (bound on |df|, bound on |dg|) per path
+BOUNDS = {qe.PATH_MFMA_BF16: (2e-5, 1e-5), qe.PATH_MFMA_BF16_RAW: (2e-5, 1e-5),
+          qe.PATH_MFMA_FP16: (3e-6, 2e-6), qe.PATH_MFMA_FP16_RAW: (3e-6, 2e-6)}
 
 
 @pytest.fixture(scope="module")
@@ -45,8 +52,8 @@ def test_mfma_close_to_oracle(dev, oracle, n, L):
         f, g, ref = run(oracle, dev, n, gates, T, path)
         errs[path] = (np.abs(f - ref[:, 0]).max(), np.abs(g - ref[:, 1]).max())
         assert np.all(np.isfinite(f))
-        assert errs[path][1] <= 2e-3, (path, errs[path])
-        assert errs[path][0] <= 2e-2, (path, errs[path])
+        assert errs[path][0] <= BOUNDS[path][0], (path, errs[path])
+        assert errs[path][1] <= BOUNDS[path][1], (path, errs[path])
     assert errs[qe.PATH_MFMA_FP16][1] <= errs[qe.PATH_MFMA_BF16][1] + 1e-6
     assert qe.device_errors() == 0
 
