@@ -396,6 +396,20 @@ qe_status qe_lib_table(int32_t library, int32_t n_qubits, uint16_t* table_host);
 qe_status qe_set_schedule(int32_t n_qubits, int32_t lds);
 qe_status qe_get_schedule(int32_t n_qubits, int32_t* lds);
 
+/* The whole schedule of width n for circuits of length class lclass (0: L <
+ * 32, 1: L >= 32; batches of uneven lengths use class 1): lds as above,
+ * waves = wavefronts per circuit of the LDS-staged kernels (1 for n <= 4, 1
+ * or 2 for n = 5, 4 for n = 6), cpb = circuits per workgroup of the
+ * one-wavefront population kernels (1 or 4).  Process-wide, like
+ * qe_set_schedule; the tuning table (lines "n lclass lds waves cpb") and
+ * QE_SCHEDULE="n:lds[:waves[:cpb]],..." set it too.  Every LDS-staged
+ * schedule gives the same results bit for bit (the fitness reduction runs
+ * in an order fixed by the width); the register-resident kernel agrees
+ * within the FP32 tolerance.  A mixed-population context keeps the width-5
+ * wave count it was created with.  Unknown combinations: QE_ERR_INVALID. */
+qe_status qe_set_schedule_ex(int32_t n_qubits, int32_t lclass, int32_t lds, int32_t waves, int32_t cpb);
+qe_status qe_get_schedule_ex(int32_t n_qubits, int32_t lclass, int32_t* lds, int32_t* waves, int32_t* cpb);
+
 /* Measurement helper (not part of the method): the LDS bandwidth the GPU
  * sustains, the denominator of the per-gate kernels' LDS rooflines.  Launches
  * `workgroups` workgroups of 256 threads, each owning 32 KB of LDS, whose

@@ -83,15 +83,33 @@ qe_status noalloc_scratch(int32_t** out) {
     return QE_OK;
 }
 
-// Per-width schedule of the FP32 path (1 = LDS-staged kernel).  Defaults from
-// MI355X measurements (qe_eval_fitness, n=4: 14.2 us LDS vs 19.8 us register
-// for 4096 x 30 gates; n=5: 422 vs 698 us for 65536 x 40; n=6: 268 vs 667 us
-// for 8192 x 48); QE_SCHEDULE="n:lds,..." overrides.
-int g_sched[MAX_QUBITS + 1] = {0, 0, 0, 0, 1, 1, 1};
+// Schedule of the FP32 path per width and length class (0: L < 32, 1: L >=
+// 32): the LDS-staged kernel or the register-resident one, the LDS kernel's
+// wavefronts per circuit and (one wavefront per circuit) circuits per
+// workgroup of the population kernels.  Defaults from MI355X measurements;
+// the tuning table written by paper_1809_11134_amd/tune.py replaces them, and
+// QE_SCHEDULE="n:lds[:waves[:cpb]],..." overrides both length classes of a
+// width.
+Sched g_sched[MAX_QUBITS + 1][2] = {
+    {{0, 1, 4}, {0, 1, 4}}, {{0, 1, 4}, {0, 1, 4}}, {{0, 1, 4}, {0, 1, 4}}, {{0, 1, 4}, {0, 1, 4}},
+    {{1, 1, 4}, {1, 1, 4}}, {{1, 1, 4}, {1, 1, 4}}, {{1, 4, 1}, {1, 4, 1}}};
 std::once_flag g_sched_once;
 
-// Tuning table written by paper_1809_11134_amd/tune.py: lines "n lds" (comments
-// after '#').  Path: $QE_TUNE_TABLE, else tune_mi355x.txt next to libqe.so.
+// wavefronts per circuit the LDS kernels are built for, per width
+bool waves_ok(int n, int w) {
+    if (n <= 3) return w == 1;
+    if (n == 4) return w == 1;
+    if (n == 5) return w == 1 || w == 2;
+    return w == 4;
+}
+
+bool sched_ok(int n, int lds, int w, int cpb) {
+    return n >= 1 && n <= MAX_QUBITS && (lds == 0 || lds == 1) && waves_ok(n, w) && (cpb == 1 || cpb == 4);
+}
+
+// Tuning table lines: "n lclass lds waves cpb" (one length class), or the
+// older "n lds" (both classes, default waves and cpb); '#' starts a comment.
+// Path: $QE_TUNE_TABLE, else tune_mi355x.txt next to libqe.so.
 void load_tune_table() {
     std::string path;
     if (const char* e = std::getenv("QE_TUNE_TABLE")) {
@@ -108,9 +126,15 @@ void load_tune_table() {
     if (!fh) return;
     char line[256];
     while (std::fgets(line, sizeof line, fh)) {
-        int n = 0, l = 0;
         if (line[0] == '#') continue;
-        if (std::sscanf(line, "%d %d", &n, &l) == 2 && n >= 1 && n <= MAX_QUBITS) g_sched[n] = l ? 1 : 0;
+        if (char* c = std::strchr(line, '#')) *c = 0;
+        int n = 0, x1 = 0, x2 = 0, x3 = 0, x4 = 0;
+        const int got = std::sscanf(line, "%d %d %d %d %d", &n, &x1, &x2, &x3, &x4);
+        if (got == 5 && (x1 == 0 || x1 == 1) && sched_ok(n, x2, x3, x4)) {
+            g_sched[n][x1] = Sched{x2, x3, x4};
+        } else if (got == 2 && n >= 1 && n <= MAX_QUBITS) {
+            g_sched[n][0].lds = g_sched[n][1].lds = x1 ? 1 : 0;
+        }
     }
     std::fclose(fh);
 }
@@ -124,9 +148,17 @@ void load_schedule_env() {
     while (pos < str.size()) {
         size_t comma = str.find(',', pos);
         std::string item = str.substr(pos, comma == std::string::npos ? std::string::npos : comma - pos);
-        int n = 0, l = 0;
-        if (std::sscanf(item.c_str(), "%d:%d", &n, &l) == 2 && n >= 1 && n <= MAX_QUBITS)
-            g_sched[n] = l ? 1 : 0;
+        int n = 0, l = 0, w = 0, c = 0;
+        const int got = std::sscanf(item.c_str(), "%d:%d:%d:%d", &n, &l, &w, &c);
+        if (got >= 2 && n >= 1 && n <= MAX_QUBITS) {
+            for (int k = 0; k < 2; ++k) {
+                Sched v = g_sched[n][k];
+                v.lds = l ? 1 : 0;
+                if (got >= 3) v.waves = w;
+                if (got >= 4) v.cpb = c;
+                if (sched_ok(n, v.lds, v.waves, v.cpb)) g_sched[n][k] = v;
+            }
+        }
         if (comma == std::string::npos) break;
         pos = comma + 1;
     }
@@ -177,6 +209,7 @@ qe_status to_args(const qe_batch* b, BatchArgs* a, bool need_targets) {
     a->targets = b->targets_dev;
     a->num_telems = b->num_target_elems;
     a->mode = b->fitness_mode;
+    a->mix_w5 = schedule_for(5, 32).waves;
     a->angles = b->angles_dev;
     return device_error_word(&a->err);
 }
@@ -184,10 +217,12 @@ qe_status to_args(const qe_batch* b, BatchArgs* a, bool need_targets) {
 }  // namespace
 
 namespace qe {
-bool schedule_lds(int n) {
+Sched schedule_for(int n, int L) {
     std::call_once(g_sched_once, load_schedule_env);
-    return n >= 1 && n <= MAX_QUBITS && g_sched[n] != 0;
+    if (n < 1 || n > MAX_QUBITS) return Sched{0, 1, 4};
+    return g_sched[n][L >= 32 ? 1 : 0];
 }
+bool schedule_lds(int n) { return schedule_for(n, 32).lds != 0; }
 }  // namespace qe
 
 // ====================================================================== ctx
@@ -232,6 +267,7 @@ struct qe_ctx {
     int32_t* mix_eval_work = nullptr;
     size_t mix_work_bytes = 0;
     uint32_t* check_word = nullptr;   // flags of the phase-insensitive target check
+    int32_t mix_w5 = 1;               // the schedule the mixed order was computed for
 };
 
 namespace {
@@ -299,6 +335,7 @@ BatchArgs mixed_batch(const qe_ctx* c, const uint16_t* gates) {
     b.targets = c->la.target32;
     b.num_telems = c->target_elems;
     b.mode = c->prob.fitness_mode;
+    b.mix_w5 = c->mix_w5;
     b.angles = nullptr;
     b.err = c->la.err;
     return b;
@@ -340,14 +377,34 @@ qe_status qe_lib_table(int32_t library, int32_t n, uint16_t* table_host) {
 qe_status qe_set_schedule(int32_t n, int32_t lds) {
     std::call_once(g_sched_once, load_schedule_env);
     if (n < 1 || n > MAX_QUBITS) return fail(QE_ERR_INVALID, "width must be 1..6");
-    g_sched[n] = lds ? 1 : 0;
+    g_sched[n][0].lds = g_sched[n][1].lds = lds ? 1 : 0;
     return QE_OK;
 }
 
 qe_status qe_get_schedule(int32_t n, int32_t* lds) {
     std::call_once(g_sched_once, load_schedule_env);
     if (n < 1 || n > MAX_QUBITS || !lds) return fail(QE_ERR_INVALID, "width must be 1..6");
-    *lds = g_sched[n];
+    *lds = g_sched[n][1].lds;
+    return QE_OK;
+}
+
+qe_status qe_set_schedule_ex(int32_t n, int32_t lclass, int32_t lds, int32_t waves, int32_t cpb) {
+    std::call_once(g_sched_once, load_schedule_env);
+    if (lclass != 0 && lclass != 1) return fail(QE_ERR_INVALID, "lclass must be 0 (L < 32) or 1 (L >= 32)");
+    if (!sched_ok(n, lds, waves, cpb))
+        return fail(QE_ERR_INVALID, "no such schedule: lds 0/1; waves 1 (n <= 5), 2 (n = 5) or 4 (n = 6); cpb 1 or 4");
+    g_sched[n][lclass] = Sched{lds, waves, cpb};
+    return QE_OK;
+}
+
+qe_status qe_get_schedule_ex(int32_t n, int32_t lclass, int32_t* lds, int32_t* waves, int32_t* cpb) {
+    std::call_once(g_sched_once, load_schedule_env);
+    if (n < 1 || n > MAX_QUBITS || (lclass != 0 && lclass != 1) || !lds || !waves || !cpb)
+        return fail(QE_ERR_INVALID, "width 1..6, lclass 0 or 1, non-NULL outputs");
+    const Sched v = g_sched[n][lclass];
+    *lds = v.lds;
+    *waves = v.waves;
+    *cpb = v.cpb;
     return QE_OK;
 }
 
@@ -653,6 +710,7 @@ qe_status create_impl(const qe_problem* p_in, const int32_t* inst_n, const int32
         if (e == hipSuccess)
             e = hipMemcpy(c->circ_toff, h_ctoff.data(), I * P * sizeof(int64_t), hipMemcpyHostToDevice);
         // the cost order of the circuits: widths and lengths never change
+        c->mix_w5 = schedule_for(5, 32).waves;
         if (e == hipSuccess) e = launch_mix_sort(mixed_batch(c, c->gates), c->mix_order, nullptr);
     }
     if (p->algorithm == QE_ALG_QEQEA) {

@@ -79,20 +79,18 @@ __global__ __launch_bounds__(64 * W) void lds32_kernel(BatchArgs a, float* __res
     constexpr int N = 1 << NQ, CW = N / W;
     __shared__ float2 M[N * N];
     __shared__ uint4 GT[W][ANG ? GATE_TABLE_ANGLED : GATE_TABLE];
-    __shared__ float red[W][3];
     const int b = blockIdx.x;
     const int lane = (int)lane_id(), wave = (int)(threadIdx.x >> 6);
     Item it = resolve(a, b, !IDENT);
     if (FILTER && it.n != NQ) return;
     if (it.err == 0 && it.n != NQ) it.err = QE_DEVERR_WIDTH;
     bool ok = it.err == 0;
-    float off = 0.0f;
-    float2 dg = make_float2(0.0f, 0.0f);
+    RowMap map{};
     if (ok) {
         const int L = it.L;
         auto src = [&](int ch) { return batch_gate<ANG>(it, ch * 64 + lane); };
         const float* T = IDENT ? nullptr : reinterpret_cast<const float*>(a.targets) + 2 * it.toff;
-        ok = run_lds_path<NQ, W, IDENT>(M, GT[wave], T, L, src, IDENT ? nullptr : &off, &dg);
+        ok = run_lds_path<NQ, W, IDENT>(M, GT[wave], T, L, src, IDENT ? nullptr : &map);
         if (!ok) it.err = QE_DEVERR_DESC;
     }
     if (IDENT) {
@@ -103,30 +101,12 @@ __global__ __launch_bounds__(64 * W) void lds32_kernel(BatchArgs a, float* __res
         if (threadIdx.x == 0 && it.err) atomicOr(a.err, it.err);
         return;
     }
-    // fitness: reduce the per-wave partial sums over the workgroup
-    const float offw = wave_sum(off), trw = wave_sum(dg.x), tiw = wave_sum(dg.y);
-    if (lane == 0) { red[wave][0] = offw; red[wave][1] = trw; red[wave][2] = tiw; }
-    __syncthreads();
-    float offs = 0.0f, tr = 0.0f, ti = 0.0f;
-#pragma unroll
-    for (int w = 0; w < W; ++w) { offs += red[w][0]; tr += red[w][1]; ti += red[w][2]; }
-    const float am = sqrtf(tr * tr + ti * ti);
-    float er = 1.0f, ei = 0.0f;
-    if (am > 0.0f) { er = tr / am; ei = ti / am; }
-    float dl = 0.0f;
-    if (lane < CW) { const float xr = dg.x - er, xi = dg.y - ei; dl = xr * xr + xi * xi; }
-    const float dw = wave_sum(dl);
-    __syncthreads();
-    if (lane == 0) red[wave][0] = dw;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        float D = 0.0f;
-#pragma unroll
-        for (int w = 0; w < W; ++w) D += red[w][0];
-        float dlt = 0.5f * (offs + D);
-        float q = fminf(fmaxf(dlt / (float)N, 0.0f), 1.0f);
-        float fv = 1.0f - sqrtf(q), gv = am / (float)N;
-        if (a.mode == QE_FIT_PHASE_INSENSITIVE) fitness_pi(offs, N, &fv, &gv, &dlt);
+    // fitness: one wavefront over the whole matrix, in the width's fixed order
+    if constexpr (W > 1) __syncthreads();
+    if (wave != 0) return;
+    float gv, dlt;
+    const float fv = canonical_fitness<NQ>(M, map, a.mode, &gv, &dlt);
+    if (lane == 0) {
         const float nan = __builtin_nanf("");
         if (ok && !(fv == fv)) it.err = QE_DEVERR_NUMERIC;
         f[b] = ok ? fv : nan;
@@ -157,7 +137,9 @@ __device__ __forceinline__ int mix_key(const BatchArgs& a, int b) {
     const int lc = len >= 120 ? 0 : (len < 8 ? MIX_LCLASSES - 1 : MIX_LCLASSES - 1 - (int)(len >> 3));
     return mix_bucket(a.nq[b]) * MIX_LCLASSES + lc;
 }
-__device__ __forceinline__ int mix_per_item(int k) { return k == 0 ? 1 : 4; }
+// circuits per work item: one of width 6 (four wavefronts), four (or with two
+// wavefronts per circuit two) of width 5, four of the other widths
+__device__ __forceinline__ int mix_per_item(int k, int w5) { return k == 0 ? 1 : (k == 1 && w5 == 2 ? 2 : 4); }
 
 // meta: [0..7) first order position, [8..15) first item (8 entries, the last
 // the total), [16..23) count per bucket.
@@ -195,7 +177,7 @@ __global__ __launch_bounds__(1024) void mix_bucket_kernel(BatchArgs a, int32_t* 
             meta[k] = pos;
             meta[8 + k] = item;
             meta[16 + k] = end - pos;
-            item += (end - pos + mix_per_item(k) - 1) / mix_per_item(k);
+            item += (end - pos + mix_per_item(k, a.mix_w5) - 1) / mix_per_item(k, a.mix_w5);
         }
         meta[8 + MIX_BUCKETS] = item;
     }
@@ -205,14 +187,13 @@ __global__ __launch_bounds__(1024) void mix_bucket_kernel(BatchArgs a, int32_t* 
 
 template <int NQ, int W>
 __device__ __forceinline__ void mix_lds_item(const BatchArgs& a, int b, float2* M, uint4* gt,
-                                             float (*red)[3], float* f, float* g, float* delta) {
+                                             float* f, float* g, float* delta) {
     const int lane = (int)lane_id(), wave = (int)(threadIdx.x >> 6);
     Item it;
     it.err = 1;
     if (b >= 0) it = resolve(a, b);
     bool ok = it.err == 0;
-    float off = 0.0f;
-    float2 dg = make_float2(0.0f, 0.0f);
+    RowMap map{};
     if (ok) {
         const uint16_t* gp = it.g;
         const int L = it.L;
@@ -221,12 +202,14 @@ __device__ __forceinline__ void mix_lds_item(const BatchArgs& a, int b, float2* 
             return p < L ? (uint32_t)gp[p] : 0u;
         };
         const float* T = reinterpret_cast<const float*>(a.targets) + 2 * it.toff;
-        ok = run_lds_path<NQ, W, false>(M, gt, T, L, src, &off, &dg, wave % W);
+        ok = run_lds_path<NQ, W, false>(M, gt, T, L, src, &map, wave % W);
         if (!ok) it.err = QE_DEVERR_DESC;
     }
+    if constexpr (W > 1) __syncthreads();     // every wavefront's columns are in place
+    if (wave % W != 0) return;
     float gv, dv;
-    const float fv = group_fitness<W>(off, dg, red, 1 << NQ, &gv, &dv, a.mode);
-    if (b >= 0 && wave % W == 0 && lane == 0) {
+    const float fv = canonical_fitness<NQ>(M, map, a.mode, &gv, &dv);
+    if (b >= 0 && lane == 0) {
         const float nan = __builtin_nanf("");
         if (ok && !(fv == fv)) it.err = QE_DEVERR_NUMERIC;
         f[b] = ok ? fv : nan;
@@ -272,22 +255,24 @@ __global__ __launch_bounds__(256) void mix_kernel(BatchArgs a, const int32_t* __
                                                   float* __restrict__ delta) {
     __shared__ float2 M[4096];
     __shared__ uint4 GT[4][GATE_TABLE];
-    __shared__ float red[4][3];
     const int item = blockIdx.x;
     if (item >= meta[8 + MIX_BUCKETS]) return;
     int k = 0;
     while (k + 1 < MIX_BUCKETS && item >= meta[8 + k + 1]) ++k;
     const int wave = (int)(threadIdx.x >> 6);
-    const int per = mix_per_item(k);
+    const int per = mix_per_item(k, a.mix_w5);
     const int local = (item - meta[8 + k]) * per;
     const int sub = per == 1 ? 0 : (per == 2 ? wave >> 1 : wave);
     int b = local + sub < meta[16 + k] ? order[meta[k] + local + sub] : -1;
     if (b >= a.B) b = -1;        // an order written for another batch never indexes past this one
     switch (k) {
         // (widths 4 and 5 run one circuit per wavefront, each with its gate table)
-        case 0: mix_lds_item<6, 4>(a, b, M, nullptr, red, f, g, delta); break;
-        case 1: mix_lds_item<5, 1>(a, b, M + sub * 1024, GT[wave], red, f, g, delta); break;
-        case 2: mix_lds_item<4, 1>(a, b, M + sub * 256, GT[wave], red, f, g, delta); break;
+        case 0: mix_lds_item<6, 4>(a, b, M, nullptr, f, g, delta); break;
+        case 1:
+            if (a.mix_w5 == 2) mix_lds_item<5, 2>(a, b, M + sub * 1024, nullptr, f, g, delta);
+            else mix_lds_item<5, 1>(a, b, M + sub * 1024, GT[wave], f, g, delta);
+            break;
+        case 2: mix_lds_item<4, 1>(a, b, M + sub * 256, GT[wave], f, g, delta); break;
         case 3: mix_wave_item<3>(a, b, f, g, delta); break;
         case 4: mix_wave_item<2>(a, b, f, g, delta); break;
         case 5: mix_wave_item<1>(a, b, f, g, delta); break;
@@ -330,12 +315,15 @@ static size_t lds_kernel_bytes(const BatchArgs& a, size_t real_bytes) {
 // Per-width schedule: which kernel evaluates a circuit of width n on the
 // FP32 path.  path: QE_PATH_FP32 (default schedule), QE_PATH_FP32_REG,
 // QE_PATH_FP32_LDS.
-static bool use_lds(int n, int path) {
+static bool use_lds(int n, int path, int L) {
     if (n <= 3) return false;
     if (path == QE_PATH_FP32_REG) return false;
     if (path == QE_PATH_FP32_LDS) return true;
-    return schedule_lds(n);
+    return schedule_for(n, L).lds != 0;
 }
+
+// length of the batch's circuits for the schedule (uneven batches: the long class)
+static int sched_len(const BatchArgs& a) { return a.uniform_L > 0 ? a.uniform_L : 32; }
 
 // Angled batches (ANG): the one-element-per-lane kernel for n <= 3 and the
 // LDS-staged one above (the register-resident path has no Ising kinds).
@@ -349,7 +337,12 @@ static void launch_width(const BatchArgs& a, int n, bool lds, float* f, float* g
             case 2: wave_kernel<2, FILTER, true><<<wgrid, wblock, 0, s>>>(a, f, g, delta); break;
             case 3: wave_kernel<3, FILTER, true><<<wgrid, wblock, 0, s>>>(a, f, g, delta); break;
             case 4: lds32_kernel<4, 1, FILTER, false, true><<<a.B, 64, 0, s>>>(a, f, g, delta, nullptr); break;
-            case 5: lds32_kernel<5, 1, FILTER, false, true><<<a.B, 64, 0, s>>>(a, f, g, delta, nullptr); break;
+            case 5:
+                if (schedule_for(5, sched_len(a)).waves == 2)
+                    lds32_kernel<5, 2, FILTER, false, true><<<a.B, 128, 0, s>>>(a, f, g, delta, nullptr);
+                else
+                    lds32_kernel<5, 1, FILTER, false, true><<<a.B, 64, 0, s>>>(a, f, g, delta, nullptr);
+                break;
             default: lds32_kernel<6, 4, FILTER, false, true><<<a.B, 256, 0, s>>>(a, f, g, delta, nullptr); break;
         }
         return;
@@ -357,7 +350,12 @@ static void launch_width(const BatchArgs& a, int n, bool lds, float* f, float* g
     if (lds) {
         switch (n) {
             case 4: lds32_kernel<4, 1, FILTER, false><<<a.B, 64, 0, s>>>(a, f, g, delta, nullptr); break;
-            case 5: lds32_kernel<5, 1, FILTER, false><<<a.B, 64, 0, s>>>(a, f, g, delta, nullptr); break;
+            case 5:
+                if (schedule_for(5, sched_len(a)).waves == 2)
+                    lds32_kernel<5, 2, FILTER, false><<<a.B, 128, 0, s>>>(a, f, g, delta, nullptr);
+                else
+                    lds32_kernel<5, 1, FILTER, false><<<a.B, 64, 0, s>>>(a, f, g, delta, nullptr);
+                break;
             default: lds32_kernel<6, 4, FILTER, false><<<a.B, 256, 0, s>>>(a, f, g, delta, nullptr); break;
         }
         return;
@@ -383,7 +381,7 @@ hipError_t launch_eval_fp32(const BatchArgs& a, int path, float* f, float* g, fl
             for (int n = 1; n <= MAX_QUBITS; ++n) launch_width<true, true>(a, n, true, f, g, delta, s);
         }
     } else if (a.uniform_n > 0) {
-        launch_width<false>(a, a.uniform_n, use_lds(a.uniform_n, path), f, g, delta, s);
+        launch_width<false>(a, a.uniform_n, use_lds(a.uniform_n, path, sched_len(a)), f, g, delta, s);
     } else if (path == QE_PATH_FP32 && work) {
         // one launch over width-sorted work items (LDS-staged for n >= 4)
         mix_bucket_kernel<<<1, 1024, 0, s>>>(a, work + MIX_WORK_META, work);
@@ -391,7 +389,7 @@ hipError_t launch_eval_fp32(const BatchArgs& a, int path, float* f, float* g, fl
     } else {
         width_check_kernel<<<(a.B + 255) / 256, 256, 0, s>>>(a, f, g, delta);
         for (int n = 1; n <= MAX_QUBITS; ++n)
-            launch_width<true>(a, n, use_lds(n, path), f, g, delta, s);
+            launch_width<true>(a, n, use_lds(n, path, sched_len(a)), f, g, delta, s);
     }
     return hipGetLastError();
 }

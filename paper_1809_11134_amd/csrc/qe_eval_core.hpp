@@ -566,9 +566,8 @@ __device__ __forceinline__ void wave_lds_fence() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Runs the circuit on this wave's columns and, with `fit`, leaves per-wave
-// partial sums for the fitness: off-diagonal |m|^2, and the diagonal
-// elements of the wave's columns (lane l < CW holds element (j, j)).
+// Runs the circuit on this wave's columns, leaving the product in M (its
+// rows under the row map, which goes to *map_out for the fitness).
 // gt: this wavefront's gate table in LDS (GATE_TABLE uint4, or
 // GATE_TABLE_ANGLED for angled gate sources).  NCV: the source only yields
 // kinds of {I, NOT, CNOT, CV, CV+} (circuits decoded by the QEQEA sampler);
@@ -577,10 +576,16 @@ __device__ __forceinline__ void wave_lds_fence() {
 constexpr int GATE_TABLE = 128;
 constexpr int GATE_TABLE_ANGLED = 192;
 
+// The logical-to-stored row map of the LDS layout: logical row r of the
+// product lives in stored row A r ^ b (A's column p in bits 6p..6p+5).
+struct RowMap {
+    uint64_t A;
+    uint32_t b;
+};
+
 template <int NQ, int W, bool IDENT, bool NCV = false, typename GateSrc>
 __device__ __forceinline__ bool run_lds_path(float2* M, uint4* gt, const float* __restrict__ T, int L,
-                                             GateSrc&& src, float* off_out, float2* diag_out,
-                                             int wave = -1) {
+                                             GateSrc&& src, RowMap* map_out, int wave = -1) {
     constexpr int N = 1 << NQ, CW = N / W, RG = 64 / CW;
     constexpr bool ANG = src_angled<GateSrc>();
     constexpr int ES = ANG ? 3 : 2;        // uint4 per gate-table entry
@@ -995,29 +1000,7 @@ __device__ __forceinline__ bool run_lds_path(float2* M, uint4* gt, const float* 
             }
         }
     }
-    if (off_out) {
-        // logical entry (j, j) is stored in row phi(j) = A j + b
-        int pj = (int)bmap;
-#pragma unroll
-        for (int p = 0; p < NQ; ++p)
-            if ((j >> p) & 1) pj ^= (int)((Amap >> (6 * p)) & 63u);
-        // every read is issued before any is used (the reads are kept
-        // unconditional: a read under the diagonal test would wait for each
-        // in turn)
-        float2 vv[N / RG];
-#pragma unroll
-        for (int m = 0; m < N / RG; ++m) vv[m] = M[(m * RG + rg) * N + j];
-#pragma unroll
-        for (int m = 0; m < N / RG; ++m) asm volatile("" ::"v"(vv[m].x), "v"(vv[m].y));
-        float off = 0.0f;
-#pragma unroll
-        for (int m = 0; m < N / RG; ++m) {
-            const int r = m * RG + rg;
-            off += (r == pj) ? 0.0f : vv[m].x * vv[m].x + vv[m].y * vv[m].y;
-        }
-        *off_out = off;
-        *diag_out = (lane < CW) ? M[pj * N + j] : make_float2(0.0f, 0.0f);
-    }
+    if (map_out) *map_out = RowMap{Amap, bmap};
     return ok;
 }
 
@@ -1223,67 +1206,71 @@ __device__ __forceinline__ void lds_generic_body(int n, int L, const uint16_t* g
     lds_fitness<Real>(Mr, Mi, N, ok, err, f, g, delta, errw, mode, red);
 }
 
-// Eq. 11 from the per-wave partial sums of the LDS-staged path, for the W
-// wavefronts gb .. gb+W-1 of a 4-wave workgroup that share a circuit (for
-// W > 1 every wavefront of the workgroup must call it: it contains workgroup
-// barriers; W = 1 uses none).
-// red: 4 x 3 floats of LDS.  Returns the fitness on every lane; g, delta out.
-template <int W>
-__device__ __forceinline__ float group_fitness(float off, float2 dg, float (*red)[3], int N,
-                                               float* g_out, float* delta_out,
-                                               int mode = QE_FIT_EQ11) {
-    const int lane = (int)lane_id(), wave = (int)(threadIdx.x >> 6);
-    const int gb = (wave / W) * W, CW = N / W;
-    const float offw = wave_sum(off), trw = wave_sum(dg.x), tiw = wave_sum(dg.y);
-    if (mode == QE_FIT_PHASE_INSENSITIVE) {
-        float offs = offw;
-        if constexpr (W > 1) {
-            __syncthreads();
-            if (lane == 0) red[wave][0] = offw;
-            __syncthreads();
-            offs = 0.0f;
+// Eq. 11 (or the phase-insensitive form) of one circuit from its product in
+// LDS, by one wavefront, in an order fixed by the width alone: lane l takes
+// column j = l mod N and the logical rows r = q, q + 64/N, ... (q = l div N)
+// in increasing order (row r is stored at A r ^ b), then the wavefront's
+// reduction tree adds the lanes.  Every LDS-staged schedule -- wavefronts
+// per circuit, circuits per workgroup, packing of mixed batches -- therefore
+// gives the same bits.  Returns f on every lane; g, delta out.
+template <int NQ>
+__device__ __forceinline__ float canonical_fitness(const float2* M, const RowMap map, int mode,
+                                                   float* g_out, float* delta_out) {
+    constexpr int N = 1 << NQ, Q = 64 / N, ROWB = NQ + 3;
+    const int lane = (int)lane_id(), j = lane % N, q = lane / N;
+    const char* Mj = reinterpret_cast<const char*>(M) + (uint32_t)j * 8u;
+    auto col = [&](int p) -> uint32_t { return (uint32_t)(map.A >> (6 * p)) & 63u; };
+    // stored row of logical row q (lane part) and of Q m (uniform part)
+    uint32_t sq = 0u;
 #pragma unroll
-            for (int w = 0; w < W; ++w) offs += red[gb + w][0];
+    for (int p = 0; p < NQ; ++p)
+        if ((1 << p) < Q && ((q >> p) & 1)) sq ^= col(p);
+    // the rows in blocks of at most 16 (the block's reads are issued together)
+    constexpr int R = N / Q, BLK = R < 16 ? R : 16;
+    float off = 0.0f;
+    float2 d = make_float2(0.0f, 0.0f);
+    for (int m0 = 0; m0 < R; m0 += BLK) {
+        uint32_t s0 = map.b;               // stored image of Q m0 (bits above the block's)
+#pragma unroll
+        for (int p = 0; p < NQ; ++p)
+            if (((Q * m0) >> p) & 1) s0 ^= col(p);
+        float2 v[BLK];
+#pragma unroll
+        for (int i = 0; i < BLK; ++i) {
+            uint32_t sm = s0;
+#pragma unroll
+            for (int p = 0; p < NQ; ++p)
+                if (((Q * i) >> p) & 1) sm ^= col(p);
+            v[i] = *reinterpret_cast<const float2*>(Mj + ((sq ^ sm) << ROWB));
         }
+        // (the reads stay unconditional: under the diagonal test each would
+        // be waited for in turn)
+#pragma unroll
+        for (int i = 0; i < BLK; ++i) asm volatile("" ::"v"(v[i].x), "v"(v[i].y));
+#pragma unroll
+        for (int i = 0; i < BLK; ++i) {
+            const int r = q + Q * (m0 + i);
+            if (r == j) d = v[i];
+            else off += v[i].x * v[i].x + v[i].y * v[i].y;
+        }
+    }
+    const float offs = wave_sum(off);
+    if (mode == QE_FIT_PHASE_INSENSITIVE) {
         float fv;
         fitness_pi(offs, N, &fv, g_out, delta_out);
         return fv;
     }
-    if constexpr (W == 1) {   // one wavefront per circuit: no LDS exchange
-        const float am = sqrtf(trw * trw + tiw * tiw);
-        float er = 1.0f, ei = 0.0f;
-        if (am > 0.0f) { er = trw / am; ei = tiw / am; }
-        float dl = 0.0f;
-        if (lane < CW) { const float xr = dg.x - er, xi = dg.y - ei; dl = xr * xr + xi * xi; }
-        const float dlt = 0.5f * (offw + wave_sum(dl));
-        const float q = fminf(fmaxf(dlt / (float)N, 0.0f), 1.0f);
-        *g_out = am / (float)N;
-        *delta_out = dlt;
-        return 1.0f - sqrtf(q);
-    }
-    __syncthreads();
-    if (lane == 0) { red[wave][0] = offw; red[wave][1] = trw; red[wave][2] = tiw; }
-    __syncthreads();
-    float offs = 0.0f, tr = 0.0f, ti = 0.0f;
-#pragma unroll
-    for (int w = 0; w < W; ++w) { offs += red[gb + w][0]; tr += red[gb + w][1]; ti += red[gb + w][2]; }
+    const float tr = wave_sum(d.x), ti = wave_sum(d.y);
     const float am = sqrtf(tr * tr + ti * ti);
     float er = 1.0f, ei = 0.0f;
     if (am > 0.0f) { er = tr / am; ei = ti / am; }
     float dl = 0.0f;
-    if (lane < CW) { const float xr = dg.x - er, xi = dg.y - ei; dl = xr * xr + xi * xi; }
-    const float dw = wave_sum(dl);
-    __syncthreads();
-    if (lane == 0) red[wave][0] = dw;
-    __syncthreads();
-    float D = 0.0f;
-#pragma unroll
-    for (int w = 0; w < W; ++w) D += red[gb + w][0];
-    const float dlt = 0.5f * (offs + D);
-    const float q = fminf(fmaxf(dlt / (float)N, 0.0f), 1.0f);
+    if (j % Q == q) { const float xr = d.x - er, xi = d.y - ei; dl = xr * xr + xi * xi; }
+    const float dlt = 0.5f * (offs + wave_sum(dl));
+    const float qq = fminf(fmaxf(dlt / (float)N, 0.0f), 1.0f);
     *g_out = am / (float)N;
     *delta_out = dlt;
-    return 1.0f - sqrtf(q);
+    return 1.0f - sqrtf(qq);
 }
 
 template <bool IDENT, typename GateSrc>

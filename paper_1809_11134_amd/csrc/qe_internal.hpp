@@ -19,11 +19,19 @@ struct BatchArgs {
     const void* targets;
     int64_t num_telems;
     int32_t mode;           // QE_FIT_*
+    int32_t mix_w5;         // wavefronts per width-5 circuit in the sorted mixed launch (1 or 2)
     const uint32_t* angles; // per-gate angles (u32 turn fractions, parallel to gates) or null
     uint32_t* err;          // device error word (atomicOr of QE_DEVERR_*)
 };
 
-// api.hip: per-width schedule of the FP32 path (true = LDS-staged kernel)
+// api.hip: schedule of the FP32 path for circuits of width n and length L:
+// LDS-staged (lds = 1) or register-resident kernel, the LDS kernels'
+// wavefronts per circuit, circuits per workgroup of the one-wavefront
+// population kernels
+struct Sched {
+    int lds, waves, cpb;
+};
+Sched schedule_for(int n, int L);
 bool schedule_lds(int n);
 
 // Workspace of a mixed-width batch: MIX_WORK_META int32 of item table, then

@@ -258,8 +258,7 @@ __device__ __forceinline__ void eval_circuit(const LoopArgs& a, uint32_t gen, ui
                                              const uint16_t* gates_in, const uint32_t* angles_in,
                                              uint32_t* slots_out, uint16_t* gates_out,
                                              uint32_t* angles_out, float* f_out, bool writer,
-                                             bool decide, float2* M, uint4* gt, float (*red)[3],
-                                             void* xch = nullptr) {
+                                             bool decide, float2* M, uint4* gt, void* xch = nullptr) {
     const uint32_t i = ci / (uint32_t)a.P, k = ci % (uint32_t)a.P;
     const int lane = (int)lane_id();
     const int L = a.L;
@@ -335,13 +334,13 @@ __device__ __forceinline__ void eval_circuit(const LoopArgs& a, uint32_t gen, ui
         ok = run_width<NQ, false>(NQ, T, L, src, nullptr, &o, a.fit_mode);
         fv = o.f;
     } else {
-        constexpr int N = 1 << NQ;
-        float off, gd, dd;
-        float2 dg;
+        float gd, dd;
+        RowMap map{};
         // circuits the sampler decodes hold only {I, NOT, CNOT, CV, CV+}
         constexpr bool NCV = SAMPLE && !ISING;
-        ok = run_lds_path<NQ, W, false, NCV>(M, gt, T, L, src, &off, &dg, W == 1 ? 0 : -1);
-        fv = group_fitness<W>(off, dg, red, N, &gd, &dd, a.fit_mode);
+        ok = run_lds_path<NQ, W, false, NCV>(M, gt, T, L, src, &map, W == 1 ? 0 : -1);
+        if constexpr (W > 1) __syncthreads();     // every wavefront's columns are in place
+        fv = writer ? canonical_fitness<NQ>(M, map, a.fit_mode, &gd, &dd) : 0.0f;
     }
     if (!ok) fv = __builtin_nanf("");
     if (writer && lane == 0) {
@@ -367,7 +366,7 @@ __device__ __forceinline__ void eval_circuit(const LoopArgs& a, uint32_t gen, ui
         mark_mutation(a, gen, i, k);
 }
 
-template <int NQ, int W, bool SAMPLE, bool ISING = false>
+template <int NQ, int W, bool SAMPLE, bool ISING = false, int CPB = (W == 1 ? 4 : 1)>
 __global__ __launch_bounds__(256) void population_kernel(LoopArgs a, uint64_t gen64,
                                                          const uint16_t* __restrict__ gates_in,
                                                          const uint32_t* __restrict__ angles_in,
@@ -382,15 +381,15 @@ __global__ __launch_bounds__(256) void population_kernel(LoopArgs a, uint64_t ge
         const uint32_t ci = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
         if (ci >= total) return;
         eval_circuit<NQ, 0, SAMPLE, ISING>(a, gen, ci, gates_in, angles_in, slots_out, gates_out,
-                                           angles_out, f_out, true, decide, nullptr, nullptr, nullptr);
+                                           angles_out, f_out, true, decide, nullptr, nullptr);
     } else {
-        // W = 1: four circuits per workgroup, one per wavefront (no barrier
+        // W = 1: CPB circuits per workgroup, one per wavefront (no barrier
         // is shared, so a wavefront past the end may leave); W > 1: one
         // circuit per workgroup of W wavefronts
-        constexpr int N = 1 << NQ, CPB = W == 1 ? 4 : 1;
+        static_assert(W == 1 || CPB == 1, "one circuit per workgroup of several wavefronts");
+        constexpr int N = 1 << NQ;
         __shared__ float2 M[CPB][N * N];
-        __shared__ uint4 GT[W == 1 ? 4 : W][ISING ? GATE_TABLE_ANGLED : GATE_TABLE];
-        __shared__ float red[4][3];
+        __shared__ uint4 GT[W == 1 ? CPB : W][ISING ? GATE_TABLE_ANGLED : GATE_TABLE];
         const int wave = (int)(threadIdx.x >> 6);
         const uint32_t ci = W == 1 ? blockIdx.x * CPB + (uint32_t)wave : blockIdx.x;
         if (ci >= total) return;
@@ -398,14 +397,14 @@ __global__ __launch_bounds__(256) void population_kernel(LoopArgs a, uint64_t ge
         // descriptor exchange)
         eval_circuit<NQ, W, SAMPLE, ISING>(a, gen, ci, gates_in, angles_in, slots_out, gates_out,
                                            angles_out, f_out, W == 1 || threadIdx.x < 64, decide,
-                                           M[W == 1 ? wave : 0], GT[wave], red,
+                                           M[W == 1 ? wave : 0], GT[wave],
                                            W == 1 ? nullptr : static_cast<void*>(GT[0]));
     }
 }
 
 // -------------------------------------------------------------- scatter-max
 // Segment fitness for the step-by-step path (qe_update): every entry raises
-// its slot's key to its circuit's (fitness, index).
+// its slot's key to its circuit's fitness.
 __global__ void scatter_kernel(LoopArgs a, const uint32_t* __restrict__ slots,
                                const float* __restrict__ f) {
     const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1000,22 +999,42 @@ static void launch_population(const LoopArgs& a, uint64_t gen, const uint16_t* g
                               bool decide = false) {
     const uint32_t total = (uint32_t)a.I * (uint32_t)a.P;
     const unsigned wb = blocks(total, 4);
+    const Sched sc = schedule_for(a.n, a.L);
+    // the LDS-staged kernels of widths 4 and 5 under the schedule (waves per
+    // circuit; circuits per workgroup with one wavefront per circuit)
+    auto lds45 = [&](auto nq, auto ising) {
+        constexpr int NQ = decltype(nq)::value;
+        constexpr bool IS = decltype(ising)::value;
+        if constexpr (NQ == 5) {
+            if (sc.waves == 2) {
+                population_kernel<NQ, 2, SAMPLE, IS><<<total, 128, 0, s>>>(a, gen, gin, ain, sout, gout, aout, f, decide);
+                return;
+            }
+        }
+        if (sc.cpb == 1)
+            population_kernel<NQ, 1, SAMPLE, IS, 1><<<total, 64, 0, s>>>(a, gen, gin, ain, sout, gout, aout, f, decide);
+        else
+            population_kernel<NQ, 1, SAMPLE, IS, 4><<<wb, 256, 0, s>>>(a, gen, gin, ain, sout, gout, aout, f, decide);
+    };
+    using I4 = std::integral_constant<int, 4>;
+    using I5 = std::integral_constant<int, 5>;
+    using T_ = std::true_type;
+    using F_ = std::false_type;
     if (a.lib == LIB_ISING) {
         // one wavefront per circuit below 4 wires, the LDS-staged layout above
         switch (a.n) {
             case 2: population_kernel<2, 0, SAMPLE, true><<<wb, 256, 0, s>>>(a, gen, gin, ain, sout, gout, aout, f, decide); break;
             case 3: population_kernel<3, 0, SAMPLE, true><<<wb, 256, 0, s>>>(a, gen, gin, ain, sout, gout, aout, f, decide); break;
-            case 4: population_kernel<4, 1, SAMPLE, true><<<wb, 256, 0, s>>>(a, gen, gin, ain, sout, gout, aout, f, decide); break;
-            case 5: population_kernel<5, 1, SAMPLE, true><<<wb, 256, 0, s>>>(a, gen, gin, ain, sout, gout, aout, f, decide); break;
+            case 4: lds45(I4{}, T_{}); break;
+            case 5: lds45(I5{}, T_{}); break;
             default: population_kernel<6, 4, SAMPLE, true><<<total, 256, 0, s>>>(a, gen, gin, ain, sout, gout, aout, f, decide); break;
         }
         return;
     }
-    const bool lds = schedule_lds(a.n);
-    if (lds && a.n >= 4) {
+    if (sc.lds && a.n >= 4) {
         switch (a.n) {
-            case 4: population_kernel<4, 1, SAMPLE><<<wb, 256, 0, s>>>(a, gen, gin, ain, sout, gout, aout, f, decide); break;
-            case 5: population_kernel<5, 1, SAMPLE><<<wb, 256, 0, s>>>(a, gen, gin, ain, sout, gout, aout, f, decide); break;
+            case 4: lds45(I4{}, F_{}); break;
+            case 5: lds45(I5{}, F_{}); break;
             default: population_kernel<6, 4, SAMPLE><<<total, 256, 0, s>>>(a, gen, gin, ain, sout, gout, aout, f, decide); break;
         }
         return;

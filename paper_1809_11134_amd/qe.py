@@ -95,6 +95,8 @@ def load():
         "qe_create_mixed": [P(Problem), vp, vp, P(vp)],
         "qe_eval_fitness_ws": [P(Batch), i32, vp, vp, vp, vp, ctypes.c_size_t, vp],
         "qe_eval_fitness_noalloc": [P(Batch), i32, vp, vp, vp, vp],
+        "qe_set_schedule_ex": [i32, i32, i32, i32, i32],
+        "qe_get_schedule_ex": [i32, i32, P(i32), P(i32), P(i32)],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -286,6 +288,18 @@ def get_schedule(n):
     v = ctypes.c_int32(0)
     _call("qe_get_schedule", n, ctypes.byref(v))
     return v.value
+
+
+def set_schedule_ex(n, lclass, lds, waves, cpb):
+    """Full schedule of width n, length class lclass (0: L < 32, 1: L >= 32)."""
+    _call("qe_set_schedule_ex", n, lclass, int(lds), int(waves), int(cpb))
+
+
+def get_schedule_ex(n, lclass):
+    """(lds, waves, cpb) of width n, length class lclass."""
+    v = [ctypes.c_int32(0) for _ in range(3)]
+    _call("qe_get_schedule_ex", n, lclass, *[ctypes.byref(x) for x in v])
+    return tuple(x.value for x in v)
 
 
 class Context:

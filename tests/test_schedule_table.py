@@ -1,13 +1,17 @@
-"""The per-width schedule table written by the autotuner is read by libqe at
-first use (QE_TUNE_TABLE), and QE_SCHEDULE overrides single widths.  Runs in
-subprocesses because the table is loaded once per process; no GPU needed."""
+"""The schedule table written by the autotuner is read by libqe at first use
+(QE_TUNE_TABLE), in its full form ("n lclass lds waves cpb") and the short
+one ("n lds"); QE_SCHEDULE overrides single widths; impossible schedules are
+ignored.  Runs in subprocesses because the table is loaded once per process;
+no GPU needed."""
 import os
 import subprocess
 import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 PROBE = ("import sys; sys.path.insert(0, %r); from paper_1809_11134_amd import qe; "
-         "print(' '.join(str(qe.get_schedule(n)) for n in range(1, 7)))" % ROOT)
+         "print(' '.join(str(qe.get_schedule(n)) for n in range(1, 7))); "
+         "print(' '.join(','.join(str(x) for x in qe.get_schedule_ex(n, c)) for n in range(1, 7) for c in (0, 1)))"
+         % ROOT)
 
 
 def schedule_with(env_extra):
@@ -17,16 +21,46 @@ def schedule_with(env_extra):
     env.update(env_extra)
     out = subprocess.run([sys.executable, "-c", PROBE], env=env, capture_output=True, text=True,
                          check=True)
-    return [int(x) for x in out.stdout.split()]
+    a, b = out.stdout.split("\n")[:2]
+    full = [tuple(int(x) for x in t.split(",")) for t in b.split()]
+    return [int(x) for x in a.split()], {(n, c): full[2 * (n - 1) + c] for n in range(1, 7) for c in (0, 1)}
 
 
 def test_table_and_override(tmp_path):
     table = tmp_path / "tune.txt"
     table.write_text("# test table\n4 0   # register\n5 1\n6 0 # comment\n")
-    assert schedule_with({"QE_TUNE_TABLE": str(table)})[3:] == [0, 1, 0]
-    assert schedule_with({"QE_TUNE_TABLE": str(table), "QE_SCHEDULE": "6:1,4:1"})[3:] == [1, 1, 1]
+    assert schedule_with({"QE_TUNE_TABLE": str(table)})[0][3:] == [0, 1, 0]
+    assert schedule_with({"QE_TUNE_TABLE": str(table), "QE_SCHEDULE": "6:1,4:1"})[0][3:] == [1, 1, 1]
+
+
+def test_full_table_lines(tmp_path):
+    table = tmp_path / "tune.txt"
+    table.write_text("5 0 1 2 1   # short circuits: two wavefronts\n"
+                     "5 1 1 1 1\n"
+                     "4 1 1 1 1\n"
+                     "6 0 1 2 1   # impossible (n = 6 takes four wavefronts): ignored\n"
+                     "5 1 1 3 4   # impossible: ignored\n")
+    short, full = schedule_with({"QE_TUNE_TABLE": str(table)})
+    assert full[(5, 0)] == (1, 2, 1) and full[(5, 1)] == (1, 1, 1)
+    assert full[(4, 1)] == (1, 1, 1) and full[(4, 0)] == (1, 1, 4)
+    assert full[(6, 0)] == (1, 4, 1)
+    _, full = schedule_with({"QE_TUNE_TABLE": str(table), "QE_SCHEDULE": "5:1:2,4:1:1:4"})
+    assert full[(5, 0)] == (1, 2, 1) and full[(5, 1)] == (1, 2, 1)
+    assert full[(4, 0)] == (1, 1, 4) and full[(4, 1)] == (1, 1, 4)
 
 
 def test_missing_table_keeps_defaults(tmp_path):
-    got = schedule_with({"QE_TUNE_TABLE": str(tmp_path / "absent.txt")})
+    got, full = schedule_with({"QE_TUNE_TABLE": str(tmp_path / "absent.txt")})
     assert got[:3] == [0, 0, 0] and all(x in (0, 1) for x in got)
+    assert full[(5, 1)][1] in (1, 2) and full[(6, 1)][1] == 4
+
+
+def test_set_schedule_ex_validates():
+    import pytest
+    from paper_1809_11134_amd import qe
+    with pytest.raises(qe.QeError):
+        qe.set_schedule_ex(6, 1, 1, 2, 1)
+    with pytest.raises(qe.QeError):
+        qe.set_schedule_ex(5, 2, 1, 1, 4)
+    with pytest.raises(qe.QeError):
+        qe.set_schedule_ex(4, 0, 1, 1, 3)
