@@ -101,12 +101,15 @@ __global__ __launch_bounds__(64 * W) void lds32_kernel(BatchArgs a, float* __res
         if (threadIdx.x == 0 && it.err) atomicOr(a.err, it.err);
         return;
     }
-    // fitness: one wavefront over the whole matrix, in the width's fixed order
-    if constexpr (W > 1) __syncthreads();
-    if (wave != 0) return;
+    // fitness, in the width's fixed order
+    constexpr int WR = reduction_waves<NQ>();
+    static_assert(WR == 1 || WR == W, "the reduction's wavefronts are the circuit's");
+    __shared__ float red[4][3];
+    if constexpr (W > 1) __syncthreads();      // every wavefront's columns are in place
+    if (WR == 1 && wave != 0) return;
     float gv, dlt;
-    const float fv = canonical_fitness<NQ>(M, map, a.mode, &gv, &dlt);
-    if (lane == 0) {
+    const float fv = canonical_fitness<NQ, WR>(M, map, a.mode, &gv, &dlt, WR == 1 ? 0 : wave, red);
+    if (wave == 0 && lane == 0) {
         const float nan = __builtin_nanf("");
         if (ok && !(fv == fv)) it.err = QE_DEVERR_NUMERIC;
         f[b] = ok ? fv : nan;
@@ -137,9 +140,13 @@ __device__ __forceinline__ int mix_key(const BatchArgs& a, int b) {
     const int lc = len >= 120 ? 0 : (len < 8 ? MIX_LCLASSES - 1 : MIX_LCLASSES - 1 - (int)(len >> 3));
     return mix_bucket(a.nq[b]) * MIX_LCLASSES + lc;
 }
-// circuits per work item: one of width 6 (four wavefronts), four (or with two
-// wavefronts per circuit two) of width 5, four of the other widths
-__device__ __forceinline__ int mix_per_item(int k, int w5) { return k == 0 ? 1 : (k == 1 && w5 == 2 ? 2 : 4); }
+// circuits per work item: one of width 6 (four wavefronts), three of width
+// 5 with one wavefront each (their 8 KB matrices and gate tables fill the
+// 32 KB of LDS; the fourth wavefront idles) or two with two wavefronts each,
+// four of the other widths
+__device__ __forceinline__ int mix_per_item(int k, int w5) {
+    return k == 0 ? 1 : (k == 1 ? (w5 == 2 ? 2 : 3) : 4);
+}
 
 // meta: [0..7) first order position, [8..15) first item (8 entries, the last
 // the total), [16..23) count per bucket.
@@ -187,7 +194,7 @@ __global__ __launch_bounds__(1024) void mix_bucket_kernel(BatchArgs a, int32_t* 
 
 template <int NQ, int W>
 __device__ __forceinline__ void mix_lds_item(const BatchArgs& a, int b, float2* M, uint4* gt,
-                                             float* f, float* g, float* delta) {
+                                             float (*red)[3], float* f, float* g, float* delta) {
     const int lane = (int)lane_id(), wave = (int)(threadIdx.x >> 6);
     Item it;
     it.err = 1;
@@ -205,11 +212,13 @@ __device__ __forceinline__ void mix_lds_item(const BatchArgs& a, int b, float2* 
         ok = run_lds_path<NQ, W, false>(M, gt, T, L, src, &map, wave % W);
         if (!ok) it.err = QE_DEVERR_DESC;
     }
+    constexpr int WR = reduction_waves<NQ>();
+    static_assert(WR == 1 || WR == W, "the reduction's wavefronts are the circuit's");
     if constexpr (W > 1) __syncthreads();     // every wavefront's columns are in place
-    if (wave % W != 0) return;
+    if (WR == 1 && wave % W != 0) return;
     float gv, dv;
-    const float fv = canonical_fitness<NQ>(M, map, a.mode, &gv, &dv);
-    if (b >= 0 && lane == 0) {
+    const float fv = canonical_fitness<NQ, WR>(M, map, a.mode, &gv, &dv, WR == 1 ? 0 : wave % W, red);
+    if (b >= 0 && wave % W == 0 && lane == 0) {
         const float nan = __builtin_nanf("");
         if (ok && !(fv == fv)) it.err = QE_DEVERR_NUMERIC;
         f[b] = ok ? fv : nan;
@@ -254,7 +263,7 @@ __global__ __launch_bounds__(256) void mix_kernel(BatchArgs a, const int32_t* __
                                                   float* __restrict__ f, float* __restrict__ g,
                                                   float* __restrict__ delta) {
     __shared__ float2 M[4096];
-    __shared__ uint4 GT[4][GATE_TABLE];
+    __shared__ float red[4][3];
     const int item = blockIdx.x;
     if (item >= meta[8 + MIX_BUCKETS]) return;
     int k = 0;
@@ -263,16 +272,21 @@ __global__ __launch_bounds__(256) void mix_kernel(BatchArgs a, const int32_t* __
     const int per = mix_per_item(k, a.mix_w5);
     const int local = (item - meta[8 + k]) * per;
     const int sub = per == 1 ? 0 : (per == 2 ? wave >> 1 : wave);
-    int b = local + sub < meta[16 + k] ? order[meta[k] + local + sub] : -1;
+    int b = sub < per && local + sub < meta[16 + k] ? order[meta[k] + local + sub] : -1;
     if (b >= a.B) b = -1;        // an order written for another batch never indexes past this one
     switch (k) {
         // (widths 4 and 5 run one circuit per wavefront, each with its gate table)
-        case 0: mix_lds_item<6, 4>(a, b, M, nullptr, f, g, delta); break;
+        case 0: mix_lds_item<6, 4>(a, b, M, nullptr, red, f, g, delta); break;
         case 1:
-            if (a.mix_w5 == 2) mix_lds_item<5, 2>(a, b, M + sub * 1024, nullptr, f, g, delta);
-            else mix_lds_item<5, 1>(a, b, M + sub * 1024, GT[wave], f, g, delta);
+            if (a.mix_w5 == 2) mix_lds_item<5, 2>(a, b, M + sub * 1024, nullptr, red, f, g, delta);
+            else if (wave < 3)   // gate tables in the last quarter of M
+                mix_lds_item<5, 1>(a, b, M + sub * 1024, reinterpret_cast<uint4*>(M + 3072) + wave * GATE_TABLE,
+                                   red, f, g, delta);
             break;
-        case 2: mix_lds_item<4, 1>(a, b, M + sub * 256, GT[wave], f, g, delta); break;
+        case 2:   // gate tables after the four 16 x 16 matrices
+            mix_lds_item<4, 1>(a, b, M + sub * 256, reinterpret_cast<uint4*>(M + 1024) + wave * GATE_TABLE, red,
+                               f, g, delta);
+            break;
         case 3: mix_wave_item<3>(a, b, f, g, delta); break;
         case 4: mix_wave_item<2>(a, b, f, g, delta); break;
         case 5: mix_wave_item<1>(a, b, f, g, delta); break;

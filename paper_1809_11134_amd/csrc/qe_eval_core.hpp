@@ -1207,17 +1207,24 @@ __device__ __forceinline__ void lds_generic_body(int n, int L, const uint16_t* g
 }
 
 // Eq. 11 (or the phase-insensitive form) of one circuit from its product in
-// LDS, by one wavefront, in an order fixed by the width alone: lane l takes
-// column j = l mod N and the logical rows r = q, q + 64/N, ... (q = l div N)
-// in increasing order (row r is stored at A r ^ b), then the wavefront's
-// reduction tree adds the lanes.  Every LDS-staged schedule -- wavefronts
-// per circuit, circuits per workgroup, packing of mixed batches -- therefore
-// gives the same bits.  Returns f on every lane; g, delta out.
-template <int NQ>
+// LDS, in an order fixed by the width alone.  WR wavefronts share the work
+// (WR = 1 for widths up to 5, whose kernels may run one or two wavefronts per
+// circuit; WR = 4 for width 6, whose kernels all run four): lane l of
+// wavefront w takes column j = w (N / WR) + l mod (N / WR) and the logical
+// rows r = q, q + Q, q + 2Q, ... (q = l div (N / WR), Q = 64 WR / N) in
+// increasing order (row r is stored at A r ^ b); the wavefront's reduction
+// tree adds its lanes and the WR wavefront sums are added in order.  Every
+// LDS-staged schedule of a width therefore gives the same bits.  WR > 1:
+// every wavefront of the circuit calls it (it holds workgroup barriers) with
+// `w` its index and red 4 x 3 floats of LDS.  Returns f on every lane; g,
+// delta out.
+template <int NQ, int WR>
 __device__ __forceinline__ float canonical_fitness(const float2* M, const RowMap map, int mode,
-                                                   float* g_out, float* delta_out) {
-    constexpr int N = 1 << NQ, Q = 64 / N, ROWB = NQ + 3;
-    const int lane = (int)lane_id(), j = lane % N, q = lane / N;
+                                                   float* g_out, float* delta_out, int w = 0,
+                                                   float (*red)[3] = nullptr) {
+    constexpr int N = 1 << NQ, CWR = N / WR, Q = 64 / CWR, ROWB = NQ + 3;
+    static_assert(CWR <= 64 && 64 % CWR == 0 && Q <= N, "reduction layout");
+    const int lane = (int)lane_id(), j = w * CWR + lane % CWR, q = lane / CWR;
     const char* Mj = reinterpret_cast<const char*>(M) + (uint32_t)j * 8u;
     auto col = [&](int p) -> uint32_t { return (uint32_t)(map.A >> (6 * p)) & 63u; };
     // stored row of logical row q (lane part) and of Q m (uniform part)
@@ -1254,24 +1261,43 @@ __device__ __forceinline__ float canonical_fitness(const float2* M, const RowMap
             else off += v[i].x * v[i].x + v[i].y * v[i].y;
         }
     }
-    const float offs = wave_sum(off);
+    // sums over the circuit's WR wavefronts, added in order
+    auto total = [&](float x) -> float {
+        const float s = wave_sum(x);
+        if constexpr (WR == 1) {
+            return s;
+        } else {
+            __syncthreads();
+            if (lane == 0) red[w][0] = s;
+            __syncthreads();
+            float t = 0.0f;
+#pragma unroll
+            for (int k = 0; k < WR; ++k) t += red[k][0];
+            return t;
+        }
+    };
+    const float offs = total(off);
     if (mode == QE_FIT_PHASE_INSENSITIVE) {
         float fv;
         fitness_pi(offs, N, &fv, g_out, delta_out);
         return fv;
     }
-    const float tr = wave_sum(d.x), ti = wave_sum(d.y);
+    const float tr = total(d.x), ti = total(d.y);
     const float am = sqrtf(tr * tr + ti * ti);
     float er = 1.0f, ei = 0.0f;
     if (am > 0.0f) { er = tr / am; ei = ti / am; }
     float dl = 0.0f;
     if (j % Q == q) { const float xr = d.x - er, xi = d.y - ei; dl = xr * xr + xi * xi; }
-    const float dlt = 0.5f * (offs + wave_sum(dl));
+    const float dlt = 0.5f * (offs + total(dl));
     const float qq = fminf(fmaxf(dlt / (float)N, 0.0f), 1.0f);
     *g_out = am / (float)N;
     *delta_out = dlt;
     return 1.0f - sqrtf(qq);
 }
+
+// wavefronts of the canonical reduction per width
+template <int NQ>
+constexpr int reduction_waves() { return NQ == 6 ? 4 : 1; }
 
 template <bool IDENT, typename GateSrc>
 __device__ __forceinline__ bool run_any_width(int n, const float* __restrict__ T, int L,

@@ -258,7 +258,8 @@ __device__ __forceinline__ void eval_circuit(const LoopArgs& a, uint32_t gen, ui
                                              const uint16_t* gates_in, const uint32_t* angles_in,
                                              uint32_t* slots_out, uint16_t* gates_out,
                                              uint32_t* angles_out, float* f_out, bool writer,
-                                             bool decide, float2* M, uint4* gt, void* xch = nullptr) {
+                                             bool decide, float2* M, uint4* gt, float (*red)[3],
+                                             void* xch = nullptr) {
     const uint32_t i = ci / (uint32_t)a.P, k = ci % (uint32_t)a.P;
     const int lane = (int)lane_id();
     const int L = a.L;
@@ -339,8 +340,13 @@ __device__ __forceinline__ void eval_circuit(const LoopArgs& a, uint32_t gen, ui
         // circuits the sampler decodes hold only {I, NOT, CNOT, CV, CV+}
         constexpr bool NCV = SAMPLE && !ISING;
         ok = run_lds_path<NQ, W, false, NCV>(M, gt, T, L, src, &map, W == 1 ? 0 : -1);
+        constexpr int WR = reduction_waves<NQ>();
+        static_assert(WR == 1 || WR == W, "the reduction's wavefronts are the circuit's");
         if constexpr (W > 1) __syncthreads();     // every wavefront's columns are in place
-        fv = writer ? canonical_fitness<NQ>(M, map, a.fit_mode, &gd, &dd) : 0.0f;
+        if (WR > 1)
+            fv = canonical_fitness<NQ, WR>(M, map, a.fit_mode, &gd, &dd, (int)(threadIdx.x >> 6) % W, red);
+        else
+            fv = writer ? canonical_fitness<NQ, 1>(M, map, a.fit_mode, &gd, &dd) : 0.0f;
     }
     if (!ok) fv = __builtin_nanf("");
     if (writer && lane == 0) {
@@ -381,7 +387,7 @@ __global__ __launch_bounds__(256) void population_kernel(LoopArgs a, uint64_t ge
         const uint32_t ci = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
         if (ci >= total) return;
         eval_circuit<NQ, 0, SAMPLE, ISING>(a, gen, ci, gates_in, angles_in, slots_out, gates_out,
-                                           angles_out, f_out, true, decide, nullptr, nullptr);
+                                           angles_out, f_out, true, decide, nullptr, nullptr, nullptr);
     } else {
         // W = 1: CPB circuits per workgroup, one per wavefront (no barrier
         // is shared, so a wavefront past the end may leave); W > 1: one
@@ -390,6 +396,7 @@ __global__ __launch_bounds__(256) void population_kernel(LoopArgs a, uint64_t ge
         constexpr int N = 1 << NQ;
         __shared__ float2 M[CPB][N * N];
         __shared__ uint4 GT[W == 1 ? CPB : W][ISING ? GATE_TABLE_ANGLED : GATE_TABLE];
+        __shared__ float red[4][3];
         const int wave = (int)(threadIdx.x >> 6);
         const uint32_t ci = W == 1 ? blockIdx.x * CPB + (uint32_t)wave : blockIdx.x;
         if (ci >= total) return;
@@ -397,7 +404,7 @@ __global__ __launch_bounds__(256) void population_kernel(LoopArgs a, uint64_t ge
         // descriptor exchange)
         eval_circuit<NQ, W, SAMPLE, ISING>(a, gen, ci, gates_in, angles_in, slots_out, gates_out,
                                            angles_out, f_out, W == 1 || threadIdx.x < 64, decide,
-                                           M[W == 1 ? wave : 0], GT[wave],
+                                           M[W == 1 ? wave : 0], GT[wave], red,
                                            W == 1 ? nullptr : static_cast<void*>(GT[0]));
     }
 }
