@@ -435,10 +435,10 @@ def time_generation_kernels(ctx, gen0, R, dev):
     """The two kernels of a generation as the graph launches them, timed
     with HIP events on the launch stream: R fused sampling + fitness kernels
     (qe_sample_eval without slot output) back to back between two events give
-    its mean duration; then R generations of the fused kernel followed by
-    the update kernel (qe_update right after it) between two events, less
-    R fused durations, give the update kernel's.  Returns (fused us, update
-    us, the last generation's gates, next generation index)."""
+    its mean duration; then R generations of the fused kernel and the update
+    kernel (qe_update right after it), each update between its own two
+    events, give the update kernel's.  Returns (fused us, update us, the
+    last generation's gates, next generation index)."""
     import torch
     IP = ctx.I * ctx.P
     gates = torch.empty((IP, ctx.L), dtype=torch.int16, device=dev)
@@ -457,17 +457,19 @@ def time_generation_kernels(ctx, gen0, R, dev):
     torch.cuda.synchronize()
     fused = e0.elapsed_time(e1) / R * 1e3
     # the update of the last of those generations, then R whole generations
+    # with each update launch bracketed by its own pair of events
     ctx.update(gen + R - 1, None, gates, f)
     gen += R
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(R)]
     torch.cuda.synchronize()
-    e0.record()
     for r in range(R):
         ctx.sample_eval(gen + r, None, gates, f, keep_slots=False)
+        ev[r][0].record()
         ctx.update(gen + r, None, gates, f)
-    e1.record()
+        ev[r][1].record()
     torch.cuda.synchronize()
-    pair = e0.elapsed_time(e1) / R * 1e3
-    return fused, pair - fused, gates, gen + R
+    upd = sum(a.elapsed_time(b) for a, b in ev) / R * 1e3
+    return fused, upd, gates, gen + R
 
 
 def update_algorithmic_bytes(ctx, gen, dev):
