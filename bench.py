@@ -678,11 +678,14 @@ def main():
     lds_bytes = algorithmic_lds_bytes(gh, n)
     achieved = lds_bytes / (fused_us * 1e-6) / 1e9
     alu = flops / (fused_us * 1e-6) / 1e12
+    _, waves, cpb = qe.get_schedule_ex(n, 1 if L >= 32 else 0)
+    cpb = cpb if waves == 1 else 1
     roofline = {"bound": "lds", "achieved": round(achieved, 2), "peak": round(LDS_PEAK_GBPS, 1),
                 "unit": "GB/s", "frac": round(achieved / LDS_PEAK_GBPS, 6),
                 "traffic": traffic_from_profiles("qeqea_fused_n5", src),
-                "kernel": "population_kernel<5,2,true,false> (sampling + Eq. 11 fitness + segment "
-                          "max + mutation decisions, LDS-staged, two wavefronts per circuit)",
+                "kernel": f"population_kernel<5,{waves},true,false,{cpb}> (sampling + Eq. 11 fitness + "
+                          f"segment max + mutation decisions, LDS-staged, {waves} wavefront(s) per circuit, "
+                          f"{cpb} circuit(s) per workgroup)",
                 "kernel_us": round(fused_us, 3), "algorithmic_lds_bytes_per_launch": lds_bytes,
                 "peak_source": "LDS probe kernel in this run, copy mode (each 16-byte word read and "
                                "written once, the mix of the per-gate updates)",
@@ -702,6 +705,10 @@ def main():
                        "kernel": "qeqea_update_kernel (segment fitness, elitism, mutation, best circuit)",
                        "kernel_us": round(upd_us, 3), "algorithmic_hbm_bytes_per_launch": upd_bytes,
                        "units": upd_counts}
+    for r, us in ((roofline, fused_us), (roofline_update, upd_us)):
+        if r["traffic"] is not None:    # the counted HBM bytes at the measured duration
+            r["traffic_gbps"] = round(r["traffic"] / (us * 1e-6) / 1e9, 2)
+            r["traffic_frac_of_hbm_peak"] = round(r["traffic_gbps"] / HBM_PEAK_GBPS, 6)
     log(f"update kernel: {upd_us:.2f} us/launch, {upd_ach:.1f} GB/s algorithmic HBM "
         f"({upd_ach / HBM_PEAK_GBPS:.3f} of peak)")
     ctx.close()
