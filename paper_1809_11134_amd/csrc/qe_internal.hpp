@@ -83,6 +83,17 @@ struct SlotRec {
 };
 static_assert(sizeof(SlotRec) == 16, "slot records are 16 bytes");
 
+// Workgroups are dispatched round-robin over the eight XCDs, each with its
+// own L2: block j of a range of n blocks that starts at a multiple of 8 is
+// the (j / 8)-th block to reach XCD j % 8.  The returned index gives every
+// XCD one contiguous share of the range, taken in order, so that the
+// circuits of one population (whose slot records share lines) run under
+// one L2.
+__device__ __forceinline__ uint32_t xcd_swizzle(uint32_t j, uint32_t n) {
+    const uint32_t q = n >> 3, r = n & 7u, x = j & 7u;
+    return x * q + (x < r ? x : r) + (j >> 3);
+}
+
 __device__ __forceinline__ uint32_t seg_key(float f) { return __float_as_uint(f) + 1u; }
 __device__ __forceinline__ float seg_fitness(uint32_t key) { return __uint_as_float(key - 1u); }
 

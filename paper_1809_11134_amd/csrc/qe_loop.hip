@@ -382,9 +382,10 @@ __global__ __launch_bounds__(256) void population_kernel(LoopArgs a, uint64_t ge
                                                          float* __restrict__ f_out, bool decide) {
     const uint32_t gen = gen_of(a, gen64);
     const uint32_t total = (uint32_t)a.I * (uint32_t)a.P;
+    const uint32_t bid = xcd_swizzle(blockIdx.x, gridDim.x);
     if constexpr (W == 0) {
         static_assert(!ISING || NQ <= 3, "Ising circuits of 4 or more wires take the LDS-staged path");
-        const uint32_t ci = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+        const uint32_t ci = __builtin_amdgcn_readfirstlane(bid * 4 + (threadIdx.x >> 6));
         if (ci >= total) return;
         eval_circuit<NQ, 0, SAMPLE, ISING>(a, gen, ci, gates_in, angles_in, slots_out, gates_out,
                                            angles_out, f_out, true, decide, nullptr, nullptr, nullptr);
@@ -398,7 +399,7 @@ __global__ __launch_bounds__(256) void population_kernel(LoopArgs a, uint64_t ge
         __shared__ uint4 GT[W == 1 ? CPB : W][ISING ? GATE_TABLE_ANGLED : GATE_TABLE];
         __shared__ float red[4][3];
         const int wave = (int)(threadIdx.x >> 6);
-        const uint32_t ci = W == 1 ? blockIdx.x * CPB + (uint32_t)wave : blockIdx.x;
+        const uint32_t ci = W == 1 ? bid * CPB + (uint32_t)wave : bid;
         if (ci >= total) return;
         // (W > 1: the gate tables are unused, the first one is the
         // descriptor exchange)
@@ -707,13 +708,19 @@ __global__ __launch_bounds__(UPD_BLOCK) void qeqea_update_kernel(LoopArgs a, uin
                                                                  uint32_t nC, uint32_t nB,
                                                                  uint32_t per_inst) {
     const uint32_t gen = gen_of(a, gen64);
-    if (blockIdx.x < nC)
+    const uint32_t a0 = (nC + nB + 7u) & ~7u;   // part A starts at a multiple of 8
+    if (blockIdx.x < nC) {
         update_part_c(a, blockIdx.x, gates, angles, f);
-    else if (blockIdx.x < nC + nB)
+    } else if (blockIdx.x < nC + nB) {
         update_part_b(a, gen, blockIdx.x - nC, per_inst);
-    else   // part A from the last entries back: the records the fused kernel
-           // touched last are the likeliest to be in the memory-side cache
-        update_part_a(a, gen, (gridDim.x - 1u - blockIdx.x) * UPD_BLOCK + threadIdx.x, slots, f);
+    } else if (blockIdx.x >= a0) {
+        // part A: each XCD takes the circuits the fused kernel ran on it,
+        // from the last back (the records touched last are the likeliest to
+        // still be cached)
+        const uint32_t nA = gridDim.x - a0;
+        const uint32_t blk = nA - 1u - xcd_swizzle(blockIdx.x - a0, nA);
+        update_part_a(a, gen, blk * UPD_BLOCK + threadIdx.x, slots, f);
+    }
 }
 
 // Dense copy of one field of the encoding state.
@@ -947,6 +954,168 @@ __global__ __launch_bounds__(256) void elite_eval_kernel(LoopArgs a, const uint1
                                     Mr, Mr + ((size_t)1 << (2 * a.n)));
 }
 
+// FP64 re-check of elite circuits of width NQ (4 or 5) over a discrete
+// library: one wavefront per circuit, CPB circuits per workgroup, the
+// product U T^dagger (Eq. 11) as complex128 in LDS.  Lane l owns column
+// j = l mod N and row group h = l div N; a gate's row pairs are its pair
+// indices (the target bit taken out) or, for a controlled gate, its quad
+// indices (target and control bits taken out), the row group supplying the
+// low bits.  NOT and CNOT move no data: as in the FP32 LDS path, logical
+// row r is stored at row A r ^ b (A's column p in bits 6p..6p+5), and they
+// only update A and b.  CV and CV+ take the halves of a + b and i (a - b);
+// H and T are applied as their matrices say.  The results agree with the
+// generic FP64 body to rounding.
+template <int NQ, bool CTL>
+__device__ __forceinline__ void elite64_pairs(double2* M, int kind, int tp, int cp, int j, int h,
+                                              uint64_t A, uint32_t b) {
+    constexpr int N = 1 << NQ, RG = 64 / N, RGB = NQ == 5 ? 1 : 2;
+    static_assert(RG == (1 << RGB), "row groups");
+    constexpr int QB = NQ - 1 - (CTL ? 1 : 0);       // bits of the pair index
+    constexpr int NP = (1 << QB) / RG;               // pairs per lane
+    auto col = [&](int p) -> uint32_t { return (uint32_t)(A >> (6 * p)) & 63u; };
+    const int lo = CTL ? min(tp, cp) : tp, hi = CTL ? max(tp, cp) : NQ;
+    // stored image of pair-index bit k (its logical row bit after the insertions)
+    auto img = [&](int k) -> uint32_t {
+        int pos = k < lo ? k : k + 1;
+        pos = pos < hi ? pos : pos + 1;
+        return col(pos);
+    };
+    uint32_t base = b ^ (CTL ? col(cp) : 0u);
+#pragma unroll
+    for (int k = 0; k < RGB; ++k)
+        if ((h >> k) & 1) base ^= img(k);
+    const uint32_t tstep = col(tp);
+    double2 X[NP], Y[NP];
+    int o0[NP], o1[NP];
+#pragma unroll
+    for (int m = 0; m < NP; ++m) {
+        uint32_t sr = base;
+#pragma unroll
+        for (int k = 0; (1 << k) < NP; ++k)
+            if ((m >> k) & 1) sr ^= img(RGB + k);
+        o0[m] = (int)((sr << NQ) | (uint32_t)j);
+        o1[m] = (int)(((sr ^ tstep) << NQ) | (uint32_t)j);
+        X[m] = M[o0[m]];
+        Y[m] = M[o1[m]];
+    }
+    constexpr double S2 = 0.70710678118654752440084436210485;
+#pragma unroll
+    for (int m = 0; m < NP; ++m) {
+        const double2 a = X[m], bb = Y[m];
+        double2 x, y;
+        if (kind == KIND_CV || kind == KIND_CVDG) {
+            // V = [[1+i, 1-i], [1-i, 1+i]] / 2: a' = (s + i d) / 2, b' = (s - i d) / 2
+            // with s = a + b, d = a - b; V+ swaps the two
+            const double sr = 0.5 * (a.x + bb.x), si = 0.5 * (a.y + bb.y);
+            const double dr = 0.5 * (a.x - bb.x), di = 0.5 * (a.y - bb.y);
+            const double2 p = make_double2(sr - di, si + dr), q = make_double2(sr + di, si - dr);
+            x = kind == KIND_CV ? p : q;
+            y = kind == KIND_CV ? q : p;
+        } else if (kind == KIND_H) {
+            x = make_double2(S2 * (a.x + bb.x), S2 * (a.y + bb.y));
+            y = make_double2(S2 * (a.x - bb.x), S2 * (a.y - bb.y));
+        } else {   // T: b' = b (1 + i) / sqrt 2
+            x = a;
+            y = make_double2(S2 * (bb.x - bb.y), S2 * (bb.x + bb.y));
+        }
+        M[o0[m]] = x;
+        M[o1[m]] = y;
+    }
+}
+
+template <int NQ, int CPB>
+__global__ __launch_bounds__(64 * CPB) void elite64_kernel(LoopArgs a, const uint16_t* __restrict__ gates,
+                                                           int k, const int32_t* __restrict__ idx,
+                                                           double* __restrict__ f64) {
+    constexpr int N = 1 << NQ, RG = 64 / N, RGB = NQ == 5 ? 1 : 2;
+    __shared__ double2 Ms[CPB][N * N];
+    const int wave = (int)(threadIdx.x >> 6), lane = (int)lane_id();
+    const uint32_t ci = __builtin_amdgcn_readfirstlane(blockIdx.x * CPB + (uint32_t)wave);
+    if (ci >= (uint32_t)a.I * (uint32_t)k) return;
+    const uint32_t i = ci / (uint32_t)k;
+    const int c = idx[ci];
+    uint32_t err = (c < 0 || c >= a.P) ? (uint32_t)QE_DEVERR_RANGE : 0u;
+    const int L = a.L;
+    const uint16_t* g = gates + ((size_t)i * a.P + (size_t)(err ? 0 : c)) * L;
+    const double2* T = reinterpret_cast<const double2*>(a.target64) + ((size_t)i << (2 * NQ));
+    double2* M = Ms[wave];
+    const int j = lane & (N - 1), h = lane >> NQ;
+    uint64_t A = 0;                                   // the row map, identity
+#pragma unroll
+    for (int p = 0; p < NQ; ++p) A |= (uint64_t)(1u << p) << (6 * p);
+    uint32_t b = 0;
+    bool ok = err == 0;
+    if (ok) {
+        // M = T^dagger
+        for (int e = lane; e < N * N; e += 64) {
+            const double2 t = T[e];
+            M[(e & (N - 1)) * N + (e >> NQ)] = make_double2(t.x, -t.y);
+        }
+        wave_lds_fence();
+        for (int l0 = 0; l0 < L && ok; l0 += 64) {
+            const uint32_t mine = l0 + lane < L ? (uint32_t)g[l0 + lane] : 0u;
+            const int cnt = min(64, L - l0);
+            for (int u = 0; u < cnt; ++u) {
+                const uint32_t d = __builtin_amdgcn_readlane(mine, u);
+                if (!desc_valid(d, NQ)) { ok = false; break; }
+                const int kind = (int)(d & 15u);
+                if (kind == KIND_I) continue;
+                const int tp = NQ - 1 - (int)((d >> 4) & 15u), cp = NQ - 1 - (int)((d >> 8) & 15u);
+                const uint32_t ct = (uint32_t)(A >> (6 * tp)) & 63u;
+                if (kind == KIND_NOT) { b ^= ct; continue; }
+                if (kind == KIND_CNOT) { A ^= (uint64_t)ct << (6 * cp); continue; }
+                if (kind == KIND_CV || kind == KIND_CVDG)
+                    elite64_pairs<NQ, true>(M, kind, tp, cp, j, h, A, b);
+                else
+                    elite64_pairs<NQ, false>(M, kind, tp, 0, j, h, A, b);
+                wave_lds_fence();
+            }
+        }
+        if (!ok) err = QE_DEVERR_DESC;
+    }
+    // Eq. 11 (or the phase-insensitive form): lane (j, h) reads the logical
+    // rows h, h + RG, ... at their stored rows
+    double off = 0.0, dr = 0.0, di = 0.0;
+    bool hasd = false;
+    if (ok) {
+        uint32_t sh = b;
+#pragma unroll
+        for (int p = 0; p < RGB; ++p)
+            if ((h >> p) & 1) sh ^= (uint32_t)(A >> (6 * p)) & 63u;
+#pragma unroll
+        for (int m = 0; m < N / RG; ++m) {
+            uint32_t sr = sh;
+#pragma unroll
+            for (int p = 0; p < NQ - RGB; ++p)
+                if ((m >> p) & 1) sr ^= (uint32_t)(A >> (6 * (RGB + p))) & 63u;
+            const double2 v = M[(sr << NQ) | (uint32_t)j];
+            if (h + m * RG == j) { dr = v.x; di = v.y; hasd = true; }
+            else off += v.x * v.x + v.y * v.y;
+        }
+    }
+    off = wave_sum(off);
+    double fv, gv, dl;
+    if (a.fit_mode == QE_FIT_PHASE_INSENSITIVE) {
+        fitness_pi(off, N, &fv, &gv, &dl);
+    } else {
+        const double tr = wave_sum(dr), ti = wave_sum(di);
+        const double am = sqrt(tr * tr + ti * ti);
+        double er = 1.0, ei = 0.0;
+        if (am > 0.0) { er = tr / am; ei = ti / am; }
+        double D = 0.0;
+        if (hasd) { const double xr = dr - er, xi = di - ei; D = xr * xr + xi * xi; }
+        dl = 0.5 * (off + wave_sum(D));
+        double q = dl / (double)N;
+        q = q < 0.0 ? 0.0 : (q > 1.0 ? 1.0 : q);
+        fv = 1.0 - sqrt(q);
+    }
+    if (lane == 0) {
+        if (ok && !(fv == fv)) err = QE_DEVERR_NUMERIC;
+        f64[ci] = ok ? fv : (double)__builtin_nan("");
+        if (err) atomicOr(a.err, err);
+    }
+}
+
 // Complex128 -> complex64 copy of the targets for the FP32 path.
 __global__ void c128_to_c64_kernel(const double* __restrict__ src, float* __restrict__ dst, int64_t n) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1110,7 +1279,8 @@ hipError_t launch_qeqea_update(const LoopArgs& a, uint64_t gen, const uint32_t* 
         1.0, std::min<double>(std::ceil(expect + slack), (double)a.P * chunks));
     const uint32_t nB = per_inst * (uint32_t)a.I;
     const size_t lds = ((size_t)a.P * sizeof(uint16_t) + 15) & ~(size_t)15;
-    qeqea_update_kernel<<<nC + nB + nA, UPD_BLOCK, lds, s>>>(a, gen, slots, gates, angles, f, nC, nB,
+    const uint32_t a0 = (nC + nB + 7u) & ~7u;
+    qeqea_update_kernel<<<a0 + nA, UPD_BLOCK, lds, s>>>(a, gen, slots, gates, angles, f, nC, nB,
                                                              per_inst);
     return hipGetLastError();
 }
@@ -1156,7 +1326,15 @@ hipError_t launch_elite_select(const LoopArgs& a, const float* f, int k, int32_t
 
 hipError_t launch_elite_eval(const LoopArgs& a, const uint16_t* gates, const uint32_t* angles, int k,
                              const int32_t* idx, double* f64, hipStream_t s) {
-    elite_eval_kernel<<<a.I * k, 256, generic_lds_bytes(a.n, sizeof(double)), s>>>(a, gates, angles, k, idx, f64);
+    // uniform widths 4 and 5 over a discrete library: one wavefront per circuit
+    const unsigned nc = (unsigned)a.I * (unsigned)k;
+    if (!a.inst_n && !angles && a.n == 5) {
+        elite64_kernel<5, 2><<<(nc + 1) / 2, 128, 0, s>>>(a, gates, k, idx, f64);
+    } else if (!a.inst_n && !angles && a.n == 4) {
+        elite64_kernel<4, 4><<<(nc + 3) / 4, 256, 0, s>>>(a, gates, k, idx, f64);
+    } else {
+        elite_eval_kernel<<<nc, 256, generic_lds_bytes(a.n, sizeof(double)), s>>>(a, gates, angles, k, idx, f64);
+    }
     return hipGetLastError();
 }
 
