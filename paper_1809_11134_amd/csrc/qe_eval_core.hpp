@@ -586,36 +586,46 @@ struct RowMap {
 template <int NQ, int W, bool IDENT, bool NCV = false, typename GateSrc>
 __device__ __forceinline__ bool run_lds_path(float2* M, uint4* gt, const float* __restrict__ T, int L,
                                              GateSrc&& src, RowMap* map_out, int wave = -1) {
-    constexpr int N = 1 << NQ, CW = N / W, RG = 64 / CW;
+    // CV body of one wavefront per circuit (a gate table of per-row-group
+    // offsets and signs); at n = 5 each of its lanes owns two adjacent
+    // columns, so that a row pair is two 16-byte accesses
+    constexpr bool CVB = NCV && W == 1;
+    constexpr int CPL = (CVB && NQ == 5) ? 2 : 1;          // columns per lane
+    constexpr int N = 1 << NQ, CW = N / W, LPR = CW / CPL, RG = 64 / LPR;
     constexpr bool ANG = src_angled<GateSrc>();
     constexpr int ES = ANG ? 3 : 2;        // uint4 per gate-table entry
     using SrcT = std::decay_t<decltype(src(0))>;
     // four row groups per wavefront (16 columns: n = 4, or n = 5, 6 split over
     // 2 or 4 wavefronts), or two (32 columns: n = 5 in one wavefront, whose
     // half-wavefronts then read whole 256-byte rows, free of bank conflicts)
-    static_assert(CW <= 64 && 64 % CW == 0 && N % RG == 0 && (RG == 4 || RG == 2),
+    static_assert(LPR <= 64 && 64 % LPR == 0 && N % RG == 0 && (RG == 4 || RG == 2),
                   "layout: two or four row groups per wavefront");
     static_assert((N / 2) / RG <= 8, "at most three pass bits");
     const int lane = (int)lane_id();
     if (wave < 0) wave = (int)(threadIdx.x >> 6);
-    const int jl = lane % CW, rg = lane / CW;
-    const int j = wave * CW + jl;
+    const int jl = lane % LPR, rg = lane / LPR;
+    const int j = wave * CW + jl * CPL;                     // the lane's (first) column
     // The target loads are issued first, then the first chunk of descriptors
     // is fetched (or sampled, which may take dependent loads of its own), so
     // that the latencies overlap; M_0 = T^dagger (or I): M[r][j] = conj(T[j][r]).
     const float2* T2 = reinterpret_cast<const float2*>(T);
-    float2 tv[N / RG];
+    float2 tv[CPL][N / RG];
 #pragma unroll
     for (int m = 0; m < N / RG; ++m) {
         const int r = m * RG + rg;
-        if (IDENT) tv[m] = make_float2(r == j ? 1.0f : 0.0f, 0.0f);
-        else tv[m] = T2[(size_t)j * N + r];
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            if (IDENT) tv[c][m] = make_float2(r == j + c ? 1.0f : 0.0f, 0.0f);
+            else tv[c][m] = T2[(size_t)(j + c) * N + r];
+        }
     }
     const SrcT dv0 = L > 0 ? src(0) : SrcT{};
 #pragma unroll
     for (int m = 0; m < N / RG; ++m) {
         const int r = m * RG + rg;
-        M[r * N + j] = IDENT ? tv[m] : make_float2(tv[m].x, -tv[m].y);
+#pragma unroll
+        for (int c = 0; c < CPL; ++c)
+            M[r * N + j + c] = IDENT ? tv[c][m] : make_float2(tv[c][m].x, -tv[c][m].y);
     }
     wave_lds_fence();
     bool ok = true;
@@ -642,9 +652,6 @@ __device__ __forceinline__ bool run_lds_path(float2* M, uint4* gt, const float* 
     // uncontrolled gate has (N / 2) / RG passes)
     constexpr bool NIT_USES_R2 = (N / 2) / RG > 1, NIT_USES_R3 = (N / 2) / RG > 2,
                    NIT_USES_R4 = (N / 2) / RG > 4;
-    // CV body of one wavefront per circuit (a gate table of per-row-group
-    // offsets and signs)
-    constexpr bool CVB = NCV && W == 1;
     // CV or CV+ of sampled NCV circuits on the lane's pairs (T0 ^ o, T0 ^ tb ^ o)
     // of column j, o over the offsets of pair-index bits 2 and 3 (o2, o3),
     // written back in place.  With a, b the two rows of a pair, p + iq = a + b
@@ -653,8 +660,10 @@ __device__ __forceinline__ bool run_lds_path(float2* M, uint4* gt, const float* 
     // fused multiply-add of the exact halves p / 2, q / 2 and the exact factor
     // +-1/2 (CV +, CV+ -): it rounds (p - v) / 2 once, which is 0.5 times p - v
     // rounded.  `next` runs once the addresses are known, before the data reads.
+    // With two columns per lane the same arithmetic runs on both.
     char* const Mj = reinterpret_cast<char*>(M) + jb;
     auto el = [&](uint32_t off) -> float2& { return *reinterpret_cast<float2*>(Mj + off); };
+    auto el4 = [&](uint32_t off) -> float4& { return *reinterpret_cast<float4*>(Mj + off); };
     auto cv_gate = [&](const uint32_t T0, const uint32_t tb, const float hs, const uint32_t o2,
                        const uint32_t o3, auto&& next) {
         constexpr int NITC = (N / 4) / RG;
@@ -664,15 +673,31 @@ __device__ __forceinline__ bool run_lds_path(float2* M, uint4* gt, const float* 
         if constexpr (NITC > 1) offm[1] = o2;
         if constexpr (NITC > 2) { offm[2] = o3; offm[3] = o2 ^ o3; }
         next();
-        float2 A[NITC], B[NITC];
+        if constexpr (CPL == 2) {
+            float4 A[NITC], B[NITC];
 #pragma unroll
-        for (int m = 0; m < NITC; ++m) { A[m] = el(T0 ^ offm[m]); B[m] = el(T1 ^ offm[m]); }
+            for (int m = 0; m < NITC; ++m) { A[m] = el4(T0 ^ offm[m]); B[m] = el4(T1 ^ offm[m]); }
 #pragma unroll
-        for (int m = 0; m < NITC; ++m) {
-            const float2 a = A[m], b = B[m];
-            const float ph = 0.5f * (a.x + b.x), qh = 0.5f * (a.y + b.y), u = a.x - b.x, v = a.y - b.y;
-            el(T0 ^ offm[m]) = make_float2(__builtin_fmaf(hs, -v, ph), __builtin_fmaf(hs, u, qh));
-            el(T1 ^ offm[m]) = make_float2(__builtin_fmaf(hs, v, ph), __builtin_fmaf(hs, -u, qh));
+            for (int m = 0; m < NITC; ++m) {
+                const float4 a = A[m], b = B[m];
+                const float ph0 = 0.5f * (a.x + b.x), qh0 = 0.5f * (a.y + b.y), u0 = a.x - b.x, v0 = a.y - b.y;
+                const float ph1 = 0.5f * (a.z + b.z), qh1 = 0.5f * (a.w + b.w), u1 = a.z - b.z, v1 = a.w - b.w;
+                el4(T0 ^ offm[m]) = make_float4(__builtin_fmaf(hs, -v0, ph0), __builtin_fmaf(hs, u0, qh0),
+                                                __builtin_fmaf(hs, -v1, ph1), __builtin_fmaf(hs, u1, qh1));
+                el4(T1 ^ offm[m]) = make_float4(__builtin_fmaf(hs, v0, ph0), __builtin_fmaf(hs, -u0, qh0),
+                                                __builtin_fmaf(hs, v1, ph1), __builtin_fmaf(hs, -u1, qh1));
+            }
+        } else {
+            float2 A[NITC], B[NITC];
+#pragma unroll
+            for (int m = 0; m < NITC; ++m) { A[m] = el(T0 ^ offm[m]); B[m] = el(T1 ^ offm[m]); }
+#pragma unroll
+            for (int m = 0; m < NITC; ++m) {
+                const float2 a = A[m], b = B[m];
+                const float ph = 0.5f * (a.x + b.x), qh = 0.5f * (a.y + b.y), u = a.x - b.x, v = a.y - b.y;
+                el(T0 ^ offm[m]) = make_float2(__builtin_fmaf(hs, -v, ph), __builtin_fmaf(hs, u, qh));
+                el(T1 ^ offm[m]) = make_float2(__builtin_fmaf(hs, v, ph), __builtin_fmaf(hs, -u, qh));
+            }
         }
     };
     for (int ch = 0; ch < chunks; ++ch) {

@@ -395,7 +395,7 @@ __global__ __launch_bounds__(256) void population_kernel(LoopArgs a, uint64_t ge
         // circuit per workgroup of W wavefronts
         static_assert(W == 1 || CPB == 1, "one circuit per workgroup of several wavefronts");
         constexpr int N = 1 << NQ;
-        __shared__ float2 M[CPB][N * N];
+        __shared__ __align__(16) float2 M[CPB][N * N];
         __shared__ uint4 GT[W == 1 ? CPB : W][ISING ? GATE_TABLE_ANGLED : GATE_TABLE];
         __shared__ float red[4][3];
         const int wave = (int)(threadIdx.x >> 6);
