@@ -410,6 +410,26 @@ qe_status qe_get_schedule(int32_t n_qubits, int32_t* lds);
 qe_status qe_set_schedule_ex(int32_t n_qubits, int32_t lclass, int32_t lds, int32_t waves, int32_t cpb);
 qe_status qe_get_schedule_ex(int32_t n_qubits, int32_t lclass, int32_t* lds, int32_t* waves, int32_t* cpb);
 
+/* Library classes of the schedule table: the best kernel shape depends on
+ * what the gates are.  QE_SCHED_DISCRETE: circuits given in a discrete
+ * library (qe_eval_fitness, qe_eval_population, the GA); QE_SCHED_SAMPLED:
+ * circuits the QEQEA sampler decodes from the encoding of Sec. IV-D (only
+ * I, NOT, CNOT, CV, CV+: qe_sample_eval and the generation kernels);
+ * QE_SCHED_ISING: circuits of the Ising library (Sec. III), whose gates
+ * carry angles (batches with angles_dev, Ising contexts).  Angled circuits
+ * of 4 or more wires always take the LDS-staged kernels, whatever lds says. */
+enum { QE_SCHED_DISCRETE = 0, QE_SCHED_SAMPLED = 1, QE_SCHED_ISING = 2 };
+
+/* The schedule of one (width, length class, library class).
+ * qe_set_schedule_ex sets all three library classes at once and
+ * qe_get_schedule_ex reads the QE_SCHED_DISCRETE one; tuning table lines
+ * "n lclass lib lds waves cpb" set one class, the shorter forms all of them.
+ * Arguments and errors as for qe_set_schedule_ex, plus lib_class 0..2. */
+qe_status qe_set_schedule_lib(int32_t n_qubits, int32_t lclass, int32_t lib_class, int32_t lds,
+                              int32_t waves, int32_t cpb);
+qe_status qe_get_schedule_lib(int32_t n_qubits, int32_t lclass, int32_t lib_class, int32_t* lds,
+                              int32_t* waves, int32_t* cpb);
+
 /* Measurement helper (not part of the method): the LDS bandwidth the GPU
  * sustains, the denominator of the per-gate kernels' LDS rooflines.  Launches
  * `workgroups` workgroups of 256 threads, each owning 32 KB of LDS, whose

@@ -83,17 +83,26 @@ qe_status noalloc_scratch(int32_t** out) {
     return QE_OK;
 }
 
-// Schedule of the FP32 path per width and length class (0: L < 32, 1: L >=
-// 32): the LDS-staged kernel or the register-resident one, the LDS kernel's
-// wavefronts per circuit and (one wavefront per circuit) circuits per
-// workgroup of the population kernels.  Defaults from MI355X measurements;
-// the tuning table written by paper_1809_11134_amd/tune.py replaces them, and
-// QE_SCHEDULE="n:lds[:waves[:cpb]],..." overrides both length classes of a
-// width.
-Sched g_sched[MAX_QUBITS + 1][2] = {
-    {{0, 1, 4}, {0, 1, 4}}, {{0, 1, 4}, {0, 1, 4}}, {{0, 1, 4}, {0, 1, 4}}, {{0, 1, 4}, {0, 1, 4}},
-    {{1, 1, 4}, {1, 1, 4}}, {{1, 1, 4}, {1, 1, 4}}, {{1, 4, 1}, {1, 4, 1}}};
+// Schedule of the FP32 path per width, length class (0: L < 32, 1: L >= 32)
+// and library class (SCHED_*): the LDS-staged kernel or the register-resident
+// one, the LDS kernel's wavefronts per circuit and (one wavefront per
+// circuit) circuits per workgroup of the population kernels.  Defaults from
+// MI355X measurements; the tuning table written by
+// paper_1809_11134_amd/tune.py replaces them, and
+// QE_SCHEDULE="n:lds[:waves[:cpb]],..." overrides every class of a width.
+Sched g_sched[MAX_QUBITS + 1][2][SCHED_CLASSES];
 std::once_flag g_sched_once;
+
+void default_schedules() {
+    for (int n = 0; n <= MAX_QUBITS; ++n)
+        for (int l = 0; l < 2; ++l)
+            for (int c = 0; c < SCHED_CLASSES; ++c)
+                g_sched[n][l][c] = n <= 3 ? Sched{0, 1, 4} : (n == 6 ? Sched{1, 4, 1} : Sched{1, 1, 4});
+}
+
+void set_classes(int n, int l, const Sched& v) {
+    for (int c = 0; c < SCHED_CLASSES; ++c) g_sched[n][l][c] = v;
+}
 
 // wavefronts per circuit the LDS kernels are built for, per width
 bool waves_ok(int n, int w) {
@@ -107,8 +116,9 @@ bool sched_ok(int n, int lds, int w, int cpb) {
     return n >= 1 && n <= MAX_QUBITS && (lds == 0 || lds == 1) && waves_ok(n, w) && (cpb == 1 || cpb == 4);
 }
 
-// Tuning table lines: "n lclass lds waves cpb" (one length class), or the
-// older "n lds" (both classes, default waves and cpb); '#' starts a comment.
+// Tuning table lines: "n lclass lib lds waves cpb" (one length and library
+// class), "n lclass lds waves cpb" (one length class, every library class),
+// or "n lds" (every class, default waves and cpb); '#' starts a comment.
 // Path: $QE_TUNE_TABLE, else tune_mi355x.txt next to libqe.so.
 void load_tune_table() {
     std::string path;
@@ -128,18 +138,22 @@ void load_tune_table() {
     while (std::fgets(line, sizeof line, fh)) {
         if (line[0] == '#') continue;
         if (char* c = std::strchr(line, '#')) *c = 0;
-        int n = 0, x1 = 0, x2 = 0, x3 = 0, x4 = 0;
-        const int got = std::sscanf(line, "%d %d %d %d %d", &n, &x1, &x2, &x3, &x4);
-        if (got == 5 && (x1 == 0 || x1 == 1) && sched_ok(n, x2, x3, x4)) {
-            g_sched[n][x1] = Sched{x2, x3, x4};
+        int n = 0, x1 = 0, x2 = 0, x3 = 0, x4 = 0, x5 = 0;
+        const int got = std::sscanf(line, "%d %d %d %d %d %d", &n, &x1, &x2, &x3, &x4, &x5);
+        if (got == 6 && (x1 == 0 || x1 == 1) && x2 >= 0 && x2 < SCHED_CLASSES && sched_ok(n, x3, x4, x5)) {
+            g_sched[n][x1][x2] = Sched{x3, x4, x5};
+        } else if (got == 5 && (x1 == 0 || x1 == 1) && sched_ok(n, x2, x3, x4)) {
+            set_classes(n, x1, Sched{x2, x3, x4});
         } else if (got == 2 && n >= 1 && n <= MAX_QUBITS) {
-            g_sched[n][0].lds = g_sched[n][1].lds = x1 ? 1 : 0;
+            for (int l = 0; l < 2; ++l)
+                for (int c = 0; c < SCHED_CLASSES; ++c) g_sched[n][l][c].lds = x1 ? 1 : 0;
         }
     }
     std::fclose(fh);
 }
 
 void load_schedule_env() {
+    default_schedules();
     load_tune_table();
     const char* s = std::getenv("QE_SCHEDULE");
     if (!s) return;
@@ -151,13 +165,14 @@ void load_schedule_env() {
         int n = 0, l = 0, w = 0, c = 0;
         const int got = std::sscanf(item.c_str(), "%d:%d:%d:%d", &n, &l, &w, &c);
         if (got >= 2 && n >= 1 && n <= MAX_QUBITS) {
-            for (int k = 0; k < 2; ++k) {
-                Sched v = g_sched[n][k];
-                v.lds = l ? 1 : 0;
-                if (got >= 3) v.waves = w;
-                if (got >= 4) v.cpb = c;
-                if (sched_ok(n, v.lds, v.waves, v.cpb)) g_sched[n][k] = v;
-            }
+            for (int k = 0; k < 2; ++k)
+                for (int cl = 0; cl < SCHED_CLASSES; ++cl) {
+                    Sched v = g_sched[n][k][cl];
+                    v.lds = l ? 1 : 0;
+                    if (got >= 3) v.waves = w;
+                    if (got >= 4) v.cpb = c;
+                    if (sched_ok(n, v.lds, v.waves, v.cpb)) g_sched[n][k][cl] = v;
+                }
         }
         if (comma == std::string::npos) break;
         pos = comma + 1;
@@ -209,7 +224,7 @@ qe_status to_args(const qe_batch* b, BatchArgs* a, bool need_targets) {
     a->targets = b->targets_dev;
     a->num_telems = b->num_target_elems;
     a->mode = b->fitness_mode;
-    a->mix_w5 = schedule_for(5, 32).waves;
+    a->mix_w5 = schedule_for(5, 32, b->angles_dev ? SCHED_ISING : SCHED_DISCRETE).waves;
     a->angles = b->angles_dev;
     return device_error_word(&a->err);
 }
@@ -217,10 +232,11 @@ qe_status to_args(const qe_batch* b, BatchArgs* a, bool need_targets) {
 }  // namespace
 
 namespace qe {
-Sched schedule_for(int n, int L) {
+Sched schedule_for(int n, int L, int lib_class) {
     std::call_once(g_sched_once, load_schedule_env);
     if (n < 1 || n > MAX_QUBITS) return Sched{0, 1, 4};
-    return g_sched[n][L >= 32 ? 1 : 0];
+    if (lib_class < 0 || lib_class >= SCHED_CLASSES) lib_class = SCHED_DISCRETE;
+    return g_sched[n][L >= 32 ? 1 : 0][lib_class];
 }
 bool schedule_lds(int n) { return schedule_for(n, 32).lds != 0; }
 }  // namespace qe
@@ -377,14 +393,15 @@ qe_status qe_lib_table(int32_t library, int32_t n, uint16_t* table_host) {
 qe_status qe_set_schedule(int32_t n, int32_t lds) {
     std::call_once(g_sched_once, load_schedule_env);
     if (n < 1 || n > MAX_QUBITS) return fail(QE_ERR_INVALID, "width must be 1..6");
-    g_sched[n][0].lds = g_sched[n][1].lds = lds ? 1 : 0;
+    for (int l = 0; l < 2; ++l)
+        for (int c = 0; c < SCHED_CLASSES; ++c) g_sched[n][l][c].lds = lds ? 1 : 0;
     return QE_OK;
 }
 
 qe_status qe_get_schedule(int32_t n, int32_t* lds) {
     std::call_once(g_sched_once, load_schedule_env);
     if (n < 1 || n > MAX_QUBITS || !lds) return fail(QE_ERR_INVALID, "width must be 1..6");
-    *lds = g_sched[n][1].lds;
+    *lds = g_sched[n][1][SCHED_DISCRETE].lds;
     return QE_OK;
 }
 
@@ -393,15 +410,33 @@ qe_status qe_set_schedule_ex(int32_t n, int32_t lclass, int32_t lds, int32_t wav
     if (lclass != 0 && lclass != 1) return fail(QE_ERR_INVALID, "lclass must be 0 (L < 32) or 1 (L >= 32)");
     if (!sched_ok(n, lds, waves, cpb))
         return fail(QE_ERR_INVALID, "no such schedule: lds 0/1; waves 1 (n <= 5), 2 (n = 5) or 4 (n = 6); cpb 1 or 4");
-    g_sched[n][lclass] = Sched{lds, waves, cpb};
+    set_classes(n, lclass, Sched{lds, waves, cpb});
     return QE_OK;
 }
 
 qe_status qe_get_schedule_ex(int32_t n, int32_t lclass, int32_t* lds, int32_t* waves, int32_t* cpb) {
+    return qe_get_schedule_lib(n, lclass, QE_SCHED_DISCRETE, lds, waves, cpb);
+}
+
+qe_status qe_set_schedule_lib(int32_t n, int32_t lclass, int32_t lib_class, int32_t lds, int32_t waves,
+                              int32_t cpb) {
     std::call_once(g_sched_once, load_schedule_env);
-    if (n < 1 || n > MAX_QUBITS || (lclass != 0 && lclass != 1) || !lds || !waves || !cpb)
-        return fail(QE_ERR_INVALID, "width 1..6, lclass 0 or 1, non-NULL outputs");
-    const Sched v = g_sched[n][lclass];
+    if (lclass != 0 && lclass != 1) return fail(QE_ERR_INVALID, "lclass must be 0 (L < 32) or 1 (L >= 32)");
+    if (lib_class < 0 || lib_class >= SCHED_CLASSES)
+        return fail(QE_ERR_INVALID, "lib_class must be QE_SCHED_DISCRETE, QE_SCHED_SAMPLED or QE_SCHED_ISING");
+    if (!sched_ok(n, lds, waves, cpb))
+        return fail(QE_ERR_INVALID, "no such schedule: lds 0/1; waves 1 (n <= 5), 2 (n = 5) or 4 (n = 6); cpb 1 or 4");
+    g_sched[n][lclass][lib_class] = Sched{lds, waves, cpb};
+    return QE_OK;
+}
+
+qe_status qe_get_schedule_lib(int32_t n, int32_t lclass, int32_t lib_class, int32_t* lds, int32_t* waves,
+                              int32_t* cpb) {
+    std::call_once(g_sched_once, load_schedule_env);
+    if (n < 1 || n > MAX_QUBITS || (lclass != 0 && lclass != 1) || lib_class < 0 ||
+        lib_class >= SCHED_CLASSES || !lds || !waves || !cpb)
+        return fail(QE_ERR_INVALID, "width 1..6, lclass 0 or 1, lib_class 0..2, non-NULL outputs");
+    const Sched v = g_sched[n][lclass][lib_class];
     *lds = v.lds;
     *waves = v.waves;
     *cpb = v.cpb;

@@ -352,7 +352,7 @@ static void launch_width(const BatchArgs& a, int n, bool lds, float* f, float* g
             case 3: wave_kernel<3, FILTER, true><<<wgrid, wblock, 0, s>>>(a, f, g, delta); break;
             case 4: lds32_kernel<4, 1, FILTER, false, true><<<a.B, 64, 0, s>>>(a, f, g, delta, nullptr); break;
             case 5:
-                if (schedule_for(5, sched_len(a)).waves == 2)
+                if (schedule_for(5, sched_len(a), SCHED_ISING).waves == 2)
                     lds32_kernel<5, 2, FILTER, false, true><<<a.B, 128, 0, s>>>(a, f, g, delta, nullptr);
                 else
                     lds32_kernel<5, 1, FILTER, false, true><<<a.B, 64, 0, s>>>(a, f, g, delta, nullptr);

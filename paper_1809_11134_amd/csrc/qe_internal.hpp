@@ -31,7 +31,11 @@ struct BatchArgs {
 struct Sched {
     int lds, waves, cpb;
 };
-Sched schedule_for(int n, int L);
+// Library class of a schedule (QE_SCHED_*): circuits as given in a discrete
+// library, circuits the QEQEA sampler decodes (only {I, NOT, CNOT, CV, CV+}:
+// the CV body), circuits with angled gates (Ising library).
+enum : int { SCHED_DISCRETE = 0, SCHED_SAMPLED = 1, SCHED_ISING = 2, SCHED_CLASSES = 3 };
+Sched schedule_for(int n, int L, int lib_class = SCHED_DISCRETE);
 bool schedule_lds(int n);
 
 // Workspace of a mixed-width batch: MIX_WORK_META int32 of item table, then

@@ -1175,7 +1175,7 @@ static void launch_population(const LoopArgs& a, uint64_t gen, const uint16_t* g
                               bool decide = false) {
     const uint32_t total = (uint32_t)a.I * (uint32_t)a.P;
     const unsigned wb = blocks(total, 4);
-    const Sched sc = schedule_for(a.n, a.L);
+    const Sched sc = schedule_for(a.n, a.L, a.lib == LIB_ISING ? SCHED_ISING : (SAMPLE ? SCHED_SAMPLED : SCHED_DISCRETE));
     // the LDS-staged kernels of widths 4 and 5 under the schedule (waves per
     // circuit; circuits per workgroup with one wavefront per circuit)
     auto lds45 = [&](auto nq, auto ising) {

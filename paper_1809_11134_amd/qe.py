@@ -97,6 +97,8 @@ def load():
         "qe_eval_fitness_noalloc": [P(Batch), i32, vp, vp, vp, vp],
         "qe_set_schedule_ex": [i32, i32, i32, i32, i32],
         "qe_get_schedule_ex": [i32, i32, P(i32), P(i32), P(i32)],
+        "qe_set_schedule_lib": [i32, i32, i32, i32, i32, i32],
+        "qe_get_schedule_lib": [i32, i32, i32, P(i32), P(i32), P(i32)],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -299,6 +301,22 @@ def get_schedule_ex(n, lclass):
     """(lds, waves, cpb) of width n, length class lclass."""
     v = [ctypes.c_int32(0) for _ in range(3)]
     _call("qe_get_schedule_ex", n, lclass, *[ctypes.byref(x) for x in v])
+    return tuple(x.value for x in v)
+
+
+SCHED_DISCRETE, SCHED_SAMPLED, SCHED_ISING = 0, 1, 2
+
+
+def set_schedule_lib(n, lclass, lib_class, lds, waves, cpb):
+    """Schedule of width n, length class lclass, library class lib_class
+    (SCHED_DISCRETE, SCHED_SAMPLED, SCHED_ISING)."""
+    _call("qe_set_schedule_lib", n, lclass, lib_class, int(lds), int(waves), int(cpb))
+
+
+def get_schedule_lib(n, lclass, lib_class):
+    """(lds, waves, cpb) of width n, length class lclass, library class lib_class."""
+    v = [ctypes.c_int32(0) for _ in range(3)]
+    _call("qe_get_schedule_lib", n, lclass, lib_class, *[ctypes.byref(x) for x in v])
     return tuple(x.value for x in v)
 
 

@@ -1,18 +1,27 @@
 """Autotuner for the schedule of the FP32 fitness path.
 
-For each width n in 4..6 and each length class (circuits of 20 gates for
-L < 32, 48 gates for L >= 32) it times every schedule libqe can run -- the
-register-resident kernel, and the LDS-staged kernels with each allowed number
-of wavefronts per circuit and circuits per workgroup -- on three kernel
-families: qe_eval_fitness of a batch of uniform-random library circuits, the
-population evaluation of a GA context, and the fused sampling + fitness
-kernel of a QEQEA generation.  Timings are medians of repeated launches
-between HIP events; the schedule with the smallest sum wins.  The table
-(lines "n lclass lds waves cpb") goes to tune_mi355x.txt, which libqe reads
-at first use (the environment variable QE_TUNE_TABLE points elsewhere,
-QE_SCHEDULE overrides single widths).  Widths 1..3 always use the
-one-entry-per-lane kernel.  Every LDS-staged schedule gives the same bits,
-so the choice changes only speed.
+The schedule is chosen per width n in 4..6, length class (circuits of 20
+gates stand for L < 32, of 48 gates for L >= 32) and library class:
+
+* discrete (qe.SCHED_DISCRETE): circuits given in a discrete library, timed
+  as qe_eval_fitness of uniform-random {H, T, CNOT, CV, CV+} circuits plus
+  the population evaluation of a GA context over that library;
+* sampled (qe.SCHED_SAMPLED): circuits the QEQEA sampler decodes, timed as
+  the fused sampling + fitness kernel of a QEQEA generation over
+  {I, NOT, CNOT, CV, CV+};
+* Ising (qe.SCHED_ISING): circuits of the Ising library with angled gates,
+  timed as qe_eval_fitness of random Ising circuits plus the fused kernel of
+  a QEQEA generation over the Ising library.
+
+Every schedule libqe can run for the class is timed -- the register-resident
+kernel (not for angled circuits, which always take the LDS-staged kernels),
+and the LDS-staged kernels with each allowed number of wavefronts per circuit
+and circuits per workgroup; timings are medians of repeated launches between
+HIP events, and the schedule with the smallest sum wins.  The table (lines
+"n lclass lib lds waves cpb") goes to tune_mi355x.txt, which libqe reads at
+first use (QE_TUNE_TABLE points elsewhere, QE_SCHEDULE overrides single
+widths).  Widths 1..3 always use the one-entry-per-lane kernel.  Every
+LDS-staged schedule gives the same bits, so the choice changes only speed.
 
     python -m paper_1809_11134_amd.tune [--out PATH]
 """
@@ -33,6 +42,7 @@ CANDIDATES = {4: [(0, 1, 4), (1, 1, 4), (1, 1, 1)],
               5: [(0, 1, 4), (1, 1, 4), (1, 1, 1), (1, 2, 1)],
               6: [(0, 4, 1), (1, 4, 1)]}
 LENGTHS = {0: 20, 1: 48}
+CLASSES = {qe.SCHED_DISCRETE: "discrete", qe.SCHED_SAMPLED: "sampled", qe.SCHED_ISING: "ising"}
 
 
 def _median_us(fn, reps):
@@ -49,44 +59,75 @@ def _median_us(fn, reps):
     return t[len(t) // 2]
 
 
-def time_schedule(n, L, sched, reps, rng, dev, log):
-    for c in (0, 1):
-        qe.set_schedule_ex(n, c, *sched)
-    B = {4: 4096, 5: 16384, 6: 8192}[n]
-    g = torch.from_numpy(inputs.random_circuits(rng, B, n, L, 1).astype(np.int16)).to(dev)
-    T = qe.build_unitary(g[:1], n, L, precision=0)[0]
-    t_eval = _median_us(lambda: qe.eval_fitness(g, T, n=n, L=L), reps)
-    # population evaluation of a GA context (library {H,T,CNOT,CV,CV+})
-    P = 4096 if n < 6 else 1024
-    ga = qe.Context(n, 1, qe.ALG_GA, L, P, 1, seed=inputs.SEED_BASE)
-    ga.set_targets(qe.build_unitary(g[:1], n, L, precision=1))
-    _, gg = ga.sample(0)
-    t_pop = _median_us(lambda: ga.eval_population(gg), reps)
-    ga.close()
-    # the fused kernel of a QEQEA generation (library {I,NOT,CNOT,CV,CV+})
+def _qeqea_fused_us(n, L, P, library, reps, rng, dev):
     tg = torch.from_numpy(inputs.random_target_gates(rng, n, 12, permutation=True).astype(np.int16)[None]).to(dev)
-    ctx = qe.Context(n, 0, qe.ALG_QEQEA, L, P, 1, prob_mutation=0.1, mutation_range=math.pi / 4,
+    ctx = qe.Context(n, library, qe.ALG_QEQEA, L, P, 1, prob_mutation=0.1, mutation_range=math.pi / 4,
                      seed=inputs.SEED_BASE)
     ctx.set_targets(qe.build_unitary(tg, n, tg.shape[1], precision=1))
-    s, gq, f = ctx.sample_eval(0)
-    t_fused = _median_us(lambda: ctx.sample_eval(1, s, gq, f), reps)
+    out = ctx.sample_eval(0)
+    if library == qe.LIB_ISING:
+        s, gq, a, f = out
+        t = _median_us(lambda: ctx.sample_eval(1, s, gq, f, angles=a), reps)
+    else:
+        s, gq, f = out
+        t = _median_us(lambda: ctx.sample_eval(1, s, gq, f), reps)
     ctx.close()
-    log(f"n={n} L={L} schedule lds={sched[0]} waves={sched[1]} cpb={sched[2]}: eval {t_eval:.1f} us, "
-        f"population {t_pop:.1f} us, fused {t_fused:.1f} us")
-    return t_eval + t_pop + t_fused
+    return t
 
 
-def sweep(reps=7, log=print):
+def time_schedule(n, L, cls, sched, reps, rng, dev, log):
+    """Summed median time (us) of the class's kernels under one schedule."""
+    for c in (0, 1):
+        qe.set_schedule_lib(n, c, cls, *sched)
+    P = 4096 if n < 6 else 1024
+    parts = {}
+    if cls == qe.SCHED_DISCRETE:
+        B = {4: 4096, 5: 16384, 6: 8192}[n]
+        g = torch.from_numpy(inputs.random_circuits(rng, B, n, L, 1).astype(np.int16)).to(dev)
+        T = qe.build_unitary(g[:1], n, L, precision=0)[0]
+        parts["eval"] = _median_us(lambda: qe.eval_fitness(g, T, n=n, L=L), reps)
+        ga = qe.Context(n, 1, qe.ALG_GA, L, P, 1, seed=inputs.SEED_BASE)
+        ga.set_targets(qe.build_unitary(g[:1], n, L, precision=1))
+        _, gg = ga.sample(0)
+        parts["population"] = _median_us(lambda: ga.eval_population(gg), reps)
+        ga.close()
+    elif cls == qe.SCHED_SAMPLED:
+        parts["fused"] = _qeqea_fused_us(n, L, P, qe.LIB_NCV, reps, rng, dev)
+    else:
+        B = {4: 4096, 5: 8192, 6: 2048}[n]
+        g, a = inputs.random_ising_circuits(rng, B, n, L, discrete_frac=0.0)
+        gd = torch.from_numpy(np.ascontiguousarray(g).view(np.int16)).to(dev)
+        ad = torch.from_numpy(np.ascontiguousarray(a).view(np.int32)).to(dev)
+        T = qe.build_unitary(gd[:1], n, L, precision=0, angles=ad[:1])[0]
+        parts["eval"] = _median_us(lambda: qe.eval_fitness(gd, T, n=n, L=L, angles=ad), reps)
+        parts["fused"] = _qeqea_fused_us(n, L, P, qe.LIB_ISING, reps, rng, dev)
+    log(f"n={n} L={L} {CLASSES[cls]} schedule lds={sched[0]} waves={sched[1]} cpb={sched[2]}: " +
+        ", ".join(f"{k} {v:.1f} us" for k, v in parts.items()))
+    return sum(parts.values())
+
+
+def candidates(n, cls):
+    c = CANDIDATES[n]
+    return [s for s in c if s[0] == 1] if cls == qe.SCHED_ISING else c
+
+
+def sweep(reps=7, log=print, widths=(4, 5, 6)):
     dev = torch.device("cuda", 0)
+    saved = {(n, c, k): qe.get_schedule_lib(n, c, k) for n in widths for c in (0, 1) for k in CLASSES}
     table = {}
-    for n in (4, 5, 6):
-        for lclass, L in LENGTHS.items():
-            times = {}
-            for sched in CANDIDATES[n]:
-                rng = np.random.default_rng(inputs.SEED_BASE + 77 + 10 * n + lclass)
-                times[sched] = time_schedule(n, L, sched, reps, rng, dev, log)
-            best = min(times, key=times.get)
-            table[(n, lclass)] = (best, times)
+    try:
+        for n in widths:
+            for lclass, L in LENGTHS.items():
+                for cls in CLASSES:
+                    times = {}
+                    for sched in candidates(n, cls):
+                        rng = np.random.default_rng(inputs.SEED_BASE + 77 + 10 * n + lclass)
+                        times[sched] = time_schedule(n, L, cls, sched, reps, rng, dev, log)
+                    best = min(times, key=times.get)
+                    table[(n, lclass, cls)] = (best, times)
+    finally:
+        for (n, c, k), v in saved.items():
+            qe.set_schedule_lib(n, c, k, *v)
     return table
 
 
@@ -97,14 +138,15 @@ def main():
     args = ap.parse_args()
     qe.load()
     table = sweep(args.reps, log=lambda m: print(m, flush=True))
-    lines = ["# libqe FP32 schedule: n lclass lds waves cpb",
-             "#   lclass 0: L < 32, 1: L >= 32; lds 1 = LDS-staged, 0 = register-resident;",
-             "#   waves = wavefronts per circuit; cpb = circuits per workgroup (one-wavefront kernels)",
+    lines = ["# libqe FP32 schedule: n lclass lib lds waves cpb",
+             "#   lclass 0: L < 32, 1: L >= 32; lib 0: discrete library, 1: QEQEA-sampled, 2: Ising;",
+             "#   lds 1 = LDS-staged, 0 = register-resident; waves = wavefronts per circuit;",
+             "#   cpb = circuits per workgroup (one-wavefront population kernels)",
              "# written by paper_1809_11134_amd/tune.py on " + torch.cuda.get_device_name(0) +
-             " (sum of the eval, population and fused-kernel medians per schedule, us)"]
-    for (n, lclass), (best, times) in sorted(table.items()):
+             " (sum of the class's kernel medians per schedule, us)"]
+    for (n, lclass, cls), (best, times) in sorted(table.items()):
         alt = ", ".join(f"{s[0]}/{s[1]}/{s[2]}: {t:.1f}" for s, t in times.items())
-        lines.append(f"{n} {lclass} {best[0]} {best[1]} {best[2]}   # {alt}")
+        lines.append(f"{n} {lclass} {cls} {best[0]} {best[1]} {best[2]}   # {CLASSES[cls]}: {alt}")
     with open(args.out, "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print("\n".join(lines))

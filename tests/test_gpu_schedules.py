@@ -1,6 +1,7 @@
 """Every schedule the autotuner can choose for the LDS-staged kernels --
 wavefronts per circuit (width 5: one or two), circuits per workgroup of the
-one-wavefront population kernels (one or four), either length class -- gives
+one-wavefront population kernels (one or four), either length class, each
+library class on its own -- gives
 the same fitness bit for bit (the reduction runs in an order fixed by the
 width), in every kernel family: qe_eval_fitness on uniform and mixed-width
 batches, the population evaluation, the fused QEQEA kernel (discrete and
@@ -30,10 +31,10 @@ def dev():
 
 @pytest.fixture()
 def restore_schedules():
-    saved = {(n, c): qe.get_schedule_ex(n, c) for n in range(1, 7) for c in (0, 1)}
+    saved = {(n, c, k): qe.get_schedule_lib(n, c, k) for n in range(1, 7) for c in (0, 1) for k in (0, 1, 2)}
     yield
-    for (n, c), v in saved.items():
-        qe.set_schedule_ex(n, c, *v)
+    for (n, c, k), v in saved.items():
+        qe.set_schedule_lib(n, c, k, *v)
 
 
 def set_all(n, sched):
@@ -136,3 +137,34 @@ def test_mixed_ga_same_bits_every_width5_schedule(dev, oracle, restore_schedules
     for r in runs[1:]:
         for a, b in zip(r, runs[0]):
             assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("lib", [qe.LIB_NCV, qe.LIB_ISING])
+def test_library_classes_take_own_schedules_same_bits(dev, oracle, restore_schedules, lib):
+    """The sampled, discrete and Ising classes each under a schedule of their
+    own (width 5): the QEQEA loop, its population re-evaluation and a batch
+    evaluation keep the bits of one common schedule."""
+    n, L, P, I, seed = 5, 40, 48, 2, 4321 + lib
+    rng = np.random.default_rng(seed)
+    T = np.stack([oracle.unitary(n, inputs.random_target_gates(rng, n, 10, permutation=True)) for _ in range(I)])
+    own = {qe.SCHED_SAMPLED: (1, 2, 1), qe.SCHED_DISCRETE: (1, 1, 1), qe.SCHED_ISING: (1, 2, 1)}
+    runs = []
+    for per_class in (False, True):
+        for c in (0, 1):
+            for k in (0, 1, 2):
+                qe.set_schedule_lib(n, c, k, *(own[k] if per_class else (1, 1, 4)))
+        ctx = qe.Context(n, lib, qe.ALG_QEQEA, L, P, I, prob_mutation=0.3, mutation_range=math.pi / 4,
+                         seed=seed)
+        ctx.set_targets(torch.from_numpy(T).to(dev))
+        fs = [ctx.generation(gen).clone() for gen in range(3)]
+        out = ctx.sample_eval(3)
+        fe = ctx.eval_population(out[1], angles=out[2] if lib == qe.LIB_ISING else None)
+        torch.cuda.synchronize()
+        runs.append((fs, out, fe))
+        ctx.close()
+    for a, b in zip(runs[0][0], runs[1][0]):
+        assert torch.equal(a, b)
+    for a, b in zip(runs[0][1], runs[1][1]):
+        assert torch.equal(a, b)
+    assert torch.equal(runs[0][2], runs[1][2]) and torch.equal(runs[1][2], runs[1][1][-1])
+    assert qe.device_errors() == 0

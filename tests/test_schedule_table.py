@@ -10,7 +10,9 @@ import sys
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 PROBE = ("import sys; sys.path.insert(0, %r); from paper_1809_11134_amd import qe; "
          "print(' '.join(str(qe.get_schedule(n)) for n in range(1, 7))); "
-         "print(' '.join(','.join(str(x) for x in qe.get_schedule_ex(n, c)) for n in range(1, 7) for c in (0, 1)))"
+         "print(' '.join(','.join(str(x) for x in qe.get_schedule_ex(n, c)) for n in range(1, 7) for c in (0, 1))); "
+         "print(' '.join(','.join(str(x) for x in qe.get_schedule_lib(n, c, k)) "
+         "for n in range(1, 7) for c in (0, 1) for k in (0, 1, 2)))"
          % ROOT)
 
 
@@ -21,8 +23,11 @@ def schedule_with(env_extra):
     env.update(env_extra)
     out = subprocess.run([sys.executable, "-c", PROBE], env=env, capture_output=True, text=True,
                          check=True)
-    a, b = out.stdout.split("\n")[:2]
+    a, b, c3 = out.stdout.split("\n")[:3]
     full = [tuple(int(x) for x in t.split(",")) for t in b.split()]
+    by_lib = [tuple(int(x) for x in t.split(",")) for t in c3.split()]
+    schedule_with.by_lib = {(n, c, k): by_lib[6 * (n - 1) + 3 * c + k]
+                            for n in range(1, 7) for c in (0, 1) for k in (0, 1, 2)}
     return [int(x) for x in a.split()], {(n, c): full[2 * (n - 1) + c] for n in range(1, 7) for c in (0, 1)}
 
 
@@ -64,3 +69,41 @@ def test_set_schedule_ex_validates():
         qe.set_schedule_ex(5, 2, 1, 1, 4)
     with pytest.raises(qe.QeError):
         qe.set_schedule_ex(4, 0, 1, 1, 3)
+
+
+def test_library_class_lines(tmp_path):
+    """"n lclass lib lds waves cpb" sets one library class; the five-field
+    form sets all three; later lines win."""
+    table = tmp_path / "tune.txt"
+    table.write_text("5 1 1 1 1\n"
+                     "5 1 1 1 2 1   # sampled, long: two wavefronts\n"
+                     "5 0 2 1 2 1   # Ising, short\n"
+                     "4 0 1 1 4\n"
+                     "4 0 2 1 1 1\n"
+                     "5 1 3 1 1 1   # no such class: ignored\n")
+    schedule_with({"QE_TUNE_TABLE": str(table)})
+    got = schedule_with.by_lib
+    assert got[(5, 1, 1)] == (1, 2, 1) and got[(5, 1, 0)] == (1, 1, 1) and got[(5, 1, 2)] == (1, 1, 1)
+    assert got[(5, 0, 2)] == (1, 2, 1) and got[(5, 0, 0)][1] == 1
+    assert got[(4, 0, 0)] == (1, 1, 4) and got[(4, 0, 1)] == (1, 1, 4) and got[(4, 0, 2)] == (1, 1, 1)
+    # QE_SCHEDULE overrides every class of a width
+    schedule_with({"QE_TUNE_TABLE": str(table), "QE_SCHEDULE": "5:1:1:4"})
+    got = schedule_with.by_lib
+    assert all(got[(5, c, k)] == (1, 1, 4) for c in (0, 1) for k in (0, 1, 2))
+
+
+def test_set_schedule_lib_validates():
+    import pytest
+    from paper_1809_11134_amd import qe
+    saved = qe.get_schedule_lib(5, 1, qe.SCHED_ISING)
+    try:
+        qe.set_schedule_lib(5, 1, qe.SCHED_ISING, 1, 2, 1)
+        assert qe.get_schedule_lib(5, 1, qe.SCHED_ISING) == (1, 2, 1)
+        with pytest.raises(qe.QeError):
+            qe.set_schedule_lib(5, 1, 3, 1, 1, 1)
+        with pytest.raises(qe.QeError):
+            qe.set_schedule_lib(6, 0, qe.SCHED_SAMPLED, 1, 1, 1)
+        with pytest.raises(qe.QeError):
+            qe.get_schedule_lib(5, 2, 0)
+    finally:
+        qe.set_schedule_lib(5, 1, qe.SCHED_ISING, *saved)
