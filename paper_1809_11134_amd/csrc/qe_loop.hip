@@ -955,36 +955,36 @@ __global__ __launch_bounds__(256) void elite_eval_kernel(LoopArgs a, const uint1
 }
 
 // FP64 re-check of elite circuits of width NQ (4 or 5) over a discrete
-// library: one wavefront per circuit, CPB circuits per workgroup, the
-// product U T^dagger (Eq. 11) as complex128 in LDS.  Lane l owns column
-// j = l mod N and row group h = l div N; a gate's row pairs are its pair
-// indices (the target bit taken out) or, for a controlled gate, its quad
-// indices (target and control bits taken out), the row group supplying the
-// low bits.  NOT and CNOT move no data: as in the FP32 LDS path, logical
-// row r is stored at row A r ^ b (A's column p in bits 6p..6p+5), and they
-// only update A and b.  CV and CV+ take the halves of a + b and i (a - b);
-// H and T are applied as their matrices say.  The results agree with the
-// generic FP64 body to rounding.
-template <int NQ, bool CTL>
-__device__ __forceinline__ void elite64_pairs(double2* M, int kind, int tp, int cp, int j, int h,
-                                              uint64_t A, uint32_t b) {
-    constexpr int N = 1 << NQ, RG = 64 / N, RGB = NQ == 5 ? 1 : 2;
-    static_assert(RG == (1 << RGB), "row groups");
+// library: W wavefronts per circuit (each owning N / W columns: gates mix
+// rows only, so the wavefronts of a circuit never exchange data until the
+// reduction), CPB circuits per workgroup, the product U T^dagger (Eq. 11)
+// as complex128 in LDS.  Lane l of a wavefront owns column
+// j = w N / W + l mod (N / W) and row group h = l div (N / W); a gate's row
+// pairs are its pair indices (the target bit taken out) or, for a
+// controlled gate, its quad indices (target and control bits taken out),
+// the row group supplying the low bits.  NOT and CNOT move no data: as in
+// the FP32 LDS path, logical row r is stored at row A r ^ b (A's column p in
+// bits 6p..6p+5), and they only update A and b.  CV and CV+ take the halves
+// of a + b and i (a - b); H and T are applied as their matrices say.  The
+// results agree with the generic FP64 body to rounding.
+template <int NQ, int W>
+struct Elite64Layout {
+    static constexpr int N = 1 << NQ, LPR = N / W, RG = 64 / LPR;
+    static constexpr int RGB = RG == 2 ? 1 : (RG == 4 ? 2 : 3);
+    static_assert(RG == (1 << RGB) && RG <= 8, "row groups");
+    static_assert(NQ - 2 >= RGB, "a controlled gate's quads cover the row groups");
+};
+
+// One gate on the lane's pairs: base = stored row of the lane's first pair
+// (row group bits, control row and the map's translation folded in), pass[k]
+// = stored image of pair-index bit RGB + k, tstep = stored image of the
+// target bit.
+template <int NQ, int W, bool CTL>
+__device__ __forceinline__ void elite64_pairs(double2* M, int kind, uint32_t base, const uint32_t* pass,
+                                              uint32_t tstep, int j) {
+    using LY = Elite64Layout<NQ, W>;
     constexpr int QB = NQ - 1 - (CTL ? 1 : 0);       // bits of the pair index
-    constexpr int NP = (1 << QB) / RG;               // pairs per lane
-    auto col = [&](int p) -> uint32_t { return (uint32_t)(A >> (6 * p)) & 63u; };
-    const int lo = CTL ? min(tp, cp) : tp, hi = CTL ? max(tp, cp) : NQ;
-    // stored image of pair-index bit k (its logical row bit after the insertions)
-    auto img = [&](int k) -> uint32_t {
-        int pos = k < lo ? k : k + 1;
-        pos = pos < hi ? pos : pos + 1;
-        return col(pos);
-    };
-    uint32_t base = b ^ (CTL ? col(cp) : 0u);
-#pragma unroll
-    for (int k = 0; k < RGB; ++k)
-        if ((h >> k) & 1) base ^= img(k);
-    const uint32_t tstep = col(tp);
+    constexpr int NP = (1 << QB) / LY::RG;           // pairs per lane
     double2 X[NP], Y[NP];
     int o0[NP], o1[NP];
 #pragma unroll
@@ -992,7 +992,7 @@ __device__ __forceinline__ void elite64_pairs(double2* M, int kind, int tp, int 
         uint32_t sr = base;
 #pragma unroll
         for (int k = 0; (1 << k) < NP; ++k)
-            if ((m >> k) & 1) sr ^= img(RGB + k);
+            if ((m >> k) & 1) sr ^= pass[k];
         o0[m] = (int)((sr << NQ) | (uint32_t)j);
         o1[m] = (int)(((sr ^ tstep) << NQ) | (uint32_t)j);
         X[m] = M[o0[m]];
@@ -1003,7 +1003,7 @@ __device__ __forceinline__ void elite64_pairs(double2* M, int kind, int tp, int 
     for (int m = 0; m < NP; ++m) {
         const double2 a = X[m], bb = Y[m];
         double2 x, y;
-        if (kind == KIND_CV || kind == KIND_CVDG) {
+        if (CTL) {
             // V = [[1+i, 1-i], [1-i, 1+i]] / 2: a' = (s + i d) / 2, b' = (s - i d) / 2
             // with s = a + b, d = a - b; V+ swaps the two
             const double sr = 0.5 * (a.x + bb.x), si = 0.5 * (a.y + bb.y);
@@ -1023,77 +1023,140 @@ __device__ __forceinline__ void elite64_pairs(double2* M, int kind, int tp, int 
     }
 }
 
-template <int NQ, int CPB>
-__global__ __launch_bounds__(64 * CPB) void elite64_kernel(LoopArgs a, const uint16_t* __restrict__ gates,
-                                                           int k, const int32_t* __restrict__ idx,
-                                                           double* __restrict__ f64) {
-    constexpr int N = 1 << NQ, RG = 64 / N, RGB = NQ == 5 ? 1 : 2;
+template <int NQ, int W, int CPB>
+__global__ __launch_bounds__(64 * W * CPB) void elite64_kernel(LoopArgs a, const uint16_t* __restrict__ gates,
+                                                               int k, const int32_t* __restrict__ idx,
+                                                               double* __restrict__ f64) {
+    using LY = Elite64Layout<NQ, W>;
+    constexpr int N = LY::N, LPR = LY::LPR, RG = LY::RG, RGB = LY::RGB;
     __shared__ double2 Ms[CPB][N * N];
+    __shared__ double red[CPB][W];
     const int wave = (int)(threadIdx.x >> 6), lane = (int)lane_id();
-    const uint32_t ci = __builtin_amdgcn_readfirstlane(blockIdx.x * CPB + (uint32_t)wave);
-    if (ci >= (uint32_t)a.I * (uint32_t)k) return;
-    const uint32_t i = ci / (uint32_t)k;
-    const int c = idx[ci];
+    const int circ = wave / W, wv = wave % W;
+    const uint32_t ci = __builtin_amdgcn_readfirstlane(blockIdx.x * CPB + (uint32_t)circ);
+    const bool valid = ci < (uint32_t)a.I * (uint32_t)k;   // (every wavefront reaches the barrier)
+    const uint32_t i = valid ? ci / (uint32_t)k : 0u;
+    const int c = valid ? idx[ci] : 0;
     uint32_t err = (c < 0 || c >= a.P) ? (uint32_t)QE_DEVERR_RANGE : 0u;
     const int L = a.L;
     const uint16_t* g = gates + ((size_t)i * a.P + (size_t)(err ? 0 : c)) * L;
     const double2* T = reinterpret_cast<const double2*>(a.target64) + ((size_t)i << (2 * NQ));
-    double2* M = Ms[wave];
-    const int j = lane & (N - 1), h = lane >> NQ;
+    double2* M = Ms[circ];
+    const int j = wv * LPR + lane % LPR, h = lane / LPR;
     uint64_t A = 0;                                   // the row map, identity
 #pragma unroll
     for (int p = 0; p < NQ; ++p) A |= (uint64_t)(1u << p) << (6 * p);
     uint32_t b = 0;
-    bool ok = err == 0;
+    bool ok = valid && err == 0;
     if (ok) {
-        // M = T^dagger
-        for (int e = lane; e < N * N; e += 64) {
-            const double2 t = T[e];
-            M[(e & (N - 1)) * N + (e >> NQ)] = make_double2(t.x, -t.y);
+        // M = T^dagger on this wavefront's columns: M[r][j] = conj(T[j][r])
+#pragma unroll
+        for (int m = 0; m < N / RG; ++m) {
+            const int r = h + m * RG;
+            const double2 t = T[(size_t)j * N + r];
+            M[r * N + j] = make_double2(t.x, -t.y);
         }
         wave_lds_fence();
         for (int l0 = 0; l0 < L && ok; l0 += 64) {
-            const uint32_t mine = l0 + lane < L ? (uint32_t)g[l0 + lane] : 0u;
+            // the chunk's gate program, one gate per lane: descriptor checks,
+            // the row map in force at each gate (NOT and CNOT folded in, in
+            // circuit order), and each data-moving gate's stored offsets
             const int cnt = min(64, L - l0);
-            for (int u = 0; u < cnt; ++u) {
-                const uint32_t d = __builtin_amdgcn_readlane(mine, u);
-                if (!desc_valid(d, NQ)) { ok = false; break; }
-                const int kind = (int)(d & 15u);
-                if (kind == KIND_I) continue;
-                const int tp = NQ - 1 - (int)((d >> 4) & 15u), cp = NQ - 1 - (int)((d >> 8) & 15u);
-                const uint32_t ct = (uint32_t)(A >> (6 * tp)) & 63u;
-                if (kind == KIND_NOT) { b ^= ct; continue; }
-                if (kind == KIND_CNOT) { A ^= (uint64_t)ct << (6 * cp); continue; }
-                if (kind == KIND_CV || kind == KIND_CVDG)
-                    elite64_pairs<NQ, true>(M, kind, tp, cp, j, h, A, b);
+            const bool in = lane < cnt;
+            const uint32_t dv = in ? (uint32_t)g[l0 + lane] : 0u;
+            if (__ballot(in && !desc_valid(dv, NQ))) { ok = false; break; }
+            const int kind = (int)(dv & 15u);
+            const int tp = NQ - 1 - (int)((dv >> 4) & 15u), cp = NQ - 1 - (int)((dv >> 8) & 15u);
+            const bool perm = in && (kind == KIND_NOT || kind == KIND_CNOT);
+            uint64_t myA = A;
+            uint32_t myB = b;
+            uint64_t pm = __ballot(perm);
+            while (pm) {
+                const int gg = (int)__builtin_ctzll(pm);
+                pm &= pm - 1;
+                const uint32_t d = (uint32_t)__builtin_amdgcn_readlane((int)dv, gg);
+                const int pt = NQ - 1 - (int)((d >> 4) & 15u);
+                const uint32_t colt = (uint32_t)(A >> (6 * pt)) & 63u;
+                if ((d & 15u) == (uint32_t)KIND_NOT) {
+                    b ^= colt;
+                } else {
+                    const int pc = NQ - 1 - (int)((d >> 8) & 15u);
+                    A ^= (uint64_t)colt << (6 * pc);
+                }
+                if (lane > gg) { myA = A; myB = b; }
+            }
+            const bool live = in && kind != KIND_I && !perm;
+            const bool ctl = kind == KIND_CV || kind == KIND_CVDG;
+            auto col = [&](int p) -> uint32_t { return (uint32_t)(myA >> (6 * (p & 7))) & 63u; };
+            const int lo = ctl ? min(tp, cp) : tp, hi = ctl ? max(tp, cp) : NQ;
+            auto img = [&](int kk) -> uint32_t {       // pair-index bit kk -> stored row bits
+                int pos = kk < lo ? kk : kk + 1;
+                pos = pos < hi ? pos : pos + 1;
+                return col(pos);
+            };
+            const uint32_t gbase = live ? (myB ^ (ctl ? col(cp) : 0u)) : 0u;
+            const uint32_t gt = live ? col(tp) : 0u;
+            uint32_t gimg[NQ - 1];
+#pragma unroll
+            for (int kk = 0; kk < NQ - 1; ++kk) gimg[kk] = live ? img(kk) : 0u;
+            uint64_t todo = __ballot(live);
+            while (todo) {
+                const int gg = (int)__builtin_ctzll(todo);
+                todo &= todo - 1;
+                auto rl = [&](uint32_t v) { return (uint32_t)__builtin_amdgcn_readlane((int)v, gg); };
+                const int kg = (int)rl((uint32_t)kind);
+                uint32_t base = rl(gbase);
+                uint32_t im[NQ - 1];
+#pragma unroll
+                for (int kk = 0; kk < NQ - 1; ++kk) im[kk] = rl(gimg[kk]);
+#pragma unroll
+                for (int kk = 0; kk < RGB; ++kk)
+                    if ((h >> kk) & 1) base ^= im[kk];
+                const uint32_t ts = rl(gt);
+                if (kg == KIND_CV || kg == KIND_CVDG)
+                    elite64_pairs<NQ, W, true>(M, kg, base, im + RGB, ts, j);
                 else
-                    elite64_pairs<NQ, false>(M, kind, tp, 0, j, h, A, b);
+                    elite64_pairs<NQ, W, false>(M, kg, base, im + RGB, ts, j);
                 wave_lds_fence();
             }
         }
-        if (!ok) err = QE_DEVERR_DESC;
+        if (valid && !ok && !err) err = QE_DEVERR_DESC;
     }
-    // Eq. 11 (or the phase-insensitive form): lane (j, h) reads the logical
-    // rows h, h + RG, ... at their stored rows
-    double off = 0.0, dr = 0.0, di = 0.0;
-    bool hasd = false;
-    if (ok) {
-        uint32_t sh = b;
+    auto stored = [&](uint32_t r) -> uint32_t {      // stored row of logical row r
+        uint32_t s = b;
 #pragma unroll
-        for (int p = 0; p < RGB; ++p)
-            if ((h >> p) & 1) sh ^= (uint32_t)(A >> (6 * p)) & 63u;
+        for (int p = 0; p < NQ; ++p)
+            if ((r >> p) & 1) s ^= (uint32_t)(A >> (6 * p)) & 63u;
+        return s;
+    };
+    // Eq. 11 (or the phase-insensitive form): the off-diagonal energy over
+    // the lane's logical rows h, h + RG, ..., summed over the wavefronts of
+    // the circuit in order; then the first wavefront reads the diagonal
+    double off = 0.0;
+    if (ok) {
+        const uint32_t sh = stored((uint32_t)h);
 #pragma unroll
         for (int m = 0; m < N / RG; ++m) {
-            uint32_t sr = sh;
-#pragma unroll
-            for (int p = 0; p < NQ - RGB; ++p)
-                if ((m >> p) & 1) sr ^= (uint32_t)(A >> (6 * (RGB + p))) & 63u;
+            const uint32_t sr = sh ^ (stored((uint32_t)(m * RG)) ^ b);
             const double2 v = M[(sr << NQ) | (uint32_t)j];
-            if (h + m * RG == j) { dr = v.x; di = v.y; hasd = true; }
-            else off += v.x * v.x + v.y * v.y;
+            if (h + m * RG != j) off += v.x * v.x + v.y * v.y;
         }
     }
     off = wave_sum(off);
+    if constexpr (W > 1) {
+        if (lane == 0) red[circ][wv] = off;
+        __syncthreads();
+        off = 0.0;
+#pragma unroll
+        for (int w = 0; w < W; ++w) off += red[circ][w];
+    }
+    if (wv != 0 || !valid) return;
+    double dr = 0.0, di = 0.0;
+    if (ok && lane < N) {
+        const double2 v = M[(stored((uint32_t)lane) << NQ) | (uint32_t)lane];
+        dr = v.x;
+        di = v.y;
+    }
     double fv, gv, dl;
     if (a.fit_mode == QE_FIT_PHASE_INSENSITIVE) {
         fitness_pi(off, N, &fv, &gv, &dl);
@@ -1103,7 +1166,7 @@ __global__ __launch_bounds__(64 * CPB) void elite64_kernel(LoopArgs a, const uin
         double er = 1.0, ei = 0.0;
         if (am > 0.0) { er = tr / am; ei = ti / am; }
         double D = 0.0;
-        if (hasd) { const double xr = dr - er, xi = di - ei; D = xr * xr + xi * xi; }
+        if (lane < N) { const double xr = dr - er, xi = di - ei; D = xr * xr + xi * xi; }
         dl = 0.5 * (off + wave_sum(D));
         double q = dl / (double)N;
         q = q < 0.0 ? 0.0 : (q > 1.0 ? 1.0 : q);
@@ -1329,9 +1392,9 @@ hipError_t launch_elite_eval(const LoopArgs& a, const uint16_t* gates, const uin
     // uniform widths 4 and 5 over a discrete library: one wavefront per circuit
     const unsigned nc = (unsigned)a.I * (unsigned)k;
     if (!a.inst_n && !angles && a.n == 5) {
-        elite64_kernel<5, 2><<<(nc + 1) / 2, 128, 0, s>>>(a, gates, k, idx, f64);
+        elite64_kernel<5, 2, 2><<<(nc + 1) / 2, 256, 0, s>>>(a, gates, k, idx, f64);
     } else if (!a.inst_n && !angles && a.n == 4) {
-        elite64_kernel<4, 4><<<(nc + 3) / 4, 256, 0, s>>>(a, gates, k, idx, f64);
+        elite64_kernel<4, 1, 4><<<(nc + 3) / 4, 256, 0, s>>>(a, gates, k, idx, f64);
     } else {
         elite_eval_kernel<<<nc, 256, generic_lds_bytes(a.n, sizeof(double)), s>>>(a, gates, angles, k, idx, f64);
     }
