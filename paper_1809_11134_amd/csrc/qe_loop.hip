@@ -525,13 +525,14 @@ __device__ __forceinline__ void mutate_state(const LoopArgs& a, uint32_t gen, ui
 }
 
 // Part C: the instance's best circuit of the generation (largest f, lowest
-// index; NaN never counts) updates its best circuit ever.  Part A: used slots
-// of individuals that do not mutate, one thread per (circuit, position)
-// entry; an entry handles its slot only if its circuit holds the slot's key.
-// Part B: every slot of the individuals that mutate
-// (one thread per slot, since the individual's slots belong to nobody else):
-// elitism if the slot was used, then mutation (qubit mode: every slot;
-// qutrit mode: rotation slots).  The grid holds part C, then part B (the
+// index; NaN never counts) updates its best circuit ever.  Part A: the used
+// slots the mutation leaves alone (those of individuals that do not mutate,
+// and the template slots of individuals mutating in qutrit mode), one thread
+// per (circuit, position) entry; an entry handles its slot only if its
+// circuit holds the slot's key.  Part B: the slots the mutation moves (qubit
+// mode: every slot of the individual; qutrit mode: its rotation slots), one
+// thread per slot, since the individual's slots belong to nobody else:
+// elitism if the slot was used, then mutation.  The grid holds part C, then part B (the
 // longest chains), then part A, so the longer work is dispatched first.
 constexpr int UPD_BLOCK = 256;
 constexpr int UPD_MAX_P = 16384;          // part B's list of mutated individuals lives in LDS
@@ -561,7 +562,13 @@ __device__ __forceinline__ void update_part_a(const LoopArgs& a, uint32_t gen, u
     // fitness (when several circuits share that fitness, each applies the
     // same elitism to the same record, which leaves the same state)
     if (r.key == 0u || !(fk >= 0.0f) || r.key != seg_key(fk)) return;
-    if (mut) return;
+    if (mut) {
+        // part B takes the slots the mutation moves: every slot of an
+        // individual in qubit mode, the rotation slots in qutrit mode
+        bool qm;
+        mutates(a, gen, i, ind, &qm);
+        if (!qm || rot) return;
+    }
     const float v = seg_fitness(r.key);
     r.key = 0u;
     elitism(v, r, q, rot);
@@ -629,15 +636,20 @@ __device__ __forceinline__ void update_part_b(const LoopArgs& a, uint32_t gen, u
         const uint32_t s = r_ * LP + ind * L + pos;
         const size_t o = (size_t)i * a.S + s, oq = (size_t)i * a.Q + s;
         const bool rot = r_ < (uint32_t)a.n;
-        SlotRec r = a.slot[o];
-        QState q{};
-        if (rot) q = load_qstate(a.qrec + oq);
         bool qm;
         mutates(a, gen, i, ind, &qm);
+        // qutrit mode moves only the rotation slots; the others' elitism is
+        // part A's
+        if (qm && !rot) continue;
+        SlotRec r = a.slot[o];
+        QState q{};
+        if (rot && qm) q = load_qstate(a.qrec + oq);
         const bool used = r.key != 0u;
+        // qubit mode reads a rotation slot's qutrit only for its elitism
+        if (rot && !qm && used) q = load_qstate(a.qrec + oq);
         if (used) elitism(seg_fitness(r.key), r, q, rot);
         r.key = 0u;
-        if (!qm || rot) mutate_state(a, gen, i, s, qm, r, q);
+        mutate_state(a, gen, i, s, qm, r, q);
         // an unused slot in qutrit mode keeps its record (only the qutrit moves)
         if (used || !qm) a.slot[o] = r;
         if (rot && (used || qm)) store_qstate(a.qrec + oq, q);
