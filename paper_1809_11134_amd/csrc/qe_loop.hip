@@ -536,6 +536,9 @@ __device__ __forceinline__ void mutate_state(const LoopArgs& a, uint32_t gen, ui
 // longest chains), then part A, so the longer work is dispatched first.
 constexpr int UPD_BLOCK = 256;
 constexpr int UPD_MAX_P = 16384;          // part B's list of mutated individuals lives in LDS
+constexpr int UPD_SPL = 4;                // part B: slots per lane of an item (2 and 8 measured slower)
+constexpr int UPD_ITEM = 64 * UPD_SPL;    // part B: slots of an item (one wavefront)
+constexpr int UPD_WPB = UPD_BLOCK / 64;   // wavefronts per workgroup
 
 // slots NULL: the entry's slot is drawn again (the generation's own
 // sampling, which saves a dependent load); otherwise it is read.
@@ -577,15 +580,16 @@ __device__ __forceinline__ void update_part_a(const LoopArgs& a, uint32_t gen, u
 }
 
 // Workgroup b of part B serves instance b / per_inst: it lists the
-// instance's mutated individuals in LDS from the decision mask, then walks
-// the (individual, slot chunk) items with stride per_inst.
+// instance's mutated individuals in LDS from the decision mask, then its
+// wavefronts walk the (individual, chunk of UPD_ITEM slots) items, one item
+// each, with stride per_inst * UPD_WPB.
 __device__ __forceinline__ void update_part_b(const LoopArgs& a, uint32_t gen, uint32_t b,
                                               uint32_t per_inst) {
     extern __shared__ uint16_t list[];        // P entries (launch-time size)
     __shared__ uint32_t total;
     const uint32_t L = (uint32_t)a.L, P = (uint32_t)a.P, LP = L * P;
     const uint32_t per = a.R * L;                               // slots of one individual
-    const uint32_t chunks = (per + UPD_BLOCK - 1) / UPD_BLOCK;
+    const uint32_t chunks = (per + UPD_ITEM - 1) / UPD_ITEM;
     const uint32_t i = b / per_inst;
     if (i >= (uint32_t)a.I) return;
     if (threadIdx.x < 64) {
@@ -626,33 +630,50 @@ __device__ __forceinline__ void update_part_b(const LoopArgs& a, uint32_t gen, u
     }
     __syncthreads();
     const uint32_t count = total;
-    for (uint32_t t = b % per_inst; t < count * chunks; t += per_inst) {
-        // (every thread of the workgroup serves the same individual: its
-        // decision is drawn once per wavefront, on the scalar unit)
+    // one (individual, chunk) item per wavefront, UPD_SPL slots per lane with
+    // their loads issued together
+    const uint32_t wv = threadIdx.x >> 6, ln = threadIdx.x & 63u;
+    for (uint32_t t = (b % per_inst) * UPD_WPB + wv; t < count * chunks; t += per_inst * UPD_WPB) {
+        // (the wavefront serves one individual: its decision is drawn once,
+        // on the scalar unit)
         const uint32_t ind = (uint32_t)__builtin_amdgcn_readfirstlane((int)list[t / chunks]);
-        const uint32_t e = (t % chunks) * UPD_BLOCK + threadIdx.x;
-        if (e >= per) continue;
-        const uint32_t r_ = e / L, pos = e - r_ * L;
-        const uint32_t s = r_ * LP + ind * L + pos;
-        const size_t o = (size_t)i * a.S + s, oq = (size_t)i * a.Q + s;
-        const bool rot = r_ < (uint32_t)a.n;
         bool qm;
         mutates(a, gen, i, ind, &qm);
-        // qutrit mode moves only the rotation slots; the others' elitism is
-        // part A's
-        if (qm && !rot) continue;
-        SlotRec r = a.slot[o];
-        QState q{};
-        if (rot && qm) q = load_qstate(a.qrec + oq);
-        const bool used = r.key != 0u;
-        // qubit mode reads a rotation slot's qutrit only for its elitism
-        if (rot && !qm && used) q = load_qstate(a.qrec + oq);
-        if (used) elitism(seg_fitness(r.key), r, q, rot);
-        r.key = 0u;
-        mutate_state(a, gen, i, s, qm, r, q);
-        // an unused slot in qutrit mode keeps its record (only the qutrit moves)
-        if (used || !qm) a.slot[o] = r;
-        if (rot && (used || qm)) store_qstate(a.qrec + oq, q);
+        SlotRec r[UPD_SPL];
+        QState q[UPD_SPL];
+        uint32_t sl[UPD_SPL];
+        bool act[UPD_SPL];
+#pragma unroll
+        for (int u = 0; u < UPD_SPL; ++u) {
+            const uint32_t e = (t % chunks) * UPD_ITEM + (uint32_t)u * 64u + ln;
+            const uint32_t r_ = e / L, pos = e - r_ * L;
+            sl[u] = r_ * LP + ind * L + pos;
+            const bool rot = r_ < (uint32_t)a.n;
+            // qutrit mode moves only the rotation slots; the others'
+            // elitism is part A's
+            act[u] = e < per && !(qm && !rot);
+            q[u] = QState{};
+            if (act[u]) {
+                r[u] = a.slot[(size_t)i * a.S + sl[u]];
+                if (rot && qm) q[u] = load_qstate(a.qrec + (size_t)i * a.Q + sl[u]);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < UPD_SPL; ++u) {
+            if (!act[u]) continue;
+            const uint32_t s = sl[u];
+            const size_t o = (size_t)i * a.S + s, oq = (size_t)i * a.Q + s;
+            const bool rot = s < a.Q;
+            const bool used = r[u].key != 0u;
+            // qubit mode reads a rotation slot's qutrit only for its elitism
+            if (rot && !qm && used) q[u] = load_qstate(a.qrec + oq);
+            if (used) elitism(seg_fitness(r[u].key), r[u], q[u], rot);
+            r[u].key = 0u;
+            mutate_state(a, gen, i, s, qm, r[u], q[u]);
+            // an unused slot in qutrit mode keeps its record (only the qutrit moves)
+            if (used || !qm) a.slot[o] = r[u];
+            if (rot && (used || qm)) store_qstate(a.qrec + oq, q[u]);
+        }
     }
 }
 
@@ -1346,12 +1367,13 @@ hipError_t launch_qeqea_update(const LoopArgs& a, uint64_t gen, const uint32_t* 
     // workgroups than the GPU runs at once and the total is close to its mean,
     // so the slack only adds workgroups that find nothing to do: then each
     // instance gets its mean and the busier ones loop.
-    const size_t chunks = ((size_t)a.R * a.L + UPD_BLOCK - 1) / UPD_BLOCK;
+    const size_t chunks = ((size_t)a.R * a.L + UPD_ITEM - 1) / UPD_ITEM;
     const double pm = (double)a.thr_pm / 4294967296.0;
     const double expect = pm * a.P * chunks, sd = std::sqrt(a.P * pm * (1.0 - pm)) * chunks;
     const double slack = expect * a.I > 8192.0 ? 1.0 : 4.0 * sd + 8.0;
+    // (each workgroup serves UPD_WPB items at once, one per wavefront)
     const uint32_t per_inst = (uint32_t)std::max<double>(
-        1.0, std::min<double>(std::ceil(expect + slack), (double)a.P * chunks));
+        1.0, std::ceil(std::min<double>(std::ceil(expect + slack), (double)a.P * chunks) / UPD_WPB));
     const uint32_t nB = per_inst * (uint32_t)a.I;
     const size_t lds = ((size_t)a.P * sizeof(uint16_t) + 15) & ~(size_t)15;
     const uint32_t a0 = (nC + nB + 7u) & ~7u;
