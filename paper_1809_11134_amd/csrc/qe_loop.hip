@@ -536,9 +536,10 @@ __device__ __forceinline__ void mutate_state(const LoopArgs& a, uint32_t gen, ui
 // longest chains), then part A, so the longer work is dispatched first.
 constexpr int UPD_BLOCK = 256;
 constexpr int UPD_MAX_P = 16384;          // part B's list of mutated individuals lives in LDS
-constexpr int UPD_SPL = 4;                // part B: slots per lane of an item (2 and 8 measured slower)
-constexpr int UPD_ITEM = 64 * UPD_SPL;    // part B: slots of an item (one wavefront)
 constexpr int UPD_WPB = UPD_BLOCK / 64;   // wavefronts per workgroup
+// part B: SPL slots per lane of an item (64 SPL slots, one wavefront): 4
+// when many populations fill the launch (2 and 8 measured slower), 1 for a
+// few large populations, which need the wavefronts
 
 // slots NULL: the entry's slot is drawn again (the generation's own
 // sampling, which saves a dependent load); otherwise it is read.
@@ -581,15 +582,17 @@ __device__ __forceinline__ void update_part_a(const LoopArgs& a, uint32_t gen, u
 
 // Workgroup b of part B serves instance b / per_inst: it lists the
 // instance's mutated individuals in LDS from the decision mask, then its
-// wavefronts walk the (individual, chunk of UPD_ITEM slots) items, one item
+// wavefronts walk the (individual, chunk of 64 SPL slots) items, one item
 // each, with stride per_inst * UPD_WPB.
+template <int SPL>
 __device__ __forceinline__ void update_part_b(const LoopArgs& a, uint32_t gen, uint32_t b,
                                               uint32_t per_inst) {
     extern __shared__ uint16_t list[];        // P entries (launch-time size)
     __shared__ uint32_t total;
     const uint32_t L = (uint32_t)a.L, P = (uint32_t)a.P, LP = L * P;
     const uint32_t per = a.R * L;                               // slots of one individual
-    const uint32_t chunks = (per + UPD_ITEM - 1) / UPD_ITEM;
+    constexpr uint32_t ITEM = 64u * SPL;
+    const uint32_t chunks = (per + ITEM - 1) / ITEM;
     const uint32_t i = b / per_inst;
     if (i >= (uint32_t)a.I) return;
     if (threadIdx.x < 64) {
@@ -630,7 +633,7 @@ __device__ __forceinline__ void update_part_b(const LoopArgs& a, uint32_t gen, u
     }
     __syncthreads();
     const uint32_t count = total;
-    // one (individual, chunk) item per wavefront, UPD_SPL slots per lane with
+    // one (individual, chunk) item per wavefront, SPL slots per lane with
     // their loads issued together
     const uint32_t wv = threadIdx.x >> 6, ln = threadIdx.x & 63u;
     for (uint32_t t = (b % per_inst) * UPD_WPB + wv; t < count * chunks; t += per_inst * UPD_WPB) {
@@ -639,13 +642,13 @@ __device__ __forceinline__ void update_part_b(const LoopArgs& a, uint32_t gen, u
         const uint32_t ind = (uint32_t)__builtin_amdgcn_readfirstlane((int)list[t / chunks]);
         bool qm;
         mutates(a, gen, i, ind, &qm);
-        SlotRec r[UPD_SPL];
-        QState q[UPD_SPL];
-        uint32_t sl[UPD_SPL];
-        bool act[UPD_SPL];
+        SlotRec r[SPL];
+        QState q[SPL];
+        uint32_t sl[SPL];
+        bool act[SPL];
 #pragma unroll
-        for (int u = 0; u < UPD_SPL; ++u) {
-            const uint32_t e = (t % chunks) * UPD_ITEM + (uint32_t)u * 64u + ln;
+        for (int u = 0; u < SPL; ++u) {
+            const uint32_t e = (t % chunks) * ITEM + (uint32_t)u * 64u + ln;
             const uint32_t r_ = e / L, pos = e - r_ * L;
             sl[u] = r_ * LP + ind * L + pos;
             const bool rot = r_ < (uint32_t)a.n;
@@ -659,7 +662,7 @@ __device__ __forceinline__ void update_part_b(const LoopArgs& a, uint32_t gen, u
             }
         }
 #pragma unroll
-        for (int u = 0; u < UPD_SPL; ++u) {
+        for (int u = 0; u < SPL; ++u) {
             if (!act[u]) continue;
             const uint32_t s = sl[u];
             const size_t o = (size_t)i * a.S + s, oq = (size_t)i * a.Q + s;
@@ -733,6 +736,7 @@ __device__ __forceinline__ void update_part_c(const LoopArgs& a, uint32_t b,
     if (lane == 0) a.inst_best_f[i] = best;
 }
 
+template <int SPL>
 __global__ __launch_bounds__(UPD_BLOCK) void qeqea_update_kernel(LoopArgs a, uint64_t gen64,
                                                                  const uint32_t* __restrict__ slots,
                                                                  const uint16_t* __restrict__ gates,
@@ -745,7 +749,7 @@ __global__ __launch_bounds__(UPD_BLOCK) void qeqea_update_kernel(LoopArgs a, uin
     if (blockIdx.x < nC) {
         update_part_c(a, blockIdx.x, gates, angles, f);
     } else if (blockIdx.x < nC + nB) {
-        update_part_b(a, gen, blockIdx.x - nC, per_inst);
+        update_part_b<SPL>(a, gen, blockIdx.x - nC, per_inst);
     } else if (blockIdx.x >= a0) {
         // part A: each XCD takes the circuits the fused kernel ran on it,
         // from the last back (the records touched last are the likeliest to
@@ -1367,8 +1371,10 @@ hipError_t launch_qeqea_update(const LoopArgs& a, uint64_t gen, const uint32_t* 
     // workgroups than the GPU runs at once and the total is close to its mean,
     // so the slack only adds workgroups that find nothing to do: then each
     // instance gets its mean and the busier ones loop.
-    const size_t chunks = ((size_t)a.R * a.L + UPD_ITEM - 1) / UPD_ITEM;
     const double pm = (double)a.thr_pm / 4294967296.0;
+    const bool many = pm * a.P * a.I * (((double)a.R * a.L + 255.0) / 256.0) > 8192.0;
+    const int spl = many ? 4 : 1;
+    const size_t chunks = ((size_t)a.R * a.L + 64 * spl - 1) / (64 * spl);
     const double expect = pm * a.P * chunks, sd = std::sqrt(a.P * pm * (1.0 - pm)) * chunks;
     const double slack = expect * a.I > 8192.0 ? 1.0 : 4.0 * sd + 8.0;
     // (each workgroup serves UPD_WPB items at once, one per wavefront)
@@ -1377,8 +1383,10 @@ hipError_t launch_qeqea_update(const LoopArgs& a, uint64_t gen, const uint32_t* 
     const uint32_t nB = per_inst * (uint32_t)a.I;
     const size_t lds = ((size_t)a.P * sizeof(uint16_t) + 15) & ~(size_t)15;
     const uint32_t a0 = (nC + nB + 7u) & ~7u;
-    qeqea_update_kernel<<<a0 + nA, UPD_BLOCK, lds, s>>>(a, gen, slots, gates, angles, f, nC, nB,
-                                                             per_inst);
+    if (many)
+        qeqea_update_kernel<4><<<a0 + nA, UPD_BLOCK, lds, s>>>(a, gen, slots, gates, angles, f, nC, nB, per_inst);
+    else
+        qeqea_update_kernel<1><<<a0 + nA, UPD_BLOCK, lds, s>>>(a, gen, slots, gates, angles, f, nC, nB, per_inst);
     return hipGetLastError();
 }
 
