@@ -383,6 +383,23 @@ def measure_lds_peak(dev, reps=5):
     return out
 
 
+def measure_record_floor(dev, records, accesses, reps=5):
+    """Random 16-byte record accesses in HBM (the record probe): `accesses`
+    uniform random records of a buffer of `records` records (the size of the
+    workload's slot encoding), read, and read then written back; microseconds
+    per launch (median of `reps`)."""
+    import torch
+    from paper_1809_11134_amd import qe
+    buf = torch.zeros((records, 4), dtype=torch.int32, device=dev)
+    sink = torch.zeros(1, dtype=torch.int32, device=dev)
+    out = {}
+    for mode, name in ((0, "read_us"), (1, "read_write_us")):
+        out[name] = round(_events_us(lambda: qe.probe_records(mode, buf, accesses, sink, salt=mode), reps), 2)
+    del buf
+    torch.cuda.empty_cache()
+    return out
+
+
 def qeqea_context(w, dev, fitness_mode=0):
     import numpy as np
     import torch
@@ -705,6 +722,16 @@ def main():
                        "kernel": "qeqea_update_kernel (segment fitness, elitism, mutation, best circuit)",
                        "kernel_us": round(upd_us, 3), "algorithmic_hbm_bytes_per_launch": upd_bytes,
                        "units": upd_counts}
+    # the part of the update no kernel can avoid with this encoding: each used
+    # slot's record (and a used rotation slot's qutrit record) read and written
+    # back at a random place, timed on a buffer the size of the encoding
+    S = n * n * L * P                # slots per population (n^2 regions of L x P, discrete library)
+    probe = measure_record_floor(dev, I * S, upd_counts["used_slots"] + upd_counts["used_rotation_slots"])
+    roofline_update["record_probe"] = dict(
+        probe, accesses=upd_counts["used_slots"] + upd_counts["used_rotation_slots"], records=I * S,
+        frac_of_update=round(probe["read_write_us"] / upd_us, 4))
+    log(f"record probe: {probe} for the used slots' records -> "
+        f"{probe['read_write_us'] / upd_us:.3f} of the update kernel's time")
     for r, us in ((roofline, fused_us), (roofline_update, upd_us)):
         if r["traffic"] is not None:    # the counted HBM bytes at the measured duration
             r["traffic_gbps"] = round(r["traffic"] / (us * 1e-6) / 1e9, 2)

@@ -443,6 +443,19 @@ qe_status qe_get_schedule_lib(int32_t n_qubits, int32_t lclass, int32_t lib_clas
 qe_status qe_probe_lds(int32_t mode, int32_t workgroups, int32_t iters, uint32_t* sink_dev,
                        double* bytes_host, void* stream);
 
+/* Measurement helper (not part of the method): the rate of random 16-byte
+ * record accesses in HBM, the floor of the QEQEA update (whose slot records
+ * are 16 bytes, one 128-byte line per random access).  Launches `accesses`
+ * threads; thread t takes record h(t) mod count of records_dev (count
+ * 16-byte records of caller-owned device memory; h a hash of t and salt,
+ * uniform over the buffer), reads it (mode 0) or reads it and writes it back
+ * changed (mode 1).  sink_dev: one caller-owned uint32, written only for a
+ * record pattern the caller's buffer does not hold.  count and accesses up
+ * to 2^32 - 1.  Asynchronous on `stream`; time it with events.
+ * QE_ERR_INVALID for a bad mode, NULL pointers or sizes out of range. */
+qe_status qe_probe_records(int32_t mode, void* records_dev, int64_t count, int64_t accesses, uint32_t salt,
+                           uint32_t* sink_dev, void* stream);
+
 const char* qe_last_error(void);
 const char* qe_version(void);
 

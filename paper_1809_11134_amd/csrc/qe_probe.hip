@@ -1,6 +1,9 @@
-// Measurement helper: the LDS bandwidth the chip sustains, the denominator of
-// the LDS rooflines of the per-gate kernels.  Not part of the method.
+// Measurement helpers: the LDS bandwidth the chip sustains, the denominator of
+// the LDS rooflines of the per-gate kernels, and the rate of random 16-byte
+// record accesses in HBM, the floor of the QEQEA update.  Not part of the
+// method.
 //
+// LDS probe:
 // Each workgroup of 256 threads owns 32 KB of LDS (2048 16-byte words, so
 // five workgroups fit a compute unit's 160 KB).  Every wavefront instruction
 // moves 64 consecutive 16-byte words (ds_read_b128 / ds_write_b128, one
@@ -63,7 +66,52 @@ __global__ __launch_bounds__(PROBE_BLOCK) void lds_probe_kernel(int iters, uint3
     sink[blockIdx.x * PROBE_BLOCK + t] = r;
 }
 
+// Random record probe: thread t takes record h(t) mod count of a buffer of
+// 16-byte records (h: a multiply-xorshift hash of t and the salt, uniform
+// over the buffer), reads it, and (MODE 1) writes it back changed -- the
+// access pattern of a slot record in the update, one 128-byte line per
+// record.
+__device__ __forceinline__ uint32_t probe_hash(uint32_t x) {
+    x ^= x >> 16;
+    x *= 0x7FEB352Du;
+    x ^= x >> 15;
+    x *= 0x846CA68Bu;
+    x ^= x >> 16;
+    return x;
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void record_probe_kernel(uint4* __restrict__ rec, uint32_t count,
+                                                           uint32_t n, uint32_t salt,
+                                                           uint32_t* __restrict__ sink) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const uint32_t i = (uint32_t)(((uint64_t)probe_hash(t * 0x9E3779B9u + salt) * count) >> 32);
+    uint4 v = rec[i];
+    if (MODE == 1) {
+        v.w = 0u;
+        v.z += 1u;
+        rec[i] = v;
+    } else if (v.x == 0xFFFFFFFFu && v.y == salt) {
+        sink[0] = v.z ^ v.w;          // (never true for the buffers the caller passes)
+    }
+}
+
 }  // namespace
+
+extern "C" qe_status qe_probe_records(int32_t mode, void* records_dev, int64_t count, int64_t accesses,
+                                      uint32_t salt, uint32_t* sink_dev, void* stream) {
+    if (mode < 0 || mode > 1 || !records_dev || !sink_dev || count < 1 || count > 0xFFFFFFFFll ||
+        accesses < 0 || accesses > 0xFFFFFFFFll)
+        return QE_ERR_INVALID;
+    if (accesses == 0) return QE_OK;
+    const hipStream_t s = (hipStream_t)stream;
+    const uint32_t n = (uint32_t)accesses, blocks = (uint32_t)((accesses + 255) / 256);
+    uint4* rec = static_cast<uint4*>(records_dev);
+    if (mode == 0) record_probe_kernel<0><<<blocks, 256, 0, s>>>(rec, (uint32_t)count, n, salt, sink_dev);
+    else record_probe_kernel<1><<<blocks, 256, 0, s>>>(rec, (uint32_t)count, n, salt, sink_dev);
+    return hipGetLastError() == hipSuccess ? QE_OK : QE_ERR_DEVICE;
+}
 
 extern "C" qe_status qe_probe_lds(int32_t mode, int32_t workgroups, int32_t iters, uint32_t* sink_dev,
                                   double* bytes_host, void* stream) {

@@ -92,6 +92,7 @@ def load():
         "qe_set_schedule": [i32, i32],
         "qe_get_schedule": [i32, P(i32)],
         "qe_probe_lds": [i32, i32, i32, vp, P(ctypes.c_double), vp],
+        "qe_probe_records": [i32, vp, i64, i64, ctypes.c_uint32, vp, vp],
         "qe_create_mixed": [P(Problem), vp, vp, P(vp)],
         "qe_eval_fitness_ws": [P(Batch), i32, vp, vp, vp, vp, ctypes.c_size_t, vp],
         "qe_eval_fitness_noalloc": [P(Batch), i32, vp, vp, vp, vp],
@@ -479,6 +480,14 @@ class Context:
         if n.value:
             _call("qe_state_read", self.handle, which, _ptr(out), ctypes.byref(n), _stream(stream))
         return out
+
+
+def probe_records(mode, records, accesses, sink, salt=0, stream=None):
+    """Launches the random record probe over `records` (a device tensor of
+    16-byte records, e.g. int32 [count, 4]): mode 0 reads, 1 reads and
+    writes back `accesses` random records."""
+    count = records.numel() * records.element_size() // 16
+    _call("qe_probe_records", mode, _ptr(records), count, accesses, salt, _ptr(sink), _stream(stream))
 
 
 def probe_lds(mode, workgroups, iters, sink, stream=None):

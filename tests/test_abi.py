@@ -95,3 +95,19 @@ def test_schedule_roundtrip(lib):
     assert qe.get_schedule(5) == 1 - old
     qe.set_schedule(5, old)
     assert qe.get_schedule(5) == old
+
+
+def test_probes_validate_arguments(lib):
+    """The measurement probes refuse bad modes, NULL buffers and sizes out of
+    range before launching anything."""
+    dummy = ctypes.c_void_p(16)           # never dereferenced: rejected first
+    assert lib.qe_probe_lds(3, 1, 1, dummy, None, None) == qe.QE_ERR_INVALID
+    assert lib.qe_probe_lds(0, 0, 1, dummy, None, None) == qe.QE_ERR_INVALID
+    assert lib.qe_probe_lds(0, 1, 1, None, None, None) == qe.QE_ERR_INVALID
+    assert lib.qe_probe_records(2, dummy, 10, 10, 0, dummy, None) == qe.QE_ERR_INVALID
+    assert lib.qe_probe_records(0, None, 10, 10, 0, dummy, None) == qe.QE_ERR_INVALID
+    assert lib.qe_probe_records(0, dummy, 10, 10, 0, None, None) == qe.QE_ERR_INVALID
+    assert lib.qe_probe_records(0, dummy, 0, 10, 0, dummy, None) == qe.QE_ERR_INVALID
+    assert lib.qe_probe_records(0, dummy, 1 << 32, 10, 0, dummy, None) == qe.QE_ERR_INVALID
+    assert lib.qe_probe_records(1, dummy, 10, -1, 0, dummy, None) == qe.QE_ERR_INVALID
+    assert lib.qe_probe_records(1, dummy, 10, 0, 0, dummy, None) == qe.QE_OK   # nothing to launch
