@@ -216,9 +216,17 @@ def secondary_precision(dev, reps=5):
     out = {"workload": w["name"], "reference": "FP64 path on the GPU", "paths": {}}
     batch, keep, _ = qe.make_batch(g, T32, n=n, L=L, target_stride=0)
     lds = algorithmic_lds_bytes(w["gates"], n)
-    for name, path in (("fp32", qe.PATH_FP32), ("bf16_mfma", qe.PATH_MFMA_BF16),
-                       ("fp16_mfma", qe.PATH_MFMA_FP16), ("bf16_mfma_no_renorm", qe.PATH_MFMA_BF16_RAW),
-                       ("fp16_mfma_no_renorm", qe.PATH_MFMA_FP16_RAW)):
+    lc = 1 if L >= 32 else 0
+    tuned_mb = qe.get_mfma_min_block(n, lc)
+    out["mfma_min_block"] = tuned_mb
+    for name, path, mb in (("fp32", qe.PATH_FP32, tuned_mb), ("bf16_mfma", qe.PATH_MFMA_BF16, tuned_mb),
+                           ("fp16_mfma", qe.PATH_MFMA_FP16, tuned_mb),
+                           ("bf16_mfma_no_renorm", qe.PATH_MFMA_BF16_RAW, tuned_mb),
+                           ("fp16_mfma_no_renorm", qe.PATH_MFMA_FP16_RAW, tuned_mb),
+                           ("bf16_mfma_every_block", qe.PATH_MFMA_BF16, 1)):
+        # (the tuned threshold: groups of fewer gates go gate by gate in FP32;
+        # every_block fuses every group)
+        qe.set_mfma_min_block(n, lc, mb)
         us, fd = _timed_eval(batch, path, P, reps, dev)
         f = fd.cpu().numpy().astype(np.float64)
         err = np.abs(f - f64)
@@ -231,6 +239,7 @@ def secondary_precision(dev, reps=5):
             # the per-gate model's LDS bytes for these circuits against the LDS peak
             out["paths"][name]["algorithmic_lds_bytes"] = lds
             out["paths"][name]["lds_frac"] = lds / (us * 1e-6) / 1e9 / LDS_PEAK_GBPS
+    qe.set_mfma_min_block(n, lc, tuned_mb)
     return out
 
 

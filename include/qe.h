@@ -430,6 +430,20 @@ qe_status qe_set_schedule_lib(int32_t n_qubits, int32_t lclass, int32_t lib_clas
 qe_status qe_get_schedule_lib(int32_t n_qubits, int32_t lclass, int32_t lib_class, int32_t* lds,
                               int32_t* waves, int32_t* cpb);
 
+/* MFMA paths (QE_PATH_MFMA_*): consecutive gates within four wires are fused
+ * into a 16 x 16 block applied on the matrix cores; a group of fewer than
+ * min_block non-identity gates is applied gate by gate in FP32 instead (the
+ * block's construction and its three hi/lo products cost more than a few
+ * row-pair updates).  min_block 1 fuses every group; 65 never fuses (a group
+ * holds at most the 64 gates of a descriptor chunk).  Per width and length
+ * class (lclass as above), process-wide; tuning table lines
+ * "mfma n lclass min_block".  The results stay within the MFMA paths'
+ * stated error (the FP32 gate updates are the more accurate part).
+ * QE_ERR_INVALID for a width outside 1..6, lclass not 0/1, min_block
+ * outside 1..65 or a NULL output. */
+qe_status qe_set_mfma_min_block(int32_t n_qubits, int32_t lclass, int32_t min_block);
+qe_status qe_get_mfma_min_block(int32_t n_qubits, int32_t lclass, int32_t* min_block);
+
 /* Measurement helper (not part of the method): the LDS bandwidth the GPU
  * sustains, the denominator of the per-gate kernels' LDS rooflines.  Launches
  * `workgroups` workgroups of 256 threads, each owning 32 KB of LDS, whose

@@ -93,11 +93,17 @@ qe_status noalloc_scratch(int32_t** out) {
 Sched g_sched[MAX_QUBITS + 1][2][SCHED_CLASSES];
 std::once_flag g_sched_once;
 
+// MFMA paths: fewest non-identity gates of a fused block, per width and
+// length class (1: every group is fused); table lines "mfma n lclass v"
+int g_mfma_min[MAX_QUBITS + 1][2];
+constexpr int MFMA_MIN_BLOCK_MAX = 65;       // above the 64 gates of a chunk: never fuse
+
 void default_schedules() {
     for (int n = 0; n <= MAX_QUBITS; ++n)
         for (int l = 0; l < 2; ++l)
             for (int c = 0; c < SCHED_CLASSES; ++c)
                 g_sched[n][l][c] = n <= 3 ? Sched{0, 1, 4} : (n == 6 ? Sched{1, 4, 1} : Sched{1, 1, 4});
+    for (int n = 0; n <= MAX_QUBITS; ++n) g_mfma_min[n][0] = g_mfma_min[n][1] = 1;
 }
 
 void set_classes(int n, int l, const Sched& v) {
@@ -138,6 +144,14 @@ void load_tune_table() {
     while (std::fgets(line, sizeof line, fh)) {
         if (line[0] == '#') continue;
         if (char* c = std::strchr(line, '#')) *c = 0;
+        {
+            int n = 0, l = 0, v = 0;
+            if (std::sscanf(line, " mfma %d %d %d", &n, &l, &v) == 3) {
+                if (n >= 1 && n <= MAX_QUBITS && (l == 0 || l == 1) && v >= 1 && v <= MFMA_MIN_BLOCK_MAX)
+                    g_mfma_min[n][l] = v;
+                continue;
+            }
+        }
         int n = 0, x1 = 0, x2 = 0, x3 = 0, x4 = 0, x5 = 0;
         const int got = std::sscanf(line, "%d %d %d %d %d %d", &n, &x1, &x2, &x3, &x4, &x5);
         if (got == 6 && (x1 == 0 || x1 == 1) && x2 >= 0 && x2 < SCHED_CLASSES && sched_ok(n, x3, x4, x5)) {
@@ -239,6 +253,11 @@ Sched schedule_for(int n, int L, int lib_class) {
     return g_sched[n][L >= 32 ? 1 : 0][lib_class];
 }
 bool schedule_lds(int n) { return schedule_for(n, 32).lds != 0; }
+int mfma_min_block(int n, int L) {
+    std::call_once(g_sched_once, load_schedule_env);
+    if (n < 1 || n > MAX_QUBITS) return 1;
+    return g_mfma_min[n][L >= 32 ? 1 : 0];
+}
 }  // namespace qe
 
 // ====================================================================== ctx
@@ -416,6 +435,23 @@ qe_status qe_set_schedule_ex(int32_t n, int32_t lclass, int32_t lds, int32_t wav
 
 qe_status qe_get_schedule_ex(int32_t n, int32_t lclass, int32_t* lds, int32_t* waves, int32_t* cpb) {
     return qe_get_schedule_lib(n, lclass, QE_SCHED_DISCRETE, lds, waves, cpb);
+}
+
+qe_status qe_set_mfma_min_block(int32_t n, int32_t lclass, int32_t min_block) {
+    std::call_once(g_sched_once, load_schedule_env);
+    if (n < 1 || n > MAX_QUBITS || (lclass != 0 && lclass != 1) || min_block < 1 ||
+        min_block > MFMA_MIN_BLOCK_MAX)
+        return fail(QE_ERR_INVALID, "width 1..6, lclass 0 or 1, min_block 1..65");
+    g_mfma_min[n][lclass] = min_block;
+    return QE_OK;
+}
+
+qe_status qe_get_mfma_min_block(int32_t n, int32_t lclass, int32_t* min_block) {
+    std::call_once(g_sched_once, load_schedule_env);
+    if (n < 1 || n > MAX_QUBITS || (lclass != 0 && lclass != 1) || !min_block)
+        return fail(QE_ERR_INVALID, "width 1..6, lclass 0 or 1, non-NULL output");
+    *min_block = g_mfma_min[n][lclass];
+    return QE_OK;
 }
 
 qe_status qe_set_schedule_lib(int32_t n, int32_t lclass, int32_t lib_class, int32_t lds, int32_t waves,

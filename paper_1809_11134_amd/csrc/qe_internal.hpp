@@ -36,6 +36,9 @@ struct Sched {
 // the CV body), circuits with angled gates (Ising library).
 enum : int { SCHED_DISCRETE = 0, SCHED_SAMPLED = 1, SCHED_ISING = 2, SCHED_CLASSES = 3 };
 Sched schedule_for(int n, int L, int lib_class = SCHED_DISCRETE);
+// MFMA paths: the fewest non-identity gates a group needs to be fused into a
+// block (smaller groups go gate by gate in FP32), per width and length class
+int mfma_min_block(int n, int L);
 bool schedule_lds(int n);
 
 // Workspace of a mixed-width batch: MIX_WORK_META int32 of item table, then

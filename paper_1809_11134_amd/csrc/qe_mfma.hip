@@ -13,6 +13,12 @@
 // U T^dagger is rescaled to unit norm after each block (the columns of a
 // unitary have unit norm; the rescaling removes the drift of the rounding).
 //
+// A group with fewer than `min_block` non-identity gates is not worth a
+// block (building B and the three products cost more than a few row-pair
+// updates): its gates are applied to U T^dagger one by one in FP32, as the
+// LDS-staged path does.  min_block = 1 fuses every group; the autotuner
+// chooses it per width and length class.
+//
 // Layout: U T^dagger lives in LDS as in the LDS-staged FP32 path, and the
 // W wavefronts of a circuit own 16 columns each, so no barrier is needed
 // between blocks; each wavefront builds its own copy of B in a 2 KB LDS
@@ -118,6 +124,44 @@ __device__ __forceinline__ void build_block(float2* B, uint32_t dv, int first, i
     }
 }
 
+// One gate (descriptor d, wires of the circuit) applied to the wavefront's
+// 16 columns of U T^dagger: lane l takes column jbase + l mod 16 and the row
+// pairs whose pair index is l div 16 modulo 4.
+template <int NQ>
+__device__ __forceinline__ void gate_on_columns(float2* M, uint32_t d, int jbase) {
+    constexpr int N = 1 << NQ, RG = 4;
+    const int lane = (int)lane_id();
+    const int j = jbase + (lane & 15), rg = lane >> 4;
+    const int kind = d & 15;
+    const int tpos = NQ - 1 - (int)((d >> 4) & 15);
+    const int tb = 1 << tpos;
+    const int cb = kind_controlled(kind) ? 1 << (NQ - 1 - (int)((d >> 8) & 15)) : 0;
+    const float r = 0.70710678118654752f;
+#pragma unroll
+    for (int m = 0; m < N / 2 / RG; ++m) {
+        const int i0 = ins0(rg + RG * m, tpos), i1 = i0 | tb;
+        if (cb && !(i0 & cb)) continue;
+        const float2 a = M[i0 * N + j], b = M[i1 * N + j];
+        float2 x = a, y = b;
+        if (kind == KIND_NOT || kind == KIND_CNOT) {
+            x = b; y = a;
+        } else if (kind == KIND_CV || kind == KIND_CVDG) {
+            const float p_ = a.x + b.x, q = a.y + b.y, u = a.x - b.x, v = a.y - b.y;
+            const float2 s0 = make_float2(0.5f * (p_ - v), 0.5f * (q + u));
+            const float2 s1 = make_float2(0.5f * (p_ + v), 0.5f * (q - u));
+            x = kind == KIND_CV ? s0 : s1;
+            y = kind == KIND_CV ? s1 : s0;
+        } else if (kind == KIND_H) {
+            x = make_float2((a.x + b.x) * r, (a.y + b.y) * r);
+            y = make_float2((a.x - b.x) * r, (a.y - b.y) * r);
+        } else {
+            y = make_float2((b.x - b.y) * r, (b.x + b.y) * r);
+        }
+        M[i0 * N + j] = x;
+        M[i1 * N + j] = y;
+    }
+}
+
 template <int NQ, bool FP16>
 __device__ __forceinline__ void apply_block(float2* M, const float2* B, uint32_t wq,
                                             uint32_t ow, int jbase, bool renorm) {
@@ -199,7 +243,7 @@ template <int NQ, bool FP16>
 __global__ __launch_bounds__(64 * (1 << (NQ - 4))) void mfma_kernel(BatchArgs a, float* __restrict__ f,
                                                                    float* __restrict__ g,
                                                                    float* __restrict__ delta,
-                                                                   int renorm) {
+                                                                   int renorm, int min_block) {
     constexpr int N = 1 << NQ, W = N / 16, CW = 16, RG = 64 / CW;
     __shared__ float2 M[N * N];
     __shared__ float2 Bs[W][256];
@@ -224,9 +268,22 @@ __global__ __launch_bounds__(64 * (1 << (NQ - 4))) void mfma_kernel(BatchArgs a,
         const int L = it.L;
         const uint16_t* gp = it.g;
         uint32_t gmask = 0, dv = 0;
-        int gstart = 0, gcnt = 0;
+        int gstart = 0, gcnt = 0, gnon = 0;
         auto flush = [&]() {
             if (gcnt == 0) return;
+            if (gnon < min_block) {
+                // too few gates for a block: one by one, in FP32
+                for (int k = gstart; k < gstart + gcnt; ++k) {
+                    const uint32_t d = __builtin_amdgcn_readlane(dv, k);
+                    if ((d & 15) == KIND_I) continue;
+                    gate_on_columns<NQ>(M, d, wave * CW);
+                    wave_lds_fence();
+                }
+                gmask = 0;
+                gcnt = 0;
+                gnon = 0;
+                return;
+            }
             // window = the group's wires padded with the lowest unused ones;
             // packed 4 bits per entry: wq (window wire of position q), wpos
             // (position of each wire), ow (the other wires, ascending)
@@ -243,6 +300,7 @@ __global__ __launch_bounds__(64 * (1 << (NQ - 4))) void mfma_kernel(BatchArgs a,
             wave_lds_fence();
             gmask = 0;
             gcnt = 0;
+            gnon = 0;
         };
         // groups never straddle a chunk of 64 descriptors (positions within
         // the chunk index the register dv)
@@ -262,6 +320,7 @@ __global__ __launch_bounds__(64 * (1 << (NQ - 4))) void mfma_kernel(BatchArgs a,
                 // a group is a contiguous run of the stream (identities inside are kept)
                 gcnt = k - gstart + 1;
                 gmask |= wm;
+                ++gnon;
             }
             flush();
         }
@@ -315,12 +374,13 @@ hipError_t launch_eval_mfma(const BatchArgs& a, bool fp16, bool renorm, float* f
                             float* delta, hipStream_t s) {
     if (a.B == 0) return hipSuccess;
     const int rn = renorm ? 1 : 0;
+    const int mb = mfma_min_block(a.uniform_n, a.uniform_L > 0 ? a.uniform_L : 32);
     if (a.uniform_n == 5) {
-        if (fp16) mfma_kernel<5, true><<<a.B, 128, 0, s>>>(a, f, g, delta, rn);
-        else mfma_kernel<5, false><<<a.B, 128, 0, s>>>(a, f, g, delta, rn);
+        if (fp16) mfma_kernel<5, true><<<a.B, 128, 0, s>>>(a, f, g, delta, rn, mb);
+        else mfma_kernel<5, false><<<a.B, 128, 0, s>>>(a, f, g, delta, rn, mb);
     } else if (a.uniform_n == 6) {
-        if (fp16) mfma_kernel<6, true><<<a.B, 256, 0, s>>>(a, f, g, delta, rn);
-        else mfma_kernel<6, false><<<a.B, 256, 0, s>>>(a, f, g, delta, rn);
+        if (fp16) mfma_kernel<6, true><<<a.B, 256, 0, s>>>(a, f, g, delta, rn, mb);
+        else mfma_kernel<6, false><<<a.B, 256, 0, s>>>(a, f, g, delta, rn, mb);
     } else {
         return hipErrorInvalidValue;
     }

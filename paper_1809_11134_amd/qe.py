@@ -99,6 +99,8 @@ def load():
         "qe_set_schedule_ex": [i32, i32, i32, i32, i32],
         "qe_get_schedule_ex": [i32, i32, P(i32), P(i32), P(i32)],
         "qe_set_schedule_lib": [i32, i32, i32, i32, i32, i32],
+        "qe_set_mfma_min_block": [i32, i32, i32],
+        "qe_get_mfma_min_block": [i32, i32, P(i32)],
         "qe_get_schedule_lib": [i32, i32, i32, P(i32), P(i32), P(i32)],
     }
     for name, args in sig.items():
@@ -312,6 +314,17 @@ def set_schedule_lib(n, lclass, lib_class, lds, waves, cpb):
     """Schedule of width n, length class lclass, library class lib_class
     (SCHED_DISCRETE, SCHED_SAMPLED, SCHED_ISING)."""
     _call("qe_set_schedule_lib", n, lclass, lib_class, int(lds), int(waves), int(cpb))
+
+
+def set_mfma_min_block(n, lclass, min_block):
+    """MFMA paths: groups of fewer than min_block gates go gate by gate in FP32."""
+    _call("qe_set_mfma_min_block", n, lclass, int(min_block))
+
+
+def get_mfma_min_block(n, lclass):
+    v = ctypes.c_int32(0)
+    _call("qe_get_mfma_min_block", n, lclass, ctypes.byref(v))
+    return v.value
 
 
 def get_schedule_lib(n, lclass, lib_class):

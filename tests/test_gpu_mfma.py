@@ -79,3 +79,33 @@ def test_mfma_rejects_other_widths(dev):
     with pytest.raises(qe.QeError) as e:
         qe.eval_fitness(g, T, n=4, L=3, path=qe.PATH_MFMA_BF16)
     assert e.value.status == qe.QE_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("n", [5, 6])
+@pytest.mark.parametrize("min_block", [1, 3, 65])
+def test_mfma_block_threshold(dev, oracle, n, min_block):
+    """Groups of fewer than min_block gates go gate by gate in FP32 (65: every
+    group, 1: none); the results stay within the path's bounds, circuits of
+    two descriptor chunks included."""
+    saved = {c: qe.get_mfma_min_block(n, c) for c in (0, 1)}
+    try:
+        for c in (0, 1):
+            qe.set_mfma_min_block(n, c, min_block)
+        for L in (7, 70):
+            rng = np.random.default_rng(900 + 10 * n + L + min_block)
+            B = 24
+            tg = inputs.random_target_gates(rng, n, 24, 1)
+            gates = np.concatenate([inputs.random_circuits(rng, B // 2, n, L, 1),
+                                    inputs.planted_population(rng, tg, B // 2, n, L, 1, max_edits=3)])
+            T = oracle.unitary(n, tg)
+            for path in (qe.PATH_MFMA_BF16, qe.PATH_MFMA_FP16):
+                f, g, ref = run(oracle, dev, n, gates, T, path)
+                assert np.all(np.isfinite(f))
+                assert np.abs(f - ref[:, 0]).max() <= BOUNDS[path][0], (L, path)
+                assert np.abs(g - ref[:, 1]).max() <= BOUNDS[path][1], (L, path)
+                if min_block == 65:        # no block at all: the FP32 per-gate error
+                    assert np.abs(f - ref[:, 0]).max() <= 1e-5
+        assert qe.device_errors() == 0
+    finally:
+        for c, v in saved.items():
+            qe.set_mfma_min_block(n, c, v)

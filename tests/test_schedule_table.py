@@ -12,7 +12,8 @@ PROBE = ("import sys; sys.path.insert(0, %r); from paper_1809_11134_amd import q
          "print(' '.join(str(qe.get_schedule(n)) for n in range(1, 7))); "
          "print(' '.join(','.join(str(x) for x in qe.get_schedule_ex(n, c)) for n in range(1, 7) for c in (0, 1))); "
          "print(' '.join(','.join(str(x) for x in qe.get_schedule_lib(n, c, k)) "
-         "for n in range(1, 7) for c in (0, 1) for k in (0, 1, 2)))"
+         "for n in range(1, 7) for c in (0, 1) for k in (0, 1, 2))); "
+         "print(' '.join(str(qe.get_mfma_min_block(n, c)) for n in range(1, 7) for c in (0, 1)))"
          % ROOT)
 
 
@@ -23,7 +24,9 @@ def schedule_with(env_extra):
     env.update(env_extra)
     out = subprocess.run([sys.executable, "-c", PROBE], env=env, capture_output=True, text=True,
                          check=True)
-    a, b, c3 = out.stdout.split("\n")[:3]
+    a, b, c3, c4 = out.stdout.split("\n")[:4]
+    mm = [int(x) for x in c4.split()]
+    schedule_with.mfma = {(n, c): mm[2 * (n - 1) + c] for n in range(1, 7) for c in (0, 1)}
     full = [tuple(int(x) for x in t.split(",")) for t in b.split()]
     by_lib = [tuple(int(x) for x in t.split(",")) for t in c3.split()]
     schedule_with.by_lib = {(n, c, k): by_lib[6 * (n - 1) + 3 * c + k]
@@ -107,3 +110,33 @@ def test_set_schedule_lib_validates():
             qe.get_schedule_lib(5, 2, 0)
     finally:
         qe.set_schedule_lib(5, 1, qe.SCHED_ISING, *saved)
+
+
+def test_mfma_min_block_lines(tmp_path):
+    """"mfma n lclass min_block" lines set the MFMA block threshold; values
+    outside 1..65 are ignored; the default fuses every group."""
+    table = tmp_path / "tune.txt"
+    table.write_text("mfma 6 1 4   # long circuits at n = 6\n"
+                     "mfma 5 0 3\n"
+                     "mfma 5 1 0   # out of range: ignored\n"
+                     "mfma 5 1 66  # out of range: ignored\n"
+                     "5 1 1 1 1\n")
+    schedule_with({"QE_TUNE_TABLE": str(table)})
+    got = schedule_with.mfma
+    assert got[(6, 1)] == 4 and got[(5, 0)] == 3 and got[(5, 1)] == 1 and got[(6, 0)] == 1
+    schedule_with({"QE_TUNE_TABLE": str(tmp_path / "absent.txt")})
+    assert all(v == 1 for v in schedule_with.mfma.values())
+
+
+def test_set_mfma_min_block_validates():
+    import pytest
+    from paper_1809_11134_amd import qe
+    saved = qe.get_mfma_min_block(6, 0)
+    try:
+        qe.set_mfma_min_block(6, 0, 65)
+        assert qe.get_mfma_min_block(6, 0) == 65
+        for bad in ((6, 0, 0), (6, 0, 66), (7, 0, 3), (6, 2, 3)):
+            with pytest.raises(qe.QeError):
+                qe.set_mfma_min_block(*bad)
+    finally:
+        qe.set_mfma_min_block(6, 0, saved)
