@@ -142,6 +142,28 @@ def test_fused_generation_long_circuits(dev, oracle, n, L, P):
     assert qe.device_errors() == 0
 
 
+@pytest.mark.parametrize("n,L,I", [(3, 64, 96), (5, 40, 72)])
+def test_many_populations_update_bitexact(dev, oracle, n, L, I):
+    # enough mutating individuals per launch that the update serves four
+    # slots per lane in part B (the layout of the n = 5 benchmark), with the
+    # qutrit-mode split between parts A and B; state bit-exact with the oracle
+    P, seed, pm = 64, 8080 + n, 0.5
+    qe.device_errors()
+    ctx, T = qeqea_ctx(dev, oracle, n, L, P, I, seed, pm=pm)
+    for gen in range(3):
+        o = to_oracle(oracle, ctx, gpu_state(ctx))
+        rs, rg = o.sample(gen)
+        f = ctx.generation(gen)
+        fh = f.cpu().numpy()
+        ref = np.concatenate([oracle.eval_batch(np.full(P, n, np.int8), np.arange(P + 1, dtype=np.int32) * L,
+                                                rg[i * P:(i + 1) * P].ravel(), np.zeros(P, np.int64), T[i])[:, 0]
+                              for i in range(I)])
+        assert np.abs(fh - ref).max() <= 1e-5, gen
+        o.update(gen, pm, float(np.pi / 4), rs, fh)
+        assert_same_state(o, gpu_state(ctx))
+    assert qe.device_errors() == 0
+
+
 @pytest.mark.parametrize("n", [4, 6])
 def test_sample_eval_then_update_equals_generation(dev, oracle, n):
     L, P, I, seed = 17, 48, 3, 4040 + n
