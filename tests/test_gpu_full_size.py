@@ -7,7 +7,8 @@ times, on its seeded synthetic workloads:
   fitness of every circuit within the FP32 bar;
 * n=5 QEQEA, 1024 populations x 64 circuits x 40 gates: the fused kernel's
   first generation against the oracle's sampling (bit for bit) and fitness
-  (every circuit), and against the evaluation kernel (bit for bit);
+  (every circuit), and against the evaluation kernel (bit for bit); then the
+  update, the whole 1.9 GB encoding state bit for bit against the oracle's;
 * n=6, 8192 circuits x 48 gates: the FP32 path on every circuit within the
   FP32 bar, the BF16 and FP16 hi+lo MFMA paths within their stated bounds;
 * 16384 circuits of widths 3..6 and lengths 8..64 in one mixed-width launch
@@ -108,9 +109,19 @@ def test_qeqea_n5_bench_first_generation(dev, oracle):
     assert np.array_equal(gates.cpu().numpy().view(np.uint16), rg)
     assert torch.equal(f, ctx.eval_population(gates))
     assert np.abs(f.cpu().numpy() - oracle_fitness(oracle, n, rg, T, P)).max() <= TOL32
+    # the update at full size (many populations: four slots per lane in part
+    # B), the whole encoding state bit for bit against the oracle's update
+    ctx.update(0, slots, gates, f)
+    torch.cuda.synchronize()
+    o.update(0, 0.1, float(np.float32(math.pi / 4)), rs, f.cpu().numpy())
+    for k, ref in (("theta", o.theta), ("best_theta", o.best_theta), ("best_f", o.best_f),
+                   ("qutrit", o.qutrit), ("best_qutrit", o.best_qutrit)):
+        got = ctx.state(k).cpu().numpy()
+        assert np.array_equal(got.view(np.uint32), np.asarray(ref).view(np.uint32)), k
+    del o
     # a few graph generations on top: finite fitness in [0, 1], FP64 elites agree
     hist = torch.empty((3, I * P), dtype=torch.float32, device=dev)
-    ctx.run_graph(0, 3, hist)
+    ctx.run_graph(1, 3, hist)
     hh = hist.cpu().numpy()
     assert np.all(np.isfinite(hh)) and hh.min() >= 0.0 and hh.max() <= 1.0
     idx, f64 = ctx.elite_recheck(None, hist[2], 32)
