@@ -7,8 +7,10 @@ times, on its seeded synthetic workloads:
   fitness of every circuit within the FP32 bar;
 * n=5 QEQEA, 1024 populations x 64 circuits x 40 gates: the fused kernel's
   first generation against the oracle's sampling (bit for bit) and fitness
-  (every circuit), and against the evaluation kernel (bit for bit); then the
-  update, the whole 1.9 GB encoding state bit for bit against the oracle's;
+  (every circuit), and against the evaluation kernel (bit for bit); the FP64
+  re-check of every population's 32 best against the oracle's FP64 fitness;
+  then the update, the whole 1.9 GB encoding state bit for bit against the
+  oracle's;
 * n=6, 8192 circuits x 48 gates: the FP32 path on every circuit within the
   FP32 bar, the BF16 and FP16 hi+lo MFMA paths within their stated bounds;
 * 16384 circuits of widths 3..6 and lengths 8..64 in one mixed-width launch
@@ -108,7 +110,13 @@ def test_qeqea_n5_bench_first_generation(dev, oracle):
     assert np.array_equal(slots.cpu().numpy().view(np.uint32), rs)
     assert np.array_equal(gates.cpu().numpy().view(np.uint16), rg)
     assert torch.equal(f, ctx.eval_population(gates))
-    assert np.abs(f.cpu().numpy() - oracle_fitness(oracle, n, rg, T, P)).max() <= TOL32
+    ref = oracle_fitness(oracle, n, rg, T, P)
+    assert np.abs(f.cpu().numpy() - ref).max() <= TOL32
+    # the FP64 re-check of every population's 32 best at full size (the kernel
+    # the benchmark times) against the oracle's FP64 fitness of those circuits
+    idx, f64 = ctx.elite_recheck(gates, f, 32)
+    rows = (np.arange(I)[:, None] * P + idx.cpu().numpy()).ravel()
+    assert np.abs((1 - f64.cpu().numpy().ravel()) ** 2 - (1 - ref[rows]) ** 2).max() <= 1e-12
     # the update at full size (many populations: four slots per lane in part
     # B), the whole encoding state bit for bit against the oracle's update
     ctx.update(0, slots, gates, f)
