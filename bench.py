@@ -509,7 +509,10 @@ def update_algorithmic_bytes(ctx, gen, dev):
     best fitness and writes the qutrit (52 B, n*L slots), the two modes
     equiprobable; the generation's best circuit reads the P fitness values
     (4 B each).  Counts come from the generation's own slots and decision
-    bitmaps (it is sampled here, then updated)."""
+    bitmaps (it is sampled here, then updated).  Returns the update kernel's
+    bytes (the elitism of the shared slots, the mutation, the best circuit),
+    the bytes of the elitism the fused kernel commits (the slots one circuit
+    alone used) and the counts."""
     import numpy as np
     import torch
     IP = ctx.I * ctx.P
@@ -524,16 +527,26 @@ def update_algorithmic_bytes(ctx, gen, dev):
     Q = ctx.n * ctx.L * ctx.P
     R = ctx.n + ctx.n * (ctx.n - 1)
     inst = np.arange(ctx.I, dtype=np.int64)[:, None] * (R * ctx.L * ctx.P)
-    used = np.unique((sl + inst).ravel())
-    used_rot = int(np.count_nonzero((used % (R * ctx.L * ctx.P)) < Q))
+    used, uses = np.unique((sl + inst).ravel(), return_counts=True)
+    rot = (used % (R * ctx.L * ctx.P)) < Q
+    used_rot = int(np.count_nonzero(rot))
+    # slots one circuit alone used: their elitism is committed by the fused
+    # kernel (populations small enough for the shared-slot search)
+    dedup = ctx.P * ctx.L <= 4096 and ctx.L <= 256
+    alone = (uses == 1) if dedup else np.zeros(used.size, bool)
+    alone_n, alone_rot = int(alone.sum()), int((alone & rot).sum())
     mw = (ctx.P + 31) // 32
     m = masks.cpu().numpy().view(np.uint32).reshape(2, ctx.I, mw)[gen & 1]
     bits = np.unpackbits(m.view(np.uint8), bitorder="little").reshape(ctx.I, mw * 32)[:, :ctx.P]
     mutated = int(bits.sum())
     per_mut = 0.5 * (R * ctx.L * 12.0) + 0.5 * (ctx.n * ctx.L * 52.0)
-    total = used.size * 24.0 + used_rot * 72.0 + mutated * per_mut + IP * 4.0
-    return total, {"used_slots": int(used.size), "used_rotation_slots": used_rot,
-                   "mutated_individuals": mutated}
+    update_bytes = ((used.size - alone_n) * 24.0 + (used_rot - alone_rot) * 72.0 + mutated * per_mut
+                    + IP * 4.0)
+    commit_bytes = alone_n * 24.0 + alone_rot * 72.0
+    return update_bytes, commit_bytes, {"used_slots": int(used.size), "used_rotation_slots": used_rot,
+                                        "committed_by_fused_kernel": alone_n,
+                                        "committed_rotation_slots": alone_rot,
+                                        "mutated_individuals": mutated}
 
 
 def secondary_qeqea_n4(dev, K, W):
@@ -722,25 +735,27 @@ def main():
                 "alu_frac": round(alu / FP32_VECTOR_PEAK_TFLOPS, 6)}
     log(f"fused kernel: {fused_us:.2f} us/launch, {achieved:.1f} GB/s algorithmic LDS "
         f"({achieved / LDS_PEAK_GBPS:.3f} of the measured peak)")
-    upd_bytes, upd_counts = update_algorithmic_bytes(ctx, gen, dev)
+    upd_bytes, commit_bytes, upd_counts = update_algorithmic_bytes(ctx, gen, dev)
+    roofline["commit_hbm_bytes_per_launch"] = commit_bytes
+    roofline["commit_note"] = ("elitism of the slots one circuit alone used, committed by this kernel "
+                               "(24 B per slot, 72 B more per rotation slot)")
     gen += 1
     upd_ach = upd_bytes / (upd_us * 1e-6) / 1e9
     roofline_update = {"bound": "hbm", "achieved": round(upd_ach, 2), "peak": HBM_PEAK_GBPS,
                        "unit": "GB/s", "frac": round(upd_ach / HBM_PEAK_GBPS, 6),
                        "traffic": traffic_from_profiles("qeqea_update_n5", src),
-                       "kernel": "qeqea_update_kernel (segment fitness, elitism, mutation, best circuit)",
+                       "kernel": "qeqea_update_kernel (elitism of the slots several circuits used, mutation, best circuit)",
                        "kernel_us": round(upd_us, 3), "algorithmic_hbm_bytes_per_launch": upd_bytes,
                        "units": upd_counts}
-    # the part of the update no kernel can avoid with this encoding: each used
-    # slot's record (and a used rotation slot's qutrit record) read and written
-    # back at a random place, timed on a buffer the size of the encoding
+    # the elitism's record work at random places (each used slot's record, and
+    # a used rotation slot's qutrit record, read and written back), timed on a
+    # buffer the size of the encoding; the fused kernel does most of it now,
+    # on records it has just gathered
     S = n * n * L * P                # slots per population (n^2 regions of L x P, discrete library)
-    probe = measure_record_floor(dev, I * S, upd_counts["used_slots"] + upd_counts["used_rotation_slots"])
-    roofline_update["record_probe"] = dict(
-        probe, accesses=upd_counts["used_slots"] + upd_counts["used_rotation_slots"], records=I * S,
-        frac_of_update=round(probe["read_write_us"] / upd_us, 4))
-    log(f"record probe: {probe} for the used slots' records -> "
-        f"{probe['read_write_us'] / upd_us:.3f} of the update kernel's time")
+    acc = upd_counts["used_slots"] + upd_counts["used_rotation_slots"]
+    probe = measure_record_floor(dev, I * S, acc)
+    roofline_update["record_probe"] = dict(probe, accesses=acc, records=I * S)
+    log(f"record probe: {probe} for {acc} records; update kernel {upd_us:.1f} us")
     for r, us in ((roofline, fused_us), (roofline_update, upd_us)):
         if r["traffic"] is not None:    # the counted HBM bytes at the measured duration
             r["traffic_gbps"] = round(r["traffic"] / (us * 1e-6) / 1e9, 2)

@@ -314,20 +314,29 @@ qe_status qe_update(qe_ctx* ctx, uint64_t gen, const uint32_t* slots_dev,
                     const uint16_t* gates_dev, const uint32_t* angles_dev, const float* f_dev,
                     void* stream);
 
-/* sample + eval + update of generation `gen` in two kernel launches (QEQEA)
- * or two (GA); f_dev [I*P] receives the generation's fitness (may be NULL).
- * Results equal qe_sample, qe_eval_population and qe_update in sequence. */
+/* sample + eval + update of generation `gen` (QEQEA: three kernel launches,
+ * the shared-slot search, the fused kernel and the update; GA: two); f_dev
+ * [I*P] receives the generation's fitness (may be NULL).  Results equal
+ * qe_sample, qe_eval_population and qe_update in sequence. */
 qe_status qe_generation(qe_ctx* ctx, uint64_t gen, float* f_dev, void* stream);
 
-/* The first half of qe_generation for QEQEA, one kernel launch (the one
- * qe_generation and qe_run_graph launch): circuit construction (as
- * qe_sample, into gates_dev, and into slots_dev unless it is NULL) fused with
- * the fitness evaluation (f_dev), the segment-fitness maximum that qe_update
- * starts from and the generation's mutation decisions (Sec. IV-F).
- * qe_update(gen, slots, gates, angles, f) afterwards completes the
- * generation with the same result as qe_generation; with slots_dev NULL
- * there, it is the second kernel launch of qe_generation alone.  angles_dev
- * as in qe_sample.  QEQEA only. */
+/* The first half of qe_generation for QEQEA (the launches qe_generation and
+ * qe_run_graph make before the update): circuit construction (as qe_sample,
+ * into gates_dev, and into slots_dev unless it is NULL) fused with the
+ * fitness evaluation (f_dev), the segment fitness (Sec. IV-E.1) and the
+ * generation's mutation decisions (Sec. IV-F).  For populations of at most
+ * 4096 (circuit, position) entries and 256 positions, a search for the slots
+ * that more than one circuit uses runs first, and the fused kernel commits
+ * the elitism of every slot its circuit alone used (its segment fitness is
+ * that circuit's fitness, final as soon as the circuit is evaluated); the
+ * shared slots keep the largest fitness for qe_update.  The encoding is then
+ * partly updated: sampling generation gen again (qe_sample) sees the
+ * committed states, so sample it before.  qe_update(gen, slots, gates,
+ * angles, f) afterwards completes the generation with the same result as
+ * qe_generation (with slots_dev it runs the elitism of every slot, which
+ * leaves a committed slot as it is); with slots_dev NULL there, it is the
+ * last launch of qe_generation alone.  angles_dev as in qe_sample.  QEQEA
+ * only. */
 qe_status qe_sample_eval(qe_ctx* ctx, uint64_t gen, uint32_t* slots_dev, uint16_t* gates_dev,
                          uint32_t* angles_dev, float* f_dev, void* stream);
 

@@ -378,9 +378,11 @@ BatchArgs mixed_batch(const qe_ctx* c, const uint16_t* gates) {
 
 qe_status enqueue_generation(qe_ctx* c, const LoopArgs& a, uint64_t gen, float* f, hipStream_t s) {
     if (c->prob.algorithm == QE_ALG_QEQEA) {
-        // the update draws each entry's slot again instead of reading it
+        // the update draws each entry's slot again instead of reading it;
+        // with the shared-slot flags only the shared slots go through it
+        QE_HIP(launch_dedup(a, gen, s));
         QE_HIP(launch_qeqea_fused(a, gen, nullptr, c->gates, c->angles, f, true, s));
-        QE_HIP(launch_qeqea_update(a, gen, nullptr, c->gates, c->angles, f, s));
+        QE_HIP(launch_qeqea_update(a, gen, nullptr, c->gates, c->angles, f, s, a.dup));
     } else {
         QE_HIP(launch_ga_copy(a, gen, c->gates, s));
         if (c->mixed) QE_HIP(launch_mix_eval(mixed_batch(c, c->gates), c->mix_order, f, nullptr, nullptr, s));
@@ -698,6 +700,9 @@ qe_status create_impl(const qe_problem* p_in, const int32_t* inst_n, const int32
     if (p->algorithm == QE_ALG_QEQEA) {
         ALLOC(a.slot, I * S);
         ALLOC(a.qrec, I * Q);
+        // populations small enough for the shared-slot search in LDS: the
+        // fused kernel commits the elitism of the slots one circuit alone used
+        if (P * L <= (size_t)DEDUP_MAX_ENTRIES && L <= 256) ALLOC(a.dup, I * P * L);
         ALLOC(a.su3_tab, (size_t)4 * SU3_TAB);
     } else {
         ALLOC(a.genomes[0], (size_t)genes);
@@ -914,7 +919,11 @@ qe_status qe_update(qe_ctx* c, uint64_t gen, const uint32_t* slots, const uint16
             QE_TRY(prepare_decisions(c, gen, 1, s));
             QE_HIP(launch_mutation_decisions(c->la, gen, s));
         }
-        QE_HIP(launch_qeqea_update(c->la, gen, slots, gates, is_ising(c) ? angles : nullptr, f, s));
+        // after qe_sample_eval with no slot array the fused kernel has committed
+        // the unshared slots (the flags say which); with slots_dev every entry's
+        // slot has its key (the elitism is the same, run again, for those)
+        QE_HIP(launch_qeqea_update(c->la, gen, slots, gates, is_ising(c) ? angles : nullptr, f, s,
+                                   (fused && !slots) ? c->la.dup : nullptr));
     } else {
         QE_HIP(launch_ga_update(c->la, gen, f, s));
     }
@@ -936,6 +945,7 @@ qe_status qe_sample_eval(qe_ctx* c, uint64_t gen, uint32_t* slots, uint16_t* gat
     if (is_ising(c) && !angles) return fail(QE_ERR_INVALID, "the Ising library needs angles_dev");
     // the generation's mutation decisions are drawn here, as in qe_generation
     QE_TRY(prepare_decisions(c, gen, 1, (hipStream_t)stream));
+    QE_HIP(launch_dedup(c->la, gen, (hipStream_t)stream));
     QE_HIP(launch_qeqea_fused(c->la, gen, slots, gates, is_ising(c) ? angles : nullptr, f, true,
                               (hipStream_t)stream));
     c->fused_gen = (int64_t)gen;

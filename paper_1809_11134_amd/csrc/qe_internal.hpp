@@ -148,7 +148,13 @@ struct LoopArgs {
     const int64_t* inst_goff;
     const int64_t* inst_toff;
     int64_t genes;                     // genes per genome buffer (all populations)
+    // QEQEA, populations of at most DEDUP_MAX_ENTRIES entries (P * L) of at
+    // most 256 positions: per (circuit, position) entry of the current
+    // generation, 1 if another circuit uses the same slot (null otherwise)
+    uint8_t* dup;
 };
+constexpr int DEDUP_MAX_ENTRIES = 4096;
+constexpr int DEDUP_TABLE = 2 * DEDUP_MAX_ENTRIES;
 
 // loop.hip
 hipError_t launch_qeqea_init(const LoopArgs& a, hipStream_t s);
@@ -168,9 +174,14 @@ hipError_t launch_scatter(const LoopArgs& a, uint64_t gen, const uint32_t* slots
                           hipStream_t s);
 // slots: the generation's slot indices [I*P*L], or NULL to draw them again
 // from the SAMPLE stream (the internal generation path).
+// shared: the flags of launch_dedup for a generation sampled by the fused
+// kernel (whose unshared slots it committed), or null (every entry's slot
+// goes through the keys)
 hipError_t launch_qeqea_update(const LoopArgs& a, uint64_t gen, const uint32_t* slots,
                                const uint16_t* gates, const uint32_t* angles, const float* f,
-                               hipStream_t s);
+                               hipStream_t s, const uint8_t* shared = nullptr);
+// the shared-slot flags of generation gen (a.dup), before its fused kernel
+hipError_t launch_dedup(const LoopArgs& a, uint64_t gen, hipStream_t s);
 hipError_t launch_mutmask_clear(const LoopArgs& a, hipStream_t s);
 // Dense copy of one field of the encoding state (which: 0 theta, 1 qutrit
 // amplitudes, 2 best_f, 3 best_theta, 4 best qutrit amplitudes).

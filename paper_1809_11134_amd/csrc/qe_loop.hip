@@ -239,6 +239,9 @@ __device__ __forceinline__ void clear_next_mask(const LoopArgs& a, uint32_t gen,
     if ((ind & 31u) == 0) mask_of(a, gen + 1u, i)[ind >> 5] = 0u;
 }
 
+// Elitism of a slot that one circuit alone used (defined with the update).
+__device__ void commit_alone(const LoopArgs& a, uint32_t i, uint32_t s, float v);
+
 // -------------------------------------------- population evaluation (FP32)
 // One circuit per wavefront (register / per-lane layouts, and the LDS layout
 // with W = 1) or per workgroup (LDS layout, W > 1); the target is the
@@ -267,8 +270,12 @@ __device__ __forceinline__ void eval_circuit(const LoopArgs& a, uint32_t gen, ui
     if (SAMPLE && decide && writer && lane == 0) clear_next_mask(a, gen, i, k);
     constexpr int KEEP = 4;                 // chunks of 64 slots kept for the scatter
     uint32_t kept[KEEP];
+    bool alone[KEEP];                       // no other circuit of the generation uses the slot
 #pragma unroll
-    for (int c = 0; c < KEEP; ++c) kept[c] = 0xFFFFFFFFu;
+    for (int c = 0; c < KEEP; ++c) { kept[c] = 0xFFFFFFFFu; alone[c] = false; }
+    // (the flags exist only for sampled generations whose duplicates were
+    // found beforehand, and then L <= KEEP * 64)
+    auto is_alone = [&](int p) -> bool { return a.dup && a.dup[(size_t)ci * L + p] == 0; };
     using SrcT = std::conditional_t<ISING, uint2, uint32_t>;
     auto own = [&](int ch) -> SrcT {
         const int p = ch * 64 + lane;
@@ -291,9 +298,10 @@ __device__ __forceinline__ void eval_circuit(const LoopArgs& a, uint32_t gen, ui
             return SrcT{};
         }
         const uint32_t s = slot_of_draw(a, w, (uint32_t)p);
+        const bool al = is_alone(p);
 #pragma unroll
         for (int c = 0; c < KEEP; ++c)
-            if (c == ch) kept[c] = s;
+            if (c == ch) { kept[c] = s; alone[c] = al; }
         if constexpr (ISING) {
             const uint2 g = decode_ising(a, gen, i, s);
             if (writer) {
@@ -354,13 +362,18 @@ __device__ __forceinline__ void eval_circuit(const LoopArgs& a, uint32_t gen, ui
         if (!ok) atomicOr(a.err, (uint32_t)QE_DEVERR_DESC);
         else if (!(fv == fv)) atomicOr(a.err, (uint32_t)QE_DEVERR_NUMERIC);
     }
-    // segment fitness: every slot this circuit used keeps the largest key
+    // segment fitness: a slot no other circuit of the generation uses takes
+    // this circuit's fitness as its segment fitness and its elitism now
+    // (nothing else reads or writes it before the update); every other slot
+    // keeps the largest key, for the update's elitism
     if (SAMPLE && writer && fv >= 0.0f) {
         const uint32_t key = seg_key(fv);
 #pragma unroll
         for (int c = 0; c < KEEP; ++c) {
             const int p = c * 64 + lane;
-            if (p < L) atomicMax(&a.slot[(size_t)i * a.S + kept[c]].key, key);
+            if (p >= L) continue;
+            if (alone[c]) commit_alone(a, i, kept[c], fv);
+            else atomicMax(&a.slot[(size_t)i * a.S + kept[c]].key, key);
         }
         for (int p = KEEP * 64 + lane; p < L; p += 64) {
             const uint32_t s = sample_slot(a, gen, i, k, (uint32_t)p);
@@ -504,6 +517,25 @@ __device__ __forceinline__ bool elitism(float v, SlotRec& r, QState& q, bool rot
     return false;
 }
 
+// The elitism of a slot that no other circuit of the generation used, with
+// its circuit's fitness v as the segment fitness: run by that circuit as soon
+// as its fitness is known.  Only what changes is written; the key stays 0, so
+// the update sees the slot as unused.
+__device__ __forceinline__ void commit_alone(const LoopArgs& a, uint32_t i, uint32_t s, float v) {
+    const size_t o = (size_t)i * a.S + s, oq = (size_t)i * a.Q + s;
+    const bool rot = s < a.Q;
+    SlotRec r = a.slot[o];
+    QState q{};
+    if (rot) q = load_qstate(a.qrec + oq);
+    const uint32_t th = r.theta;
+    bool qsame = true;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) qsame = qsame && __float_as_uint(q.q[c]) == __float_as_uint(q.bq[c]);
+    const bool better = elitism(v, r, q, rot);
+    if (better || r.theta != th) a.slot[o] = r;
+    if (rot && !qsame) store_qstate(a.qrec + oq, q);
+}
+
 // Mutation of one slot (Sec. IV-F) with its own draw; segFit is the slot's
 // best fitness (0 if never used).  Qubit mode: theta +- floor((1 - segFit) *
 // range); qutrit mode: one SU(3) parameter step.
@@ -521,6 +553,58 @@ __device__ __forceinline__ void mutate_state(const LoopArgs& a, uint32_t gen, ui
         const float x = u * om;
         const int ai = (int)floorf(x * 4096.0f);
         su3_step(q.q, j, ai, a.su3_tab);
+    }
+}
+
+// Which slots of a generation more than one circuit uses: one workgroup per
+// population draws every (circuit, position) entry's slot again and counts
+// the slots in an LDS hash table (open addressing, at most half full), then
+// writes a flag per entry, 1 where the entry's slot is shared.  The fused
+// kernel commits the elitism of the unshared slots itself (commit_alone) and
+// raises the key of the shared ones; the update handles only those.  Used
+// when a population has at most DEDUP_MAX_ENTRIES entries of at most 256
+// positions.
+__device__ __forceinline__ uint32_t dedup_hash(uint32_t x) {
+    x ^= x >> 16;
+    x *= 0x45D9F3Bu;
+    x ^= x >> 16;
+    return x;
+}
+
+__global__ __launch_bounds__(256) void dedup_kernel(LoopArgs a, uint64_t gen64) {
+    constexpr uint32_t EMPTY = 0xFFFFFFFFu, MASK = DEDUP_TABLE - 1;
+    constexpr int PER = DEDUP_MAX_ENTRIES / 256;
+    __shared__ uint32_t keys[DEDUP_TABLE];
+    __shared__ uint32_t cnt[DEDUP_TABLE];
+    const uint32_t gen = gen_of(a, gen64);
+    const uint32_t i = blockIdx.x, L = (uint32_t)a.L, LP = L * (uint32_t)a.P;
+    for (uint32_t t = threadIdx.x; t < DEDUP_TABLE; t += 256) { keys[t] = EMPTY; cnt[t] = 0u; }
+    __syncthreads();
+    uint32_t sl[PER], at[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const uint32_t e = (uint32_t)u * 256u + threadIdx.x;
+        sl[u] = EMPTY;
+        at[u] = 0u;
+        if (e >= LP) continue;
+        const uint32_t s = sample_slot(a, gen, i, e / L, e % L);
+        uint32_t h = dedup_hash(s) & MASK;
+        // the table holds at most LP <= DEDUP_TABLE / 2 keys: a free entry is
+        // always found
+        while (true) {
+            const uint32_t prev = atomicCAS(&keys[h], EMPTY, s);
+            if (prev == EMPTY || prev == s) break;
+            h = (h + 1u) & MASK;
+        }
+        atomicAdd(&cnt[h], 1u);
+        sl[u] = s;
+        at[u] = h;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const uint32_t e = (uint32_t)u * 256u + threadIdx.x;
+        if (e < LP) a.dup[(size_t)i * LP + e] = cnt[at[u]] > 1u ? 1 : 0;
     }
 }
 
@@ -545,9 +629,12 @@ constexpr int UPD_WPB = UPD_BLOCK / 64;   // wavefronts per workgroup
 // sampling, which saves a dependent load); otherwise it is read.
 __device__ __forceinline__ void update_part_a(const LoopArgs& a, uint32_t gen, uint32_t idx,
                                               const uint32_t* __restrict__ slots,
-                                              const float* __restrict__ f) {
+                                              const float* __restrict__ f,
+                                              const uint8_t* __restrict__ shared) {
     const uint32_t L = (uint32_t)a.L, LP = L * (uint32_t)a.P;
     if (idx >= (uint32_t)a.I * LP) return;
+    // (a slot no other circuit used was committed by the fused kernel)
+    if (shared && shared[idx] == 0) return;
     const uint32_t i = idx / LP, k = (idx % LP) / L;
     const float fk = f[idx / L];                // the entry's circuit's fitness
     const uint32_t s = slots ? slots[idx] : sample_slot(a, gen, i, k, idx % L);
@@ -743,7 +830,8 @@ __global__ __launch_bounds__(UPD_BLOCK) void qeqea_update_kernel(LoopArgs a, uin
                                                                  const uint32_t* __restrict__ angles,
                                                                  const float* __restrict__ f,
                                                                  uint32_t nC, uint32_t nB,
-                                                                 uint32_t per_inst) {
+                                                                 uint32_t per_inst,
+                                                                 const uint8_t* __restrict__ shared) {
     const uint32_t gen = gen_of(a, gen64);
     const uint32_t a0 = (nC + nB + 7u) & ~7u;   // part A starts at a multiple of 8
     if (blockIdx.x < nC) {
@@ -756,7 +844,7 @@ __global__ __launch_bounds__(UPD_BLOCK) void qeqea_update_kernel(LoopArgs a, uin
         // still be cached)
         const uint32_t nA = gridDim.x - a0;
         const uint32_t blk = nA - 1u - xcd_swizzle(blockIdx.x - a0, nA);
-        update_part_a(a, gen, blk * UPD_BLOCK + threadIdx.x, slots, f);
+        update_part_a(a, gen, blk * UPD_BLOCK + threadIdx.x, slots, f, shared);
     }
 }
 
@@ -1359,9 +1447,15 @@ hipError_t launch_scatter(const LoopArgs& a, uint64_t gen, const uint32_t* slots
     return hipGetLastError();
 }
 
+hipError_t launch_dedup(const LoopArgs& a, uint64_t gen, hipStream_t s) {
+    if (!a.dup) return hipSuccess;
+    dedup_kernel<<<a.I, 256, 0, s>>>(a, gen);
+    return hipGetLastError();
+}
+
 hipError_t launch_qeqea_update(const LoopArgs& a, uint64_t gen, const uint32_t* slots,
                                const uint16_t* gates, const uint32_t* angles, const float* f,
-                               hipStream_t s) {
+                               hipStream_t s, const uint8_t* shared) {
     if (a.P > UPD_MAX_P) return hipErrorInvalidValue;
     const uint32_t nC = blocks((size_t)a.I * part_c_waves(a.P), UPD_BLOCK / 64);
     const uint32_t nA = blocks((size_t)a.I * a.P * a.L, UPD_BLOCK);
@@ -1384,9 +1478,11 @@ hipError_t launch_qeqea_update(const LoopArgs& a, uint64_t gen, const uint32_t* 
     const size_t lds = ((size_t)a.P * sizeof(uint16_t) + 15) & ~(size_t)15;
     const uint32_t a0 = (nC + nB + 7u) & ~7u;
     if (many)
-        qeqea_update_kernel<4><<<a0 + nA, UPD_BLOCK, lds, s>>>(a, gen, slots, gates, angles, f, nC, nB, per_inst);
+        qeqea_update_kernel<4><<<a0 + nA, UPD_BLOCK, lds, s>>>(a, gen, slots, gates, angles, f, nC, nB, per_inst,
+                                                               shared);
     else
-        qeqea_update_kernel<1><<<a0 + nA, UPD_BLOCK, lds, s>>>(a, gen, slots, gates, angles, f, nC, nB, per_inst);
+        qeqea_update_kernel<1><<<a0 + nA, UPD_BLOCK, lds, s>>>(a, gen, slots, gates, angles, f, nC, nB, per_inst,
+                                                               shared);
     return hipGetLastError();
 }
 

@@ -237,8 +237,8 @@ def test_ising_sample_eval_graph_and_best(dev, oracle, n):
     b, _ = ising_ctx(dev, oracle, n, L, P, I, seed)
     c, _ = ising_ctx(dev, oracle, n, L, P, I, seed)
     for gen in range(G):
+        rs, rg, ra = a.sample(gen)                 # (before qe_sample_eval, which commits)
         slots, gates, angles, f = a.sample_eval(gen)
-        rs, rg, ra = a.sample(gen)
         assert torch.equal(slots, rs) and torch.equal(gates, rg) and torch.equal(angles, ra)
         a.update(gen, slots, gates, f, angles=angles)
         assert torch.equal(f, b.generation(gen))

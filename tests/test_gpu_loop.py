@@ -170,8 +170,10 @@ def test_sample_eval_then_update_equals_generation(dev, oracle, n):
     a, _ = qeqea_ctx(dev, oracle, n, L, P, I, seed)
     b, _ = qeqea_ctx(dev, oracle, n, L, P, I, seed)
     for gen in range(4):
-        slots, gates, f = a.sample_eval(gen)
+        # (qe_sample before qe_sample_eval: the latter already commits the
+        # elitism of the slots one circuit alone used)
         rs, rg = a.sample(gen)
+        slots, gates, f = a.sample_eval(gen)
         assert torch.equal(slots, rs) and torch.equal(gates, rg)
         a.update(gen, slots, gates, f)
         fb = b.generation(gen)
