@@ -52,6 +52,23 @@ struct SlotState {
     float2 q0, q1, q2;
 };
 
+struct QState {
+    float q[6], bq[6];
+};
+
+__device__ __forceinline__ QState load_qstate(const QutritRec* r) {
+    const float4* p = reinterpret_cast<const float4*>(r);
+    const float4 x = p[0], y = p[1], z = p[2];
+    return QState{{x.x, x.y, x.z, x.w, y.x, y.y}, {y.z, y.w, z.x, z.y, z.z, z.w}};
+}
+
+__device__ __forceinline__ void store_qstate(QutritRec* r, const QState& s) {
+    float4* p = reinterpret_cast<float4*>(r);
+    p[0] = make_float4(s.q[0], s.q[1], s.q[2], s.q[3]);
+    p[1] = make_float4(s.q[4], s.q[5], s.bq[0], s.bq[1]);
+    p[2] = make_float4(s.bq[2], s.bq[3], s.bq[4], s.bq[5]);
+}
+
 __device__ __forceinline__ SlotState load_slot_state(const LoopArgs& a, uint32_t i, uint32_t s, bool rot) {
     SlotState st;
     st.theta = a.slot[(size_t)i * a.S + s].theta;
@@ -62,15 +79,47 @@ __device__ __forceinline__ SlotState load_slot_state(const LoopArgs& a, uint32_t
     return st;
 }
 
+// A slot's whole record and (rotation slot) qutrit record, as the fused
+// kernel gathers them for the first 64 positions: decoding needs the angle
+// and the qutrit, and a slot no other circuit uses is committed from them.
+struct SlotFull {
+    SlotRec r;
+    QState q;
+};
+
+__device__ __forceinline__ SlotFull load_slot_full(const LoopArgs& a, uint32_t i, uint32_t s, bool rot) {
+    SlotFull f;
+    f.r = a.slot[(size_t)i * a.S + s];
+    f.q = load_qstate(a.qrec + (size_t)i * a.Q + (rot ? s : 0u));
+    return f;
+}
+
+__device__ __forceinline__ SlotState state_of(const SlotFull& f) {
+    SlotState st;
+    st.theta = f.r.theta;
+    st.q0 = make_float2(f.q.q[0], f.q.q[1]);
+    st.q1 = make_float2(f.q.q[2], f.q.q[3]);
+    st.q2 = make_float2(f.q.q[4], f.q.q[5]);
+    return st;
+}
+
 // Decodes slot s of instance i: rotation slot -> NOT on its wire when the
 // measured axis is x and the angle rounds to a half turn, else I; template
 // slot (c, t) -> controlled V^q with q the angle in quarter turns.
+// (FULL: the whole records are loaded and returned in *full)
+template <bool FULL = false>
 __device__ __forceinline__ uint16_t decode_slot(const LoopArgs& a, uint32_t gen, uint32_t i,
-                                                uint32_t s) {
+                                                uint32_t s, SlotFull* full = nullptr) {
     const uint32_t LP = (uint32_t)a.L * (uint32_t)a.P;
     const uint32_t r = s / LP;
     const bool rot = r < (uint32_t)a.n;
-    const SlotState st = load_slot_state(a, i, s, rot);
+    SlotState st;
+    if constexpr (FULL) {
+        *full = load_slot_full(a, i, s, rot);
+        st = state_of(*full);
+    } else {
+        st = load_slot_state(a, i, s, rot);
+    }
     // every lane measures (a wavefront with any rotation slot runs the draw
     // anyway) while the loads are in flight; template slots ignore the outcome
     const u32x4 w = draw(a.seed, TAG_MEASURE, gen, i, s);
@@ -91,11 +140,19 @@ __device__ __forceinline__ uint16_t decode_slot(const LoopArgs& a, uint32_t gen,
 // rotation about the measured axis (outcome 0, 1, 2 = x, y, z) on w, a
 // template slot on the unordered pair (a, b) the interaction J on (a, b);
 // both take the slot's angle.  Returns {descriptor, angle}.
-__device__ __forceinline__ uint2 decode_ising(const LoopArgs& a, uint32_t gen, uint32_t i, uint32_t s) {
+template <bool FULL = false>
+__device__ __forceinline__ uint2 decode_ising(const LoopArgs& a, uint32_t gen, uint32_t i, uint32_t s,
+                                              SlotFull* full = nullptr) {
     const uint32_t LP = (uint32_t)a.L * (uint32_t)a.P;
     const uint32_t r = s / LP;
     const bool rot = r < (uint32_t)a.n;
-    const SlotState st = load_slot_state(a, i, s, rot);
+    SlotState st;
+    if constexpr (FULL) {
+        *full = load_slot_full(a, i, s, rot);
+        st = state_of(*full);
+    } else {
+        st = load_slot_state(a, i, s, rot);
+    }
     const u32x4 w = draw(a.seed, TAG_MEASURE, gen, i, s);   // every lane, as in decode_slot
     anchor(w.x);
     anchor(st.q0.x);
@@ -240,7 +297,7 @@ __device__ __forceinline__ void clear_next_mask(const LoopArgs& a, uint32_t gen,
 }
 
 // Elitism of a slot that one circuit alone used (defined with the update).
-__device__ void commit_alone(const LoopArgs& a, uint32_t i, uint32_t s, float v);
+__device__ void commit_alone(const LoopArgs& a, uint32_t i, uint32_t s, float v, SlotFull f);
 
 // -------------------------------------------- population evaluation (FP32)
 // One circuit per wavefront (register / per-lane layouts, and the LDS layout
@@ -276,6 +333,7 @@ __device__ __forceinline__ void eval_circuit(const LoopArgs& a, uint32_t gen, ui
     // (the flags exist only for sampled generations whose duplicates were
     // found beforehand, and then L <= KEEP * 64)
     auto is_alone = [&](int p) -> bool { return a.dup && a.dup[(size_t)ci * L + p] == 0; };
+    SlotFull full0{};                       // the records of the lane's slot in chunk 0
     using SrcT = std::conditional_t<ISING, uint2, uint32_t>;
     auto own = [&](int ch) -> SrcT {
         const int p = ch * 64 + lane;
@@ -303,7 +361,7 @@ __device__ __forceinline__ void eval_circuit(const LoopArgs& a, uint32_t gen, ui
         for (int c = 0; c < KEEP; ++c)
             if (c == ch) { kept[c] = s; alone[c] = al; }
         if constexpr (ISING) {
-            const uint2 g = decode_ising(a, gen, i, s);
+            const uint2 g = ch == 0 ? decode_ising<true>(a, gen, i, s, &full0) : decode_ising(a, gen, i, s);
             if (writer) {
                 if (slots_out) slots_out[(size_t)ci * L + p] = s;
                 gates_out[(size_t)ci * L + p] = (uint16_t)g.x;
@@ -311,7 +369,7 @@ __device__ __forceinline__ void eval_circuit(const LoopArgs& a, uint32_t gen, ui
             }
             return g;
         } else {
-            const uint16_t d = decode_slot(a, gen, i, s);
+            const uint16_t d = ch == 0 ? decode_slot<true>(a, gen, i, s, &full0) : decode_slot(a, gen, i, s);
             if (writer) {
                 if (slots_out) slots_out[(size_t)ci * L + p] = s;
                 gates_out[(size_t)ci * L + p] = d;
@@ -372,7 +430,10 @@ __device__ __forceinline__ void eval_circuit(const LoopArgs& a, uint32_t gen, ui
         for (int c = 0; c < KEEP; ++c) {
             const int p = c * 64 + lane;
             if (p >= L) continue;
-            if (alone[c]) commit_alone(a, i, kept[c], fv);
+            if (alone[c]) {
+                if (c == 0) commit_alone(a, i, kept[0], fv, full0);
+                else commit_alone(a, i, kept[c], fv, load_slot_full(a, i, kept[c], kept[c] < a.Q));
+            }
             else atomicMax(&a.slot[(size_t)i * a.S + kept[c]].key, key);
         }
         for (int p = KEEP * 64 + lane; p < L; p += 64) {
@@ -481,23 +542,6 @@ __device__ __forceinline__ void su3_step(float* q, int j, int ai, const float* t
 }
 
 // Amplitudes of a qutrit record (the first 48 of its 64 bytes).
-struct QState {
-    float q[6], bq[6];
-};
-
-__device__ __forceinline__ QState load_qstate(const QutritRec* r) {
-    const float4* p = reinterpret_cast<const float4*>(r);
-    const float4 x = p[0], y = p[1], z = p[2];
-    return QState{{x.x, x.y, x.z, x.w, y.x, y.y}, {y.z, y.w, z.x, z.y, z.z, z.w}};
-}
-
-__device__ __forceinline__ void store_qstate(QutritRec* r, const QState& s) {
-    float4* p = reinterpret_cast<float4*>(r);
-    p[0] = make_float4(s.q[0], s.q[1], s.q[2], s.q[3]);
-    p[1] = make_float4(s.q[4], s.q[5], s.bq[0], s.bq[1]);
-    p[2] = make_float4(s.bq[2], s.bq[3], s.bq[4], s.bq[5]);
-}
-
 // Elitism (Sec. IV-E.1) of a used slot whose segment fitness is v: strictly
 // better -> the state becomes the best, otherwise the best state is restored.
 // Returns whether the best copy changed.
@@ -519,14 +563,14 @@ __device__ __forceinline__ bool elitism(float v, SlotRec& r, QState& q, bool rot
 
 // The elitism of a slot that no other circuit of the generation used, with
 // its circuit's fitness v as the segment fitness: run by that circuit as soon
-// as its fitness is known.  Only what changes is written; the key stays 0, so
-// the update sees the slot as unused.
-__device__ __forceinline__ void commit_alone(const LoopArgs& a, uint32_t i, uint32_t s, float v) {
+// as its fitness is known, from the records it gathered (nothing else writes
+// them before the update).  Only what changes is written; the key stays 0,
+// so the update sees the slot as unused.
+__device__ __forceinline__ void commit_alone(const LoopArgs& a, uint32_t i, uint32_t s, float v, SlotFull f) {
     const size_t o = (size_t)i * a.S + s, oq = (size_t)i * a.Q + s;
     const bool rot = s < a.Q;
-    SlotRec r = a.slot[o];
-    QState q{};
-    if (rot) q = load_qstate(a.qrec + oq);
+    SlotRec r = f.r;
+    QState q = f.q;                         // (a template slot's is never stored)
     const uint32_t th = r.theta;
     bool qsame = true;
 #pragma unroll
