@@ -149,12 +149,14 @@ struct LoopArgs {
     const int64_t* inst_toff;
     int64_t genes;                     // genes per genome buffer (all populations)
     // QEQEA, populations of at most DEDUP_MAX_ENTRIES entries (P * L) of at
-    // most 256 positions: per (circuit, position) entry of the current
-    // generation, 1 if another circuit uses the same slot (null otherwise)
-    uint8_t* dup;
+    // most 256 positions and fewer than 2^31 slots: per (circuit, position)
+    // entry of the current generation, its slot index, with bit 31 set if
+    // another circuit uses the same slot (null otherwise)
+    uint32_t* dup;
 };
+constexpr uint32_t DUP_SHARED = 0x80000000u;
 constexpr int DEDUP_MAX_ENTRIES = 4096;
-constexpr int DEDUP_TABLE = 2 * DEDUP_MAX_ENTRIES;
+constexpr int DEDUP_TABLE = 2 * DEDUP_MAX_ENTRIES;   // (32 KB of LDS)
 
 // loop.hip
 hipError_t launch_qeqea_init(const LoopArgs& a, hipStream_t s);
@@ -174,12 +176,12 @@ hipError_t launch_scatter(const LoopArgs& a, uint64_t gen, const uint32_t* slots
                           hipStream_t s);
 // slots: the generation's slot indices [I*P*L], or NULL to draw them again
 // from the SAMPLE stream (the internal generation path).
-// shared: the flags of launch_dedup for a generation sampled by the fused
-// kernel (whose unshared slots it committed), or null (every entry's slot
-// goes through the keys)
+// shared: the slot words of launch_dedup for a generation sampled by the
+// fused kernel (whose unshared slots it committed), or null (every entry's
+// slot goes through the keys)
 hipError_t launch_qeqea_update(const LoopArgs& a, uint64_t gen, const uint32_t* slots,
                                const uint16_t* gates, const uint32_t* angles, const float* f,
-                               hipStream_t s, const uint8_t* shared = nullptr);
+                               hipStream_t s, const uint32_t* shared = nullptr);
 // the shared-slot flags of generation gen (a.dup), before its fused kernel
 hipError_t launch_dedup(const LoopArgs& a, uint64_t gen, hipStream_t s);
 hipError_t launch_mutmask_clear(const LoopArgs& a, hipStream_t s);

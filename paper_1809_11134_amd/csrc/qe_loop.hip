@@ -332,7 +332,7 @@ __device__ __forceinline__ void eval_circuit(const LoopArgs& a, uint32_t gen, ui
     for (int c = 0; c < KEEP; ++c) { kept[c] = 0xFFFFFFFFu; alone[c] = false; }
     // (the flags exist only for sampled generations whose duplicates were
     // found beforehand, and then L <= KEEP * 64)
-    auto is_alone = [&](int p) -> bool { return a.dup && a.dup[(size_t)ci * L + p] == 0; };
+    auto is_alone = [&](uint32_t word) -> bool { return a.dup && !(word & DUP_SHARED); };
     SlotFull full0{};                       // the records of the lane's slot in chunk 0
     using SrcT = std::conditional_t<ISING, uint2, uint32_t>;
     auto own = [&](int ch) -> SrcT {
@@ -348,15 +348,22 @@ __device__ __forceinline__ void eval_circuit(const LoopArgs& a, uint32_t gen, ui
         const bool dec = decide && writer && p == L;
         if (!pos && !dec) return SrcT{};
         // one Philox pass: position lanes draw their entry's individual and
-        // region, lane L the mutation decision of individual k
-        const u32x4 w = draw(a.seed, pos ? (uint32_t)TAG_SAMPLE : (uint32_t)TAG_MUT_IND, gen, i,
-                             pos ? k * (uint32_t)L + (uint32_t)p : k);
-        if (!pos) {
-            if ((uint64_t)w.x < a.thr_pm) mark_mutation(a, gen, i, k);
-            return SrcT{};
+        // region (or, after the shared-slot search, read the slot it drew),
+        // lane L the mutation decision of individual k
+        uint32_t word = 0u;
+        if (a.dup && pos) {
+            word = a.dup[(size_t)ci * L + p];
+        } else {
+            const u32x4 w = draw(a.seed, pos ? (uint32_t)TAG_SAMPLE : (uint32_t)TAG_MUT_IND, gen, i,
+                                 pos ? k * (uint32_t)L + (uint32_t)p : k);
+            if (!pos) {
+                if ((uint64_t)w.x < a.thr_pm) mark_mutation(a, gen, i, k);
+                return SrcT{};
+            }
+            word = slot_of_draw(a, w, (uint32_t)p);
         }
-        const uint32_t s = slot_of_draw(a, w, (uint32_t)p);
-        const bool al = is_alone(p);
+        const uint32_t s = a.dup ? (word & ~DUP_SHARED) : word;
+        const bool al = is_alone(word);
 #pragma unroll
         for (int c = 0; c < KEEP; ++c)
             if (c == ch) { kept[c] = s; alone[c] = al; }
@@ -600,14 +607,16 @@ __device__ __forceinline__ void mutate_state(const LoopArgs& a, uint32_t gen, ui
     }
 }
 
-// Which slots of a generation more than one circuit uses: one workgroup per
-// population draws every (circuit, position) entry's slot again and counts
-// the slots in an LDS hash table (open addressing, at most half full), then
-// writes a flag per entry, 1 where the entry's slot is shared.  The fused
-// kernel commits the elitism of the unshared slots itself (commit_alone) and
-// raises the key of the shared ones; the update handles only those.  Used
+// The slots of a generation and which of them more than one circuit uses:
+// one workgroup per population draws every (circuit, position) entry's slot
+// (the generation's SAMPLE stream) and enters it in an LDS hash table (open
+// addressing, at most half full; bit 31 of an entry marks a slot entered
+// twice), then writes each entry's slot word: the slot index, bit 31 set if
+// the slot is shared.  The fused kernel takes its slots from these words and
+// commits the elitism of the unshared ones itself (commit_alone); the shared
+// ones keep the largest key for the update, which handles only those.  Used
 // when a population has at most DEDUP_MAX_ENTRIES entries of at most 256
-// positions.
+// positions and fewer than 2^31 slots.
 __device__ __forceinline__ uint32_t dedup_hash(uint32_t x) {
     x ^= x >> 16;
     x *= 0x45D9F3Bu;
@@ -619,28 +628,30 @@ __global__ __launch_bounds__(256) void dedup_kernel(LoopArgs a, uint64_t gen64) 
     constexpr uint32_t EMPTY = 0xFFFFFFFFu, MASK = DEDUP_TABLE - 1;
     constexpr int PER = DEDUP_MAX_ENTRIES / 256;
     __shared__ uint32_t keys[DEDUP_TABLE];
-    __shared__ uint32_t cnt[DEDUP_TABLE];
     const uint32_t gen = gen_of(a, gen64);
     const uint32_t i = blockIdx.x, L = (uint32_t)a.L, LP = L * (uint32_t)a.P;
-    for (uint32_t t = threadIdx.x; t < DEDUP_TABLE; t += 256) { keys[t] = EMPTY; cnt[t] = 0u; }
+    for (uint32_t t = threadIdx.x; t < DEDUP_TABLE; t += 256) keys[t] = EMPTY;
     __syncthreads();
     uint32_t sl[PER], at[PER];
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
         const uint32_t e = (uint32_t)u * 256u + threadIdx.x;
-        sl[u] = EMPTY;
+        sl[u] = 0u;
         at[u] = 0u;
         if (e >= LP) continue;
-        const uint32_t s = sample_slot(a, gen, i, e / L, e % L);
+        const uint32_t s = sample_slot(a, gen, i, e / L, e % L);      // < 2^31
         uint32_t h = dedup_hash(s) & MASK;
-        // the table holds at most LP <= DEDUP_TABLE / 2 keys: a free entry is
+        // the table holds at most LP <= DEDUP_TABLE / 2 slots: a free entry is
         // always found
         while (true) {
             const uint32_t prev = atomicCAS(&keys[h], EMPTY, s);
-            if (prev == EMPTY || prev == s) break;
+            if (prev == EMPTY) break;
+            if ((prev & ~DUP_SHARED) == s) {
+                atomicOr(&keys[h], DUP_SHARED);
+                break;
+            }
             h = (h + 1u) & MASK;
         }
-        atomicAdd(&cnt[h], 1u);
         sl[u] = s;
         at[u] = h;
     }
@@ -648,7 +659,7 @@ __global__ __launch_bounds__(256) void dedup_kernel(LoopArgs a, uint64_t gen64) 
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
         const uint32_t e = (uint32_t)u * 256u + threadIdx.x;
-        if (e < LP) a.dup[(size_t)i * LP + e] = cnt[at[u]] > 1u ? 1 : 0;
+        if (e < LP) a.dup[(size_t)i * LP + e] = sl[u] | (keys[at[u]] & DUP_SHARED);
     }
 }
 
@@ -674,14 +685,17 @@ constexpr int UPD_WPB = UPD_BLOCK / 64;   // wavefronts per workgroup
 __device__ __forceinline__ void update_part_a(const LoopArgs& a, uint32_t gen, uint32_t idx,
                                               const uint32_t* __restrict__ slots,
                                               const float* __restrict__ f,
-                                              const uint8_t* __restrict__ shared) {
+                                              const uint32_t* __restrict__ shared) {
     const uint32_t L = (uint32_t)a.L, LP = L * (uint32_t)a.P;
     if (idx >= (uint32_t)a.I * LP) return;
-    // (a slot no other circuit used was committed by the fused kernel)
-    if (shared && shared[idx] == 0) return;
     const uint32_t i = idx / LP, k = (idx % LP) / L;
+    // with the slot words of the shared-slot search: a slot no other circuit
+    // used was committed by the fused kernel
+    const uint32_t w = shared ? shared[idx] : 0u;
+    if (shared && !(w & DUP_SHARED)) return;
     const float fk = f[idx / L];                // the entry's circuit's fitness
-    const uint32_t s = slots ? slots[idx] : sample_slot(a, gen, i, k, idx % L);
+    const uint32_t s = shared ? (w & ~DUP_SHARED)
+                              : (slots ? slots[idx] : sample_slot(a, gen, i, k, idx % L));
     if (s >= a.S) return;
     const uint32_t ind = (s % LP) / L;
     const size_t o = (size_t)i * a.S + s, oq = (size_t)i * a.Q + s;
@@ -875,7 +889,7 @@ __global__ __launch_bounds__(UPD_BLOCK) void qeqea_update_kernel(LoopArgs a, uin
                                                                  const float* __restrict__ f,
                                                                  uint32_t nC, uint32_t nB,
                                                                  uint32_t per_inst,
-                                                                 const uint8_t* __restrict__ shared) {
+                                                                 const uint32_t* __restrict__ shared) {
     const uint32_t gen = gen_of(a, gen64);
     const uint32_t a0 = (nC + nB + 7u) & ~7u;   // part A starts at a multiple of 8
     if (blockIdx.x < nC) {
@@ -1499,7 +1513,7 @@ hipError_t launch_dedup(const LoopArgs& a, uint64_t gen, hipStream_t s) {
 
 hipError_t launch_qeqea_update(const LoopArgs& a, uint64_t gen, const uint32_t* slots,
                                const uint16_t* gates, const uint32_t* angles, const float* f,
-                               hipStream_t s, const uint8_t* shared) {
+                               hipStream_t s, const uint32_t* shared) {
     if (a.P > UPD_MAX_P) return hipErrorInvalidValue;
     const uint32_t nC = blocks((size_t)a.I * part_c_waves(a.P), UPD_BLOCK / 64);
     const uint32_t nA = blocks((size_t)a.I * a.P * a.L, UPD_BLOCK);
