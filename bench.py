@@ -459,42 +459,34 @@ def qeqea_graph_run(ctx, K, W, dev, reps=3, elite_k=32):
 
 def time_generation_kernels(ctx, gen0, R, dev):
     """The two kernels of a generation as the graph launches them, timed
-    with HIP events on the launch stream: R fused sampling + fitness kernels
-    (qe_sample_eval without slot output) back to back between two events give
-    its mean duration; then R generations of the fused kernel and the update
-    kernel (qe_update right after it), each update between its own two
-    events, give the update kernel's.  Returns (fused us, update us, the
-    last generation's gates, next generation index)."""
+    with HIP events on the launch stream: R generations run as
+    qe_sample_eval (without slot output) then qe_update, each launch between
+    its own two events.  After the first generation qe_sample_eval is the
+    fused sampling + fitness kernel alone (the update before it ran the
+    generation's shared-slot search), and qe_update is the update kernel
+    with the next generation's search, as in the graph.  Returns (fused us,
+    update us, the last generation's gates, next generation index)."""
     import torch
     IP = ctx.I * ctx.P
     gates = torch.empty((IP, ctx.L), dtype=torch.int16, device=dev)
     f = torch.empty(IP, dtype=torch.float32, device=dev)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
     gen = gen0
-    ctx.sample_eval(gen, None, gates, f, keep_slots=False)
-    ctx.update(gen, None, gates, f)
-    gen += 1
-    torch.cuda.synchronize()
-    e0.record()
-    for r in range(R):
-        ctx.sample_eval(gen + r, None, gates, f, keep_slots=False)
-    e1.record()
-    torch.cuda.synchronize()
-    fused = e0.elapsed_time(e1) / R * 1e3
-    # the update of the last of those generations, then R whole generations
-    # with each update launch bracketed by its own pair of events
-    ctx.update(gen + R - 1, None, gates, f)
-    gen += R
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(R)]
+    for _ in range(2):
+        ctx.sample_eval(gen, None, gates, f, keep_slots=False)
+        ctx.update(gen, None, gates, f)
+        gen += 1
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(R)]
     torch.cuda.synchronize()
     for r in range(R):
-        ctx.sample_eval(gen + r, None, gates, f, keep_slots=False)
         ev[r][0].record()
-        ctx.update(gen + r, None, gates, f)
+        ctx.sample_eval(gen + r, None, gates, f, keep_slots=False)
         ev[r][1].record()
+        ev[r][2].record()
+        ctx.update(gen + r, None, gates, f)
+        ev[r][3].record()
     torch.cuda.synchronize()
-    upd = sum(a.elapsed_time(b) for a, b in ev) / R * 1e3
+    fused = sum(e[0].elapsed_time(e[1]) for e in ev) / R * 1e3
+    upd = sum(e[2].elapsed_time(e[3]) for e in ev) / R * 1e3
     return fused, upd, gates, gen + R
 
 
@@ -508,9 +500,11 @@ def update_algorithmic_bytes(ctx, gen, dev):
     R*L slots), every rotation slot of one in qutrit mode reads its qutrit and
     best fitness and writes the qutrit (52 B, n*L slots), the two modes
     equiprobable; the generation's best circuit reads the P fitness values
-    (4 B each).  Counts come from the generation's own slots and decision
-    bitmaps (it is sampled here, then updated).  Returns the update kernel's
-    bytes (the elitism of the shared slots, the mutation, the best circuit),
+    (4 B each); with the shared-slot search, the update reads every entry's
+    slot word and writes the next generation's (4 B + 4 B per entry).
+    Counts come from the generation's own slots and decision bitmaps (it is
+    sampled here, then updated).  Returns the update kernel's bytes (the
+    elitism of the shared slots, the mutation, the best circuit, the words),
     the bytes of the elitism the fused kernel commits (the slots one circuit
     alone used) and the counts."""
     import numpy as np
@@ -541,7 +535,7 @@ def update_algorithmic_bytes(ctx, gen, dev):
     mutated = int(bits.sum())
     per_mut = 0.5 * (R * ctx.L * 12.0) + 0.5 * (ctx.n * ctx.L * 52.0)
     update_bytes = ((used.size - alone_n) * 24.0 + (used_rot - alone_rot) * 72.0 + mutated * per_mut
-                    + IP * 4.0)
+                    + IP * 4.0 + (IP * ctx.L * 8.0 if dedup else 0.0))
     commit_bytes = alone_n * 24.0 + alone_rot * 72.0
     return update_bytes, commit_bytes, {"used_slots": int(used.size), "used_rotation_slots": used_rot,
                                         "committed_by_fused_kernel": alone_n,
@@ -744,7 +738,8 @@ def main():
     roofline_update = {"bound": "hbm", "achieved": round(upd_ach, 2), "peak": HBM_PEAK_GBPS,
                        "unit": "GB/s", "frac": round(upd_ach / HBM_PEAK_GBPS, 6),
                        "traffic": traffic_from_profiles("qeqea_update_n5", src),
-                       "kernel": "qeqea_update_kernel (elitism of the slots several circuits used, mutation, best circuit)",
+                       "kernel": "qeqea_update_kernel (elitism of the slots several circuits used, mutation, "
+                                 "best circuit, the next generation's shared-slot search)",
                        "kernel_us": round(upd_us, 3), "algorithmic_hbm_bytes_per_launch": upd_bytes,
                        "units": upd_counts}
     # the elitism's record work at random places (each used slot's record, and

@@ -314,10 +314,12 @@ qe_status qe_update(qe_ctx* ctx, uint64_t gen, const uint32_t* slots_dev,
                     const uint16_t* gates_dev, const uint32_t* angles_dev, const float* f_dev,
                     void* stream);
 
-/* sample + eval + update of generation `gen` (QEQEA: three kernel launches,
- * the shared-slot search, the fused kernel and the update; GA: two); f_dev
- * [I*P] receives the generation's fitness (may be NULL).  Results equal
- * qe_sample, qe_eval_population and qe_update in sequence. */
+/* sample + eval + update of generation `gen` (QEQEA: the fused kernel and
+ * the update, preceded by the shared-slot search described at
+ * qe_sample_eval unless the update of generation gen - 1 on this context
+ * already ran it; GA: two launches); f_dev [I*P] receives the generation's
+ * fitness (may be NULL).  Results equal qe_sample, qe_eval_population and
+ * qe_update in sequence. */
 qe_status qe_generation(qe_ctx* ctx, uint64_t gen, float* f_dev, void* stream);
 
 /* The first half of qe_generation for QEQEA (the launches qe_generation and
@@ -326,7 +328,12 @@ qe_status qe_generation(qe_ctx* ctx, uint64_t gen, float* f_dev, void* stream);
  * fitness evaluation (f_dev), the segment fitness (Sec. IV-E.1) and the
  * generation's mutation decisions (Sec. IV-F).  For populations of at most
  * 4096 (circuit, position) entries and 256 positions, a search for the slots
- * that more than one circuit uses runs first, and the fused kernel commits
+ * that more than one circuit uses runs first (skipped when the context holds
+ * its result already: the slots drawn depend on the seed and the generation
+ * only, and the update after qe_sample_eval, qe_generation and every
+ * generation of qe_run_graph searches the next generation's slots; the
+ * context keeps the results of two generations, so calls on one context
+ * must be ordered, one stream or synchronised), and the fused kernel commits
  * the elitism of every slot its circuit alone used (its segment fitness is
  * that circuit's fitness, final as soon as the circuit is evaluated); the
  * shared slots keep the largest fitness for qe_update.  The encoding is then

@@ -284,6 +284,11 @@ struct qe_ctx {
     // the generation of the last qe_sample_eval (its segment keys and mutation
     // decisions are in place for qe_update), -1 when another call came since
     int64_t fused_gen = -1;
+    // QEQEA with the shared-slot search: the generation whose slot words each
+    // of the two buffers holds (buffer g & 1 for generation g; -1 none).  The
+    // words depend on the seed and the generation only, so they stay valid
+    // until the buffer is written for another generation.
+    int64_t words_gen[2] = {-1, -1};
     // mixed GA populations (qe_create_mixed): per population width, genome
     // length and target offset (host copies), genes per genome buffer,
     // complex elements of the targets; per circuit width, gate offsets and
@@ -376,13 +381,28 @@ BatchArgs mixed_batch(const qe_ctx* c, const uint16_t* gates) {
     return b;
 }
 
+void note_words(qe_ctx* c, uint64_t gen) {
+    if (c->la.dup) c->words_gen[gen & 1] = (int64_t)gen;
+}
+
+// The shared-slot search of generation gen, unless its words are in place.
+qe_status ensure_words(qe_ctx* c, uint64_t gen, hipStream_t s) {
+    if (!c->la.dup || c->words_gen[gen & 1] == (int64_t)gen) return QE_OK;
+    QE_HIP(launch_dedup(c->la, gen, s));
+    note_words(c, gen);
+    return QE_OK;
+}
+
+// One generation.  QEQEA: the slot words of the generation must be in place
+// (ensure_words, or the update of the generation before it); the update runs
+// the next generation's search.
 qe_status enqueue_generation(qe_ctx* c, const LoopArgs& a, uint64_t gen, float* f, hipStream_t s) {
     if (c->prob.algorithm == QE_ALG_QEQEA) {
         // the update draws each entry's slot again instead of reading it;
-        // with the shared-slot flags only the shared slots go through it
-        QE_HIP(launch_dedup(a, gen, s));
+        // with the slot words only the shared slots go through it
         QE_HIP(launch_qeqea_fused(a, gen, nullptr, c->gates, c->angles, f, true, s));
-        QE_HIP(launch_qeqea_update(a, gen, nullptr, c->gates, c->angles, f, s, a.dup));
+        QE_HIP(launch_qeqea_update(a, gen, nullptr, c->gates, c->angles, f, s, a.dup != nullptr,
+                                   a.dup != nullptr));
     } else {
         QE_HIP(launch_ga_copy(a, gen, c->gates, s));
         if (c->mixed) QE_HIP(launch_mix_eval(mixed_batch(c, c->gates), c->mix_order, f, nullptr, nullptr, s));
@@ -702,7 +722,7 @@ qe_status create_impl(const qe_problem* p_in, const int32_t* inst_n, const int32
         ALLOC(a.qrec, I * Q);
         // populations small enough for the shared-slot search in LDS: the
         // fused kernel commits the elitism of the slots one circuit alone used
-        if (P * L <= (size_t)DEDUP_MAX_ENTRIES && L <= 256 && S < ((size_t)1 << 31)) ALLOC(a.dup, I * P * L);
+        if (P * L <= (size_t)DEDUP_MAX_ENTRIES && L <= 256 && S < ((size_t)1 << 31)) ALLOC(a.dup, 2 * I * P * L);
         ALLOC(a.su3_tab, (size_t)4 * SU3_TAB);
     } else {
         ALLOC(a.genomes[0], (size_t)genes);
@@ -922,8 +942,11 @@ qe_status qe_update(qe_ctx* c, uint64_t gen, const uint32_t* slots, const uint16
         // after qe_sample_eval with no slot array the fused kernel has committed
         // the unshared slots (the flags say which); with slots_dev every entry's
         // slot has its key (the elitism is the same, run again, for those)
-        QE_HIP(launch_qeqea_update(c->la, gen, slots, gates, is_ising(c) ? angles : nullptr, f, s,
-                                   (fused && !slots) ? c->la.dup : nullptr));
+        // (and then the search of the next generation)
+        const bool words = fused && !slots && c->la.dup != nullptr;
+        QE_HIP(launch_qeqea_update(c->la, gen, slots, gates, is_ising(c) ? angles : nullptr, f, s, words,
+                                   words));
+        if (words) note_words(c, gen + 1);
     } else {
         QE_HIP(launch_ga_update(c->la, gen, f, s));
     }
@@ -934,7 +957,10 @@ qe_status qe_generation(qe_ctx* c, uint64_t gen, float* f, void* stream) {
     QE_TRY(check_ctx(c, true));
     c->fused_gen = -1;
     QE_TRY(prepare_decisions(c, gen, 1, (hipStream_t)stream));
-    return enqueue_generation(c, c->la, gen, f ? f : c->f, (hipStream_t)stream);
+    if (c->prob.algorithm == QE_ALG_QEQEA) QE_TRY(ensure_words(c, gen, (hipStream_t)stream));
+    QE_TRY(enqueue_generation(c, c->la, gen, f ? f : c->f, (hipStream_t)stream));
+    note_words(c, gen + 1);
+    return QE_OK;
 }
 
 qe_status qe_sample_eval(qe_ctx* c, uint64_t gen, uint32_t* slots, uint16_t* gates,
@@ -945,7 +971,7 @@ qe_status qe_sample_eval(qe_ctx* c, uint64_t gen, uint32_t* slots, uint16_t* gat
     if (is_ising(c) && !angles) return fail(QE_ERR_INVALID, "the Ising library needs angles_dev");
     // the generation's mutation decisions are drawn here, as in qe_generation
     QE_TRY(prepare_decisions(c, gen, 1, (hipStream_t)stream));
-    QE_HIP(launch_dedup(c->la, gen, (hipStream_t)stream));
+    QE_TRY(ensure_words(c, gen, (hipStream_t)stream));
     QE_HIP(launch_qeqea_fused(c->la, gen, slots, gates, is_ising(c) ? angles : nullptr, f, true,
                               (hipStream_t)stream));
     c->fused_gen = (int64_t)gen;
@@ -962,6 +988,8 @@ static qe_status graph_for(qe_ctx* c, int32_t n_gen, float* f_hist, hipGraphExec
     hipGraph_t g = nullptr;
     QE_HIP(hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
     qe_status st = QE_OK;
+    // (each generation's update runs the next one's shared-slot search;
+    // qe_run_graph provides the first generation's words)
     for (int j = 0; j < n_gen && st == QE_OK; ++j)
         st = enqueue_generation(c, a, (uint64_t)j, f_hist ? f_hist + j * IP : c->f, c->capture_stream);
     hipError_t e = hipStreamEndCapture(c->capture_stream, &g);
@@ -998,8 +1026,11 @@ qe_status qe_run_graph(qe_ctx* c, uint64_t first_gen, int32_t n_gen, float* f_hi
     QE_TRY(graph_for(c, n_gen, f_hist, &ex));
     c->fused_gen = -1;
     QE_TRY(prepare_decisions(c, first_gen, (uint64_t)n_gen, s));
+    if (c->prob.algorithm == QE_ALG_QEQEA) QE_TRY(ensure_words(c, first_gen, s));
     QE_HIP(launch_gen_set(c->d_gen, first_gen, s));
     QE_HIP(hipGraphLaunch(ex, s));
+    note_words(c, first_gen + (uint64_t)n_gen - 1);
+    note_words(c, first_gen + (uint64_t)n_gen);
     return QE_OK;
 }
 

@@ -150,13 +150,17 @@ struct LoopArgs {
     int64_t genes;                     // genes per genome buffer (all populations)
     // QEQEA, populations of at most DEDUP_MAX_ENTRIES entries (P * L) of at
     // most 256 positions and fewer than 2^31 slots: per (circuit, position)
-    // entry of the current generation, its slot index, with bit 31 set if
-    // another circuit uses the same slot (null otherwise)
+    // entry of a generation, its slot index, with bit 31 set if another
+    // circuit uses the same slot; two buffers of I * P * L words, generation g
+    // in buffer g & 1, so that the search of the next generation can run
+    // while the current one's words are read (null otherwise)
     uint32_t* dup;
 };
 constexpr uint32_t DUP_SHARED = 0x80000000u;
 constexpr int DEDUP_MAX_ENTRIES = 4096;
-constexpr int DEDUP_TABLE = 2 * DEDUP_MAX_ENTRIES;   // (32 KB of LDS)
+// words of the search's LDS hash table for a population of `entries`
+// entries: at most half full, whole multiples of 256 (at most 32 KB)
+__host__ __device__ inline uint32_t dedup_table(uint32_t entries) { return (2u * entries + 255u) & ~255u; }
 
 // loop.hip
 hipError_t launch_qeqea_init(const LoopArgs& a, hipStream_t s);
@@ -176,13 +180,16 @@ hipError_t launch_scatter(const LoopArgs& a, uint64_t gen, const uint32_t* slots
                           hipStream_t s);
 // slots: the generation's slot indices [I*P*L], or NULL to draw them again
 // from the SAMPLE stream (the internal generation path).
-// shared: the slot words of launch_dedup for a generation sampled by the
-// fused kernel (whose unshared slots it committed), or null (every entry's
-// slot goes through the keys)
+// shared: the generation was sampled by the fused kernel after the
+// shared-slot search, so its slot words say which slots the fused kernel
+// committed (false: every entry's slot goes through the keys).
+// dedup_next: the same launch runs the shared-slot search of generation
+// gen + 1 (needs a.dup).
 hipError_t launch_qeqea_update(const LoopArgs& a, uint64_t gen, const uint32_t* slots,
                                const uint16_t* gates, const uint32_t* angles, const float* f,
-                               hipStream_t s, const uint32_t* shared = nullptr);
-// the shared-slot flags of generation gen (a.dup), before its fused kernel
+                               hipStream_t s, bool shared = false, bool dedup_next = false);
+// the slot words of generation gen (buffer gen & 1 of a.dup), before its
+// fused kernel
 hipError_t launch_dedup(const LoopArgs& a, uint64_t gen, hipStream_t s);
 hipError_t launch_mutmask_clear(const LoopArgs& a, hipStream_t s);
 // Dense copy of one field of the encoding state (which: 0 theta, 1 qutrit

@@ -23,6 +23,12 @@ __device__ __forceinline__ uint32_t gen_of(const LoopArgs& a, uint64_t gen) {
     return (uint32_t)(a.gen_ptr ? *a.gen_ptr + gen : gen);
 }
 
+// The slot words of generation gen (buffer gen & 1 of the shared-slot search's
+// output).
+__device__ __forceinline__ uint32_t* dup_words(const LoopArgs& a, uint32_t gen) {
+    return a.dup + (size_t)(gen & 1u) * ((size_t)a.I * a.P * a.L);
+}
+
 // ------------------------------------------------------------- measurement
 // Born-rule measurement of a qutrit (3 complex amplitudes, unnormalised):
 // u in [0,1) from the top 24 bits of w scales the cumulative weights.
@@ -352,7 +358,7 @@ __device__ __forceinline__ void eval_circuit(const LoopArgs& a, uint32_t gen, ui
         // lane L the mutation decision of individual k
         uint32_t word = 0u;
         if (a.dup && pos) {
-            word = a.dup[(size_t)ci * L + p];
+            word = dup_words(a, gen)[(size_t)ci * L + p];
         } else {
             const u32x4 w = draw(a.seed, pos ? (uint32_t)TAG_SAMPLE : (uint32_t)TAG_MUT_IND, gen, i,
                                  pos ? k * (uint32_t)L + (uint32_t)p : k);
@@ -616,7 +622,11 @@ __device__ __forceinline__ void mutate_state(const LoopArgs& a, uint32_t gen, ui
 // commits the elitism of the unshared ones itself (commit_alone); the shared
 // ones keep the largest key for the update, which handles only those.  Used
 // when a population has at most DEDUP_MAX_ENTRIES entries of at most 256
-// positions and fewer than 2^31 slots.
+// positions and fewer than 2^31 slots.  The slots drawn depend on the seed and
+// the generation alone, not on the encoding, so the search of a generation
+// can run before the previous generation has been updated: the update kernel
+// runs it for the next generation (its part D), and dedup_kernel serves a
+// generation with no update before it.
 __device__ __forceinline__ uint32_t dedup_hash(uint32_t x) {
     x ^= x >> 16;
     x *= 0x45D9F3Bu;
@@ -624,13 +634,14 @@ __device__ __forceinline__ uint32_t dedup_hash(uint32_t x) {
     return x;
 }
 
-__global__ __launch_bounds__(256) void dedup_kernel(LoopArgs a, uint64_t gen64) {
-    constexpr uint32_t EMPTY = 0xFFFFFFFFu, MASK = DEDUP_TABLE - 1;
+// Population i's search, by a whole workgroup of 256 threads, with keys the
+// dedup_table(P * L) words of dynamic LDS.
+__device__ __forceinline__ void dedup_population(const LoopArgs& a, uint32_t gen, uint32_t i,
+                                                 uint32_t* keys) {
+    constexpr uint32_t EMPTY = 0xFFFFFFFFu;
     constexpr int PER = DEDUP_MAX_ENTRIES / 256;
-    __shared__ uint32_t keys[DEDUP_TABLE];
-    const uint32_t gen = gen_of(a, gen64);
-    const uint32_t i = blockIdx.x, L = (uint32_t)a.L, LP = L * (uint32_t)a.P;
-    for (uint32_t t = threadIdx.x; t < DEDUP_TABLE; t += 256) keys[t] = EMPTY;
+    const uint32_t L = (uint32_t)a.L, LP = L * (uint32_t)a.P, T = dedup_table(LP);
+    for (uint32_t t = threadIdx.x; t < T; t += 256) keys[t] = EMPTY;
     __syncthreads();
     uint32_t sl[PER], at[PER];
 #pragma unroll
@@ -640,9 +651,9 @@ __global__ __launch_bounds__(256) void dedup_kernel(LoopArgs a, uint64_t gen64) 
         at[u] = 0u;
         if (e >= LP) continue;
         const uint32_t s = sample_slot(a, gen, i, e / L, e % L);      // < 2^31
-        uint32_t h = dedup_hash(s) & MASK;
-        // the table holds at most LP <= DEDUP_TABLE / 2 slots: a free entry is
-        // always found
+        uint32_t h = (uint32_t)(((uint64_t)dedup_hash(s) * T) >> 32);
+        // the table holds at most LP <= T / 2 slots: a free entry is always
+        // found
         while (true) {
             const uint32_t prev = atomicCAS(&keys[h], EMPTY, s);
             if (prev == EMPTY) break;
@@ -650,17 +661,23 @@ __global__ __launch_bounds__(256) void dedup_kernel(LoopArgs a, uint64_t gen64) 
                 atomicOr(&keys[h], DUP_SHARED);
                 break;
             }
-            h = (h + 1u) & MASK;
+            h = h + 1u == T ? 0u : h + 1u;
         }
         sl[u] = s;
         at[u] = h;
     }
     __syncthreads();
+    uint32_t* out = dup_words(a, gen) + (size_t)i * LP;
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
         const uint32_t e = (uint32_t)u * 256u + threadIdx.x;
-        if (e < LP) a.dup[(size_t)i * LP + e] = sl[u] | (keys[at[u]] & DUP_SHARED);
+        if (e < LP) out[e] = sl[u] | (keys[at[u]] & DUP_SHARED);
     }
+}
+
+__global__ __launch_bounds__(256) void dedup_kernel(LoopArgs a, uint64_t gen64) {
+    extern __shared__ __align__(16) uint32_t dedup_keys[];
+    dedup_population(a, gen_of(a, gen64), blockIdx.x, dedup_keys);
 }
 
 // Part C: the instance's best circuit of the generation (largest f, lowest
@@ -671,8 +688,11 @@ __global__ __launch_bounds__(256) void dedup_kernel(LoopArgs a, uint64_t gen64) 
 // circuit holds the slot's key.  Part B: the slots the mutation moves (qubit
 // mode: every slot of the individual; qutrit mode: its rotation slots), one
 // thread per slot, since the individual's slots belong to nobody else:
-// elitism if the slot was used, then mutation.  The grid holds part C, then part B (the
-// longest chains), then part A, so the longer work is dispatched first.
+// elitism if the slot was used, then mutation.  Part D (optional): the
+// shared-slot search of the next generation, one workgroup per population;
+// its hash arithmetic overlaps the record traffic of the other parts.  The
+// grid holds part C, then part B (the longest chains), then part D, then
+// part A, so the longer work is dispatched first.
 constexpr int UPD_BLOCK = 256;
 constexpr int UPD_MAX_P = 16384;          // part B's list of mutated individuals lives in LDS
 constexpr int UPD_WPB = UPD_BLOCK / 64;   // wavefronts per workgroup
@@ -887,22 +907,30 @@ __global__ __launch_bounds__(UPD_BLOCK) void qeqea_update_kernel(LoopArgs a, uin
                                                                  const uint16_t* __restrict__ gates,
                                                                  const uint32_t* __restrict__ angles,
                                                                  const float* __restrict__ f,
-                                                                 uint32_t nC, uint32_t nB,
-                                                                 uint32_t per_inst,
-                                                                 const uint32_t* __restrict__ shared) {
+                                                                 uint32_t nC, uint32_t nB, uint32_t nD,
+                                                                 uint32_t per_inst, bool shared) {
     const uint32_t gen = gen_of(a, gen64);
-    const uint32_t a0 = (nC + nB + 7u) & ~7u;   // part A starts at a multiple of 8
+    // parts D and A start at multiples of 8, so that a block's XCD is its
+    // index within the part modulo 8
+    const uint32_t d0 = (nC + nB + 7u) & ~7u;
+    const uint32_t a0 = (d0 + nD + 7u) & ~7u;
     if (blockIdx.x < nC) {
         update_part_c(a, blockIdx.x, gates, angles, f);
     } else if (blockIdx.x < nC + nB) {
         update_part_b<SPL>(a, gen, blockIdx.x - nC, per_inst);
+    } else if (blockIdx.x >= d0 && blockIdx.x < d0 + nD) {
+        // part D: the shared-slot search of the next generation (its words go
+        // to the other buffer), each population's on the XCD whose L2 the
+        // fused kernel will read them from
+        extern __shared__ __align__(16) uint32_t dedup_keys[];
+        dedup_population(a, gen + 1u, xcd_swizzle(blockIdx.x - d0, nD), dedup_keys);
     } else if (blockIdx.x >= a0) {
         // part A: each XCD takes the circuits the fused kernel ran on it,
         // from the last back (the records touched last are the likeliest to
         // still be cached)
         const uint32_t nA = gridDim.x - a0;
         const uint32_t blk = nA - 1u - xcd_swizzle(blockIdx.x - a0, nA);
-        update_part_a(a, gen, blk * UPD_BLOCK + threadIdx.x, slots, f, shared);
+        update_part_a(a, gen, blk * UPD_BLOCK + threadIdx.x, slots, f, shared ? dup_words(a, gen) : nullptr);
     }
 }
 
@@ -1507,14 +1535,14 @@ hipError_t launch_scatter(const LoopArgs& a, uint64_t gen, const uint32_t* slots
 
 hipError_t launch_dedup(const LoopArgs& a, uint64_t gen, hipStream_t s) {
     if (!a.dup) return hipSuccess;
-    dedup_kernel<<<a.I, 256, 0, s>>>(a, gen);
+    dedup_kernel<<<a.I, 256, (size_t)dedup_table((uint32_t)a.L * (uint32_t)a.P) * 4, s>>>(a, gen);
     return hipGetLastError();
 }
 
 hipError_t launch_qeqea_update(const LoopArgs& a, uint64_t gen, const uint32_t* slots,
                                const uint16_t* gates, const uint32_t* angles, const float* f,
-                               hipStream_t s, const uint32_t* shared) {
-    if (a.P > UPD_MAX_P) return hipErrorInvalidValue;
+                               hipStream_t s, bool shared, bool dedup_next) {
+    if (a.P > UPD_MAX_P || ((shared || dedup_next) && !a.dup)) return hipErrorInvalidValue;
     const uint32_t nC = blocks((size_t)a.I * part_c_waves(a.P), UPD_BLOCK / 64);
     const uint32_t nA = blocks((size_t)a.I * a.P * a.L, UPD_BLOCK);
     // part B: per instance, enough workgroups for the (mutated individual,
@@ -1533,14 +1561,17 @@ hipError_t launch_qeqea_update(const LoopArgs& a, uint64_t gen, const uint32_t* 
     const uint32_t per_inst = (uint32_t)std::max<double>(
         1.0, std::ceil(std::min<double>(std::ceil(expect + slack), (double)a.P * chunks) / UPD_WPB));
     const uint32_t nB = per_inst * (uint32_t)a.I;
-    const size_t lds = ((size_t)a.P * sizeof(uint16_t) + 15) & ~(size_t)15;
-    const uint32_t a0 = (nC + nB + 7u) & ~7u;
+    // part D: one workgroup per population
+    const uint32_t nD = dedup_next ? (uint32_t)a.I : 0u;
+    size_t lds = ((size_t)a.P * sizeof(uint16_t) + 15) & ~(size_t)15;
+    if (nD) lds = std::max(lds, (size_t)dedup_table((uint32_t)a.L * (uint32_t)a.P) * 4);
+    const uint32_t a0 = (((nC + nB + 7u) & ~7u) + nD + 7u) & ~7u;
     if (many)
-        qeqea_update_kernel<4><<<a0 + nA, UPD_BLOCK, lds, s>>>(a, gen, slots, gates, angles, f, nC, nB, per_inst,
-                                                               shared);
+        qeqea_update_kernel<4><<<a0 + nA, UPD_BLOCK, lds, s>>>(a, gen, slots, gates, angles, f, nC, nB, nD,
+                                                               per_inst, shared);
     else
-        qeqea_update_kernel<1><<<a0 + nA, UPD_BLOCK, lds, s>>>(a, gen, slots, gates, angles, f, nC, nB, per_inst,
-                                                               shared);
+        qeqea_update_kernel<1><<<a0 + nA, UPD_BLOCK, lds, s>>>(a, gen, slots, gates, angles, f, nC, nB, nD,
+                                                               per_inst, shared);
     return hipGetLastError();
 }
 

@@ -275,6 +275,29 @@ def test_generation_and_graph_equal_steps(dev, oracle, n):
     assert ga[:2] == c.get_best(0, with_fp64=False)[:2]
 
 
+def test_graph_many_populations_equal_generations(dev, oracle):
+    # the layout of the n = 5 benchmark (P * L within the shared-slot search):
+    # in a graph each update runs the next generation's search, and a replay
+    # or generation that follows on reuses it; replays of two and of one
+    # generation (one after a skipped generation, whose words are then
+    # searched again) against single generations, state bit for bit
+    n, L, P, I, seed = 5, 40, 64, 72, 6060
+    a, _ = qeqea_ctx(dev, oracle, n, L, P, I, seed, pm=0.3)
+    b, _ = qeqea_ctx(dev, oracle, n, L, P, I, seed, pm=0.3)
+    ha = torch.empty((2, I * P), dtype=torch.float32, device=dev)
+    fa = []
+    for first, G in ((0, 2), (2, 2), (4, 1), (6, 2)):
+        a.run_graph(first, G, ha)
+        torch.cuda.synchronize()
+        fa += [ha[j].clone() for j in range(G)]
+    fb = [b.generation(gen).clone() for gen in (0, 1, 2, 3, 4, 6, 7)]
+    for x, y in zip(fa, fb):
+        assert torch.equal(x, y)
+    sa, sb = gpu_state(a), gpu_state(b)
+    for k in sa:
+        assert np.array_equal(sa[k], sb[k]), k
+
+
 def test_graph_replays_are_stable(dev, oracle):
     # several replays with eager work and synchronisation between them
     n, L, P, I, seed = 4, 16, 64, 2, 5
