@@ -543,6 +543,14 @@ def update_algorithmic_bytes(ctx, gen, dev):
                                         "mutated_individuals": mutated}
 
 
+def sampled_schedule(n, L):
+    """(wavefronts per circuit, circuits per workgroup) of the fused QEQEA
+    kernel for width n and length L (the sampled library class)."""
+    from paper_1809_11134_amd import qe
+    _, waves, cpb = qe.get_schedule_lib(n, 1 if L >= 32 else 0, qe.SCHED_SAMPLED)
+    return waves, (cpb if waves == 1 else 1)
+
+
 def secondary_qeqea_n4(dev, K, W):
     """n=4, library {I,NOT,CNOT,CV,CV+}, one QEQEA population of 4096
     circuits x 30 gates: the graph of K generations + the FP64 re-check
@@ -556,7 +564,8 @@ def secondary_qeqea_n4(dev, K, W):
     ctx.close()
     return {"workload": w["name"], "generations": K, "evals_per_s": K * w["P"] / (ms * 1e-3),
             "ms_per_generation": ms / K, "replay_ms": times, "elite_fp32_vs_fp64_max_abs_df": err,
-            "fused_kernel": "population_kernel<4,1,true,false>", "fused_kernel_us": fused_us,
+            "fused_kernel": "population_kernel<4,{},true,false,{}>".format(*sampled_schedule(4, w["L"])),
+            "fused_kernel_us": fused_us,
             "update_kernel_us": upd_us, "algorithmic_lds_bytes_per_launch": lds,
             "lds_frac": lds / (fused_us * 1e-6) / 1e9 / LDS_PEAK_GBPS,
             "traffic": traffic_from_profiles("qeqea_fused_n4", source_hash())}
@@ -711,14 +720,14 @@ def main():
     lds_bytes = algorithmic_lds_bytes(gh, n)
     achieved = lds_bytes / (fused_us * 1e-6) / 1e9
     alu = flops / (fused_us * 1e-6) / 1e12
-    _, waves, cpb = qe.get_schedule_ex(n, 1 if L >= 32 else 0)
-    cpb = cpb if waves == 1 else 1
+    waves, cpb = sampled_schedule(n, L)
     roofline = {"bound": "lds", "achieved": round(achieved, 2), "peak": round(LDS_PEAK_GBPS, 1),
                 "unit": "GB/s", "frac": round(achieved / LDS_PEAK_GBPS, 6),
                 "traffic": traffic_from_profiles("qeqea_fused_n5", src),
-                "kernel": f"population_kernel<5,{waves},true,false,{cpb}> (sampling + Eq. 11 fitness + "
-                          f"segment max + mutation decisions, LDS-staged, {waves} wavefront(s) per circuit, "
-                          f"{cpb} circuit(s) per workgroup)",
+                "kernel": f"population_kernel<5,{waves},true,false,{cpb}> (circuit construction from the "
+                          f"slot words + Eq. 11 fitness + elitism of the slots a circuit alone used + "
+                          f"segment max of the shared ones + mutation decisions, LDS-staged, {waves} "
+                          f"wavefront(s) per circuit, {cpb} circuit(s) per workgroup)",
                 "kernel_us": round(fused_us, 3), "algorithmic_lds_bytes_per_launch": lds_bytes,
                 "peak_source": "LDS probe kernel in this run, copy mode (each 16-byte word read and "
                                "written once, the mix of the per-gate updates)",
