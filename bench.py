@@ -459,13 +459,16 @@ def qeqea_graph_run(ctx, K, W, dev, reps=3, elite_k=32):
 
 def time_generation_kernels(ctx, gen0, R, dev):
     """The two kernels of a generation as the graph launches them, timed
-    with HIP events on the launch stream: R generations run as
-    qe_sample_eval (without slot output) then qe_update, each launch between
-    its own two events.  After the first generation qe_sample_eval is the
-    fused sampling + fitness kernel alone (the update before it ran the
-    generation's shared-slot search), and qe_update is the update kernel
-    with the next generation's search, as in the graph.  Returns (fused us,
-    update us, the last generation's gates, next generation index)."""
+    with HIP events on the launch stream.  Populations small enough for the
+    shared-slot search: R generations run as qe_sample_eval (without slot
+    output) then qe_update, each launch between its own two events; after the
+    first generation qe_sample_eval is the fused sampling + fitness kernel
+    alone (the update before it ran the generation's search) and qe_update
+    is the update kernel with the next generation's search, as in the graph.
+    Other populations: R fused launches back to back between two events,
+    then R generations with each update between its own two events.
+    Returns (fused us, update us, the last generation's gates, next
+    generation index)."""
     import torch
     IP = ctx.I * ctx.P
     gates = torch.empty((IP, ctx.L), dtype=torch.int16, device=dev)
@@ -476,16 +479,34 @@ def time_generation_kernels(ctx, gen0, R, dev):
         ctx.update(gen, None, gates, f)
         gen += 1
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(R)]
-    torch.cuda.synchronize()
-    for r in range(R):
-        ev[r][0].record()
-        ctx.sample_eval(gen + r, None, gates, f, keep_slots=False)
-        ev[r][1].record()
-        ev[r][2].record()
-        ctx.update(gen + r, None, gates, f)
-        ev[r][3].record()
-    torch.cuda.synchronize()
-    fused = sum(e[0].elapsed_time(e[1]) for e in ev) / R * 1e3
+    if ctx.P * ctx.L <= 4096 and ctx.L <= 256:
+        torch.cuda.synchronize()
+        for r in range(R):
+            ev[r][0].record()
+            ctx.sample_eval(gen + r, None, gates, f, keep_slots=False)
+            ev[r][1].record()
+            ev[r][2].record()
+            ctx.update(gen + r, None, gates, f)
+            ev[r][3].record()
+        torch.cuda.synchronize()
+        fused = sum(e[0].elapsed_time(e[1]) for e in ev) / R * 1e3
+    else:
+        torch.cuda.synchronize()
+        ev[0][0].record()
+        for r in range(R):
+            ctx.sample_eval(gen + r, None, gates, f, keep_slots=False)
+        ev[0][1].record()
+        torch.cuda.synchronize()
+        fused = ev[0][0].elapsed_time(ev[0][1]) / R * 1e3
+        ctx.update(gen + R - 1, None, gates, f)
+        gen += R
+        torch.cuda.synchronize()
+        for r in range(R):
+            ctx.sample_eval(gen + r, None, gates, f, keep_slots=False)
+            ev[r][2].record()
+            ctx.update(gen + r, None, gates, f)
+            ev[r][3].record()
+        torch.cuda.synchronize()
     upd = sum(e[2].elapsed_time(e[3]) for e in ev) / R * 1e3
     return fused, upd, gates, gen + R
 

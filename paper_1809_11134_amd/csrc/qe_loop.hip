@@ -374,7 +374,9 @@ __device__ __forceinline__ void eval_circuit(const LoopArgs& a, uint32_t gen, ui
         for (int c = 0; c < KEEP; ++c)
             if (c == ch) { kept[c] = s; alone[c] = al; }
         if constexpr (ISING) {
-            const uint2 g = ch == 0 ? decode_ising<true>(a, gen, i, s, &full0) : decode_ising(a, gen, i, s);
+            // (whole records only where the fused kernel may commit them)
+            const uint2 g = (ch == 0 && a.dup) ? decode_ising<true>(a, gen, i, s, &full0)
+                                               : decode_ising(a, gen, i, s);
             if (writer) {
                 if (slots_out) slots_out[(size_t)ci * L + p] = s;
                 gates_out[(size_t)ci * L + p] = (uint16_t)g.x;
@@ -382,7 +384,8 @@ __device__ __forceinline__ void eval_circuit(const LoopArgs& a, uint32_t gen, ui
             }
             return g;
         } else {
-            const uint16_t d = ch == 0 ? decode_slot<true>(a, gen, i, s, &full0) : decode_slot(a, gen, i, s);
+            const uint16_t d = (ch == 0 && a.dup) ? decode_slot<true>(a, gen, i, s, &full0)
+                                                  : decode_slot(a, gen, i, s);
             if (writer) {
                 if (slots_out) slots_out[(size_t)ci * L + p] = s;
                 gates_out[(size_t)ci * L + p] = d;
