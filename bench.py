@@ -521,8 +521,10 @@ def update_algorithmic_bytes(ctx, gen, dev):
     R*L slots), every rotation slot of one in qutrit mode reads its qutrit and
     best fitness and writes the qutrit (52 B, n*L slots), the two modes
     equiprobable; the generation's best circuit reads the P fitness values
-    (4 B each); with the shared-slot search, the update reads every entry's
-    slot word and writes the next generation's (4 B + 4 B per entry).
+    (4 B each); with the shared-slot search, the update writes the next
+    generation's slot words (4 B per entry) and reads this generation's list
+    of shared entries and writes the next one's (8 + 8 B per shared entry,
+    this generation's count standing for both).
     Counts come from the generation's own slots and decision bitmaps (it is
     sampled here, then updated).  Returns the update kernel's bytes (the
     elitism of the shared slots, the mutation, the best circuit, the words),
@@ -555,12 +557,14 @@ def update_algorithmic_bytes(ctx, gen, dev):
     bits = np.unpackbits(m.view(np.uint8), bitorder="little").reshape(ctx.I, mw * 32)[:, :ctx.P]
     mutated = int(bits.sum())
     per_mut = 0.5 * (R * ctx.L * 12.0) + 0.5 * (ctx.n * ctx.L * 52.0)
+    shared_entries = int(uses[uses > 1].sum()) if dedup else 0
     update_bytes = ((used.size - alone_n) * 24.0 + (used_rot - alone_rot) * 72.0 + mutated * per_mut
-                    + IP * 4.0 + (IP * ctx.L * 8.0 if dedup else 0.0))
+                    + IP * 4.0 + ((IP * ctx.L * 4.0 + shared_entries * 16.0) if dedup else 0.0))
     commit_bytes = alone_n * 24.0 + alone_rot * 72.0
     return update_bytes, commit_bytes, {"used_slots": int(used.size), "used_rotation_slots": used_rot,
                                         "committed_by_fused_kernel": alone_n,
                                         "committed_rotation_slots": alone_rot,
+                                        "shared_entries": shared_entries,
                                         "mutated_individuals": mutated}
 
 

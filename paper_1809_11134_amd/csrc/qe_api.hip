@@ -722,7 +722,11 @@ qe_status create_impl(const qe_problem* p_in, const int32_t* inst_n, const int32
         ALLOC(a.qrec, I * Q);
         // populations small enough for the shared-slot search in LDS: the
         // fused kernel commits the elitism of the slots one circuit alone used
-        if (P * L <= (size_t)DEDUP_MAX_ENTRIES && L <= 256 && S < ((size_t)1 << 31)) ALLOC(a.dup, 2 * I * P * L);
+        if (P * L <= (size_t)DEDUP_MAX_ENTRIES && L <= 256 && S < ((size_t)1 << 31)) {
+            ALLOC(a.dup, 2 * I * P * L);
+            ALLOC(a.shared_list, 2 * I * P * L);
+            ALLOC(a.shared_count, 2 * I);
+        }
         ALLOC(a.su3_tab, (size_t)4 * SU3_TAB);
     } else {
         ALLOC(a.genomes[0], (size_t)genes);

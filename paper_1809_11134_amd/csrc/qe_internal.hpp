@@ -155,6 +155,11 @@ struct LoopArgs {
     // in buffer g & 1, so that the search of the next generation can run
     // while the current one's words are read (null otherwise)
     uint32_t* dup;
+    // with dup: per generation parity and population, the entries whose slot
+    // is shared ({entry index within the population, slot}, [2][I][P * L])
+    // and their number ([2][I])
+    uint2* shared_list;
+    uint32_t* shared_count;
 };
 constexpr uint32_t DUP_SHARED = 0x80000000u;
 constexpr int DEDUP_MAX_ENTRIES = 4096;

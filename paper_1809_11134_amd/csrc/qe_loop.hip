@@ -620,10 +620,11 @@ __device__ __forceinline__ void mutate_state(const LoopArgs& a, uint32_t gen, ui
 // one workgroup per population draws every (circuit, position) entry's slot
 // (the generation's SAMPLE stream) and enters it in an LDS hash table (open
 // addressing, at most half full; bit 31 of an entry marks a slot entered
-// twice), then writes each entry's slot word: the slot index, bit 31 set if
-// the slot is shared.  The fused kernel takes its slots from these words and
-// commits the elitism of the unshared ones itself (commit_alone); the shared
-// ones keep the largest key for the update, which handles only those.  Used
+// twice), then writes each entry's slot word (the slot index, bit 31 set if
+// the slot is shared) and the list of the shared entries.  The fused kernel
+// takes its slots from the words and commits the elitism of the unshared
+// ones itself (commit_alone); the shared ones keep the largest key for the
+// update, whose part A walks the list.  Used
 // when a population has at most DEDUP_MAX_ENTRIES entries of at most 256
 // positions and fewer than 2^31 slots.  The slots drawn depend on the seed and
 // the generation alone, not on the encoding, so the search of a generation
@@ -669,13 +670,24 @@ __device__ __forceinline__ void dedup_population(const LoopArgs& a, uint32_t gen
         sl[u] = s;
         at[u] = h;
     }
+    __shared__ uint32_t n_shared;
+    if (threadIdx.x == 0) n_shared = 0u;
     __syncthreads();
+    const size_t base = (size_t)(gen & 1u) * a.I + i;
     uint32_t* out = dup_words(a, gen) + (size_t)i * LP;
+    uint2* list = a.shared_list + base * LP;
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
         const uint32_t e = (uint32_t)u * 256u + threadIdx.x;
-        if (e < LP) out[e] = sl[u] | (keys[at[u]] & DUP_SHARED);
+        if (e >= LP) continue;
+        const uint32_t sh = keys[at[u]] & DUP_SHARED;
+        out[e] = sl[u] | sh;
+        // the shared entries, for the update (in no particular order: each
+        // entry's work on its slot does not depend on the others')
+        if (sh) list[atomicAdd(&n_shared, 1u)] = make_uint2(e, sl[u]);
     }
+    __syncthreads();
+    if (threadIdx.x == 0) a.shared_count[base] = n_shared;
 }
 
 __global__ __launch_bounds__(256) void dedup_kernel(LoopArgs a, uint64_t gen64) {
@@ -687,8 +699,10 @@ __global__ __launch_bounds__(256) void dedup_kernel(LoopArgs a, uint64_t gen64) 
 // index; NaN never counts) updates its best circuit ever.  Part A: the used
 // slots the mutation leaves alone (those of individuals that do not mutate,
 // and the template slots of individuals mutating in qutrit mode), one thread
-// per (circuit, position) entry; an entry handles its slot only if its
-// circuit holds the slot's key.  Part B: the slots the mutation moves (qubit
+// per (circuit, position) entry, or, after the shared-slot search, per entry
+// of the population's list of shared entries (the fused kernel committed
+// the rest); an entry handles its slot only if its circuit holds the slot's
+// key.  Part B: the slots the mutation moves (qubit
 // mode: every slot of the individual; qutrit mode: its rotation slots), one
 // thread per slot, since the individual's slots belong to nobody else:
 // elitism if the slot was used, then mutation.  Part D (optional): the
@@ -703,22 +717,11 @@ constexpr int UPD_WPB = UPD_BLOCK / 64;   // wavefronts per workgroup
 // when many populations fill the launch (2 and 8 measured slower), 1 for a
 // few large populations, which need the wavefronts
 
-// slots NULL: the entry's slot is drawn again (the generation's own
-// sampling, which saves a dependent load); otherwise it is read.
-__device__ __forceinline__ void update_part_a(const LoopArgs& a, uint32_t gen, uint32_t idx,
-                                              const uint32_t* __restrict__ slots,
-                                              const float* __restrict__ f,
-                                              const uint32_t* __restrict__ shared) {
+// Entry idx (= i * P * L + k * L + pos) of population i, whose slot is s.
+__device__ __forceinline__ void part_a_entry(const LoopArgs& a, uint32_t gen, uint32_t i, uint32_t idx,
+                                             uint32_t s, const float* __restrict__ f) {
     const uint32_t L = (uint32_t)a.L, LP = L * (uint32_t)a.P;
-    if (idx >= (uint32_t)a.I * LP) return;
-    const uint32_t i = idx / LP, k = (idx % LP) / L;
-    // with the slot words of the shared-slot search: a slot no other circuit
-    // used was committed by the fused kernel
-    const uint32_t w = shared ? shared[idx] : 0u;
-    if (shared && !(w & DUP_SHARED)) return;
     const float fk = f[idx / L];                // the entry's circuit's fitness
-    const uint32_t s = shared ? (w & ~DUP_SHARED)
-                              : (slots ? slots[idx] : sample_slot(a, gen, i, k, idx % L));
     if (s >= a.S) return;
     const uint32_t ind = (s % LP) / L;
     const size_t o = (size_t)i * a.S + s, oq = (size_t)i * a.Q + s;
@@ -746,6 +749,32 @@ __device__ __forceinline__ void update_part_a(const LoopArgs& a, uint32_t gen, u
     elitism(v, r, q, rot);
     a.slot[o] = r;
     if (rot) store_qstate(a.qrec + oq, q);
+}
+
+// One thread per entry (idx over all populations' entries): slots NULL
+// draws the entry's slot again (the generation's own sampling, which saves
+// a dependent load); otherwise it is read.
+__device__ __forceinline__ void update_part_a(const LoopArgs& a, uint32_t gen, uint32_t idx,
+                                              const uint32_t* __restrict__ slots,
+                                              const float* __restrict__ f) {
+    const uint32_t L = (uint32_t)a.L, LP = L * (uint32_t)a.P;
+    if (idx >= (uint32_t)a.I * LP) return;
+    const uint32_t i = idx / LP, k = (idx % LP) / L;
+    part_a_entry(a, gen, i, idx, slots ? slots[idx] : sample_slot(a, gen, i, k, idx % L), f);
+}
+
+// With the shared-slot search (the fused kernel committed the slots one
+// circuit alone used): one workgroup per population over its list of shared
+// entries.
+__device__ __forceinline__ void update_part_a_shared(const LoopArgs& a, uint32_t gen, uint32_t i,
+                                                     const float* __restrict__ f) {
+    const size_t base = (size_t)(gen & 1u) * a.I + i;
+    const uint32_t n = a.shared_count[base], LP = (uint32_t)a.L * (uint32_t)a.P;
+    const uint2* list = a.shared_list + base * LP;
+    for (uint32_t t = threadIdx.x; t < n; t += UPD_BLOCK) {
+        const uint2 es = list[t];
+        part_a_entry(a, gen, i, i * LP + es.x, es.y, f);
+    }
 }
 
 // Workgroup b of part B serves instance b / per_inst: it lists the
@@ -932,8 +961,12 @@ __global__ __launch_bounds__(UPD_BLOCK) void qeqea_update_kernel(LoopArgs a, uin
         // from the last back (the records touched last are the likeliest to
         // still be cached)
         const uint32_t nA = gridDim.x - a0;
-        const uint32_t blk = nA - 1u - xcd_swizzle(blockIdx.x - a0, nA);
-        update_part_a(a, gen, blk * UPD_BLOCK + threadIdx.x, slots, f, shared ? dup_words(a, gen) : nullptr);
+        if (shared) {
+            update_part_a_shared(a, gen, xcd_swizzle(blockIdx.x - a0, nA), f);
+        } else {
+            const uint32_t blk = nA - 1u - xcd_swizzle(blockIdx.x - a0, nA);
+            update_part_a(a, gen, blk * UPD_BLOCK + threadIdx.x, slots, f);
+        }
     }
 }
 
@@ -1547,7 +1580,9 @@ hipError_t launch_qeqea_update(const LoopArgs& a, uint64_t gen, const uint32_t* 
                                hipStream_t s, bool shared, bool dedup_next) {
     if (a.P > UPD_MAX_P || ((shared || dedup_next) && !a.dup)) return hipErrorInvalidValue;
     const uint32_t nC = blocks((size_t)a.I * part_c_waves(a.P), UPD_BLOCK / 64);
-    const uint32_t nA = blocks((size_t)a.I * a.P * a.L, UPD_BLOCK);
+    // part A: one workgroup per population over its shared entries, or one
+    // thread per entry
+    const uint32_t nA = shared ? (uint32_t)a.I : blocks((size_t)a.I * a.P * a.L, UPD_BLOCK);
     // part B: per instance, enough workgroups for the (mutated individual,
     // slot chunk) items up to four standard deviations above the binomial
     // mean (more items loop).  With many instances the grid holds far more

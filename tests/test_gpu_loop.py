@@ -298,6 +298,37 @@ def test_graph_many_populations_equal_generations(dev, oracle):
         assert np.array_equal(sa[k], sb[k]), k
 
 
+def test_mixed_calls_reuse_slot_words(dev, oracle):
+    # graph replays, qe_generation and qe_sample_eval + qe_update in one
+    # sequence, with a skipped generation: each call reuses the slot words the
+    # update before it wrote, or searches them when they are missing; the
+    # fitness and the state match single generations bit for bit
+    n, L, P, I, seed = 4, 24, 32, 6, 6161
+    a, _ = qeqea_ctx(dev, oracle, n, L, P, I, seed, pm=0.4)
+    b, _ = qeqea_ctx(dev, oracle, n, L, P, I, seed, pm=0.4)
+    hist = torch.empty((2, I * P), dtype=torch.float32, device=dev)
+    fa = []
+    a.run_graph(0, 2, hist)
+    torch.cuda.synchronize()
+    fa += [hist[0].clone(), hist[1].clone()]
+    _, gates, f = a.sample_eval(2, keep_slots=False)
+    a.update(2, None, gates, f)
+    fa.append(f.clone())
+    fa.append(a.generation(3).clone())
+    _, gates, f = a.sample_eval(5, keep_slots=False)
+    a.update(5, None, gates, f)
+    fa.append(f.clone())
+    a.run_graph(6, 2, hist)
+    torch.cuda.synchronize()
+    fa += [hist[0].clone(), hist[1].clone()]
+    fb = [b.generation(gen).clone() for gen in (0, 1, 2, 3, 5, 6, 7)]
+    for j, (x, y) in enumerate(zip(fa, fb)):
+        assert torch.equal(x, y), j
+    sa, sb = gpu_state(a), gpu_state(b)
+    for k in sa:
+        assert np.array_equal(sa[k], sb[k]), k
+
+
 def test_graph_replays_are_stable(dev, oracle):
     # several replays with eager work and synchronisation between them
     n, L, P, I, seed = 4, 16, 64, 2, 5
