@@ -308,8 +308,11 @@ qe_status qe_eval_population(qe_ctx* ctx, const uint16_t* gates_dev, const uint3
  * produced by qe_sample and qe_eval_population for the same `gen`
  * (angles_dev: Ising library only, NULL otherwise).  QEQEA with slots_dev
  * NULL: allowed only right after qe_sample_eval(gen) on this context (else
- * QE_ERR_STATE); the slot indices are then drawn again from the SAMPLE
- * stream, and the segment keys and decisions that call left are used. */
+ * QE_ERR_STATE); the segment keys and decisions that call left are used,
+ * with the slot indices of its shared-slot search (the update then handles
+ * only the slots several circuits shared, and runs the next generation's
+ * search) or, for populations too large for the search, drawn again from
+ * the SAMPLE stream. */
 qe_status qe_update(qe_ctx* ctx, uint64_t gen, const uint32_t* slots_dev,
                     const uint16_t* gates_dev, const uint32_t* angles_dev, const float* f_dev,
                     void* stream);
