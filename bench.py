@@ -686,7 +686,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--timed-replays", type=int, default=3,
+    ap.add_argument("--timed-replays", type=int, default=5,
                     help="timed replays of the K-generation graph (the median is reported)")
     ap.add_argument("--cpu-seconds", type=float, default=16.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
