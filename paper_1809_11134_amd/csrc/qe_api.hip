@@ -398,8 +398,9 @@ qe_status ensure_words(qe_ctx* c, uint64_t gen, hipStream_t s) {
 // the next generation's search.
 qe_status enqueue_generation(qe_ctx* c, const LoopArgs& a, uint64_t gen, float* f, hipStream_t s) {
     if (c->prob.algorithm == QE_ALG_QEQEA) {
-        // the update draws each entry's slot again instead of reading it;
-        // with the slot words only the shared slots go through it
+        // without slot words the update draws each entry's slot again; with
+        // them it walks the search's list of shared entries (the fused kernel
+        // committed the others)
         QE_HIP(launch_qeqea_fused(a, gen, nullptr, c->gates, c->angles, f, true, s));
         QE_HIP(launch_qeqea_update(a, gen, nullptr, c->gates, c->angles, f, s, a.dup != nullptr,
                                    a.dup != nullptr));
@@ -944,9 +945,10 @@ qe_status qe_update(qe_ctx* c, uint64_t gen, const uint32_t* slots, const uint16
             QE_HIP(launch_mutation_decisions(c->la, gen, s));
         }
         // after qe_sample_eval with no slot array the fused kernel has committed
-        // the unshared slots (the flags say which); with slots_dev every entry's
-        // slot has its key (the elitism is the same, run again, for those)
-        // (and then the search of the next generation)
+        // the unshared slots (the search's list names the shared ones), and
+        // the update runs the next generation's search; with slots_dev every
+        // entry's slot has its key (the elitism is the same, run again, for
+        // the committed ones)
         const bool words = fused && !slots && c->la.dup != nullptr;
         QE_HIP(launch_qeqea_update(c->la, gen, slots, gates, is_ising(c) ? angles : nullptr, f, s, words,
                                    words));

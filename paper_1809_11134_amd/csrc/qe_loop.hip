@@ -706,8 +706,8 @@ __global__ __launch_bounds__(256) void dedup_kernel(LoopArgs a, uint64_t gen64) 
 // mode: every slot of the individual; qutrit mode: its rotation slots), one
 // thread per slot, since the individual's slots belong to nobody else:
 // elitism if the slot was used, then mutation.  Part D (optional): the
-// shared-slot search of the next generation, one workgroup per population;
-// its hash arithmetic overlaps the record traffic of the other parts.  The
+// shared-slot search of the next generation, one workgroup per population
+// (a launch fewer per generation than a kernel of its own).  The
 // grid holds part C, then part B (the longest chains), then part D, then
 // part A, so the longer work is dispatched first.
 constexpr int UPD_BLOCK = 256;
