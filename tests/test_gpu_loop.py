@@ -142,11 +142,13 @@ def test_fused_generation_long_circuits(dev, oracle, n, L, P):
     assert qe.device_errors() == 0
 
 
-@pytest.mark.parametrize("n,L,I", [(3, 64, 96), (5, 40, 72)])
+@pytest.mark.parametrize("n,L,I", [(3, 64, 96), (5, 40, 72), (2, 64, 16)])
 def test_many_populations_update_bitexact(dev, oracle, n, L, I):
     # enough mutating individuals per launch that the update serves four
     # slots per lane in part B (the layout of the n = 5 benchmark), with the
     # qutrit-mode split between parts A and B; state bit-exact with the oracle
+    # (n = 2: four regions, so each population shares hundreds of entries and
+    # part A's workgroup walks its list several times over)
     P, seed, pm = 64, 8080 + n, 0.5
     qe.device_errors()
     ctx, T = qeqea_ctx(dev, oracle, n, L, P, I, seed, pm=pm)
